@@ -1,0 +1,263 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the two-level lattice-Boltzmann hot path on one
+MI355X.
+
+A step is one coarse time step of the two-level scheme (one coarse update and
+two fine substeps with the full interface treatment).  The default workload
+is the D2Q9 two-level problem with a 4096^2 periodic coarse grid and a
+4097 x 2049-node fine band (patch [1024, 3072] x [1536, 2560] in coarse
+vertices), recursive regularised collision, tau_c = 0.51, populations stored
+in FP32 as deviations from the lattice weights; input: a convected vortex
+plus a Gaussian acoustic pulse (amplitude 1e-3), seeded.
+
+Prints ONE JSON line.  value = MLUPS = (evolving coarse nodes + 2 x fine
+nodes) x steps / seconds / 1e6, inputs resident in HBM.  The roofline object
+prices the dominant kernel (the fine-level pull-stream + collide) with its
+algorithmic bytes (one read and one write of Q populations per node) over its
+mean launch duration measured with HIP events on its launch stream during
+the timed region.  cpu_baseline times the FP64 CPU oracle on a bounded sample
+of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fine_stream.json")
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1000)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--workload", default="d2q9-4096", choices=["d2q9-4096", "d3q19-384", "d2q9-1024"])
+    p.add_argument("--collision", default="RR", choices=["BGK", "RR", "HRR"])
+    p.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    p.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-steps", type=int, default=3)
+    p.add_argument("--copy-probe", type=int, default=0,
+                   help="only run a plain device copy of this many MiB (counter calibration)")
+    return p.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lattice.hpp", "geometry.hpp", "kernels.hpp", "lbm.hip"):
+        with open(os.path.join(ROOT, "paper_2004_11863_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name, seed=0):
+    from paper_2004_11863_amd import inputs as I
+    if name == "d2q9-4096":
+        return I.config2(seed=seed, n=4096)
+    if name == "d2q9-1024":
+        return I.config2(seed=seed, n=1024)
+    return I.config3(seed=seed, n=384)
+
+
+def make_gpu(wl, collision, precision):
+    from paper_2004_11863_amd import inputs as I
+    from paper_2004_11863_amd import lbm
+    g = wl.geom
+    D = g.D
+    lat = lbm.LBM_D2Q9 if D == 2 else lbm.LBM_D3Q19
+    col = {"BGK": lbm.LBM_BGK, "RR": lbm.LBM_RR, "HRR": lbm.LBM_HRR}[collision]
+    prec = lbm.LBM_FP32_DEV if precision == "fp32" else lbm.LBM_FP64
+    grid = lbm.Grid(lat, col, prec, g.n[:D], g.lo[:D], g.hi[:D], tau_coarse=0.51, sigma=0.995)
+    for lv in (0, 1):
+        rho, u = I.fields(wl, lv)
+        grid.set_state(lv, rho, u)
+        del rho, u
+    return grid
+
+
+def timed_run(grid, steps, warmup, profile):
+    import torch
+    from paper_2004_11863_amd import lbm
+    stream = torch.cuda.current_stream().cuda_stream
+    grid.step(warmup, stream)
+    torch.cuda.synchronize()
+    if profile:
+        lbm.lbm_profile_enable(grid.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grid.step(steps, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = None
+    if profile:
+        kt = lbm.lbm_kernel_time(grid.h)
+        lbm.lbm_profile_enable(grid.h, False)
+    return t1 - t0, kt
+
+
+def stored_traffic(kernel_hash, key):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, or None if it was taken on other code."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_hash:
+        return None
+    e = d.get("entries", {}).get(key)
+    return None if e is None else e.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(wl, collision, steps):
+    import oracle as O
+    from paper_2004_11863_amd import inputs as I
+    g = wl.geom
+    D = g.D
+    ref = O.Grid(O.D2Q9 if D == 2 else O.D3Q19, {"BGK": O.BGK, "RR": O.RR, "HRR": O.HRR}[collision],
+                 g.n[:D], g.lo[:D], g.hi[:D], tau_c=0.51, sigma=0.995)
+    for lv in (0, 1):
+        rho, u = I.fields(wl, lv)
+        ref.set_state(lv, rho, u)
+        del rho, u
+    t0 = time.perf_counter()
+    ref.step(steps)
+    dt = time.perf_counter() - t0
+    return g.updates_per_step() * steps / dt / 1e6, O.threads(), dt
+
+
+def copy_probe(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 5}))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no multi-GPU path.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+    from paper_2004_11863_amd import lbm
+    lbm.load()
+
+    wl = workload(args.workload)
+    grid = make_gpu(wl, args.collision, args.precision)
+    ups = grid.updates_per_step()
+    dt, kt = timed_run(grid, args.steps, args.warmup, profile=True)
+    mlups = ups * args.steps / dt / 1e6
+    m, p = grid.totals()  # finite check
+    launches, mean_ms, nodes = kt
+    Q = grid.Q
+    pb = 4 if args.precision == "fp32" else 8
+    alg_bytes = 2 * Q * pb * nodes
+    achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
+    khash = kernel_source_hash()
+    key = f"{args.workload}/{args.collision}/{args.precision}"
+    traffic = stored_traffic(khash, key)
+    grid.close()
+    del grid
+    torch.cuda.empty_cache()
+
+    g = wl.geom
+    D = g.D
+    result = {
+        "metric": "MLUPS & % HBM roofline, FP32 vs FP64 two-level; batched p50/p99 solve latency",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": ("D2Q9 two-level, coarse %dx%d periodic, fine patch %dx%d nodes, %s, %s storage"
+                         % (g.n[0], g.n[1], 2 * (g.hi[0] - g.lo[0]) + 1, 2 * (g.hi[1] - g.lo[1]) + 1,
+                            args.collision, "FP32-deviation" if args.precision == "fp32" else "FP64")
+                         if D == 2 else
+                         "D3Q19 two-level, coarse %d^3 periodic, fine cube %d^3 nodes, %s, %s storage"
+                         % (g.n[0], 2 * (g.hi[0] - g.lo[0]) + 1, args.collision,
+                            "FP32-deviation" if args.precision == "fp32" else "FP64")),
+            "lattice": "D2Q9" if D == 2 else "D3Q19",
+            "coarse": list(g.n[:D]),
+            "patch_lo": list(g.lo[:D]),
+            "patch_hi": list(g.hi[:D]),
+            "collision": args.collision,
+            "tau_coarse": 0.51,
+            "updates_per_step": ups,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_stream (fine level, pull + collide)",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "bytes_per_launch": alg_bytes,
+            "launches": launches,
+            "mean_launch_ms": mean_ms,
+        },
+        "totals_finite": bool(all(map(lambda v: v == v, list(m) + list(p.ravel())))),
+        "kernel_source_hash": khash,
+    }
+
+    if not args.no_extra:
+        extra = {}
+        for name, wname, col, prec, steps in (
+                ("d2q9_4096_rr_fp64", "d2q9-4096", "RR", "fp64", 200),
+                ("d2q9_4096_hrr_fp32", "d2q9-4096", "HRR", "fp32", 200),
+                ("d3q19_384_rr_fp32", "d3q19-384", "RR", "fp32", 60),
+                ("d3q19_384_hrr_fp32", "d3q19-384", "HRR", "fp32", 40)):
+            if (wname, col, prec) == (args.workload, args.collision, args.precision):
+                continue
+            w2 = workload(wname)
+            gr = make_gpu(w2, col, prec)
+            u2 = gr.updates_per_step()
+            d2, k2 = timed_run(gr, steps, 5, profile=True)
+            q2, pb2 = gr.Q, (4 if prec == "fp32" else 8)
+            a2 = 2 * q2 * pb2 * k2[2] / (k2[1] * 1e-3) / 1e9
+            extra[name] = {"mlups": round(u2 * steps / d2 / 1e6, 1), "steps": steps,
+                           "ms_per_step": d2 / steps * 1e3,
+                           "fine_kernel_GBs": round(a2, 1), "fine_kernel_frac": round(a2 / HBM_PEAK_GBS, 4)}
+            gr.close()
+            del gr, w2
+            torch.cuda.empty_cache()
+            print(f"# extra {name}: {extra[name]}", file=sys.stderr, flush=True)
+        result["extra"] = extra
+
+    if not args.no_cpu:
+        v, cores, t = cpu_baseline(wl, args.collision, args.cpu_steps)
+        result["cpu_baseline"] = {"value": round(v, 2), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+                                  "sample": "%d coarse steps of the same grid and input in FP64 (%.1f s)"
+                                            % (args.cpu_steps, t)}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,164 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) two-level lattice-Boltzmann library.
+ *
+ * The library evolves populations on a periodic coarse grid that carries one
+ * fine patch at refinement ratio 2, following the cell-vertex scheme analysed
+ * in Astoul et al., "Analysis and reduction of spurious noise generated at
+ * grid refinement interfaces with the lattice Boltzmann method"
+ * (arXiv:2004.11863):
+ *   - lattices D2Q9 (Sec. 3.1, eqs xi_i and w_i) and D3Q19 (named in Sec. 10);
+ *   - collisions BGK (eq BGKmodel), recursive regularised RR (eqs a1Proj,
+ *     f1RR, a13RR, LBMscheme_reg) and hybrid recursive regularised H-RR
+ *     (eqs stressT, a1ij_HRR), all with the third-order equilibrium
+ *     (eq fEqO3);
+ *   - two fine substeps per coarse step; non-equilibrium rescaling by the
+ *     relaxation-time ratio (eqs rescTau, fneqResc, rescff, rescfc), the
+ *     filtered fine-to-coarse transfer (eq filterFneq), the strain-rate
+ *     hand-off (eq PijResc), third-order temporal and cubic spatial
+ *     interpolation (eqs TempInt, spaceInt), in the order of Sec. 4.3.
+ *
+ * Conventions
+ *   - Every function returns an int: LBM_OK (0) or a negative error code.
+ *     No C++ exception crosses this boundary.  lbm_last_error() returns a
+ *     text for the last failure on a handle (or the last create failure when
+ *     called with NULL).
+ *   - Field arrays are structure-of-arrays, x fastest: a level with nodes
+ *     (nx, ny, nz) stores node (x, y, z) at index x + nx (y + ny z).
+ *     rho[N]; u[D][N] (component-major); populations f[Q][N].
+ *   - Population order: D2Q9 as eq xi_i; D3Q19 as lbm_lattice_info reports
+ *     (rest, +x, -x, +y, -y, +z, -z, then the 12 two-axis diagonals).
+ *   - Coarse level = 0, fine level = 1.  Fine node j sits at coarse
+ *     coordinate lo + j/2; the fine level has 2 (hi - lo) + 1 nodes per axis.
+ *   - mem: LBM_HOST for host pointers, LBM_DEVICE for device pointers on the
+ *     handle's device.  The caller owns every buffer it passes; the library
+ *     copies in and out and keeps no pointer to it.
+ *   - A handle is used by one host thread at a time.  All device work is
+ *     ordered on the stream given to lbm_step (or the handle's own stream).
+ */
+#ifndef LBM_H_
+#define LBM_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,        /* bad argument or descriptor                         */
+  LBM_ENOMEM = -2,        /* device or host allocation failed                   */
+  LBM_EUNSUPPORTED = -3,  /* valid request this build does not serve            */
+  LBM_EUNSTABLE = -4,     /* non-finite totals detected                         */
+  LBM_EDEVICE = -5        /* a HIP call failed                                  */
+};
+
+typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 } lbm_lattice;
+typedef enum { LBM_BGK = 0, LBM_RR = 1, LBM_HRR = 2 } lbm_collision;
+/* LBM_FP64: populations stored and updated in double precision.
+ * LBM_FP32_DEV: populations stored in single precision as deviations
+ * h_i = f_i - w_i from the rest state; bulk updates in single precision,
+ * interface history, interpolation, filtering and rescaling in double,
+ * global totals accumulated in double. */
+typedef enum { LBM_FP64 = 0, LBM_FP32_DEV = 1 } lbm_precision;
+typedef enum { LBM_HOST = 0, LBM_DEVICE = 1 } lbm_mem;
+
+/* Coarse node classes (Fig. Overlap) as returned by lbm_get_index_maps(0). */
+enum { LBM_C_MIDDLE = 0, LBM_C_TF = 1, LBM_C_TN = 2, LBM_C_COVERED = 3 };
+/* Fine node classes as returned by lbm_get_index_maps(1): middle, ring nodes
+ * co-located with coarse nodes (TF), ring nodes between coarse nodes (IE,
+ * cubic along one axis; IE_FACE, tensor cubic on a 3D face centre), and
+ * middle nodes co-located with TN coarse nodes. */
+enum { LBM_F_MIDDLE = 0, LBM_F_TF = 1, LBM_F_IE = 2, LBM_F_IE_FACE = 3, LBM_F_TN = 4 };
+
+typedef struct lbm_grid* lbm_handle;
+
+typedef struct {
+  int32_t lattice;    /* lbm_lattice                                            */
+  int32_t collision;  /* lbm_collision                                          */
+  int32_t precision;  /* lbm_precision                                          */
+  int32_t n[3];       /* coarse nodes per axis, periodic; n[2] = 1 for D2Q9    */
+  int32_t lo[3];      /* fine patch = box [lo, hi] of coarse vertices; lo == hi */
+  int32_t hi[3];      /* on every axis means a single uniform periodic level.   */
+                      /* Otherwise per used axis: hi - lo >= 4, lo >= 2 and     */
+                      /* hi <= n - 3 (the patch and its interpolation stencils  */
+                      /* lie strictly inside one period).                       */
+  double tau_coarse;  /* > 0.5; tau_fine = 2 tau_coarse - 1/2 (eq rescTau)      */
+  double sigma;       /* H-RR weight of the projected stress, in [0, 1]         */
+                      /* (eq a1ij_HRR; the paper uses 0.995); ignored otherwise */
+  int32_t device;     /* HIP device ordinal                                     */
+  int32_t reserved;   /* must be 0                                              */
+} lbm_grid_desc;
+
+/* Creates a grid: validates the descriptor, builds the node-class maps and
+ * interface stencil tables, allocates all device state (two population
+ * buffers per level, the three-time-level coarse history, stencil tables)
+ * and a non-blocking stream.  The state is zero until lbm_set_state. */
+int lbm_create_grid(const lbm_grid_desc* d, lbm_handle* out);
+int lbm_destroy(lbm_handle h);
+
+/* Sets one level's state at t = 0 to the equilibrium populations
+ * f = f0(rho, u) of the given fields (Sec. 4.3, reference state).  Setting
+ * the coarse level also resets the coarse history: the levels t-1 and t hold
+ * rho, u, a zero non-equilibrium part and, for H-RR, the centred-difference
+ * strain rate of u.  rho[N], u[D][N], double precision.  Synchronous. */
+int lbm_set_state(lbm_handle h, int level, const double* rho, const double* u, int mem);
+
+/* Enqueues n_coarse_steps coarse steps (each = one coarse update and two
+ * fine substeps, Sec. 4.3) on hip_stream (a hipStream_t; NULL = the handle's
+ * stream).  Asynchronous; returns after the launches. */
+int lbm_step(lbm_handle h, int n_coarse_steps, void* hip_stream);
+
+/* Density and velocity of one level at the current time (moments of the
+ * post-collision populations, eqs moment_rho and moment_rhoU) in double
+ * precision.  Covered coarse nodes take the values of the co-located fine
+ * node.  With mem = LBM_HOST the call waits for the stream. */
+int lbm_get_macros(lbm_handle h, int level, double* rho, double* u, int mem);
+
+/* Post-collision populations f[Q][N] of one level (double precision, full
+ * values, not deviations).  Setting them on the coarse level re-initialises
+ * the history from their moments as lbm_set_state does.  Synchronous. */
+int lbm_set_populations(lbm_handle h, int level, const double* f, int mem);
+int lbm_get_populations(lbm_handle h, int level, double* f, int mem);
+
+/* Sums of rho and rho u over the evolving nodes of each level (coarse: all
+ * but covered nodes; fine: all nodes), accumulated in double precision in a
+ * fixed order.  mass[2], momentum[2][3].  Returns LBM_EUNSTABLE if any sum
+ * is not finite.  Synchronous. */
+int lbm_get_totals(lbm_handle h, double mass[2], double momentum[6]);
+
+/* Node-class map of one level, one byte per node (LBM_C_* / LBM_F_*). */
+int lbm_get_index_maps(lbm_handle h, int level, uint8_t* cls, int mem);
+
+/* Nodes per axis of a level (dims[3]); error if the level does not exist. */
+int lbm_level_dims(lbm_handle h, int level, int32_t dims[3]);
+
+/* Lattice table: D, Q, xi[Q][3], w[Q]. */
+int lbm_lattice_info(int lattice, int32_t* D, int32_t* Q, int32_t* xi, double* w);
+
+/* Interface tables as built by the library, for bit-exact checks:
+ * counts[3] = {history nodes, ring nodes, TN nodes};
+ * hist_nodes[H] coarse node indices; ring_nodes[R] fine node indices,
+ * ring_npts[R] in {1, 4, 16}, ring_pts[R][16] history entries (unused -1). */
+int lbm_interface_counts(lbm_handle h, int64_t counts[3]);
+int lbm_interface_tables(lbm_handle h, int64_t* hist_nodes, int64_t* ring_nodes, int32_t* ring_npts,
+                         int64_t* ring_pts);
+
+/* Lattice updates per coarse step: evolving coarse nodes + 2 x fine nodes. */
+int lbm_updates_per_step(lbm_handle h, int64_t* updates);
+
+/* Per-launch timing of the fine-level stream-collide kernel (the dominant
+ * kernel): when enabled, lbm_step records HIP events around each of its
+ * launches on the launch stream; lbm_kernel_time returns the number of
+ * timed launches, their mean duration in ms and the nodes one launch
+ * updates.  Synchronous. */
+int lbm_profile_enable(lbm_handle h, int on);
+int lbm_kernel_time(lbm_handle h, int64_t* launches, double* mean_ms, int64_t* nodes_per_launch);
+
+/* Last error text for a handle (NULL: last failure of lbm_create_grid). */
+const char* lbm_last_error(lbm_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H_ */

@@ -1,0 +1,74 @@
+// geometry.hpp -- two-level grid geometry and node classes (host and device).
+//
+// The fine patch is the box [a, a+m] of coarse vertices; fine node j sits at
+// coarse coordinate a + j/2, so the fine level has 2m+1 nodes per axis and
+// its outer layer (j = 0 or 2m) is the overlap ring of Fig. Overlap.  The
+// classes follow that figure, written for a closed patch:
+//   coarse TF  : coarse vertices on the boundary of [a, a+m]      (c -> f)
+//   coarse TN  : coarse vertices on the boundary of [a+1, a+m-1]  (f -> c)
+//   covered    : coarse vertices inside [a+1, a+m-1] (not evolved)
+//   fine TF    : ring nodes co-located with a coarse vertex
+//   fine IE    : other ring nodes (one half-integer coordinate)
+//   fine IEFACE: 3D ring nodes with two half-integer coordinates
+//   fine TN    : fine nodes co-located with coarse TN nodes
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbm {
+
+enum CoarseClass : int { CC_MIDDLE = 0, CC_TF = 1, CC_TN = 2, CC_COVERED = 3 };
+enum FineClass : int { FC_MIDDLE = 0, FC_TF = 1, FC_IE = 2, FC_IEFACE = 3, FC_TN = 4 };
+
+struct Geo {
+  int D;
+  int n[3];   // coarse nodes per axis (1 on unused axes)
+  int a[3];   // patch lower corner (coarse vertex)
+  int m[3];   // patch size in coarse cells
+  int nf[3];  // fine nodes per axis (2m+1; 1 on unused axes or without patch)
+  int has_fine;
+  int64_t Nc, Nf;
+};
+
+__host__ __device__ inline int coarse_class(const Geo& g, int x, int y, int z) {
+  if (!g.has_fine) return CC_MIDDLE;
+  const int c[3] = {x, y, z};
+  bool in_tn = true, on_tn = false, in_tf = true, on_tf = false;
+  for (int d = 0; d < g.D; ++d) {
+    const int lo = g.a[d], hi = g.a[d] + g.m[d];
+    if (c[d] < lo + 1 || c[d] > hi - 1) in_tn = false;
+    if (c[d] == lo + 1 || c[d] == hi - 1) on_tn = true;
+    if (c[d] < lo || c[d] > hi) in_tf = false;
+    if (c[d] == lo || c[d] == hi) on_tf = true;
+  }
+  if (in_tn) return on_tn ? CC_TN : CC_COVERED;
+  return (in_tf && on_tf) ? CC_TF : CC_MIDDLE;
+}
+
+__host__ __device__ inline bool fine_is_ring(const Geo& g, int x, int y, int z) {
+  return x == 0 || x == g.nf[0] - 1 || y == 0 || y == g.nf[1] - 1 ||
+         (g.D == 3 && (z == 0 || z == g.nf[2] - 1));
+}
+
+__host__ __device__ inline int fine_class(const Geo& g, int x, int y, int z) {
+  const int j[3] = {x, y, z};
+  int odd = 0;
+  bool even = true, in_tn = true, on_tn = false;
+  for (int d = 0; d < g.D; ++d) {
+    const int M = g.nf[d] - 1;
+    if (j[d] & 1) {
+      odd++;
+      even = false;
+    }
+    if (j[d] < 2 || j[d] > M - 2) in_tn = false;
+    if (j[d] == 2 || j[d] == M - 2) on_tn = true;
+  }
+  if (fine_is_ring(g, x, y, z)) return odd == 0 ? FC_TF : (odd == 1 ? FC_IE : FC_IEFACE);
+  return (even && in_tn && on_tn) ? FC_TN : FC_MIDDLE;
+}
+
+// Periodic wrap of a coarse coordinate displaced by at most one period.
+__host__ __device__ inline int wrap(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }
+
+}  // namespace lbm

@@ -1,0 +1,272 @@
+"""Python binding of the C ABI in include/lbm.h (argument marshalling only).
+
+Every computation runs in the gfx950 kernels of ``liblbm.so``; this module
+only converts arguments.  PyTorch supplies device memory and streams when a
+caller wants to pass device buffers (``tensor.data_ptr()``) or a stream
+(``torch.cuda.current_stream().cuda_stream``).  There is no fallback: if the
+library is not built, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+try:  # load torch's HIP runtime first so the library and torch share it
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover - torch is optional for the binding
+    torch = None
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EUNSUPPORTED, LBM_EUNSTABLE, LBM_EDEVICE = 0, -1, -2, -3, -4, -5
+LBM_D2Q9, LBM_D3Q19 = 0, 1
+LBM_BGK, LBM_RR, LBM_HRR = 0, 1, 2
+LBM_FP64, LBM_FP32_DEV = 0, 1
+LBM_HOST, LBM_DEVICE = 0, 1
+
+EXPORTS = (
+    "lbm_create_grid", "lbm_destroy", "lbm_set_state", "lbm_step", "lbm_get_macros",
+    "lbm_set_populations", "lbm_get_populations", "lbm_get_totals", "lbm_get_index_maps",
+    "lbm_level_dims", "lbm_lattice_info", "lbm_interface_counts", "lbm_interface_tables",
+    "lbm_updates_per_step", "lbm_profile_enable", "lbm_kernel_time", "lbm_last_error",
+)
+
+
+class lbm_grid_desc(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int32), ("collision", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("n", ctypes.c_int32 * 3), ("lo", ctypes.c_int32 * 3), ("hi", ctypes.c_int32 * 3),
+        ("tau_coarse", ctypes.c_double), ("sigma", ctypes.c_double),
+        ("device", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lbm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads liblbm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(path)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+    L.lbm_create_grid.argtypes = [ctypes.POINTER(lbm_grid_desc), ctypes.POINTER(vp)]
+    L.lbm_destroy.argtypes = [vp]
+    L.lbm_set_state.argtypes = [vp, ip, vp, vp, ip]
+    L.lbm_step.argtypes = [vp, ip, vp]
+    L.lbm_get_macros.argtypes = [vp, ip, vp, vp, ip]
+    L.lbm_set_populations.argtypes = [vp, ip, vp, ip]
+    L.lbm_get_populations.argtypes = [vp, ip, vp, ip]
+    L.lbm_get_totals.argtypes = [vp, dp, dp]
+    L.lbm_get_index_maps.argtypes = [vp, ip, vp, ip]
+    L.lbm_level_dims.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int32)]
+    L.lbm_lattice_info.argtypes = [ip, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32), dp]
+    L.lbm_interface_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.lbm_interface_tables.argtypes = [vp, vp, vp, vp, vp]
+    L.lbm_updates_per_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.lbm_profile_enable.argtypes = [vp, ip]
+    L.lbm_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), dp, ctypes.POINTER(ctypes.c_int64)]
+    L.lbm_last_error.argtypes = [vp]
+    L.lbm_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc, h=None):
+    if rc != LBM_OK:
+        msg = load().lbm_last_error(h)
+        raise LbmError(rc, msg.decode() if msg else "")
+
+
+def _ptr(a):
+    """Host numpy array or device torch tensor -> (pointer, mem)."""
+    if isinstance(a, np.ndarray):
+        return ctypes.c_void_p(a.ctypes.data), LBM_HOST
+    if torch is not None and isinstance(a, torch.Tensor):
+        return ctypes.c_void_p(a.data_ptr()), (LBM_DEVICE if a.is_cuda else LBM_HOST)
+    raise TypeError(type(a))
+
+
+def lbm_lattice_info(lattice: int):
+    D = ctypes.c_int32()
+    Q = ctypes.c_int32()
+    xi = (ctypes.c_int32 * 57)()
+    w = (ctypes.c_double * 19)()
+    _check(load().lbm_lattice_info(lattice, ctypes.byref(D), ctypes.byref(Q), xi, w))
+    q = Q.value
+    return D.value, q, np.array(xi[: 3 * q], np.int32).reshape(q, 3), np.array(w[:q])
+
+
+def lbm_create_grid(lattice, collision, precision, n, lo=None, hi=None, tau_coarse=0.51, sigma=0.995, device=0):
+    d = lbm_grid_desc()
+    d.lattice, d.collision, d.precision = lattice, collision, precision
+    D = 2 if lattice == LBM_D2Q9 else 3
+    nn = list(n) + [1] * (3 - len(n))
+    lo = list(lo if lo is not None else [0] * D) + [0] * (3 - D)
+    hi = list(hi if hi is not None else [0] * D) + [0] * (3 - D)
+    for k in range(3):
+        d.n[k], d.lo[k], d.hi[k] = int(nn[k]), int(lo[k]), int(hi[k])
+    d.tau_coarse, d.sigma, d.device, d.reserved = float(tau_coarse), float(sigma), int(device), 0
+    h = ctypes.c_void_p()
+    rc = load().lbm_create_grid(ctypes.byref(d), ctypes.byref(h))
+    if rc != LBM_OK:
+        raise LbmError(rc, load().lbm_last_error(None).decode())
+    return h
+
+
+def lbm_destroy(h):
+    _check(load().lbm_destroy(h))
+
+
+def lbm_level_dims(h, level):
+    d = (ctypes.c_int32 * 3)()
+    _check(load().lbm_level_dims(h, level, d), h)
+    return tuple(d)
+
+
+def lbm_set_state(h, level, rho, u):
+    pr, m1 = _ptr(rho)
+    pu, m2 = _ptr(u)
+    assert m1 == m2
+    _check(load().lbm_set_state(h, level, pr, pu, m1), h)
+
+
+def lbm_step(h, n, stream=None):
+    _check(load().lbm_step(h, int(n), ctypes.c_void_p(stream) if stream else None), h)
+
+
+def lbm_get_macros(h, level, rho, u):
+    pr, m1 = _ptr(rho)
+    pu, m2 = _ptr(u)
+    assert m1 == m2
+    _check(load().lbm_get_macros(h, level, pr, pu, m1), h)
+
+
+def lbm_set_populations(h, level, f):
+    p, m = _ptr(f)
+    _check(load().lbm_set_populations(h, level, p, m), h)
+
+
+def lbm_get_populations(h, level, f):
+    p, m = _ptr(f)
+    _check(load().lbm_get_populations(h, level, p, m), h)
+
+
+def lbm_get_totals(h):
+    mass = (ctypes.c_double * 2)()
+    mom = (ctypes.c_double * 6)()
+    _check(load().lbm_get_totals(h, mass, mom), h)
+    return np.array(mass[:]), np.array(mom[:]).reshape(2, 3)
+
+
+def lbm_get_index_maps(h, level, out):
+    p, m = _ptr(out)
+    _check(load().lbm_get_index_maps(h, level, p, m), h)
+
+
+def lbm_interface_counts(h):
+    c = (ctypes.c_int64 * 3)()
+    _check(load().lbm_interface_counts(h, c), h)
+    return tuple(c)
+
+
+def lbm_interface_tables(h):
+    nh, nr, _ = lbm_interface_counts(h)
+    hn = np.zeros(nh, np.int64)
+    rn = np.zeros(nr, np.int64)
+    rnp = np.zeros(nr, np.int32)
+    rpt = np.zeros((nr, 16), np.int64)
+    _check(load().lbm_interface_tables(h, hn.ctypes.data, rn.ctypes.data, rnp.ctypes.data, rpt.ctypes.data), h)
+    return hn, rn, rnp, rpt
+
+
+def lbm_updates_per_step(h):
+    v = ctypes.c_int64()
+    _check(load().lbm_updates_per_step(h, ctypes.byref(v)), h)
+    return v.value
+
+
+def lbm_profile_enable(h, on=True):
+    _check(load().lbm_profile_enable(h, 1 if on else 0), h)
+
+
+def lbm_kernel_time(h):
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    nodes = ctypes.c_int64()
+    _check(load().lbm_kernel_time(h, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(nodes)), h)
+    return n.value, ms.value, nodes.value
+
+
+class Grid:
+    """Convenience wrapper over one handle (host numpy arrays in and out)."""
+
+    def __init__(self, lattice, collision, precision, n, lo=None, hi=None, tau_coarse=0.51, sigma=0.995, device=0):
+        self.h = lbm_create_grid(lattice, collision, precision, n, lo, hi, tau_coarse, sigma, device)
+        self.D, self.Q, self.xi, self.w = lbm_lattice_info(lattice)
+        self.lattice, self.collision, self.precision = lattice, collision, precision
+
+    def close(self):
+        if self.h:
+            lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def dims(self, level):
+        return lbm_level_dims(self.h, level)
+
+    def nodes(self, level):
+        a, b, c = self.dims(level)
+        return a * b * c
+
+    def set_state(self, level, rho, u):
+        N = self.nodes(level)
+        lbm_set_state(self.h, level, np.ascontiguousarray(rho, np.float64).reshape(N),
+                      np.ascontiguousarray(u, np.float64).reshape(self.D, N))
+
+    def step(self, n=1, stream=None):
+        lbm_step(self.h, n, stream)
+
+    def get_macros(self, level):
+        N = self.nodes(level)
+        rho = np.zeros(N)
+        u = np.zeros((self.D, N))
+        lbm_get_macros(self.h, level, rho, u)
+        return rho, u
+
+    def set_populations(self, level, f):
+        lbm_set_populations(self.h, level, np.ascontiguousarray(f, np.float64).reshape(self.Q, self.nodes(level)))
+
+    def get_populations(self, level):
+        f = np.zeros((self.Q, self.nodes(level)))
+        lbm_get_populations(self.h, level, f)
+        return f
+
+    def totals(self):
+        return lbm_get_totals(self.h)
+
+    def class_map(self, level):
+        out = np.zeros(self.nodes(level), np.uint8)
+        lbm_get_index_maps(self.h, level, out)
+        return out
+
+    def updates_per_step(self):
+        return lbm_updates_per_step(self.h)

@@ -1,0 +1,142 @@
+"""GPU parity: the HIP library against the CPU oracle, element by element,
+on the same seeded inputs.  FP64 results must agree to 1e-12 relative;
+interface index maps and stencil tables must be identical."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2004_11863_amd import inputs as I
+from parity_util import compare_fp64, make_pair
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _lbm():
+    from paper_2004_11863_amd import lbm
+    return lbm
+
+
+def _geom(D, n, lo, hi):
+    nn = tuple(n) + (1,) * (3 - D)
+    return I.Geometry(D, nn, tuple(lo) + (0,) * (3 - D), tuple(hi) + (0,) * (3 - D))
+
+
+@pytest.mark.parametrize("D,n,lo,hi", [(2, (64, 64), (16, 16), (48, 48)), (2, (67, 53), (5, 7), (30, 40)),
+                                       (2, (20, 20), (2, 2), (17, 6)),
+                                       (3, (24, 24, 24), (6, 6, 6), (17, 17, 17)),
+                                       (3, (21, 19, 23), (3, 5, 2), (12, 14, 20))])
+def test_index_maps_and_tables_bit_exact(D, n, lo, hi):
+    lbm = _lbm()
+    lg = lbm.LBM_D2Q9 if D == 2 else lbm.LBM_D3Q19
+    gpu = lbm.Grid(lg, lbm.LBM_RR, lbm.LBM_FP64, n, lo, hi)
+    ref = O.Grid(O.D2Q9 if D == 2 else O.D3Q19, O.RR, n, lo, hi)
+    for lv in (0, 1):
+        assert np.array_equal(gpu.class_map(lv), ref.class_map(lv))
+    hn, rn, rnp, rpt = lbm.lbm_interface_tables(gpu.h)
+    hn0 = ref.history_nodes()
+    rn0, rnp0, rpt0, _ = ref.ring_stencils()
+    assert np.array_equal(hn, hn0)
+    assert np.array_equal(rn, rn0)
+    assert np.array_equal(rnp, rnp0)
+    assert np.array_equal(rpt, rpt0)
+    gpu.close()
+
+
+@pytest.mark.parametrize("model", ["BGK", "RR", "HRR"])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_fp64_d2q9_config1(model, seed):
+    lbm = _lbm()
+    wl = I.config1(seed)
+    gpu, ref, levels = make_pair(wl, model, lbm.LBM_FP64)
+    steps = 200 if seed == 0 else 60
+    gpu.step(steps)
+    ref.step(steps)
+    w = compare_fp64(gpu, ref, levels)
+    gpu.close()
+    assert max(w.values()) <= TOL64, w
+
+
+@pytest.mark.parametrize("model", ["BGK", "RR", "HRR"])
+def test_fp64_d2q9_ragged(model):
+    lbm = _lbm()
+    geom = _geom(2, (67, 53), (5, 7), (30, 40))
+    wl = I.Workload(geom=geom, U=(0.05, -0.02, 0.0),
+                    vortices=[I.Vortex(center=(29.3, 20.7), eps=0.02, U=(0.05, -0.02, 0.0))],
+                    pulses=[I.Pulse(center=(10.0, 45.0), A=1e-3)])
+    gpu, ref, levels = make_pair(wl, model, lbm.LBM_FP64, tau_c=0.55)
+    gpu.step(40)
+    ref.step(40)
+    w = compare_fp64(gpu, ref, levels)
+    gpu.close()
+    assert max(w.values()) <= TOL64, w
+
+
+@pytest.mark.parametrize("D", [2, 3])
+@pytest.mark.parametrize("model", ["BGK", "RR", "HRR"])
+def test_fp64_uniform_grid(D, model):
+    lbm = _lbm()
+    n = (70, 33) if D == 2 else (20, 18, 13)
+    geom = _geom(D, n, (0,) * D, (0,) * D)
+    wl = I.Workload(geom=geom, U=(0.05, 0.01, 0.0), pulses=[I.Pulse(center=tuple(x / 2 for x in n), A=1e-2, R=3.0)])
+    gpu, ref, levels = make_pair(wl, model, lbm.LBM_FP64, tau_c=0.6)
+    gpu.step(30)
+    ref.step(30)
+    w = compare_fp64(gpu, ref, levels)
+    gpu.close()
+    assert max(w.values()) <= TOL64, w
+
+
+@pytest.mark.parametrize("model", ["BGK", "RR", "HRR"])
+def test_fp64_d3q19_two_level_small(model):
+    lbm = _lbm()
+    geom = _geom(3, (22, 20, 24), (5, 4, 6), (15, 14, 17))
+    U = (0.1 / np.sqrt(3), 0.01, -0.005)
+    wl = I.Workload(geom=geom, U=U, pulses=[I.Pulse(center=(15.2, 9.6, 11.1), A=1e-3, R=2.5)])
+    gpu, ref, levels = make_pair(wl, model, lbm.LBM_FP64, tau_c=0.51)
+    gpu.step(25)
+    ref.step(25)
+    w = compare_fp64(gpu, ref, levels)
+    gpu.close()
+    assert max(w.values()) <= TOL64, w
+
+
+@pytest.mark.parametrize("model", ["RR", "HRR"])
+def test_fp64_d3q19_64cube_subcase(model):
+    lbm = _lbm()
+    wl = I.config3(seed=0, n=64)
+    gpu, ref, levels = make_pair(wl, model, lbm.LBM_FP64, tau_c=0.51)
+    gpu.step(6)
+    ref.step(6)
+    w = compare_fp64(gpu, ref, levels)
+    gpu.close()
+    assert max(w.values()) <= TOL64, w
+
+
+def test_totals_match_oracle():
+    lbm = _lbm()
+    wl = I.config1(2)
+    gpu, ref, levels = make_pair(wl, "RR", lbm.LBM_FP64)
+    gpu.step(30)
+    ref.step(30)
+    m1, p1 = gpu.totals()
+    m0, p0 = ref.totals()
+    gpu.close()
+    assert np.abs(m1 - m0).max() <= 1e-12 * np.abs(m0).max()
+    assert np.abs(p1 - p0).max() <= 1e-12 * np.abs(m0).max()
+
+
+def test_zero_steps_and_determinism():
+    lbm = _lbm()
+    wl = I.config1(3)
+    outs = []
+    for _ in range(2):
+        gpu, _, levels = make_pair(wl, "HRR", lbm.LBM_FP32_DEV, with_oracle=False)
+        f_before = gpu.get_populations(1)
+        gpu.step(0)
+        assert np.array_equal(gpu.get_populations(1), f_before)
+        gpu.step(15)
+        outs.append((gpu.get_populations(0), gpu.get_populations(1)))
+        gpu.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])

@@ -1,0 +1,71 @@
+"""Host-side checks of the C-ABI library: it loads, exports every function
+the header declares, reports the same lattice tables as the oracle, and
+rejects invalid descriptors (validation happens before any device call)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2004_11863_amd import lbm
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lbm.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(lbm_\w+)\s*\(", txt, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbm.load()
+    names = declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(lbm.EXPORTS)
+
+
+@pytest.mark.parametrize("lat,olat", [(lbm.LBM_D2Q9, O.D2Q9), (lbm.LBM_D3Q19, O.D3Q19)])
+def test_lattice_tables_agree_with_oracle(lat, olat):
+    D, Q, xi, w = lbm.lbm_lattice_info(lat)
+    D0, Q0, xi0, w0 = O.lattice(olat)
+    assert (D, Q) == (D0, Q0)
+    assert np.array_equal(xi, xi0)
+    assert np.array_equal(w, w0)
+
+
+BAD = [
+    dict(tau_coarse=0.5),
+    dict(tau_coarse=0.4),
+    dict(lo=(16, 16), hi=(19, 48)),       # m < 4
+    dict(lo=(1, 16), hi=(40, 48)),        # lo < 2
+    dict(lo=(16, 16), hi=(62, 48)),       # hi > n - 3
+    dict(collision=7),
+    dict(sigma=1.5, collision=lbm.LBM_HRR),
+]
+
+
+@pytest.mark.parametrize("kw", BAD)
+def test_invalid_descriptor_rejected(kw):
+    args = dict(lattice=lbm.LBM_D2Q9, collision=lbm.LBM_RR, precision=lbm.LBM_FP64, n=(64, 64),
+                lo=(16, 16), hi=(48, 48), tau_coarse=0.51, sigma=0.995)
+    args.update(kw)
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create_grid(**args)
+    assert e.value.code == lbm.LBM_EINVAL
+
+
+@pytest.mark.parametrize("lat,n,lo,hi", [(lbm.LBM_D2Q9, (64, 64), (16, 16), (48, 48)),
+                                         (lbm.LBM_D2Q9, (8, 9), (0, 0), (0, 0)),
+                                         (lbm.LBM_D3Q19, (24, 24, 24), (6, 6, 6), (17, 17, 17))])
+def test_valid_descriptor_passes_validation(lat, n, lo, hi):
+    """A valid descriptor gets past validation; without a GPU the library
+    then reports a device error, never EINVAL."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present: covered by the GPU tests")
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create_grid(lat, lbm.LBM_RR, lbm.LBM_FP64, n, lo, hi)
+    assert e.value.code == lbm.LBM_EDEVICE
