@@ -83,10 +83,12 @@ def make_gpu(wl, collision, precision):
     return grid
 
 
-def timed_run(grid, steps, warmup, profile):
+def timed_run(grid, steps, warmup, profile, tune=True):
     import torch
     from paper_2004_11863_amd import lbm
     stream = torch.cuda.current_stream().cuda_stream
+    if tune:
+        grid.variants = grid.tune(reps=3)
     grid.step(warmup, stream)
     torch.cuda.synchronize()
     if profile:
@@ -172,6 +174,7 @@ def main():
     pb = 4 if args.precision == "fp32" else 8
     alg_bytes = 2 * Q * pb * nodes
     achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
+    variants = getattr(grid, "variants", None)
     khash = kernel_source_hash()
     key = f"{args.workload}/{args.collision}/{args.precision}"
     traffic = stored_traffic(khash, key)
@@ -223,6 +226,7 @@ def main():
             "launches": launches,
             "mean_launch_ms": mean_ms,
         },
+        "kernel_variants": variants,
         "totals_finite": bool(all(map(lambda v: v == v, list(m) + list(p.ravel())))),
         "kernel_source_hash": khash,
     }

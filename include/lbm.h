@@ -116,8 +116,10 @@ int lbm_step(lbm_handle h, int n_coarse_steps, void* hip_stream);
 int lbm_get_macros(lbm_handle h, int level, double* rho, double* u, int mem);
 
 /* Post-collision populations f[Q][N] of one level (double precision, full
- * values, not deviations).  Setting them on the coarse level re-initialises
- * the history from their moments as lbm_set_state does.  Synchronous. */
+ * values, not deviations).  Covered coarse nodes do not evolve: their
+ * populations are unspecified.  Setting them on the coarse level
+ * re-initialises the history from their moments as lbm_set_state does.
+ * Synchronous. */
 int lbm_set_populations(lbm_handle h, int level, const double* f, int mem);
 int lbm_get_populations(lbm_handle h, int level, double* f, int mem);
 
@@ -154,6 +156,18 @@ int lbm_updates_per_step(lbm_handle h, int64_t* updates);
  * updates.  Synchronous. */
 int lbm_profile_enable(lbm_handle h, int on);
 int lbm_kernel_time(lbm_handle h, int64_t* launches, double* mean_ms, int64_t* nodes_per_launch);
+
+/* Autotuner: times every bulk-kernel variant (nodes per lane x lanes along
+ * x of the work group) of each bulk role of this grid -- coarse stream, fine
+ * stream, coarse and fine H-RR collision -- over reps launches on the grid's
+ * own data and keeps the fastest.  variants[4] receives the chosen index per
+ * role (roles the grid does not use keep their default).  Only buffers that
+ * the next lbm_step rewrites are touched, so the state is unchanged.
+ * Synchronous. */
+int lbm_tune(lbm_handle h, int reps, int32_t variants[4]);
+/* Sets the variant index per role (as returned by lbm_tune); LBM_EINVAL if
+ * an index is out of range for the grid's precision. */
+int lbm_set_variants(lbm_handle h, const int32_t variants[4]);
 
 /* Last error text for a handle (NULL: last failure of lbm_create_grid). */
 const char* lbm_last_error(lbm_handle h);

@@ -25,6 +25,9 @@ def flags():
         # no packed-FP32 instructions (v_pk_*_f32)
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
+        # contraction only inside one expression: the per-node arithmetic (and so
+        # the result) does not depend on how a kernel variant groups nodes
+        "-ffp-contract=on",
         "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     ]
 

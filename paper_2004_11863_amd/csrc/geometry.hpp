@@ -21,6 +21,10 @@ namespace lbm {
 enum CoarseClass : int { CC_MIDDLE = 0, CC_TF = 1, CC_TN = 2, CC_COVERED = 3 };
 enum FineClass : int { FC_MIDDLE = 0, FC_TF = 1, FC_IE = 2, FC_IEFACE = 3, FC_TN = 4 };
 
+// Device arrays use a padded row pitch (pc, pf: nodes per row rounded up to
+// a multiple of 4) so every row starts 16-byte aligned; Ncp, Nfp are the
+// padded node counts of one population plane.  Nc, Nf count logical nodes
+// (the x-fastest order of the C ABI and of the interface tables).
 struct Geo {
   int D;
   int n[3];   // coarse nodes per axis (1 on unused axes)
@@ -29,7 +33,35 @@ struct Geo {
   int nf[3];  // fine nodes per axis (2m+1; 1 on unused axes or without patch)
   int has_fine;
   int64_t Nc, Nf;
+  int pc, pf;        // row pitch of coarse / fine device arrays
+  int fxo;           // offset of fine node x = 0 inside its row: the first
+                     // middle node (x = 1) starts a 16-byte boundary
+  int64_t Ncp, Nfp;  // padded plane sizes
 };
+
+constexpr int kPitchAlign = 4;
+__host__ __device__ inline int pitch_of(int nx) { return (nx + kPitchAlign - 1) / kPitchAlign * kPitchAlign; }
+
+// Padded device offset of a coarse / fine node.
+__host__ __device__ inline int64_t cpos(const Geo& g, int x, int y, int z) {
+  return (int64_t)x + (int64_t)g.pc * ((int64_t)y + (int64_t)g.n[1] * z);
+}
+__host__ __device__ inline int64_t fpos(const Geo& g, int x, int y, int z) {
+  return (int64_t)(x + g.fxo) + (int64_t)g.pf * ((int64_t)y + (int64_t)g.nf[1] * z);
+}
+// Logical node index -> coordinates.
+__host__ __device__ inline void cdecode(const Geo& g, int64_t i, int& x, int& y, int& z) {
+  x = (int)(i % g.n[0]);
+  const int64_t r = i / g.n[0];
+  y = (int)(r % g.n[1]);
+  z = (int)(r / g.n[1]);
+}
+__host__ __device__ inline void fdecode(const Geo& g, int64_t i, int& x, int& y, int& z) {
+  x = (int)(i % g.nf[0]);
+  const int64_t r = i / g.nf[0];
+  y = (int)(r % g.nf[1]);
+  z = (int)(r / g.nf[1]);
+}
 
 __host__ __device__ inline int coarse_class(const Geo& g, int x, int y, int z) {
   if (!g.has_fine) return CC_MIDDLE;

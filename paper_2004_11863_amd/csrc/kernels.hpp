@@ -1,16 +1,22 @@
 // kernels.hpp -- gfx950 kernels of the two-level LBM hot path.
 //
 // Layout in HBM: every level stores its populations structure-of-arrays,
-// s[q][node] with node = x + nx (y + ny z), in a ping-pong pair of buffers
-// (pull scheme: a step reads one buffer and writes the other).  The bulk
-// kernels are one work-item per node, 64-wide along x so a wavefront reads
-// and writes 64 consecutive nodes of one population per instruction.  Work
-// groups cover TX x TY node tiles; the tile index is remapped so that each of
-// the 8 XCDs (which receive work groups round-robin) gets one contiguous run
-// of tiles, keeping the +-y / +-z neighbour rows of a tile in the same L2.
+// s[q][z][y][x] with a padded row pitch (a multiple of 4 nodes, so rows start
+// 16-byte aligned), in a ping-pong pair of buffers (pull scheme: a step reads
+// one buffer and writes the other).
+//
+// Bulk kernels: one work-item updates V consecutive nodes of a row, so every
+// population is moved with one 16-byte access per lane (V = 4 in FP32, V = 2
+// in FP64); the streams shifted by +-1 along x use 4/8-byte-aligned 16-byte
+// loads, stores are aligned and non-temporal.  A work group is 64 lanes along
+// x times TY rows.  Work groups are handed to the 8 XCDs round-robin by the
+// hardware; the tile index is remapped so each XCD receives one contiguous
+// run of tiles, which keeps the +-y / +-z neighbour rows of a tile in the
+// same L2.
 //
 // Interface kernels (history capture, ring reconstruction, fine-to-coarse
-// coalescence) run one work-item per interface node in double precision.
+// coalescence) work per interface node in double precision, with small work
+// groups so the few thousand interface nodes spread over all CUs.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -20,35 +26,69 @@
 namespace lbm {
 
 constexpr int kXCD = 8;
+constexpr int kIfaceBlock = 64;
 
-// Model codes: BGK and RR collide in the streaming kernel; H-RR needs the
-// strain rate of neighbouring nodes and so streams first (kernel writes the
-// pre-collision state and rho, u) and collides in a second kernel.
+// Model codes: BGK and RR collide in the streaming kernel; the split H-RR
+// path streams first (kernel writes the pre-collision state and rho, u) and
+// collides in a second kernel that reads neighbouring velocities.
 enum Model : int { M_BGK = 0, M_RR = 1, M_HRR = 2 };
 
-struct Tiling {
-  int nx, ny, nz;     // level extent
-  int ntx, nty;       // tiles per axis
-  int ntiles;         // ntx * nty * nz
-  int per_xcd;        // tiles given to each XCD (launch = per_xcd * 8 groups)
+// 16-byte vectors: "a" is the aligned type, "u" the same vector with element
+// alignment only (used for the x-shifted loads).
+template <typename S, int V>
+struct VT;
+template <>
+struct VT<float, 4> {
+  typedef float a __attribute__((ext_vector_type(4)));
+  typedef float u __attribute__((ext_vector_type(4), aligned(4)));
+};
+template <>
+struct VT<float, 2> {
+  typedef float a __attribute__((ext_vector_type(2)));
+  typedef float u __attribute__((ext_vector_type(2), aligned(4)));
+};
+template <>
+struct VT<double, 2> {
+  typedef double a __attribute__((ext_vector_type(2)));
+  typedef double u __attribute__((ext_vector_type(2), aligned(8)));
 };
 
-template <int TX, int TY>
-inline Tiling make_tiling(int nx, int ny, int nz) {
+template <bool NT, typename A>
+__device__ inline void vstore(A* p, const A& v) {
+  if (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// A work group is LX lanes along x times TY rows (LX * TY = 256); each lane
+// owns V consecutive nodes starting at xb + V k.  The fine level starts at
+// xb = 1 (its first middle node, 16-byte aligned in storage); the coarse
+// level at xb = 0.
+struct Tiling {
+  int nx, ny, nz;  // level extent (nodes)
+  int xb;          // first node of the vector grid along x
+  int nv;          // vectors per row
+  int ntx, nty;    // tiles per axis
+  int ntiles;      // ntx * nty * nz
+  int per_xcd;     // tiles given to each XCD (launch = per_xcd * 8 groups)
+};
+
+inline Tiling make_tiling(int nx, int ny, int nz, int xb, int V, int LX, int TY) {
   Tiling t;
   t.nx = nx;
   t.ny = ny;
   t.nz = nz;
-  t.ntx = (nx + TX - 1) / TX;
+  t.xb = xb;
+  t.nv = (nx - xb + V - 1) / V;
+  t.ntx = (t.nv + LX - 1) / LX;
   t.nty = (ny + TY - 1) / TY;
   t.ntiles = t.ntx * t.nty * nz;
   t.per_xcd = (t.ntiles + kXCD - 1) / kXCD;
   return t;
 }
 
-// Node of this work-item; false when outside the level.
-template <int TX, int TY>
-__device__ inline bool tile_node(const Tiling& t, int& x, int& y, int& z) {
+// First node x0 of this work-item's V-node vector; false outside the level.
+template <int V, int LX, int TY>
+__device__ inline bool tile_vec(const Tiling& t, int& x0, int& y, int& z) {
   const int b = blockIdx.x;
   const int tile = (b % kXCD) * t.per_xcd + b / kXCD;
   if (tile >= t.ntiles) return false;
@@ -56,120 +96,186 @@ __device__ inline bool tile_node(const Tiling& t, int& x, int& y, int& z) {
   const int r = tile / t.ntx;
   const int ty = r % t.nty;
   z = r / t.nty;
-  x = tx * TX + (int)(threadIdx.x % TX);
-  y = ty * TY + (int)(threadIdx.x / TX);
-  return x < t.nx && y < t.ny;
+  const int vi = tx * LX + (int)(threadIdx.x % LX);
+  x0 = t.xb + vi * V;
+  y = ty * TY + (int)(threadIdx.x / LX);
+  return vi < t.nv && y < t.ny;
 }
 
-template <typename S, bool DEV, typename T>
-__device__ inline T load_pop(const S* p) {
-  return (T)(*p);
+// x coordinate wrapped into [0, n) (any displacement).
+__device__ inline int wrapx(int x, int n) {
+  while (x < 0) x += n;
+  while (x >= n) x -= n;
+  return x;
+}
+
+// Loads the V values of one population row starting at x0 - cx.  Coarse
+// rows are periodic: vectors that cross a row end are gathered element-wise.
+template <typename S, int V, int LEVEL>
+__device__ inline typename VT<S, V>::a load_row(const S* __restrict__ row, int x0, int cx, int nx) {
+  using VA = typename VT<S, V>::a;
+  using VU = typename VT<S, V>::u;
+  const int xs = x0 - cx;
+  if (LEVEL == 0 && cx != 0 && (xs < 0 || xs + V > nx)) {
+    VA v;
+#pragma unroll
+    for (int k = 0; k < V; ++k) v[k] = row[wrapx(xs + k, nx)];
+    return v;
+  }
+  if (cx == 0) return *(const VA*)(row + xs);
+  return (VA)(*(const VU*)(row + xs));
+}
+
+// Skip test shared by the bulk kernels: fine ring rows/planes (the ring
+// columns are computed and later overwritten by the ring kernel) and coarse
+// vectors lying wholly inside the covered box.
+template <int LEVEL, int D>
+__device__ inline bool skip_vec(const Geo& g, int x0, int V, int y, int z, int nx, int ny, int nz) {
+  if (LEVEL == 1) return y == 0 || y == ny - 1 || (D == 3 && (z == 0 || z == nz - 1));
+  if (!g.has_fine) return false;
+  const int xl = min(x0 + V - 1, nx - 1);
+  return coarse_class(g, x0, y, z) == CC_COVERED && coarse_class(g, xl, y, z) == CC_COVERED;
 }
 
 // ---------------------------------------------------------------------------
-// Bulk stream (+ collide) of one level.
-//   LEVEL 0: coarse, periodic, skips TN and covered nodes.
-//   LEVEL 1: fine patch, skips the ring (reconstructed from the coarse level).
-// MODEL BGK/RR: dst = collide(pull(src)).  MODEL HRR: dst = pull(src),
-// mac = (rho, u) of the pulled state.
-template <int LAT, bool DEV, typename S, typename T, int MODEL, int LEVEL, int TX, int TY>
-__global__ __launch_bounds__(TX* TY) void k_stream(const S* __restrict__ src, S* __restrict__ dst,
-                                                    T* __restrict__ mac, const Geo g, const Tiling tl,
-                                                    const T om) {
+// Bulk pull-stream (+ collide) of one level.
+//   LEVEL 0: coarse, periodic.  LEVEL 1: fine patch.
+// MODEL BGK/RR: dst = collide(pull(src)).  MODEL HRR: dst = pull(src) and
+// mac = (rho, u) of the pulled state (padded planes of the level).
+// Every node of a processed vector is written, including coarse TN/covered
+// nodes and fine ring columns: the schedule overwrites TN and ring nodes
+// afterwards and never reads covered ones.
+template <int LAT, bool DEV, typename S, int MODEL, int LEVEL, int V, int LX, bool NT>
+__global__ __launch_bounds__(256) void k_stream(const S* __restrict__ src, S* __restrict__ dst, S* __restrict__ mac,
+                                                const Geo g, const Tiling tl, const S om) {
   using L = Lattice<LAT>;
-  using N = Node<LAT, DEV, T>;
+  using N = Node<LAT, DEV, S>;
+  using VA = typename VT<S, V>::a;
   constexpr int Q = L::Q;
-  int x, y, z;
-  if (!tile_node<TX, TY>(tl, x, y, z)) return;
+  constexpr int TY = 256 / LX;
+  int x0, y, z;
+  if (!tile_vec<V, LX, TY>(tl, x0, y, z)) return;
   const int nx = tl.nx, ny = tl.ny, nz = tl.nz;
-  if (LEVEL == 0) {
-    const int c = coarse_class(g, x, y, z);
-    if (c == CC_TN || c == CC_COVERED) return;
-  } else {
-    if (fine_is_ring(g, x, y, z)) return;
-  }
-  const size_t NN = (size_t)nx * ny * nz;
-  const size_t idx = (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z);
-  T s[Q];
+  if (skip_vec<LEVEL, L::D>(g, x0, V, y, z, nx, ny, nz)) return;
+  const int64_t P = LEVEL == 0 ? g.pc : g.pf;
+  const int64_t NP = LEVEL == 0 ? g.Ncp : g.Nfp;
+  const int xo = LEVEL == 0 ? 0 : g.fxo;
+  VA v[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    int xs = x - L::cx(i), ys = y - L::cy(i), zs = z - L::cz(i);
+    int ys = y - L::cy(i), zs = z - L::cz(i);
     if (LEVEL == 0) {
-      xs = wrap(xs, nx);
       ys = wrap(ys, ny);
       if (L::D == 3) zs = wrap(zs, nz);
     }
-    const size_t sidx = (size_t)xs + (size_t)nx * ((size_t)ys + (size_t)ny * zs);
-    s[i] = (T)src[(size_t)i * NN + sidx];
+    v[i] = load_row<S, V, LEVEL>(src + (int64_t)i * NP + P * ((int64_t)ys + (int64_t)ny * zs) + xo, x0, L::cx(i), nx);
   }
+  const int64_t own = P * ((int64_t)y + (int64_t)ny * z) + xo + x0;
   if (MODEL == M_HRR) {
-    T rho, r0, u[3];
-    N::moments(s, rho, r0, u);
-    mac[idx] = rho;
-    mac[NN + idx] = u[0];
-    mac[2 * NN + idx] = u[1];
-    if (L::D == 3) mac[3 * NN + idx] = u[2];
+    VA r, ux, uy, uz;
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      S s[Q], rho, r0, u[3];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) s[i] = v[i][k];
+      N::moments(s, rho, r0, u);
+      r[k] = rho;
+      ux[k] = u[0];
+      uy[k] = u[1];
+      uz[k] = u[2];
+    }
+    vstore<NT>((VA*)(mac + own), r);
+    vstore<NT>((VA*)(mac + NP + own), ux);
+    vstore<NT>((VA*)(mac + 2 * NP + own), uy);
+    if (L::D == 3) vstore<NT>((VA*)(mac + 3 * NP + own), uz);
   } else {
-    N::collide(s, MODEL, om, T(0), T(0), nullptr);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      S s[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) s[i] = v[i][k];
+      N::collide(s, MODEL, om, S(0), S(0), nullptr);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) v[i][k] = s[i];
+    }
   }
 #pragma unroll
-  for (int i = 0; i < Q; ++i) dst[(size_t)i * NN + idx] = (S)s[i];
-}
-
-// Centred differences of u (second order, level lattice units) -> strain.
-template <int D, typename T, typename IdxFn>
-__device__ inline Sym<T> strain_fd(const T* __restrict__ mac, size_t NN, IdxFn nb) {
-  // nb(axis, sign) -> node index of x + sign e_axis
-  T g[3][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
-#pragma unroll
-  for (int a = 0; a < D; ++a) {
-    const size_t ip = nb(a, +1), im = nb(a, -1);
-#pragma unroll
-    for (int b = 0; b < D; ++b) g[a][b] = (mac[(size_t)(1 + b) * NN + ip] - mac[(size_t)(1 + b) * NN + im]) * T(0.5);
-  }
-  Sym<T> S;
-  S.xx = g[0][0];
-  S.yy = g[1][1];
-  S.zz = (D == 3) ? g[2][2] : T(0);
-  S.xy = T(0.5) * (g[0][1] + g[1][0]);
-  S.xz = (D == 3) ? T(0.5) * (g[0][2] + g[2][0]) : T(0);
-  S.yz = (D == 3) ? T(0.5) * (g[1][2] + g[2][1]) : T(0);
-  return S;
+  for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + (int64_t)i * NP + own), v[i]);
 }
 
 // H-RR collision in place on a level, with the strain rate from centred
-// differences of the macroscopic velocity array (Sec. 3.3).
-template <int LAT, bool DEV, typename S, typename T, int LEVEL, int TX, int TY>
-__global__ __launch_bounds__(TX* TY) void k_collide_hrr(S* __restrict__ buf, const T* __restrict__ mac,
-                                                         const Geo g, const Tiling tl, const T om, const T tau,
-                                                         const T sig) {
+// differences (second order, level lattice units) of the velocity planes of
+// mac (Sec. 3.3).  Processes whole vectors like k_stream; the coarse pass runs
+// before the fine-to-coarse transfer overwrites TN nodes.
+template <int LAT, bool DEV, typename S, int LEVEL, int V, int LX, bool NT>
+__global__ __launch_bounds__(256) void k_collide_hrr(S* __restrict__ buf, const S* __restrict__ mac, const Geo g,
+                                                     const Tiling tl, const S om, const S tau, const S sig) {
   using L = Lattice<LAT>;
-  using N = Node<LAT, DEV, T>;
-  constexpr int Q = L::Q;
-  int x, y, z;
-  if (!tile_node<TX, TY>(tl, x, y, z)) return;
+  using N = Node<LAT, DEV, S>;
+  using VA = typename VT<S, V>::a;
+  constexpr int Q = L::Q, D = L::D;
+  constexpr int TY = 256 / LX;
+  int x0, y, z;
+  if (!tile_vec<V, LX, TY>(tl, x0, y, z)) return;
   const int nx = tl.nx, ny = tl.ny, nz = tl.nz;
-  if (LEVEL == 0) {
-    const int c = coarse_class(g, x, y, z);
-    if (c == CC_TN || c == CC_COVERED) return;
-  } else {
-    if (fine_is_ring(g, x, y, z)) return;
+  if (skip_vec<LEVEL, D>(g, x0, V, y, z, nx, ny, nz)) return;
+  const int64_t P = LEVEL == 0 ? g.pc : g.pf;
+  const int64_t NP = LEVEL == 0 ? g.Ncp : g.Nfp;
+  const int xo = LEVEL == 0 ? 0 : g.fxo;
+  const int64_t own = P * ((int64_t)y + (int64_t)ny * z) + xo + x0;
+  // velocity gradient: gr[a][b] = (u_b(x + e_a) - u_b(x - e_a)) / 2
+  VA gr[3][3];
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    const S* ub = mac + (int64_t)(1 + b) * NP + xo;
+    const S* rowc = ub + P * ((int64_t)y + (int64_t)ny * z);
+    gr[0][b] = (load_row<S, V, LEVEL>(rowc, x0, -1, nx) - load_row<S, V, LEVEL>(rowc, x0, 1, nx)) * S(0.5);
+    {
+      int yp = y + 1, ym = y - 1;
+      if (LEVEL == 0) {
+        yp = wrap(yp, ny);
+        ym = wrap(ym, ny);
+      }
+      const VA up = *(const VA*)(ub + P * ((int64_t)yp + (int64_t)ny * z) + x0);
+      const VA um = *(const VA*)(ub + P * ((int64_t)ym + (int64_t)ny * z) + x0);
+      gr[1][b] = (up - um) * S(0.5);
+    }
+    if (D == 3) {
+      int zp = z + 1, zm = z - 1;
+      if (LEVEL == 0) {
+        zp = wrap(zp, nz);
+        zm = wrap(zm, nz);
+      }
+      const VA up = *(const VA*)(ub + P * ((int64_t)y + (int64_t)ny * zp) + x0);
+      const VA um = *(const VA*)(ub + P * ((int64_t)y + (int64_t)ny * zm) + x0);
+      gr[2][b] = (up - um) * S(0.5);
+    }
   }
-  const size_t NN = (size_t)nx * ny * nz;
-  const size_t idx = (size_t)x + (size_t)nx * ((size_t)y + (size_t)ny * z);
-  auto nb = [&](int a, int sgn) -> size_t {
-    int c[3] = {x, y, z};
-    c[a] += sgn;
-    if (LEVEL == 0) c[a] = wrap(c[a], a == 0 ? nx : (a == 1 ? ny : nz));
-    return (size_t)c[0] + (size_t)nx * ((size_t)c[1] + (size_t)ny * c[2]);
-  };
-  const Sym<T> Sr = strain_fd<L::D, T>(mac, NN, nb);
-  T s[Q];
+  VA v[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) s[i] = (T)buf[(size_t)i * NN + idx];
-  N::collide(s, M_HRR, om, tau, sig, &Sr);
+  for (int i = 0; i < Q; ++i) v[i] = *(const VA*)(buf + (int64_t)i * NP + own);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) buf[(size_t)i * NN + idx] = (S)s[i];
+  for (int k = 0; k < V; ++k) {
+    Sym<S> Sr;
+    Sr.xx = gr[0][0][k];
+    Sr.yy = gr[1][1][k];
+    Sr.xy = S(0.5) * (gr[0][1][k] + gr[1][0][k]);
+    if (D == 3) {
+      Sr.zz = gr[2][2][k];
+      Sr.xz = S(0.5) * (gr[0][2][k] + gr[2][0][k]);
+      Sr.yz = S(0.5) * (gr[1][2][k] + gr[2][1][k]);
+    } else {
+      Sr.zz = Sr.xz = Sr.yz = S(0);
+    }
+    S s[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) s[i] = v[i][k];
+    N::collide(s, M_HRR, om, tau, sig, &Sr);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i][k] = s[i];
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(buf + (int64_t)i * NP + own), v[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -185,14 +291,14 @@ struct HF {
 
 struct Iface {
   int64_t NH;
-  const int64_t* hnode;   // [NH] coarse node of each history entry
+  const int64_t* hnode;  // [NH] coarse node (logical index) of each history entry
   int64_t NR;
-  const int64_t* rnode;   // [NR] fine node of each ring entry
-  const int32_t* rnp;     // [NR] stencil points (1, 4, 16)
-  const int32_t* rpt;     // [NR][16] history entries
+  const int64_t* rnode;  // [NR] fine node (logical index) of each ring entry
+  const int32_t* rnp;    // [NR] stencil points (1, 4, 16)
+  const int32_t* rpt;    // [NR][16] history entries
   int64_t NT;
-  const int64_t* tnf;     // [NT] fine TN nodes
-  const int64_t* tnc;     // [NT] coarse TN nodes
+  const int64_t* tnf;    // [NT] fine TN nodes (logical)
+  const int64_t* tnc;    // [NT] coarse TN nodes (logical)
 };
 
 template <typename S, bool DEV, int LAT>
@@ -214,16 +320,15 @@ __global__ void k_hist_capture(const S* __restrict__ src, double* __restrict__ H
   constexpr int Q = L::Q;
   const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= itf.NH) return;
-  const int64_t ci = itf.hnode[h];
+  int x, y, z;
+  cdecode(g, itf.hnode[h], x, y, z);
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-  const int x = (int)(ci % nx), y = (int)((ci / nx) % ny), z = (int)(ci / ((int64_t)nx * ny));
-  const size_t NN = (size_t)g.Nc;
   double f[Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int xs = wrap(x - L::cx(i), nx), ys = wrap(y - L::cy(i), ny);
     const int zs = L::D == 3 ? wrap(z - L::cz(i), nz) : 0;
-    f[i] = full_pop<S, DEV, LAT>(src[(size_t)i * NN + (size_t)xs + (size_t)nx * ((size_t)ys + (size_t)ny * zs)], i);
+    f[i] = full_pop<S, DEV, LAT>(src[(int64_t)i * g.Ncp + cpos(g, xs, ys, zs)], i);
   }
   double rho, r0, u[3], f0[Q];
   N::moments(f, rho, r0, u);
@@ -237,33 +342,36 @@ __global__ void k_hist_capture(const S* __restrict__ src, double* __restrict__ H
 }
 
 // H-RR: coarse strain rate at t+1 on the history nodes, by centred
-// differences of the coarse macroscopic velocity (TN entries come from the
+// differences of the coarse velocity planes (TN entries come from the
 // fictitious propagation on the fine level).
 template <int LAT, typename T>
 __global__ void k_hist_strain(const T* __restrict__ mac_c, double* __restrict__ H, const Geo g, const Iface itf) {
   using L = Lattice<LAT>;
   using F = HF<LAT>;
+  constexpr int D = L::D;
   const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= itf.NH) return;
-  const int64_t ci = itf.hnode[h];
-  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-  const int x = (int)(ci % nx), y = (int)((ci / nx) % ny), z = (int)(ci / ((int64_t)nx * ny));
-  auto nb = [&](int a, int sgn) -> size_t {
-    int c[3] = {x, y, z};
-    c[a] = wrap(c[a] + sgn, a == 0 ? nx : (a == 1 ? ny : nz));
-    return (size_t)c[0] + (size_t)nx * ((size_t)c[1] + (size_t)ny * c[2]);
-  };
-  const Sym<T> S = strain_fd<L::D, T>(mac_c, (size_t)g.Nc, nb);
+  int x, y, z;
+  cdecode(g, itf.hnode[h], x, y, z);
+  const int n3[3] = {g.n[0], g.n[1], g.n[2]};
+  double gr[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int a = 0; a < D; ++a) {
+    int cp[3] = {x, y, z}, cm[3] = {x, y, z};
+    cp[a] = wrap(cp[a] + 1, n3[a]);
+    cm[a] = wrap(cm[a] - 1, n3[a]);
+    const int64_t ip = cpos(g, cp[0], cp[1], cp[2]), im = cpos(g, cm[0], cm[1], cm[2]);
+    for (int b = 0; b < D; ++b) gr[a][b] = 0.5 * ((double)mac_c[(1 + b) * g.Ncp + ip] - (double)mac_c[(1 + b) * g.Ncp + im]);
+  }
   const int64_t NH = itf.NH;
-  H[(F::S + 0) * NH + h] = (double)S.xx;
-  H[(F::S + 1) * NH + h] = (double)S.yy;
-  if (L::D == 2) {
-    H[(F::S + 2) * NH + h] = (double)S.xy;
+  H[(F::S + 0) * NH + h] = gr[0][0];
+  H[(F::S + 1) * NH + h] = gr[1][1];
+  if (D == 2) {
+    H[(F::S + 2) * NH + h] = 0.5 * (gr[0][1] + gr[1][0]);
   } else {
-    H[(F::S + 2) * NH + h] = (double)S.zz;
-    H[(F::S + 3) * NH + h] = (double)S.xy;
-    H[(F::S + 4) * NH + h] = (double)S.xz;
-    H[(F::S + 5) * NH + h] = (double)S.yz;
+    H[(F::S + 2) * NH + h] = gr[2][2];
+    H[(F::S + 3) * NH + h] = 0.5 * (gr[0][1] + gr[1][0]);
+    H[(F::S + 4) * NH + h] = 0.5 * (gr[0][2] + gr[2][0]);
+    H[(F::S + 5) * NH + h] = 0.5 * (gr[1][2] + gr[2][1]);
   }
 }
 
@@ -311,10 +419,11 @@ __global__ void k_ring_macro(const double* __restrict__ Hm, const double* __rest
       v[k] += ws * (c0 * Hm[o] + c1 * H0[o] + c2 * Hp[o]);
     }
   }
-  const size_t NN = (size_t)g.Nf;
-  const size_t fi = (size_t)itf.rnode[r];
+  int x, y, z;
+  fdecode(g, itf.rnode[r], x, y, z);
+  const int64_t fi = fpos(g, x, y, z);
 #pragma unroll
-  for (int k = 0; k < 1 + L::D; ++k) mac_f[(size_t)k * NN + fi] = (T)v[k];
+  for (int k = 0; k < 1 + L::D; ++k) mac_f[(int64_t)k * g.Nfp + fi] = (T)v[k];
 }
 
 // Ring nodes: rho, u, f1 (and S) interpolated from the (time-interpolated)
@@ -363,137 +472,157 @@ __global__ void k_ring(const double* __restrict__ G, S* __restrict__ dst, const 
     }
   }
   N::collide(f, MODEL, om_f, tau_f, sig, &Sf);
-  const size_t NN = (size_t)g.Nf;
-  const size_t fi = (size_t)itf.rnode[r];
+  int x, y, z;
+  fdecode(g, itf.rnode[r], x, y, z);
+  const int64_t fi = fpos(g, x, y, z);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) dst[(size_t)i * NN + fi] = store_pop<S, DEV, LAT>(f[i], i);
+  for (int i = 0; i < Q; ++i) dst[(int64_t)i * g.Nfp + fi] = store_pop<S, DEV, LAT>(f[i], i);
 }
 
 // Pull of Q populations into fine node (x, y, z) from a fine buffer.
 template <int LAT, bool DEV, typename S>
 __device__ inline void pull_fine(const S* __restrict__ src, const Geo& g, int x, int y, int z, double* f) {
   using L = Lattice<LAT>;
-  const int nx = g.nf[0], ny = g.nf[1];
-  const size_t NN = (size_t)g.Nf;
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) {
-    const size_t sidx = (size_t)(x - L::cx(i)) + (size_t)nx * ((size_t)(y - L::cy(i)) + (size_t)ny * (z - L::cz(i)));
-    f[i] = full_pop<S, DEV, LAT>(src[(size_t)i * NN + sidx], i);
-  }
+  for (int i = 0; i < L::Q; ++i)
+    f[i] = full_pop<S, DEV, LAT>(src[(int64_t)i * g.Nfp + fpos(g, x - L::cx(i), y - L::cy(i), z - L::cz(i))], i);
 }
 
 // H-RR: fictitious propagation onto TN^f (Sec. 4.3, step e): u(TN, t+1) from
-// the fine post-collision state at t+1/2, written to the coarse macro array.
+// the fine post-collision state at t+1/2, written to the coarse macro planes.
 template <int LAT, bool DEV, typename S, typename T>
 __global__ void k_fict(const S* __restrict__ src_f, T* __restrict__ mac_c, const Geo g, const Iface itf) {
   using L = Lattice<LAT>;
   using N = Node<LAT, false, double>;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= itf.NT) return;
-  const int64_t fi = itf.tnf[t];
-  const int nx = g.nf[0], ny = g.nf[1];
-  const int x = (int)(fi % nx), y = (int)((fi / nx) % ny), z = (int)(fi / ((int64_t)nx * ny));
+  int x, y, z;
+  fdecode(g, itf.tnf[t], x, y, z);
   double f[L::Q], rho, r0, u[3];
   pull_fine<LAT, DEV, S>(src_f, g, x, y, z, f);
   N::moments(f, rho, r0, u);
-  const size_t NN = (size_t)g.Nc;
-  const size_t ci = (size_t)itf.tnc[t];
+  int cx, cy, cz;
+  cdecode(g, itf.tnc[t], cx, cy, cz);
+  const int64_t ci = cpos(g, cx, cy, cz);
   mac_c[ci] = (T)rho;
 #pragma unroll
-  for (int d = 0; d < L::D; ++d) mac_c[(size_t)(1 + d) * NN + ci] = (T)u[d];
+  for (int d = 0; d < L::D; ++d) mac_c[(int64_t)(1 + d) * g.Ncp + ci] = (T)u[d];
 }
 
-// Fine-to-coarse transfer at TN (Sec. 4.3, synchronous step d): the fine
+// Fine-to-coarse transfer at TN (Sec. 4.3, synchronous step d).  The fine
 // pre-collision state at t+1 around TN^f is re-pulled from the fine
 // post-collision state at t+1/2; its non-equilibrium part is filtered with
 // the tensor product of (1/4, 1/2, 1/4) (eq filterFneq), rescaled by
 // 2 tau_c / tau_f (eq rescfc) and added to f0 of the co-located fine node;
 // H-RR takes S^c = 2 S^f (eq PijResc) with S^f by fine centred differences.
 // The coarse node is then collided with tau_c and stored.
+// One work group handles PER TN nodes: one lane per (TN node, stencil node)
+// computes that node's weighted non-equilibrium part into LDS, lanes per
+// (TN node, population) sum the stencil in a fixed order, and one lane per
+// TN node rebuilds and collides.
 template <int LAT, bool DEV, typename S, int MODEL>
-__global__ void k_coalesce(const S* __restrict__ src_f, S* __restrict__ dst_c, const Geo g, const Iface itf,
-                           double kc, double om_c, double tau_c, double sig) {
+__global__ __launch_bounds__(256) void k_coalesce(const S* __restrict__ src_f, S* __restrict__ dst_c, const Geo g,
+                                                  const Iface itf, double kc, double om_c, double tau_c, double sig) {
   using L = Lattice<LAT>;
   using N = Node<LAT, false, double>;
   constexpr int Q = L::Q, D = L::D;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= itf.NT) return;
-  const int64_t fi = itf.tnf[t];
-  const int nx = g.nf[0], ny = g.nf[1];
-  const int x = (int)(fi % nx), y = (int)((fi / nx) % ny), z = (int)(fi / ((int64_t)nx * ny));
-  double ft[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) ft[i] = 0.0;
-  double rc = 0.0, uc[3] = {0.0, 0.0, 0.0};
-  double up[3][3] = {{0}}, um[3][3] = {{0}};  // u at x +- e_a
   constexpr int NST = (D == 2) ? 9 : 27;
-  for (int s = 0; s < NST; ++s) {
+  constexpr int PER = 256 / NST;
+  constexpr int CEN = (D == 2) ? 4 : 13;
+  __shared__ double sf1[PER][NST][Q];
+  __shared__ double sm[PER][NST][4];
+  __shared__ double sacc[PER][Q];
+  const int lt = threadIdx.x / NST, s = threadIdx.x % NST;
+  const int64_t t = (int64_t)blockIdx.x * PER + lt;
+  if (lt < PER && t < itf.NT) {
+    int x, y, z;
+    fdecode(g, itf.tnf[t], x, y, z);
     const int ox = s % 3 - 1, oy = (s / 3) % 3 - 1, oz = (D == 3) ? s / 9 - 1 : 0;
     double f[Q], rho, r0, u[3], f0[Q];
     pull_fine<LAT, DEV, S>(src_f, g, x + ox, y + oy, z + oz, f);
     N::moments(f, rho, r0, u);
     N::feq(rho, r0, u, f0);
-    const int nz = (ox != 0) + (oy != 0) + (oz != 0);
-    const double w = (nz == 0 ? 1.0 : 1.0) * (ox ? 0.25 : 0.5) * (oy ? 0.25 : 0.5) * (D == 3 ? (oz ? 0.25 : 0.5) : 1.0);
+    const double w = (ox ? 0.25 : 0.5) * (oy ? 0.25 : 0.5) * (D == 3 ? (oz ? 0.25 : 0.5) : 1.0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) ft[i] += w * (f[i] - f0[i]);
-    if (nz == 0) {
-      rc = rho;
-      uc[0] = u[0];
-      uc[1] = u[1];
-      uc[2] = u[2];
-    } else if (nz == 1) {
-      const int a = ox ? 0 : (oy ? 1 : 2);
-      const int sg = ox + oy + oz;
-      for (int b = 0; b < 3; ++b) {
-        if (sg > 0) up[a][b] = u[b];
-        else um[a][b] = u[b];
-      }
-    }
+    for (int i = 0; i < Q; ++i) sf1[lt][s][i] = w * (f[i] - f0[i]);
+    sm[lt][s][0] = rho;
+    sm[lt][s][1] = u[0];
+    sm[lt][s][2] = u[1];
+    sm[lt][s][3] = u[2];
   }
+  __syncthreads();
+  for (int p = threadIdx.x; p < PER * Q; p += blockDim.x) {
+    const int l2 = p / Q, q = p % Q;
+    double acc = 0.0;
+    for (int k = 0; k < NST; ++k) acc += sf1[l2][k][q];
+    sacc[l2][q] = acc;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x >= PER) return;
+  const int l3 = threadIdx.x;
+  const int64_t t3 = (int64_t)blockIdx.x * PER + l3;
+  if (t3 >= itf.NT) return;
+  const double rc = sm[l3][CEN][0];
+  double uc[3] = {sm[l3][CEN][1], sm[l3][CEN][2], sm[l3][CEN][3]};
   double f[Q];
   N::feq(rc, rc, uc, f);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) f[i] += kc * ft[i];
+  for (int i = 0; i < Q; ++i) f[i] += kc * sacc[l3][i];
   Sym<double> Sc{0, 0, 0, 0, 0, 0};
   if (MODEL == M_HRR) {
-    double gr[3][3] = {{0}};
+    // neighbours along +-x, +-y, +-z are stencil entries CEN +- 1, 3, 9
+    const int st[3] = {1, 3, 9};
+    double gr[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     for (int a = 0; a < D; ++a)
-      for (int b = 0; b < D; ++b) gr[a][b] = 0.5 * (up[a][b] - um[a][b]);
+      for (int b = 0; b < D; ++b) gr[a][b] = 0.5 * (sm[l3][CEN + st[a]][1 + b] - sm[l3][CEN - st[a]][1 + b]);
     Sc.xx = 2.0 * gr[0][0];
     Sc.yy = 2.0 * gr[1][1];
-    Sc.zz = (D == 3) ? 2.0 * gr[2][2] : 0.0;
     Sc.xy = 2.0 * (0.5 * (gr[0][1] + gr[1][0]));
-    Sc.xz = (D == 3) ? 2.0 * (0.5 * (gr[0][2] + gr[2][0])) : 0.0;
-    Sc.yz = (D == 3) ? 2.0 * (0.5 * (gr[1][2] + gr[2][1])) : 0.0;
+    if (D == 3) {
+      Sc.zz = 2.0 * gr[2][2];
+      Sc.xz = 2.0 * (0.5 * (gr[0][2] + gr[2][0]));
+      Sc.yz = 2.0 * (0.5 * (gr[1][2] + gr[2][1]));
+    }
   }
   N::collide(f, MODEL, om_c, tau_c, sig, &Sc);
-  const size_t NN = (size_t)g.Nc;
-  const size_t ci = (size_t)itf.tnc[t];
+  int cx, cy, cz;
+  cdecode(g, itf.tnc[t3], cx, cy, cz);
+  const int64_t ci = cpos(g, cx, cy, cz);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) dst_c[(size_t)i * NN + ci] = store_pop<S, DEV, LAT>(f[i], i);
+  for (int i = 0; i < Q; ++i) dst_c[(int64_t)i * g.Ncp + ci] = store_pop<S, DEV, LAT>(f[i], i);
 }
 
 // ---------------------------------------------------------------------------
-// State transfer kernels.
+// State transfer kernels (logical x-fastest arrays <-> padded device planes).
 
-// Equilibrium populations of given fields: s = f0(rho, u) - DEV w.
 template <int LAT, bool DEV, typename S>
 __global__ void k_set_state(const double* __restrict__ rho, const double* __restrict__ u, S* __restrict__ dst,
-                            int64_t NN) {
+                            const Geo g, int level) {
   using L = Lattice<LAT>;
   using N = Node<LAT, false, double>;
+  const int64_t NN = level == 0 ? g.Nc : g.Nf;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= NN) return;
+  int x, y, z;
+  int64_t pos, NP;
+  if (level == 0) {
+    cdecode(g, k, x, y, z);
+    pos = cpos(g, x, y, z);
+    NP = g.Ncp;
+  } else {
+    fdecode(g, k, x, y, z);
+    pos = fpos(g, x, y, z);
+    NP = g.Nfp;
+  }
   double uu[3] = {u[k], u[NN + k], L::D == 3 ? u[2 * NN + k] : 0.0};
   double f[L::Q];
   N::feq(rho[k], rho[k], uu, f);
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) dst[(size_t)i * NN + k] = store_pop<S, DEV, LAT>(f[i], i);
+  for (int i = 0; i < L::Q; ++i) dst[(int64_t)i * NP + pos] = store_pop<S, DEV, LAT>(f[i], i);
 }
 
-// History at t = 0 from coarse fields rho, u (full coarse arrays): all three
-// levels get rho, u, f1 = 0 and S = centred differences of u.
+// History at t = 0 from coarse fields rho, u (logical coarse arrays): all
+// three levels get rho, u, f1 = 0 and S = centred differences of u.
 template <int LAT>
 __global__ void k_hist_init(const double* __restrict__ rho, const double* __restrict__ u, double* __restrict__ H0,
                             double* __restrict__ H1, double* __restrict__ H2, const Geo g, const Iface itf) {
@@ -502,22 +631,23 @@ __global__ void k_hist_init(const double* __restrict__ rho, const double* __rest
   const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= itf.NH) return;
   const int64_t ci = itf.hnode[h];
+  int x, y, z;
+  cdecode(g, ci, x, y, z);
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-  const int x = (int)(ci % nx), y = (int)((ci / nx) % ny), z = (int)(ci / ((int64_t)nx * ny));
-  const size_t NN = (size_t)g.Nc;
+  const int64_t NN = g.Nc;
   double v[F::N];
   v[F::RHO] = rho[ci];
-  for (int d = 0; d < L::D; ++d) v[F::U + d] = u[(size_t)d * NN + ci];
+  for (int d = 0; d < L::D; ++d) v[F::U + d] = u[d * NN + ci];
   for (int i = 0; i < L::Q; ++i) v[F::F1 + i] = 0.0;
-  double gr[3][3] = {{0}};
+  double gr[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   for (int a = 0; a < L::D; ++a) {
     int cp[3] = {x, y, z}, cm[3] = {x, y, z};
     const int na = a == 0 ? nx : (a == 1 ? ny : nz);
     cp[a] = wrap(cp[a] + 1, na);
     cm[a] = wrap(cm[a] - 1, na);
-    const size_t ip = (size_t)cp[0] + (size_t)nx * ((size_t)cp[1] + (size_t)ny * cp[2]);
-    const size_t im = (size_t)cm[0] + (size_t)nx * ((size_t)cm[1] + (size_t)ny * cm[2]);
-    for (int b = 0; b < L::D; ++b) gr[a][b] = 0.5 * (u[(size_t)b * NN + ip] - u[(size_t)b * NN + im]);
+    const int64_t ip = (int64_t)cp[0] + (int64_t)nx * ((int64_t)cp[1] + (int64_t)ny * cp[2]);
+    const int64_t im = (int64_t)cm[0] + (int64_t)nx * ((int64_t)cm[1] + (int64_t)ny * cm[2]);
+    for (int b = 0; b < L::D; ++b) gr[a][b] = 0.5 * (u[b * NN + ip] - u[b * NN + im]);
   }
   if (L::D == 2) {
     v[F::S] = gr[0][0];
@@ -539,8 +669,8 @@ __global__ void k_hist_init(const double* __restrict__ rho, const double* __rest
   }
 }
 
-// Moments of the stored post-collision state (double).  On the coarse level
-// covered nodes take the co-located fine node's values.
+// Moments of the stored post-collision state (double, logical order).  On the
+// coarse level covered nodes take the co-located fine node's values.
 template <int LAT, bool DEV, typename S>
 __global__ void k_macros(const S* __restrict__ src, const S* __restrict__ fine, double* __restrict__ rho,
                          double* __restrict__ u, const Geo g, int level) {
@@ -549,42 +679,75 @@ __global__ void k_macros(const S* __restrict__ src, const S* __restrict__ fine, 
   const int64_t NN = level == 0 ? g.Nc : g.Nf;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= NN) return;
+  int x, y, z;
   const S* p = src;
-  int64_t kk = k, MM = NN;
-  if (level == 0 && g.has_fine) {
-    const int nx = g.n[0], ny = g.n[1];
-    const int x = (int)(k % nx), y = (int)((k / nx) % ny), z = (int)(k / ((int64_t)nx * ny));
-    if (coarse_class(g, x, y, z) == CC_COVERED) {
-      const int jx = 2 * (x - g.a[0]), jy = 2 * (y - g.a[1]), jz = L::D == 3 ? 2 * (z - g.a[2]) : 0;
-      kk = (int64_t)jx + (int64_t)g.nf[0] * ((int64_t)jy + (int64_t)g.nf[1] * jz);
+  int64_t pos, NP;
+  if (level == 0) {
+    cdecode(g, k, x, y, z);
+    pos = cpos(g, x, y, z);
+    NP = g.Ncp;
+    if (g.has_fine && coarse_class(g, x, y, z) == CC_COVERED) {
       p = fine;
-      MM = g.Nf;
+      pos = fpos(g, 2 * (x - g.a[0]), 2 * (y - g.a[1]), L::D == 3 ? 2 * (z - g.a[2]) : 0);
+      NP = g.Nfp;
     }
+  } else {
+    fdecode(g, k, x, y, z);
+    pos = fpos(g, x, y, z);
+    NP = g.Nfp;
   }
   double f[L::Q], r, r0, uu[3];
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) f[i] = full_pop<S, DEV, LAT>(p[(size_t)i * MM + kk], i);
+  for (int i = 0; i < L::Q; ++i) f[i] = full_pop<S, DEV, LAT>(p[(int64_t)i * NP + pos], i);
   N::moments(f, r, r0, uu);
   rho[k] = r;
 #pragma unroll
-  for (int d = 0; d < L::D; ++d) u[(size_t)d * NN + k] = uu[d];
+  for (int d = 0; d < L::D; ++d) u[d * NN + k] = uu[d];
 }
 
+// Populations out / in: f[q][logical node] (double, full values).
 template <int LAT, bool DEV, typename S>
-__global__ void k_pops_out(const S* __restrict__ src, double* __restrict__ f, int64_t n, int64_t NN) {
+__global__ void k_pops_out(const S* __restrict__ src, double* __restrict__ f, const Geo g, int level) {
+  const int64_t NN = level == 0 ? g.Nc : g.Nf;
+  const int64_t n = NN * Lattice<LAT>::Q;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  f[k] = full_pop<S, DEV, LAT>(src[k], (int)(k / NN));
+  const int i = (int)(k / NN);
+  const int64_t node = k % NN;
+  int x, y, z;
+  int64_t pos;
+  if (level == 0) {
+    cdecode(g, node, x, y, z);
+    pos = (int64_t)i * g.Ncp + cpos(g, x, y, z);
+  } else {
+    fdecode(g, node, x, y, z);
+    pos = (int64_t)i * g.Nfp + fpos(g, x, y, z);
+  }
+  f[k] = full_pop<S, DEV, LAT>(src[pos], i);
 }
 template <int LAT, bool DEV, typename S>
-__global__ void k_pops_in(const double* __restrict__ f, S* __restrict__ dst, int64_t n, int64_t NN) {
+__global__ void k_pops_in(const double* __restrict__ f, S* __restrict__ dst, const Geo g, int level) {
+  const int64_t NN = level == 0 ? g.Nc : g.Nf;
+  const int64_t n = NN * Lattice<LAT>::Q;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  dst[k] = store_pop<S, DEV, LAT>(f[k], (int)(k / NN));
+  const int i = (int)(k / NN);
+  const int64_t node = k % NN;
+  int x, y, z;
+  int64_t pos;
+  if (level == 0) {
+    cdecode(g, node, x, y, z);
+    pos = (int64_t)i * g.Ncp + cpos(g, x, y, z);
+  } else {
+    fdecode(g, node, x, y, z);
+    pos = (int64_t)i * g.Nfp + fpos(g, x, y, z);
+  }
+  dst[pos] = store_pop<S, DEV, LAT>(f[k], i);
 }
 
 // Global totals, pass 1: per-block sums of rho and rho u (double) over the
-// evolving nodes of a level.  256 threads per block, fixed reduction tree.
+// evolving nodes of a level, in logical node order.  256 lanes per block,
+// fixed reduction tree.
 template <int LAT, bool DEV, typename S>
 __global__ __launch_bounds__(256) void k_totals(const S* __restrict__ src, double* __restrict__ part,
                                                 const Geo g, int level) {
@@ -593,16 +756,23 @@ __global__ __launch_bounds__(256) void k_totals(const S* __restrict__ src, doubl
   const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   if (k < NN) {
+    int x, y, z;
+    int64_t pos, NP;
     bool use = true;
-    if (level == 0 && g.has_fine) {
-      const int nx = g.n[0], ny = g.n[1];
-      const int x = (int)(k % nx), y = (int)((k / nx) % ny), z = (int)(k / ((int64_t)nx * ny));
-      use = coarse_class(g, x, y, z) != CC_COVERED;
+    if (level == 0) {
+      cdecode(g, k, x, y, z);
+      pos = cpos(g, x, y, z);
+      NP = g.Ncp;
+      use = !g.has_fine || coarse_class(g, x, y, z) != CC_COVERED;
+    } else {
+      fdecode(g, k, x, y, z);
+      pos = fpos(g, x, y, z);
+      NP = g.Nfp;
     }
     if (use) {
 #pragma unroll
       for (int i = 0; i < L::Q; ++i) {
-        const double f = full_pop<S, DEV, LAT>(src[(size_t)i * NN + k], i);
+        const double f = full_pop<S, DEV, LAT>(src[(int64_t)i * NP + pos], i);
         v[0] += f;
         v[1] += L::cx(i) * f;
         v[2] += L::cy(i) * f;

@@ -85,14 +85,49 @@ struct Sym {
 __host__ __device__ constexpr double h3aab(int a, int b) { return (double)(a * a * b) - b / 3.0; }
 
 // ---------------------------------------------------------------------------
-// Macroscopic moments (eqs moment_rho, moment_rhoU) of stored populations.
+// Per-node physics in moment space.
+//
+// Every population the scheme produces (equilibrium, BGK or regularised
+// post-collision state) is a polynomial in the lattice velocity,
+//   s_i = w_i [ A + xi_i.J + xi_i xi_i : M + sum_P H_P(xi_i) K_P ],
+// where the H_P are the third-order Hermite polynomials the lattice carries
+// (D2Q9: H_xxy, H_xyy; D3Q19: the sums and differences of the pairs
+// (H_xxy, H_yzz), (H_xzz, H_xyy), (H_yyz, H_xxz)).  The node computes the
+// coefficients (A, J, M, K) once and evaluates opposite velocities together:
+// the even part A + xi xi : M is shared, the odd part flips sign.
 template <int LAT, bool DEV, typename T>
 struct Node {
   using L = Lattice<LAT>;
   static constexpr int Q = L::Q;
   static constexpr int D = L::D;
+  static constexpr int NP = D == 2 ? 2 : 6;
 
-  // r0: sum of stored values (rho for DEV = 0, rho - 1 for DEV = 1)
+  // index of the opposite velocity
+  __host__ __device__ static constexpr int opp(int i) {
+    for (int j = 0; j < Q; ++j)
+      if (L::cx(j) == -L::cx(i) && L::cy(j) == -L::cy(i) && L::cz(j) == -L::cz(i)) return j;
+    return i;
+  }
+  // value of third-order basis polynomial p at velocity i
+  __host__ __device__ static constexpr double hp(int p, int i) {
+    const int x = L::cx(i), y = L::cy(i), z = L::cz(i);
+    if (D == 2) return p == 0 ? h3aab(x, y) : h3aab(y, x);
+    const double pa[3] = {h3aab(x, y), h3aab(z, x), h3aab(y, z)};  // xxy, xzz, yyz
+    const double pb[3] = {h3aab(z, y), h3aab(y, x), h3aab(x, z)};  // yzz, xyy, xxz
+    return p < 3 ? pa[p] + pb[p] : pa[p - 3] - pb[p - 3];
+  }
+  // 1 / (lattice norm of H_P), i.e. 1/(2 c_s^6) or 1/(6 c_s^6)
+  __host__ __device__ static constexpr double cp(int p) { return (D == 2 || p < 3) ? 13.5 : 4.5; }
+
+  struct Coef {
+    T A;
+    T J[3];
+    Sym<T> M;
+    T K[6];
+  };
+
+  // eqs moment_rho, moment_rhoU.  r0: sum of stored values (rho for DEV = 0,
+  // rho - 1 for DEV = 1).
   __device__ __host__ static inline void moments(const T* s, T& rho, T& r0, T* u) {
     T m = T(0), jx = T(0), jy = T(0), jz = T(0);
 #pragma unroll
@@ -115,61 +150,8 @@ struct Node {
     u[2] = (D == 3) ? jz * ir : T(0);
   }
 
-  // Third-order part of the equilibrium per unit density, per population,
-  // given the six (or two) products u_a^2 u_b.  D2Q9: eq fEqO3.  D3Q19: the
-  // pairs (xxy, yzz), (xzz, xyy), (yyz, xxz) enter through their sum (lattice
-  // norm 2 c_s^6) and difference (lattice norm 6 c_s^6).
-  template <int i>
-  __device__ __host__ static inline T third(T axxy, T axyy, T ayzz, T axzz, T ayyz, T axxz) {
-    constexpr int x = L::cx(i), y = L::cy(i), z = L::cz(i);
-    if (D == 2) {
-      constexpr double Hxxy = h3aab(x, y), Hxyy = h3aab(y, x);
-      return T(13.5) * (T(Hxxy) * axxy + T(Hxyy) * axyy);
-    } else {
-      constexpr double Hxxy = h3aab(x, y), Hyzz = h3aab(z, y);
-      constexpr double Hxzz = h3aab(z, x), Hxyy = h3aab(y, x);
-      constexpr double Hyyz = h3aab(y, z), Hxxz = h3aab(x, z);
-      T t = T(0);
-      if (Hxxy + Hyzz != 0.0) t += T(13.5 * (Hxxy + Hyzz)) * (axxy + ayzz);
-      if (Hxzz + Hxyy != 0.0) t += T(13.5 * (Hxzz + Hxyy)) * (axzz + axyy);
-      if (Hyyz + Hxxz != 0.0) t += T(13.5 * (Hyyz + Hxxz)) * (ayyz + axxz);
-      if (Hxxy - Hyzz != 0.0) t += T(4.5 * (Hxxy - Hyzz)) * (axxy - ayzz);
-      if (Hxzz - Hxyy != 0.0) t += T(4.5 * (Hxzz - Hxyy)) * (axzz - axyy);
-      if (Hyyz - Hxxz != 0.0) t += T(4.5 * (Hyyz - Hxxz)) * (ayyz - axxz);
-      return t;
-    }
-  }
-
-  // Stored-form equilibrium s0_i = w_i (r0 + rho E_i(u)) with
-  // E_i = 3 xi.u + 9/2 (xi.u)^2 - 3/2 u^2 + third-order terms.
-  template <int i>
-  __device__ __host__ static inline T feq_one(T rho, T r0, const T* u, T usq, T axxy, T axyy, T ayzz,
-                                              T axzz, T ayyz, T axxz) {
-    constexpr int x = L::cx(i), y = L::cy(i), z = L::cz(i);
-    T cu = T(0);
-    if (x) cu += T(x) * u[0];
-    if (y) cu += T(y) * u[1];
-    if (D == 3 && z) cu += T(z) * u[2];
-    T e = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq + third<i>(axxy, axyy, ayzz, axzz, ayyz, axxz);
-    return T(L::w(i)) * (r0 + rho * e);
-  }
-
-  __device__ __host__ static inline void feq(T rho, T r0, const T* u, T* out) {
-    const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    const T axxy = u[0] * u[0] * u[1], axyy = u[0] * u[1] * u[1];
-    const T ayzz = u[1] * u[2] * u[2], axzz = u[0] * u[2] * u[2];
-    const T ayyz = u[1] * u[1] * u[2], axxz = u[0] * u[0] * u[2];
-    static_for<Q>([&](auto ic) {
-      constexpr int i = decltype(ic)::value;
-      out[i] = feq_one<i>(rho, r0, u, usq, axxy, axyy, ayzz, axzz, ayyz, axxz);
-    });
-  }
-
-  // Second-order non-equilibrium moments a1^(2) = sum_i H2_i (f_i - f0_i)
-  // (eq a1Proj).  With the third-order equilibrium,
-  // sum_i xi xi f0_i = rho (u u + c_s^2 I), so a1 = Pi - r0/3 I - rho u u in
-  // stored form (the rest state carries Pi = I/3).
-  __device__ __host__ static inline Sym<T> a1(const T* s, T rho, T r0, const T* u) {
+  // Second moments Pi_ab = sum_i xi_a xi_b s_i.
+  __device__ __host__ static inline Sym<T> second(const T* s) {
     T pxx = T(0), pyy = T(0), pzz = T(0), pxy = T(0), pxz = T(0), pyz = T(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -186,75 +168,149 @@ struct Node {
         if (y * z < 0) pyz -= s[i];
       }
     }
-    const T third_r0 = r0 * T(1.0 / 3.0);
-    Sym<T> a;
-    a.xx = pxx - third_r0 - rho * u[0] * u[0];
-    a.yy = pyy - third_r0 - rho * u[1] * u[1];
-    a.zz = (D == 3) ? pzz - third_r0 - rho * u[2] * u[2] : T(0);
-    a.xy = pxy - rho * u[0] * u[1];
-    a.xz = (D == 3) ? pxz - rho * u[0] * u[2] : T(0);
-    a.yz = (D == 3) ? pyz - rho * u[1] * u[2] : T(0);
-    return a;
+    return Sym<T>{pxx, pyy, pzz, pxy, pxz, pyz};
   }
 
-  // Recursive regularised non-equilibrium part (eqs f1RR, a13RR) from a1^(2)
-  // and u, written to f1[i]:
-  // f1_i = w_i [ 9/2 H2_i : a + third-order terms with a1^(3) ].
-  __device__ __host__ static inline void f1rr(const Sym<T>& a, const T* u, T* f1) {
-    const T tr = a.xx + a.yy + a.zz;
-    const T axxy = T(2) * u[0] * a.xy + u[1] * a.xx;
-    const T axyy = T(2) * u[1] * a.xy + u[0] * a.yy;
-    const T ayzz = T(2) * u[2] * a.yz + u[1] * a.zz;
-    const T axzz = T(2) * u[2] * a.xz + u[0] * a.zz;
-    const T ayyz = T(2) * u[1] * a.yz + u[2] * a.yy;
-    const T axxz = T(2) * u[0] * a.xz + u[2] * a.xx;
+  // Third-order coefficient combinations of a fully symmetric tensor given
+  // by its components (xxy, xyy, yzz, xzz, yyz, xxz), in basis order.
+  __device__ __host__ static inline void third_combo(T xxy, T xyy, T yzz, T xzz, T yyz, T xxz, T* out) {
+    if (D == 2) {
+      out[0] = xxy;
+      out[1] = xyy;
+    } else {
+      out[0] = xxy + yzz;
+      out[1] = xzz + xyy;
+      out[2] = yyz + xxz;
+      out[3] = xxy - yzz;
+      out[4] = xzz - xyy;
+      out[5] = yyz - xxz;
+    }
+  }
+
+  // Coefficients of om * f1^RR + f0 (eqs fEqO3, f1RR, a13RR), a = a1^(2):
+  //   A = r0 - 3/2 rho u^2 - 3/2 om tr(a),  J = 3 rho u,
+  //   M = 9/2 (rho u u + om a),            K_P = c_P (rho u^3 + om a1^(3))_P.
+  // om = 0 gives the equilibrium alone.
+  __device__ __host__ static inline Coef coef(T rho, T r0, const T* u, T om, const Sym<T>& a) {
+    Coef c;
+    const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const T tra = a.xx + a.yy + a.zz;
+    c.A = r0 - T(1.5) * rho * usq - T(1.5) * om * tra;
+    c.J[0] = T(3) * rho * u[0];
+    c.J[1] = T(3) * rho * u[1];
+    c.J[2] = T(3) * rho * u[2];
+    c.M.xx = T(4.5) * (rho * u[0] * u[0] + om * a.xx);
+    c.M.yy = T(4.5) * (rho * u[1] * u[1] + om * a.yy);
+    c.M.zz = T(4.5) * (rho * u[2] * u[2] + om * a.zz);
+    c.M.xy = T(4.5) * (rho * u[0] * u[1] + om * a.xy);
+    c.M.xz = T(4.5) * (rho * u[0] * u[2] + om * a.xz);
+    c.M.yz = T(4.5) * (rho * u[1] * u[2] + om * a.yz);
+    // a1^(3)_abg = u_a a_bg + u_b a_ag + u_g a_ab (eq a13RR), mixed components
+    const T b_xxy = T(2) * u[0] * a.xy + u[1] * a.xx;
+    const T b_xyy = T(2) * u[1] * a.xy + u[0] * a.yy;
+    const T b_yzz = T(2) * u[2] * a.yz + u[1] * a.zz;
+    const T b_xzz = T(2) * u[2] * a.xz + u[0] * a.zz;
+    const T b_yyz = T(2) * u[1] * a.yz + u[2] * a.yy;
+    const T b_xxz = T(2) * u[0] * a.xz + u[2] * a.xx;
+    const T ru0 = rho * u[0], ru1 = rho * u[1], ru2 = rho * u[2];
+    T k[6];
+    third_combo(ru0 * u[0] * u[1] + om * b_xxy, ru0 * u[1] * u[1] + om * b_xyy, ru1 * u[2] * u[2] + om * b_yzz,
+                ru0 * u[2] * u[2] + om * b_xzz, ru1 * u[1] * u[2] + om * b_yyz, ru0 * u[0] * u[2] + om * b_xxz, k);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) c.K[p] = T(cp(p)) * k[p];
+    return c;
+  }
+
+  template <int i>
+  __device__ __host__ static inline T even(const Coef& c) {
+    constexpr int x = L::cx(i), y = L::cy(i), z = L::cz(i);
+    T e = c.A;
+    if (x) e += c.M.xx;
+    if (y) e += c.M.yy;
+    if (D == 3 && z) e += c.M.zz;
+    if (x * y) e += T(2 * x * y) * c.M.xy;
+    if (D == 3 && x * z) e += T(2 * x * z) * c.M.xz;
+    if (D == 3 && y * z) e += T(2 * y * z) * c.M.yz;
+    return e;
+  }
+  template <int i>
+  __device__ __host__ static inline T odd(const Coef& c) {
+    constexpr int x = L::cx(i), y = L::cy(i), z = L::cz(i);
+    T o = T(0);
+    if (x > 0) o += c.J[0];
+    if (x < 0) o -= c.J[0];
+    if (y > 0) o += c.J[1];
+    if (y < 0) o -= c.J[1];
+    if (D == 3 && z > 0) o += c.J[2];
+    if (D == 3 && z < 0) o -= c.J[2];
+    static_for<NP>([&](auto pc) {
+      constexpr int p = decltype(pc)::value;
+      constexpr double h = hp(p, i);
+      if (h != 0.0) o += T(h) * c.K[p];
+    });
+    return o;
+  }
+
+  // All Q stored values from coefficients.
+  __device__ __host__ static inline void eval(const Coef& c, T* out) {
+    out[0] = T(L::w(0)) * even<0>(c);
     static_for<Q>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
-      constexpr int x = L::cx(i), y = L::cy(i), z = L::cz(i);
-      T h = -tr * T(1.0 / 3.0);
-      if (x) h += a.xx;
-      if (y) h += a.yy;
-      if (D == 3 && z) h += a.zz;
-      if (x * y) h += T(2 * x * y) * a.xy;
-      if (D == 3 && x * z) h += T(2 * x * z) * a.xz;
-      if (D == 3 && y * z) h += T(2 * y * z) * a.yz;
-      f1[i] = T(L::w(i)) * (T(4.5) * h + third<i>(axxy, axyy, ayzz, axzz, ayyz, axxz));
+      constexpr int j = opp(i);
+      if constexpr (i != 0 && i < j) {
+        const T e = even<i>(c), o = odd<i>(c);
+        out[i] = T(L::w(i)) * (e + o);
+        out[j] = T(L::w(j)) * (e - o);
+      }
     });
   }
 
+  // Stored-form equilibrium s0_i = f0_i - DEV w_i (eq fEqO3 and its D3Q19
+  // counterpart).
+  __device__ __host__ static inline void feq(T rho, T r0, const T* u, T* out) {
+    const Sym<T> z{T(0), T(0), T(0), T(0), T(0), T(0)};
+    eval(coef(rho, r0, u, T(0), z), out);
+  }
+
   // Collision of one node, in place on stored populations s[Q].
-  //   model 0 (BGK, eq BGKmodel):   s* = s0 + om (s - s0)
+  //   model 0 (BGK, eq BGKmodel):      s* = s0 + om (s - s0)
   //   model 1 (RR,  eq LBMscheme_reg): s* = s0 + om f1RR(a1)
-  //   model 2 (H-RR, eq a1ij_HRR): a1 <- sig a1 + (1 - sig)(-2 tau rho c_s^2 S)
-  // om = 1 - 1/tau.
+  //   model 2 (H-RR, eq a1ij_HRR):     a1 <- sig a1 + (1 - sig)(-2 tau rho c_s^2 S)
+  // om = 1 - 1/tau.  With the third-order equilibrium,
+  // sum_i xi xi f0_i = rho (u u + c_s^2 I), so a1 = Pi - r0/3 I - rho u u
+  // in stored form (the rest state carries Pi = I/3).
   __device__ __host__ static inline void collide(T* s, int model, T om, T tau, T sig, const Sym<T>* S) {
     T rho, r0, u[3];
     moments(s, rho, r0, u);
-    T s0[Q];
-    feq(rho, r0, u, s0);
     if (model == 0) {
+      T s0[Q];
+      feq(rho, r0, u, s0);
 #pragma unroll
       for (int i = 0; i < Q; ++i) s[i] = s0[i] + om * (s[i] - s0[i]);
       return;
     }
-    Sym<T> a = a1(s, rho, r0, u);
+    const Sym<T> P = second(s);
+    const T tr0 = r0 * T(1.0 / 3.0);
+    Sym<T> a;
+    a.xx = P.xx - tr0 - rho * u[0] * u[0];
+    a.yy = P.yy - tr0 - rho * u[1] * u[1];
+    a.zz = (D == 3) ? P.zz - tr0 - rho * u[2] * u[2] : T(0);
+    a.xy = P.xy - rho * u[0] * u[1];
+    a.xz = (D == 3) ? P.xz - rho * u[0] * u[2] : T(0);
+    a.yz = (D == 3) ? P.yz - rho * u[1] * u[2] : T(0);
     if (model == 2) {
       const T k = (T(1) - sig) * (T(-2.0 / 3.0) * tau * rho);
       a.xx = sig * a.xx + k * S->xx;
       a.yy = sig * a.yy + k * S->yy;
-      a.zz = sig * a.zz + k * S->zz;
       a.xy = sig * a.xy + k * S->xy;
-      a.xz = sig * a.xz + k * S->xz;
-      a.yz = sig * a.yz + k * S->yz;
-      if (D == 2) a.zz = a.xz = a.yz = T(0);
+      if (D == 3) {
+        a.zz = sig * a.zz + k * S->zz;
+        a.xz = sig * a.xz + k * S->xz;
+        a.yz = sig * a.yz + k * S->yz;
+      }
     }
-    T f1[Q];
-    f1rr(a, u, f1);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) s[i] = s0[i] + om * f1[i];
+    eval(coef(rho, r0, u, om, a), s);
   }
 };
-
-
 
 }  // namespace lbm

@@ -170,6 +170,8 @@ struct GridBase {
   virtual void set_pops(int level, const double* f, bool dev) = 0;
   virtual void get_pops(int level, double* f, bool dev) = 0;
   virtual void totals(double* mass, double* mom) = 0;
+  virtual void tune(int reps, int32_t* out) = 0;
+  virtual void set_variants(const int32_t* v) = 0;
   int64_t nodes(int level) const { return level == 0 ? g.Nc : g.Nf; }
   int64_t updates() const {
     if (!g.has_fine) return g.Nc;
@@ -183,35 +185,44 @@ template <int LAT, int PREC>
 struct Grid final : GridBase {
   using L = Lattice<LAT>;
   static constexpr bool DEV = PREC == LBM_FP32_DEV;
-  using S = typename std::conditional<DEV, float, double>::type;  // stored type
-  using T = S;                                                      // bulk compute type
+  using S = typename std::conditional<DEV, float, double>::type;  // stored and bulk compute type
   using F = HF<LAT>;
   static constexpr int Q = L::Q, D = L::D;
-  static constexpr int TX = 64, TY = 4;
+  static constexpr bool NT = true;  // non-temporal stores of the streamed planes
+  // Bulk-kernel variants (nodes per lane V, lanes along x LX; work groups are
+  // LX x 256/LX).  FP32: 16-byte (V = 4) or 8-byte (V = 2) accesses; FP64:
+  // 16-byte (V = 2).
+  static constexpr int NVAR = DEV ? 5 : 3;
+  static constexpr int kV[5] = {DEV ? 4 : 2, DEV ? 4 : 2, DEV ? 4 : 2, 2, 2};
+  static constexpr int kLX[5] = {64, 32, 16, 64, 32};
+  // chosen variant per role: 0 coarse stream, 1 fine stream, 2 coarse H-RR
+  // collision, 3 fine H-RR collision
+  int var[4] = {0, 0, 0, 0};
 
   DevBuf cbuf[2], fbuf[2], mac_c, mac_f, hist[3], G, tmp_rho, tmp_u, tmp_f, part, tot;
   DevBuf d_hnode, d_rnode, d_rnp, d_rpt, d_tnf, d_tnc;
-  int cpar = 0;    // coarse buffer holding the current state
+  int cpar = 0;  // coarse buffer holding the current state
   int hs[3] = {0, 1, 2};
-  Tiling tc{}, tf{};
   Iface itf{};
   double tau_c = 0, tau_f = 0, sig = 0;
 
+  // padded plane storage plus slack for the one-element overreach of the
+  // x-shifted vector loads at the very end of a buffer
+  static size_t plane_bytes(int64_t NP, int nplanes) { return sizeof(S) * ((size_t)NP * nplanes + 64); }
+
   void init() override {
-    const size_t Nc = (size_t)g.Nc, Nf = (size_t)g.Nf;
-    for (int p = 0; p < 2; ++p) cbuf[p].alloc(sizeof(S) * Q * Nc);
+    for (int p = 0; p < 2; ++p) cbuf[p].alloc(plane_bytes(g.Ncp, Q));
     if (g.has_fine)
-      for (int p = 0; p < 2; ++p) fbuf[p].alloc(sizeof(S) * Q * Nf);
+      for (int p = 0; p < 2; ++p) fbuf[p].alloc(plane_bytes(g.Nfp, Q));
     if (desc.collision == LBM_HRR) {
-      mac_c.alloc(sizeof(T) * (1 + D) * Nc);
-      if (g.has_fine) mac_f.alloc(sizeof(T) * (1 + D) * Nf);
+      mac_c.alloc(plane_bytes(g.Ncp, 1 + D));
+      if (g.has_fine) mac_f.alloc(plane_bytes(g.Nfp, 1 + D));
     }
     tau_c = desc.tau_coarse;
     tau_f = 2.0 * tau_c - 0.5;
     sig = desc.sigma;
-    tc = make_tiling<TX, TY>(g.n[0], g.n[1], g.n[2]);
+    for (int r = 0; r < 4; ++r) var[r] = default_variant(r & 1);
     if (g.has_fine) {
-      tf = make_tiling<TX, TY>(g.nf[0], g.nf[1], g.nf[2]);
       const size_t NH = tabs.hnode.size();
       for (int s = 0; s < 3; ++s) hist[s].alloc(sizeof(double) * F::N * NH);
       G.alloc(sizeof(double) * F::N * NH);
@@ -235,7 +246,7 @@ struct Grid final : GridBase {
       itf.tnf = d_tnf.as<int64_t>();
       itf.tnc = d_tnc.as<int64_t>();
     }
-    const size_t Nmax = std::max(Nc, Nf);
+    const size_t Nmax = (size_t)std::max(g.Nc, g.Nf);
     tmp_rho.alloc(sizeof(double) * Nmax);
     tmp_u.alloc(sizeof(double) * D * Nmax);
     part.alloc(sizeof(double) * 4 * ((Nmax + 255) / 256));
@@ -243,26 +254,89 @@ struct Grid final : GridBase {
     for (int p = 0; p < 2; ++p) HIPCHK(hipMemset(cbuf[p].p, 0, cbuf[p].bytes));
     if (g.has_fine)
       for (int p = 0; p < 2; ++p) HIPCHK(hipMemset(fbuf[p].p, 0, fbuf[p].bytes));
+    if (mac_c.p) HIPCHK(hipMemset(mac_c.p, 0, mac_c.bytes));
+    if (mac_f.p) HIPCHK(hipMemset(mac_f.p, 0, mac_f.bytes));
   }
 
-  static unsigned blocks(int64_t n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
-  static dim3 tgrid(const Tiling& t) { return dim3((unsigned)(t.per_xcd * kXCD)); }
+  static unsigned blocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+  Tiling tiling(int level, int v) const {
+    const int V = kV[v], LX = kLX[v];
+    if (level == 0) return make_tiling(g.n[0], g.n[1], g.n[2], 0, V, LX, 256 / LX);
+    return make_tiling(g.nf[0], g.nf[1], g.nf[2], 1, V, LX, 256 / LX);
+  }
+  // Variant with the fewest idle lanes along x (ties: the earlier one).
+  int default_variant(int level) const {
+    if (level == 1 && !g.has_fine) return 0;
+    int best = 0;
+    int64_t bw = -1;
+    for (int v = 0; v < NVAR; ++v) {
+      if (kV[v] != kV[0]) continue;
+      const Tiling t = tiling(level, v);
+      const int64_t waste = (int64_t)t.ntx * kLX[v] - t.nv;
+      if (bw < 0 || waste < bw) {
+        bw = waste;
+        best = v;
+      }
+    }
+    return best;
+  }
 
   S* cur_c() { return cbuf[cpar].as<S>(); }
   S* fineA() { return fbuf[0].as<S>(); }
   S* fineB() { return fbuf[1].as<S>(); }
 
+  template <int MODEL, int LEVEL, int V, int LX>
+  void go_stream(const S* src, S* dst, S* mac, double tau, hipStream_t s, int v) {
+    const Tiling t = tiling(LEVEL, v);
+    const S om = (S)(1.0 - 1.0 / tau);
+    hipLaunchKernelGGL((k_stream<LAT, DEV, S, MODEL, LEVEL, V, LX, NT>), dim3((unsigned)(t.per_xcd * kXCD)),
+                       dim3(256), 0, s, src, dst, mac, g, t, om);
+  }
   template <int MODEL, int LEVEL>
-  void launch_stream(const S* src, S* dst, T* mac, const Tiling& t, double tau, hipStream_t s) {
-    const T om = (T)(1.0 - 1.0 / tau);
-    hipLaunchKernelGGL((k_stream<LAT, DEV, S, T, MODEL, LEVEL, TX, TY>), tgrid(t), dim3(TX * TY), 0, s, src, dst,
-                       mac, g, t, om);
+  void launch_stream(const S* src, S* dst, S* mac, double tau, hipStream_t s, int v = -1) {
+    if (v < 0) v = var[LEVEL];
+    if constexpr (DEV) {
+      switch (v) {
+        case 0: go_stream<MODEL, LEVEL, 4, 64>(src, dst, mac, tau, s, v); break;
+        case 1: go_stream<MODEL, LEVEL, 4, 32>(src, dst, mac, tau, s, v); break;
+        case 2: go_stream<MODEL, LEVEL, 4, 16>(src, dst, mac, tau, s, v); break;
+        case 3: go_stream<MODEL, LEVEL, 2, 64>(src, dst, mac, tau, s, v); break;
+        default: go_stream<MODEL, LEVEL, 2, 32>(src, dst, mac, tau, s, 4); break;
+      }
+    } else {
+      switch (v) {
+        case 0: go_stream<MODEL, LEVEL, 2, 64>(src, dst, mac, tau, s, v); break;
+        case 1: go_stream<MODEL, LEVEL, 2, 32>(src, dst, mac, tau, s, v); break;
+        default: go_stream<MODEL, LEVEL, 2, 16>(src, dst, mac, tau, s, 2); break;
+      }
+    }
   }
 
+  template <int LEVEL, int V, int LX>
+  void go_collide(S* buf, const S* mac, double tau, hipStream_t s, int v) {
+    const Tiling t = tiling(LEVEL, v);
+    hipLaunchKernelGGL((k_collide_hrr<LAT, DEV, S, LEVEL, V, LX, NT>), dim3((unsigned)(t.per_xcd * kXCD)), dim3(256),
+                       0, s, buf, mac, g, t, (S)(1.0 - 1.0 / tau), (S)tau, (S)sig);
+  }
   template <int LEVEL>
-  void launch_collide_hrr(S* buf, const T* mac, const Tiling& t, double tau, hipStream_t s) {
-    hipLaunchKernelGGL((k_collide_hrr<LAT, DEV, S, T, LEVEL, TX, TY>), tgrid(t), dim3(TX * TY), 0, s, buf, mac, g, t,
-                       (T)(1.0 - 1.0 / tau), (T)tau, (T)sig);
+  void launch_collide_hrr(S* buf, const S* mac, double tau, hipStream_t s, int v = -1) {
+    if (v < 0) v = var[2 + LEVEL];
+    if constexpr (DEV) {
+      switch (v) {
+        case 0: go_collide<LEVEL, 4, 64>(buf, mac, tau, s, v); break;
+        case 1: go_collide<LEVEL, 4, 32>(buf, mac, tau, s, v); break;
+        case 2: go_collide<LEVEL, 4, 16>(buf, mac, tau, s, v); break;
+        case 3: go_collide<LEVEL, 2, 64>(buf, mac, tau, s, v); break;
+        default: go_collide<LEVEL, 2, 32>(buf, mac, tau, s, 4); break;
+      }
+    } else {
+      switch (v) {
+        case 0: go_collide<LEVEL, 2, 64>(buf, mac, tau, s, v); break;
+        case 1: go_collide<LEVEL, 2, 32>(buf, mac, tau, s, v); break;
+        default: go_collide<LEVEL, 2, 16>(buf, mac, tau, s, 2); break;
+      }
+    }
   }
 
   void fine_stream_timed(int model, const S* src, S* dst, hipStream_t s) {
@@ -272,28 +346,91 @@ struct Grid final : GridBase {
       HIPCHK(hipEventCreate(&e1));
       HIPCHK(hipEventRecord(e0, s));
     }
-    if (model == M_BGK) launch_stream<M_BGK, 1>(src, dst, nullptr, tf, tau_f, s);
-    else if (model == M_RR) launch_stream<M_RR, 1>(src, dst, nullptr, tf, tau_f, s);
-    else launch_stream<M_HRR, 1>(src, dst, mac_f.as<T>(), tf, tau_f, s);
+    if (model == M_BGK) launch_stream<M_BGK, 1>(src, dst, nullptr, tau_f, s);
+    else if (model == M_RR) launch_stream<M_RR, 1>(src, dst, nullptr, tau_f, s);
+    else launch_stream<M_HRR, 1>(src, dst, mac_f.as<S>(), tau_f, s);
     if (profile) {
       HIPCHK(hipEventRecord(e1, s));
       events.emplace_back(e0, e1);
     }
   }
 
+  // Autotuner: times every bulk-kernel variant of each role on this grid
+  // (reps launches each, after one warm-up) and keeps the fastest.  Only
+  // buffers that the next step rewrites are touched (the coarse and fine
+  // buffers not holding the current state, and the macro planes).
+  void role_launch(int role, int v, hipStream_t s) {
+    const int model = desc.collision;
+    S* c_cur = cur_c();
+    S* c_oth = cbuf[cpar ^ 1].as<S>();
+    if (role == 0) {
+      if (model == M_BGK) launch_stream<M_BGK, 0>(c_cur, c_oth, nullptr, tau_c, s, v);
+      else if (model == M_RR) launch_stream<M_RR, 0>(c_cur, c_oth, nullptr, tau_c, s, v);
+      else launch_stream<M_HRR, 0>(c_cur, c_oth, mac_c.as<S>(), tau_c, s, v);
+    } else if (role == 1) {
+      if (model == M_BGK) launch_stream<M_BGK, 1>(fineA(), fineB(), nullptr, tau_f, s, v);
+      else if (model == M_RR) launch_stream<M_RR, 1>(fineA(), fineB(), nullptr, tau_f, s, v);
+      else launch_stream<M_HRR, 1>(fineA(), fineB(), mac_f.as<S>(), tau_f, s, v);
+    } else if (role == 2) {
+      launch_collide_hrr<0>(c_oth, mac_c.as<S>(), tau_c, s, v);
+    } else {
+      launch_collide_hrr<1>(fineB(), mac_f.as<S>(), tau_f, s, v);
+    }
+  }
+
+  void set_variants(const int32_t* v) override {
+    for (int r = 0; r < 4; ++r)
+      if (v[r] < 0 || v[r] >= NVAR) throw LbmError(LBM_EINVAL, "variant index out of range");
+    for (int r = 0; r < 4; ++r) var[r] = v[r];
+  }
+
+  void tune(int reps, int32_t* out) override {
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipStreamSynchronize(stream));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (int role = 0; role < 4; ++role) {
+      const bool used = (role & 1) ? g.has_fine : true;
+      const bool hrr_role = role >= 2;
+      if (!used || (hrr_role && desc.collision != LBM_HRR)) continue;
+      float best = -1.f;
+      for (int v = 0; v < NVAR; ++v) {
+        role_launch(role, v, stream);
+        HIPCHK(hipEventRecord(e0, stream));
+        for (int k = 0; k < reps; ++k) role_launch(role, v, stream);
+        HIPCHK(hipEventRecord(e1, stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (best < 0.f || ms < best) {
+          best = ms;
+          var[role] = v;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(hipGetLastError());
+    for (int r = 0; r < 4; ++r) out[r] = var[r];
+  }
+
   void step_uniform(hipStream_t s) {
     const int model = desc.collision;
     S* src = cbuf[cpar].as<S>();
     S* dst = cbuf[cpar ^ 1].as<S>();
-    if (model == M_BGK) launch_stream<M_BGK, 0>(src, dst, nullptr, tc, tau_c, s);
-    else if (model == M_RR) launch_stream<M_RR, 0>(src, dst, nullptr, tc, tau_c, s);
+    if (model == M_BGK) launch_stream<M_BGK, 0>(src, dst, nullptr, tau_c, s);
+    else if (model == M_RR) launch_stream<M_RR, 0>(src, dst, nullptr, tau_c, s);
     else {
-      launch_stream<M_HRR, 0>(src, dst, mac_c.as<T>(), tc, tau_c, s);
-      launch_collide_hrr<0>(dst, mac_c.as<T>(), tc, tau_c, s);
+      launch_stream<M_HRR, 0>(src, dst, mac_c.as<S>(), tau_c, s);
+      launch_collide_hrr<0>(dst, mac_c.as<S>(), tau_c, s);
     }
     cpar ^= 1;
   }
 
+  // One coarse step, Sec. 4.3: asynchronous iteration (coarse t -> t+1, fine
+  // t -> t+1/2) then synchronous iteration (fine t+1/2 -> t+1).  Fine buffer
+  // A holds the state at integer times, B at half times.
   template <int MODEL>
   void step_two_level(hipStream_t s) {
     S* csrc = cbuf[cpar].as<S>();
@@ -307,42 +444,42 @@ struct Grid final : GridBase {
     const double kf = tau_f / (2.0 * tau_c), kc = 2.0 * tau_c / tau_f;
     const double omf = 1.0 - 1.0 / tau_f, omc = 1.0 - 1.0 / tau_c;
     const double c0 = -1.0 / 8.0, c1 = 3.0 / 4.0, c2 = 3.0 / 8.0;
-    const unsigned bh = blocks(NH), br = blocks(itf.NR), bt = blocks(itf.NT), bg = blocks(NH * F::N);
-    // asynchronous iteration: coarse t -> t+1, fine t -> t+1/2
-    hipLaunchKernelGGL((k_hist_capture<LAT, DEV, S>), dim3(bh), dim3(256), 0, s, csrc, Hp, g, itf);
+    constexpr int IB = kIfaceBlock;
+    constexpr int PER = 256 / (D == 2 ? 9 : 27);
+    const unsigned bh = blocks(NH, IB), br = blocks(itf.NR, IB), bt = blocks(itf.NT, IB), bg = blocks(NH * F::N, 256);
+    const unsigned bc = blocks(itf.NT, PER);
+    hipLaunchKernelGGL((k_hist_capture<LAT, DEV, S>), dim3(bh), dim3(IB), 0, s, csrc, Hp, g, itf);
     if (MODEL != M_HRR) {
-      launch_stream<MODEL, 0>(csrc, cdst, nullptr, tc, tau_c, s);
+      launch_stream<MODEL, 0>(csrc, cdst, nullptr, tau_c, s);
       fine_stream_timed(MODEL, fA, fB, s);
       hipLaunchKernelGGL(k_hist_time, dim3(bg), dim3(256), 0, s, Hm, H0, Hp, G.as<double>(), NH * F::N, c0, c1, c2);
-      hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL>), dim3(br), dim3(256), 0, s, G.as<double>(), fB, g, itf, kf, omf,
+      hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL>), dim3(br), dim3(IB), 0, s, G.as<double>(), fB, g, itf, kf, omf,
                          tau_f, sig);
-      // synchronous iteration: fine t+1/2 -> t+1
       fine_stream_timed(MODEL, fB, fA, s);
-      hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL>), dim3(br), dim3(256), 0, s, Hp, fA, g, itf, kf, omf, tau_f,
-                         sig);
-      hipLaunchKernelGGL((k_coalesce<LAT, DEV, S, MODEL>), dim3(bt), dim3(256), 0, s, fB, cdst, g, itf, kc, omc,
+      hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL>), dim3(br), dim3(IB), 0, s, Hp, fA, g, itf, kf, omf, tau_f, sig);
+      hipLaunchKernelGGL((k_coalesce<LAT, DEV, S, MODEL>), dim3(bc), dim3(256), 0, s, fB, cdst, g, itf, kc, omc,
                          tau_c, sig);
     } else {
-      T* mc = mac_c.as<T>();
-      T* mf = mac_f.as<T>();
-      launch_stream<M_HRR, 0>(csrc, cdst, mc, tc, tau_c, s);
+      S* mc = mac_c.as<S>();
+      S* mf = mac_f.as<S>();
+      launch_stream<M_HRR, 0>(csrc, cdst, mc, tau_c, s);
       fine_stream_timed(M_HRR, fA, fB, s);
-      hipLaunchKernelGGL((k_ring_macro<LAT, T>), dim3(br), dim3(256), 0, s, Hm, H0, Hp, c0, c1, c2, mf, g, itf);
-      launch_collide_hrr<1>(fB, mf, tf, tau_f, s);
-      hipLaunchKernelGGL((k_fict<LAT, DEV, S, T>), dim3(bt), dim3(256), 0, s, fB, mc, g, itf);
-      hipLaunchKernelGGL((k_hist_strain<LAT, T>), dim3(bh), dim3(256), 0, s, mc, Hp, g, itf);
+      hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, c0, c1, c2, mf, g, itf);
+      launch_collide_hrr<1>(fB, mf, tau_f, s);
+      hipLaunchKernelGGL((k_fict<LAT, DEV, S, S>), dim3(bt), dim3(IB), 0, s, fB, mc, g, itf);
+      hipLaunchKernelGGL((k_hist_strain<LAT, S>), dim3(bh), dim3(IB), 0, s, mc, Hp, g, itf);
       hipLaunchKernelGGL(k_hist_time, dim3(bg), dim3(256), 0, s, Hm, H0, Hp, G.as<double>(), NH * F::N, c0, c1, c2);
-      hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR>), dim3(br), dim3(256), 0, s, G.as<double>(), fB, g, itf, kf,
-                         omf, tau_f, sig);
-      // synchronous iteration
+      hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR>), dim3(br), dim3(IB), 0, s, G.as<double>(), fB, g, itf, kf, omf,
+                         tau_f, sig);
       fine_stream_timed(M_HRR, fB, fA, s);
-      hipLaunchKernelGGL((k_ring_macro<LAT, T>), dim3(br), dim3(256), 0, s, Hm, H0, Hp, 0.0, 0.0, 1.0, mf, g, itf);
-      launch_collide_hrr<1>(fA, mf, tf, tau_f, s);
-      hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR>), dim3(br), dim3(256), 0, s, Hp, fA, g, itf, kf, omf, tau_f,
-                         sig);
-      hipLaunchKernelGGL((k_coalesce<LAT, DEV, S, M_HRR>), dim3(bt), dim3(256), 0, s, fB, cdst, g, itf, kc, omc,
+      hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, 0.0, 0.0, 1.0, mf, g, itf);
+      launch_collide_hrr<1>(fA, mf, tau_f, s);
+      hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR>), dim3(br), dim3(IB), 0, s, Hp, fA, g, itf, kf, omf, tau_f, sig);
+      // coarse collision before the TN transfer: the vector kernel also
+      // passes over TN nodes, which the transfer then overwrites
+      launch_collide_hrr<0>(cdst, mc, tau_c, s);
+      hipLaunchKernelGGL((k_coalesce<LAT, DEV, S, M_HRR>), dim3(bc), dim3(256), 0, s, fB, cdst, g, itf, kc, omc,
                          tau_c, sig);
-      launch_collide_hrr<0>(cdst, mc, tc, tau_c, s);
     }
     HIPCHK(hipGetLastError());
     cpar ^= 1;
@@ -368,22 +505,24 @@ struct Grid final : GridBase {
                           stream));
   }
 
+  void reset_history_from_tmp() {
+    hs[0] = 0;
+    hs[1] = 1;
+    hs[2] = 2;
+    hipLaunchKernelGGL((k_hist_init<LAT>), dim3(blocks(itf.NH, kIfaceBlock)), dim3(kIfaceBlock), 0, stream,
+                       tmp_rho.as<double>(), tmp_u.as<double>(), hist[0].as<double>(), hist[1].as<double>(),
+                       hist[2].as<double>(), g, itf);
+  }
+
   void set_state(int level, const double* rho, const double* u, bool dev) override {
     HIPCHK(hipSetDevice(device));
     const int64_t N = nodes(level);
     upload(tmp_rho, rho, (size_t)N, dev);
     upload(tmp_u, u, (size_t)N * D, dev);
     S* dst = level == 0 ? cur_c() : fineA();
-    hipLaunchKernelGGL((k_set_state<LAT, DEV, S>), dim3(blocks(N)), dim3(256), 0, stream, tmp_rho.as<double>(),
-                       tmp_u.as<double>(), dst, N);
-    if (level == 0 && g.has_fine) {
-      hs[0] = 0;
-      hs[1] = 1;
-      hs[2] = 2;
-      hipLaunchKernelGGL((k_hist_init<LAT>), dim3(blocks(itf.NH)), dim3(256), 0, stream, tmp_rho.as<double>(),
-                         tmp_u.as<double>(), hist[0].as<double>(), hist[1].as<double>(), hist[2].as<double>(), g,
-                         itf);
-    }
+    hipLaunchKernelGGL((k_set_state<LAT, DEV, S>), dim3(blocks(N, 256)), dim3(256), 0, stream, tmp_rho.as<double>(),
+                       tmp_u.as<double>(), dst, g, level);
+    if (level == 0 && g.has_fine) reset_history_from_tmp();
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream));
   }
@@ -391,7 +530,7 @@ struct Grid final : GridBase {
   void compute_macros(int level) {
     const int64_t N = nodes(level);
     const S* src = level == 0 ? cur_c() : fineA();
-    hipLaunchKernelGGL((k_macros<LAT, DEV, S>), dim3(blocks(N)), dim3(256), 0, stream, src,
+    hipLaunchKernelGGL((k_macros<LAT, DEV, S>), dim3(blocks(N, 256)), dim3(256), 0, stream, src,
                        g.has_fine ? fineA() : nullptr, tmp_rho.as<double>(), tmp_u.as<double>(), g, level);
     HIPCHK(hipGetLastError());
   }
@@ -406,27 +545,27 @@ struct Grid final : GridBase {
     HIPCHK(hipStreamSynchronize(stream));
   }
 
+  void ensure_tmp_f(int64_t N) {
+    if (tmp_f.bytes < sizeof(double) * Q * N) {
+      if (tmp_f.p) HIPCHK(hipFree(tmp_f.p));
+      tmp_f.p = nullptr;
+      tmp_f.bytes = 0;
+      tmp_f.alloc(sizeof(double) * Q * N);
+    }
+  }
+
   void set_pops(int level, const double* f, bool dev) override {
     HIPCHK(hipSetDevice(device));
     const int64_t N = nodes(level);
-    if (tmp_f.bytes < sizeof(double) * Q * N) {
-      tmp_f.~DevBuf();
-      new (&tmp_f) DevBuf();
-      tmp_f.alloc(sizeof(double) * Q * N);
-    }
+    ensure_tmp_f(N);
     HIPCHK(hipMemcpyAsync(tmp_f.p, f, sizeof(double) * Q * N, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                           stream));
     S* dst = level == 0 ? cur_c() : fineA();
-    hipLaunchKernelGGL((k_pops_in<LAT, DEV, S>), dim3(blocks(Q * N)), dim3(256), 0, stream, tmp_f.as<double>(), dst,
-                       (int64_t)Q * N, N);
+    hipLaunchKernelGGL((k_pops_in<LAT, DEV, S>), dim3(blocks(Q * N, 256)), dim3(256), 0, stream, tmp_f.as<double>(),
+                       dst, g, level);
     if (level == 0 && g.has_fine) {
       compute_macros(0);
-      hs[0] = 0;
-      hs[1] = 1;
-      hs[2] = 2;
-      hipLaunchKernelGGL((k_hist_init<LAT>), dim3(blocks(itf.NH)), dim3(256), 0, stream, tmp_rho.as<double>(),
-                         tmp_u.as<double>(), hist[0].as<double>(), hist[1].as<double>(), hist[2].as<double>(), g,
-                         itf);
+      reset_history_from_tmp();
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream));
@@ -435,14 +574,10 @@ struct Grid final : GridBase {
   void get_pops(int level, double* f, bool dev) override {
     HIPCHK(hipSetDevice(device));
     const int64_t N = nodes(level);
-    if (tmp_f.bytes < sizeof(double) * Q * N) {
-      tmp_f.~DevBuf();
-      new (&tmp_f) DevBuf();
-      tmp_f.alloc(sizeof(double) * Q * N);
-    }
+    ensure_tmp_f(N);
     const S* src = level == 0 ? cur_c() : fineA();
-    hipLaunchKernelGGL((k_pops_out<LAT, DEV, S>), dim3(blocks(Q * N)), dim3(256), 0, stream, src, tmp_f.as<double>(),
-                       (int64_t)Q * N, N);
+    hipLaunchKernelGGL((k_pops_out<LAT, DEV, S>), dim3(blocks(Q * N, 256)), dim3(256), 0, stream, src,
+                       tmp_f.as<double>(), g, level);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(f, tmp_f.p, sizeof(double) * Q * N, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
                           stream));
@@ -456,7 +591,7 @@ struct Grid final : GridBase {
       for (int d = 0; d < 3; ++d) mom[3 * lv + d] = 0.0;
       if (lv == 1 && !g.has_fine) continue;
       const int64_t N = nodes(lv);
-      const unsigned nb = blocks(N);
+      const unsigned nb = blocks(N, 256);
       const S* src = lv == 0 ? cur_c() : fineA();
       hipLaunchKernelGGL((k_totals<LAT, DEV, S>), dim3(nb), dim3(256), 0, stream, src, part.as<double>(), g, lv);
       hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(256), 0, stream, part.as<double>(), (int64_t)nb,
@@ -510,6 +645,11 @@ static Geo validate(const lbm_grid_desc& d) {
     }
     g.Nf = (int64_t)g.nf[0] * g.nf[1] * g.nf[2];
   }
+  g.pc = pitch_of(g.n[0]);
+  g.Ncp = (int64_t)g.pc * g.n[1] * g.n[2];
+  g.fxo = d.precision == LBM_FP32_DEV ? 3 : 1;
+  g.pf = g.has_fine ? pitch_of(g.nf[0] + g.fxo) : 0;
+  g.Nfp = g.has_fine ? (int64_t)g.pf * g.nf[1] * g.nf[2] : 0;
   return g;
 }
 
@@ -743,6 +883,19 @@ int lbm_kernel_time(lbm_handle h, int64_t* launches, double* mean_ms, int64_t* n
     for (int d = 0; d < G.g.D; ++d) mid *= (G.g.has_fine ? G.g.nf[d] - 2 : 0);
     *nodes_per_launch = mid;
   });
+}
+
+int lbm_tune(lbm_handle h, int reps, int32_t variants[4]) {
+  if (!h || reps < 1 || !variants) return LBM_EINVAL;
+  return guard(h, [&] {
+    HIPCHK(hipDeviceSynchronize());
+    h->impl->tune(reps, variants);
+  });
+}
+
+int lbm_set_variants(lbm_handle h, const int32_t variants[4]) {
+  if (!h || !variants) return LBM_EINVAL;
+  return guard(h, [&] { h->impl->set_variants(variants); });
 }
 
 const char* lbm_last_error(lbm_handle h) {

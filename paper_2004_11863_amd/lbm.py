@@ -26,12 +26,15 @@ LBM_D2Q9, LBM_D3Q19 = 0, 1
 LBM_BGK, LBM_RR, LBM_HRR = 0, 1, 2
 LBM_FP64, LBM_FP32_DEV = 0, 1
 LBM_HOST, LBM_DEVICE = 0, 1
+LBM_C_MIDDLE, LBM_C_TF, LBM_C_TN, LBM_C_COVERED = 0, 1, 2, 3
+LBM_F_MIDDLE, LBM_F_TF, LBM_F_IE, LBM_F_IE_FACE, LBM_F_TN = 0, 1, 2, 3, 4
 
 EXPORTS = (
     "lbm_create_grid", "lbm_destroy", "lbm_set_state", "lbm_step", "lbm_get_macros",
     "lbm_set_populations", "lbm_get_populations", "lbm_get_totals", "lbm_get_index_maps",
     "lbm_level_dims", "lbm_lattice_info", "lbm_interface_counts", "lbm_interface_tables",
-    "lbm_updates_per_step", "lbm_profile_enable", "lbm_kernel_time", "lbm_last_error",
+    "lbm_updates_per_step", "lbm_profile_enable", "lbm_kernel_time", "lbm_tune", "lbm_set_variants",
+    "lbm_last_error",
 )
 
 
@@ -79,6 +82,8 @@ def load(path: str = LIB_PATH):
     L.lbm_updates_per_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.lbm_profile_enable.argtypes = [vp, ip]
     L.lbm_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), dp, ctypes.POINTER(ctypes.c_int64)]
+    L.lbm_tune.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int32)]
+    L.lbm_set_variants.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.lbm_last_error.argtypes = [vp]
     L.lbm_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -211,6 +216,17 @@ def lbm_kernel_time(h):
     return n.value, ms.value, nodes.value
 
 
+def lbm_tune(h, reps=5):
+    v = (ctypes.c_int32 * 4)()
+    _check(load().lbm_tune(h, int(reps), v), h)
+    return list(v)
+
+
+def lbm_set_variants(h, variants):
+    v = (ctypes.c_int32 * 4)(*[int(x) for x in variants])
+    _check(load().lbm_set_variants(h, v), h)
+
+
 class Grid:
     """Convenience wrapper over one handle (host numpy arrays in and out)."""
 
@@ -270,3 +286,9 @@ class Grid:
 
     def updates_per_step(self):
         return lbm_updates_per_step(self.h)
+
+    def tune(self, reps=5):
+        return lbm_tune(self.h, reps)
+
+    def set_variants(self, variants):
+        lbm_set_variants(self.h, variants)

@@ -1,0 +1,105 @@
+"""GPU FP32 deviation storage against the FP64 oracle, at the stated
+tolerances: density max-abs error < 1e-5, velocity relative L2 error < 1e-4
+(per level), on the benchmark workloads at reduced size and, for one or two
+steps, at full size."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2004_11863_amd import inputs as I
+from parity_util import compare_fp32, compare_fp64, make_pair
+
+pytestmark = pytest.mark.gpu
+
+RHO_TOL = 1e-5
+U_TOL = 1e-4
+
+
+def _lbm():
+    from paper_2004_11863_amd import lbm
+    return lbm
+
+
+def _check(out):
+    for k, v in out.items():
+        tol = RHO_TOL if k.startswith("rho") else U_TOL
+        assert v < tol, (k, v, out)
+
+
+@pytest.mark.parametrize("model", ["BGK", "RR", "HRR"])
+def test_fp32_config1(model):
+    lbm = _lbm()
+    gpu, ref, levels = make_pair(I.config1(0), model, lbm.LBM_FP32_DEV)
+    gpu.step(200)
+    ref.step(200)
+    out = compare_fp32(gpu, ref, levels)
+    gpu.close()
+    print(model, out)
+    _check(out)
+
+
+@pytest.mark.parametrize("model", ["RR", "HRR"])
+def test_fp32_config2_at_512(model):
+    lbm = _lbm()
+    gpu, ref, levels = make_pair(I.config2(seed=1, n=512), model, lbm.LBM_FP32_DEV)
+    gpu.step(300)
+    ref.step(300)
+    out = compare_fp32(gpu, ref, levels)
+    gpu.close()
+    print(model, out)
+    _check(out)
+
+
+@pytest.mark.parametrize("model", ["RR", "HRR"])
+def test_fp32_config3_64cube_subcase(model):
+    lbm = _lbm()
+    gpu, ref, levels = make_pair(I.config3(seed=2, n=64), model, lbm.LBM_FP32_DEV)
+    gpu.step(24)
+    ref.step(24)
+    out = compare_fp32(gpu, ref, levels)
+    gpu.close()
+    print(model, out)
+    _check(out)
+
+
+def test_full_size_config2_fp32_and_fp64():
+    """The 4096^2 benchmark grid itself, two coarse steps, against the oracle."""
+    lbm = _lbm()
+    wl = I.config2(seed=0, n=4096)
+    gpu, ref, levels = make_pair(wl, "RR", lbm.LBM_FP32_DEV)
+    g64, _, _ = make_pair(wl, "RR", lbm.LBM_FP64, with_oracle=False)
+    gpu.step(2)
+    g64.step(2)
+    ref.step(2)
+    out = compare_fp32(gpu, ref, levels)
+    gpu.close()
+    worst = 0.0
+    for lv in levels:
+        r1, u1 = g64.get_macros(lv)
+        r0, u0 = ref.get_macros(lv)
+        worst = max(worst, float(np.abs(r1 - r0).max() / np.abs(r0).max()),
+                    float(np.abs(u1 - u0).max() / np.abs(u0).max()))
+    g64.close()
+    print(out, worst)
+    _check(out)
+    assert worst <= 1e-12
+
+
+def test_full_size_config3_fp32_one_step():
+    """The 384^3 benchmark grid itself, one coarse step, against the oracle."""
+    import os
+    try:
+        mem = os.sysconf("SC_PAGE_SIZE") * os.sysconf("SC_PHYS_PAGES")
+    except (ValueError, OSError):
+        mem = 0
+    if mem < 96 * 2 ** 30:
+        pytest.skip("needs about 60 GiB of host memory for the oracle")
+    lbm = _lbm()
+    wl = I.config3(seed=0, n=384)
+    gpu, ref, levels = make_pair(wl, "RR", lbm.LBM_FP32_DEV)
+    gpu.step(1)
+    ref.step(1)
+    out = compare_fp32(gpu, ref, levels)
+    gpu.close()
+    print(out)
+    _check(out)

@@ -140,3 +140,63 @@ def test_zero_steps_and_determinism():
         outs.append((gpu.get_populations(0), gpu.get_populations(1)))
         gpu.close()
     assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("model", ["RR", "HRR"])
+def test_every_kernel_variant_gives_identical_results(prec, model):
+    """Bulk-kernel variants differ only in work decomposition: each node's
+    arithmetic is the same, so results are bitwise equal; the autotuner
+    leaves the state untouched."""
+    lbm = _lbm()
+    p = lbm.LBM_FP32_DEV if prec == "fp32" else lbm.LBM_FP64
+    nvar = 5 if prec == "fp32" else 3
+    wl = I.config1(4)
+    ref = None
+    live = None
+    for v in range(nvar):
+        gpu, _, _ = make_pair(wl, model, p, with_oracle=False)
+        if live is None:  # covered coarse nodes hold unspecified values
+            live = gpu.class_map(0) != lbm.LBM_C_COVERED
+        gpu.set_variants([v, v, v, v])
+        gpu.step(12)
+        out = (gpu.get_populations(0)[:, live], gpu.get_populations(1))
+        gpu.close()
+        if ref is None:
+            ref = out
+        else:
+            d = max(float(np.abs(out[0] - ref[0]).max()), float(np.abs(out[1] - ref[1]).max()))
+            assert d == 0.0, (v, d)
+    gpu, _, _ = make_pair(wl, model, p, with_oracle=False)
+    gpu.step(5)
+    chosen = gpu.tune(reps=2)
+    assert all(0 <= c < nvar for c in chosen)
+    gpu.step(7)
+    out = (gpu.get_populations(0)[:, live], gpu.get_populations(1))
+    gpu.close()
+    assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_variants_on_ragged_3d_and_2d(D):
+    lbm = _lbm()
+    if D == 2:
+        geom = _geom(2, (71, 37), (6, 5), (33, 30))
+    else:
+        geom = _geom(3, (27, 21, 22), (4, 5, 3), (19, 14, 17))
+    wl = I.Workload(geom=geom, U=(0.04, 0.01, 0.0), pulses=[I.Pulse(center=tuple(x / 2 for x in geom.n[:D]), A=1e-3, R=2.0)])
+    ref = None
+    for v in range(3):
+        gpu, orc, levels = make_pair(wl, "RR", lbm.LBM_FP64, with_oracle=(v == 0))
+        gpu.set_variants([v, v, v, v])
+        gpu.step(9)
+        if v == 0:
+            orc.step(9)
+            w = compare_fp64(gpu, orc, levels)
+            assert max(w.values()) <= TOL64, w
+        out = gpu.get_populations(1)
+        gpu.close()
+        if ref is None:
+            ref = out
+        else:
+            assert np.array_equal(out, ref)
