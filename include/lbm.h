@@ -172,6 +172,48 @@ int lbm_set_variants(lbm_handle h, const int32_t variants[4]);
 /* Last error text for a handle (NULL: last failure of lbm_create_grid). */
 const char* lbm_last_error(lbm_handle h);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent grids of one lattice, collision model and
+ * precision, each with its own geometry, tau and sigma, advanced together.
+ * Each coarse step is one sequence of persistent launches over the work of
+ * all grids (bulk tiles, interface node blocks), captured once as a hipGraph
+ * and replayed; grids may join and leave between steps (continuous
+ * batching), which rewrites device work lists without re-capturing.  A grid
+ * in a batch computes exactly what the same grid computes alone.
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_batch* lbm_batch_handle;
+
+/* capacity: maximum number of grids held at once. */
+int lbm_batch_create(int lattice, int collision, int precision, int device, int capacity, lbm_batch_handle* out);
+int lbm_batch_destroy(lbm_batch_handle b);
+/* Adds a grid (allocates its device state; the descriptor's lattice,
+ * collision and precision must match the batch).  *slot receives its index.
+ * LBM_ENOMEM when the batch is full or device memory runs out. */
+int lbm_batch_add(lbm_batch_handle b, const lbm_grid_desc* d, int32_t* slot);
+/* Removes a grid and frees its device state. */
+int lbm_batch_remove(lbm_batch_handle b, int slot);
+/* As lbm_set_state / lbm_get_macros / lbm_get_populations for one grid. */
+int lbm_batch_set_state(lbm_batch_handle b, int slot, int level, const double* rho, const double* u, int mem);
+int lbm_batch_get_macros(lbm_batch_handle b, int slot, int level, double* rho, double* u, int mem);
+int lbm_batch_get_populations(lbm_batch_handle b, int slot, int level, double* f, int mem);
+/* Enqueues n coarse steps of every grid in the batch (asynchronous). */
+int lbm_batch_step(lbm_batch_handle b, int n, void* hip_stream);
+/* on = 0: launch the phases directly instead of replaying the graph. */
+int lbm_batch_use_graph(lbm_batch_handle b, int on);
+/* Autotuner over the bulk-kernel variants of the whole batch; variants[2]
+ * receives the chosen coarse and fine variant.  Synchronous. */
+int lbm_batch_tune(lbm_batch_handle b, int reps, int32_t variants[2]);
+/* info[3] = {grids held, lattice updates per coarse step over all grids,
+ * device bytes of their state}. */
+int lbm_batch_info(lbm_batch_handle b, int64_t info[3]);
+/* Coarse steps taken by a grid since it joined (or since its last
+ * lbm_batch_set_state of level 0). */
+int lbm_batch_slot_steps(lbm_batch_handle b, int slot, int64_t* steps);
+/* Device bytes a grid of this descriptor occupies (populations, macro
+ * planes, history, interface tables), for admission by memory footprint. */
+int lbm_footprint(const lbm_grid_desc* d, int64_t* bytes);
+const char* lbm_batch_last_error(lbm_batch_handle b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -86,11 +86,17 @@ inline Tiling make_tiling(int nx, int ny, int nz, int xb, int V, int LX, int TY)
   return t;
 }
 
-// First node x0 of this work-item's V-node vector; false outside the level.
-template <int V, int LX, int TY>
-__device__ inline bool tile_vec(const Tiling& t, int& x0, int& y, int& z) {
+// Tile of this work group in a single-grid launch: each XCD gets one
+// contiguous run of per_xcd tiles.
+__device__ inline int xcd_tile(const Tiling& t) {
   const int b = blockIdx.x;
-  const int tile = (b % kXCD) * t.per_xcd + b / kXCD;
+  return (b % kXCD) * t.per_xcd + b / kXCD;
+}
+
+// First node x0 of this work-item's V-node vector in tile `tile`; false
+// outside the level.
+template <int V, int LX, int TY>
+__device__ inline bool tile_vec(const Tiling& t, int tile, int& x0, int& y, int& z) {
   if (tile >= t.ntiles) return false;
   const int tx = tile % t.ntx;
   const int r = tile / t.ntx;
@@ -146,15 +152,15 @@ __device__ inline bool skip_vec(const Geo& g, int x0, int V, int y, int z, int n
 // nodes and fine ring columns: the schedule overwrites TN and ring nodes
 // afterwards and never reads covered ones.
 template <int LAT, bool DEV, typename S, int MODEL, int LEVEL, int V, int LX, bool NT>
-__global__ __launch_bounds__(256) void k_stream(const S* __restrict__ src, S* __restrict__ dst, S* __restrict__ mac,
-                                                const Geo g, const Tiling tl, const S om) {
+__device__ inline void stream_body(const S* __restrict__ src, S* __restrict__ dst, S* __restrict__ mac, const Geo& g,
+                                   const Tiling& tl, const S om, int tile) {
   using L = Lattice<LAT>;
   using N = Node<LAT, DEV, S>;
   using VA = typename VT<S, V>::a;
   constexpr int Q = L::Q;
   constexpr int TY = 256 / LX;
   int x0, y, z;
-  if (!tile_vec<V, LX, TY>(tl, x0, y, z)) return;
+  if (!tile_vec<V, LX, TY>(tl, tile, x0, y, z)) return;
   const int nx = tl.nx, ny = tl.ny, nz = tl.nz;
   if (skip_vec<LEVEL, L::D>(g, x0, V, y, z, nx, ny, nz)) return;
   const int64_t P = LEVEL == 0 ? g.pc : g.pf;
@@ -203,20 +209,26 @@ __global__ __launch_bounds__(256) void k_stream(const S* __restrict__ src, S* __
   for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + (int64_t)i * NP + own), v[i]);
 }
 
+template <int LAT, bool DEV, typename S, int MODEL, int LEVEL, int V, int LX, bool NT>
+__global__ __launch_bounds__(256) void k_stream(const S* __restrict__ src, S* __restrict__ dst, S* __restrict__ mac,
+                                                const Geo g, const Tiling tl, const S om) {
+  stream_body<LAT, DEV, S, MODEL, LEVEL, V, LX, NT>(src, dst, mac, g, tl, om, xcd_tile(tl));
+}
+
 // H-RR collision in place on a level, with the strain rate from centred
 // differences (second order, level lattice units) of the velocity planes of
 // mac (Sec. 3.3).  Processes whole vectors like k_stream; the coarse pass runs
 // before the fine-to-coarse transfer overwrites TN nodes.
 template <int LAT, bool DEV, typename S, int LEVEL, int V, int LX, bool NT>
-__global__ __launch_bounds__(256) void k_collide_hrr(S* __restrict__ buf, const S* __restrict__ mac, const Geo g,
-                                                     const Tiling tl, const S om, const S tau, const S sig) {
+__device__ inline void collide_hrr_body(S* __restrict__ buf, const S* __restrict__ mac, const Geo& g, const Tiling& tl,
+                                        const S om, const S tau, const S sig, int tile) {
   using L = Lattice<LAT>;
   using N = Node<LAT, DEV, S>;
   using VA = typename VT<S, V>::a;
   constexpr int Q = L::Q, D = L::D;
   constexpr int TY = 256 / LX;
   int x0, y, z;
-  if (!tile_vec<V, LX, TY>(tl, x0, y, z)) return;
+  if (!tile_vec<V, LX, TY>(tl, tile, x0, y, z)) return;
   const int nx = tl.nx, ny = tl.ny, nz = tl.nz;
   if (skip_vec<LEVEL, D>(g, x0, V, y, z, nx, ny, nz)) return;
   const int64_t P = LEVEL == 0 ? g.pc : g.pf;
@@ -278,16 +290,84 @@ __global__ __launch_bounds__(256) void k_collide_hrr(S* __restrict__ buf, const 
   for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(buf + (int64_t)i * NP + own), v[i]);
 }
 
+template <int LAT, bool DEV, typename S, int LEVEL, int V, int LX, bool NT>
+__global__ __launch_bounds__(256) void k_collide_hrr(S* __restrict__ buf, const S* __restrict__ mac, const Geo g,
+                                                     const Tiling tl, const S om, const S tau, const S sig) {
+  collide_hrr_body<LAT, DEV, S, LEVEL, V, LX, NT>(buf, mac, g, tl, om, tau, sig, xcd_tile(tl));
+}
+
 // ---------------------------------------------------------------------------
 // Interface data.  History fields per coarse history node, double precision:
-// rho, u[D], f1[Q] (pre-collision non-equilibrium part), S[NS] (H-RR).
-template <int LAT>
+// rho, u[D], the pre-collision non-equilibrium part, and (H-RR) S[NS].  The
+// non-equilibrium part is kept in full (f1[Q]) for BGK, whose collision keeps
+// every non-equilibrium moment.  RR and H-RR rebuild ring and TN nodes from
+// rho, u and the second-order moment a1 = sum_i H2_i f1_i only: the
+// interpolation, rescaling and filtering are linear and f1 carries no mass or
+// momentum, so transferring a1 (NS components) gives the same populations as
+// transferring f1 and projecting afterwards.
+template <int LAT, int MODEL>
 struct HF {
   static constexpr int D = Lattice<LAT>::D, Q = Lattice<LAT>::Q;
-  static constexpr int RHO = 0, U = 1, F1 = 1 + D, S = 1 + D + Q;
   static constexpr int NSC = NS<D>::value;
-  static constexpr int N = 1 + D + Q + NSC;
+  static constexpr int NF1 = MODEL == M_BGK ? Q : NSC;
+  static constexpr int RHO = 0, U = 1, F1 = 1 + D, S = 1 + D + NF1;
+  static constexpr int N = 1 + D + NF1 + (MODEL == M_HRR ? NSC : 0);
 };
+
+// Symmetric tensor <-> its NS stored components (xx, yy, xy | xx, yy, zz, xy,
+// xz, yz).
+template <int D>
+__device__ inline void sym_put(const Sym<double>& a, double* out, double scale) {
+  out[0] = scale * a.xx;
+  out[1] = scale * a.yy;
+  if (D == 2) {
+    out[2] = scale * a.xy;
+  } else {
+    out[2] = scale * a.zz;
+    out[3] = scale * a.xy;
+    out[4] = scale * a.xz;
+    out[5] = scale * a.yz;
+  }
+}
+template <int D>
+__device__ inline Sym<double> sym_get(const double* v, double scale) {
+  Sym<double> a{0, 0, 0, 0, 0, 0};
+  a.xx = scale * v[0];
+  a.yy = scale * v[1];
+  if (D == 2) {
+    a.xy = scale * v[2];
+  } else {
+    a.zz = scale * v[2];
+    a.xy = scale * v[3];
+    a.xz = scale * v[4];
+    a.yz = scale * v[5];
+  }
+  return a;
+}
+
+// Second-order non-equilibrium moment of full populations f with moments
+// rho, u (eq a1Proj with the third-order equilibrium).
+template <int LAT>
+__device__ inline Sym<double> a1_of(const double* f, double rho, const double* u) {
+  using N = Node<LAT, false, double>;
+  const Sym<double> P = N::second(f);
+  const double r3 = rho * (1.0 / 3.0);
+  Sym<double> a;
+  a.xx = P.xx - r3 - rho * u[0] * u[0];
+  a.yy = P.yy - r3 - rho * u[1] * u[1];
+  a.zz = Lattice<LAT>::D == 3 ? P.zz - r3 - rho * u[2] * u[2] : 0.0;
+  a.xy = P.xy - rho * u[0] * u[1];
+  a.xz = Lattice<LAT>::D == 3 ? P.xz - rho * u[0] * u[2] : 0.0;
+  a.yz = Lattice<LAT>::D == 3 ? P.yz - rho * u[1] * u[2] : 0.0;
+  return a;
+}
+
+// H-RR stress mix of eq a1ij_HRR: a <- sig a + (1 - sig)(-2 tau rho c_s^2 S).
+__device__ inline Sym<double> hrr_mix(const Sym<double>& a, const Sym<double>& S, double sig, double tau, double rho) {
+  const double k = (1.0 - sig) * (-2.0 / 3.0) * tau * rho;
+  return Sym<double>{sig * a.xx + k * S.xx, sig * a.yy + k * S.yy, sig * a.zz + k * S.zz,
+                     sig * a.xy + k * S.xy, sig * a.xz + k * S.xz, sig * a.yz + k * S.yz};
+}
 
 struct Iface {
   int64_t NH;
@@ -311,14 +391,14 @@ __device__ inline S store_pop(double f, int i) {
 }
 
 // Pre-collision state of coarse history nodes at t+1 (pulled from the
-// post-collision coarse state at t): rho, u and f1 = f - f0(rho, u).
-template <int LAT, bool DEV, typename S>
-__global__ void k_hist_capture(const S* __restrict__ src, double* __restrict__ H, const Geo g, const Iface itf) {
+// post-collision coarse state at t): rho, u and the non-equilibrium part.
+template <int LAT, bool DEV, typename S, int MODEL>
+__device__ inline void hist_capture_body(const S* __restrict__ src, double* __restrict__ H, const Geo& g,
+                                         const Iface& itf, int64_t h) {
   using L = Lattice<LAT>;
-  using F = HF<LAT>;
+  using F = HF<LAT, MODEL>;
   using N = Node<LAT, false, double>;
   constexpr int Q = L::Q;
-  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= itf.NH) return;
   int x, y, z;
   cdecode(g, itf.hnode[h], x, y, z);
@@ -330,26 +410,39 @@ __global__ void k_hist_capture(const S* __restrict__ src, double* __restrict__ H
     const int zs = L::D == 3 ? wrap(z - L::cz(i), nz) : 0;
     f[i] = full_pop<S, DEV, LAT>(src[(int64_t)i * g.Ncp + cpos(g, xs, ys, zs)], i);
   }
-  double rho, r0, u[3], f0[Q];
+  double rho, r0, u[3];
   N::moments(f, rho, r0, u);
-  N::feq(rho, r0, u, f0);
   const int64_t NH = itf.NH;
   H[F::RHO * NH + h] = rho;
 #pragma unroll
   for (int d = 0; d < L::D; ++d) H[(F::U + d) * NH + h] = u[d];
+  if (MODEL == M_BGK) {
+    double f0[Q];
+    N::feq(rho, r0, u, f0);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) H[(F::F1 + i) * NH + h] = f[i] - f0[i];
+    for (int i = 0; i < Q; ++i) H[(F::F1 + i) * NH + h] = f[i] - f0[i];
+  } else {
+    double a[NS<L::D>::value];
+    sym_put<L::D>(a1_of<LAT>(f, rho, u), a, 1.0);
+#pragma unroll
+    for (int k = 0; k < NS<L::D>::value; ++k) H[(F::F1 + k) * NH + h] = a[k];
+  }
 }
+template <int LAT, bool DEV, typename S, int MODEL>
+__global__ void k_hist_capture(const S* __restrict__ src, double* __restrict__ H, const Geo g, const Iface itf) {
+  hist_capture_body<LAT, DEV, S, MODEL>(src, H, g, itf, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 
 // H-RR: coarse strain rate at t+1 on the history nodes, by centred
 // differences of the coarse velocity planes (TN entries come from the
 // fictitious propagation on the fine level).
 template <int LAT, typename T>
-__global__ void k_hist_strain(const T* __restrict__ mac_c, double* __restrict__ H, const Geo g, const Iface itf) {
+__device__ inline void hist_strain_body(const T* __restrict__ mac_c, double* __restrict__ H, const Geo& g,
+                                        const Iface& itf, int64_t h) {
   using L = Lattice<LAT>;
-  using F = HF<LAT>;
+  using F = HF<LAT, M_HRR>;
   constexpr int D = L::D;
-  const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= itf.NH) return;
   int x, y, z;
   cdecode(g, itf.hnode[h], x, y, z);
@@ -362,18 +455,19 @@ __global__ void k_hist_strain(const T* __restrict__ mac_c, double* __restrict__ 
     const int64_t ip = cpos(g, cp[0], cp[1], cp[2]), im = cpos(g, cm[0], cm[1], cm[2]);
     for (int b = 0; b < D; ++b) gr[a][b] = 0.5 * ((double)mac_c[(1 + b) * g.Ncp + ip] - (double)mac_c[(1 + b) * g.Ncp + im]);
   }
+  const Sym<double> S{gr[0][0], gr[1][1], gr[2][2], 0.5 * (gr[0][1] + gr[1][0]), 0.5 * (gr[0][2] + gr[2][0]),
+                      0.5 * (gr[1][2] + gr[2][1])};
+  double v[NS<D>::value];
+  sym_put<D>(S, v, 1.0);
   const int64_t NH = itf.NH;
-  H[(F::S + 0) * NH + h] = gr[0][0];
-  H[(F::S + 1) * NH + h] = gr[1][1];
-  if (D == 2) {
-    H[(F::S + 2) * NH + h] = 0.5 * (gr[0][1] + gr[1][0]);
-  } else {
-    H[(F::S + 2) * NH + h] = gr[2][2];
-    H[(F::S + 3) * NH + h] = 0.5 * (gr[0][1] + gr[1][0]);
-    H[(F::S + 4) * NH + h] = 0.5 * (gr[0][2] + gr[2][0]);
-    H[(F::S + 5) * NH + h] = 0.5 * (gr[1][2] + gr[2][1]);
-  }
+#pragma unroll
+  for (int k = 0; k < NS<D>::value; ++k) H[(F::S + k) * NH + h] = v[k];
 }
+template <int LAT, typename T>
+__global__ void k_hist_strain(const T* __restrict__ mac_c, double* __restrict__ H, const Geo g, const Iface itf) {
+  hist_strain_body<LAT, T>(mac_c, H, g, itf, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 
 // Temporal interpolation of every history field (eq TempInt): G = c0 H(t-1)
 // + c1 H(t) + c2 H(t+1), for all fields of all history nodes.
@@ -398,11 +492,10 @@ __device__ inline double ring_w(int np, int s) {
 // Ring nodes, rho and u only (H-RR needs them before the fine collision).
 // Temporal weights c applied inline to the three history levels.
 template <int LAT, typename T>
-__global__ void k_ring_macro(const double* __restrict__ Hm, const double* __restrict__ H0,
-                             const double* __restrict__ Hp, double c0, double c1, double c2,
-                             T* __restrict__ mac_f, const Geo g, const Iface itf) {
+__device__ inline void ring_macro_body(const double* __restrict__ Hm, const double* __restrict__ H0,
+                                       const double* __restrict__ Hp, double c0, double c1, double c2,
+                                       T* __restrict__ mac_f, const Geo& g, const Iface& itf, int64_t r) {
   using L = Lattice<LAT>;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= itf.NR) return;
   const int np = itf.rnp[r];
   const int32_t* pt = itf.rpt + 16 * r;
@@ -425,59 +518,64 @@ __global__ void k_ring_macro(const double* __restrict__ Hm, const double* __rest
 #pragma unroll
   for (int k = 0; k < 1 + L::D; ++k) mac_f[(int64_t)k * g.Nfp + fi] = (T)v[k];
 }
+template <int LAT, typename T>
+__global__ void k_ring_macro(const double* __restrict__ Hm, const double* __restrict__ H0,
+                             const double* __restrict__ Hp, double c0, double c1, double c2,
+                             T* __restrict__ mac_f, const Geo g, const Iface itf) {
+  ring_macro_body<LAT, T>(Hm, H0, Hp, c0, c1, c2, mac_f, g, itf, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
 
-// Ring nodes: rho, u, f1 (and S) interpolated from the (time-interpolated)
-// history G, populations rebuilt as f0(rho, u) + tau_f/(2 tau_c) f1 (eq
-// rescff), S^f = S^c / 2 (eq PijResc), collided with tau_f and stored.
+
+// Ring nodes: rho, u, the non-equilibrium part (and S) interpolated from the
+// (time-interpolated) history G; populations rebuilt as f0(rho, u) +
+// tau_f/(2 tau_c) f1 (eq rescff), S^f = S^c / 2 (eq PijResc), collided with
+// tau_f and stored.  RR / H-RR evaluate the post-collision state directly
+// from rho, u and the rescaled a1.
 template <int LAT, bool DEV, typename S, int MODEL>
-__global__ void k_ring(const double* __restrict__ G, S* __restrict__ dst, const Geo g, const Iface itf,
-                       double kf, double om_f, double tau_f, double sig) {
+__device__ inline void ring_body(const double* __restrict__ G, S* __restrict__ dst, const Geo& g, const Iface& itf,
+                                 double kf, double om_f, double tau_f, double sig, int64_t r) {
   using L = Lattice<LAT>;
-  using F = HF<LAT>;
+  using F = HF<LAT, MODEL>;
   using N = Node<LAT, false, double>;
-  constexpr int Q = L::Q;
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  constexpr int Q = L::Q, D = L::D;
   if (r >= itf.NR) return;
   const int np = itf.rnp[r];
   const int32_t* pt = itf.rpt + 16 * r;
   const int64_t NH = itf.NH;
-  constexpr int NF = (MODEL == M_HRR) ? F::N : F::S;
-  double v[NF];
+  double v[F::N];
 #pragma unroll
-  for (int k = 0; k < NF; ++k) v[k] = 0.0;
+  for (int k = 0; k < F::N; ++k) v[k] = 0.0;
   for (int s = 0; s < np; ++s) {
     const int64_t h = pt[s];
     const double ws = ring_w(np, s);
 #pragma unroll
-    for (int k = 0; k < NF; ++k) v[k] += ws * G[(int64_t)k * NH + h];
+    for (int k = 0; k < F::N; ++k) v[k] += ws * G[(int64_t)k * NH + h];
   }
-  double u[3] = {v[F::U], v[F::U + 1], L::D == 3 ? v[F::U + 2] : 0.0};
+  const double rho = v[F::RHO];
+  double u[3] = {v[F::U], v[F::U + 1], D == 3 ? v[F::U + 2] : 0.0};
   double f[Q];
-  N::feq(v[F::RHO], v[F::RHO], u, f);
+  if (MODEL == M_BGK) {
+    N::feq(rho, rho, u, f);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) f[i] += kf * v[F::F1 + i];
-  Sym<double> Sf{0, 0, 0, 0, 0, 0};
-  if (MODEL == M_HRR) {
-    if (L::D == 2) {
-      Sf.xx = 0.5 * v[F::S];
-      Sf.yy = 0.5 * v[F::S + 1];
-      Sf.xy = 0.5 * v[F::S + 2];
-    } else {
-      Sf.xx = 0.5 * v[F::S];
-      Sf.yy = 0.5 * v[F::S + 1];
-      Sf.zz = 0.5 * v[F::S + 2];
-      Sf.xy = 0.5 * v[F::S + 3];
-      Sf.xz = 0.5 * v[F::S + 4];
-      Sf.yz = 0.5 * v[F::S + 5];
-    }
+    for (int i = 0; i < Q; ++i) f[i] += kf * v[F::F1 + i];
+    N::collide(f, M_BGK, om_f, tau_f, sig, nullptr);
+  } else {
+    Sym<double> a = sym_get<D>(v + F::F1, kf);
+    if (MODEL == M_HRR) a = hrr_mix(a, sym_get<D>(v + F::S, 0.5), sig, tau_f, rho);
+    N::eval(N::coef(rho, rho, u, om_f, a), f);
   }
-  N::collide(f, MODEL, om_f, tau_f, sig, &Sf);
   int x, y, z;
   fdecode(g, itf.rnode[r], x, y, z);
   const int64_t fi = fpos(g, x, y, z);
 #pragma unroll
   for (int i = 0; i < Q; ++i) dst[(int64_t)i * g.Nfp + fi] = store_pop<S, DEV, LAT>(f[i], i);
 }
+template <int LAT, bool DEV, typename S, int MODEL>
+__global__ void k_ring(const double* __restrict__ G, S* __restrict__ dst, const Geo g, const Iface itf,
+                       double kf, double om_f, double tau_f, double sig) {
+  ring_body<LAT, DEV, S, MODEL>(G, dst, g, itf, kf, om_f, tau_f, sig, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 
 // Pull of Q populations into fine node (x, y, z) from a fine buffer.
 template <int LAT, bool DEV, typename S>
@@ -491,10 +589,10 @@ __device__ inline void pull_fine(const S* __restrict__ src, const Geo& g, int x,
 // H-RR: fictitious propagation onto TN^f (Sec. 4.3, step e): u(TN, t+1) from
 // the fine post-collision state at t+1/2, written to the coarse macro planes.
 template <int LAT, bool DEV, typename S, typename T>
-__global__ void k_fict(const S* __restrict__ src_f, T* __restrict__ mac_c, const Geo g, const Iface itf) {
+__device__ inline void fict_body(const S* __restrict__ src_f, T* __restrict__ mac_c, const Geo& g, const Iface& itf,
+                                 int64_t t) {
   using L = Lattice<LAT>;
   using N = Node<LAT, false, double>;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= itf.NT) return;
   int x, y, z;
   fdecode(g, itf.tnf[t], x, y, z);
@@ -508,51 +606,68 @@ __global__ void k_fict(const S* __restrict__ src_f, T* __restrict__ mac_c, const
 #pragma unroll
   for (int d = 0; d < L::D; ++d) mac_c[(int64_t)(1 + d) * g.Ncp + ci] = (T)u[d];
 }
+template <int LAT, bool DEV, typename S, typename T>
+__global__ void k_fict(const S* __restrict__ src_f, T* __restrict__ mac_c, const Geo g, const Iface itf) {
+  fict_body<LAT, DEV, S, T>(src_f, mac_c, g, itf, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 
 // Fine-to-coarse transfer at TN (Sec. 4.3, synchronous step d).  The fine
 // pre-collision state at t+1 around TN^f is re-pulled from the fine
-// post-collision state at t+1/2; its non-equilibrium part is filtered with
-// the tensor product of (1/4, 1/2, 1/4) (eq filterFneq), rescaled by
-// 2 tau_c / tau_f (eq rescfc) and added to f0 of the co-located fine node;
-// H-RR takes S^c = 2 S^f (eq PijResc) with S^f by fine centred differences.
-// The coarse node is then collided with tau_c and stored.
-// One work group handles PER TN nodes: one lane per (TN node, stencil node)
-// computes that node's weighted non-equilibrium part into LDS, lanes per
-// (TN node, population) sum the stencil in a fixed order, and one lane per
-// TN node rebuilds and collides.
+// post-collision state at t+1/2; its non-equilibrium part (full f1 for BGK,
+// a1 for RR / H-RR) is filtered with the tensor product of (1/4, 1/2, 1/4)
+// (eq filterFneq), rescaled by 2 tau_c / tau_f (eq rescfc) and added to f0
+// of the co-located fine node; H-RR takes S^c = 2 S^f (eq PijResc) with S^f
+// by fine centred differences.  The coarse node is then collided with tau_c.
+// One work group handles PER TN nodes: lane (stencil point s, TN node t),
+// t fastest so neighbouring lanes read neighbouring nodes, computes the
+// weighted non-equilibrium part of one stencil node into LDS; lanes per
+// (TN node, component) sum the stencil in a fixed order; one lane per TN node
+// rebuilds and collides.
 template <int LAT, bool DEV, typename S, int MODEL>
-__global__ __launch_bounds__(256) void k_coalesce(const S* __restrict__ src_f, S* __restrict__ dst_c, const Geo g,
-                                                  const Iface itf, double kc, double om_c, double tau_c, double sig) {
+__device__ inline void coalesce_body(const S* __restrict__ src_f, S* __restrict__ dst_c, const Geo& g, const Iface& itf,
+                                     double kc, double om_c, double tau_c, double sig, int64_t blk) {
   using L = Lattice<LAT>;
   using N = Node<LAT, false, double>;
+  using F = HF<LAT, MODEL>;
   constexpr int Q = L::Q, D = L::D;
   constexpr int NST = (D == 2) ? 9 : 27;
   constexpr int PER = 256 / NST;
   constexpr int CEN = (D == 2) ? 4 : 13;
-  __shared__ double sf1[PER][NST][Q];
+  constexpr int NC = F::NF1;  // components filtered per stencil node
+  __shared__ double sf1[PER][NST][NC];
   __shared__ double sm[PER][NST][4];
-  __shared__ double sacc[PER][Q];
-  const int lt = threadIdx.x / NST, s = threadIdx.x % NST;
-  const int64_t t = (int64_t)blockIdx.x * PER + lt;
-  if (lt < PER && t < itf.NT) {
+  __shared__ double sacc[PER][NC];
+  __syncthreads();  // the LDS may still be read by a previous call in this work group
+  const int lt = threadIdx.x % PER, s = threadIdx.x / PER;
+  const int64_t t = blk * PER + lt;
+  if (s < NST && t < itf.NT) {
     int x, y, z;
     fdecode(g, itf.tnf[t], x, y, z);
     const int ox = s % 3 - 1, oy = (s / 3) % 3 - 1, oz = (D == 3) ? s / 9 - 1 : 0;
-    double f[Q], rho, r0, u[3], f0[Q];
+    double f[Q], rho, r0, u[3];
     pull_fine<LAT, DEV, S>(src_f, g, x + ox, y + oy, z + oz, f);
     N::moments(f, rho, r0, u);
-    N::feq(rho, r0, u, f0);
     const double w = (ox ? 0.25 : 0.5) * (oy ? 0.25 : 0.5) * (D == 3 ? (oz ? 0.25 : 0.5) : 1.0);
+    if (MODEL == M_BGK) {
+      double f0[Q];
+      N::feq(rho, r0, u, f0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) sf1[lt][s][i] = w * (f[i] - f0[i]);
+      for (int i = 0; i < Q; ++i) sf1[lt][s][i] = w * (f[i] - f0[i]);
+    } else {
+      double a[NS<D>::value];
+      sym_put<D>(a1_of<LAT>(f, rho, u), a, w);
+#pragma unroll
+      for (int k = 0; k < NC; ++k) sf1[lt][s][k] = a[k];
+    }
     sm[lt][s][0] = rho;
     sm[lt][s][1] = u[0];
     sm[lt][s][2] = u[1];
     sm[lt][s][3] = u[2];
   }
   __syncthreads();
-  for (int p = threadIdx.x; p < PER * Q; p += blockDim.x) {
-    const int l2 = p / Q, q = p % Q;
+  for (int p = threadIdx.x; p < PER * NC; p += blockDim.x) {
+    const int l2 = p / NC, q = p % NC;
     double acc = 0.0;
     for (int k = 0; k < NST; ++k) acc += sf1[l2][k][q];
     sacc[l2][q] = acc;
@@ -560,36 +675,45 @@ __global__ __launch_bounds__(256) void k_coalesce(const S* __restrict__ src_f, S
   __syncthreads();
   if ((int)threadIdx.x >= PER) return;
   const int l3 = threadIdx.x;
-  const int64_t t3 = (int64_t)blockIdx.x * PER + l3;
+  const int64_t t3 = blk * PER + l3;
   if (t3 >= itf.NT) return;
   const double rc = sm[l3][CEN][0];
   double uc[3] = {sm[l3][CEN][1], sm[l3][CEN][2], sm[l3][CEN][3]};
   double f[Q];
-  N::feq(rc, rc, uc, f);
+  if (MODEL == M_BGK) {
+    N::feq(rc, rc, uc, f);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) f[i] += kc * sacc[l3][i];
-  Sym<double> Sc{0, 0, 0, 0, 0, 0};
-  if (MODEL == M_HRR) {
-    // neighbours along +-x, +-y, +-z are stencil entries CEN +- 1, 3, 9
-    const int st[3] = {1, 3, 9};
-    double gr[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    for (int a = 0; a < D; ++a)
-      for (int b = 0; b < D; ++b) gr[a][b] = 0.5 * (sm[l3][CEN + st[a]][1 + b] - sm[l3][CEN - st[a]][1 + b]);
-    Sc.xx = 2.0 * gr[0][0];
-    Sc.yy = 2.0 * gr[1][1];
-    Sc.xy = 2.0 * (0.5 * (gr[0][1] + gr[1][0]));
-    if (D == 3) {
-      Sc.zz = 2.0 * gr[2][2];
-      Sc.xz = 2.0 * (0.5 * (gr[0][2] + gr[2][0]));
-      Sc.yz = 2.0 * (0.5 * (gr[1][2] + gr[2][1]));
+    for (int i = 0; i < Q; ++i) f[i] += kc * sacc[l3][i];
+    N::collide(f, M_BGK, om_c, tau_c, sig, nullptr);
+  } else {
+    Sym<double> a = sym_get<D>(sacc[l3], kc);
+    if (MODEL == M_HRR) {
+      // neighbours along +-x, +-y, +-z are stencil entries CEN +- 1, 3, 9
+      const int st[3] = {1, 3, 9};
+      double gr[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      for (int aa = 0; aa < D; ++aa)
+        for (int b = 0; b < D; ++b) gr[aa][b] = 0.5 * (sm[l3][CEN + st[aa]][1 + b] - sm[l3][CEN - st[aa]][1 + b]);
+      const Sym<double> Sc{2.0 * gr[0][0],
+                           2.0 * gr[1][1],
+                           2.0 * gr[2][2],
+                           2.0 * (0.5 * (gr[0][1] + gr[1][0])),
+                           2.0 * (0.5 * (gr[0][2] + gr[2][0])),
+                           2.0 * (0.5 * (gr[1][2] + gr[2][1]))};
+      a = hrr_mix(a, Sc, sig, tau_c, rc);
     }
+    N::eval(N::coef(rc, rc, uc, om_c, a), f);
   }
-  N::collide(f, MODEL, om_c, tau_c, sig, &Sc);
   int cx, cy, cz;
   cdecode(g, itf.tnc[t3], cx, cy, cz);
   const int64_t ci = cpos(g, cx, cy, cz);
 #pragma unroll
   for (int i = 0; i < Q; ++i) dst_c[(int64_t)i * g.Ncp + ci] = store_pop<S, DEV, LAT>(f[i], i);
+}
+
+template <int LAT, bool DEV, typename S, int MODEL>
+__global__ __launch_bounds__(256) void k_coalesce(const S* __restrict__ src_f, S* __restrict__ dst_c, const Geo g,
+                                                  const Iface itf, double kc, double om_c, double tau_c, double sig) {
+  coalesce_body<LAT, DEV, S, MODEL>(src_f, dst_c, g, itf, kc, om_c, tau_c, sig, (int64_t)blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -623,11 +747,11 @@ __global__ void k_set_state(const double* __restrict__ rho, const double* __rest
 
 // History at t = 0 from coarse fields rho, u (logical coarse arrays): all
 // three levels get rho, u, f1 = 0 and S = centred differences of u.
-template <int LAT>
+template <int LAT, int MODEL>
 __global__ void k_hist_init(const double* __restrict__ rho, const double* __restrict__ u, double* __restrict__ H0,
                             double* __restrict__ H1, double* __restrict__ H2, const Geo g, const Iface itf) {
   using L = Lattice<LAT>;
-  using F = HF<LAT>;
+  using F = HF<LAT, MODEL>;
   const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (h >= itf.NH) return;
   const int64_t ci = itf.hnode[h];
@@ -635,10 +759,10 @@ __global__ void k_hist_init(const double* __restrict__ rho, const double* __rest
   cdecode(g, ci, x, y, z);
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const int64_t NN = g.Nc;
-  double v[F::N];
+  double v[HF<LAT, M_HRR>::N + L::Q];
   v[F::RHO] = rho[ci];
   for (int d = 0; d < L::D; ++d) v[F::U + d] = u[d * NN + ci];
-  for (int i = 0; i < L::Q; ++i) v[F::F1 + i] = 0.0;
+  for (int i = 0; i < F::NF1; ++i) v[F::F1 + i] = 0.0;
   double gr[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   for (int a = 0; a < L::D; ++a) {
     int cp[3] = {x, y, z}, cm[3] = {x, y, z};
@@ -649,17 +773,10 @@ __global__ void k_hist_init(const double* __restrict__ rho, const double* __rest
     const int64_t im = (int64_t)cm[0] + (int64_t)nx * ((int64_t)cm[1] + (int64_t)ny * cm[2]);
     for (int b = 0; b < L::D; ++b) gr[a][b] = 0.5 * (u[b * NN + ip] - u[b * NN + im]);
   }
-  if (L::D == 2) {
-    v[F::S] = gr[0][0];
-    v[F::S + 1] = gr[1][1];
-    v[F::S + 2] = 0.5 * (gr[0][1] + gr[1][0]);
-  } else {
-    v[F::S] = gr[0][0];
-    v[F::S + 1] = gr[1][1];
-    v[F::S + 2] = gr[2][2];
-    v[F::S + 3] = 0.5 * (gr[0][1] + gr[1][0]);
-    v[F::S + 4] = 0.5 * (gr[0][2] + gr[2][0]);
-    v[F::S + 5] = 0.5 * (gr[1][2] + gr[2][1]);
+  if (MODEL == M_HRR) {
+    const Sym<double> S{gr[0][0], gr[1][1], gr[2][2], 0.5 * (gr[0][1] + gr[1][0]), 0.5 * (gr[0][2] + gr[2][0]),
+                        0.5 * (gr[1][2] + gr[2][1])};
+    sym_put<L::D>(S, v + F::S, 1.0);
   }
   const int64_t NH = itf.NH;
   for (int k = 0; k < F::N; ++k) {

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "batch.hpp"
 #include "kernels.hpp"
 #include "lbm.h"
 
@@ -186,8 +187,9 @@ struct Grid final : GridBase {
   using L = Lattice<LAT>;
   static constexpr bool DEV = PREC == LBM_FP32_DEV;
   using S = typename std::conditional<DEV, float, double>::type;  // stored and bulk compute type
-  using F = HF<LAT>;
   static constexpr int Q = L::Q, D = L::D;
+  // history fields per node: the largest layout over the collision models
+  static constexpr int HN = HF<LAT, M_BGK>::N > HF<LAT, M_HRR>::N ? HF<LAT, M_BGK>::N : HF<LAT, M_HRR>::N;
   static constexpr bool NT = true;  // non-temporal stores of the streamed planes
   // Bulk-kernel variants (nodes per lane V, lanes along x LX; work groups are
   // LX x 256/LX).  FP32: 16-byte (V = 4) or 8-byte (V = 2) accesses; FP64:
@@ -224,8 +226,8 @@ struct Grid final : GridBase {
     for (int r = 0; r < 4; ++r) var[r] = default_variant(r & 1);
     if (g.has_fine) {
       const size_t NH = tabs.hnode.size();
-      for (int s = 0; s < 3; ++s) hist[s].alloc(sizeof(double) * F::N * NH);
-      G.alloc(sizeof(double) * F::N * NH);
+      for (int s = 0; s < 3; ++s) hist[s].alloc(sizeof(double) * HN * NH);
+      G.alloc(sizeof(double) * HN * NH);
       auto up = [&](DevBuf& b, const void* src, size_t bytes) {
         b.alloc(bytes);
         if (bytes) HIPCHK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
@@ -433,6 +435,7 @@ struct Grid final : GridBase {
   // A holds the state at integer times, B at half times.
   template <int MODEL>
   void step_two_level(hipStream_t s) {
+    using F = HF<LAT, MODEL>;
     S* csrc = cbuf[cpar].as<S>();
     S* cdst = cbuf[cpar ^ 1].as<S>();
     S* fA = fineA();
@@ -448,7 +451,7 @@ struct Grid final : GridBase {
     constexpr int PER = 256 / (D == 2 ? 9 : 27);
     const unsigned bh = blocks(NH, IB), br = blocks(itf.NR, IB), bt = blocks(itf.NT, IB), bg = blocks(NH * F::N, 256);
     const unsigned bc = blocks(itf.NT, PER);
-    hipLaunchKernelGGL((k_hist_capture<LAT, DEV, S>), dim3(bh), dim3(IB), 0, s, csrc, Hp, g, itf);
+    hipLaunchKernelGGL((k_hist_capture<LAT, DEV, S, MODEL>), dim3(bh), dim3(IB), 0, s, csrc, Hp, g, itf);
     if (MODEL != M_HRR) {
       launch_stream<MODEL, 0>(csrc, cdst, nullptr, tau_c, s);
       fine_stream_timed(MODEL, fA, fB, s);
@@ -509,9 +512,17 @@ struct Grid final : GridBase {
     hs[0] = 0;
     hs[1] = 1;
     hs[2] = 2;
-    hipLaunchKernelGGL((k_hist_init<LAT>), dim3(blocks(itf.NH, kIfaceBlock)), dim3(kIfaceBlock), 0, stream,
-                       tmp_rho.as<double>(), tmp_u.as<double>(), hist[0].as<double>(), hist[1].as<double>(),
-                       hist[2].as<double>(), g, itf);
+    const dim3 gb(blocks(itf.NH, kIfaceBlock)), bb(kIfaceBlock);
+    double *h0 = hist[0].as<double>(), *h1 = hist[1].as<double>(), *h2 = hist[2].as<double>();
+    if (desc.collision == LBM_BGK)
+      hipLaunchKernelGGL((k_hist_init<LAT, M_BGK>), gb, bb, 0, stream, tmp_rho.as<double>(), tmp_u.as<double>(), h0,
+                         h1, h2, g, itf);
+    else if (desc.collision == LBM_RR)
+      hipLaunchKernelGGL((k_hist_init<LAT, M_RR>), gb, bb, 0, stream, tmp_rho.as<double>(), tmp_u.as<double>(), h0,
+                         h1, h2, g, itf);
+    else
+      hipLaunchKernelGGL((k_hist_init<LAT, M_HRR>), gb, bb, 0, stream, tmp_rho.as<double>(), tmp_u.as<double>(), h0,
+                         h1, h2, g, itf);
   }
 
   void set_state(int level, const double* rho, const double* u, bool dev) override {
@@ -651,6 +662,563 @@ static Geo validate(const lbm_grid_desc& d) {
   g.pf = g.has_fine ? pitch_of(g.nf[0] + g.fxo) : 0;
   g.Nfp = g.has_fine ? (int64_t)g.pf * g.nf[1] * g.nf[2] : 0;
   return g;
+}
+
+
+// ---------------------------------------------------------------------------
+// Batch of independent grids (same lattice, collision model and precision),
+// advanced together by persistent launches; one coarse step is captured as a
+// hipGraph and replayed.
+struct BatchBase {
+  int lattice = 0, collision = 0, precision = 0, device = 0, capacity = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  virtual ~BatchBase() {
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+  virtual int add(const lbm_grid_desc& d) = 0;
+  virtual void remove(int slot) = 0;
+  virtual void set_state(int slot, int level, const double* rho, const double* u, bool dev) = 0;
+  virtual void get_macros(int slot, int level, double* rho, double* u, bool dev) = 0;
+  virtual void get_pops(int slot, int level, double* f, bool dev) = 0;
+  virtual void step(int n, hipStream_t s) = 0;
+  virtual void tune(int reps, int32_t* out) = 0;
+  virtual void set_graph(bool on) = 0;
+  virtual void info(int64_t* out) = 0;
+  virtual int64_t slot_steps(int slot) = 0;
+};
+
+// Device bytes one grid of this descriptor needs (populations, macro planes,
+// history, interface tables), without any scratch.
+static int64_t grid_footprint(const lbm_grid_desc& d, const Geo& g) {
+  const int Q = d.lattice == LBM_D2Q9 ? 9 : 19;
+  const int D = g.D;
+  const int64_t sb = d.precision == LBM_FP32_DEV ? 4 : 8;
+  int64_t bytes = 2 * sb * (Q * g.Ncp + 64) + (g.has_fine ? 2 * sb * (Q * g.Nfp + 64) : 0);
+  if (d.collision == LBM_HRR) bytes += sb * (1 + D) * (g.Ncp + g.Nfp + 128);
+  if (g.has_fine) {
+    int64_t nh = 0, ring_out = 1, ring_in = 1, tn_out = 1, tn_in = 1;
+    for (int a = 0; a < D; ++a) {
+      int64_t face = 2;
+      for (int b = 0; b < D; ++b)
+        if (b != a) face *= (g.m[b] + 3);
+      nh += face;
+      ring_out *= 2 * g.m[a] + 1;
+      ring_in *= 2 * g.m[a] - 1;
+      tn_out *= g.m[a] - 1;
+      tn_in *= g.m[a] - 3;
+    }
+    const int64_t nr = ring_out - ring_in, nt = tn_out - tn_in;
+    const int64_t hn = 1 + D + Q + (D == 2 ? 3 : 6);
+    bytes += 4 * 8 * hn * nh + nh * 8 + nr * (8 + 4 + 64) + nt * 16;
+  }
+  return bytes;
+}
+
+template <int LAT, int PREC>
+struct Batch final : BatchBase {
+  using L = Lattice<LAT>;
+  static constexpr bool DEV = PREC == LBM_FP32_DEV;
+  using S = typename std::conditional<DEV, float, double>::type;
+  static constexpr int Q = L::Q, D = L::D;
+  static constexpr bool NT = true;
+  static constexpr int NVAR = Grid<LAT, PREC>::NVAR;
+  static constexpr int HN = Grid<LAT, PREC>::HN;
+  static constexpr int BULK_GRID = kXCD * 512;  // work groups of the persistent launches
+  static constexpr int IF_GRID = kXCD * 512;
+  static constexpr int TN_GRID = kXCD * 256;
+
+  struct Inst {
+    lbm_grid_desc desc{};
+    Geo g{};
+    HostTables tabs;
+    DevBuf cbuf[2], fbuf[2], mac_c, mac_f, hist[3], G, d_hnode, d_rnode, d_rnp, d_rpt, d_tnf, d_tnc;
+    Iface itf{};
+  };
+  std::vector<std::unique_ptr<Inst>> slots;
+  std::vector<InstDev> hinst;
+  std::vector<int64_t> steps_done;
+  DevBuf d_inst, d_counts, d_items[W_KINDS];
+  size_t item_cap[W_KINDS] = {0, 0, 0, 0, 0, 0, 0};
+  int counts[W_KINDS] = {0, 0, 0, 0, 0, 0, 0};
+  DevBuf tmp_rho, tmp_u, tmp_f;
+  int var_c = 0, var_f = 0;
+  bool use_graph = true, graph_ok = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+
+  ~Batch() override { drop_graph(); }
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    graph_ok = false;
+  }
+
+  void init(int cap) {
+    capacity = cap;
+    slots.resize((size_t)cap);
+    hinst.assign((size_t)cap, InstDev{});
+    steps_done.assign((size_t)cap, 0);
+    d_inst.alloc(sizeof(InstDev) * (size_t)cap);
+    HIPCHK(hipMemset(d_inst.p, 0, d_inst.bytes));
+    d_counts.alloc(sizeof(int) * W_KINDS);
+    HIPCHK(hipMemset(d_counts.p, 0, d_counts.bytes));
+    for (int k = 0; k < W_KINDS; ++k) grow_items(k, 1024);
+  }
+
+  void grow_items(int k, size_t n) {
+    if (n <= item_cap[k]) return;
+    size_t cap = std::max(n, 2 * item_cap[k]);
+    if (d_items[k].p) HIPCHK(hipFree(d_items[k].p));
+    d_items[k].p = nullptr;
+    d_items[k].alloc(sizeof(Work) * cap);
+    item_cap[k] = cap;
+    drop_graph();  // the graph holds the old list addresses
+  }
+
+  Tiling tiling(const Geo& g, int level, int v) const {
+    const int V = Grid<LAT, PREC>::kV[v], LX = Grid<LAT, PREC>::kLX[v];
+    if (level == 0) return make_tiling(g.n[0], g.n[1], g.n[2], 0, V, LX, 256 / LX);
+    return make_tiling(g.nf[0], g.nf[1], g.nf[2], 1, V, LX, 256 / LX);
+  }
+
+  void upload_inst(int slot) {
+    HIPCHK(hipMemcpy(d_inst.template as<InstDev>() + slot, &hinst[(size_t)slot], sizeof(InstDev), hipMemcpyHostToDevice));
+  }
+  void fetch_inst(int slot) {
+    HIPCHK(hipMemcpy(&hinst[(size_t)slot], d_inst.template as<InstDev>() + slot, sizeof(InstDev), hipMemcpyDeviceToHost));
+  }
+
+  // Work lists of every phase from the active instances.
+  void rebuild_lists() {
+    std::vector<Work> lists[W_KINDS];
+    constexpr int PER = 256 / (D == 2 ? 9 : 27);
+    const int hfields = collision == LBM_BGK ? HF<LAT, M_BGK>::N : (collision == LBM_RR ? HF<LAT, M_RR>::N
+                                                                                         : HF<LAT, M_HRR>::N);
+    for (int sl = 0; sl < capacity; ++sl) {
+      if (!slots[(size_t)sl]) continue;
+      const InstDev& I = hinst[(size_t)sl];
+      for (int t = 0; t < I.tc.ntiles; ++t) lists[W_COARSE].push_back({sl, t});
+      if (!I.g.has_fine) continue;
+      for (int t = 0; t < I.tf.ntiles; ++t) lists[W_FINE].push_back({sl, t});
+      const int64_t nh = I.itf.NH, nr = I.itf.NR, nt = I.itf.NT;
+      for (int64_t c = 0; c < (nh + 63) / 64; ++c) lists[W_HIST].push_back({sl, (int)c});
+      for (int64_t c = 0; c < (nh * hfields + 63) / 64; ++c) lists[W_HTIME].push_back({sl, (int)c});
+      for (int64_t c = 0; c < (nr + 63) / 64; ++c) lists[W_RING].push_back({sl, (int)c});
+      for (int64_t c = 0; c < (nt + 63) / 64; ++c) lists[W_TN].push_back({sl, (int)c});
+      for (int64_t c = 0; c < (nt + PER - 1) / PER; ++c) lists[W_TNB].push_back({sl, (int)c});
+    }
+    for (int k = 0; k < W_KINDS; ++k) {
+      grow_items(k, lists[k].size());
+      counts[k] = (int)lists[k].size();
+      if (!lists[k].empty())
+        HIPCHK(hipMemcpy(d_items[k].p, lists[k].data(), sizeof(Work) * lists[k].size(), hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMemcpy(d_counts.p, counts, sizeof(counts), hipMemcpyHostToDevice));
+  }
+
+  int add(const lbm_grid_desc& d) override {
+    if (d.lattice != lattice || d.collision != collision || d.precision != precision)
+      throw LbmError(LBM_EINVAL, "descriptor does not match the batch's lattice, collision and precision");
+    int sl = -1;
+    for (int k = 0; k < capacity; ++k)
+      if (!slots[(size_t)k]) {
+        sl = k;
+        break;
+      }
+    if (sl < 0) throw LbmError(LBM_ENOMEM, "batch is full");
+    Geo g = validate(d);
+    auto in = std::make_unique<Inst>();
+    in->desc = d;
+    in->g = g;
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipDeviceSynchronize());
+    build_tables(g, in->tabs);
+    const size_t sb = sizeof(S);
+    for (int p = 0; p < 2; ++p) {
+      in->cbuf[p].alloc(sb * ((size_t)g.Ncp * Q + 64));
+      HIPCHK(hipMemset(in->cbuf[p].p, 0, in->cbuf[p].bytes));
+    }
+    if (collision == LBM_HRR) {
+      in->mac_c.alloc(sb * ((size_t)g.Ncp * (1 + D) + 64));
+      HIPCHK(hipMemset(in->mac_c.p, 0, in->mac_c.bytes));
+    }
+    if (g.has_fine) {
+      for (int p = 0; p < 2; ++p) {
+        in->fbuf[p].alloc(sb * ((size_t)g.Nfp * Q + 64));
+        HIPCHK(hipMemset(in->fbuf[p].p, 0, in->fbuf[p].bytes));
+      }
+      if (collision == LBM_HRR) {
+        in->mac_f.alloc(sb * ((size_t)g.Nfp * (1 + D) + 64));
+        HIPCHK(hipMemset(in->mac_f.p, 0, in->mac_f.bytes));
+      }
+      const size_t NH = in->tabs.hnode.size();
+      for (int k = 0; k < 3; ++k) in->hist[k].alloc(sizeof(double) * HN * NH);
+      in->G.alloc(sizeof(double) * HN * NH);
+      auto up = [&](DevBuf& b, const void* src, size_t bytes) {
+        b.alloc(bytes);
+        if (bytes) HIPCHK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+      };
+      const HostTables& t = in->tabs;
+      up(in->d_hnode, t.hnode.data(), sizeof(int64_t) * t.hnode.size());
+      up(in->d_rnode, t.rnode.data(), sizeof(int64_t) * t.rnode.size());
+      up(in->d_rnp, t.rnp.data(), sizeof(int32_t) * t.rnp.size());
+      up(in->d_rpt, t.rpt.data(), sizeof(int32_t) * t.rpt.size());
+      up(in->d_tnf, t.tnf.data(), sizeof(int64_t) * t.tnf.size());
+      up(in->d_tnc, t.tnc.data(), sizeof(int64_t) * t.tnc.size());
+      in->itf = Iface{(int64_t)t.hnode.size(), in->d_hnode.template as<int64_t>(), (int64_t)t.rnode.size(),
+                      in->d_rnode.template as<int64_t>(), in->d_rnp.template as<int32_t>(), in->d_rpt.template as<int32_t>(),
+                      (int64_t)t.tnf.size(), in->d_tnf.template as<int64_t>(), in->d_tnc.template as<int64_t>()};
+    }
+    const int64_t Nmax = std::max(g.Nc, g.Nf);
+    if (tmp_rho.bytes < sizeof(double) * (size_t)Nmax) {
+      if (tmp_rho.p) HIPCHK(hipFree(tmp_rho.p));
+      if (tmp_u.p) HIPCHK(hipFree(tmp_u.p));
+      tmp_rho.p = tmp_u.p = nullptr;
+      tmp_rho.alloc(sizeof(double) * (size_t)Nmax);
+      tmp_u.alloc(sizeof(double) * D * (size_t)Nmax);
+    }
+    InstDev I{};
+    I.g = g;
+    I.itf = in->itf;
+    I.tc = tiling(g, 0, var_c);
+    if (g.has_fine) I.tf = tiling(g, 1, var_f);
+    I.cbuf[0] = in->cbuf[0].p;
+    I.cbuf[1] = in->cbuf[1].p;
+    I.fbuf[0] = in->fbuf[0].p;
+    I.fbuf[1] = in->fbuf[1].p;
+    I.mac_c = in->mac_c.p;
+    I.mac_f = in->mac_f.p;
+    for (int k = 0; k < 3; ++k) I.hist[k] = in->hist[k].template as<double>();
+    I.G = in->G.template as<double>();
+    I.tau_c = d.tau_coarse;
+    I.tau_f = 2.0 * d.tau_coarse - 0.5;
+    I.sig = d.sigma;
+    I.cpar = 0;
+    I.hs[0] = 0;
+    I.hs[1] = 1;
+    I.hs[2] = 2;
+    I.active = 1;
+    slots[(size_t)sl] = std::move(in);
+    hinst[(size_t)sl] = I;
+    steps_done[(size_t)sl] = 0;
+    upload_inst(sl);
+    rebuild_lists();
+    return sl;
+  }
+
+  Inst& slot_ref(int sl) {
+    if (sl < 0 || sl >= capacity || !slots[(size_t)sl]) throw LbmError(LBM_EINVAL, "no grid in this slot");
+    return *slots[(size_t)sl];
+  }
+
+  void remove(int sl) override {
+    slot_ref(sl);
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipDeviceSynchronize());
+    hinst[(size_t)sl] = InstDev{};
+    upload_inst(sl);
+    slots[(size_t)sl].reset();
+    rebuild_lists();
+  }
+
+  void set_state(int sl, int level, const double* rho, const double* u, bool dev) override {
+    Inst& in = slot_ref(sl);
+    if (level == 1 && !in.g.has_fine) throw LbmError(LBM_EINVAL, "no fine level");
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipDeviceSynchronize());
+    fetch_inst(sl);
+    InstDev& I = hinst[(size_t)sl];
+    const int64_t N = level == 0 ? in.g.Nc : in.g.Nf;
+    const hipMemcpyKind k = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    HIPCHK(hipMemcpy(tmp_rho.p, rho, sizeof(double) * N, k));
+    HIPCHK(hipMemcpy(tmp_u.p, u, sizeof(double) * N * D, k));
+    S* dst = (S*)(level == 0 ? I.cbuf[I.cpar] : I.fbuf[0]);
+    hipLaunchKernelGGL((k_set_state<LAT, DEV, S>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream,
+                       tmp_rho.template as<double>(), tmp_u.template as<double>(), dst, in.g, level);
+    if (level == 0 && in.g.has_fine) {
+      I.hs[0] = 0;
+      I.hs[1] = 1;
+      I.hs[2] = 2;
+      const dim3 gb((unsigned)((in.itf.NH + 63) / 64)), bb(64);
+      if (collision == LBM_BGK)
+        hipLaunchKernelGGL((k_hist_init<LAT, M_BGK>), gb, bb, 0, stream, tmp_rho.template as<double>(), tmp_u.template as<double>(),
+                           I.hist[0], I.hist[1], I.hist[2], in.g, in.itf);
+      else if (collision == LBM_RR)
+        hipLaunchKernelGGL((k_hist_init<LAT, M_RR>), gb, bb, 0, stream, tmp_rho.template as<double>(), tmp_u.template as<double>(),
+                           I.hist[0], I.hist[1], I.hist[2], in.g, in.itf);
+      else
+        hipLaunchKernelGGL((k_hist_init<LAT, M_HRR>), gb, bb, 0, stream, tmp_rho.template as<double>(), tmp_u.template as<double>(),
+                           I.hist[0], I.hist[1], I.hist[2], in.g, in.itf);
+      upload_inst(sl);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream));
+    if (level == 0) steps_done[(size_t)sl] = 0;
+  }
+
+  void get_macros(int sl, int level, double* rho, double* u, bool dev) override {
+    Inst& in = slot_ref(sl);
+    if (level == 1 && !in.g.has_fine) throw LbmError(LBM_EINVAL, "no fine level");
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipDeviceSynchronize());
+    fetch_inst(sl);
+    const InstDev& I = hinst[(size_t)sl];
+    const int64_t N = level == 0 ? in.g.Nc : in.g.Nf;
+    const S* src = (const S*)(level == 0 ? I.cbuf[I.cpar] : I.fbuf[0]);
+    hipLaunchKernelGGL((k_macros<LAT, DEV, S>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream, src,
+                       (const S*)I.fbuf[0], tmp_rho.template as<double>(), tmp_u.template as<double>(), in.g, level);
+    HIPCHK(hipGetLastError());
+    const hipMemcpyKind k = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIPCHK(hipMemcpyAsync(rho, tmp_rho.p, sizeof(double) * N, k, stream));
+    HIPCHK(hipMemcpyAsync(u, tmp_u.p, sizeof(double) * N * D, k, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+  }
+
+  void get_pops(int sl, int level, double* f, bool dev) override {
+    Inst& in = slot_ref(sl);
+    if (level == 1 && !in.g.has_fine) throw LbmError(LBM_EINVAL, "no fine level");
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipDeviceSynchronize());
+    fetch_inst(sl);
+    const InstDev& I = hinst[(size_t)sl];
+    const int64_t N = level == 0 ? in.g.Nc : in.g.Nf;
+    if (tmp_f.bytes < sizeof(double) * Q * (size_t)N) {
+      if (tmp_f.p) HIPCHK(hipFree(tmp_f.p));
+      tmp_f.p = nullptr;
+      tmp_f.alloc(sizeof(double) * Q * (size_t)N);
+    }
+    const S* src = (const S*)(level == 0 ? I.cbuf[I.cpar] : I.fbuf[0]);
+    hipLaunchKernelGGL((k_pops_out<LAT, DEV, S>), dim3((unsigned)((Q * N + 255) / 256)), dim3(256), 0, stream, src,
+                       tmp_f.template as<double>(), in.g, level);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(f, tmp_f.p, sizeof(double) * Q * N, dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                          stream));
+    HIPCHK(hipStreamSynchronize(stream));
+  }
+
+  // ---- phase launches ----
+  const InstDev* di() const { return d_inst.template as<InstDev>(); }
+  const Work* items(int k) const { return d_items[k].template as<Work>(); }
+  const int* cnt(int k) const { return d_counts.template as<int>() + k; }
+
+  template <int MODEL, int LEVEL, int SUB, int V, int LX>
+  void go_stream(hipStream_t s) {
+    hipLaunchKernelGGL((kb_stream<LAT, DEV, S, MODEL, LEVEL, SUB, V, LX, NT>), dim3(BULK_GRID), dim3(256), 0, s, di(),
+                       items(LEVEL == 0 ? W_COARSE : W_FINE), cnt(LEVEL == 0 ? W_COARSE : W_FINE));
+  }
+  template <int MODEL, int LEVEL, int SUB>
+  void phase_stream(hipStream_t s, int v) {
+    if constexpr (DEV) {
+      switch (v) {
+        case 0: go_stream<MODEL, LEVEL, SUB, 4, 64>(s); break;
+        case 1: go_stream<MODEL, LEVEL, SUB, 4, 32>(s); break;
+        case 2: go_stream<MODEL, LEVEL, SUB, 4, 16>(s); break;
+        case 3: go_stream<MODEL, LEVEL, SUB, 2, 64>(s); break;
+        default: go_stream<MODEL, LEVEL, SUB, 2, 32>(s); break;
+      }
+    } else {
+      switch (v) {
+        case 0: go_stream<MODEL, LEVEL, SUB, 2, 64>(s); break;
+        case 1: go_stream<MODEL, LEVEL, SUB, 2, 32>(s); break;
+        default: go_stream<MODEL, LEVEL, SUB, 2, 16>(s); break;
+      }
+    }
+  }
+  template <int LEVEL, int SUB, int V, int LX>
+  void go_collide(hipStream_t s) {
+    hipLaunchKernelGGL((kb_collide<LAT, DEV, S, LEVEL, SUB, V, LX, NT>), dim3(BULK_GRID), dim3(256), 0, s, di(),
+                       items(LEVEL == 0 ? W_COARSE : W_FINE), cnt(LEVEL == 0 ? W_COARSE : W_FINE));
+  }
+  template <int LEVEL, int SUB>
+  void phase_collide(hipStream_t s, int v) {
+    if constexpr (DEV) {
+      switch (v) {
+        case 0: go_collide<LEVEL, SUB, 4, 64>(s); break;
+        case 1: go_collide<LEVEL, SUB, 4, 32>(s); break;
+        case 2: go_collide<LEVEL, SUB, 4, 16>(s); break;
+        case 3: go_collide<LEVEL, SUB, 2, 64>(s); break;
+        default: go_collide<LEVEL, SUB, 2, 32>(s); break;
+      }
+    } else {
+      switch (v) {
+        case 0: go_collide<LEVEL, SUB, 2, 64>(s); break;
+        case 1: go_collide<LEVEL, SUB, 2, 32>(s); break;
+        default: go_collide<LEVEL, SUB, 2, 16>(s); break;
+      }
+    }
+  }
+
+  template <int MODEL>
+  void launch_step_model(hipStream_t s) {
+    using F = HF<LAT, MODEL>;
+    const dim3 ig(IF_GRID), ib(64);
+    hipLaunchKernelGGL((kb_hist_capture<LAT, DEV, S, MODEL>), ig, ib, 0, s, di(), items(W_HIST), cnt(W_HIST));
+    if (MODEL != M_HRR) {
+      phase_stream<MODEL, 0, 0>(s, var_c);
+      phase_stream<MODEL, 1, 0>(s, var_f);
+      hipLaunchKernelGGL((kb_hist_time<F::N>), ig, ib, 0, s, di(), items(W_HTIME), cnt(W_HTIME));
+      hipLaunchKernelGGL((kb_ring<LAT, DEV, S, MODEL, 0>), ig, ib, 0, s, di(), items(W_RING), cnt(W_RING));
+      phase_stream<MODEL, 1, 1>(s, var_f);
+      hipLaunchKernelGGL((kb_ring<LAT, DEV, S, MODEL, 1>), ig, ib, 0, s, di(), items(W_RING), cnt(W_RING));
+      hipLaunchKernelGGL((kb_coalesce<LAT, DEV, S, MODEL>), dim3(TN_GRID), dim3(256), 0, s, di(), items(W_TNB),
+                         cnt(W_TNB));
+    } else {
+      phase_stream<M_HRR, 0, 0>(s, var_c);
+      phase_stream<M_HRR, 1, 0>(s, var_f);
+      hipLaunchKernelGGL((kb_ring_macro<LAT, S, 0>), ig, ib, 0, s, di(), items(W_RING), cnt(W_RING));
+      phase_collide<1, 0>(s, var_f);
+      hipLaunchKernelGGL((kb_fict<LAT, DEV, S>), ig, ib, 0, s, di(), items(W_TN), cnt(W_TN));
+      hipLaunchKernelGGL((kb_hist_strain<LAT, S>), ig, ib, 0, s, di(), items(W_HIST), cnt(W_HIST));
+      hipLaunchKernelGGL((kb_hist_time<F::N>), ig, ib, 0, s, di(), items(W_HTIME), cnt(W_HTIME));
+      hipLaunchKernelGGL((kb_ring<LAT, DEV, S, M_HRR, 0>), ig, ib, 0, s, di(), items(W_RING), cnt(W_RING));
+      phase_stream<M_HRR, 1, 1>(s, var_f);
+      hipLaunchKernelGGL((kb_ring_macro<LAT, S, 1>), ig, ib, 0, s, di(), items(W_RING), cnt(W_RING));
+      phase_collide<1, 1>(s, var_f);
+      hipLaunchKernelGGL((kb_ring<LAT, DEV, S, M_HRR, 1>), ig, ib, 0, s, di(), items(W_RING), cnt(W_RING));
+      phase_collide<0, 0>(s, var_c);
+      hipLaunchKernelGGL((kb_coalesce<LAT, DEV, S, M_HRR>), dim3(TN_GRID), dim3(256), 0, s, di(), items(W_TNB),
+                         cnt(W_TNB));
+    }
+    hipLaunchKernelGGL(kb_advance, dim3((unsigned)((capacity + 255) / 256)), dim3(256), 0, s, d_inst.template as<InstDev>(),
+                       capacity);
+  }
+  void launch_step(hipStream_t s) {
+    if (collision == LBM_BGK) launch_step_model<M_BGK>(s);
+    else if (collision == LBM_RR) launch_step_model<M_RR>(s);
+    else launch_step_model<M_HRR>(s);
+  }
+
+  void capture() {
+    drop_graph();
+    HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    launch_step(stream);
+    hipGraph_t gr = nullptr;
+    HIPCHK(hipStreamEndCapture(stream, &gr));
+    graph = gr;
+    HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    graph_ok = true;
+  }
+
+  void step(int n, hipStream_t s) override {
+    HIPCHK(hipSetDevice(device));
+    int64_t active = 0;
+    for (int k = 0; k < capacity; ++k) active += slots[(size_t)k] ? 1 : 0;
+    if (active == 0 || n <= 0) return;
+    if (use_graph && !graph_ok) capture();
+    for (int k = 0; k < n; ++k) {
+      if (use_graph) HIPCHK(hipGraphLaunch(exec, s));
+      else launch_step(s);
+    }
+    HIPCHK(hipGetLastError());
+    for (int k = 0; k < capacity; ++k)
+      if (slots[(size_t)k]) steps_done[(size_t)k] += n;
+  }
+
+  void set_graph(bool on) override {
+    use_graph = on;
+    if (!on) drop_graph();
+  }
+
+  // Autotuner over the bulk variants of the whole batch.  Times the coarse and
+  // fine stream phases (writing only buffers the next step rewrites).
+  void tune(int reps, int32_t* out) override {
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipDeviceSynchronize());
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (int level = 0; level < 2; ++level) {
+      if (counts[level == 0 ? W_COARSE : W_FINE] == 0) continue;
+      float best = -1.f;
+      int bv = 0;
+      for (int v = 0; v < NVAR; ++v) {
+        if (level == 0) var_c = v;
+        else var_f = v;
+        for (int sl = 0; sl < capacity; ++sl)
+          if (slots[(size_t)sl]) {
+            fetch_inst(sl);
+            if (level == 0) hinst[(size_t)sl].tc = tiling(hinst[(size_t)sl].g, 0, v);
+            else if (hinst[(size_t)sl].g.has_fine) hinst[(size_t)sl].tf = tiling(hinst[(size_t)sl].g, 1, v);
+            upload_inst(sl);
+          }
+        rebuild_lists();
+        auto run = [&] {
+          if (collision == LBM_BGK) {
+            if (level == 0) phase_stream<M_BGK, 0, 0>(stream, v);
+            else phase_stream<M_BGK, 1, 0>(stream, v);
+          } else if (collision == LBM_RR) {
+            if (level == 0) phase_stream<M_RR, 0, 0>(stream, v);
+            else phase_stream<M_RR, 1, 0>(stream, v);
+          } else {
+            if (level == 0) phase_stream<M_HRR, 0, 0>(stream, v);
+            else phase_stream<M_HRR, 1, 0>(stream, v);
+          }
+        };
+        run();
+        HIPCHK(hipEventRecord(e0, stream));
+        for (int k = 0; k < reps; ++k) run();
+        HIPCHK(hipEventRecord(e1, stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (best < 0.f || ms < best) {
+          best = ms;
+          bv = v;
+        }
+      }
+      if (level == 0) var_c = bv;
+      else var_f = bv;
+      for (int sl = 0; sl < capacity; ++sl)
+        if (slots[(size_t)sl]) {
+          fetch_inst(sl);
+          if (level == 0) hinst[(size_t)sl].tc = tiling(hinst[(size_t)sl].g, 0, bv);
+          else if (hinst[(size_t)sl].g.has_fine) hinst[(size_t)sl].tf = tiling(hinst[(size_t)sl].g, 1, bv);
+          upload_inst(sl);
+        }
+      rebuild_lists();
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    drop_graph();
+    out[0] = var_c;
+    out[1] = var_f;
+  }
+
+  void info(int64_t* out) override {
+    int64_t active = 0, ups = 0, bytes = 0;
+    for (int k = 0; k < capacity; ++k) {
+      if (!slots[(size_t)k]) continue;
+      const Inst& in = *slots[(size_t)k];
+      active++;
+      int64_t u = in.g.Nc;
+      if (in.g.has_fine) {
+        int64_t cov = 1;
+        for (int d = 0; d < D; ++d) cov *= (in.g.m[d] - 3);
+        u = in.g.Nc - cov + 2 * in.g.Nf;
+      }
+      ups += u;
+      bytes += grid_footprint(in.desc, in.g);
+    }
+    out[0] = active;
+    out[1] = ups;
+    out[2] = bytes;
+  }
+
+  int64_t slot_steps(int sl) override {
+    slot_ref(sl);
+    return steps_done[(size_t)sl];
+  }
+};
+
+static BatchBase* make_batch(int lattice, int precision) {
+  if (lattice == LBM_D2Q9 && precision == LBM_FP64) return new Batch<0, LBM_FP64>();
+  if (lattice == LBM_D2Q9 && precision == LBM_FP32_DEV) return new Batch<0, LBM_FP32_DEV>();
+  if (lattice == LBM_D3Q19 && precision == LBM_FP64) return new Batch<1, LBM_FP64>();
+  if (lattice == LBM_D3Q19 && precision == LBM_FP32_DEV) return new Batch<1, LBM_FP32_DEV>();
+  return nullptr;
 }
 
 }  // namespace lbm
@@ -901,6 +1469,145 @@ int lbm_set_variants(lbm_handle h, const int32_t variants[4]) {
 const char* lbm_last_error(lbm_handle h) {
   if (!h) return g_create_error.c_str();
   return h->impl->err.c_str();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batch ABI.
+struct lbm_batch {
+  std::unique_ptr<BatchBase> impl;
+};
+
+template <typename F>
+static int bguard(lbm_batch_handle b, F&& fn) {
+  try {
+    fn();
+    return LBM_OK;
+  } catch (const LbmError& e) {
+    if (b && b->impl) b->impl->err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (b && b->impl) b->impl->err = "host allocation failed";
+    return LBM_ENOMEM;
+  } catch (...) {
+    if (b && b->impl) b->impl->err = "unexpected exception";
+    return LBM_EDEVICE;
+  }
+}
+
+extern "C" {
+
+int lbm_batch_create(int lattice, int collision, int precision, int device, int capacity, lbm_batch_handle* out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  if ((lattice != LBM_D2Q9 && lattice != LBM_D3Q19) || collision < LBM_BGK || collision > LBM_HRR ||
+      (precision != LBM_FP64 && precision != LBM_FP32_DEV) || capacity < 1 || capacity > (1 << 20)) {
+    g_create_error = "invalid batch parameters";
+    return LBM_EINVAL;
+  }
+  try {
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) throw LbmError(LBM_EINVAL, "no such HIP device");
+    std::unique_ptr<BatchBase> b(make_batch(lattice, precision));
+    b->lattice = lattice;
+    b->collision = collision;
+    b->precision = precision;
+    b->device = device;
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    if (lattice == LBM_D2Q9 && precision == LBM_FP64) static_cast<Batch<0, LBM_FP64>*>(b.get())->init(capacity);
+    if (lattice == LBM_D2Q9 && precision == LBM_FP32_DEV) static_cast<Batch<0, LBM_FP32_DEV>*>(b.get())->init(capacity);
+    if (lattice == LBM_D3Q19 && precision == LBM_FP64) static_cast<Batch<1, LBM_FP64>*>(b.get())->init(capacity);
+    if (lattice == LBM_D3Q19 && precision == LBM_FP32_DEV)
+      static_cast<Batch<1, LBM_FP32_DEV>*>(b.get())->init(capacity);
+    auto* h = new lbm_batch;
+    h->impl = std::move(b);
+    *out = h;
+    return LBM_OK;
+  } catch (const LbmError& e) {
+    g_create_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_create_error = "host allocation failed";
+    return LBM_ENOMEM;
+  }
+}
+
+int lbm_batch_destroy(lbm_batch_handle b) {
+  if (!b) return LBM_EINVAL;
+  (void)hipSetDevice(b->impl->device);
+  (void)hipDeviceSynchronize();
+  delete b;
+  return LBM_OK;
+}
+
+int lbm_batch_add(lbm_batch_handle b, const lbm_grid_desc* d, int32_t* slot) {
+  if (!b || !d || !slot) return LBM_EINVAL;
+  return bguard(b, [&] { *slot = b->impl->add(*d); });
+}
+
+int lbm_batch_remove(lbm_batch_handle b, int slot) {
+  if (!b) return LBM_EINVAL;
+  return bguard(b, [&] { b->impl->remove(slot); });
+}
+
+int lbm_batch_set_state(lbm_batch_handle b, int slot, int level, const double* rho, const double* u, int mem) {
+  if (!b || !rho || !u || level < 0 || level > 1 || (mem != LBM_HOST && mem != LBM_DEVICE)) return LBM_EINVAL;
+  return bguard(b, [&] { b->impl->set_state(slot, level, rho, u, mem == LBM_DEVICE); });
+}
+
+int lbm_batch_get_macros(lbm_batch_handle b, int slot, int level, double* rho, double* u, int mem) {
+  if (!b || !rho || !u || level < 0 || level > 1 || (mem != LBM_HOST && mem != LBM_DEVICE)) return LBM_EINVAL;
+  return bguard(b, [&] { b->impl->get_macros(slot, level, rho, u, mem == LBM_DEVICE); });
+}
+
+int lbm_batch_get_populations(lbm_batch_handle b, int slot, int level, double* f, int mem) {
+  if (!b || !f || level < 0 || level > 1 || (mem != LBM_HOST && mem != LBM_DEVICE)) return LBM_EINVAL;
+  return bguard(b, [&] { b->impl->get_pops(slot, level, f, mem == LBM_DEVICE); });
+}
+
+int lbm_batch_step(lbm_batch_handle b, int n, void* stream) {
+  if (!b || n < 0) return LBM_EINVAL;
+  return bguard(b, [&] { b->impl->step(n, stream ? (hipStream_t)stream : b->impl->stream); });
+}
+
+int lbm_batch_use_graph(lbm_batch_handle b, int on) {
+  if (!b) return LBM_EINVAL;
+  return bguard(b, [&] { b->impl->set_graph(on != 0); });
+}
+
+int lbm_batch_tune(lbm_batch_handle b, int reps, int32_t variants[2]) {
+  if (!b || reps < 1 || !variants) return LBM_EINVAL;
+  return bguard(b, [&] { b->impl->tune(reps, variants); });
+}
+
+int lbm_batch_info(lbm_batch_handle b, int64_t info[3]) {
+  if (!b || !info) return LBM_EINVAL;
+  return bguard(b, [&] { b->impl->info(info); });
+}
+
+int lbm_batch_slot_steps(lbm_batch_handle b, int slot, int64_t* steps) {
+  if (!b || !steps) return LBM_EINVAL;
+  return bguard(b, [&] { *steps = b->impl->slot_steps(slot); });
+}
+
+int lbm_footprint(const lbm_grid_desc* d, int64_t* bytes) {
+  if (!d || !bytes) return LBM_EINVAL;
+  try {
+    const Geo g = validate(*d);
+    *bytes = grid_footprint(*d, g);
+    return LBM_OK;
+  } catch (const LbmError& e) {
+    g_create_error = e.msg;
+    return e.code;
+  }
+}
+
+const char* lbm_batch_last_error(lbm_batch_handle b) {
+  if (!b) return g_create_error.c_str();
+  return b->impl->err.c_str();
 }
 
 }  // extern "C"

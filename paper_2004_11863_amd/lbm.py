@@ -34,7 +34,10 @@ EXPORTS = (
     "lbm_set_populations", "lbm_get_populations", "lbm_get_totals", "lbm_get_index_maps",
     "lbm_level_dims", "lbm_lattice_info", "lbm_interface_counts", "lbm_interface_tables",
     "lbm_updates_per_step", "lbm_profile_enable", "lbm_kernel_time", "lbm_tune", "lbm_set_variants",
-    "lbm_last_error",
+    "lbm_last_error", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove",
+    "lbm_batch_set_state", "lbm_batch_get_macros", "lbm_batch_get_populations", "lbm_batch_step",
+    "lbm_batch_use_graph", "lbm_batch_tune", "lbm_batch_info", "lbm_batch_slot_steps", "lbm_footprint",
+    "lbm_batch_last_error",
 )
 
 
@@ -86,6 +89,22 @@ def load(path: str = LIB_PATH):
     L.lbm_set_variants.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.lbm_last_error.argtypes = [vp]
     L.lbm_last_error.restype = ctypes.c_char_p
+    i32p, i64p = ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)
+    L.lbm_batch_create.argtypes = [ip, ip, ip, ip, ip, ctypes.POINTER(vp)]
+    L.lbm_batch_destroy.argtypes = [vp]
+    L.lbm_batch_add.argtypes = [vp, ctypes.POINTER(lbm_grid_desc), i32p]
+    L.lbm_batch_remove.argtypes = [vp, ip]
+    L.lbm_batch_set_state.argtypes = [vp, ip, ip, vp, vp, ip]
+    L.lbm_batch_get_macros.argtypes = [vp, ip, ip, vp, vp, ip]
+    L.lbm_batch_get_populations.argtypes = [vp, ip, ip, vp, ip]
+    L.lbm_batch_step.argtypes = [vp, ip, vp]
+    L.lbm_batch_use_graph.argtypes = [vp, ip]
+    L.lbm_batch_tune.argtypes = [vp, ip, i32p]
+    L.lbm_batch_info.argtypes = [vp, i64p]
+    L.lbm_batch_slot_steps.argtypes = [vp, ip, i64p]
+    L.lbm_footprint.argtypes = [ctypes.POINTER(lbm_grid_desc), i64p]
+    L.lbm_batch_last_error.argtypes = [vp]
+    L.lbm_batch_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -113,6 +132,27 @@ def lbm_lattice_info(lattice: int):
     _check(load().lbm_lattice_info(lattice, ctypes.byref(D), ctypes.byref(Q), xi, w))
     q = Q.value
     return D.value, q, np.array(xi[: 3 * q], np.int32).reshape(q, 3), np.array(w[:q])
+
+
+def make_desc(lattice, collision, precision, n, lo=None, hi=None, tau_coarse=0.51, sigma=0.995, device=0):
+    d = lbm_grid_desc()
+    d.lattice, d.collision, d.precision = lattice, collision, precision
+    D = 2 if lattice == LBM_D2Q9 else 3
+    nn = list(n) + [1] * (3 - len(n))
+    lo = list(lo if lo is not None else [0] * D) + [0] * (3 - D)
+    hi = list(hi if hi is not None else [0] * D) + [0] * (3 - D)
+    for k in range(3):
+        d.n[k], d.lo[k], d.hi[k] = int(nn[k]), int(lo[k]), int(hi[k])
+    d.tau_coarse, d.sigma, d.device, d.reserved = float(tau_coarse), float(sigma), int(device), 0
+    return d
+
+
+def lbm_footprint(desc):
+    v = ctypes.c_int64()
+    rc = load().lbm_footprint(ctypes.byref(desc), ctypes.byref(v))
+    if rc != LBM_OK:
+        raise LbmError(rc, load().lbm_last_error(None).decode())
+    return v.value
 
 
 def lbm_create_grid(lattice, collision, precision, n, lo=None, hi=None, tau_coarse=0.51, sigma=0.995, device=0):
@@ -292,3 +332,97 @@ class Grid:
 
     def set_variants(self, variants):
         lbm_set_variants(self.h, variants)
+
+
+# ---------------------------------------------------------------------------
+# Batches
+
+
+def _bcheck(rc, b):
+    if rc != LBM_OK:
+        msg = load().lbm_batch_last_error(b)
+        raise LbmError(rc, msg.decode() if msg else "")
+
+
+class Batch:
+    """Many grids of one lattice / collision model / precision, stepped
+    together by persistent launches replayed from a hipGraph."""
+
+    def __init__(self, lattice, collision, precision, capacity, device=0):
+        self.b = ctypes.c_void_p()
+        rc = load().lbm_batch_create(lattice, collision, precision, device, capacity, ctypes.byref(self.b))
+        if rc != LBM_OK:
+            raise LbmError(rc, load().lbm_batch_last_error(None).decode())
+        self.D, self.Q, self.xi, self.w = lbm_lattice_info(lattice)
+        self.lattice, self.collision, self.precision = lattice, collision, precision
+        self.dims = {}
+
+    def close(self):
+        if self.b:
+            load().lbm_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add(self, n, lo=None, hi=None, tau_coarse=0.51, sigma=0.995):
+        d = make_desc(self.lattice, self.collision, self.precision, n, lo, hi, tau_coarse, sigma)
+        slot = ctypes.c_int32()
+        _bcheck(load().lbm_batch_add(self.b, ctypes.byref(d), ctypes.byref(slot)), self.b)
+        D = self.D
+        nc = [int(x) for x in list(n)[:D]]
+        nf = None
+        if lo is not None and any(int(a) != int(b) for a, b in zip(lo, hi)):
+            nf = [2 * (int(h) - int(l)) + 1 for l, h in zip(list(lo)[:D], list(hi)[:D])]
+        self.dims[slot.value] = (nc, nf)
+        return slot.value
+
+    def remove(self, slot):
+        _bcheck(load().lbm_batch_remove(self.b, slot), self.b)
+        self.dims.pop(slot, None)
+
+    def nodes(self, slot, level):
+        nc, nf = self.dims[slot]
+        return int(np.prod(nc if level == 0 else nf))
+
+    def set_state(self, slot, level, rho, u):
+        N = self.nodes(slot, level)
+        rho = np.ascontiguousarray(rho, np.float64).reshape(N)
+        u = np.ascontiguousarray(u, np.float64).reshape(self.D, N)
+        _bcheck(load().lbm_batch_set_state(self.b, slot, level, rho.ctypes.data, u.ctypes.data, LBM_HOST), self.b)
+
+    def get_macros(self, slot, level):
+        N = self.nodes(slot, level)
+        rho = np.zeros(N)
+        u = np.zeros((self.D, N))
+        _bcheck(load().lbm_batch_get_macros(self.b, slot, level, rho.ctypes.data, u.ctypes.data, LBM_HOST), self.b)
+        return rho, u
+
+    def get_populations(self, slot, level):
+        f = np.zeros((self.Q, self.nodes(slot, level)))
+        _bcheck(load().lbm_batch_get_populations(self.b, slot, level, f.ctypes.data, LBM_HOST), self.b)
+        return f
+
+    def step(self, n=1, stream=None):
+        _bcheck(load().lbm_batch_step(self.b, int(n), ctypes.c_void_p(stream) if stream else None), self.b)
+
+    def use_graph(self, on=True):
+        _bcheck(load().lbm_batch_use_graph(self.b, 1 if on else 0), self.b)
+
+    def tune(self, reps=3):
+        v = (ctypes.c_int32 * 2)()
+        _bcheck(load().lbm_batch_tune(self.b, int(reps), v), self.b)
+        return list(v)
+
+    def info(self):
+        v = (ctypes.c_int64 * 3)()
+        _bcheck(load().lbm_batch_info(self.b, v), self.b)
+        return {"grids": v[0], "updates_per_step": v[1], "bytes": v[2]}
+
+    def slot_steps(self, slot):
+        v = ctypes.c_int64()
+        _bcheck(load().lbm_batch_slot_steps(self.b, slot, ctypes.byref(v)), self.b)
+        return v.value

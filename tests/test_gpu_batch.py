@@ -1,0 +1,134 @@
+"""Batched persistent launches: a grid advanced inside a batch (captured
+hipGraph, continuous joining and leaving) computes exactly what it computes
+alone, and FP64 batches match the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2004_11863_amd import inputs as I
+from parity_util import compare_fp64, make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _lbm():
+    from paper_2004_11863_amd import lbm
+    return lbm
+
+
+def _geoms2d():
+    return [I.Geometry(2, (64, 64, 1), (16, 16, 0), (48, 48, 0)),
+            I.Geometry(2, (71, 37, 1), (6, 5, 0), (33, 30, 0)),
+            I.Geometry(2, (40, 24, 1), (0, 0, 0), (0, 0, 0)),
+            I.Geometry(2, (96, 80, 1), (20, 30, 0), (70, 50, 0))]
+
+
+def _wl(geom, k):
+    c = tuple(0.5 * (l + h) + 1.3 * k if l != h else 0.4 * n for l, h, n in zip(geom.lo[:geom.D], geom.hi[:geom.D],
+                                                                                 geom.n[:geom.D]))
+    return I.Workload(geom=geom, U=(0.05, 0.01, 0.0), vortices=[I.Vortex(center=c[:2], eps=0.01, U=(0.05, 0.01, 0.0))],
+                      pulses=[I.Pulse(center=c, A=1e-3, R=3.0)])
+
+
+def _alone(wl, model, prec, steps):
+    gpu, _, levels = make_pair(wl, model, prec, with_oracle=False)
+    gpu.step(steps)
+    out = [gpu.get_populations(lv) for lv in levels]
+    live = gpu.class_map(0) != _lbm().LBM_C_COVERED
+    gpu.close()
+    return out, live
+
+
+def _add(batch, wl):
+    g = wl.geom
+    D = g.D
+    lo = g.lo[:D] if g.has_fine else None
+    hi = g.hi[:D] if g.has_fine else None
+    sl = batch.add(g.n[:D], lo, hi, tau_coarse=0.51)
+    for lv in ((0, 1) if g.has_fine else (0,)):
+        batch.set_state(sl, lv, *I.fields(wl, lv))
+    return sl
+
+
+def _check_same(batch, sl, alone):
+    out, live = alone
+    b0 = batch.get_populations(sl, 0)
+    assert np.array_equal(b0[:, live], out[0][:, live])
+    if len(out) > 1:
+        assert np.array_equal(batch.get_populations(sl, 1), out[1])
+
+
+@pytest.mark.parametrize("model", ["BGK", "RR", "HRR"])
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_equals_alone_fp32(model, graph):
+    lbm = _lbm()
+    mcode = {"BGK": lbm.LBM_BGK, "RR": lbm.LBM_RR, "HRR": lbm.LBM_HRR}[model]
+    batch = lbm.Batch(lbm.LBM_D2Q9, mcode, lbm.LBM_FP32_DEV, capacity=8)
+    batch.use_graph(graph)
+    wls = [_wl(g, k) for k, g in enumerate(_geoms2d())]
+    slots = [_add(batch, w) for w in wls]
+    batch.step(9)
+    for w, sl in zip(wls, slots):
+        assert batch.slot_steps(sl) == 9
+        _check_same(batch, sl, _alone(w, model, lbm.LBM_FP32_DEV, 9))
+    batch.close()
+
+
+def test_continuous_batching_join_and_leave():
+    lbm = _lbm()
+    batch = lbm.Batch(lbm.LBM_D2Q9, lbm.LBM_RR, lbm.LBM_FP32_DEV, capacity=4)
+    g = _geoms2d()
+    wa, wb, wc = _wl(g[0], 0), _wl(g[1], 1), _wl(g[3], 2)
+    a = _add(batch, wa)
+    batch.step(5)
+    b = _add(batch, wb)
+    batch.step(4)
+    batch.remove(a)
+    c = _add(batch, wc)
+    batch.step(6)
+    assert batch.slot_steps(b) == 10 and batch.slot_steps(c) == 6
+    _check_same(batch, b, _alone(wb, "RR", lbm.LBM_FP32_DEV, 10))
+    _check_same(batch, c, _alone(wc, "RR", lbm.LBM_FP32_DEV, 6))
+    info = batch.info()
+    assert info["grids"] == 2
+    batch.close()
+
+
+@pytest.mark.parametrize("model", ["RR", "HRR"])
+def test_batch_d3q19_fp64_matches_oracle(model):
+    lbm = _lbm()
+    mcode = {"RR": lbm.LBM_RR, "HRR": lbm.LBM_HRR}[model]
+    batch = lbm.Batch(lbm.LBM_D3Q19, mcode, lbm.LBM_FP64, capacity=3)
+    geoms = [I.Geometry(3, (22, 20, 24), (5, 4, 6), (15, 14, 17)), I.Geometry(3, (18, 18, 18), (4, 4, 4), (12, 12, 12))]
+    wls = [I.Workload(geom=gm, U=(0.05, 0.01, -0.01), pulses=[I.Pulse(center=(9.0, 8.5, 10.2), A=1e-3, R=2.5)])
+           for gm in geoms]
+    slots = [_add(batch, w) for w in wls]
+    batch.tune(reps=1)
+    batch.step(7)
+    for w, sl in zip(wls, slots):
+        g = w.geom
+        ref = O.Grid(O.D3Q19, {"RR": O.RR, "HRR": O.HRR}[model], g.n[:3], g.lo[:3], g.hi[:3], tau_c=0.51)
+        for lv in (0, 1):
+            ref.set_state(lv, *I.fields(w, lv))
+        ref.step(7)
+        for lv in (0, 1):
+            r1, u1 = batch.get_macros(sl, lv)
+            r0, u0 = ref.get_macros(lv)
+            assert np.abs(r1 - r0).max() <= 1e-12 * np.abs(r0).max()
+            assert np.abs(u1 - u0).max() <= 1e-12 * np.abs(u0).max()
+    batch.close()
+
+
+def test_batch_rejects_mismatched_descriptor_and_overflow():
+    lbm = _lbm()
+    batch = lbm.Batch(lbm.LBM_D2Q9, lbm.LBM_RR, lbm.LBM_FP32_DEV, capacity=1)
+    batch.add((32, 32), (8, 8), (24, 24))
+    with pytest.raises(lbm.LbmError) as e:
+        batch.add((32, 32), (8, 8), (24, 24))
+    assert e.value.code == lbm.LBM_ENOMEM
+    batch.close()
+    batch = lbm.Batch(lbm.LBM_D2Q9, lbm.LBM_RR, lbm.LBM_FP32_DEV, capacity=2)
+    with pytest.raises(lbm.LbmError) as e:
+        batch.add((32, 32), (8, 8), (40, 24))  # patch outside the grid
+    assert e.value.code == lbm.LBM_EINVAL
+    batch.close()
