@@ -45,6 +45,11 @@ def parse():
     p.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-steps", type=int, default=3)
+    p.add_argument("--no-batch", action="store_true", help="skip the batched-instances measurement")
+    p.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    p.add_argument("--batch-n", type=int, default=256)
+    p.add_argument("--batch-steps", type=int, default=200)
+    p.add_argument("--serve-n", type=int, default=16)
     p.add_argument("--copy-probe", type=int, default=0,
                    help="only run a plain device copy of this many MiB (counter calibration)")
     return p.parse_args()
@@ -133,7 +138,115 @@ def cpu_baseline(wl, collision, steps):
     t0 = time.perf_counter()
     ref.step(steps)
     dt = time.perf_counter() - t0
-    return g.updates_per_step() * steps / dt / 1e6, O.threads(), dt
+    return g.updates_per_step() * steps / dt / 1e6, O.threads(), dt, ref
+
+
+def error_vs_oracle(wl, collision, precision, steps, ref):
+    """Density max-abs and velocity relative L2 error of the GPU run against
+    the FP64 oracle after the same number of steps, worst over the levels."""
+    import numpy as np
+    grid = make_gpu(wl, collision, precision)
+    grid.step(steps)
+    err = {"rho_maxabs": 0.0, "u_relL2": 0.0, "steps": steps}
+    for lv in (0, 1):
+        r1, u1 = grid.get_macros(lv)
+        r0, u0 = ref.get_macros(lv)
+        err["rho_maxabs"] = max(err["rho_maxabs"], float(np.abs(r1 - r0).max()))
+        err["u_relL2"] = max(err["u_relL2"], float(np.linalg.norm(u1 - u0) / np.linalg.norm(u0)))
+    grid.close()
+    return err
+
+
+def batched(n_inst, steps):
+    """n_inst independent D2Q9 two-level grids (sides log-uniform in
+    [64, 1024], patch over the central half of each side, FP32, RR), all in
+    one batch: one persistent launch per phase, one hipGraph replay per
+    coarse step, autotuned tiles; against the plain per-instance loop (each
+    grid stepped on its own, one after the other)."""
+    import torch
+    from paper_2004_11863_amd import inputs as I
+    from paper_2004_11863_amd import lbm
+    wls = [I.batch_instance(0, i) for i in range(n_inst)]
+    b = lbm.Batch(lbm.LBM_D2Q9, lbm.LBM_RR, lbm.LBM_FP32_DEV, capacity=n_inst)
+    for w in wls:
+        g = w.geom
+        sl = b.add(g.n[:2], g.lo[:2], g.hi[:2], 0.51)
+        for lv in (0, 1):
+            b.set_state(sl, lv, *I.fields(w, lv))
+    ups = b.info()["updates_per_step"]
+    variants = b.tune(reps=2)
+    b.step(5)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    info = b.info()
+    b.close()
+    # plain per-instance loop on the same grids
+    grids = []
+    for w in wls:
+        g = w.geom
+        gr = lbm.Grid(lbm.LBM_D2Q9, lbm.LBM_RR, lbm.LBM_FP32_DEV, g.n[:2], g.lo[:2], g.hi[:2], 0.51)
+        for lv in (0, 1):
+            gr.set_state(lv, *I.fields(w, lv))
+        grids.append(gr)
+    loop_steps = max(5, steps // 10)
+    for gr in grids:
+        gr.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for gr in grids:
+        gr.step(loop_steps)
+    torch.cuda.synchronize()
+    dl = time.perf_counter() - t0
+    for gr in grids:
+        gr.close()
+    torch.cuda.empty_cache()
+    return {"instances": n_inst, "updates_per_step": ups, "steps": steps, "device_bytes": info["bytes"],
+            "batched_mlups": round(ups * steps / dt / 1e6, 1), "batched_ms_per_step": dt / steps * 1e3,
+            "per_instance_loop_mlups": round(ups * loop_steps / dl / 1e6, 1),
+            "per_instance_loop_steps": loop_steps, "variants": variants,
+            "speedup": round((ups * steps / dt) / (ups * loop_steps / dl), 2)}
+
+
+def serving(n_req, rate=200.0, saturation=48e6):
+    """A seeded Poisson stream (mean 200 requests/s) mixing D2Q9 (sides
+    128-2048) and D3Q19 (sides 64-256) two-level problems with 100-2000 coarse
+    steps, FP32 with 10 % flagged FP64, RR; first n_req arrivals.  Initial
+    fields are sampled before the trace starts (client side).  Continuous
+    batching (shortest work first, device load capped at `saturation` lattice
+    updates per step) against the plain FIFO per-instance loop on the same
+    trace."""
+    import torch
+    from paper_2004_11863_amd import serve
+    reqs = [r.prepare() for r in serve.poisson_trace(n_req, rate=rate, seed=5)]
+    work = sum(r.updates() for r in reqs)
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    ex = serve.DeviceExecutor(capacity=64)
+    t0 = time.perf_counter()
+    done = serve.Server(ex, budget, max_chunk=16, policy="sjf", saturation=saturation).run(reqs, realtime=True)
+    span = time.perf_counter() - t0
+    ex.close()
+    torch.cuda.empty_cache()
+    st = serve.latency_stats(done)
+    reqs2 = [r.prepare() for r in serve.poisson_trace(n_req, rate=rate, seed=5)]
+    t0 = time.perf_counter()
+    done2 = serve.fifo_loop(reqs2, realtime=True)
+    span2 = time.perf_counter() - t0
+    st2 = serve.latency_stats(done2)
+    torch.cuda.empty_cache()
+    offered = work / (reqs[-1].arrival - reqs[0].arrival + 1e-9)
+    return {"requests": n_req, "rate_per_s": rate, "total_updates": work,
+            "policy": "sjf", "saturation_updates_per_step": saturation,
+            "served": {"p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
+                       "aggregate_mlups": round(work / span / 1e6, 1), "makespan_s": round(span, 3),
+                       "fp64_fallbacks": sum(r.fell_back for r in done)},
+            "fifo_per_instance": {"p50_s": round(st2["p50_s"], 3), "p99_s": round(st2["p99_s"], 3),
+                                  "aggregate_mlups": round(work / span2 / 1e6, 1), "makespan_s": round(span2, 3)},
+            "offered_mlups": round(offered / 1e6, 1),
+            "saturated": bool(offered > work / span)}
 
 
 def copy_probe(mib):
@@ -255,11 +368,20 @@ def main():
             print(f"# extra {name}: {extra[name]}", file=sys.stderr, flush=True)
         result["extra"] = extra
 
+    if not args.no_batch:
+        result["batched"] = batched(args.batch_n, args.batch_steps)
+        print(f"# batched: {result['batched']}", file=sys.stderr, flush=True)
+    if not args.no_serve:
+        result["serving"] = serving(args.serve_n)
+        print(f"# serving: {result['serving']}", file=sys.stderr, flush=True)
+
     if not args.no_cpu:
-        v, cores, t = cpu_baseline(wl, args.collision, args.cpu_steps)
+        v, cores, t, ref = cpu_baseline(wl, args.collision, args.cpu_steps)
         result["cpu_baseline"] = {"value": round(v, 2), "unit": "MLUPS", "cores": cores, "kind": "oracle",
                                   "sample": "%d coarse steps of the same grid and input in FP64 (%.1f s)"
                                             % (args.cpu_steps, t)}
+        result["error_vs_oracle"] = error_vs_oracle(wl, args.collision, args.precision, args.cpu_steps, ref)
+        del ref
     print(json.dumps(result), flush=True)
 
 

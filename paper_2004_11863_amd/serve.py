@@ -1,0 +1,308 @@
+"""Continuous-batching request loop for two-level LBM simulations.
+
+Requests (a grid description, an initial state and a number of coarse steps)
+arrive over time.  The server admits a waiting request as soon as a batch slot
+and enough device memory (by footprint) are free, keeps its populations
+resident on the device, and advances every admitted request together: one
+coarse step of a batch is one replay of its captured launch sequence, and the
+batches of different lattices / precisions run on their own streams, so their
+work overlaps on the device.  A request leaves when it has taken its steps;
+its macroscopic fields are read back and its slot and memory freed.  FP32
+requests whose result is not finite are run again in FP64 (fallback).
+
+Everything device-side goes through an executor; ``DeviceExecutor`` drives
+the C-ABI batches of the HIP library.  The scheduling logic itself is plain
+host code and is tested on the CPU with a fake executor.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import inputs as I
+
+
+@dataclass
+class Request:
+    rid: int
+    workload: I.Workload
+    steps: int
+    arrival: float          # seconds from trace start
+    fp64: bool = False      # run in FP64 from the start
+    collision: str = "RR"
+    tau_coarse: float = 0.51
+    sigma: float = 0.995
+    payload: dict = None    # level -> (rho, u) initial fields, prepared by the client
+    # filled by the server
+    admitted: float = math.nan
+    finished: float = math.nan
+    result: dict = field(default_factory=dict)
+    fell_back: bool = False
+
+    @property
+    def lattice(self) -> int:
+        return 0 if self.workload.geom.D == 2 else 1
+
+    def key(self, fp64=None):
+        return (self.lattice, self.collision, "fp64" if (self.fp64 if fp64 is None else fp64) else "fp32")
+
+    def updates(self) -> int:
+        return self.workload.geom.updates_per_step() * self.steps
+
+    def prepare(self):
+        """Samples the initial fields (client side, before submission)."""
+        self.payload = {lv: I.fields(self.workload, lv) for lv in (0, 1)}
+        return self
+
+    def fields(self, level):
+        return self.payload[level] if self.payload is not None else I.fields(self.workload, level)
+
+
+def poisson_trace(n: int, rate: float, seed: int = 0, mix_3d: float = 0.5, d2_side=(128, 2048), d3_side=(64, 256),
+                  steps=(100, 2000), fp64_frac: float = 0.1, collision: str = "RR"):
+    """Seeded request stream: Poisson arrivals at `rate` per second; half
+    D2Q9 (side log-uniform in d2_side) and half D3Q19 (side log-uniform in
+    d3_side); fine patch over the central half of each side; steps uniform in
+    `steps`; a fraction flagged FP64; a convected vortex (2D) or an acoustic
+    pulse (3D) as initial state."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    t = 0.0
+    out = []
+    U = 0.1 * I.CS
+    for k in range(n):
+        t += rng.exponential(1.0 / rate)
+        three = rng.uniform() < mix_3d
+        lo_s, hi_s = d3_side if three else d2_side
+        N = int(4 * round(math.exp(rng.uniform(math.log(lo_s), math.log(hi_s))) / 4))
+        a, b = N // 4, 3 * N // 4
+        if three:
+            geom = I.Geometry(3, (N, N, N), (a, a, a), (b, b, b))
+            c = tuple(float(x) for x in rng.uniform(a, b, 3))
+            wl = I.Workload(geom=geom, U=(U, 0.0, 0.0), pulses=[I.Pulse(center=c, A=1e-3)])
+        else:
+            geom = I.Geometry(2, (N, N, 1), (a, a, 0), (b, b, 0))
+            c = (float(rng.uniform(a, b)), float(rng.uniform(a, b)))
+            wl = I.Workload(geom=geom, U=(U, 0.0, 0.0),
+                            vortices=[I.Vortex(center=c, eps=0.15 * U * rng.uniform(0.5, 1.5), U=(U, 0.0, 0.0))])
+        st = int(rng.integers(steps[0], steps[1] + 1))
+        out.append(Request(rid=k, workload=wl, steps=st, arrival=t, fp64=bool(rng.uniform() < fp64_frac),
+                           collision=collision))
+    return out
+
+
+class Server:
+    """Continuous batching over an executor.
+
+    Admission: waiting requests in order of their total work (shortest first,
+    policy "sjf") or of arrival ("fifo"); one is admitted when its footprint
+    fits the free memory budget, its batch has a free slot, and the work per
+    step already on the device is below `saturation` lattice updates (enough
+    to fill the GPU; admitting more only slows every request down).
+
+    executor interface:
+      footprint(req, fp64) -> bytes
+      admit(req, fp64) -> handle            (allocates and sets the state)
+      step(n)                              (advances every admitted request)
+      read(handle) -> dict                 (macroscopic fields)
+      release(handle)
+      free_slots(key) -> int
+    """
+
+    def __init__(self, executor, hbm_budget: int, clock=time.perf_counter, max_chunk: int = 32,
+                 policy: str = "sjf", saturation: float = math.inf):
+        self.ex = executor
+        self.budget = hbm_budget
+        self.clock = clock
+        self.max_chunk = max_chunk
+        self.policy = policy
+        self.saturation = saturation
+
+    def run(self, requests, realtime: bool = True):
+        """Runs the trace; returns the requests with admission and finish
+        times (seconds from the start).  With realtime=False arrival times are
+        ignored (every request is waiting from the start)."""
+        pending = sorted(requests, key=lambda r: r.arrival)
+        waiting = []                # FIFO of arrived requests
+        active = {}                 # handle -> (req, remaining steps, fp64, bytes)
+        used = 0
+        load = 0
+        t0 = self.clock()
+        now = lambda: self.clock() - t0
+        i = 0
+        done = []
+        while i < len(pending) or waiting or active:
+            t = now()
+            while i < len(pending) and (not realtime or pending[i].arrival <= t):
+                waiting.append(pending[i])
+                i += 1
+            # admission by footprint, free slot and device load
+            if self.policy == "sjf":
+                waiting.sort(key=lambda q: (q.updates(), q.arrival))
+            while waiting:
+                r = waiting[0]
+                fp = self.ex.footprint(r, r.fp64)
+                if fp > self.budget:
+                    raise ValueError(f"request {r.rid} needs {fp} bytes, more than the whole budget")
+                if used + fp > self.budget or self.ex.free_slots(r.key()) <= 0:
+                    break
+                if active and load >= self.saturation:
+                    break
+                waiting.pop(0)
+                h = self.ex.admit(r, r.fp64)
+                r.admitted = now()
+                ups = r.workload.geom.updates_per_step()
+                active[h] = [r, r.steps, r.fp64, fp, ups]
+                used += fp
+                load += ups
+            if not active:
+                if i < len(pending) and realtime:
+                    wait = pending[i].arrival - now()
+                    if wait > 0:
+                        time.sleep(min(wait, 0.05))
+                continue
+            n = min(self.max_chunk, min(v[1] for v in active.values()))
+            self.ex.step(n)
+            finished = []
+            for h, v in active.items():
+                v[1] -= n
+                if v[1] <= 0:
+                    finished.append(h)
+            for h in finished:
+                r, _, fp64, fp, ups = active.pop(h)
+                res = self.ex.read(h)
+                self.ex.release(h)
+                used -= fp
+                load -= ups
+                ok = all(np.isfinite(a).all() for a in res.values())
+                if not ok and not fp64:
+                    # FP64 fallback: the request is run again from its start
+                    r.fell_back = True
+                    r.fp64 = True
+                    waiting.insert(0, r)
+                    continue
+                r.result = res
+                r.finished = now()
+                done.append(r)
+        return done
+
+
+def latency_stats(done):
+    lat = np.array([r.finished - r.arrival for r in done])
+    return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "max_s": float(lat.max()), "n": int(lat.size)}
+
+
+class DeviceExecutor:
+    """Runs requests on the HIP library: one batch per (lattice, collision,
+    precision), each on its own stream."""
+
+    def __init__(self, capacity: int = 64, device: int = 0):
+        from . import lbm
+        self.lbm = lbm
+        self.capacity = capacity
+        self.device = device
+        self.batches = {}
+        self.where = {}
+        self.next = 0
+
+    def _code(self, key):
+        lat, col, prec = key
+        lbm = self.lbm
+        return (lat, {"BGK": lbm.LBM_BGK, "RR": lbm.LBM_RR, "HRR": lbm.LBM_HRR}[col],
+                lbm.LBM_FP64 if prec == "fp64" else lbm.LBM_FP32_DEV)
+
+    def batch(self, key):
+        if key not in self.batches:
+            lat, col, prec = self._code(key)
+            self.batches[key] = self.lbm.Batch(lat, col, prec, self.capacity, self.device)
+        return self.batches[key]
+
+    def footprint(self, req, fp64):
+        g = req.workload.geom
+        D = g.D
+        lat, col, prec = self._code(req.key(fp64))
+        d = self.lbm.make_desc(lat, col, prec, g.n[:D], g.lo[:D], g.hi[:D], req.tau_coarse, req.sigma)
+        return self.lbm.lbm_footprint(d)
+
+    def free_slots(self, key):
+        b = self.batches.get(key)
+        return self.capacity if b is None else self.capacity - b.info()["grids"]
+
+    def admit(self, req, fp64):
+        key = req.key(fp64)
+        b = self.batch(key)
+        g = req.workload.geom
+        D = g.D
+        sl = b.add(g.n[:D], g.lo[:D], g.hi[:D], req.tau_coarse, req.sigma)
+        for lv in (0, 1):
+            rho, u = req.fields(lv)
+            b.set_state(sl, lv, rho, u)
+        h = self.next
+        self.next += 1
+        self.where[h] = (key, sl)
+        return h
+
+    def step(self, n):
+        for b in self.batches.values():
+            if b.info()["grids"]:
+                b.step(n)
+
+    def read(self, h):
+        key, sl = self.where[h]
+        b = self.batches[key]
+        out = {}
+        for lv in (0, 1):
+            rho, u = b.get_macros(sl, lv)
+            out[f"rho{lv}"] = rho
+            out[f"u{lv}"] = u
+        return out
+
+    def release(self, h):
+        key, sl = self.where.pop(h)
+        self.batches[key].remove(sl)
+
+    def close(self):
+        for b in self.batches.values():
+            b.close()
+        self.batches.clear()
+
+
+def run_alone(req, fp64=None, device: int = 0):
+    """The plain per-instance path for one request: its own grid, stepped
+    alone; returns the same fields as DeviceExecutor.read."""
+    from . import lbm
+    g = req.workload.geom
+    D = g.D
+    col = {"BGK": lbm.LBM_BGK, "RR": lbm.LBM_RR, "HRR": lbm.LBM_HRR}[req.collision]
+    use64 = req.fp64 if fp64 is None else fp64
+    grid = lbm.Grid(req.lattice, col, lbm.LBM_FP64 if use64 else lbm.LBM_FP32_DEV, g.n[:D], g.lo[:D], g.hi[:D],
+                    req.tau_coarse, req.sigma, device)
+    for lv in (0, 1):
+        grid.set_state(lv, *req.fields(lv))
+    grid.step(req.steps)
+    out = {}
+    for lv in (0, 1):
+        rho, u = grid.get_macros(lv)
+        out[f"rho{lv}"] = rho
+        out[f"u{lv}"] = u
+    grid.close()
+    return out
+
+
+def fifo_loop(requests, realtime: bool = True, clock=time.perf_counter):
+    """Plain per-instance loop: one request at a time in arrival order."""
+    t0 = clock()
+    done = []
+    for r in sorted(requests, key=lambda q: q.arrival):
+        if realtime:
+            wait = r.arrival - (clock() - t0)
+            if wait > 0:
+                time.sleep(wait)
+        r.admitted = clock() - t0
+        r.result = run_alone(r)
+        r.finished = clock() - t0
+        done.append(r)
+    return done

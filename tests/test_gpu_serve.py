@@ -1,0 +1,40 @@
+"""The served path on the GPU: requests of different lattices, sizes and
+precisions overlap on the device in batches, are admitted by memory
+footprint, and each result equals the request run alone."""
+import numpy as np
+import pytest
+
+from paper_2004_11863_amd import serve
+
+pytestmark = pytest.mark.gpu
+
+
+def test_served_results_equal_running_alone():
+    reqs = serve.poisson_trace(10, rate=100.0, seed=11, d2_side=(40, 96), d3_side=(20, 28), steps=(8, 30),
+                               fp64_frac=0.3)
+    ex = serve.DeviceExecutor(capacity=3)
+    fps = [ex.footprint(r, r.fp64) for r in reqs]
+    budget = sum(sorted(fps)[-4:])          # room for about four at once: requests queue
+    done = serve.Server(ex, budget, max_chunk=6).run(reqs, realtime=False)
+    ex.close()
+    assert sorted(r.rid for r in done) == list(range(len(reqs)))
+    for r in done:
+        alone = serve.run_alone(r)
+        for k, v in alone.items():
+            assert np.array_equal(v, r.result[k]), (r.rid, k)
+    st = serve.latency_stats(done)
+    assert st["n"] == len(reqs) and st["p50_s"] <= st["p99_s"]
+
+
+def test_served_fp32_within_tolerance_of_fp64():
+    reqs = serve.poisson_trace(4, rate=100.0, seed=12, d2_side=(48, 64), d3_side=(20, 24), steps=(20, 40),
+                               fp64_frac=0.0)
+    ex = serve.DeviceExecutor(capacity=4)
+    done = serve.Server(ex, 1 << 36, max_chunk=8).run(reqs, realtime=False)
+    ex.close()
+    for r in done:
+        ref = serve.run_alone(r, fp64=True)
+        for lv in (0, 1):
+            assert np.abs(r.result[f"rho{lv}"] - ref[f"rho{lv}"]).max() < 1e-5
+            du = r.result[f"u{lv}"] - ref[f"u{lv}"]
+            assert np.linalg.norm(du) / np.linalg.norm(ref[f"u{lv}"]) < 1e-4
