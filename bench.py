@@ -210,14 +210,13 @@ def batched(n_inst, steps):
             "speedup": round((ups * steps / dt) / (ups * loop_steps / dl), 2)}
 
 
-def serving(n_req, rate=200.0, saturation=48e6):
+def serving(n_req, rate=200.0):
     """A seeded Poisson stream (mean 200 requests/s) mixing D2Q9 (sides
     128-2048) and D3Q19 (sides 64-256) two-level problems with 100-2000 coarse
     steps, FP32 with 10 % flagged FP64, RR; first n_req arrivals.  Initial
     fields are sampled before the trace starts (client side).  Continuous
-    batching (shortest work first, device load capped at `saturation` lattice
-    updates per step) against the plain FIFO per-instance loop on the same
-    trace."""
+    batching (size-class groups, shortest remaining time first with backfill)
+    against the plain FIFO per-instance loop on the same trace."""
     import torch
     from paper_2004_11863_amd import serve
     reqs = [r.prepare() for r in serve.poisson_trace(n_req, rate=rate, seed=5)]
@@ -226,7 +225,8 @@ def serving(n_req, rate=200.0, saturation=48e6):
     budget = int(0.8 * free)
     ex = serve.DeviceExecutor(capacity=64)
     t0 = time.perf_counter()
-    done = serve.Server(ex, budget, max_chunk=16, policy="sjf", saturation=saturation).run(reqs, realtime=True)
+    srv = serve.Server(ex, budget, policy="srpt")
+    done = srv.run(reqs, realtime=True)
     span = time.perf_counter() - t0
     ex.close()
     torch.cuda.empty_cache()
@@ -239,7 +239,7 @@ def serving(n_req, rate=200.0, saturation=48e6):
     torch.cuda.empty_cache()
     offered = work / (reqs[-1].arrival - reqs[0].arrival + 1e-9)
     return {"requests": n_req, "rate_per_s": rate, "total_updates": work,
-            "policy": "sjf", "saturation_updates_per_step": saturation,
+            "policy": "srpt", "slice_s": srv.slice_s, "backfill": srv.backfill,
             "served": {"p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
                        "aggregate_mlups": round(work / span / 1e6, 1), "makespan_s": round(span, 3),
                        "fp64_fallbacks": sum(r.fell_back for r in done)},

@@ -2,13 +2,23 @@
 
 Requests (a grid description, an initial state and a number of coarse steps)
 arrive over time.  The server admits a waiting request as soon as a batch slot
-and enough device memory (by footprint) are free, keeps its populations
-resident on the device, and advances every admitted request together: one
-coarse step of a batch is one replay of its captured launch sequence, and the
-batches of different lattices / precisions run on their own streams, so their
-work overlaps on the device.  A request leaves when it has taken its steps;
-its macroscopic fields are read back and its slot and memory freed.  FP32
-requests whose result is not finite are run again in FP64 (fallback).
+and enough device memory (by footprint) are free and keeps its populations
+resident on the device until it leaves.  Admitted requests are grouped by
+(lattice, collision, precision, size class); each group is one batch of the
+library, stepped by replaying its captured launch sequence on its own stream,
+so every member of a group advances in lock-step.  A request leaves when it
+has taken its steps; its macroscopic fields are read back and its slot and
+memory freed.  FP32 requests whose result is not finite are run again in FP64
+(fallback).
+
+Scheduling between groups ("srpt", the default): each round steps the group
+whose shortest member has the least estimated remaining time, for at most
+one time slice.  Other groups ride along on their own streams only if their
+memory traffic fits in a fraction (`backfill`) of that round, so small,
+launch-bound groups overlap with it for free while a large group waits with
+its state resident: long requests are preempted in favour of short ones at
+no copy cost.  Policy "share" steps every group by the same number of steps
+each round (processor sharing).
 
 Everything device-side goes through an executor; ``DeviceExecutor`` drives
 the C-ABI batches of the HIP library.  The scheduling logic itself is plain
@@ -23,6 +33,11 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import inputs as I
+
+# step-time model of a group, seconds per coarse step: a floor for the ~15
+# launches of a step plus its lattice updates at a sustained rate
+STEP_FLOOR_S = 60e-6
+UPDATE_RATE = 20e9
 
 
 @dataclass
@@ -49,8 +64,17 @@ class Request:
     def key(self, fp64=None):
         return (self.lattice, self.collision, "fp64" if (self.fp64 if fp64 is None else fp64) else "fp32")
 
+    def ups(self) -> int:
+        """Lattice updates per coarse step."""
+        return self.workload.geom.updates_per_step()
+
+    def group(self, fp64=None):
+        """Batch key: the library batch key plus a size class (factor-4 bins
+        of the updates per step), so lock-stepped members are of like size."""
+        return self.key(fp64) + (int(math.log(max(self.ups(), 1), 4)),)
+
     def updates(self) -> int:
-        return self.workload.geom.updates_per_step() * self.steps
+        return self.ups() * self.steps
 
     def prepare(self):
         """Samples the initial fields (client side, before submission)."""
@@ -96,39 +120,65 @@ def poisson_trace(n: int, rate: float, seed: int = 0, mix_3d: float = 0.5, d2_si
 class Server:
     """Continuous batching over an executor.
 
-    Admission: waiting requests in order of their total work (shortest first,
-    policy "sjf") or of arrival ("fifo"); one is admitted when its footprint
-    fits the free memory budget, its batch has a free slot, and the work per
-    step already on the device is below `saturation` lattice updates (enough
-    to fill the GPU; admitting more only slows every request down).
+    Admission in arrival order, skipping a request that does not fit yet: it
+    is admitted when its footprint fits the free memory budget and its group
+    has a free slot.
 
     executor interface:
       footprint(req, fp64) -> bytes
-      admit(req, fp64) -> handle            (allocates and sets the state)
-      step(n)                              (advances every admitted request)
-      read(handle) -> dict                 (macroscopic fields)
+      free_slots(group) -> int
+      admit(req, fp64, group) -> handle      (allocates and sets the state)
+      step({group: n})                      (advances each listed group n steps, then waits)
+      read(handle) -> dict                   (macroscopic fields)
       release(handle)
-      free_slots(key) -> int
     """
 
     def __init__(self, executor, hbm_budget: int, clock=time.perf_counter, max_chunk: int = 32,
-                 policy: str = "sjf", saturation: float = math.inf):
+                 policy: str = "srpt", slice_s: float = 0.02, backfill: float = 0.25):
+        if policy not in ("srpt", "share"):
+            raise ValueError(f"unknown policy {policy!r}")
         self.ex = executor
         self.budget = hbm_budget
         self.clock = clock
         self.max_chunk = max_chunk
         self.policy = policy
-        self.saturation = saturation
+        self.slice_s = slice_s
+        self.backfill = backfill
+
+    @staticmethod
+    def step_cost(members):
+        """Modelled seconds per coarse step of a group stepped alone."""
+        return STEP_FLOOR_S + sum(m.req.ups() for m in members) / UPDATE_RATE
+
+    def plan(self, groups):
+        """{group: n} for this round; groups maps a group to its members."""
+        left = {g: min(m.left for m in ms) for g, ms in groups.items()}
+        if self.policy == "share":
+            n = min(self.max_chunk, min(left.values()))
+            return {g: n for g in groups}
+        cost = {g: self.step_cost(ms) for g, ms in groups.items()}
+        order = sorted(groups, key=lambda g: (left[g] * cost[g], g))
+        g0 = order[0]
+        n0 = max(1, min(left[g0], int(self.slice_s / cost[g0])))
+        T = n0 * cost[g0]
+        out = {g0: n0}
+        extra = 0.0
+        for g in order[1:]:
+            n = max(1, min(left[g], math.ceil(T / cost[g])))
+            bw = n * sum(m.req.ups() for m in groups[g]) / UPDATE_RATE
+            if extra + bw <= self.backfill * T:
+                out[g] = n
+                extra += bw
+        return out
 
     def run(self, requests, realtime: bool = True):
         """Runs the trace; returns the requests with admission and finish
         times (seconds from the start).  With realtime=False arrival times are
         ignored (every request is waiting from the start)."""
         pending = sorted(requests, key=lambda r: r.arrival)
-        waiting = []                # FIFO of arrived requests
-        active = {}                 # handle -> (req, remaining steps, fp64, bytes)
+        waiting = []                # arrived, not admitted (arrival order)
+        active = {}                 # handle -> _Active
         used = 0
-        load = 0
         t0 = self.clock()
         now = lambda: self.clock() - t0
         i = 0
@@ -138,46 +188,43 @@ class Server:
             while i < len(pending) and (not realtime or pending[i].arrival <= t):
                 waiting.append(pending[i])
                 i += 1
-            # admission by footprint, free slot and device load
-            if self.policy == "sjf":
-                waiting.sort(key=lambda q: (q.updates(), q.arrival))
-            while waiting:
-                r = waiting[0]
+            for r in list(waiting):
                 fp = self.ex.footprint(r, r.fp64)
                 if fp > self.budget:
                     raise ValueError(f"request {r.rid} needs {fp} bytes, more than the whole budget")
-                if used + fp > self.budget or self.ex.free_slots(r.key()) <= 0:
-                    break
-                if active and load >= self.saturation:
-                    break
-                waiting.pop(0)
-                h = self.ex.admit(r, r.fp64)
+                g = r.group()
+                if used + fp > self.budget or self.ex.free_slots(g) <= 0:
+                    continue
+                waiting.remove(r)
+                h = self.ex.admit(r, r.fp64, g)
                 r.admitted = now()
-                ups = r.workload.geom.updates_per_step()
-                active[h] = [r, r.steps, r.fp64, fp, ups]
+                active[h] = _Active(r, r.steps, r.fp64, fp, g)
                 used += fp
-                load += ups
             if not active:
                 if i < len(pending) and realtime:
                     wait = pending[i].arrival - now()
                     if wait > 0:
                         time.sleep(min(wait, 0.05))
                 continue
-            n = min(self.max_chunk, min(v[1] for v in active.values()))
-            self.ex.step(n)
+            groups = {}
+            for a in active.values():
+                groups.setdefault(a.group, []).append(a)
+            plan = self.plan(groups)
+            self.ex.step(plan)
             finished = []
-            for h, v in active.items():
-                v[1] -= n
-                if v[1] <= 0:
-                    finished.append(h)
+            for h, a in active.items():
+                if a.group in plan:
+                    a.left -= plan[a.group]
+                    if a.left <= 0:
+                        finished.append(h)
             for h in finished:
-                r, _, fp64, fp, ups = active.pop(h)
+                a = active.pop(h)
+                r = a.req
                 res = self.ex.read(h)
                 self.ex.release(h)
-                used -= fp
-                load -= ups
-                ok = all(np.isfinite(a).all() for a in res.values())
-                if not ok and not fp64:
+                used -= a.bytes
+                ok = all(np.isfinite(v).all() for v in res.values())
+                if not ok and not a.fp64:
                     # FP64 fallback: the request is run again from its start
                     r.fell_back = True
                     r.fp64 = True
@@ -189,6 +236,15 @@ class Server:
         return done
 
 
+@dataclass
+class _Active:
+    req: Request
+    left: int
+    fp64: bool
+    bytes: int
+    group: tuple
+
+
 def latency_stats(done):
     lat = np.array([r.finished - r.arrival for r in done])
     return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
@@ -196,29 +252,33 @@ def latency_stats(done):
 
 
 class DeviceExecutor:
-    """Runs requests on the HIP library: one batch per (lattice, collision,
-    precision), each on its own stream."""
+    """Runs requests on the HIP library: one batch per group, each stepped on
+    its own stream."""
 
     def __init__(self, capacity: int = 64, device: int = 0):
+        import torch
         from . import lbm
+        self.torch = torch
         self.lbm = lbm
         self.capacity = capacity
         self.device = device
         self.batches = {}
+        self.streams = {}
         self.where = {}
         self.next = 0
 
     def _code(self, key):
-        lat, col, prec = key
+        lat, col, prec = key[:3]
         lbm = self.lbm
         return (lat, {"BGK": lbm.LBM_BGK, "RR": lbm.LBM_RR, "HRR": lbm.LBM_HRR}[col],
                 lbm.LBM_FP64 if prec == "fp64" else lbm.LBM_FP32_DEV)
 
-    def batch(self, key):
-        if key not in self.batches:
-            lat, col, prec = self._code(key)
-            self.batches[key] = self.lbm.Batch(lat, col, prec, self.capacity, self.device)
-        return self.batches[key]
+    def batch(self, group):
+        if group not in self.batches:
+            lat, col, prec = self._code(group)
+            self.batches[group] = self.lbm.Batch(lat, col, prec, self.capacity, self.device)
+            self.streams[group] = self.torch.cuda.Stream(device=self.device)
+        return self.batches[group]
 
     def footprint(self, req, fp64):
         g = req.workload.geom
@@ -227,13 +287,12 @@ class DeviceExecutor:
         d = self.lbm.make_desc(lat, col, prec, g.n[:D], g.lo[:D], g.hi[:D], req.tau_coarse, req.sigma)
         return self.lbm.lbm_footprint(d)
 
-    def free_slots(self, key):
-        b = self.batches.get(key)
+    def free_slots(self, group):
+        b = self.batches.get(group)
         return self.capacity if b is None else self.capacity - b.info()["grids"]
 
-    def admit(self, req, fp64):
-        key = req.key(fp64)
-        b = self.batch(key)
+    def admit(self, req, fp64, group):
+        b = self.batch(group)
         g = req.workload.geom
         D = g.D
         sl = b.add(g.n[:D], g.lo[:D], g.hi[:D], req.tau_coarse, req.sigma)
@@ -242,17 +301,18 @@ class DeviceExecutor:
             b.set_state(sl, lv, rho, u)
         h = self.next
         self.next += 1
-        self.where[h] = (key, sl)
+        self.where[h] = (group, sl)
         return h
 
-    def step(self, n):
-        for b in self.batches.values():
-            if b.info()["grids"]:
-                b.step(n)
+    def step(self, plan):
+        for g, n in plan.items():
+            self.batches[g].step(n, self.streams[g].cuda_stream)
+        for g in plan:
+            self.streams[g].synchronize()
 
     def read(self, h):
-        key, sl = self.where[h]
-        b = self.batches[key]
+        group, sl = self.where[h]
+        b = self.batches[group]
         out = {}
         for lv in (0, 1):
             rho, u = b.get_macros(sl, lv)
@@ -261,13 +321,14 @@ class DeviceExecutor:
         return out
 
     def release(self, h):
-        key, sl = self.where.pop(h)
-        self.batches[key].remove(sl)
+        group, sl = self.where.pop(h)
+        self.batches[group].remove(sl)
 
     def close(self):
         for b in self.batches.values():
             b.close()
         self.batches.clear()
+        self.streams.clear()
 
 
 def run_alone(req, fp64=None, device: int = 0):

@@ -1,5 +1,7 @@
 """Host logic of the continuous-batching server, on the CPU with a fake
 executor that runs each request on the CPU oracle (tiny grids)."""
+import math
+
 import numpy as np
 import pytest
 
@@ -8,8 +10,22 @@ from paper_2004_11863_amd import inputs as I
 from paper_2004_11863_amd import serve
 
 
+class VirtualClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+
 class FakeExecutor:
-    def __init__(self, capacity=3, nan_fp32=False):
+    """Oracle grids per request.  On the virtual clock a round costs the
+    longest launch floor of its groups (they overlap on their streams) plus
+    the memory time of all of their updates (bandwidth is shared)."""
+
+    def __init__(self, capacity=3, nan_fp32=False, clock=None):
+        self.clock = clock
+        self.plans = []
         self.capacity = capacity
         self.nan_fp32 = nan_fp32
         self.grids = {}
@@ -24,10 +40,10 @@ class FakeExecutor:
     def footprint(self, req, fp64):
         return req.workload.geom.nodes(0) * (16 if fp64 else 8)
 
-    def free_slots(self, key):
-        return self.capacity - self.used_slots.get(key, 0)
+    def free_slots(self, group):
+        return self.capacity - self.used_slots.get(group, 0)
 
-    def admit(self, req, fp64):
+    def admit(self, req, fp64, group):
         g = req.workload.geom
         D = g.D
         grid = O.Grid(O.D2Q9 if D == 2 else O.D3Q19, O.RR, g.n[:D], g.lo[:D], g.hi[:D], tau_c=req.tau_coarse)
@@ -35,7 +51,8 @@ class FakeExecutor:
             grid.set_state(lv, *req.fields(lv))
         h = self.next
         self.next += 1
-        key = req.key(fp64)
+        key = group
+        assert group == req.group(fp64)
         self.grids[h] = (grid, req, fp64, key)
         self.used_slots[key] = self.used_slots.get(key, 0) + 1
         self.bytes_used += self.footprint(req, fp64)
@@ -44,10 +61,19 @@ class FakeExecutor:
         self.steps_seen[h] = 0
         return h
 
-    def step(self, n):
-        for h, (grid, _, _, _) in self.grids.items():
-            grid.step(n)
-            self.steps_seen[h] += n
+    def step(self, plan):
+        self.plans.append(dict(plan))
+        for h, (grid, req, _, key) in self.grids.items():
+            if key in plan:
+                grid.step(plan[key])
+                self.steps_seen[h] += plan[key]
+        if self.clock is not None:
+            floor, mem = 0.0, 0.0
+            for g, n in plan.items():
+                ms = [req for (_, req, _, key) in self.grids.values() if key == g]
+                floor = max(floor, n * serve.STEP_FLOOR_S)
+                mem += n * sum(r.ups() for r in ms) / serve.UPDATE_RATE
+            self.clock.t += floor + mem
 
     def read(self, h):
         grid, req, fp64, _ = self.grids[h]
@@ -86,10 +112,24 @@ def test_every_request_completes_within_budget_and_slots():
     reqs = _trace()
     ex = FakeExecutor(capacity=2)
     budget = 3 * max(ex.footprint(r, True) for r in reqs)
-    done = serve.Server(ex, budget, max_chunk=4, policy="fifo").run(reqs, realtime=False)
+    done = serve.Server(ex, budget, max_chunk=4, policy="share").run(reqs, realtime=False)
     assert sorted(r.rid for r in done) == list(range(len(reqs)))
     assert ex.max_bytes <= budget
-    assert ex.admit_order == sorted(ex.admit_order)      # FIFO admission
+    for r in done:
+        assert r.finished >= r.admitted
+    st = serve.latency_stats(done)
+    assert st["p50_s"] <= st["p99_s"]
+
+
+@pytest.mark.parametrize("policy", ["srpt", "share"])
+def test_admission_in_arrival_order_within_budget(policy):
+    reqs = _trace()
+    ex = FakeExecutor(capacity=2)
+    budget = 3 * max(ex.footprint(r, True) for r in reqs)
+    done = serve.Server(ex, budget, max_chunk=4, policy=policy).run(reqs, realtime=False)
+    assert sorted(r.rid for r in done) == list(range(len(reqs)))
+    assert ex.max_bytes <= budget
+    assert max(ex.used_slots.values()) == 0
     for r in done:
         assert r.finished >= r.admitted
         assert np.isfinite(r.result["rho0"]).all()
@@ -132,18 +172,105 @@ def test_request_larger_than_budget_is_rejected():
         serve.Server(ex, 10, max_chunk=2).run(reqs, realtime=False)
 
 
-def test_sjf_admits_shortest_work_first_and_saturation_caps_concurrency():
-    reqs = _trace(n=6, seed=9)
-    ex = FakeExecutor(capacity=6)
-    sat = min(r.workload.geom.updates_per_step() for r in reqs)
-    done = serve.Server(ex, 10 ** 12, max_chunk=2, policy="sjf", saturation=sat).run(reqs, realtime=False)
-    assert len(done) == len(reqs)
-    order = [r.rid for r in sorted(reqs, key=lambda q: (q.updates(), q.arrival))]
-    assert ex.admit_order == order
-    # with the cap at the smallest request's load, one request runs at a time
-    spans = sorted((r.admitted, r.finished) for r in done)
-    for (a0, f0), (a1, f1) in zip(spans, spans[1:]):
-        assert a1 >= f0 - 1e-9
+def test_groups_split_by_key_and_size_class():
+    reqs = _trace(n=7, seed=3)
+    for r in reqs:
+        lat, col, prec, sc = r.group()
+        assert (lat, col, prec) == r.key()
+        assert 4 ** sc <= r.ups() < 4 ** (sc + 1)
+    r = reqs[0]
+    assert r.group(fp64=True)[2] == "fp64" and r.group(fp64=False)[2] == "fp32"
+
+
+def test_srpt_runs_shortest_remaining_first():
+    reqs = _trace(n=8, seed=4)
+    for k, r in enumerate(reqs):
+        r.steps = 30 if k == 0 else 3
+        r.fp64 = False
+    clock = VirtualClock()
+    ex = FakeExecutor(capacity=8, clock=clock)
+    done = serve.Server(ex, 10 ** 12, clock=clock, max_chunk=4, policy="srpt").run(reqs, realtime=False)
+    fin = {r.rid: r.finished for r in done}
+    assert all(fin[0] >= fin[k] for k in fin)            # the long request leaves last
+
+
+class _R:
+    """Stand-in request for plan(): only its size matters."""
+
+    def __init__(self, ups):
+        self._u = ups
+
+    def ups(self):
+        return self._u
+
+
+def _members(ups, lefts):
+    return [serve._Active(_R(ups), n, False, 0, None) for n in lefts]
+
+
+def test_plan_pauses_a_large_group_for_a_short_one():
+    srv = serve.Server(None, 0, policy="srpt", slice_s=0.02, backfill=0.25)
+    groups = {"big": _members(50e6, [1000]), "small": _members(1e5, [100, 300])}
+    plan = srv.plan(groups)
+    cost_small = serve.STEP_FLOOR_S + 2e5 / serve.UPDATE_RATE
+    assert plan == {"small": min(100, int(0.02 / cost_small))}
+
+
+def test_plan_backfills_small_groups_and_caps_the_slice():
+    srv = serve.Server(None, 0, policy="srpt", slice_s=0.02, backfill=0.25)
+    groups = {"big": _members(50e6, [1000]), "a": _members(1e4, [60000]), "b": _members(2e4, [50000])}
+    plan = srv.plan(groups)
+    # the big group has the least remaining time (1000 steps) and takes one slice
+    cost_big = serve.STEP_FLOOR_S + 50e6 / serve.UPDATE_RATE
+    n0 = int(0.02 / cost_big)
+    assert plan["big"] == n0
+    # the small, launch-bound groups ride along for about the same time
+    T = n0 * cost_big
+    for g, u in (("a", 1e4), ("b", 2e4)):
+        assert plan[g] == math.ceil(T / (serve.STEP_FLOOR_S + u / serve.UPDATE_RATE))
+
+
+def test_plan_share_steps_every_group_alike():
+    srv = serve.Server(None, 0, policy="share", max_chunk=8)
+    groups = {"big": _members(50e6, [1000]), "small": _members(1e5, [5, 300])}
+    assert srv.plan(groups) == {"big": 5, "small": 5}
+
+
+def test_srpt_preempts_a_running_long_request():
+    pool = _trace(n=8, seed=6)
+    long_ = next(r for r in pool if r.workload.geom.D == 3)
+    short = next(r for r in pool if r.workload.geom.D == 2)   # another group
+    long_.steps, short.steps = 200, 2
+    long_.fp64 = short.fp64 = False
+    long_.arrival = 0.0
+    c_long = serve.STEP_FLOOR_S + long_.ups() / serve.UPDATE_RATE
+    short.arrival = 10.5 * c_long                        # arrives while the long one runs
+    clock = VirtualClock()
+    ex = FakeExecutor(capacity=2, clock=clock)
+    srv = serve.Server(ex, 10 ** 12, clock=clock, policy="srpt", slice_s=2 * c_long)
+    done = srv.run([long_, short], realtime=True)
+    fin = {r.rid: r.finished for r in done}
+    assert fin[short.rid] < fin[long_.rid]
+    assert long_.group() in ex.plans[0] and short.group() not in ex.plans[0]
+    assert any(short.group() in p for p in ex.plans)
+
+
+def test_srpt_mean_latency_not_worse_than_sharing():
+    def run(policy):
+        reqs = _trace(n=8, seed=4)
+        for k, r in enumerate(reqs):
+            r.steps = 30 if k % 4 == 0 else 3
+            r.fp64 = False
+        clock = VirtualClock()
+        ex = FakeExecutor(capacity=8, clock=clock)
+        done = serve.Server(ex, 10 ** 12, clock=clock, max_chunk=4, policy=policy).run(reqs, realtime=False)
+        return serve.latency_stats(done)["mean_s"]
+    assert run("srpt") <= run("share") + 1e-12
+
+
+def test_unknown_policy_rejected():
+    with pytest.raises(ValueError):
+        serve.Server(FakeExecutor(), 1, policy="lifo")
 
 
 def test_prepared_payload_is_used():
