@@ -157,16 +157,20 @@ int lbm_updates_per_step(lbm_handle h, int64_t* updates);
 int lbm_profile_enable(lbm_handle h, int on);
 int lbm_kernel_time(lbm_handle h, int64_t* launches, double* mean_ms, int64_t* nodes_per_launch);
 
-/* Autotuner: times every bulk-kernel variant (nodes per lane x lanes along
- * x of the work group) of each bulk role of this grid -- coarse stream, fine
- * stream, coarse and fine H-RR collision -- over reps launches on the grid's
- * own data and keeps the fastest.  variants[4] receives the chosen index per
- * role (roles the grid does not use keep their default).  Only buffers that
- * the next lbm_step rewrites are touched, so the state is unchanged.
- * Synchronous. */
+/* Bulk-kernel launch variants, 0 .. LBM_N_VARIANTS - 1: the same kernels
+ * launched with 0, 53, 80 or 160 KB of unused LDS per 256-lane work group,
+ * which caps the work groups resident on a CU (no cap, 3, 2, 1).  Every
+ * variant computes bitwise the same result. */
+enum { LBM_N_VARIANTS = 4 };
+/* Autotuner: times every bulk-kernel variant of each bulk role of this grid
+ * -- coarse stream, fine stream, coarse and fine H-RR collision -- over reps
+ * launches on the grid's own data and keeps the fastest.  variants[4]
+ * receives the chosen index per role (roles the grid does not use keep their
+ * default).  Only buffers that the next lbm_step rewrites are touched, so the
+ * state is unchanged.  Synchronous. */
 int lbm_tune(lbm_handle h, int reps, int32_t variants[4]);
 /* Sets the variant index per role (as returned by lbm_tune); LBM_EINVAL if
- * an index is out of range for the grid's precision. */
+ * an index is outside 0 .. LBM_N_VARIANTS - 1. */
 int lbm_set_variants(lbm_handle h, const int32_t variants[4]);
 
 /* Last error text for a handle (NULL: last failure of lbm_create_grid). */

@@ -5,9 +5,9 @@
 // table of InstDev descriptors holds their geometry, buffer pointers and
 // time-level state (coarse ping-pong parity, history rotation).  For each
 // phase of the coarse step there is one work list of (instance, index)
-// items: a bulk tile, a block of 64 interface nodes, or a block of TN nodes.
-// A phase is one launch of a persistent kernel whose work groups walk the
-// list; the list is split into 8 contiguous chunks, one per XCD, so the tiles
+// items: a bulk chunk of 256 vectors, a block of 64 interface nodes, or a
+// block of TN nodes.  A phase is one launch of a persistent kernel whose work
+// groups walk the list; the list is split into 8 contiguous runs, one per XCD, so the chunks
 // of one instance stay in one L2.  The last launch of a step flips each
 // instance's parity and rotates its history on the device, so the launch
 // sequence of a step is the same every step and is captured once as a
@@ -21,7 +21,7 @@ namespace lbm {
 struct InstDev {
   Geo g;
   Iface itf;
-  Tiling tc, tf;  // bulk tilings of the batch's kernel variant
+  Flat fc, ff;  // flat numbering of the coarse / fine bulk vectors
   void* cbuf[2];
   void* fbuf[2];
   void* mac_c;
@@ -42,8 +42,8 @@ struct Work {
 
 // Work-list kinds.
 enum WorkKind : int {
-  W_COARSE = 0,  // coarse bulk tiles
-  W_FINE = 1,    // fine bulk tiles
+  W_COARSE = 0,  // coarse bulk chunks
+  W_FINE = 1,    // fine bulk chunks
   W_HIST = 2,    // 64 history nodes
   W_HTIME = 3,   // 64 history values (all fields)
   W_RING = 4,    // 64 ring nodes
@@ -72,7 +72,7 @@ __device__ inline Work load_item(const Work* __restrict__ items, int it) {
 
 // Bulk stream of one level; SUB selects the fine buffer direction (0: A->B,
 // 1: B->A).
-template <int LAT, bool DEV, typename S, int MODEL, int LEVEL, int SUB, int V, int LX, bool NT>
+template <int LAT, bool DEV, typename S, int MODEL, int LEVEL, int SUB, bool NT>
 __global__ __launch_bounds__(256) void kb_stream(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                                  const int* __restrict__ count) {
   int it, end, stride;
@@ -83,18 +83,18 @@ __global__ __launch_bounds__(256) void kb_stream(const InstDev* __restrict__ ins
     if (LEVEL == 0) {
       const S* src = (const S*)I.cbuf[I.cpar];
       S* dst = (S*)I.cbuf[I.cpar ^ 1];
-      stream_body<LAT, DEV, S, MODEL, 0, V, LX, NT>(src, dst, (S*)I.mac_c, I.g, I.tc, (S)(1.0 - 1.0 / I.tau_c), w.idx);
+      stream_body<LAT, DEV, S, MODEL, 0, NT>(src, dst, (S*)I.mac_c, I.g, I.fc, (S)(1.0 - 1.0 / I.tau_c), w.idx);
     } else {
       const S* src = (const S*)I.fbuf[SUB];
       S* dst = (S*)I.fbuf[SUB ^ 1];
-      stream_body<LAT, DEV, S, MODEL, 1, V, LX, NT>(src, dst, (S*)I.mac_f, I.g, I.tf, (S)(1.0 - 1.0 / I.tau_f), w.idx);
+      stream_body<LAT, DEV, S, MODEL, 1, NT>(src, dst, (S*)I.mac_f, I.g, I.ff, (S)(1.0 - 1.0 / I.tau_f), w.idx);
     }
   }
 }
 
 // H-RR collision in place.  LEVEL 0: the coarse buffer being written this
 // step; LEVEL 1: fine buffer B (SUB 0) or A (SUB 1).
-template <int LAT, bool DEV, typename S, int LEVEL, int SUB, int V, int LX, bool NT>
+template <int LAT, bool DEV, typename S, int LEVEL, int SUB, bool NT>
 __global__ __launch_bounds__(256) void kb_collide(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                                   const int* __restrict__ count) {
   int it, end, stride;
@@ -103,11 +103,11 @@ __global__ __launch_bounds__(256) void kb_collide(const InstDev* __restrict__ in
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
     if (LEVEL == 0) {
-      collide_hrr_body<LAT, DEV, S, 0, V, LX, NT>((S*)I.cbuf[I.cpar ^ 1], (const S*)I.mac_c, I.g, I.tc,
-                                                  (S)(1.0 - 1.0 / I.tau_c), (S)I.tau_c, (S)I.sig, w.idx);
+      collide_hrr_body<LAT, DEV, S, 0, NT>((S*)I.cbuf[I.cpar ^ 1], (const S*)I.mac_c, I.g, I.fc,
+                                           (S)(1.0 - 1.0 / I.tau_c), (S)I.tau_c, (S)I.sig, w.idx);
     } else {
-      collide_hrr_body<LAT, DEV, S, 1, V, LX, NT>((S*)I.fbuf[SUB ^ 1], (const S*)I.mac_f, I.g, I.tf,
-                                                  (S)(1.0 - 1.0 / I.tau_f), (S)I.tau_f, (S)I.sig, w.idx);
+      collide_hrr_body<LAT, DEV, S, 1, NT>((S*)I.fbuf[SUB ^ 1], (const S*)I.mac_f, I.g, I.ff,
+                                           (S)(1.0 - 1.0 / I.tau_f), (S)I.tau_f, (S)I.sig, w.idx);
     }
   }
 }

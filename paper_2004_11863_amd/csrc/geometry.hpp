@@ -23,8 +23,9 @@ enum FineClass : int { FC_MIDDLE = 0, FC_TF = 1, FC_IE = 2, FC_IEFACE = 3, FC_TN
 
 // Device arrays use a padded row pitch (pc, pf: nodes per row rounded up to
 // a multiple of 4) so every row starts 16-byte aligned; Ncp, Nfp are the
-// padded node counts of one population plane.  Nc, Nf count logical nodes
-// (the x-fastest order of the C ABI and of the interface tables).
+// padded node counts of a level (the positions of pop_at below, and the plane
+// size of the velocity planes).  Nc, Nf count logical nodes (the x-fastest
+// order of the C ABI and of the interface tables).
 struct Geo {
   int D;
   int n[3];   // coarse nodes per axis (1 on unused axes)
@@ -102,5 +103,30 @@ __host__ __device__ inline int fine_class(const Geo& g, int x, int y, int z) {
 
 // Periodic wrap of a coarse coordinate displaced by at most one period.
 __host__ __device__ inline int wrap(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }
+
+// Population storage, array of structure-of-arrays: the padded node positions
+// p of a level are cut into blocks of PB consecutive positions; block b holds
+// Q sub-blocks of 32 KB, one per population, each with the PB values of that
+// block.  A pull-stream step then keeps its 2Q concurrent memory streams
+// within two windows of Q x 32 KB instead of 2Q planes spread over the whole
+// buffer, which HBM serves markedly faster than plain structure-of-arrays.
+template <typename S>
+struct PopBlock {
+  static constexpr int SHIFT = sizeof(S) == 4 ? 13 : 12;  // 8192 floats or 4096 doubles
+  static constexpr int64_t B = (int64_t)1 << SHIFT;
+};
+template <typename S, int Q>
+__host__ __device__ inline int64_t pop_at(int64_t p, int q) {
+  constexpr int SH = PopBlock<S>::SHIFT;
+  constexpr int64_t B = PopBlock<S>::B;
+  return (((p >> SH) * Q + q) << SH) + (p & (B - 1));
+}
+// Elements of a population buffer for NP padded positions: whole blocks up
+// to and including position NP (the last x-vector of a fine row reaches one
+// position past the end of its row).
+template <typename S>
+__host__ __device__ inline int64_t pop_elems(int64_t NP, int Q) {
+  return ((NP >> PopBlock<S>::SHIFT) + 1) * (int64_t)Q * PopBlock<S>::B;
+}
 
 }  // namespace lbm

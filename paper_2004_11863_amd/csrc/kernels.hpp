@@ -1,18 +1,21 @@
 // kernels.hpp -- gfx950 kernels of the two-level LBM hot path.
 //
-// Layout in HBM: every level stores its populations structure-of-arrays,
-// s[q][z][y][x] with a padded row pitch (a multiple of 4 nodes, so rows start
-// 16-byte aligned), in a ping-pong pair of buffers (pull scheme: a step reads
-// one buffer and writes the other).
+// Layout in HBM: every level stores its populations array-of-SoA (pop_at in
+// geometry.hpp) over padded node positions with a row pitch that is a
+// multiple of 4 nodes, so rows start 16-byte aligned, in a ping-pong pair of
+// buffers (pull scheme: a step reads one buffer and writes the other).
 //
 // Bulk kernels: one work-item updates V consecutive nodes of a row, so every
 // population is moved with one 16-byte access per lane (V = 4 in FP32, V = 2
 // in FP64); the streams shifted by +-1 along x use 4/8-byte-aligned 16-byte
-// loads, stores are aligned and non-temporal.  A work group is 64 lanes along
-// x times TY rows.  Work groups are handed to the 8 XCDs round-robin by the
-// hardware; the tile index is remapped so each XCD receives one contiguous
-// run of tiles, which keeps the +-y / +-z neighbour rows of a tile in the
-// same L2.
+// loads, stores are aligned and non-temporal.  The vectors of the processed
+// rows are numbered row after row ("flat" order) and a work group takes 256
+// consecutive ones; work groups are handed to the 8 XCDs round-robin by the
+// hardware, so the chunk index is remapped to give each XCD one contiguous
+// run, which keeps the +-y / +-z neighbour rows of a chunk in the same L2.
+// Fewer resident work groups per CU let HBM serve the 2Q streams with fewer
+// row switches; the launch variants cap the residency through unused dynamic
+// LDS (kVarLds).
 //
 // Interface kernels (history capture, ring reconstruction, fine-to-coarse
 // coalescence) work per interface node in double precision, with small work
@@ -27,6 +30,10 @@ namespace lbm {
 
 constexpr int kXCD = 8;
 constexpr int kIfaceBlock = 64;
+// Bulk-kernel launch variants: dynamic LDS per 256-lane work group (none,
+// then caps of 3, 2 and 1 resident work groups per CU of 160 KB LDS).
+constexpr int kNVar = 4;
+constexpr int kVarLds[kNVar] = {0, 53 * 1024, 80 * 1024, 160 * 1024};
 
 // Model codes: BGK and RR collide in the streaming kernel; the split H-RR
 // path streams first (kernel writes the pre-collision state and rho, u) and
@@ -43,14 +50,14 @@ struct VT<float, 4> {
   typedef float u __attribute__((ext_vector_type(4), aligned(4)));
 };
 template <>
-struct VT<float, 2> {
-  typedef float a __attribute__((ext_vector_type(2)));
-  typedef float u __attribute__((ext_vector_type(2), aligned(4)));
-};
-template <>
 struct VT<double, 2> {
   typedef double a __attribute__((ext_vector_type(2)));
   typedef double u __attribute__((ext_vector_type(2), aligned(8)));
+};
+// Nodes per lane of the bulk kernels.
+template <typename S>
+struct VecOf {
+  static constexpr int V = 16 / sizeof(S);
 };
 
 template <bool NT, typename A>
@@ -59,53 +66,59 @@ __device__ inline void vstore(A* p, const A& v) {
   else *p = v;
 }
 
-// A work group is LX lanes along x times TY rows (LX * TY = 256); each lane
-// owns V consecutive nodes starting at xb + V k.  The fine level starts at
-// xb = 1 (its first middle node, 16-byte aligned in storage); the coarse
-// level at xb = 0.
-struct Tiling {
+// Flat numbering of the bulk vectors of a level: rows y0 .. y0+nyr-1 of planes
+// z0 .. z0+nzr-1, nv vectors of V nodes per row starting at node xb (the
+// fine level starts at its first middle node x = 1, which is 16-byte aligned
+// in storage, and skips its ring rows and planes; the coarse level covers
+// every row).  A chunk is 256 consecutive vectors, one per lane.
+struct Flat {
   int nx, ny, nz;  // level extent (nodes)
   int xb;          // first node of the vector grid along x
   int nv;          // vectors per row
-  int ntx, nty;    // tiles per axis
-  int ntiles;      // ntx * nty * nz
-  int per_xcd;     // tiles given to each XCD (launch = per_xcd * 8 groups)
+  int y0, nyr;     // first processed row, processed rows per plane
+  int z0, nzr;     // first processed plane, processed planes
+  int64_t nvec;    // nv * nyr * nzr
+  int nchunks;     // ceil(nvec / 256)
+  int per_xcd;     // chunks given to each XCD (launch = per_xcd * 8 groups)
 };
 
-inline Tiling make_tiling(int nx, int ny, int nz, int xb, int V, int LX, int TY) {
-  Tiling t;
-  t.nx = nx;
-  t.ny = ny;
-  t.nz = nz;
-  t.xb = xb;
-  t.nv = (nx - xb + V - 1) / V;
-  t.ntx = (t.nv + LX - 1) / LX;
-  t.nty = (ny + TY - 1) / TY;
-  t.ntiles = t.ntx * t.nty * nz;
-  t.per_xcd = (t.ntiles + kXCD - 1) / kXCD;
-  return t;
+inline Flat make_flat(int nx, int ny, int nz, int V, bool fine, int D) {
+  Flat f;
+  f.nx = nx;
+  f.ny = ny;
+  f.nz = nz;
+  f.xb = fine ? 1 : 0;
+  f.nv = (nx - f.xb + V - 1) / V;
+  f.y0 = fine ? 1 : 0;
+  f.nyr = fine ? ny - 2 : ny;
+  f.z0 = (fine && D == 3) ? 1 : 0;
+  f.nzr = (fine && D == 3) ? nz - 2 : nz;
+  f.nvec = (int64_t)f.nv * f.nyr * f.nzr;
+  f.nchunks = (int)((f.nvec + 255) / 256);
+  f.per_xcd = (f.nchunks + kXCD - 1) / kXCD;
+  return f;
 }
 
-// Tile of this work group in a single-grid launch: each XCD gets one
-// contiguous run of per_xcd tiles.
-__device__ inline int xcd_tile(const Tiling& t) {
+// Chunk of this work group in a single-grid launch: each XCD gets one
+// contiguous run of per_xcd chunks.
+__device__ inline int xcd_chunk(const Flat& f) {
   const int b = blockIdx.x;
-  return (b % kXCD) * t.per_xcd + b / kXCD;
+  return (b % kXCD) * f.per_xcd + b / kXCD;
 }
 
-// First node x0 of this work-item's V-node vector in tile `tile`; false
-// outside the level.
-template <int V, int LX, int TY>
-__device__ inline bool tile_vec(const Tiling& t, int tile, int& x0, int& y, int& z) {
-  if (tile >= t.ntiles) return false;
-  const int tx = tile % t.ntx;
-  const int r = tile / t.ntx;
-  const int ty = r % t.nty;
-  z = r / t.nty;
-  const int vi = tx * LX + (int)(threadIdx.x % LX);
-  x0 = t.xb + vi * V;
-  y = ty * TY + (int)(threadIdx.x / LX);
-  return vi < t.nv && y < t.ny;
+// First node x0 of this work-item's V-node vector in chunk `chunk`; false
+// past the last vector.
+template <int V>
+__device__ inline bool flat_vec(const Flat& f, int chunk, int& x0, int& y, int& z) {
+  if (chunk >= f.nchunks) return false;
+  const int64_t v = (int64_t)chunk * 256 + threadIdx.x;
+  if (v >= f.nvec) return false;
+  const int64_t r = v / f.nv;
+  const int vi = (int)(v - r * f.nv);
+  x0 = f.xb + vi * V;
+  y = f.y0 + (int)(r % f.nyr);
+  z = f.z0 + (int)(r / f.nyr);
+  return true;
 }
 
 // x coordinate wrapped into [0, n) (any displacement).
@@ -115,8 +128,9 @@ __device__ inline int wrapx(int x, int n) {
   return x;
 }
 
-// Loads the V values of one population row starting at x0 - cx.  Coarse
-// rows are periodic: vectors that cross a row end are gathered element-wise.
+// Loads the V values of one row of a plain array (the velocity planes)
+// starting at x0 - cx.  Coarse rows are periodic: vectors that cross a row
+// end are gathered element-wise.
 template <typename S, int V, int LEVEL>
 __device__ inline typename VT<S, V>::a load_row(const S* __restrict__ row, int x0, int cx, int nx) {
   using VA = typename VT<S, V>::a;
@@ -132,13 +146,36 @@ __device__ inline typename VT<S, V>::a load_row(const S* __restrict__ row, int x
   return (VA)(*(const VU*)(row + xs));
 }
 
-// Skip test shared by the bulk kernels: fine ring rows/planes (the ring
-// columns are computed and later overwritten by the ring kernel) and coarse
-// vectors lying wholly inside the covered box.
-template <int LEVEL, int D>
-__device__ inline bool skip_vec(const Geo& g, int x0, int V, int y, int z, int nx, int ny, int nz) {
-  if (LEVEL == 1) return y == 0 || y == ny - 1 || (D == 3 && (z == 0 || z == nz - 1));
-  if (!g.has_fine) return false;
+// Loads population q of the V nodes x0 - cx .. x0 - cx + V - 1 of the row
+// whose x = 0 sits at padded position `rowp`.  Coarse rows are periodic;
+// vectors crossing a row end (coarse) or a storage block (x-shifted pulls)
+// are gathered element-wise; all others are one 16-byte load.
+template <typename S, int Q, int V, int LEVEL>
+__device__ inline typename VT<S, V>::a load_pull(const S* __restrict__ src, int64_t rowp, int x0, int cx, int nx,
+                                                 int q) {
+  using VA = typename VT<S, V>::a;
+  using VU = typename VT<S, V>::u;
+  constexpr int64_t BM = PopBlock<S>::B - 1;
+  const int xs = x0 - cx;
+  if (LEVEL == 0 && cx != 0 && (xs < 0 || xs + V > nx)) {
+    VA v;
+#pragma unroll
+    for (int k = 0; k < V; ++k) v[k] = src[pop_at<S, Q>(rowp + wrapx(xs + k, nx), q)];
+    return v;
+  }
+  const int64_t p = rowp + xs;
+  if (cx == 0) return *(const VA*)(src + pop_at<S, Q>(p, q));
+  if ((p & BM) + (V - 1) <= BM) return (VA)(*(const VU*)(src + pop_at<S, Q>(p, q)));
+  VA v;
+#pragma unroll
+  for (int k = 0; k < V; ++k) v[k] = src[pop_at<S, Q>(p + k, q)];
+  return v;
+}
+
+// Coarse vectors lying wholly inside the covered box are not evolved.
+template <int LEVEL>
+__device__ inline bool skip_vec(const Geo& g, int x0, int V, int y, int z, int nx) {
+  if (LEVEL == 1 || !g.has_fine) return false;
   const int xl = min(x0 + V - 1, nx - 1);
   return coarse_class(g, x0, y, z) == CC_COVERED && coarse_class(g, xl, y, z) == CC_COVERED;
 }
@@ -149,20 +186,20 @@ __device__ inline bool skip_vec(const Geo& g, int x0, int V, int y, int z, int n
 // MODEL BGK/RR: dst = collide(pull(src)).  MODEL HRR: dst = pull(src) and
 // mac = (rho, u) of the pulled state (padded planes of the level).
 // Every node of a processed vector is written, including coarse TN/covered
-// nodes and fine ring columns: the schedule overwrites TN and ring nodes
-// afterwards and never reads covered ones.
-template <int LAT, bool DEV, typename S, int MODEL, int LEVEL, int V, int LX, bool NT>
+// nodes and the fine ring column x = nx - 1: the schedule overwrites TN and
+// ring nodes afterwards and never reads covered ones.
+template <int LAT, bool DEV, typename S, int MODEL, int LEVEL, bool NT>
 __device__ inline void stream_body(const S* __restrict__ src, S* __restrict__ dst, S* __restrict__ mac, const Geo& g,
-                                   const Tiling& tl, const S om, int tile) {
+                                   const Flat& fl, const S om, int chunk) {
   using L = Lattice<LAT>;
   using N = Node<LAT, DEV, S>;
+  constexpr int V = VecOf<S>::V;
   using VA = typename VT<S, V>::a;
   constexpr int Q = L::Q;
-  constexpr int TY = 256 / LX;
   int x0, y, z;
-  if (!tile_vec<V, LX, TY>(tl, tile, x0, y, z)) return;
-  const int nx = tl.nx, ny = tl.ny, nz = tl.nz;
-  if (skip_vec<LEVEL, L::D>(g, x0, V, y, z, nx, ny, nz)) return;
+  if (!flat_vec<V>(fl, chunk, x0, y, z)) return;
+  const int nx = fl.nx, ny = fl.ny, nz = fl.nz;
+  if (skip_vec<LEVEL>(g, x0, V, y, z, nx)) return;
   const int64_t P = LEVEL == 0 ? g.pc : g.pf;
   const int64_t NP = LEVEL == 0 ? g.Ncp : g.Nfp;
   const int xo = LEVEL == 0 ? 0 : g.fxo;
@@ -174,7 +211,7 @@ __device__ inline void stream_body(const S* __restrict__ src, S* __restrict__ ds
       ys = wrap(ys, ny);
       if (L::D == 3) zs = wrap(zs, nz);
     }
-    v[i] = load_row<S, V, LEVEL>(src + (int64_t)i * NP + P * ((int64_t)ys + (int64_t)ny * zs) + xo, x0, L::cx(i), nx);
+    v[i] = load_pull<S, Q, V, LEVEL>(src, P * ((int64_t)ys + (int64_t)ny * zs) + xo, x0, L::cx(i), nx, i);
   }
   const int64_t own = P * ((int64_t)y + (int64_t)ny * z) + xo + x0;
   if (MODEL == M_HRR) {
@@ -206,31 +243,31 @@ __device__ inline void stream_body(const S* __restrict__ src, S* __restrict__ ds
     }
   }
 #pragma unroll
-  for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + (int64_t)i * NP + own), v[i]);
+  for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + pop_at<S, Q>(own, i)), v[i]);
 }
 
-template <int LAT, bool DEV, typename S, int MODEL, int LEVEL, int V, int LX, bool NT>
+template <int LAT, bool DEV, typename S, int MODEL, int LEVEL, bool NT>
 __global__ __launch_bounds__(256) void k_stream(const S* __restrict__ src, S* __restrict__ dst, S* __restrict__ mac,
-                                                const Geo g, const Tiling tl, const S om) {
-  stream_body<LAT, DEV, S, MODEL, LEVEL, V, LX, NT>(src, dst, mac, g, tl, om, xcd_tile(tl));
+                                                const Geo g, const Flat fl, const S om) {
+  stream_body<LAT, DEV, S, MODEL, LEVEL, NT>(src, dst, mac, g, fl, om, xcd_chunk(fl));
 }
 
 // H-RR collision in place on a level, with the strain rate from centred
 // differences (second order, level lattice units) of the velocity planes of
 // mac (Sec. 3.3).  Processes whole vectors like k_stream; the coarse pass runs
 // before the fine-to-coarse transfer overwrites TN nodes.
-template <int LAT, bool DEV, typename S, int LEVEL, int V, int LX, bool NT>
-__device__ inline void collide_hrr_body(S* __restrict__ buf, const S* __restrict__ mac, const Geo& g, const Tiling& tl,
-                                        const S om, const S tau, const S sig, int tile) {
+template <int LAT, bool DEV, typename S, int LEVEL, bool NT>
+__device__ inline void collide_hrr_body(S* __restrict__ buf, const S* __restrict__ mac, const Geo& g, const Flat& fl,
+                                        const S om, const S tau, const S sig, int chunk) {
   using L = Lattice<LAT>;
   using N = Node<LAT, DEV, S>;
+  constexpr int V = VecOf<S>::V;
   using VA = typename VT<S, V>::a;
   constexpr int Q = L::Q, D = L::D;
-  constexpr int TY = 256 / LX;
   int x0, y, z;
-  if (!tile_vec<V, LX, TY>(tl, tile, x0, y, z)) return;
-  const int nx = tl.nx, ny = tl.ny, nz = tl.nz;
-  if (skip_vec<LEVEL, D>(g, x0, V, y, z, nx, ny, nz)) return;
+  if (!flat_vec<V>(fl, chunk, x0, y, z)) return;
+  const int nx = fl.nx, ny = fl.ny, nz = fl.nz;
+  if (skip_vec<LEVEL>(g, x0, V, y, z, nx)) return;
   const int64_t P = LEVEL == 0 ? g.pc : g.pf;
   const int64_t NP = LEVEL == 0 ? g.Ncp : g.Nfp;
   const int xo = LEVEL == 0 ? 0 : g.fxo;
@@ -265,7 +302,7 @@ __device__ inline void collide_hrr_body(S* __restrict__ buf, const S* __restrict
   }
   VA v[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) v[i] = *(const VA*)(buf + (int64_t)i * NP + own);
+  for (int i = 0; i < Q; ++i) v[i] = *(const VA*)(buf + pop_at<S, Q>(own, i));
 #pragma unroll
   for (int k = 0; k < V; ++k) {
     Sym<S> Sr;
@@ -287,13 +324,13 @@ __device__ inline void collide_hrr_body(S* __restrict__ buf, const S* __restrict
     for (int i = 0; i < Q; ++i) v[i][k] = s[i];
   }
 #pragma unroll
-  for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(buf + (int64_t)i * NP + own), v[i]);
+  for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(buf + pop_at<S, Q>(own, i)), v[i]);
 }
 
-template <int LAT, bool DEV, typename S, int LEVEL, int V, int LX, bool NT>
+template <int LAT, bool DEV, typename S, int LEVEL, bool NT>
 __global__ __launch_bounds__(256) void k_collide_hrr(S* __restrict__ buf, const S* __restrict__ mac, const Geo g,
-                                                     const Tiling tl, const S om, const S tau, const S sig) {
-  collide_hrr_body<LAT, DEV, S, LEVEL, V, LX, NT>(buf, mac, g, tl, om, tau, sig, xcd_tile(tl));
+                                                     const Flat fl, const S om, const S tau, const S sig) {
+  collide_hrr_body<LAT, DEV, S, LEVEL, NT>(buf, mac, g, fl, om, tau, sig, xcd_chunk(fl));
 }
 
 // ---------------------------------------------------------------------------
@@ -408,7 +445,7 @@ __device__ inline void hist_capture_body(const S* __restrict__ src, double* __re
   for (int i = 0; i < Q; ++i) {
     const int xs = wrap(x - L::cx(i), nx), ys = wrap(y - L::cy(i), ny);
     const int zs = L::D == 3 ? wrap(z - L::cz(i), nz) : 0;
-    f[i] = full_pop<S, DEV, LAT>(src[(int64_t)i * g.Ncp + cpos(g, xs, ys, zs)], i);
+    f[i] = full_pop<S, DEV, LAT>(src[pop_at<S, Q>(cpos(g, xs, ys, zs), i)], i);
   }
   double rho, r0, u[3];
   N::moments(f, rho, r0, u);
@@ -568,7 +605,7 @@ __device__ inline void ring_body(const double* __restrict__ G, S* __restrict__ d
   fdecode(g, itf.rnode[r], x, y, z);
   const int64_t fi = fpos(g, x, y, z);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) dst[(int64_t)i * g.Nfp + fi] = store_pop<S, DEV, LAT>(f[i], i);
+  for (int i = 0; i < Q; ++i) dst[pop_at<S, Q>(fi, i)] = store_pop<S, DEV, LAT>(f[i], i);
 }
 template <int LAT, bool DEV, typename S, int MODEL>
 __global__ void k_ring(const double* __restrict__ G, S* __restrict__ dst, const Geo g, const Iface itf,
@@ -583,7 +620,7 @@ __device__ inline void pull_fine(const S* __restrict__ src, const Geo& g, int x,
   using L = Lattice<LAT>;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i)
-    f[i] = full_pop<S, DEV, LAT>(src[(int64_t)i * g.Nfp + fpos(g, x - L::cx(i), y - L::cy(i), z - L::cz(i))], i);
+    f[i] = full_pop<S, DEV, LAT>(src[pop_at<S, L::Q>(fpos(g, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i)], i);
 }
 
 // H-RR: fictitious propagation onto TN^f (Sec. 4.3, step e): u(TN, t+1) from
@@ -707,7 +744,7 @@ __device__ inline void coalesce_body(const S* __restrict__ src_f, S* __restrict_
   cdecode(g, itf.tnc[t3], cx, cy, cz);
   const int64_t ci = cpos(g, cx, cy, cz);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) dst_c[(int64_t)i * g.Ncp + ci] = store_pop<S, DEV, LAT>(f[i], i);
+  for (int i = 0; i < Q; ++i) dst_c[pop_at<S, Q>(ci, i)] = store_pop<S, DEV, LAT>(f[i], i);
 }
 
 template <int LAT, bool DEV, typename S, int MODEL>
@@ -717,7 +754,7 @@ __global__ __launch_bounds__(256) void k_coalesce(const S* __restrict__ src_f, S
 }
 
 // ---------------------------------------------------------------------------
-// State transfer kernels (logical x-fastest arrays <-> padded device planes).
+// State transfer kernels (logical x-fastest arrays <-> device storage).
 
 template <int LAT, bool DEV, typename S>
 __global__ void k_set_state(const double* __restrict__ rho, const double* __restrict__ u, S* __restrict__ dst,
@@ -728,21 +765,19 @@ __global__ void k_set_state(const double* __restrict__ rho, const double* __rest
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= NN) return;
   int x, y, z;
-  int64_t pos, NP;
+  int64_t pos;
   if (level == 0) {
     cdecode(g, k, x, y, z);
     pos = cpos(g, x, y, z);
-    NP = g.Ncp;
   } else {
     fdecode(g, k, x, y, z);
     pos = fpos(g, x, y, z);
-    NP = g.Nfp;
   }
   double uu[3] = {u[k], u[NN + k], L::D == 3 ? u[2 * NN + k] : 0.0};
   double f[L::Q];
   N::feq(rho[k], rho[k], uu, f);
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) dst[(int64_t)i * NP + pos] = store_pop<S, DEV, LAT>(f[i], i);
+  for (int i = 0; i < L::Q; ++i) dst[pop_at<S, L::Q>(pos, i)] = store_pop<S, DEV, LAT>(f[i], i);
 }
 
 // History at t = 0 from coarse fields rho, u (logical coarse arrays): all
@@ -798,24 +833,21 @@ __global__ void k_macros(const S* __restrict__ src, const S* __restrict__ fine, 
   if (k >= NN) return;
   int x, y, z;
   const S* p = src;
-  int64_t pos, NP;
+  int64_t pos;
   if (level == 0) {
     cdecode(g, k, x, y, z);
     pos = cpos(g, x, y, z);
-    NP = g.Ncp;
     if (g.has_fine && coarse_class(g, x, y, z) == CC_COVERED) {
       p = fine;
       pos = fpos(g, 2 * (x - g.a[0]), 2 * (y - g.a[1]), L::D == 3 ? 2 * (z - g.a[2]) : 0);
-      NP = g.Nfp;
     }
   } else {
     fdecode(g, k, x, y, z);
     pos = fpos(g, x, y, z);
-    NP = g.Nfp;
   }
   double f[L::Q], r, r0, uu[3];
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i) f[i] = full_pop<S, DEV, LAT>(p[(int64_t)i * NP + pos], i);
+  for (int i = 0; i < L::Q; ++i) f[i] = full_pop<S, DEV, LAT>(p[pop_at<S, L::Q>(pos, i)], i);
   N::moments(f, r, r0, uu);
   rho[k] = r;
 #pragma unroll
@@ -835,10 +867,10 @@ __global__ void k_pops_out(const S* __restrict__ src, double* __restrict__ f, co
   int64_t pos;
   if (level == 0) {
     cdecode(g, node, x, y, z);
-    pos = (int64_t)i * g.Ncp + cpos(g, x, y, z);
+    pos = pop_at<S, Lattice<LAT>::Q>(cpos(g, x, y, z), i);
   } else {
     fdecode(g, node, x, y, z);
-    pos = (int64_t)i * g.Nfp + fpos(g, x, y, z);
+    pos = pop_at<S, Lattice<LAT>::Q>(fpos(g, x, y, z), i);
   }
   f[k] = full_pop<S, DEV, LAT>(src[pos], i);
 }
@@ -854,10 +886,10 @@ __global__ void k_pops_in(const double* __restrict__ f, S* __restrict__ dst, con
   int64_t pos;
   if (level == 0) {
     cdecode(g, node, x, y, z);
-    pos = (int64_t)i * g.Ncp + cpos(g, x, y, z);
+    pos = pop_at<S, Lattice<LAT>::Q>(cpos(g, x, y, z), i);
   } else {
     fdecode(g, node, x, y, z);
-    pos = (int64_t)i * g.Nfp + fpos(g, x, y, z);
+    pos = pop_at<S, Lattice<LAT>::Q>(fpos(g, x, y, z), i);
   }
   dst[pos] = store_pop<S, DEV, LAT>(f[k], i);
 }
@@ -874,22 +906,20 @@ __global__ __launch_bounds__(256) void k_totals(const S* __restrict__ src, doubl
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   if (k < NN) {
     int x, y, z;
-    int64_t pos, NP;
+    int64_t pos;
     bool use = true;
     if (level == 0) {
       cdecode(g, k, x, y, z);
       pos = cpos(g, x, y, z);
-      NP = g.Ncp;
       use = !g.has_fine || coarse_class(g, x, y, z) != CC_COVERED;
     } else {
       fdecode(g, k, x, y, z);
       pos = fpos(g, x, y, z);
-      NP = g.Nfp;
     }
     if (use) {
 #pragma unroll
       for (int i = 0; i < L::Q; ++i) {
-        const double f = full_pop<S, DEV, LAT>(src[(int64_t)i * NP + pos], i);
+        const double f = full_pop<S, DEV, LAT>(src[pop_at<S, L::Q>(pos, i)], i);
         v[0] += f;
         v[1] += L::cx(i) * f;
         v[2] += L::cy(i) * f;

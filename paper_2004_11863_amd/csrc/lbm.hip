@@ -190,16 +190,14 @@ struct Grid final : GridBase {
   static constexpr int Q = L::Q, D = L::D;
   // history fields per node: the largest layout over the collision models
   static constexpr int HN = HF<LAT, M_BGK>::N > HF<LAT, M_HRR>::N ? HF<LAT, M_BGK>::N : HF<LAT, M_HRR>::N;
-  static constexpr bool NT = true;  // non-temporal stores of the streamed planes
-  // Bulk-kernel variants (nodes per lane V, lanes along x LX; work groups are
-  // LX x 256/LX).  FP32: 16-byte (V = 4) or 8-byte (V = 2) accesses; FP64:
-  // 16-byte (V = 2).
-  static constexpr int NVAR = DEV ? 5 : 3;
-  static constexpr int kV[5] = {DEV ? 4 : 2, DEV ? 4 : 2, DEV ? 4 : 2, 2, 2};
-  static constexpr int kLX[5] = {64, 32, 16, 64, 32};
-  // chosen variant per role: 0 coarse stream, 1 fine stream, 2 coarse H-RR
-  // collision, 3 fine H-RR collision
-  int var[4] = {0, 0, 0, 0};
+  static constexpr bool NT = true;  // non-temporal stores of the streamed populations
+  static constexpr int V = VecOf<S>::V;
+  // Bulk-kernel launch variants: residency caps through dynamic LDS
+  // (kVarLds); the chosen variant per role: 0 coarse stream, 1 fine stream,
+  // 2 coarse H-RR collision, 3 fine H-RR collision.
+  static constexpr int NVAR = kNVar;
+  static constexpr int kDefaultVar = 2;
+  int var[4] = {kDefaultVar, kDefaultVar, kDefaultVar, kDefaultVar};
 
   DevBuf cbuf[2], fbuf[2], mac_c, mac_f, hist[3], G, tmp_rho, tmp_u, tmp_f, part, tot;
   DevBuf d_hnode, d_rnode, d_rnp, d_rpt, d_tnf, d_tnc;
@@ -208,14 +206,17 @@ struct Grid final : GridBase {
   Iface itf{};
   double tau_c = 0, tau_f = 0, sig = 0;
 
-  // padded plane storage plus slack for the one-element overreach of the
-  // x-shifted vector loads at the very end of a buffer
+  // Velocity planes (H-RR): padded planes plus 64 spare elements.
   static size_t plane_bytes(int64_t NP, int nplanes) { return sizeof(S) * ((size_t)NP * nplanes + 64); }
+  // Populations: whole storage blocks up to and including position NP (the
+  // last x-vector of a fine row, which holds the ring column and is
+  // overwritten afterwards, pulls one position past the end of its row).
+  static size_t pop_bytes(int64_t NP) { return sizeof(S) * (size_t)pop_elems<S>(NP, Q); }
 
   void init() override {
-    for (int p = 0; p < 2; ++p) cbuf[p].alloc(plane_bytes(g.Ncp, Q));
+    for (int p = 0; p < 2; ++p) cbuf[p].alloc(pop_bytes(g.Ncp));
     if (g.has_fine)
-      for (int p = 0; p < 2; ++p) fbuf[p].alloc(plane_bytes(g.Nfp, Q));
+      for (int p = 0; p < 2; ++p) fbuf[p].alloc(pop_bytes(g.Nfp));
     if (desc.collision == LBM_HRR) {
       mac_c.alloc(plane_bytes(g.Ncp, 1 + D));
       if (g.has_fine) mac_f.alloc(plane_bytes(g.Nfp, 1 + D));
@@ -223,7 +224,6 @@ struct Grid final : GridBase {
     tau_c = desc.tau_coarse;
     tau_f = 2.0 * tau_c - 0.5;
     sig = desc.sigma;
-    for (int r = 0; r < 4; ++r) var[r] = default_variant(r & 1);
     if (g.has_fine) {
       const size_t NH = tabs.hnode.size();
       for (int s = 0; s < 3; ++s) hist[s].alloc(sizeof(double) * HN * NH);
@@ -262,83 +262,31 @@ struct Grid final : GridBase {
 
   static unsigned blocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-  Tiling tiling(int level, int v) const {
-    const int V = kV[v], LX = kLX[v];
-    if (level == 0) return make_tiling(g.n[0], g.n[1], g.n[2], 0, V, LX, 256 / LX);
-    return make_tiling(g.nf[0], g.nf[1], g.nf[2], 1, V, LX, 256 / LX);
-  }
-  // Variant with the fewest idle lanes along x (ties: the earlier one).
-  int default_variant(int level) const {
-    if (level == 1 && !g.has_fine) return 0;
-    int best = 0;
-    int64_t bw = -1;
-    for (int v = 0; v < NVAR; ++v) {
-      if (kV[v] != kV[0]) continue;
-      const Tiling t = tiling(level, v);
-      const int64_t waste = (int64_t)t.ntx * kLX[v] - t.nv;
-      if (bw < 0 || waste < bw) {
-        bw = waste;
-        best = v;
-      }
-    }
-    return best;
+  Flat flat(int level) const {
+    if (level == 0) return make_flat(g.n[0], g.n[1], g.n[2], V, false, D);
+    return make_flat(g.nf[0], g.nf[1], g.nf[2], V, true, D);
   }
 
   S* cur_c() { return cbuf[cpar].as<S>(); }
   S* fineA() { return fbuf[0].as<S>(); }
   S* fineB() { return fbuf[1].as<S>(); }
 
-  template <int MODEL, int LEVEL, int V, int LX>
-  void go_stream(const S* src, S* dst, S* mac, double tau, hipStream_t s, int v) {
-    const Tiling t = tiling(LEVEL, v);
-    const S om = (S)(1.0 - 1.0 / tau);
-    hipLaunchKernelGGL((k_stream<LAT, DEV, S, MODEL, LEVEL, V, LX, NT>), dim3((unsigned)(t.per_xcd * kXCD)),
-                       dim3(256), 0, s, src, dst, mac, g, t, om);
-  }
   template <int MODEL, int LEVEL>
   void launch_stream(const S* src, S* dst, S* mac, double tau, hipStream_t s, int v = -1) {
     if (v < 0) v = var[LEVEL];
-    if constexpr (DEV) {
-      switch (v) {
-        case 0: go_stream<MODEL, LEVEL, 4, 64>(src, dst, mac, tau, s, v); break;
-        case 1: go_stream<MODEL, LEVEL, 4, 32>(src, dst, mac, tau, s, v); break;
-        case 2: go_stream<MODEL, LEVEL, 4, 16>(src, dst, mac, tau, s, v); break;
-        case 3: go_stream<MODEL, LEVEL, 2, 64>(src, dst, mac, tau, s, v); break;
-        default: go_stream<MODEL, LEVEL, 2, 32>(src, dst, mac, tau, s, 4); break;
-      }
-    } else {
-      switch (v) {
-        case 0: go_stream<MODEL, LEVEL, 2, 64>(src, dst, mac, tau, s, v); break;
-        case 1: go_stream<MODEL, LEVEL, 2, 32>(src, dst, mac, tau, s, v); break;
-        default: go_stream<MODEL, LEVEL, 2, 16>(src, dst, mac, tau, s, 2); break;
-      }
-    }
+    const Flat f = flat(LEVEL);
+    if (f.nchunks == 0) return;
+    hipLaunchKernelGGL((k_stream<LAT, DEV, S, MODEL, LEVEL, NT>), dim3((unsigned)(f.per_xcd * kXCD)), dim3(256),
+                       (unsigned)kVarLds[v], s, src, dst, mac, g, f, (S)(1.0 - 1.0 / tau));
   }
 
-  template <int LEVEL, int V, int LX>
-  void go_collide(S* buf, const S* mac, double tau, hipStream_t s, int v) {
-    const Tiling t = tiling(LEVEL, v);
-    hipLaunchKernelGGL((k_collide_hrr<LAT, DEV, S, LEVEL, V, LX, NT>), dim3((unsigned)(t.per_xcd * kXCD)), dim3(256),
-                       0, s, buf, mac, g, t, (S)(1.0 - 1.0 / tau), (S)tau, (S)sig);
-  }
   template <int LEVEL>
   void launch_collide_hrr(S* buf, const S* mac, double tau, hipStream_t s, int v = -1) {
     if (v < 0) v = var[2 + LEVEL];
-    if constexpr (DEV) {
-      switch (v) {
-        case 0: go_collide<LEVEL, 4, 64>(buf, mac, tau, s, v); break;
-        case 1: go_collide<LEVEL, 4, 32>(buf, mac, tau, s, v); break;
-        case 2: go_collide<LEVEL, 4, 16>(buf, mac, tau, s, v); break;
-        case 3: go_collide<LEVEL, 2, 64>(buf, mac, tau, s, v); break;
-        default: go_collide<LEVEL, 2, 32>(buf, mac, tau, s, 4); break;
-      }
-    } else {
-      switch (v) {
-        case 0: go_collide<LEVEL, 2, 64>(buf, mac, tau, s, v); break;
-        case 1: go_collide<LEVEL, 2, 32>(buf, mac, tau, s, v); break;
-        default: go_collide<LEVEL, 2, 16>(buf, mac, tau, s, 2); break;
-      }
-    }
+    const Flat f = flat(LEVEL);
+    if (f.nchunks == 0) return;
+    hipLaunchKernelGGL((k_collide_hrr<LAT, DEV, S, LEVEL, NT>), dim3((unsigned)(f.per_xcd * kXCD)), dim3(256),
+                       (unsigned)kVarLds[v], s, buf, mac, g, f, (S)(1.0 - 1.0 / tau), (S)tau, (S)sig);
   }
 
   void fine_stream_timed(int model, const S* src, S* dst, hipStream_t s) {
@@ -693,8 +641,10 @@ struct BatchBase {
 static int64_t grid_footprint(const lbm_grid_desc& d, const Geo& g) {
   const int Q = d.lattice == LBM_D2Q9 ? 9 : 19;
   const int D = g.D;
-  const int64_t sb = d.precision == LBM_FP32_DEV ? 4 : 8;
-  int64_t bytes = 2 * sb * (Q * g.Ncp + 64) + (g.has_fine ? 2 * sb * (Q * g.Nfp + 64) : 0);
+  const bool f32 = d.precision == LBM_FP32_DEV;
+  const int64_t sb = f32 ? 4 : 8;
+  auto pops = [&](int64_t NP) { return sb * (f32 ? pop_elems<float>(NP, Q) : pop_elems<double>(NP, Q)); };
+  int64_t bytes = 2 * pops(g.Ncp) + (g.has_fine ? 2 * pops(g.Nfp) : 0);
   if (d.collision == LBM_HRR) bytes += sb * (1 + D) * (g.Ncp + g.Nfp + 128);
   if (g.has_fine) {
     int64_t nh = 0, ring_out = 1, ring_in = 1, tn_out = 1, tn_in = 1;
@@ -722,7 +672,8 @@ struct Batch final : BatchBase {
   using S = typename std::conditional<DEV, float, double>::type;
   static constexpr int Q = L::Q, D = L::D;
   static constexpr bool NT = true;
-  static constexpr int NVAR = Grid<LAT, PREC>::NVAR;
+  static constexpr int NVAR = kNVar;
+  static constexpr int V = VecOf<S>::V;
   static constexpr int HN = Grid<LAT, PREC>::HN;
   static constexpr int BULK_GRID = kXCD * 512;  // work groups of the persistent launches
   static constexpr int IF_GRID = kXCD * 512;
@@ -742,7 +693,7 @@ struct Batch final : BatchBase {
   size_t item_cap[W_KINDS] = {0, 0, 0, 0, 0, 0, 0};
   int counts[W_KINDS] = {0, 0, 0, 0, 0, 0, 0};
   DevBuf tmp_rho, tmp_u, tmp_f;
-  int var_c = 0, var_f = 0;
+  int var_c = Grid<LAT, PREC>::kDefaultVar, var_f = Grid<LAT, PREC>::kDefaultVar;
   bool use_graph = true, graph_ok = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -778,10 +729,9 @@ struct Batch final : BatchBase {
     drop_graph();  // the graph holds the old list addresses
   }
 
-  Tiling tiling(const Geo& g, int level, int v) const {
-    const int V = Grid<LAT, PREC>::kV[v], LX = Grid<LAT, PREC>::kLX[v];
-    if (level == 0) return make_tiling(g.n[0], g.n[1], g.n[2], 0, V, LX, 256 / LX);
-    return make_tiling(g.nf[0], g.nf[1], g.nf[2], 1, V, LX, 256 / LX);
+  static Flat flat(const Geo& g, int level) {
+    if (level == 0) return make_flat(g.n[0], g.n[1], g.n[2], V, false, D);
+    return make_flat(g.nf[0], g.nf[1], g.nf[2], V, true, D);
   }
 
   void upload_inst(int slot) {
@@ -800,9 +750,9 @@ struct Batch final : BatchBase {
     for (int sl = 0; sl < capacity; ++sl) {
       if (!slots[(size_t)sl]) continue;
       const InstDev& I = hinst[(size_t)sl];
-      for (int t = 0; t < I.tc.ntiles; ++t) lists[W_COARSE].push_back({sl, t});
+      for (int t = 0; t < I.fc.nchunks; ++t) lists[W_COARSE].push_back({sl, t});
       if (!I.g.has_fine) continue;
-      for (int t = 0; t < I.tf.ntiles; ++t) lists[W_FINE].push_back({sl, t});
+      for (int t = 0; t < I.ff.nchunks; ++t) lists[W_FINE].push_back({sl, t});
       const int64_t nh = I.itf.NH, nr = I.itf.NR, nt = I.itf.NT;
       for (int64_t c = 0; c < (nh + 63) / 64; ++c) lists[W_HIST].push_back({sl, (int)c});
       for (int64_t c = 0; c < (nh * hfields + 63) / 64; ++c) lists[W_HTIME].push_back({sl, (int)c});
@@ -838,7 +788,7 @@ struct Batch final : BatchBase {
     build_tables(g, in->tabs);
     const size_t sb = sizeof(S);
     for (int p = 0; p < 2; ++p) {
-      in->cbuf[p].alloc(sb * ((size_t)g.Ncp * Q + 64));
+      in->cbuf[p].alloc(sb * (size_t)pop_elems<S>(g.Ncp, Q));
       HIPCHK(hipMemset(in->cbuf[p].p, 0, in->cbuf[p].bytes));
     }
     if (collision == LBM_HRR) {
@@ -847,7 +797,7 @@ struct Batch final : BatchBase {
     }
     if (g.has_fine) {
       for (int p = 0; p < 2; ++p) {
-        in->fbuf[p].alloc(sb * ((size_t)g.Nfp * Q + 64));
+        in->fbuf[p].alloc(sb * (size_t)pop_elems<S>(g.Nfp, Q));
         HIPCHK(hipMemset(in->fbuf[p].p, 0, in->fbuf[p].bytes));
       }
       if (collision == LBM_HRR) {
@@ -883,8 +833,8 @@ struct Batch final : BatchBase {
     InstDev I{};
     I.g = g;
     I.itf = in->itf;
-    I.tc = tiling(g, 0, var_c);
-    if (g.has_fine) I.tf = tiling(g, 1, var_f);
+    I.fc = flat(g, 0);
+    if (g.has_fine) I.ff = flat(g, 1);
     I.cbuf[0] = in->cbuf[0].p;
     I.cbuf[1] = in->cbuf[1].p;
     I.fbuf[0] = in->fbuf[0].p;
@@ -1004,51 +954,16 @@ struct Batch final : BatchBase {
   const Work* items(int k) const { return d_items[k].template as<Work>(); }
   const int* cnt(int k) const { return d_counts.template as<int>() + k; }
 
-  template <int MODEL, int LEVEL, int SUB, int V, int LX>
-  void go_stream(hipStream_t s) {
-    hipLaunchKernelGGL((kb_stream<LAT, DEV, S, MODEL, LEVEL, SUB, V, LX, NT>), dim3(BULK_GRID), dim3(256), 0, s, di(),
-                       items(LEVEL == 0 ? W_COARSE : W_FINE), cnt(LEVEL == 0 ? W_COARSE : W_FINE));
-  }
   template <int MODEL, int LEVEL, int SUB>
   void phase_stream(hipStream_t s, int v) {
-    if constexpr (DEV) {
-      switch (v) {
-        case 0: go_stream<MODEL, LEVEL, SUB, 4, 64>(s); break;
-        case 1: go_stream<MODEL, LEVEL, SUB, 4, 32>(s); break;
-        case 2: go_stream<MODEL, LEVEL, SUB, 4, 16>(s); break;
-        case 3: go_stream<MODEL, LEVEL, SUB, 2, 64>(s); break;
-        default: go_stream<MODEL, LEVEL, SUB, 2, 32>(s); break;
-      }
-    } else {
-      switch (v) {
-        case 0: go_stream<MODEL, LEVEL, SUB, 2, 64>(s); break;
-        case 1: go_stream<MODEL, LEVEL, SUB, 2, 32>(s); break;
-        default: go_stream<MODEL, LEVEL, SUB, 2, 16>(s); break;
-      }
-    }
-  }
-  template <int LEVEL, int SUB, int V, int LX>
-  void go_collide(hipStream_t s) {
-    hipLaunchKernelGGL((kb_collide<LAT, DEV, S, LEVEL, SUB, V, LX, NT>), dim3(BULK_GRID), dim3(256), 0, s, di(),
-                       items(LEVEL == 0 ? W_COARSE : W_FINE), cnt(LEVEL == 0 ? W_COARSE : W_FINE));
+    hipLaunchKernelGGL((kb_stream<LAT, DEV, S, MODEL, LEVEL, SUB, NT>), dim3(BULK_GRID), dim3(256),
+                       (unsigned)kVarLds[v], s, di(), items(LEVEL == 0 ? W_COARSE : W_FINE),
+                       cnt(LEVEL == 0 ? W_COARSE : W_FINE));
   }
   template <int LEVEL, int SUB>
   void phase_collide(hipStream_t s, int v) {
-    if constexpr (DEV) {
-      switch (v) {
-        case 0: go_collide<LEVEL, SUB, 4, 64>(s); break;
-        case 1: go_collide<LEVEL, SUB, 4, 32>(s); break;
-        case 2: go_collide<LEVEL, SUB, 4, 16>(s); break;
-        case 3: go_collide<LEVEL, SUB, 2, 64>(s); break;
-        default: go_collide<LEVEL, SUB, 2, 32>(s); break;
-      }
-    } else {
-      switch (v) {
-        case 0: go_collide<LEVEL, SUB, 2, 64>(s); break;
-        case 1: go_collide<LEVEL, SUB, 2, 32>(s); break;
-        default: go_collide<LEVEL, SUB, 2, 16>(s); break;
-      }
-    }
+    hipLaunchKernelGGL((kb_collide<LAT, DEV, S, LEVEL, SUB, NT>), dim3(BULK_GRID), dim3(256), (unsigned)kVarLds[v], s,
+                       di(), items(LEVEL == 0 ? W_COARSE : W_FINE), cnt(LEVEL == 0 ? W_COARSE : W_FINE));
   }
 
   template <int MODEL>
@@ -1135,16 +1050,6 @@ struct Batch final : BatchBase {
       float best = -1.f;
       int bv = 0;
       for (int v = 0; v < NVAR; ++v) {
-        if (level == 0) var_c = v;
-        else var_f = v;
-        for (int sl = 0; sl < capacity; ++sl)
-          if (slots[(size_t)sl]) {
-            fetch_inst(sl);
-            if (level == 0) hinst[(size_t)sl].tc = tiling(hinst[(size_t)sl].g, 0, v);
-            else if (hinst[(size_t)sl].g.has_fine) hinst[(size_t)sl].tf = tiling(hinst[(size_t)sl].g, 1, v);
-            upload_inst(sl);
-          }
-        rebuild_lists();
         auto run = [&] {
           if (collision == LBM_BGK) {
             if (level == 0) phase_stream<M_BGK, 0, 0>(stream, v);
@@ -1171,14 +1076,6 @@ struct Batch final : BatchBase {
       }
       if (level == 0) var_c = bv;
       else var_f = bv;
-      for (int sl = 0; sl < capacity; ++sl)
-        if (slots[(size_t)sl]) {
-          fetch_inst(sl);
-          if (level == 0) hinst[(size_t)sl].tc = tiling(hinst[(size_t)sl].g, 0, bv);
-          else if (hinst[(size_t)sl].g.has_fine) hinst[(size_t)sl].tf = tiling(hinst[(size_t)sl].g, 1, bv);
-          upload_inst(sl);
-        }
-      rebuild_lists();
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -28,6 +28,7 @@ LBM_FP64, LBM_FP32_DEV = 0, 1
 LBM_HOST, LBM_DEVICE = 0, 1
 LBM_C_MIDDLE, LBM_C_TF, LBM_C_TN, LBM_C_COVERED = 0, 1, 2, 3
 LBM_F_MIDDLE, LBM_F_TF, LBM_F_IE, LBM_F_IE_FACE, LBM_F_TN = 0, 1, 2, 3, 4
+LBM_N_VARIANTS = 4
 
 EXPORTS = (
     "lbm_create_grid", "lbm_destroy", "lbm_set_state", "lbm_step", "lbm_get_macros",

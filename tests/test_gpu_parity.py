@@ -150,7 +150,7 @@ def test_every_kernel_variant_gives_identical_results(prec, model):
     leaves the state untouched."""
     lbm = _lbm()
     p = lbm.LBM_FP32_DEV if prec == "fp32" else lbm.LBM_FP64
-    nvar = 5 if prec == "fp32" else 3
+    nvar = lbm.LBM_N_VARIANTS
     wl = I.config1(4)
     ref = None
     live = None
@@ -186,7 +186,7 @@ def test_variants_on_ragged_3d_and_2d(D):
         geom = _geom(3, (27, 21, 22), (4, 5, 3), (19, 14, 17))
     wl = I.Workload(geom=geom, U=(0.04, 0.01, 0.0), pulses=[I.Pulse(center=tuple(x / 2 for x in geom.n[:D]), A=1e-3, R=2.0)])
     ref = None
-    for v in range(3):
+    for v in range(lbm.LBM_N_VARIANTS):
         gpu, orc, levels = make_pair(wl, "RR", lbm.LBM_FP64, with_oracle=(v == 0))
         gpu.set_variants([v, v, v, v])
         gpu.step(9)
