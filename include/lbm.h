@@ -149,11 +149,12 @@ int lbm_interface_tables(lbm_handle h, int64_t* hist_nodes, int64_t* ring_nodes,
 /* Lattice updates per coarse step: evolving coarse nodes + 2 x fine nodes. */
 int lbm_updates_per_step(lbm_handle h, int64_t* updates);
 
-/* Per-launch timing of the fine-level stream-collide kernel (the dominant
- * kernel): when enabled, lbm_step records HIP events around each of its
- * launches on the launch stream; lbm_kernel_time returns the number of
- * timed launches, their mean duration in ms and the nodes one launch
- * updates.  Synchronous. */
+/* Per-launch timing of the fine-level pull-stream + collide kernel (the
+ * dominant kernel; for H-RR its second pass, which pulls again and collides
+ * with the strain rate of the velocities the first pass wrote): when
+ * enabled, lbm_step records HIP events around each of its launches on the
+ * launch stream; lbm_kernel_time returns the number of timed launches, their
+ * mean duration in ms and the nodes one launch updates.  Synchronous. */
 int lbm_profile_enable(lbm_handle h, int on);
 int lbm_kernel_time(lbm_handle h, int64_t* launches, double* mean_ms, int64_t* nodes_per_launch);
 

@@ -92,8 +92,8 @@ __global__ __launch_bounds__(256) void kb_stream(const InstDev* __restrict__ ins
   }
 }
 
-// H-RR collision in place.  LEVEL 0: the coarse buffer being written this
-// step; LEVEL 1: fine buffer B (SUB 0) or A (SUB 1).
+// H-RR pull-stream and collision.  LEVEL 0: coarse current -> other buffer;
+// LEVEL 1: fine A -> B (SUB 0) or B -> A (SUB 1).
 template <int LAT, bool DEV, typename S, int LEVEL, int SUB, bool NT>
 __global__ __launch_bounds__(256) void kb_collide(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                                   const int* __restrict__ count) {
@@ -103,10 +103,10 @@ __global__ __launch_bounds__(256) void kb_collide(const InstDev* __restrict__ in
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
     if (LEVEL == 0) {
-      collide_hrr_body<LAT, DEV, S, 0, NT>((S*)I.cbuf[I.cpar ^ 1], (const S*)I.mac_c, I.g, I.fc,
-                                           (S)(1.0 - 1.0 / I.tau_c), (S)I.tau_c, (S)I.sig, w.idx);
+      collide_hrr_body<LAT, DEV, S, 0, NT>((const S*)I.cbuf[I.cpar], (S*)I.cbuf[I.cpar ^ 1], (const S*)I.mac_c, I.g,
+                                           I.fc, (S)(1.0 - 1.0 / I.tau_c), (S)I.tau_c, (S)I.sig, w.idx);
     } else {
-      collide_hrr_body<LAT, DEV, S, 1, NT>((S*)I.fbuf[SUB ^ 1], (const S*)I.mac_f, I.g, I.ff,
+      collide_hrr_body<LAT, DEV, S, 1, NT>((const S*)I.fbuf[SUB], (S*)I.fbuf[SUB ^ 1], (const S*)I.mac_f, I.g, I.ff,
                                            (S)(1.0 - 1.0 / I.tau_f), (S)I.tau_f, (S)I.sig, w.idx);
     }
   }

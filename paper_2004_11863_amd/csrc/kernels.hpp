@@ -35,9 +35,10 @@ constexpr int kIfaceBlock = 64;
 constexpr int kNVar = 4;
 constexpr int kVarLds[kNVar] = {0, 53 * 1024, 80 * 1024, 160 * 1024};
 
-// Model codes: BGK and RR collide in the streaming kernel; the split H-RR
-// path streams first (kernel writes the pre-collision state and rho, u) and
-// collides in a second kernel that reads neighbouring velocities.
+// Model codes: BGK and RR collide in the streaming kernel.  H-RR needs the
+// velocities of the neighbours at the same time level: a first pass pulls
+// and writes only rho, u; a second pass pulls again, takes the strain rate
+// from the neighbouring velocities and collides.
 enum Model : int { M_BGK = 0, M_RR = 1, M_HRR = 2 };
 
 // 16-byte vectors: "a" is the aligned type, "u" the same vector with element
@@ -183,8 +184,8 @@ __device__ inline bool skip_vec(const Geo& g, int x0, int V, int y, int z, int n
 // ---------------------------------------------------------------------------
 // Bulk pull-stream (+ collide) of one level.
 //   LEVEL 0: coarse, periodic.  LEVEL 1: fine patch.
-// MODEL BGK/RR: dst = collide(pull(src)).  MODEL HRR: dst = pull(src) and
-// mac = (rho, u) of the pulled state (padded planes of the level).
+// MODEL BGK/RR: dst = collide(pull(src)).  MODEL HRR: only mac = (rho, u) of
+// the pulled state (padded planes of the level); dst is not touched.
 // Every node of a processed vector is written, including coarse TN/covered
 // nodes and the fine ring column x = nx - 1: the schedule overwrites TN and
 // ring nodes afterwards and never reads covered ones.
@@ -231,6 +232,7 @@ __device__ inline void stream_body(const S* __restrict__ src, S* __restrict__ ds
     vstore<NT>((VA*)(mac + NP + own), ux);
     vstore<NT>((VA*)(mac + 2 * NP + own), uy);
     if (L::D == 3) vstore<NT>((VA*)(mac + 3 * NP + own), uz);
+    return;
   } else {
 #pragma unroll
     for (int k = 0; k < V; ++k) {
@@ -252,13 +254,15 @@ __global__ __launch_bounds__(256) void k_stream(const S* __restrict__ src, S* __
   stream_body<LAT, DEV, S, MODEL, LEVEL, NT>(src, dst, mac, g, fl, om, xcd_chunk(fl));
 }
 
-// H-RR collision in place on a level, with the strain rate from centred
-// differences (second order, level lattice units) of the velocity planes of
-// mac (Sec. 3.3).  Processes whole vectors like k_stream; the coarse pass runs
-// before the fine-to-coarse transfer overwrites TN nodes.
+// H-RR pull-stream and collision of a level: dst = collide(pull(src)) with
+// the strain rate from centred differences (second order, level lattice
+// units) of the velocity planes of mac (Sec. 3.3), which the first pass and
+// the interface kernels filled.  Processes whole vectors like k_stream; the
+// coarse pass runs before the fine-to-coarse transfer overwrites TN nodes.
 template <int LAT, bool DEV, typename S, int LEVEL, bool NT>
-__device__ inline void collide_hrr_body(S* __restrict__ buf, const S* __restrict__ mac, const Geo& g, const Flat& fl,
-                                        const S om, const S tau, const S sig, int chunk) {
+__device__ inline void collide_hrr_body(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ mac,
+                                        const Geo& g, const Flat& fl, const S om, const S tau, const S sig,
+                                        int chunk) {
   using L = Lattice<LAT>;
   using N = Node<LAT, DEV, S>;
   constexpr int V = VecOf<S>::V;
@@ -302,7 +306,14 @@ __device__ inline void collide_hrr_body(S* __restrict__ buf, const S* __restrict
   }
   VA v[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) v[i] = *(const VA*)(buf + pop_at<S, Q>(own, i));
+  for (int i = 0; i < Q; ++i) {
+    int ys = y - L::cy(i), zs = z - L::cz(i);
+    if (LEVEL == 0) {
+      ys = wrap(ys, ny);
+      if (D == 3) zs = wrap(zs, nz);
+    }
+    v[i] = load_pull<S, Q, V, LEVEL>(src, P * ((int64_t)ys + (int64_t)ny * zs) + xo, x0, L::cx(i), nx, i);
+  }
 #pragma unroll
   for (int k = 0; k < V; ++k) {
     Sym<S> Sr;
@@ -324,13 +335,14 @@ __device__ inline void collide_hrr_body(S* __restrict__ buf, const S* __restrict
     for (int i = 0; i < Q; ++i) v[i][k] = s[i];
   }
 #pragma unroll
-  for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(buf + pop_at<S, Q>(own, i)), v[i]);
+  for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + pop_at<S, Q>(own, i)), v[i]);
 }
 
 template <int LAT, bool DEV, typename S, int LEVEL, bool NT>
-__global__ __launch_bounds__(256) void k_collide_hrr(S* __restrict__ buf, const S* __restrict__ mac, const Geo g,
-                                                     const Flat fl, const S om, const S tau, const S sig) {
-  collide_hrr_body<LAT, DEV, S, LEVEL, NT>(buf, mac, g, fl, om, tau, sig, xcd_chunk(fl));
+__global__ __launch_bounds__(256) void k_collide_hrr(const S* __restrict__ src, S* __restrict__ dst,
+                                                     const S* __restrict__ mac, const Geo g, const Flat fl, const S om,
+                                                     const S tau, const S sig) {
+  collide_hrr_body<LAT, DEV, S, LEVEL, NT>(src, dst, mac, g, fl, om, tau, sig, xcd_chunk(fl));
 }
 
 // ---------------------------------------------------------------------------

@@ -281,28 +281,35 @@ struct Grid final : GridBase {
   }
 
   template <int LEVEL>
-  void launch_collide_hrr(S* buf, const S* mac, double tau, hipStream_t s, int v = -1) {
+  void launch_collide_hrr(const S* src, S* dst, const S* mac, double tau, hipStream_t s, int v = -1) {
     if (v < 0) v = var[2 + LEVEL];
     const Flat f = flat(LEVEL);
     if (f.nchunks == 0) return;
     hipLaunchKernelGGL((k_collide_hrr<LAT, DEV, S, LEVEL, NT>), dim3((unsigned)(f.per_xcd * kXCD)), dim3(256),
-                       (unsigned)kVarLds[v], s, buf, mac, g, f, (S)(1.0 - 1.0 / tau), (S)tau, (S)sig);
+                       (unsigned)kVarLds[v], s, src, dst, mac, g, f, (S)(1.0 - 1.0 / tau), (S)tau, (S)sig);
   }
 
-  void fine_stream_timed(int model, const S* src, S* dst, hipStream_t s) {
+  // Runs fn (one launch) between HIP events on s when profiling is on.
+  template <typename Fn>
+  void timed(hipStream_t s, Fn&& fn) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (profile) {
       HIPCHK(hipEventCreate(&e0));
       HIPCHK(hipEventCreate(&e1));
       HIPCHK(hipEventRecord(e0, s));
     }
-    if (model == M_BGK) launch_stream<M_BGK, 1>(src, dst, nullptr, tau_f, s);
-    else if (model == M_RR) launch_stream<M_RR, 1>(src, dst, nullptr, tau_f, s);
-    else launch_stream<M_HRR, 1>(src, dst, mac_f.as<S>(), tau_f, s);
+    fn();
     if (profile) {
       HIPCHK(hipEventRecord(e1, s));
       events.emplace_back(e0, e1);
     }
+  }
+  // Fine-level pull-stream + collide (BGK, RR): the timed kernel.
+  void fine_stream_timed(int model, const S* src, S* dst, hipStream_t s) {
+    timed(s, [&] {
+      if (model == M_BGK) launch_stream<M_BGK, 1>(src, dst, nullptr, tau_f, s);
+      else launch_stream<M_RR, 1>(src, dst, nullptr, tau_f, s);
+    });
   }
 
   // Autotuner: times every bulk-kernel variant of each role on this grid
@@ -322,9 +329,9 @@ struct Grid final : GridBase {
       else if (model == M_RR) launch_stream<M_RR, 1>(fineA(), fineB(), nullptr, tau_f, s, v);
       else launch_stream<M_HRR, 1>(fineA(), fineB(), mac_f.as<S>(), tau_f, s, v);
     } else if (role == 2) {
-      launch_collide_hrr<0>(c_oth, mac_c.as<S>(), tau_c, s, v);
+      launch_collide_hrr<0>(c_cur, c_oth, mac_c.as<S>(), tau_c, s, v);
     } else {
-      launch_collide_hrr<1>(fineB(), mac_f.as<S>(), tau_f, s, v);
+      launch_collide_hrr<1>(fineA(), fineB(), mac_f.as<S>(), tau_f, s, v);
     }
   }
 
@@ -373,7 +380,7 @@ struct Grid final : GridBase {
     else if (model == M_RR) launch_stream<M_RR, 0>(src, dst, nullptr, tau_c, s);
     else {
       launch_stream<M_HRR, 0>(src, dst, mac_c.as<S>(), tau_c, s);
-      launch_collide_hrr<0>(dst, mac_c.as<S>(), tau_c, s);
+      launch_collide_hrr<0>(src, dst, mac_c.as<S>(), tau_c, s);
     }
     cpar ^= 1;
   }
@@ -413,22 +420,24 @@ struct Grid final : GridBase {
     } else {
       S* mc = mac_c.as<S>();
       S* mf = mac_f.as<S>();
+      // velocity passes (rho, u of the pulled states), ring rho, u, then
+      // pull-stream + collide with the strain rate of those velocities
       launch_stream<M_HRR, 0>(csrc, cdst, mc, tau_c, s);
-      fine_stream_timed(M_HRR, fA, fB, s);
+      launch_stream<M_HRR, 1>(fA, fB, mf, tau_f, s);
       hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, c0, c1, c2, mf, g, itf);
-      launch_collide_hrr<1>(fB, mf, tau_f, s);
+      timed(s, [&] { launch_collide_hrr<1>(fA, fB, mf, tau_f, s); });
       hipLaunchKernelGGL((k_fict<LAT, DEV, S, S>), dim3(bt), dim3(IB), 0, s, fB, mc, g, itf);
       hipLaunchKernelGGL((k_hist_strain<LAT, S>), dim3(bh), dim3(IB), 0, s, mc, Hp, g, itf);
       hipLaunchKernelGGL(k_hist_time, dim3(bg), dim3(256), 0, s, Hm, H0, Hp, G.as<double>(), NH * F::N, c0, c1, c2);
       hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR>), dim3(br), dim3(IB), 0, s, G.as<double>(), fB, g, itf, kf, omf,
                          tau_f, sig);
-      fine_stream_timed(M_HRR, fB, fA, s);
+      launch_stream<M_HRR, 1>(fB, fA, mf, tau_f, s);
       hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, 0.0, 0.0, 1.0, mf, g, itf);
-      launch_collide_hrr<1>(fA, mf, tau_f, s);
+      timed(s, [&] { launch_collide_hrr<1>(fB, fA, mf, tau_f, s); });
       hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR>), dim3(br), dim3(IB), 0, s, Hp, fA, g, itf, kf, omf, tau_f, sig);
       // coarse collision before the TN transfer: the vector kernel also
       // passes over TN nodes, which the transfer then overwrites
-      launch_collide_hrr<0>(cdst, mc, tau_c, s);
+      launch_collide_hrr<0>(csrc, cdst, mc, tau_c, s);
       hipLaunchKernelGGL((k_coalesce<LAT, DEV, S, M_HRR>), dim3(bc), dim3(256), 0, s, fB, cdst, g, itf, kc, omc,
                          tau_c, sig);
     }
