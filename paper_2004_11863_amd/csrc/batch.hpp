@@ -153,7 +153,8 @@ __global__ __launch_bounds__(64) void kb_hist_time(const InstDev* __restrict__ i
 }
 
 // Ring reconstruction: SUB 0 (t+1/2, from G, into fine B), SUB 1 (t+1, from
-// the t+1 history, into fine A).
+// the t+1 history, into fine A); only the populations the stepping reads
+// (the full ring of A is completed before it is observed).
 template <int LAT, bool DEV, typename S, int MODEL, int SUB>
 __global__ __launch_bounds__(64) void kb_ring(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                               const int* __restrict__ count) {
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(64) void kb_ring(const InstDev* __restrict__ inst, 
     const InstDev& I = inst[w.inst];
     const double* G = SUB == 0 ? I.G : I.hist[I.hs[2]];
     S* dst = (S*)I.fbuf[SUB == 0 ? 1 : 0];
-    ring_body<LAT, DEV, S, MODEL>(G, dst, I.g, I.itf, I.tau_f / (2.0 * I.tau_c), 1.0 - 1.0 / I.tau_f, I.tau_f, I.sig,
+    ring_body<LAT, DEV, S, MODEL, true>(G, dst, I.g, I.itf, I.tau_f / (2.0 * I.tau_c), 1.0 - 1.0 / I.tau_f, I.tau_f, I.sig,
                                   (int64_t)w.idx * 64 + threadIdx.x);
   }
 }

@@ -580,7 +580,13 @@ __global__ void k_ring_macro(const double* __restrict__ Hm, const double* __rest
 // tau_f/(2 tau_c) f1 (eq rescff), S^f = S^c / 2 (eq PijResc), collided with
 // tau_f and stored.  RR / H-RR evaluate the post-collision state directly
 // from rho, u and the rescaled a1.
-template <int LAT, bool DEV, typename S, int MODEL>
+// PARTIAL: only the populations that stream into a middle node (x + xi
+// inside [1, nf - 2] on every axis) are stored -- the only ones the stepping
+// reads; on the x-normal faces each stored value is a lone write into its own
+// cache line, so skipping the others saves most of this kernel's traffic.
+// The full state is rebuilt from the same history level before it can be
+// observed (ring completion), with bitwise the same values.
+template <int LAT, bool DEV, typename S, int MODEL, bool PARTIAL>
 __device__ inline void ring_body(const double* __restrict__ G, S* __restrict__ dst, const Geo& g, const Iface& itf,
                                  double kf, double om_f, double tau_f, double sig, int64_t r) {
   using L = Lattice<LAT>;
@@ -617,12 +623,21 @@ __device__ inline void ring_body(const double* __restrict__ G, S* __restrict__ d
   fdecode(g, itf.rnode[r], x, y, z);
   const int64_t fi = fpos(g, x, y, z);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) dst[pop_at<S, Q>(fi, i)] = store_pop<S, DEV, LAT>(f[i], i);
+  for (int i = 0; i < Q; ++i) {
+    if (PARTIAL) {
+      const int xs = x + L::cx(i), ys = y + L::cy(i), zs = z + L::cz(i);
+      bool in = xs >= 1 && xs <= g.nf[0] - 2 && ys >= 1 && ys <= g.nf[1] - 2;
+      if (D == 3) in = in && zs >= 1 && zs <= g.nf[2] - 2;
+      if (!in) continue;
+    }
+    dst[pop_at<S, Q>(fi, i)] = store_pop<S, DEV, LAT>(f[i], i);
+  }
 }
-template <int LAT, bool DEV, typename S, int MODEL>
+template <int LAT, bool DEV, typename S, int MODEL, bool PARTIAL>
 __global__ void k_ring(const double* __restrict__ G, S* __restrict__ dst, const Geo g, const Iface itf,
                        double kf, double om_f, double tau_f, double sig) {
-  ring_body<LAT, DEV, S, MODEL>(G, dst, g, itf, kf, om_f, tau_f, sig, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  ring_body<LAT, DEV, S, MODEL, PARTIAL>(G, dst, g, itf, kf, om_f, tau_f, sig,
+                                         (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 

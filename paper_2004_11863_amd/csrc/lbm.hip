@@ -205,6 +205,9 @@ struct Grid final : GridBase {
   int hs[3] = {0, 1, 2};
   Iface itf{};
   double tau_c = 0, tau_f = 0, sig = 0;
+  // The stepping stores only the ring populations it reads again (k_ring
+  // PARTIAL); true while fine A holds such a partial ring.
+  bool ring_partial = false;
 
   // Velocity planes (H-RR): padded planes plus 64 spare elements.
   static size_t plane_bytes(int64_t NP, int nplanes) { return sizeof(S) * ((size_t)NP * nplanes + 64); }
@@ -411,10 +414,10 @@ struct Grid final : GridBase {
       launch_stream<MODEL, 0>(csrc, cdst, nullptr, tau_c, s);
       fine_stream_timed(MODEL, fA, fB, s);
       hipLaunchKernelGGL(k_hist_time, dim3(bg), dim3(256), 0, s, Hm, H0, Hp, G.as<double>(), NH * F::N, c0, c1, c2);
-      hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL>), dim3(br), dim3(IB), 0, s, G.as<double>(), fB, g, itf, kf, omf,
+      hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL, true>), dim3(br), dim3(IB), 0, s, G.as<double>(), fB, g, itf, kf, omf,
                          tau_f, sig);
       fine_stream_timed(MODEL, fB, fA, s);
-      hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL>), dim3(br), dim3(IB), 0, s, Hp, fA, g, itf, kf, omf, tau_f, sig);
+      hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL, true>), dim3(br), dim3(IB), 0, s, Hp, fA, g, itf, kf, omf, tau_f, sig);
       hipLaunchKernelGGL((k_coalesce<LAT, DEV, S, MODEL>), dim3(bc), dim3(256), 0, s, fB, cdst, g, itf, kc, omc,
                          tau_c, sig);
     } else {
@@ -429,12 +432,12 @@ struct Grid final : GridBase {
       hipLaunchKernelGGL((k_fict<LAT, DEV, S, S>), dim3(bt), dim3(IB), 0, s, fB, mc, g, itf);
       hipLaunchKernelGGL((k_hist_strain<LAT, S>), dim3(bh), dim3(IB), 0, s, mc, Hp, g, itf);
       hipLaunchKernelGGL(k_hist_time, dim3(bg), dim3(256), 0, s, Hm, H0, Hp, G.as<double>(), NH * F::N, c0, c1, c2);
-      hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR>), dim3(br), dim3(IB), 0, s, G.as<double>(), fB, g, itf, kf, omf,
+      hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR, true>), dim3(br), dim3(IB), 0, s, G.as<double>(), fB, g, itf, kf, omf,
                          tau_f, sig);
       launch_stream<M_HRR, 1>(fB, fA, mf, tau_f, s);
       hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, 0.0, 0.0, 1.0, mf, g, itf);
       timed(s, [&] { launch_collide_hrr<1>(fB, fA, mf, tau_f, s); });
-      hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR>), dim3(br), dim3(IB), 0, s, Hp, fA, g, itf, kf, omf, tau_f, sig);
+      hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR, true>), dim3(br), dim3(IB), 0, s, Hp, fA, g, itf, kf, omf, tau_f, sig);
       // coarse collision before the TN transfer: the vector kernel also
       // passes over TN nodes, which the transfer then overwrites
       launch_collide_hrr<0>(csrc, cdst, mc, tau_c, s);
@@ -447,6 +450,25 @@ struct Grid final : GridBase {
     hs[0] = hs[1];
     hs[1] = hs[2];
     hs[2] = old;
+    ring_partial = true;
+  }
+
+  // Completes the ring of fine A: rebuilds every population of the ring
+  // nodes from the history level the last step's synchronous ring used (now
+  // the middle level), which reproduces bitwise the populations stored then.
+  void complete_ring() {
+    if (!ring_partial || !g.has_fine) return;
+    const double kf = tau_f / (2.0 * tau_c), omf = 1.0 - 1.0 / tau_f;
+    const dim3 gr(blocks(itf.NR, kIfaceBlock)), bl(kIfaceBlock);
+    const double* H = hist[hs[1]].as<double>();
+    if (desc.collision == LBM_BGK)
+      hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_BGK, false>), gr, bl, 0, stream, H, fineA(), g, itf, kf, omf, tau_f, sig);
+    else if (desc.collision == LBM_RR)
+      hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_RR, false>), gr, bl, 0, stream, H, fineA(), g, itf, kf, omf, tau_f, sig);
+    else
+      hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR, false>), gr, bl, 0, stream, H, fineA(), g, itf, kf, omf, tau_f, sig);
+    HIPCHK(hipGetLastError());
+    ring_partial = false;
   }
 
   void step(int n, hipStream_t s) override {
@@ -484,6 +506,10 @@ struct Grid final : GridBase {
 
   void set_state(int level, const double* rho, const double* u, bool dev) override {
     HIPCHK(hipSetDevice(device));
+    HIPCHK(hipDeviceSynchronize());
+    // a coarse reset replaces the history the ring completion reads
+    if (level == 0) complete_ring();
+    else ring_partial = false;
     const int64_t N = nodes(level);
     upload(tmp_rho, rho, (size_t)N, dev);
     upload(tmp_u, u, (size_t)N * D, dev);
@@ -506,6 +532,7 @@ struct Grid final : GridBase {
   void get_macros(int level, double* rho, double* u, bool dev) override {
     HIPCHK(hipSetDevice(device));
     const int64_t N = nodes(level);
+    complete_ring();
     compute_macros(level);
     const hipMemcpyKind k = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     HIPCHK(hipMemcpyAsync(rho, tmp_rho.p, sizeof(double) * N, k, stream));
@@ -524,6 +551,9 @@ struct Grid final : GridBase {
 
   void set_pops(int level, const double* f, bool dev) override {
     HIPCHK(hipSetDevice(device));
+    HIPCHK(hipDeviceSynchronize());
+    if (level == 0) complete_ring();
+    else ring_partial = false;
     const int64_t N = nodes(level);
     ensure_tmp_f(N);
     HIPCHK(hipMemcpyAsync(tmp_f.p, f, sizeof(double) * Q * N, dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
@@ -542,6 +572,7 @@ struct Grid final : GridBase {
   void get_pops(int level, double* f, bool dev) override {
     HIPCHK(hipSetDevice(device));
     const int64_t N = nodes(level);
+    complete_ring();
     ensure_tmp_f(N);
     const S* src = level == 0 ? cur_c() : fineA();
     hipLaunchKernelGGL((k_pops_out<LAT, DEV, S>), dim3(blocks(Q * N, 256)), dim3(256), 0, stream, src,
@@ -554,6 +585,7 @@ struct Grid final : GridBase {
 
   void totals(double* mass, double* mom) override {
     HIPCHK(hipSetDevice(device));
+    complete_ring();
     for (int lv = 0; lv < 2; ++lv) {
       mass[lv] = 0.0;
       for (int d = 0; d < 3; ++d) mom[3 * lv + d] = 0.0;
@@ -698,6 +730,7 @@ struct Batch final : BatchBase {
   std::vector<std::unique_ptr<Inst>> slots;
   std::vector<InstDev> hinst;
   std::vector<int64_t> steps_done;
+  std::vector<char> ring_partial;  // per slot: fine A holds a partial ring (see Grid)
   DevBuf d_inst, d_counts, d_items[W_KINDS];
   size_t item_cap[W_KINDS] = {0, 0, 0, 0, 0, 0, 0};
   int counts[W_KINDS] = {0, 0, 0, 0, 0, 0, 0};
@@ -721,6 +754,7 @@ struct Batch final : BatchBase {
     slots.resize((size_t)cap);
     hinst.assign((size_t)cap, InstDev{});
     steps_done.assign((size_t)cap, 0);
+    ring_partial.assign((size_t)cap, 0);
     d_inst.alloc(sizeof(InstDev) * (size_t)cap);
     HIPCHK(hipMemset(d_inst.p, 0, d_inst.bytes));
     d_counts.alloc(sizeof(int) * W_KINDS);
@@ -863,6 +897,7 @@ struct Batch final : BatchBase {
     slots[(size_t)sl] = std::move(in);
     hinst[(size_t)sl] = I;
     steps_done[(size_t)sl] = 0;
+    ring_partial[(size_t)sl] = 0;
     upload_inst(sl);
     rebuild_lists();
     return sl;
@@ -883,6 +918,27 @@ struct Batch final : BatchBase {
     rebuild_lists();
   }
 
+  // Completes the ring of a slot's fine A (as Grid::complete_ring) from its
+  // middle history level.  Expects hinst[sl] fetched.
+  void complete_ring(int sl) {
+    if (!ring_partial[(size_t)sl]) return;
+    const Inst& in = *slots[(size_t)sl];
+    const InstDev& I = hinst[(size_t)sl];
+    const double kf = I.tau_f / (2.0 * I.tau_c), omf = 1.0 - 1.0 / I.tau_f;
+    const dim3 gr((unsigned)((in.itf.NR + kIfaceBlock - 1) / kIfaceBlock)), bl(kIfaceBlock);
+    const double* H = I.hist[I.hs[1]];
+    S* A = (S*)I.fbuf[0];
+    if (collision == LBM_BGK)
+      hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_BGK, false>), gr, bl, 0, stream, H, A, in.g, in.itf, kf, omf, I.tau_f, I.sig);
+    else if (collision == LBM_RR)
+      hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_RR, false>), gr, bl, 0, stream, H, A, in.g, in.itf, kf, omf, I.tau_f, I.sig);
+    else
+      hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR, false>), gr, bl, 0, stream, H, A, in.g, in.itf, kf, omf, I.tau_f,
+                         I.sig);
+    HIPCHK(hipGetLastError());
+    ring_partial[(size_t)sl] = 0;
+  }
+
   void set_state(int sl, int level, const double* rho, const double* u, bool dev) override {
     Inst& in = slot_ref(sl);
     if (level == 1 && !in.g.has_fine) throw LbmError(LBM_EINVAL, "no fine level");
@@ -890,6 +946,9 @@ struct Batch final : BatchBase {
     HIPCHK(hipDeviceSynchronize());
     fetch_inst(sl);
     InstDev& I = hinst[(size_t)sl];
+    // a coarse reset replaces the history the ring completion reads
+    if (level == 0) complete_ring(sl);
+    else ring_partial[(size_t)sl] = 0;
     const int64_t N = level == 0 ? in.g.Nc : in.g.Nf;
     const hipMemcpyKind k = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HIPCHK(hipMemcpy(tmp_rho.p, rho, sizeof(double) * N, k));
@@ -924,6 +983,7 @@ struct Batch final : BatchBase {
     HIPCHK(hipSetDevice(device));
     HIPCHK(hipDeviceSynchronize());
     fetch_inst(sl);
+    complete_ring(sl);
     const InstDev& I = hinst[(size_t)sl];
     const int64_t N = level == 0 ? in.g.Nc : in.g.Nf;
     const S* src = (const S*)(level == 0 ? I.cbuf[I.cpar] : I.fbuf[0]);
@@ -942,6 +1002,7 @@ struct Batch final : BatchBase {
     HIPCHK(hipSetDevice(device));
     HIPCHK(hipDeviceSynchronize());
     fetch_inst(sl);
+    complete_ring(sl);
     const InstDev& I = hinst[(size_t)sl];
     const int64_t N = level == 0 ? in.g.Nc : in.g.Nf;
     if (tmp_f.bytes < sizeof(double) * Q * (size_t)N) {
@@ -1038,7 +1099,10 @@ struct Batch final : BatchBase {
     }
     HIPCHK(hipGetLastError());
     for (int k = 0; k < capacity; ++k)
-      if (slots[(size_t)k]) steps_done[(size_t)k] += n;
+      if (slots[(size_t)k]) {
+        steps_done[(size_t)k] += n;
+        if (slots[(size_t)k]->g.has_fine) ring_partial[(size_t)k] = 1;
+      }
   }
 
   void set_graph(bool on) override {
