@@ -54,7 +54,7 @@ enum WorkKind : int {
 
 // [first, end) and stride of the items of this work group: the list is cut
 // into 8 contiguous chunks, chunk x served by the groups on XCD x.
-__device__ inline void item_range(int n, int& it, int& end, int& stride) {
+__device__ __forceinline__ void item_range(int n, int& it, int& end, int& stride) {
   const int b = blockIdx.x;
   const int chunk = (n + kXCD - 1) / kXCD;
   const int x = b % kXCD;
@@ -63,7 +63,7 @@ __device__ inline void item_range(int n, int& it, int& end, int& stride) {
   stride = gridDim.x / kXCD;
 }
 
-__device__ inline Work load_item(const Work* __restrict__ items, int it) {
+__device__ __forceinline__ Work load_item(const Work* __restrict__ items, int it) {
   Work w = items[it];
   w.inst = __builtin_amdgcn_readfirstlane(w.inst);
   w.idx = __builtin_amdgcn_readfirstlane(w.idx);

@@ -62,7 +62,7 @@ struct VecOf {
 };
 
 template <bool NT, typename A>
-__device__ inline void vstore(A* p, const A& v) {
+__device__ __forceinline__ void vstore(A* p, const A& v) {
   if (NT) __builtin_nontemporal_store(v, p);
   else *p = v;
 }
@@ -102,15 +102,23 @@ inline Flat make_flat(int nx, int ny, int nz, int V, bool fine, int D) {
 
 // Chunk of this work group in a single-grid launch: each XCD gets one
 // contiguous run of per_xcd chunks.
-__device__ inline int xcd_chunk(const Flat& f) {
+__device__ __forceinline__ int xcd_chunk(const Flat& f) {
   const int b = blockIdx.x;
   return (b % kXCD) * f.per_xcd + b / kXCD;
+}
+
+// Block index of an interface-node launch whose grid is a multiple of 8:
+// each XCD serves one contiguous range, so spatially adjacent interface
+// nodes (consecutive table entries) share one L2.
+__device__ __forceinline__ int64_t xcd_block() {
+  const int b = blockIdx.x, per = gridDim.x / kXCD;
+  return (int64_t)(b % kXCD) * per + b / kXCD;
 }
 
 // First node x0 of this work-item's V-node vector in chunk `chunk`; false
 // past the last vector.
 template <int V>
-__device__ inline bool flat_vec(const Flat& f, int chunk, int& x0, int& y, int& z) {
+__device__ __forceinline__ bool flat_vec(const Flat& f, int chunk, int& x0, int& y, int& z) {
   if (chunk >= f.nchunks) return false;
   const int64_t v = (int64_t)chunk * 256 + threadIdx.x;
   if (v >= f.nvec) return false;
@@ -122,60 +130,112 @@ __device__ inline bool flat_vec(const Flat& f, int chunk, int& x0, int& y, int& 
   return true;
 }
 
-// x coordinate wrapped into [0, n) (any displacement).
-__device__ inline int wrapx(int x, int n) {
-  while (x < 0) x += n;
-  while (x >= n) x -= n;
-  return x;
-}
-
 // Loads the V values of one row of a plain array (the velocity planes)
 // starting at x0 - cx.  Coarse rows are periodic: vectors that cross a row
 // end are gathered element-wise.
 template <typename S, int V, int LEVEL>
-__device__ inline typename VT<S, V>::a load_row(const S* __restrict__ row, int x0, int cx, int nx) {
+__device__ __forceinline__ typename VT<S, V>::a load_row(const S* __restrict__ row, int x0, int cx, int nx) {
   using VA = typename VT<S, V>::a;
   using VU = typename VT<S, V>::u;
   const int xs = x0 - cx;
   if (LEVEL == 0 && cx != 0 && (xs < 0 || xs + V > nx)) {
     VA v;
 #pragma unroll
-    for (int k = 0; k < V; ++k) v[k] = row[wrapx(xs + k, nx)];
+    for (int k = 0; k < V; ++k) v[k] = row[wrap(xs + k, nx)];
     return v;
   }
   if (cx == 0) return *(const VA*)(row + xs);
   return (VA)(*(const VU*)(row + xs));
 }
 
-// Loads population q of the V nodes x0 - cx .. x0 - cx + V - 1 of the row
-// whose x = 0 sits at padded position `rowp`.  Coarse rows are periodic;
-// vectors crossing a row end (coarse) or a storage block (x-shifted pulls)
-// are gathered element-wise; all others are one 16-byte load.
-template <typename S, int Q, int V, int LEVEL>
-__device__ inline typename VT<S, V>::a load_pull(const S* __restrict__ src, int64_t rowp, int x0, int cx, int nx,
-                                                 int q) {
+// Addressing of the pull-stream of one V-node vector, computed once per lane:
+// the position of x0 in each row of the (y, z) neighbourhood (periodic on the
+// coarse level) and, per row, whether the +x / -x shifted load leaves the
+// 16-byte vector path -- because it crosses a coarse row end (periodic wrap)
+// or a storage block (the aligned vector of x0 starts or ends a block).
+// All Q vector loads are issued first, without branches (a lane whose
+// shifted load leaves the vector path reads its own aligned vector instead,
+// which is always in bounds); the few such lanes then gather those
+// populations element-wise.  Branching around each load instead makes the
+// compiler wait for every outstanding load at each join, which leaves a wave
+// with one load in flight.
+template <typename S, int Q, int V, int LEVEL, int D>
+struct Pull {
+  static constexpr int NR = D == 3 ? 9 : 3;
   using VA = typename VT<S, V>::a;
   using VU = typename VT<S, V>::u;
-  constexpr int64_t BM = PopBlock<S>::B - 1;
-  const int xs = x0 - cx;
-  if (LEVEL == 0 && cx != 0 && (xs < 0 || xs + V > nx)) {
-    VA v;
+  int64_t rb[NR];    // position of node x0 of row (dy, dz), r = (dy + 1) + 3 (dz + 1)
+  uint32_t sm, sp;   // bit r: the load shifted by cx = +1 / -1 from row r is gathered
+  int x0, nx;
+
+  __device__ __forceinline__ Pull(int64_t P, int xo, int x0_, int y, int z, int nx_, int ny, int nz)
+      : sm(0), sp(0), x0(x0_), nx(nx_) {
+    constexpr int64_t BM = PopBlock<S>::B - 1;
 #pragma unroll
-    for (int k = 0; k < V; ++k) v[k] = src[pop_at<S, Q>(rowp + wrapx(xs + k, nx), q)];
-    return v;
+    for (int r = 0; r < NR; ++r) {
+      int ys = y + r % 3 - 1, zs = D == 3 ? z + r / 3 - 1 : z;
+      if (LEVEL == 0) {
+        ys = wrap(ys, ny);
+        if (D == 3) zs = wrap(zs, nz);
+      }
+      rb[r] = P * ((int64_t)ys + (int64_t)ny * zs) + xo + x0;
+      const int64_t o = rb[r] & BM;
+      if ((LEVEL == 0 && x0 == 0) || o == 0) sm |= 1u << r;
+      if ((LEVEL == 0 && x0 + V >= nx) || o == BM - V + 1) sp |= 1u << r;
+    }
   }
-  const int64_t p = rowp + xs;
-  if (cx == 0) return *(const VA*)(src + pop_at<S, Q>(p, q));
-  if ((p & BM) + (V - 1) <= BM) return (VA)(*(const VU*)(src + pop_at<S, Q>(p, q)));
-  VA v;
+  // row holding the node a population is pulled from (x - xi)
+  template <int CY, int CZ>
+  static constexpr int row() {
+    return (1 - CY) + (D == 3 ? 3 * (1 - CZ) : 0);
+  }
+  template <int CX, int CY>
+  __device__ __forceinline__ bool gathered(int r) const {
+    return CX > 0 ? ((sm >> r) & 1u) : (CX < 0 ? ((sp >> r) & 1u) : false);
+  }
+  // Vector load of population q with velocity (cx, cy, cz); wrong for lanes
+  // whose load is gathered (fixed by gather()).
+  template <int CX, int CY, int CZ>
+  __device__ __forceinline__ VA load(const S* __restrict__ src, int q) const {
+    constexpr int r = row<CY, CZ>();
+    const int64_t b = rb[r];
+    if (CX == 0) return *(const VA*)(src + pop_at<S, Q>(b, q));
+    const int64_t p = gathered<CX, CY>(r) ? b : b - CX;
+    return (VA)(*(const VU*)(src + pop_at<S, Q>(p, q)));
+  }
+  // Element-wise load for lanes whose shifted load is gathered.
+  template <int CX, int CY, int CZ>
+  __device__ __forceinline__ void gather(const S* __restrict__ src, int q, VA& v) const {
+    if (CX == 0) return;
+    constexpr int r = row<CY, CZ>();
+    if (!gathered<CX, CY>(r)) return;
+    const int64_t b = rb[r];
 #pragma unroll
-  for (int k = 0; k < V; ++k) v[k] = src[pop_at<S, Q>(p + k, q)];
-  return v;
-}
+    for (int k = 0; k < V; ++k) {
+      int x = x0 + k - CX;
+      if (LEVEL == 0) x = x < 0 ? x + nx : (x >= nx ? x - nx : x);
+      v[k] = src[pop_at<S, Q>(b - x0 + x, q)];
+    }
+  }
+  // All Q populations of the V nodes.
+  template <typename Lat>
+  __device__ __forceinline__ void load_all(const S* __restrict__ src, VA* v) const {
+    static_for<Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      v[i] = load<Lat::cx(i), Lat::cy(i), Lat::cz(i)>(src, i);
+    });
+    if (sm | sp) {
+      static_for<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        gather<Lat::cx(i), Lat::cy(i), Lat::cz(i)>(src, i, v[i]);
+      });
+    }
+  }
+};
 
 // Coarse vectors lying wholly inside the covered box are not evolved.
 template <int LEVEL>
-__device__ inline bool skip_vec(const Geo& g, int x0, int V, int y, int z, int nx) {
+__device__ __forceinline__ bool skip_vec(const Geo& g, int x0, int V, int y, int z, int nx) {
   if (LEVEL == 1 || !g.has_fine) return false;
   const int xl = min(x0 + V - 1, nx - 1);
   return coarse_class(g, x0, y, z) == CC_COVERED && coarse_class(g, xl, y, z) == CC_COVERED;
@@ -190,7 +250,7 @@ __device__ inline bool skip_vec(const Geo& g, int x0, int V, int y, int z, int n
 // nodes and the fine ring column x = nx - 1: the schedule overwrites TN and
 // ring nodes afterwards and never reads covered ones.
 template <int LAT, bool DEV, typename S, int MODEL, int LEVEL, bool NT>
-__device__ inline void stream_body(const S* __restrict__ src, S* __restrict__ dst, S* __restrict__ mac, const Geo& g,
+__device__ __forceinline__ void stream_body(const S* __restrict__ src, S* __restrict__ dst, S* __restrict__ mac, const Geo& g,
                                    const Flat& fl, const S om, int chunk) {
   using L = Lattice<LAT>;
   using N = Node<LAT, DEV, S>;
@@ -204,17 +264,10 @@ __device__ inline void stream_body(const S* __restrict__ src, S* __restrict__ ds
   const int64_t P = LEVEL == 0 ? g.pc : g.pf;
   const int64_t NP = LEVEL == 0 ? g.Ncp : g.Nfp;
   const int xo = LEVEL == 0 ? 0 : g.fxo;
+  const Pull<S, Q, V, LEVEL, L::D> pl(P, xo, x0, y, z, nx, ny, nz);
   VA v[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    int ys = y - L::cy(i), zs = z - L::cz(i);
-    if (LEVEL == 0) {
-      ys = wrap(ys, ny);
-      if (L::D == 3) zs = wrap(zs, nz);
-    }
-    v[i] = load_pull<S, Q, V, LEVEL>(src, P * ((int64_t)ys + (int64_t)ny * zs) + xo, x0, L::cx(i), nx, i);
-  }
-  const int64_t own = P * ((int64_t)y + (int64_t)ny * z) + xo + x0;
+  pl.template load_all<L>(src, v);
+  const int64_t own = pl.rb[Pull<S, Q, V, LEVEL, L::D>::template row<0, 0>()];
   if (MODEL == M_HRR) {
     VA r, ux, uy, uz;
 #pragma unroll
@@ -260,7 +313,7 @@ __global__ __launch_bounds__(256) void k_stream(const S* __restrict__ src, S* __
 // the interface kernels filled.  Processes whole vectors like k_stream; the
 // coarse pass runs before the fine-to-coarse transfer overwrites TN nodes.
 template <int LAT, bool DEV, typename S, int LEVEL, bool NT>
-__device__ inline void collide_hrr_body(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ mac,
+__device__ __forceinline__ void collide_hrr_body(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ mac,
                                         const Geo& g, const Flat& fl, const S om, const S tau, const S sig,
                                         int chunk) {
   using L = Lattice<LAT>;
@@ -275,45 +328,39 @@ __device__ inline void collide_hrr_body(const S* __restrict__ src, S* __restrict
   const int64_t P = LEVEL == 0 ? g.pc : g.pf;
   const int64_t NP = LEVEL == 0 ? g.Ncp : g.Nfp;
   const int xo = LEVEL == 0 ? 0 : g.fxo;
-  const int64_t own = P * ((int64_t)y + (int64_t)ny * z) + xo + x0;
-  // velocity gradient: gr[a][b] = (u_b(x + e_a) - u_b(x - e_a)) / 2
+  using PL = Pull<S, Q, V, LEVEL, D>;
+  const PL pl(P, xo, x0, y, z, nx, ny, nz);
+  const int64_t own = pl.rb[PL::template row<0, 0>()];
+  // velocity gradient: gr[a][b] = (u_b(x + e_a) - u_b(x - e_a)) / 2; the
+  // velocity planes are plain padded planes with the rows of pl
+  // the x-neighbours cross a row end only on the coarse level's first and
+  // last vectors (periodic): those lanes read their own vector, then gather
+  const bool xlo = LEVEL == 0 && x0 == 0, xhi = LEVEL == 0 && x0 + V >= nx;
   VA gr[3][3];
 #pragma unroll
   for (int b = 0; b < D; ++b) {
-    const S* ub = mac + (int64_t)(1 + b) * NP + xo;
-    const S* rowc = ub + P * ((int64_t)y + (int64_t)ny * z);
-    gr[0][b] = (load_row<S, V, LEVEL>(rowc, x0, -1, nx) - load_row<S, V, LEVEL>(rowc, x0, 1, nx)) * S(0.5);
-    {
-      int yp = y + 1, ym = y - 1;
-      if (LEVEL == 0) {
-        yp = wrap(yp, ny);
-        ym = wrap(ym, ny);
+    const S* ub = mac + (int64_t)(1 + b) * NP;
+    using VU = typename VT<S, V>::u;
+    VA up = (VA)(*(const VU*)(ub + own + (xhi ? 0 : 1)));
+    VA um = (VA)(*(const VU*)(ub + own - (xlo ? 0 : 1)));
+    if (xlo || xhi) {
+      const S* rowc = ub + own - x0;
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        up[k] = rowc[wrap(x0 + k + 1, nx)];
+        um[k] = rowc[wrap(x0 + k - 1, nx)];
       }
-      const VA up = *(const VA*)(ub + P * ((int64_t)yp + (int64_t)ny * z) + x0);
-      const VA um = *(const VA*)(ub + P * ((int64_t)ym + (int64_t)ny * z) + x0);
-      gr[1][b] = (up - um) * S(0.5);
     }
-    if (D == 3) {
-      int zp = z + 1, zm = z - 1;
-      if (LEVEL == 0) {
-        zp = wrap(zp, nz);
-        zm = wrap(zm, nz);
-      }
-      const VA up = *(const VA*)(ub + P * ((int64_t)y + (int64_t)ny * zp) + x0);
-      const VA um = *(const VA*)(ub + P * ((int64_t)y + (int64_t)ny * zm) + x0);
-      gr[2][b] = (up - um) * S(0.5);
-    }
+    gr[0][b] = (up - um) * S(0.5);
+    gr[1][b] = (*(const VA*)(ub + pl.rb[PL::template row<-1, 0>()]) - *(const VA*)(ub + pl.rb[PL::template row<1, 0>()])) *
+               S(0.5);
+    if (D == 3)
+      gr[2][b] = (*(const VA*)(ub + pl.rb[PL::template row<0, -1>()]) -
+                  *(const VA*)(ub + pl.rb[PL::template row<0, 1>()])) *
+                 S(0.5);
   }
   VA v[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    int ys = y - L::cy(i), zs = z - L::cz(i);
-    if (LEVEL == 0) {
-      ys = wrap(ys, ny);
-      if (D == 3) zs = wrap(zs, nz);
-    }
-    v[i] = load_pull<S, Q, V, LEVEL>(src, P * ((int64_t)ys + (int64_t)ny * zs) + xo, x0, L::cx(i), nx, i);
-  }
+  pl.template load_all<L>(src, v);
 #pragma unroll
   for (int k = 0; k < V; ++k) {
     Sym<S> Sr;
@@ -366,7 +413,7 @@ struct HF {
 // Symmetric tensor <-> its NS stored components (xx, yy, xy | xx, yy, zz, xy,
 // xz, yz).
 template <int D>
-__device__ inline void sym_put(const Sym<double>& a, double* out, double scale) {
+__device__ __forceinline__ void sym_put(const Sym<double>& a, double* out, double scale) {
   out[0] = scale * a.xx;
   out[1] = scale * a.yy;
   if (D == 2) {
@@ -379,7 +426,7 @@ __device__ inline void sym_put(const Sym<double>& a, double* out, double scale) 
   }
 }
 template <int D>
-__device__ inline Sym<double> sym_get(const double* v, double scale) {
+__device__ __forceinline__ Sym<double> sym_get(const double* v, double scale) {
   Sym<double> a{0, 0, 0, 0, 0, 0};
   a.xx = scale * v[0];
   a.yy = scale * v[1];
@@ -397,7 +444,7 @@ __device__ inline Sym<double> sym_get(const double* v, double scale) {
 // Second-order non-equilibrium moment of full populations f with moments
 // rho, u (eq a1Proj with the third-order equilibrium).
 template <int LAT>
-__device__ inline Sym<double> a1_of(const double* f, double rho, const double* u) {
+__device__ __forceinline__ Sym<double> a1_of(const double* f, double rho, const double* u) {
   using N = Node<LAT, false, double>;
   const Sym<double> P = N::second(f);
   const double r3 = rho * (1.0 / 3.0);
@@ -412,7 +459,7 @@ __device__ inline Sym<double> a1_of(const double* f, double rho, const double* u
 }
 
 // H-RR stress mix of eq a1ij_HRR: a <- sig a + (1 - sig)(-2 tau rho c_s^2 S).
-__device__ inline Sym<double> hrr_mix(const Sym<double>& a, const Sym<double>& S, double sig, double tau, double rho) {
+__device__ __forceinline__ Sym<double> hrr_mix(const Sym<double>& a, const Sym<double>& S, double sig, double tau, double rho) {
   const double k = (1.0 - sig) * (-2.0 / 3.0) * tau * rho;
   return Sym<double>{sig * a.xx + k * S.xx, sig * a.yy + k * S.yy, sig * a.zz + k * S.zz,
                      sig * a.xy + k * S.xy, sig * a.xz + k * S.xz, sig * a.yz + k * S.yz};
@@ -431,18 +478,18 @@ struct Iface {
 };
 
 template <typename S, bool DEV, int LAT>
-__device__ inline double full_pop(S v, int i) {
+__device__ __forceinline__ double full_pop(S v, int i) {
   return (double)v + (DEV ? Lattice<LAT>::w(i) : 0.0);
 }
 template <typename S, bool DEV, int LAT>
-__device__ inline S store_pop(double f, int i) {
+__device__ __forceinline__ S store_pop(double f, int i) {
   return (S)(f - (DEV ? Lattice<LAT>::w(i) : 0.0));
 }
 
 // Pre-collision state of coarse history nodes at t+1 (pulled from the
 // post-collision coarse state at t): rho, u and the non-equilibrium part.
 template <int LAT, bool DEV, typename S, int MODEL>
-__device__ inline void hist_capture_body(const S* __restrict__ src, double* __restrict__ H, const Geo& g,
+__device__ __forceinline__ void hist_capture_body(const S* __restrict__ src, double* __restrict__ H, const Geo& g,
                                          const Iface& itf, int64_t h) {
   using L = Lattice<LAT>;
   using F = HF<LAT, MODEL>;
@@ -479,7 +526,7 @@ __device__ inline void hist_capture_body(const S* __restrict__ src, double* __re
 }
 template <int LAT, bool DEV, typename S, int MODEL>
 __global__ void k_hist_capture(const S* __restrict__ src, double* __restrict__ H, const Geo g, const Iface itf) {
-  hist_capture_body<LAT, DEV, S, MODEL>(src, H, g, itf, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  hist_capture_body<LAT, DEV, S, MODEL>(src, H, g, itf, xcd_block() * blockDim.x + threadIdx.x);
 }
 
 
@@ -487,7 +534,7 @@ __global__ void k_hist_capture(const S* __restrict__ src, double* __restrict__ H
 // differences of the coarse velocity planes (TN entries come from the
 // fictitious propagation on the fine level).
 template <int LAT, typename T>
-__device__ inline void hist_strain_body(const T* __restrict__ mac_c, double* __restrict__ H, const Geo& g,
+__device__ __forceinline__ void hist_strain_body(const T* __restrict__ mac_c, double* __restrict__ H, const Geo& g,
                                         const Iface& itf, int64_t h) {
   using L = Lattice<LAT>;
   using F = HF<LAT, M_HRR>;
@@ -514,7 +561,7 @@ __device__ inline void hist_strain_body(const T* __restrict__ mac_c, double* __r
 }
 template <int LAT, typename T>
 __global__ void k_hist_strain(const T* __restrict__ mac_c, double* __restrict__ H, const Geo g, const Iface itf) {
-  hist_strain_body<LAT, T>(mac_c, H, g, itf, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  hist_strain_body<LAT, T>(mac_c, H, g, itf, xcd_block() * blockDim.x + threadIdx.x);
 }
 
 
@@ -528,11 +575,11 @@ __global__ void k_hist_time(const double* __restrict__ Hm, const double* __restr
   G[k] = c0 * Hm[k] + c1 * H0[k] + c2 * Hp[k];
 }
 
-__device__ inline double cubic_w(int s) { return (s == 1 || s == 2) ? 9.0 / 16.0 : -1.0 / 16.0; }
+__device__ __forceinline__ double cubic_w(int s) { return (s == 1 || s == 2) ? 9.0 / 16.0 : -1.0 / 16.0; }
 
 // Spatial weight of point s of a ring stencil (eq spaceInt; tensor product on
 // 3D face centres, first odd axis fastest).
-__device__ inline double ring_w(int np, int s) {
+__device__ __forceinline__ double ring_w(int np, int s) {
   if (np == 1) return 1.0;
   if (np == 4) return cubic_w(s);
   return cubic_w(s & 3) * cubic_w(s >> 2);
@@ -541,7 +588,7 @@ __device__ inline double ring_w(int np, int s) {
 // Ring nodes, rho and u only (H-RR needs them before the fine collision).
 // Temporal weights c applied inline to the three history levels.
 template <int LAT, typename T>
-__device__ inline void ring_macro_body(const double* __restrict__ Hm, const double* __restrict__ H0,
+__device__ __forceinline__ void ring_macro_body(const double* __restrict__ Hm, const double* __restrict__ H0,
                                        const double* __restrict__ Hp, double c0, double c1, double c2,
                                        T* __restrict__ mac_f, const Geo& g, const Iface& itf, int64_t r) {
   using L = Lattice<LAT>;
@@ -571,7 +618,7 @@ template <int LAT, typename T>
 __global__ void k_ring_macro(const double* __restrict__ Hm, const double* __restrict__ H0,
                              const double* __restrict__ Hp, double c0, double c1, double c2,
                              T* __restrict__ mac_f, const Geo g, const Iface itf) {
-  ring_macro_body<LAT, T>(Hm, H0, Hp, c0, c1, c2, mac_f, g, itf, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  ring_macro_body<LAT, T>(Hm, H0, Hp, c0, c1, c2, mac_f, g, itf, xcd_block() * blockDim.x + threadIdx.x);
 }
 
 
@@ -587,7 +634,7 @@ __global__ void k_ring_macro(const double* __restrict__ Hm, const double* __rest
 // The full state is rebuilt from the same history level before it can be
 // observed (ring completion), with bitwise the same values.
 template <int LAT, bool DEV, typename S, int MODEL, bool PARTIAL>
-__device__ inline void ring_body(const double* __restrict__ G, S* __restrict__ dst, const Geo& g, const Iface& itf,
+__device__ __forceinline__ void ring_body(const double* __restrict__ G, S* __restrict__ dst, const Geo& g, const Iface& itf,
                                  double kf, double om_f, double tau_f, double sig, int64_t r) {
   using L = Lattice<LAT>;
   using F = HF<LAT, MODEL>;
@@ -637,13 +684,13 @@ template <int LAT, bool DEV, typename S, int MODEL, bool PARTIAL>
 __global__ void k_ring(const double* __restrict__ G, S* __restrict__ dst, const Geo g, const Iface itf,
                        double kf, double om_f, double tau_f, double sig) {
   ring_body<LAT, DEV, S, MODEL, PARTIAL>(G, dst, g, itf, kf, om_f, tau_f, sig,
-                                         (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+                                         xcd_block() * blockDim.x + threadIdx.x);
 }
 
 
 // Pull of Q populations into fine node (x, y, z) from a fine buffer.
 template <int LAT, bool DEV, typename S>
-__device__ inline void pull_fine(const S* __restrict__ src, const Geo& g, int x, int y, int z, double* f) {
+__device__ __forceinline__ void pull_fine(const S* __restrict__ src, const Geo& g, int x, int y, int z, double* f) {
   using L = Lattice<LAT>;
 #pragma unroll
   for (int i = 0; i < L::Q; ++i)
@@ -653,7 +700,7 @@ __device__ inline void pull_fine(const S* __restrict__ src, const Geo& g, int x,
 // H-RR: fictitious propagation onto TN^f (Sec. 4.3, step e): u(TN, t+1) from
 // the fine post-collision state at t+1/2, written to the coarse macro planes.
 template <int LAT, bool DEV, typename S, typename T>
-__device__ inline void fict_body(const S* __restrict__ src_f, T* __restrict__ mac_c, const Geo& g, const Iface& itf,
+__device__ __forceinline__ void fict_body(const S* __restrict__ src_f, T* __restrict__ mac_c, const Geo& g, const Iface& itf,
                                  int64_t t) {
   using L = Lattice<LAT>;
   using N = Node<LAT, false, double>;
@@ -672,7 +719,7 @@ __device__ inline void fict_body(const S* __restrict__ src_f, T* __restrict__ ma
 }
 template <int LAT, bool DEV, typename S, typename T>
 __global__ void k_fict(const S* __restrict__ src_f, T* __restrict__ mac_c, const Geo g, const Iface itf) {
-  fict_body<LAT, DEV, S, T>(src_f, mac_c, g, itf, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  fict_body<LAT, DEV, S, T>(src_f, mac_c, g, itf, xcd_block() * blockDim.x + threadIdx.x);
 }
 
 
@@ -689,7 +736,7 @@ __global__ void k_fict(const S* __restrict__ src_f, T* __restrict__ mac_c, const
 // (TN node, component) sum the stencil in a fixed order; one lane per TN node
 // rebuilds and collides.
 template <int LAT, bool DEV, typename S, int MODEL>
-__device__ inline void coalesce_body(const S* __restrict__ src_f, S* __restrict__ dst_c, const Geo& g, const Iface& itf,
+__device__ __forceinline__ void coalesce_body(const S* __restrict__ src_f, S* __restrict__ dst_c, const Geo& g, const Iface& itf,
                                      double kc, double om_c, double tau_c, double sig, int64_t blk) {
   using L = Lattice<LAT>;
   using N = Node<LAT, false, double>;
@@ -777,7 +824,7 @@ __device__ inline void coalesce_body(const S* __restrict__ src_f, S* __restrict_
 template <int LAT, bool DEV, typename S, int MODEL>
 __global__ __launch_bounds__(256) void k_coalesce(const S* __restrict__ src_f, S* __restrict__ dst_c, const Geo g,
                                                   const Iface itf, double kc, double om_c, double tau_c, double sig) {
-  coalesce_body<LAT, DEV, S, MODEL>(src_f, dst_c, g, itf, kc, om_c, tau_c, sig, (int64_t)blockIdx.x);
+  coalesce_body<LAT, DEV, S, MODEL>(src_f, dst_c, g, itf, kc, om_c, tau_c, sig, xcd_block());
 }
 
 // ---------------------------------------------------------------------------

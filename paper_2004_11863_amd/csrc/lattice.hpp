@@ -128,7 +128,7 @@ struct Node {
 
   // eqs moment_rho, moment_rhoU.  r0: sum of stored values (rho for DEV = 0,
   // rho - 1 for DEV = 1).
-  __device__ __host__ static inline void moments(const T* s, T& rho, T& r0, T* u) {
+  __device__ __host__ static __forceinline__ void moments(const T* s, T& rho, T& r0, T* u) {
     T m = T(0), jx = T(0), jy = T(0), jz = T(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -151,7 +151,7 @@ struct Node {
   }
 
   // Second moments Pi_ab = sum_i xi_a xi_b s_i.
-  __device__ __host__ static inline Sym<T> second(const T* s) {
+  __device__ __host__ static __forceinline__ Sym<T> second(const T* s) {
     T pxx = T(0), pyy = T(0), pzz = T(0), pxy = T(0), pxz = T(0), pyz = T(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -173,7 +173,7 @@ struct Node {
 
   // Third-order coefficient combinations of a fully symmetric tensor given
   // by its components (xxy, xyy, yzz, xzz, yyz, xxz), in basis order.
-  __device__ __host__ static inline void third_combo(T xxy, T xyy, T yzz, T xzz, T yyz, T xxz, T* out) {
+  __device__ __host__ static __forceinline__ void third_combo(T xxy, T xyy, T yzz, T xzz, T yyz, T xxz, T* out) {
     if (D == 2) {
       out[0] = xxy;
       out[1] = xyy;
@@ -191,7 +191,7 @@ struct Node {
   //   A = r0 - 3/2 rho u^2 - 3/2 om tr(a),  J = 3 rho u,
   //   M = 9/2 (rho u u + om a),            K_P = c_P (rho u^3 + om a1^(3))_P.
   // om = 0 gives the equilibrium alone.
-  __device__ __host__ static inline Coef coef(T rho, T r0, const T* u, T om, const Sym<T>& a) {
+  __device__ __host__ static __forceinline__ Coef coef(T rho, T r0, const T* u, T om, const Sym<T>& a) {
     Coef c;
     const T usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const T tra = a.xx + a.yy + a.zz;
@@ -222,7 +222,7 @@ struct Node {
   }
 
   template <int i>
-  __device__ __host__ static inline T even(const Coef& c) {
+  __device__ __host__ static __forceinline__ T even(const Coef& c) {
     constexpr int x = L::cx(i), y = L::cy(i), z = L::cz(i);
     T e = c.A;
     if (x) e += c.M.xx;
@@ -234,7 +234,7 @@ struct Node {
     return e;
   }
   template <int i>
-  __device__ __host__ static inline T odd(const Coef& c) {
+  __device__ __host__ static __forceinline__ T odd(const Coef& c) {
     constexpr int x = L::cx(i), y = L::cy(i), z = L::cz(i);
     T o = T(0);
     if (x > 0) o += c.J[0];
@@ -252,7 +252,7 @@ struct Node {
   }
 
   // All Q stored values from coefficients.
-  __device__ __host__ static inline void eval(const Coef& c, T* out) {
+  __device__ __host__ static __forceinline__ void eval(const Coef& c, T* out) {
     out[0] = T(L::w(0)) * even<0>(c);
     static_for<Q>([&](auto ic) {
       constexpr int i = decltype(ic)::value;
@@ -267,7 +267,7 @@ struct Node {
 
   // Stored-form equilibrium s0_i = f0_i - DEV w_i (eq fEqO3 and its D3Q19
   // counterpart).
-  __device__ __host__ static inline void feq(T rho, T r0, const T* u, T* out) {
+  __device__ __host__ static __forceinline__ void feq(T rho, T r0, const T* u, T* out) {
     const Sym<T> z{T(0), T(0), T(0), T(0), T(0), T(0)};
     eval(coef(rho, r0, u, T(0), z), out);
   }
@@ -279,7 +279,7 @@ struct Node {
   // om = 1 - 1/tau.  With the third-order equilibrium,
   // sum_i xi xi f0_i = rho (u u + c_s^2 I), so a1 = Pi - r0/3 I - rho u u
   // in stored form (the rest state carries Pi = I/3).
-  __device__ __host__ static inline void collide(T* s, int model, T om, T tau, T sig, const Sym<T>* S) {
+  __device__ __host__ static __forceinline__ void collide(T* s, int model, T om, T tau, T sig, const Sym<T>* S) {
     T rho, r0, u[3];
     moments(s, rho, r0, u);
     if (model == 0) {

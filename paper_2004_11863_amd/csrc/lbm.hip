@@ -264,6 +264,8 @@ struct Grid final : GridBase {
   }
 
   static unsigned blocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+  // Grid of an interface-node kernel (xcd_block): a multiple of the XCD count.
+  static unsigned xblocks(int64_t n, int bs) { return (blocks(n, bs) + kXCD - 1) / kXCD * kXCD; }
 
   Flat flat(int level) const {
     if (level == 0) return make_flat(g.n[0], g.n[1], g.n[2], V, false, D);
@@ -407,8 +409,8 @@ struct Grid final : GridBase {
     const double c0 = -1.0 / 8.0, c1 = 3.0 / 4.0, c2 = 3.0 / 8.0;
     constexpr int IB = kIfaceBlock;
     constexpr int PER = 256 / (D == 2 ? 9 : 27);
-    const unsigned bh = blocks(NH, IB), br = blocks(itf.NR, IB), bt = blocks(itf.NT, IB), bg = blocks(NH * F::N, 256);
-    const unsigned bc = blocks(itf.NT, PER);
+    const unsigned bh = xblocks(NH, IB), br = xblocks(itf.NR, IB), bt = xblocks(itf.NT, IB), bg = blocks(NH * F::N, 256);
+    const unsigned bc = xblocks(itf.NT, PER);
     hipLaunchKernelGGL((k_hist_capture<LAT, DEV, S, MODEL>), dim3(bh), dim3(IB), 0, s, csrc, Hp, g, itf);
     if (MODEL != M_HRR) {
       launch_stream<MODEL, 0>(csrc, cdst, nullptr, tau_c, s);
@@ -459,7 +461,7 @@ struct Grid final : GridBase {
   void complete_ring() {
     if (!ring_partial || !g.has_fine) return;
     const double kf = tau_f / (2.0 * tau_c), omf = 1.0 - 1.0 / tau_f;
-    const dim3 gr(blocks(itf.NR, kIfaceBlock)), bl(kIfaceBlock);
+    const dim3 gr(xblocks(itf.NR, kIfaceBlock)), bl(kIfaceBlock);
     const double* H = hist[hs[1]].as<double>();
     if (desc.collision == LBM_BGK)
       hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_BGK, false>), gr, bl, 0, stream, H, fineA(), g, itf, kf, omf, tau_f, sig);
@@ -925,7 +927,7 @@ struct Batch final : BatchBase {
     const Inst& in = *slots[(size_t)sl];
     const InstDev& I = hinst[(size_t)sl];
     const double kf = I.tau_f / (2.0 * I.tau_c), omf = 1.0 - 1.0 / I.tau_f;
-    const dim3 gr((unsigned)((in.itf.NR + kIfaceBlock - 1) / kIfaceBlock)), bl(kIfaceBlock);
+    const dim3 gr((unsigned)((in.itf.NR + 8 * kIfaceBlock - 1) / (8 * kIfaceBlock) * 8)), bl(kIfaceBlock);
     const double* H = I.hist[I.hs[1]];
     S* A = (S*)I.fbuf[0];
     if (collision == LBM_BGK)
