@@ -180,11 +180,12 @@ const char* lbm_last_error(lbm_handle h);
 /* ------------------------------------------------------------------------
  * Batches: many independent grids of one lattice, collision model and
  * precision, each with its own geometry, tau and sigma, advanced together.
- * Each coarse step is one sequence of persistent launches over the work of
- * all grids (bulk tiles, interface node blocks), captured once as a hipGraph
- * and replayed; grids may join and leave between steps (continuous
- * batching), which rewrites device work lists without re-capturing.  A grid
- * in a batch computes exactly what the same grid computes alone.
+ * Each coarse step is one sequence of launches over the work of all grids
+ * (bulk chunks, interface node blocks), captured once as a hipGraph and
+ * replayed; grids may join and leave between steps (continuous batching),
+ * which rewrites device work lists (the launch is captured again only when a
+ * list outgrows its buffer).  A grid in a batch computes exactly what the
+ * same grid computes alone.
  * ------------------------------------------------------------------------ */
 typedef struct lbm_batch* lbm_batch_handle;
 

@@ -1,18 +1,19 @@
 // batch.hpp -- many independent two-level grids advanced by one set of
-// persistent launches per coarse step.
+// launches per coarse step.
 //
 // Every grid ("instance") of a batch keeps its own device buffers; a device
 // table of InstDev descriptors holds their geometry, buffer pointers and
 // time-level state (coarse ping-pong parity, history rotation).  For each
 // phase of the coarse step there is one work list of (instance, index)
 // items: a bulk chunk of 256 vectors, a block of 64 interface nodes, or a
-// block of TN nodes.  A phase is one launch of a persistent kernel whose work
-// groups walk the list; the list is split into 8 contiguous runs, one per XCD, so the chunks
-// of one instance stay in one L2.  The last launch of a step flips each
-// instance's parity and rotates its history on the device, so the launch
-// sequence of a step is the same every step and is captured once as a
+// block of TN nodes.  A phase is one launch with one work group per list
+// entry; the list is split into 8 contiguous parts, one per XCD, so the
+// chunks of one instance stay in one L2.  The last launch of a step flips
+// each instance's parity and rotates its history on the device, so the
+// launch sequence of a step is the same every step and is captured once as a
 // hipGraph.  Instances join or leave by rewriting the tables and lists
-// between steps; the captured graph reads list lengths from device memory.
+// between steps; the captured graph reads list lengths from device memory and
+// is captured again only when a list outgrows its buffer.
 #pragma once
 #include "kernels.hpp"
 
@@ -29,7 +30,9 @@ struct InstDev {
   double* hist[3];
   double* G;
   double tau_c, tau_f, sig;
-  int cpar;   // coarse buffer holding the current state
+  void* ccur;  // coarse buffer holding the current state (cbuf[cpar]) and the
+  void* cnext; // other one, kept as pointers so kernels read them directly
+  int cpar;    // coarse buffer holding the current state
   int hs[3];  // history buffers holding t-1, t, t+1
   int active;
   int pad;
@@ -52,15 +55,18 @@ enum WorkKind : int {
   W_KINDS = 7
 };
 
-// [first, end) and stride of the items of this work group: the list is cut
-// into 8 contiguous chunks, chunk x served by the groups on XCD x.
-__device__ __forceinline__ void item_range(int n, int& it, int& end, int& stride) {
+// Item of this work group, or -1.  A phase launches one work group per entry
+// of its list's capacity (a multiple of 8); the live count is read from
+// device memory, so a captured launch stays valid while grids join and leave.
+// Groups are handed to the XCDs round-robin; the item index is remapped so
+// each XCD serves one contiguous part of the list, in dispatch order.
+__device__ __forceinline__ int item_of(int n) {
   const int b = blockIdx.x;
-  const int chunk = (n + kXCD - 1) / kXCD;
-  const int x = b % kXCD;
-  it = x * chunk + b / kXCD;
-  end = min(n, (x + 1) * chunk);
-  stride = gridDim.x / kXCD;
+  const int per = (n + kXCD - 1) / kXCD;
+  const int w = b / kXCD;
+  if (w >= per) return -1;
+  const int it = (b % kXCD) * per + w;
+  return it < n ? it : -1;
 }
 
 __device__ __forceinline__ Work load_item(const Work* __restrict__ items, int it) {
@@ -75,14 +81,14 @@ __device__ __forceinline__ Work load_item(const Work* __restrict__ items, int it
 template <int LAT, bool DEV, typename S, int MODEL, int LEVEL, int SUB, bool NT>
 __global__ __launch_bounds__(256) void kb_stream(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                                  const int* __restrict__ count) {
-  int it, end, stride;
-  item_range(*count, it, end, stride);
-  for (; it < end; it += stride) {
+  const int it = item_of(*count);
+  if (it < 0) return;
+  {
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
     if (LEVEL == 0) {
-      const S* src = (const S*)I.cbuf[I.cpar];
-      S* dst = (S*)I.cbuf[I.cpar ^ 1];
+      const S* src = (const S*)I.ccur;
+      S* dst = (S*)I.cnext;
       stream_body<LAT, DEV, S, MODEL, 0, NT>(src, dst, (S*)I.mac_c, I.g, I.fc, (S)(1.0 - 1.0 / I.tau_c), w.idx);
     } else {
       const S* src = (const S*)I.fbuf[SUB];
@@ -97,13 +103,13 @@ __global__ __launch_bounds__(256) void kb_stream(const InstDev* __restrict__ ins
 template <int LAT, bool DEV, typename S, int LEVEL, int SUB, bool NT>
 __global__ __launch_bounds__(256) void kb_collide(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                                   const int* __restrict__ count) {
-  int it, end, stride;
-  item_range(*count, it, end, stride);
-  for (; it < end; it += stride) {
+  const int it = item_of(*count);
+  if (it < 0) return;
+  {
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
     if (LEVEL == 0) {
-      collide_hrr_body<LAT, DEV, S, 0, NT>((const S*)I.cbuf[I.cpar], (S*)I.cbuf[I.cpar ^ 1], (const S*)I.mac_c, I.g,
+      collide_hrr_body<LAT, DEV, S, 0, NT>((const S*)I.ccur, (S*)I.cnext, (const S*)I.mac_c, I.g,
                                            I.fc, (S)(1.0 - 1.0 / I.tau_c), (S)I.tau_c, (S)I.sig, w.idx);
     } else {
       collide_hrr_body<LAT, DEV, S, 1, NT>((const S*)I.fbuf[SUB], (S*)I.fbuf[SUB ^ 1], (const S*)I.mac_f, I.g, I.ff,
@@ -115,12 +121,12 @@ __global__ __launch_bounds__(256) void kb_collide(const InstDev* __restrict__ in
 template <int LAT, bool DEV, typename S, int MODEL>
 __global__ __launch_bounds__(64) void kb_hist_capture(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                                       const int* __restrict__ count) {
-  int it, end, stride;
-  item_range(*count, it, end, stride);
-  for (; it < end; it += stride) {
+  const int it = item_of(*count);
+  if (it < 0) return;
+  {
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
-    hist_capture_body<LAT, DEV, S, MODEL>((const S*)I.cbuf[I.cpar], I.hist[I.hs[2]], I.g, I.itf,
+    hist_capture_body<LAT, DEV, S, MODEL>((const S*)I.ccur, I.hist[I.hs[2]], I.g, I.itf,
                                           (int64_t)w.idx * 64 + threadIdx.x);
   }
 }
@@ -128,9 +134,9 @@ __global__ __launch_bounds__(64) void kb_hist_capture(const InstDev* __restrict_
 template <int LAT, typename S>
 __global__ __launch_bounds__(64) void kb_hist_strain(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                                      const int* __restrict__ count) {
-  int it, end, stride;
-  item_range(*count, it, end, stride);
-  for (; it < end; it += stride) {
+  const int it = item_of(*count);
+  if (it < 0) return;
+  {
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
     hist_strain_body<LAT, S>((const S*)I.mac_c, I.hist[I.hs[2]], I.g, I.itf, (int64_t)w.idx * 64 + threadIdx.x);
@@ -141,9 +147,9 @@ __global__ __launch_bounds__(64) void kb_hist_strain(const InstDev* __restrict__
 template <int NFIELD>
 __global__ __launch_bounds__(64) void kb_hist_time(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                                    const int* __restrict__ count) {
-  int it, end, stride;
-  item_range(*count, it, end, stride);
-  for (; it < end; it += stride) {
+  const int it = item_of(*count);
+  if (it < 0) return;
+  {
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
     const int64_t k = (int64_t)w.idx * 64 + threadIdx.x;
@@ -158,9 +164,9 @@ __global__ __launch_bounds__(64) void kb_hist_time(const InstDev* __restrict__ i
 template <int LAT, bool DEV, typename S, int MODEL, int SUB>
 __global__ __launch_bounds__(64) void kb_ring(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                               const int* __restrict__ count) {
-  int it, end, stride;
-  item_range(*count, it, end, stride);
-  for (; it < end; it += stride) {
+  const int it = item_of(*count);
+  if (it < 0) return;
+  {
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
     const double* G = SUB == 0 ? I.G : I.hist[I.hs[2]];
@@ -174,9 +180,9 @@ __global__ __launch_bounds__(64) void kb_ring(const InstDev* __restrict__ inst, 
 template <int LAT, typename S, int SUB>
 __global__ __launch_bounds__(64) void kb_ring_macro(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                                     const int* __restrict__ count) {
-  int it, end, stride;
-  item_range(*count, it, end, stride);
-  for (; it < end; it += stride) {
+  const int it = item_of(*count);
+  if (it < 0) return;
+  {
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
     const double c0 = SUB == 0 ? -0.125 : 0.0, c1 = SUB == 0 ? 0.75 : 0.0, c2 = SUB == 0 ? 0.375 : 1.0;
@@ -188,9 +194,9 @@ __global__ __launch_bounds__(64) void kb_ring_macro(const InstDev* __restrict__ 
 template <int LAT, bool DEV, typename S>
 __global__ __launch_bounds__(64) void kb_fict(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                               const int* __restrict__ count) {
-  int it, end, stride;
-  item_range(*count, it, end, stride);
-  for (; it < end; it += stride) {
+  const int it = item_of(*count);
+  if (it < 0) return;
+  {
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
     fict_body<LAT, DEV, S, S>((const S*)I.fbuf[1], (S*)I.mac_c, I.g, I.itf, (int64_t)w.idx * 64 + threadIdx.x);
@@ -200,12 +206,12 @@ __global__ __launch_bounds__(64) void kb_fict(const InstDev* __restrict__ inst, 
 template <int LAT, bool DEV, typename S, int MODEL>
 __global__ __launch_bounds__(256) void kb_coalesce(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                                    const int* __restrict__ count) {
-  int it, end, stride;
-  item_range(*count, it, end, stride);
-  for (; it < end; it += stride) {
+  const int it = item_of(*count);
+  if (it < 0) return;
+  {
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
-    coalesce_body<LAT, DEV, S, MODEL>((const S*)I.fbuf[1], (S*)I.cbuf[I.cpar ^ 1], I.g, I.itf, 2.0 * I.tau_c / I.tau_f,
+    coalesce_body<LAT, DEV, S, MODEL>((const S*)I.fbuf[1], (S*)I.cnext, I.g, I.itf, 2.0 * I.tau_c / I.tau_f,
                                       1.0 - 1.0 / I.tau_c, I.tau_c, I.sig, w.idx);
   }
 }
@@ -218,6 +224,9 @@ __global__ void kb_advance(InstDev* __restrict__ inst, int n) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n || !inst[k].active) return;
   inst[k].cpar ^= 1;
+  void* t = inst[k].ccur;
+  inst[k].ccur = inst[k].cnext;
+  inst[k].cnext = t;
   const int old = inst[k].hs[0];
   inst[k].hs[0] = inst[k].hs[1];
   inst[k].hs[1] = inst[k].hs[2];

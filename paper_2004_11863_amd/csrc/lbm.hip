@@ -658,7 +658,7 @@ static Geo validate(const lbm_grid_desc& d) {
 
 // ---------------------------------------------------------------------------
 // Batch of independent grids (same lattice, collision model and precision),
-// advanced together by persistent launches; one coarse step is captured as a
+// advanced together by one launch per phase; one coarse step is captured as a
 // hipGraph and replayed.
 struct BatchBase {
   int lattice = 0, collision = 0, precision = 0, device = 0, capacity = 0;
@@ -718,9 +718,6 @@ struct Batch final : BatchBase {
   static constexpr int NVAR = kNVar;
   static constexpr int V = VecOf<S>::V;
   static constexpr int HN = Grid<LAT, PREC>::HN;
-  static constexpr int BULK_GRID = kXCD * 512;  // work groups of the persistent launches
-  static constexpr int IF_GRID = kXCD * 512;
-  static constexpr int TN_GRID = kXCD * 256;
 
   struct Inst {
     lbm_grid_desc desc{};
@@ -892,6 +889,8 @@ struct Batch final : BatchBase {
     I.tau_f = 2.0 * d.tau_coarse - 0.5;
     I.sig = d.sigma;
     I.cpar = 0;
+    I.ccur = I.cbuf[0];
+    I.cnext = I.cbuf[1];
     I.hs[0] = 0;
     I.hs[1] = 1;
     I.hs[2] = 2;
@@ -1023,50 +1022,54 @@ struct Batch final : BatchBase {
 
   // ---- phase launches ----
   const InstDev* di() const { return d_inst.template as<InstDev>(); }
+  // One work group per entry of list k's capacity (a multiple of 8).
+  dim3 grid_of(int k) const { return dim3((unsigned)((item_cap[k] + kXCD - 1) / kXCD * kXCD)); }
   const Work* items(int k) const { return d_items[k].template as<Work>(); }
   const int* cnt(int k) const { return d_counts.template as<int>() + k; }
 
   template <int MODEL, int LEVEL, int SUB>
   void phase_stream(hipStream_t s, int v) {
-    hipLaunchKernelGGL((kb_stream<LAT, DEV, S, MODEL, LEVEL, SUB, NT>), dim3(BULK_GRID), dim3(256),
+    hipLaunchKernelGGL((kb_stream<LAT, DEV, S, MODEL, LEVEL, SUB, NT>), grid_of(LEVEL == 0 ? W_COARSE : W_FINE), dim3(256),
                        (unsigned)kVarLds[v], s, di(), items(LEVEL == 0 ? W_COARSE : W_FINE),
                        cnt(LEVEL == 0 ? W_COARSE : W_FINE));
   }
   template <int LEVEL, int SUB>
   void phase_collide(hipStream_t s, int v) {
-    hipLaunchKernelGGL((kb_collide<LAT, DEV, S, LEVEL, SUB, NT>), dim3(BULK_GRID), dim3(256), (unsigned)kVarLds[v], s,
+    hipLaunchKernelGGL((kb_collide<LAT, DEV, S, LEVEL, SUB, NT>), grid_of(LEVEL == 0 ? W_COARSE : W_FINE), dim3(256),
+                       (unsigned)kVarLds[v], s,
                        di(), items(LEVEL == 0 ? W_COARSE : W_FINE), cnt(LEVEL == 0 ? W_COARSE : W_FINE));
   }
 
   template <int MODEL>
   void launch_step_model(hipStream_t s) {
     using F = HF<LAT, MODEL>;
-    const dim3 ig(IF_GRID), ib(64);
-    hipLaunchKernelGGL((kb_hist_capture<LAT, DEV, S, MODEL>), ig, ib, 0, s, di(), items(W_HIST), cnt(W_HIST));
+    const dim3 ib(64);
+    hipLaunchKernelGGL((kb_hist_capture<LAT, DEV, S, MODEL>), grid_of(W_HIST), ib, 0, s, di(), items(W_HIST),
+                       cnt(W_HIST));
     if (MODEL != M_HRR) {
       phase_stream<MODEL, 0, 0>(s, var_c);
       phase_stream<MODEL, 1, 0>(s, var_f);
-      hipLaunchKernelGGL((kb_hist_time<F::N>), ig, ib, 0, s, di(), items(W_HTIME), cnt(W_HTIME));
-      hipLaunchKernelGGL((kb_ring<LAT, DEV, S, MODEL, 0>), ig, ib, 0, s, di(), items(W_RING), cnt(W_RING));
+      hipLaunchKernelGGL((kb_hist_time<F::N>), grid_of(W_HTIME), ib, 0, s, di(), items(W_HTIME), cnt(W_HTIME));
+      hipLaunchKernelGGL((kb_ring<LAT, DEV, S, MODEL, 0>), grid_of(W_RING), ib, 0, s, di(), items(W_RING), cnt(W_RING));
       phase_stream<MODEL, 1, 1>(s, var_f);
-      hipLaunchKernelGGL((kb_ring<LAT, DEV, S, MODEL, 1>), ig, ib, 0, s, di(), items(W_RING), cnt(W_RING));
-      hipLaunchKernelGGL((kb_coalesce<LAT, DEV, S, MODEL>), dim3(TN_GRID), dim3(256), 0, s, di(), items(W_TNB),
+      hipLaunchKernelGGL((kb_ring<LAT, DEV, S, MODEL, 1>), grid_of(W_RING), ib, 0, s, di(), items(W_RING), cnt(W_RING));
+      hipLaunchKernelGGL((kb_coalesce<LAT, DEV, S, MODEL>), grid_of(W_TNB), dim3(256), 0, s, di(), items(W_TNB),
                          cnt(W_TNB));
     } else {
       phase_stream<M_HRR, 0, 0>(s, var_c);
       phase_stream<M_HRR, 1, 0>(s, var_f);
-      hipLaunchKernelGGL((kb_ring_macro<LAT, S, 0>), ig, ib, 0, s, di(), items(W_RING), cnt(W_RING));
+      hipLaunchKernelGGL((kb_ring_macro<LAT, S, 0>), grid_of(W_RING), ib, 0, s, di(), items(W_RING), cnt(W_RING));
       phase_collide<1, 0>(s, var_f);
-      hipLaunchKernelGGL((kb_fict<LAT, DEV, S>), ig, ib, 0, s, di(), items(W_TN), cnt(W_TN));
-      hipLaunchKernelGGL((kb_hist_strain<LAT, S>), ig, ib, 0, s, di(), items(W_HIST), cnt(W_HIST));
-      hipLaunchKernelGGL((kb_hist_time<F::N>), ig, ib, 0, s, di(), items(W_HTIME), cnt(W_HTIME));
-      hipLaunchKernelGGL((kb_ring<LAT, DEV, S, M_HRR, 0>), ig, ib, 0, s, di(), items(W_RING), cnt(W_RING));
+      hipLaunchKernelGGL((kb_fict<LAT, DEV, S>), grid_of(W_TN), ib, 0, s, di(), items(W_TN), cnt(W_TN));
+      hipLaunchKernelGGL((kb_hist_strain<LAT, S>), grid_of(W_HIST), ib, 0, s, di(), items(W_HIST), cnt(W_HIST));
+      hipLaunchKernelGGL((kb_hist_time<F::N>), grid_of(W_HTIME), ib, 0, s, di(), items(W_HTIME), cnt(W_HTIME));
+      hipLaunchKernelGGL((kb_ring<LAT, DEV, S, M_HRR, 0>), grid_of(W_RING), ib, 0, s, di(), items(W_RING), cnt(W_RING));
       phase_stream<M_HRR, 1, 1>(s, var_f);
-      hipLaunchKernelGGL((kb_ring_macro<LAT, S, 1>), ig, ib, 0, s, di(), items(W_RING), cnt(W_RING));
+      hipLaunchKernelGGL((kb_ring_macro<LAT, S, 1>), grid_of(W_RING), ib, 0, s, di(), items(W_RING), cnt(W_RING));
       phase_collide<1, 1>(s, var_f);
-      hipLaunchKernelGGL((kb_ring<LAT, DEV, S, M_HRR, 1>), ig, ib, 0, s, di(), items(W_RING), cnt(W_RING));
+      hipLaunchKernelGGL((kb_ring<LAT, DEV, S, M_HRR, 1>), grid_of(W_RING), ib, 0, s, di(), items(W_RING), cnt(W_RING));
       phase_collide<0, 0>(s, var_c);
-      hipLaunchKernelGGL((kb_coalesce<LAT, DEV, S, M_HRR>), dim3(TN_GRID), dim3(256), 0, s, di(), items(W_TNB),
+      hipLaunchKernelGGL((kb_coalesce<LAT, DEV, S, M_HRR>), grid_of(W_TNB), dim3(256), 0, s, di(), items(W_TNB),
                          cnt(W_TNB));
     }
     hipLaunchKernelGGL(kb_advance, dim3((unsigned)((capacity + 255) / 256)), dim3(256), 0, s, d_inst.template as<InstDev>(),

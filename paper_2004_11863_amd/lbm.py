@@ -347,7 +347,7 @@ def _bcheck(rc, b):
 
 class Batch:
     """Many grids of one lattice / collision model / precision, stepped
-    together by persistent launches replayed from a hipGraph."""
+    together by one launch per phase, replayed from a hipGraph."""
 
     def __init__(self, lattice, collision, precision, capacity, device=0):
         self.b = ctypes.c_void_p()
