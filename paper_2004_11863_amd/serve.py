@@ -253,9 +253,11 @@ def latency_stats(done):
 
 class DeviceExecutor:
     """Runs requests on the HIP library: one batch per group, each stepped on
-    its own stream."""
+    its own stream.  A group whose membership changed is autotuned before it
+    is stepped again if its work per step is at least `tune_min` lattice
+    updates (kernel variants give bitwise the same results)."""
 
-    def __init__(self, capacity: int = 64, device: int = 0):
+    def __init__(self, capacity: int = 64, device: int = 0, tune_min: float = 4e6):
         import torch
         from . import lbm
         self.torch = torch
@@ -266,6 +268,8 @@ class DeviceExecutor:
         self.streams = {}
         self.where = {}
         self.next = 0
+        self.tune_min = tune_min
+        self.changed = set()
 
     def _code(self, key):
         lat, col, prec = key[:3]
@@ -302,9 +306,16 @@ class DeviceExecutor:
         h = self.next
         self.next += 1
         self.where[h] = (group, sl)
+        self.changed.add(group)
         return h
 
     def step(self, plan):
+        for g in plan:
+            if g in self.changed:
+                self.changed.discard(g)
+                b = self.batches[g]
+                if b.info()["updates_per_step"] >= self.tune_min:
+                    b.tune(reps=2)
         for g, n in plan.items():
             self.batches[g].step(n, self.streams[g].cuda_stream)
         for g in plan:
@@ -323,6 +334,7 @@ class DeviceExecutor:
     def release(self, h):
         group, sl = self.where.pop(h)
         self.batches[group].remove(sl)
+        self.changed.add(group)
 
     def close(self):
         for b in self.batches.values():
