@@ -210,43 +210,62 @@ def batched(n_inst, steps):
             "speedup": round((ups * steps / dt) / (ups * loop_steps / dl), 2)}
 
 
-def serving(n_req, rate=200.0):
-    """A seeded Poisson stream (mean 200 requests/s) mixing D2Q9 (sides
-    128-2048) and D3Q19 (sides 64-256) two-level problems with 100-2000 coarse
-    steps, FP32 with 10 % flagged FP64, RR; first n_req arrivals.  Initial
-    fields are sampled before the trace starts (client side).  Continuous
-    batching (size-class groups, shortest remaining time first with backfill)
-    against the plain FIFO per-instance loop on the same trace."""
+def serve_trace(n_req, rate, realtime=True):
+    """Served (continuous batching) and FIFO one-at-a-time runs of one trace;
+    latency statistics and aggregate throughput of each."""
     import torch
     from paper_2004_11863_amd import serve
     reqs = [r.prepare() for r in serve.poisson_trace(n_req, rate=rate, seed=5)]
     work = sum(r.updates() for r in reqs)
     free, total = torch.cuda.mem_get_info()
-    budget = int(0.8 * free)
     ex = serve.DeviceExecutor(capacity=64)
+    srv = serve.Server(ex, int(0.8 * free), policy="srpt")
     t0 = time.perf_counter()
-    srv = serve.Server(ex, budget, policy="srpt")
-    done = srv.run(reqs, realtime=True)
+    done = srv.run(reqs, realtime=realtime)
     span = time.perf_counter() - t0
     ex.close()
     torch.cuda.empty_cache()
     st = serve.latency_stats(done)
     reqs2 = [r.prepare() for r in serve.poisson_trace(n_req, rate=rate, seed=5)]
     t0 = time.perf_counter()
-    done2 = serve.fifo_loop(reqs2, realtime=True)
+    done2 = serve.fifo_loop(reqs2, realtime=realtime)
     span2 = time.perf_counter() - t0
     st2 = serve.latency_stats(done2)
     torch.cuda.empty_cache()
-    offered = work / (reqs[-1].arrival - reqs[0].arrival + 1e-9)
-    return {"requests": n_req, "rate_per_s": rate, "total_updates": work,
-            "policy": "srpt", "slice_s": srv.slice_s, "backfill": srv.backfill,
-            "served": {"p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
+    return {"served": {"p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
                        "aggregate_mlups": round(work / span / 1e6, 1), "makespan_s": round(span, 3),
                        "fp64_fallbacks": sum(r.fell_back for r in done)},
             "fifo_per_instance": {"p50_s": round(st2["p50_s"], 3), "p99_s": round(st2["p99_s"], 3),
                                   "aggregate_mlups": round(work / span2 / 1e6, 1), "makespan_s": round(span2, 3)},
-            "offered_mlups": round(offered / 1e6, 1),
-            "saturated": bool(offered > work / span)}
+            "total_updates": work, "first_arrival_s": reqs[0].arrival, "last_arrival_s": reqs[-1].arrival}
+
+
+def serving(n_req, rate=200.0, utilization=0.7):
+    """A seeded Poisson stream (mean 200 requests/s) mixing D2Q9 (sides
+    128-2048) and D3Q19 (sides 64-256) two-level problems with 100-2000 coarse
+    steps, FP32 with 10 % flagged FP64, RR; first n_req arrivals.  Initial
+    fields are sampled before the trace starts (client side).  Continuous
+    batching (size-class groups, shortest remaining time first with backfill)
+    against the plain FIFO per-instance loop on the same trace; then the same
+    requests arriving at the rate that offers `utilization` of the measured
+    served throughput (the request mix is the same: the seed fixes it)."""
+    import inspect
+    from paper_2004_11863_amd import serve
+    SERVER_DEFAULTS = {k: v.default for k, v in inspect.signature(serve.Server).parameters.items()}
+    sat = serve_trace(n_req, rate)
+    work = sat["total_updates"]
+    offered = work / (sat["last_arrival_s"] - sat["first_arrival_s"] + 1e-9)
+    out = {"requests": n_req, "rate_per_s": rate, "total_updates": work,
+           "policy": "srpt", "slice_s": SERVER_DEFAULTS["slice_s"], "backfill": SERVER_DEFAULTS["backfill"],
+           "served": sat["served"], "fifo_per_instance": sat["fifo_per_instance"],
+           "offered_mlups": round(offered / 1e6, 1), "saturated": bool(offered > sat["served"]["aggregate_mlups"] * 1e6)}
+    capacity = sat["served"]["aggregate_mlups"] * 1e6
+    mean_work = work / n_req
+    rate_u = utilization * capacity / mean_work
+    sub = serve_trace(n_req, rate_u)
+    out["sub_saturation"] = {"utilization_target": utilization, "rate_per_s": round(rate_u, 4),
+                             "served": sub["served"], "fifo_per_instance": sub["fifo_per_instance"]}
+    return out
 
 
 def copy_probe(mib):

@@ -114,6 +114,77 @@ def test_fp64_d3q19_64cube_subcase(model):
     assert max(w.values()) <= TOL64, w
 
 
+@pytest.mark.parametrize("D", [2, 3])
+@pytest.mark.parametrize("model", ["BGK", "RR", "HRR"])
+def test_fp64_smallest_patches_at_the_bounds(D, model):
+    """Patches of the minimum width (4 cells) on one axis, reaching both
+    bounds of the descriptor (lo = 2, hi = n - 3), anisotropic in 3D."""
+    lbm = _lbm()
+    if D == 2:
+        geom = _geom(2, (24, 21), (2, 2), (6, 18))
+    else:
+        geom = _geom(3, (13, 12, 14), (2, 2, 2), (6, 9, 11))
+    U = (0.04, -0.03, 0.02)
+    wl = I.Workload(geom=geom, U=U, pulses=[I.Pulse(center=tuple(x / 3 for x in geom.n[:D]), A=2e-3, R=2.0)])
+    gpu, ref, levels = make_pair(wl, model, lbm.LBM_FP64, tau_c=0.53)
+    gpu.step(20)
+    ref.step(20)
+    w = compare_fp64(gpu, ref, levels)
+    gpu.close()
+    assert max(w.values()) <= TOL64, w
+
+
+@pytest.mark.parametrize("sigma", [0.0, 0.5])
+def test_fp64_hrr_sigma_range(sigma):
+    """H-RR across the weight of eq a1ij_HRR: sigma = 0 (stress from finite
+    differences only) and an intermediate value."""
+    lbm = _lbm()
+    wl = I.config1(5)
+    gpu, ref, levels = make_pair(wl, "HRR", lbm.LBM_FP64, sigma=sigma)
+    gpu.step(40)
+    ref.step(40)
+    w = compare_fp64(gpu, ref, levels)
+    gpu.close()
+    assert max(w.values()) <= TOL64, w
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_hrr_with_sigma_one_is_rr(prec):
+    """With sigma = 1 the hybrid stress is sigma a + (1 - sigma)(...) = a
+    exactly, so H-RR must reproduce RR: the two-pass H-RR kernels, the ring
+    and the fine-to-coarse transfer with strain rates against the one-pass
+    RR path."""
+    lbm = _lbm()
+    p = lbm.LBM_FP32_DEV if prec == "fp32" else lbm.LBM_FP64
+    wl = I.config1(6)
+    a, _, _ = make_pair(wl, "HRR", p, sigma=1.0, with_oracle=False)
+    b, _, _ = make_pair(wl, "RR", p, sigma=1.0, with_oracle=False)
+    a.step(30)
+    b.step(30)
+    live = a.class_map(0) != lbm.LBM_C_COVERED
+    for lv in (0, 1):
+        fa, fb = a.get_populations(lv), b.get_populations(lv)
+        if lv == 0:
+            fa, fb = fa[:, live], fb[:, live]
+        d = float(np.abs(fa - fb).max() / np.abs(fb).max())
+        assert d <= 1e-14, (lv, d)
+    a.close()
+    b.close()
+
+
+def test_fp64_tau_near_one_half():
+    """Very low viscosity (tau_c = 0.5005, tau_f = 0.501) over a few steps."""
+    lbm = _lbm()
+    wl = I.config1(7)
+    for model in ("RR", "HRR"):
+        gpu, ref, levels = make_pair(wl, model, lbm.LBM_FP64, tau_c=0.5005)
+        gpu.step(25)
+        ref.step(25)
+        w = compare_fp64(gpu, ref, levels)
+        gpu.close()
+        assert max(w.values()) <= TOL64, (model, w)
+
+
 def test_totals_match_oracle():
     lbm = _lbm()
     wl = I.config1(2)
