@@ -63,6 +63,16 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def kernel_label(D, collision):
+    """The fine-level kernel lbm_profile_enable times for this grid."""
+    if D == 2 and collision != "HRR":
+        return ("k_fine2: both fine substeps of a coarse step (pull + collide twice, the t+1/2 state in LDS); "
+                "algorithmic bytes count 2 Q P_b per lattice update, 2 updates per node per launch")
+    if collision == "HRR":
+        return "k_collide_hrr: fine-level pull + H-RR collide (second pass)"
+    return "k_stream: fine-level pull + collide"
+
+
 def workload(name, seed=0):
     from paper_2004_11863_amd import inputs as I
     if name == "d2q9-4096":
@@ -348,15 +358,21 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_stream (fine level, pull + collide)",
+            "kernel": kernel_label(D, args.collision),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "bytes_per_launch": alg_bytes,
+            "updates_per_launch": nodes,
             "launches": launches,
             "mean_launch_ms": mean_ms,
+            # HBM bandwidth the kernel actually drew (counter traffic over the
+            # live launch time); differs from `achieved` when one launch
+            # performs several lattice updates per node
+            "hbm_achieved": None if traffic is None else round(traffic / (mean_ms * 1e-3) / 1e9, 1),
+            "hbm_frac": None if traffic is None else round(traffic / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         },
         "kernel_variants": variants,
         "totals_finite": bool(all(map(lambda v: v == v, list(m) + list(p.ravel())))),
@@ -380,7 +396,8 @@ def main():
             a2 = 2 * q2 * pb2 * k2[2] / (k2[1] * 1e-3) / 1e9
             extra[name] = {"mlups": round(u2 * steps / d2 / 1e6, 1), "steps": steps,
                            "ms_per_step": d2 / steps * 1e3,
-                           "fine_kernel_GBs": round(a2, 1), "fine_kernel_frac": round(a2 / HBM_PEAK_GBS, 4)}
+                           "fine_kernel": kernel_label(2 if wname.startswith("d2q9") else 3, col).split(":")[0],
+                           "fine_kernel_alg_GBs": round(a2, 1), "fine_kernel_alg_frac": round(a2 / HBM_PEAK_GBS, 4)}
             gr.close()
             del gr, w2
             torch.cuda.empty_cache()

@@ -150,11 +150,13 @@ int lbm_interface_tables(lbm_handle h, int64_t* hist_nodes, int64_t* ring_nodes,
 int lbm_updates_per_step(lbm_handle h, int64_t* updates);
 
 /* Per-launch timing of the fine-level pull-stream + collide kernel (the
- * dominant kernel; for H-RR its second pass, which pulls again and collides
- * with the strain rate of the velocities the first pass wrote): when
- * enabled, lbm_step records HIP events around each of its launches on the
- * launch stream; lbm_kernel_time returns the number of timed launches, their
- * mean duration in ms and the nodes one launch updates.  Synchronous. */
+ * dominant kernel; D2Q9 BGK / RR: the kernel that runs both fine substeps of
+ * a coarse step; H-RR: its second pass, which pulls again and collides with
+ * the strain rate of the velocities the first pass wrote): when enabled,
+ * lbm_step records HIP events around each of its launches on the launch
+ * stream; lbm_kernel_time returns the number of timed launches, their mean
+ * duration in ms and the lattice updates one launch performs (fine middle
+ * nodes times the substeps it runs).  Synchronous. */
 int lbm_profile_enable(lbm_handle h, int on);
 int lbm_kernel_time(lbm_handle h, int64_t* launches, double* mean_ms, int64_t* nodes_per_launch);
 

@@ -828,6 +828,135 @@ __global__ __launch_bounds__(256) void k_coalesce(const S* __restrict__ src_f, S
 }
 
 // ---------------------------------------------------------------------------
+// Both fine substeps of a coarse step in one kernel (D2Q9, BGK / RR).
+// A work group owns a tile of TXV vectors x TY rows of middle nodes.  Substep
+// 1 (t -> t+1/2) is computed into LDS for the tile and a one-node halo (one
+// vector on each side, one row above and below): middle nodes pull from src
+// and collide exactly as k_stream does; ring nodes take their t+1/2 values
+// from `half`, where the ring reconstruction stored them.  Substep 2
+// (t+1/2 -> t+1) then pulls from LDS and collides the tile, writing dst.  HBM
+// sees one read and one write of the populations per fine node per coarse
+// step instead of two of each; the arithmetic per node is that of two
+// k_stream launches, so the results are bitwise the same.  The t+1/2 state of
+// the middle nodes within 2 nodes of the TN line (where the fine-to-coarse
+// transfer pulls) is also stored into `half`.
+template <typename S>
+struct Fine2Tile {
+  static constexpr int V = VecOf<S>::V;
+  static constexpr int TXV = 32;                  // vectors per tile row
+  static constexpr int TY = 14;                   // tile rows
+  static constexpr int RV = TXV + 2, RH = TY + 2;  // substep-1 region (vectors, rows)
+  static constexpr int RW = RV * V;                // region width in nodes
+};
+
+template <int LAT, bool DEV, typename S, int MODEL, bool NT>
+__global__ __launch_bounds__(256) void k_fine2(const S* __restrict__ src, S* __restrict__ dst,
+                                               S* __restrict__ half, const Geo g, const S om, int ntx, int nty,
+                                               int per_xcd) {
+  using L = Lattice<LAT>;
+  using N = Node<LAT, DEV, S>;
+  using T = Fine2Tile<S>;
+  constexpr int V = T::V, Q = L::Q;
+  static_assert(L::D == 2, "fused fine substeps are two-dimensional");
+  using VA = typename VT<S, V>::a;
+  __shared__ S lds[Q][T::RH][T::RW];
+  const int b = blockIdx.x;
+  const int tile = (b % kXCD) * per_xcd + b / kXCD;
+  if (tile >= ntx * nty) return;  // whole work group, before any barrier
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int nx = g.nf[0], ny = g.nf[1];
+  const int nv = (nx - 1 + V - 1) / V;
+  const int64_t P = g.pf;
+  const int xo = g.fxo;
+  const int kx0 = tx * T::TXV, y0 = 1 + ty * T::TY;
+  auto in_band = [&](int x, int y) { return x <= 4 || x >= nx - 5 || y <= 4 || y >= ny - 5; };
+
+  // substep 1 into LDS
+  for (int e = threadIdx.x; e < T::RV * T::RH; e += 256) {
+    const int rv = e % T::RV, rr = e / T::RV;
+    const int k = kx0 - 1 + rv, y = y0 - 1 + rr;
+    if (y < 0 || y > ny - 1 || k < -1 || k >= nv) continue;  // never read
+    const int x0 = 1 + V * k;
+    const int c0 = rv * V;
+    if (y == 0 || y == ny - 1 || k == -1) {
+      // ring row, or the vector ending at ring node x = 0
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const int x = x0 + j;
+        if (x < 0 || x > nx - 1) continue;
+        const int64_t p = fpos(g, x, y, 0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lds[i][rr][c0 + j] = half[pop_at<S, Q>(p, i)];
+      }
+      continue;
+    }
+    const Pull<S, Q, V, 1, 2> pl(P, xo, x0, y, 0, nx, ny, 1);
+    VA v[Q];
+    pl.template load_all<L>(src, v);
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      S f[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) f[i] = v[i][j];
+      N::collide(f, MODEL, om, S(0), S(0), nullptr);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) v[i][j] = f[i];
+    }
+#pragma unroll
+    for (int j = 0; j < V; ++j)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) lds[i][rr][c0 + j] = v[i][j];
+    if (k == nv - 1) {
+      // the ring node x = nx - 1 inside the last vector of the row
+      const int jr = nx - 1 - x0;
+      const int64_t p = fpos(g, nx - 1, y, 0);
+      if (jr >= 0 && jr < V)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lds[i][rr][c0 + jr] = half[pop_at<S, Q>(p, i)];
+    }
+    if (rr >= 1 && rr <= T::TY && rv >= 1 && rv <= T::TXV) {
+      // tile interior: t+1/2 of the middle nodes the transfer pulls from
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const int x = x0 + j;
+        if (x > nx - 2 || !in_band(x, y)) continue;
+        const int64_t p = fpos(g, x, y, 0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) half[pop_at<S, Q>(p, i)] = v[i][j];
+      }
+    }
+  }
+  __syncthreads();
+
+  // substep 2 from LDS
+  for (int e = threadIdx.x; e < T::TXV * T::TY; e += 256) {
+    const int iv = e % T::TXV, ir = e / T::TXV;
+    const int k = kx0 + iv, y = y0 + ir;
+    if (k >= nv || y > ny - 2) continue;
+    const int x0 = 1 + V * k;
+    const int rr = ir + 1, c0 = (iv + 1) * V;
+    VA v[Q];
+    static_for<Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+#pragma unroll
+      for (int j = 0; j < V; ++j) v[i][j] = lds[i][rr - L::cy(i)][c0 + j - L::cx(i)];
+    });
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      S f[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) f[i] = v[i][j];
+      N::collide(f, MODEL, om, S(0), S(0), nullptr);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) v[i][j] = f[i];
+    }
+    const int64_t own = fpos(g, x0, y, 0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + pop_at<S, Q>(own, i)), v[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // State transfer kernels (logical x-fastest arrays <-> device storage).
 
 template <int LAT, bool DEV, typename S>

@@ -157,6 +157,7 @@ struct GridBase {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   int64_t prof_launches = 0;
   double prof_ms = 0.0;
+  int timed_factor = 1;  // fine substeps one timed launch performs
   virtual ~GridBase() {
     for (auto& e : events) {
       (void)hipEventDestroy(e.first);
@@ -199,9 +200,16 @@ struct Grid final : GridBase {
   static constexpr int kDefaultVar = 2;
   int var[4] = {kDefaultVar, kDefaultVar, kDefaultVar, kDefaultVar};
 
-  DevBuf cbuf[2], fbuf[2], mac_c, mac_f, hist[3], G, tmp_rho, tmp_u, tmp_f, part, tot;
+  DevBuf cbuf[2], fbuf[3], mac_c, mac_f, hist[3], G, tmp_rho, tmp_u, tmp_f, part, tot;
   DevBuf d_hnode, d_rnode, d_rnp, d_rpt, d_tnf, d_tnc;
   int cpar = 0;  // coarse buffer holding the current state
+  // Fine buffers: fbuf[fpar] holds the state at integer times.  D2Q9 BGK / RR
+  // run both fine substeps in one kernel (k_fine2) from fbuf[fpar] into the
+  // other buffer, which then becomes current; fbuf[2] receives the t+1/2 ring
+  // and the t+1/2 band the fine-to-coarse transfer pulls from.  Otherwise the
+  // substeps go fbuf[0] -> fbuf[1] -> fbuf[0] and fpar stays 0.
+  int fpar = 0;
+  bool fused = false;
   int hs[3] = {0, 1, 2};
   Iface itf{};
   double tau_c = 0, tau_f = 0, sig = 0;
@@ -217,9 +225,11 @@ struct Grid final : GridBase {
   static size_t pop_bytes(int64_t NP) { return sizeof(S) * (size_t)pop_elems<S>(NP, Q); }
 
   void init() override {
+    fused = D == 2 && desc.collision != LBM_HRR && g.has_fine;
+    timed_factor = fused ? 2 : 1;
     for (int p = 0; p < 2; ++p) cbuf[p].alloc(pop_bytes(g.Ncp));
     if (g.has_fine)
-      for (int p = 0; p < 2; ++p) fbuf[p].alloc(pop_bytes(g.Nfp));
+      for (int p = 0; p < (fused ? 3 : 2); ++p) fbuf[p].alloc(pop_bytes(g.Nfp));
     if (desc.collision == LBM_HRR) {
       mac_c.alloc(plane_bytes(g.Ncp, 1 + D));
       if (g.has_fine) mac_f.alloc(plane_bytes(g.Nfp, 1 + D));
@@ -258,7 +268,7 @@ struct Grid final : GridBase {
     tot.alloc(sizeof(double) * 4);
     for (int p = 0; p < 2; ++p) HIPCHK(hipMemset(cbuf[p].p, 0, cbuf[p].bytes));
     if (g.has_fine)
-      for (int p = 0; p < 2; ++p) HIPCHK(hipMemset(fbuf[p].p, 0, fbuf[p].bytes));
+      for (int p = 0; p < (fused ? 3 : 2); ++p) HIPCHK(hipMemset(fbuf[p].p, 0, fbuf[p].bytes));
     if (mac_c.p) HIPCHK(hipMemset(mac_c.p, 0, mac_c.bytes));
     if (mac_f.p) HIPCHK(hipMemset(mac_f.p, 0, mac_f.bytes));
   }
@@ -273,8 +283,8 @@ struct Grid final : GridBase {
   }
 
   S* cur_c() { return cbuf[cpar].as<S>(); }
-  S* fineA() { return fbuf[0].as<S>(); }
-  S* fineB() { return fbuf[1].as<S>(); }
+  S* fineA() { return fbuf[fpar].as<S>(); }       // state at integer times
+  S* fineB() { return fbuf[fpar ^ 1].as<S>(); }   // the other buffer
 
   template <int MODEL, int LEVEL>
   void launch_stream(const S* src, S* dst, S* mac, double tau, hipStream_t s, int v = -1) {
@@ -292,6 +302,19 @@ struct Grid final : GridBase {
     if (f.nchunks == 0) return;
     hipLaunchKernelGGL((k_collide_hrr<LAT, DEV, S, LEVEL, NT>), dim3((unsigned)(f.per_xcd * kXCD)), dim3(256),
                        (unsigned)kVarLds[v], s, src, dst, mac, g, f, (S)(1.0 - 1.0 / tau), (S)tau, (S)sig);
+  }
+
+  // Both fine substeps (D2Q9 BGK / RR), src -> dst, t+1/2 ring and band in half.
+  template <int MODEL>
+  void launch_fine2(const S* src, S* dst, S* half, hipStream_t s) {
+    if constexpr (D == 2 && MODEL != M_HRR) {
+      using T = Fine2Tile<S>;
+      const int nv = (g.nf[0] - 1 + V - 1) / V;
+      const int ntx = (nv + T::TXV - 1) / T::TXV, nty = (g.nf[1] - 2 + T::TY - 1) / T::TY;
+      const int per = (ntx * nty + kXCD - 1) / kXCD;
+      hipLaunchKernelGGL((k_fine2<LAT, DEV, S, MODEL, NT>), dim3((unsigned)(per * kXCD)), dim3(256), 0, s, src, dst,
+                         half, g, (S)(1.0 - 1.0 / tau_f), ntx, nty, per);
+    }
   }
 
   // Runs fn (one launch) between HIP events on s when profiling is on.
@@ -356,6 +379,7 @@ struct Grid final : GridBase {
       const bool used = (role & 1) ? g.has_fine : true;
       const bool hrr_role = role >= 2;
       if (!used || (hrr_role && desc.collision != LBM_HRR)) continue;
+      if (role == 1 && fused) continue;  // k_fine2 has one launch shape
       float best = -1.f;
       for (int v = 0; v < NVAR; ++v) {
         role_launch(role, v, stream);
@@ -412,7 +436,18 @@ struct Grid final : GridBase {
     const unsigned bh = xblocks(NH, IB), br = xblocks(itf.NR, IB), bt = xblocks(itf.NT, IB), bg = blocks(NH * F::N, 256);
     const unsigned bc = xblocks(itf.NT, PER);
     hipLaunchKernelGGL((k_hist_capture<LAT, DEV, S, MODEL>), dim3(bh), dim3(IB), 0, s, csrc, Hp, g, itf);
-    if (MODEL != M_HRR) {
+    if (MODEL != M_HRR && fused) {
+      S* fH = fbuf[2].as<S>();
+      launch_stream<MODEL, 0>(csrc, cdst, nullptr, tau_c, s);
+      hipLaunchKernelGGL(k_hist_time, dim3(bg), dim3(256), 0, s, Hm, H0, Hp, G.as<double>(), NH * F::N, c0, c1, c2);
+      hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL, true>), dim3(br), dim3(IB), 0, s, G.as<double>(), fH, g, itf, kf, omf,
+                         tau_f, sig);
+      timed(s, [&] { launch_fine2<MODEL>(fA, fB, fH, s); });
+      hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL, true>), dim3(br), dim3(IB), 0, s, Hp, fB, g, itf, kf, omf, tau_f, sig);
+      hipLaunchKernelGGL((k_coalesce<LAT, DEV, S, MODEL>), dim3(bc), dim3(256), 0, s, fH, cdst, g, itf, kc, omc,
+                         tau_c, sig);
+      fpar ^= 1;
+    } else if (MODEL != M_HRR) {
       launch_stream<MODEL, 0>(csrc, cdst, nullptr, tau_c, s);
       fine_stream_timed(MODEL, fA, fB, s);
       hipLaunchKernelGGL(k_hist_time, dim3(bg), dim3(256), 0, s, Hm, H0, Hp, G.as<double>(), NH * F::N, c0, c1, c2);
@@ -1424,7 +1459,7 @@ int lbm_kernel_time(lbm_handle h, int64_t* launches, double* mean_ms, int64_t* n
     *mean_ms = G.prof_launches ? G.prof_ms / (double)G.prof_launches : 0.0;
     int64_t mid = 1;
     for (int d = 0; d < G.g.D; ++d) mid *= (G.g.has_fine ? G.g.nf[d] - 2 : 0);
-    *nodes_per_launch = mid;
+    *nodes_per_launch = mid * G.timed_factor;
   });
 }
 
