@@ -162,8 +162,12 @@ int lbm_kernel_time(lbm_handle h, int64_t* launches, double* mean_ms, int64_t* n
 
 /* Bulk-kernel launch variants, 0 .. LBM_N_VARIANTS - 1: the same kernels
  * launched with 0, 53, 80 or 160 KB of unused LDS per 256-lane work group,
- * which caps the work groups resident on a CU (no cap, 3, 2, 1).  Every
- * variant computes bitwise the same result. */
+ * which caps the work groups resident on a CU (no cap, 3, 2, 1).  For the
+ * fine role of a D2Q9 BGK / RR grid, whose kernel runs both substeps with
+ * the half-step state in LDS, the variants are tile shapes (vectors x rows)
+ * and register budgets (waves per SIMD the compiler must fit): 32 x 6,
+ * 32 x 6 at 4, 32 x 4 at 5 and 16 x 6 at 6.  Every variant computes bitwise
+ * the same result. */
 enum { LBM_N_VARIANTS = 4 };
 /* Autotuner: times every bulk-kernel variant of each bulk role of this grid
  * -- coarse stream, fine stream, coarse and fine H-RR collision -- over reps

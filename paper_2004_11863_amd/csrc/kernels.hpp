@@ -840,119 +840,143 @@ __global__ __launch_bounds__(256) void k_coalesce(const S* __restrict__ src_f, S
 // k_stream launches, so the results are bitwise the same.  The t+1/2 state of
 // the middle nodes within 2 nodes of the TN line (where the fine-to-coarse
 // transfer pulls) is also stored into `half`.
-template <typename S>
-struct Fine2Tile {
-  static constexpr int V = VecOf<S>::V;
-  static constexpr int TXV = 32;                  // vectors per tile row
-  static constexpr int TY = 14;                   // tile rows
-  static constexpr int RV = TXV + 2, RH = TY + 2;  // substep-1 region (vectors, rows)
-  static constexpr int RW = RV * V;                // region width in nodes
-};
+// Substep 1 of one vector (node x0 = 1 + V k of row y) into an LDS row
+// (`row[i]` points at population i of that row, c0 the vector's first
+// column).  Middle nodes pull from src and collide; ring nodes take their
+// t+1/2 values from `half`; `band` asks to store the result of middle nodes
+// within 2 nodes of the TN line into `half` as well.
+template <int LAT, bool DEV, typename S, int MODEL>
+__device__ __forceinline__ void fine2_s1(const S* __restrict__ src, S* __restrict__ half, const Geo& g, const S om,
+                                         int k, int y, int nv, S* const* row, int c0, bool band) {
+  using L = Lattice<LAT>;
+  using N = Node<LAT, DEV, S>;
+  constexpr int V = VecOf<S>::V, Q = L::Q;
+  using VA = typename VT<S, V>::a;
+  const int nx = g.nf[0], ny = g.nf[1];
+  const int x0 = 1 + V * k;
+  if (y == 0 || y == ny - 1 || k == -1) {
+    // ring row, or the vector ending at ring node x = 0
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int x = x0 + j;
+      if (x < 0 || x > nx - 1) continue;
+      const int64_t p = fpos(g, x, y, 0);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) row[i][c0 + j] = half[pop_at<S, Q>(p, i)];
+    }
+    return;
+  }
+  const Pull<S, Q, V, 1, 2> pl(g.pf, g.fxo, x0, y, 0, nx, ny, 1);
+  VA v[Q];
+  pl.template load_all<L>(src, v);
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    S f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = v[i][j];
+    N::collide(f, MODEL, om, S(0), S(0), nullptr);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i][j] = f[i];
+  }
+#pragma unroll
+  for (int j = 0; j < V; ++j)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) row[i][c0 + j] = v[i][j];
+  if (k == nv - 1) {
+    // the ring node x = nx - 1 inside the last vector of the row
+    const int jr = nx - 1 - x0;
+    const int64_t p = fpos(g, nx - 1, y, 0);
+    if (jr >= 0 && jr < V)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) row[i][c0 + jr] = half[pop_at<S, Q>(p, i)];
+  }
+  if (band) {
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int x = x0 + j;
+      if (x > nx - 2 || !(x <= 4 || x >= nx - 5 || y <= 4 || y >= ny - 5)) continue;
+      const int64_t p = fpos(g, x, y, 0);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) half[pop_at<S, Q>(p, i)] = v[i][j];
+    }
+  }
+}
 
+// Substep 2 of one vector (node x0 = 1 + V k of row y) from LDS: population i
+// is read from the row holding y - cy_i (rows[1 - cy_i]) at column c0 + j -
+// cx_i; the result is stored to dst.
 template <int LAT, bool DEV, typename S, int MODEL, bool NT>
-__global__ __launch_bounds__(256) void k_fine2(const S* __restrict__ src, S* __restrict__ dst,
+__device__ __forceinline__ void fine2_s2(S* __restrict__ dst, const Geo& g, const S om, int k, int y,
+                                         S* const* rm, S* const* r0, S* const* rp, int c0) {
+  using L = Lattice<LAT>;
+  using N = Node<LAT, DEV, S>;
+  constexpr int V = VecOf<S>::V, Q = L::Q;
+  using VA = typename VT<S, V>::a;
+  VA v[Q];
+  static_for<Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    S* const* rows = L::cy(i) == 1 ? rm : (L::cy(i) == 0 ? r0 : rp);
+#pragma unroll
+    for (int j = 0; j < V; ++j) v[i][j] = rows[i][c0 + j - L::cx(i)];
+  });
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    S f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = v[i][j];
+    N::collide(f, MODEL, om, S(0), S(0), nullptr);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i][j] = f[i];
+  }
+  const int64_t own = fpos(g, 1 + V * k, y, 0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + pop_at<S, Q>(own, i)), v[i]);
+}
+
+// Tiles (k_fine2): a work group owns TXV vectors x TY rows of middle nodes
+// and computes substep 1 for the tile plus a one-node halo (one vector on
+// each side, one row above and below) into LDS, then substep 2 for the tile.
+// MINW asks the compiler to fit that many waves per SIMD (registers), so
+// small tiles can be resident several at a time.
+template <int LAT, bool DEV, typename S, int MODEL, bool NT, int TXV, int TY, int MINW>
+__global__ __launch_bounds__(256, MINW) void k_fine2(const S* __restrict__ src, S* __restrict__ dst,
                                                S* __restrict__ half, const Geo g, const S om, int ntx, int nty,
                                                int per_xcd) {
   using L = Lattice<LAT>;
-  using N = Node<LAT, DEV, S>;
-  using T = Fine2Tile<S>;
-  constexpr int V = T::V, Q = L::Q;
+  constexpr int V = VecOf<S>::V, Q = L::Q;
+  constexpr int RV = TXV + 2, RH = TY + 2, RW = RV * V;
   static_assert(L::D == 2, "fused fine substeps are two-dimensional");
-  using VA = typename VT<S, V>::a;
-  __shared__ S lds[Q][T::RH][T::RW];
+  __shared__ S lds[Q][RH][RW];
   const int b = blockIdx.x;
   const int tile = (b % kXCD) * per_xcd + b / kXCD;
   if (tile >= ntx * nty) return;  // whole work group, before any barrier
   const int tx = tile % ntx, ty = tile / ntx;
-  const int nx = g.nf[0], ny = g.nf[1];
-  const int nv = (nx - 1 + V - 1) / V;
-  const int64_t P = g.pf;
-  const int xo = g.fxo;
-  const int kx0 = tx * T::TXV, y0 = 1 + ty * T::TY;
-  auto in_band = [&](int x, int y) { return x <= 4 || x >= nx - 5 || y <= 4 || y >= ny - 5; };
-
-  // substep 1 into LDS
-  for (int e = threadIdx.x; e < T::RV * T::RH; e += 256) {
-    const int rv = e % T::RV, rr = e / T::RV;
+  const int ny = g.nf[1];
+  const int nv = (g.nf[0] - 1 + V - 1) / V;
+  const int kx0 = tx * TXV, y0 = 1 + ty * TY;
+  for (int e = threadIdx.x; e < RV * RH; e += 256) {
+    const int rv = e % RV, rr = e / RV;
     const int k = kx0 - 1 + rv, y = y0 - 1 + rr;
     if (y < 0 || y > ny - 1 || k < -1 || k >= nv) continue;  // never read
-    const int x0 = 1 + V * k;
-    const int c0 = rv * V;
-    if (y == 0 || y == ny - 1 || k == -1) {
-      // ring row, or the vector ending at ring node x = 0
+    S* row[Q];
 #pragma unroll
-      for (int j = 0; j < V; ++j) {
-        const int x = x0 + j;
-        if (x < 0 || x > nx - 1) continue;
-        const int64_t p = fpos(g, x, y, 0);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) lds[i][rr][c0 + j] = half[pop_at<S, Q>(p, i)];
-      }
-      continue;
-    }
-    const Pull<S, Q, V, 1, 2> pl(P, xo, x0, y, 0, nx, ny, 1);
-    VA v[Q];
-    pl.template load_all<L>(src, v);
-#pragma unroll
-    for (int j = 0; j < V; ++j) {
-      S f[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) f[i] = v[i][j];
-      N::collide(f, MODEL, om, S(0), S(0), nullptr);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) v[i][j] = f[i];
-    }
-#pragma unroll
-    for (int j = 0; j < V; ++j)
-#pragma unroll
-      for (int i = 0; i < Q; ++i) lds[i][rr][c0 + j] = v[i][j];
-    if (k == nv - 1) {
-      // the ring node x = nx - 1 inside the last vector of the row
-      const int jr = nx - 1 - x0;
-      const int64_t p = fpos(g, nx - 1, y, 0);
-      if (jr >= 0 && jr < V)
-#pragma unroll
-        for (int i = 0; i < Q; ++i) lds[i][rr][c0 + jr] = half[pop_at<S, Q>(p, i)];
-    }
-    if (rr >= 1 && rr <= T::TY && rv >= 1 && rv <= T::TXV) {
-      // tile interior: t+1/2 of the middle nodes the transfer pulls from
-#pragma unroll
-      for (int j = 0; j < V; ++j) {
-        const int x = x0 + j;
-        if (x > nx - 2 || !in_band(x, y)) continue;
-        const int64_t p = fpos(g, x, y, 0);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) half[pop_at<S, Q>(p, i)] = v[i][j];
-      }
-    }
+    for (int i = 0; i < Q; ++i) row[i] = &lds[i][rr][0];
+    const bool interior = rr >= 1 && rr <= TY && rv >= 1 && rv <= TXV;
+    fine2_s1<LAT, DEV, S, MODEL>(src, half, g, om, k, y, nv, row, rv * V, interior);
   }
   __syncthreads();
-
-  // substep 2 from LDS
-  for (int e = threadIdx.x; e < T::TXV * T::TY; e += 256) {
-    const int iv = e % T::TXV, ir = e / T::TXV;
+  for (int e = threadIdx.x; e < TXV * TY; e += 256) {
+    const int iv = e % TXV, ir = e / TXV;
     const int k = kx0 + iv, y = y0 + ir;
     if (k >= nv || y > ny - 2) continue;
-    const int x0 = 1 + V * k;
-    const int rr = ir + 1, c0 = (iv + 1) * V;
-    VA v[Q];
-    static_for<Q>([&](auto I) {
-      constexpr int i = decltype(I)::value;
+    S *rm[Q], *r0[Q], *rp[Q];
 #pragma unroll
-      for (int j = 0; j < V; ++j) v[i][j] = lds[i][rr - L::cy(i)][c0 + j - L::cx(i)];
-    });
-#pragma unroll
-    for (int j = 0; j < V; ++j) {
-      S f[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i) f[i] = v[i][j];
-      N::collide(f, MODEL, om, S(0), S(0), nullptr);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) v[i][j] = f[i];
+    for (int i = 0; i < Q; ++i) {
+      rm[i] = &lds[i][ir][0];
+      r0[i] = &lds[i][ir + 1][0];
+      rp[i] = &lds[i][ir + 2][0];
     }
-    const int64_t own = fpos(g, x0, y, 0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + pop_at<S, Q>(own, i)), v[i]);
+    fine2_s2<LAT, DEV, S, MODEL, NT>(dst, g, om, k, y, rm, r0, rp, (iv + 1) * V);
   }
 }
 

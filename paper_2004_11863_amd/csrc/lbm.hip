@@ -227,6 +227,7 @@ struct Grid final : GridBase {
   void init() override {
     fused = D == 2 && desc.collision != LBM_HRR && g.has_fine;
     timed_factor = fused ? 2 : 1;
+    if (fused) var[1] = 0;
     for (int p = 0; p < 2; ++p) cbuf[p].alloc(pop_bytes(g.Ncp));
     if (g.has_fine)
       for (int p = 0; p < (fused ? 3 : 2); ++p) fbuf[p].alloc(pop_bytes(g.Nfp));
@@ -305,15 +306,27 @@ struct Grid final : GridBase {
   }
 
   // Both fine substeps (D2Q9 BGK / RR), src -> dst, t+1/2 ring and band in half.
-  template <int MODEL>
-  void launch_fine2(const S* src, S* dst, S* half, hipStream_t s) {
+  // Both fine substeps (D2Q9 BGK / RR), src -> dst, t+1/2 ring and band in
+  // half.  Variants of the fine role (tile vectors x rows, waves per SIMD the
+  // registers must allow): 32 x 6, 32 x 6 at 4, 32 x 4 at 5, 16 x 6 at 6.
+  template <int MODEL, int TXV, int TY, int MINW>
+  void go_fine2(const S* src, S* dst, S* half, hipStream_t s) {
     if constexpr (D == 2 && MODEL != M_HRR) {
-      using T = Fine2Tile<S>;
       const int nv = (g.nf[0] - 1 + V - 1) / V;
-      const int ntx = (nv + T::TXV - 1) / T::TXV, nty = (g.nf[1] - 2 + T::TY - 1) / T::TY;
+      const int ntx = (nv + TXV - 1) / TXV, nty = (g.nf[1] - 2 + TY - 1) / TY;
       const int per = (ntx * nty + kXCD - 1) / kXCD;
-      hipLaunchKernelGGL((k_fine2<LAT, DEV, S, MODEL, NT>), dim3((unsigned)(per * kXCD)), dim3(256), 0, s, src, dst,
-                         half, g, (S)(1.0 - 1.0 / tau_f), ntx, nty, per);
+      hipLaunchKernelGGL((k_fine2<LAT, DEV, S, MODEL, NT, TXV, TY, MINW>), dim3((unsigned)(per * kXCD)), dim3(256), 0,
+                         s, src, dst, half, g, (S)(1.0 - 1.0 / tau_f), ntx, nty, per);
+    }
+  }
+  template <int MODEL>
+  void launch_fine2(const S* src, S* dst, S* half, hipStream_t s, int v = -1) {
+    if (v < 0) v = var[1];
+    switch (v) {
+      case 0: go_fine2<MODEL, 32, 6, 1>(src, dst, half, s); break;
+      case 1: go_fine2<MODEL, 32, 6, 4>(src, dst, half, s); break;
+      case 2: go_fine2<MODEL, 32, 4, 5>(src, dst, half, s); break;
+      default: go_fine2<MODEL, 16, 6, 6>(src, dst, half, s); break;
     }
   }
 
@@ -352,6 +365,11 @@ struct Grid final : GridBase {
       if (model == M_BGK) launch_stream<M_BGK, 0>(c_cur, c_oth, nullptr, tau_c, s, v);
       else if (model == M_RR) launch_stream<M_RR, 0>(c_cur, c_oth, nullptr, tau_c, s, v);
       else launch_stream<M_HRR, 0>(c_cur, c_oth, mac_c.as<S>(), tau_c, s, v);
+    } else if (role == 1 && fused) {
+      // both substeps: writes the other buffer and the t+1/2 band, which the
+      // next step rewrites
+      if (model == M_BGK) launch_fine2<M_BGK>(fineA(), fineB(), fbuf[2].as<S>(), s, v);
+      else launch_fine2<M_RR>(fineA(), fineB(), fbuf[2].as<S>(), s, v);
     } else if (role == 1) {
       if (model == M_BGK) launch_stream<M_BGK, 1>(fineA(), fineB(), nullptr, tau_f, s, v);
       else if (model == M_RR) launch_stream<M_RR, 1>(fineA(), fineB(), nullptr, tau_f, s, v);
@@ -379,7 +397,7 @@ struct Grid final : GridBase {
       const bool used = (role & 1) ? g.has_fine : true;
       const bool hrr_role = role >= 2;
       if (!used || (hrr_role && desc.collision != LBM_HRR)) continue;
-      if (role == 1 && fused) continue;  // k_fine2 has one launch shape
+
       float best = -1.f;
       for (int v = 0; v < NVAR; ++v) {
         role_launch(role, v, stream);
