@@ -120,9 +120,11 @@ def timed_run(grid, steps, warmup, profile, tune=True):
     return t1 - t0, kt
 
 
-def stored_traffic(kernel_hash, key):
+def stored_traffic(kernel_hash, key, variant=None):
     """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, or None if it was taken on other code."""
+    rocprofv3 counter summary, or None if it was taken on other code.  Where
+    the launch variants are distinct kernels (the fused D2Q9 fine kernel's
+    tile shapes) the entry holds one figure per variant."""
     try:
         with open(TRAFFIC_FILE) as fh:
             d = json.load(fh)
@@ -131,6 +133,8 @@ def stored_traffic(kernel_hash, key):
     if d.get("kernel_source_hash") != kernel_hash:
         return None
     e = d.get("entries", {}).get(key)
+    if e is not None and "by_variant" in e:
+        e = e["by_variant"].get(str(variant))
     return None if e is None else e.get("hbm_bytes_per_launch")
 
 
@@ -319,7 +323,7 @@ def main():
     variants = getattr(grid, "variants", None)
     khash = kernel_source_hash()
     key = f"{args.workload}/{args.collision}/{args.precision}"
-    traffic = stored_traffic(khash, key)
+    traffic = stored_traffic(khash, key, None if variants is None else variants[1])
     grid.close()
     del grid
     torch.cuda.empty_cache()

@@ -92,8 +92,11 @@ typedef struct {
 
 /* Creates a grid: validates the descriptor, builds the node-class maps and
  * interface stencil tables, allocates all device state (two population
- * buffers per level, the three-time-level coarse history, stencil tables)
- * and a non-blocking stream.  The state is zero until lbm_set_state. */
+ * buffers per level, a third fine one for BGK / RR, the three-time-level
+ * coarse history, stencil tables) and a non-blocking stream.  The state is
+ * zero until lbm_set_state.  LBM_EINVAL for a bad descriptor, including a
+ * level of 2^31 or more padded node positions (rows padded to a multiple of
+ * 4 nodes). */
 int lbm_create_grid(const lbm_grid_desc* d, lbm_handle* out);
 int lbm_destroy(lbm_handle h);
 
@@ -164,10 +167,13 @@ int lbm_kernel_time(lbm_handle h, int64_t* launches, double* mean_ms, int64_t* n
  * launched with 0, 53, 80 or 160 KB of unused LDS per 256-lane work group,
  * which caps the work groups resident on a CU (no cap, 3, 2, 1).  For the
  * fine role of a D2Q9 BGK / RR grid, whose kernel runs both substeps with
- * the half-step state in LDS, the variants are tile shapes (vectors x rows)
+ * the half-step state on chip, the variants are tile shapes (vectors x rows)
  * and register budgets (waves per SIMD the compiler must fit): 32 x 6,
- * 32 x 6 at 4, 32 x 4 at 5 and 16 x 6 at 6.  Every variant computes bitwise
- * the same result. */
+ * 32 x 6 at 4, 32 x 4 at 5 and 16 x 6 at 6.  For the fine role of a D3Q19
+ * BGK / RR grid, variants 0 and 1 run the two substeps as two launches
+ * (capped at 2 and 3 resident work groups per CU), 2 and 3 as one kernel
+ * walking tiles of 14 x 14 and 30 x 6 along z.  Every variant computes
+ * bitwise the same result. */
 enum { LBM_N_VARIANTS = 4 };
 /* Autotuner: times every bulk-kernel variant of each bulk role of this grid
  * -- coarse stream, fine stream, coarse and fine H-RR collision -- over reps
@@ -221,8 +227,11 @@ int lbm_batch_info(lbm_batch_handle b, int64_t info[3]);
 /* Coarse steps taken by a grid since it joined (or since its last
  * lbm_batch_set_state of level 0). */
 int lbm_batch_slot_steps(lbm_batch_handle b, int slot, int64_t* steps);
-/* Device bytes a grid of this descriptor occupies (populations, macro
- * planes, history, interface tables), for admission by memory footprint. */
+/* Device bytes a grid of this descriptor occupies in a batch slot
+ * (populations, macro planes, history, interface tables), for admission by
+ * memory footprint.  A single grid (lbm_create_grid) with BGK or RR and a
+ * fine patch holds one more fine population buffer (the half-step ring and
+ * band of its fused fine kernel). */
 int lbm_footprint(const lbm_grid_desc* d, int64_t* bytes);
 const char* lbm_batch_last_error(lbm_batch_handle b);
 

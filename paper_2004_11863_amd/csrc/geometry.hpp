@@ -25,7 +25,9 @@ enum FineClass : int { FC_MIDDLE = 0, FC_TF = 1, FC_IE = 2, FC_IEFACE = 3, FC_TN
 // a multiple of 4) so every row starts 16-byte aligned; Ncp, Nfp are the
 // padded node counts of a level (the positions of pop_at below, and the plane
 // size of the velocity planes).  Nc, Nf count logical nodes (the x-fastest
-// order of the C ABI and of the interface tables).
+// order of the C ABI and of the interface tables).  (A power-of-two fine
+// pitch, which keeps rows inside one storage block, was measured slower: rows
+// a power of two apart share HBM channels.)
 struct Geo {
   int D;
   int n[3];   // coarse nodes per axis (1 on unused axes)
@@ -115,11 +117,13 @@ struct PopBlock {
   static constexpr int SHIFT = sizeof(S) == 4 ? 13 : 12;  // 8192 floats or 4096 doubles
   static constexpr int64_t B = (int64_t)1 << SHIFT;
 };
+// Written as base(p) + q B, base(p) = p + (Q - 1) B floor(p / B), which is
+// ((p / B) Q + q) B + p mod B: the Q populations of a node share base(p).
 template <typename S, int Q>
 __host__ __device__ inline int64_t pop_at(int64_t p, int q) {
   constexpr int SH = PopBlock<S>::SHIFT;
   constexpr int64_t B = PopBlock<S>::B;
-  return (((p >> SH) * Q + q) << SH) + (p & (B - 1));
+  return p + (int64_t)(Q - 1) * B * (p >> SH) + (int64_t)q * B;
 }
 // Elements of a population buffer for NP padded positions: whole blocks up
 // to and including position NP (the last x-vector of a fine row reaches one

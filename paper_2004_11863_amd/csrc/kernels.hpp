@@ -117,16 +117,18 @@ __device__ __forceinline__ int64_t xcd_block() {
 
 // First node x0 of this work-item's V-node vector in chunk `chunk`; false
 // past the last vector.
+// (The vector count of a level is below 2^31, checked on the host, so the
+// index arithmetic is 32-bit.)
 template <int V>
 __device__ __forceinline__ bool flat_vec(const Flat& f, int chunk, int& x0, int& y, int& z) {
   if (chunk >= f.nchunks) return false;
-  const int64_t v = (int64_t)chunk * 256 + threadIdx.x;
-  if (v >= f.nvec) return false;
-  const int64_t r = v / f.nv;
-  const int vi = (int)(v - r * f.nv);
-  x0 = f.xb + vi * V;
-  y = f.y0 + (int)(r % f.nyr);
-  z = f.z0 + (int)(r / f.nyr);
+  const uint32_t v = (uint32_t)chunk * 256u + threadIdx.x;
+  if ((int64_t)v >= f.nvec) return false;
+  const uint32_t r = v / (uint32_t)f.nv;
+  x0 = f.xb + (int)(v - r * (uint32_t)f.nv) * V;
+  const uint32_t zq = r / (uint32_t)f.nyr;
+  y = f.y0 + (int)(r - zq * (uint32_t)f.nyr);
+  z = f.z0 + (int)zq;
   return true;
 }
 
@@ -198,10 +200,10 @@ struct Pull {
   template <int CX, int CY, int CZ>
   __device__ __forceinline__ VA load(const S* __restrict__ src, int q) const {
     constexpr int r = row<CY, CZ>();
-    const int64_t b = rb[r];
-    if (CX == 0) return *(const VA*)(src + pop_at<S, Q>(b, q));
-    const int64_t p = gathered<CX, CY>(r) ? b : b - CX;
-    return (VA)(*(const VU*)(src + pop_at<S, Q>(p, q)));
+    const int64_t a = pop_at<S, Q>(rb[r], q);
+    if (CX == 0) return *(const VA*)(src + a);
+    // a lane that is not gathered stays inside the storage block of rb[r]
+    return (VA)(*(const VU*)(src + (gathered<CX, CY>(r) ? a : a - CX)));
   }
   // Element-wise load for lanes whose shifted load is gathered.
   template <int CX, int CY, int CZ>
@@ -977,6 +979,204 @@ __global__ __launch_bounds__(256, MINW) void k_fine2(const S* __restrict__ src, 
       rp[i] = &lds[i][ir + 2][0];
     }
     fine2_s2<LAT, DEV, S, MODEL, NT>(dst, g, om, k, y, rm, r0, rp, (iv + 1) * V);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Both fine substeps of a coarse step in one kernel (D3Q19, BGK / RR).
+// A work group owns TXV vectors x TY rows of middle nodes over a run of zlen
+// planes and walks it along z.  The iteration for plane z computes substep 1
+// (t -> t+1/2) of plane z+1 for the tile and a one-node halo in x and y
+// (middle nodes pull and collide as k_stream does, ring nodes read `half`,
+// where the ring reconstruction stored them), then substep 2 of plane z.
+// Substep 2 pulls population i from plane z - cz_i: the 16 populations that
+// move in x or y come from neighbouring lanes through one LDS plane of 16
+// slots (cz = -1: the plane just computed; cz = 0: computed one iteration
+// earlier; cz = +1: two iterations earlier -- every lane keeps its own
+// column's values in registers until their turn), the 3 that move along z
+// only come from the lane's own registers.  HBM sees one read and one write
+// per fine node per coarse step; the arithmetic is that of two k_stream
+// launches, so the results are bitwise the same.  The t+1/2 state of middle
+// nodes within 4 nodes of a patch face (what the fine-to-coarse transfer
+// pulls) is stored into `half`.
+template <int LAT>
+struct Fine3Sets {
+  using L = Lattice<LAT>;
+  __host__ __device__ static constexpr bool moving(int i) { return L::cx(i) != 0 || L::cy(i) != 0; }
+  __host__ __device__ static constexpr int count(int i, int cz) {
+    int s = 0;
+    for (int k = 0; k < i; ++k) s += (moving(k) && (cz == 2 || L::cz(k) == cz)) ? 1 : 0;
+    return s;
+  }
+  __host__ __device__ static constexpr int slot(int i) { return count(i, 2); }  // LDS slot of a moving population
+  __host__ __device__ static constexpr int uidx(int i) { return count(i, 1); }  // among moving, cz = +1
+  __host__ __device__ static constexpr int midx(int i) { return count(i, 0); }  // among moving, cz = 0
+  static constexpr int NS = count(L::Q, 2), NU = count(L::Q, 1), NM = count(L::Q, 0);
+};
+
+// Substep 1 of one vector (node x0 = 1 + V k of row y, plane z) into T.
+// `band` asks to store middle nodes within 4 nodes of a face into `half`.
+template <int LAT, bool DEV, typename S, int MODEL>
+__device__ __forceinline__ void fine3_s1(const S* __restrict__ src, S* __restrict__ half, const Geo& g, const S om,
+                                         int k, int y, int z, int nv, typename VT<S, VecOf<S>::V>::a* T, bool band) {
+  using L = Lattice<LAT>;
+  using N = Node<LAT, DEV, S>;
+  constexpr int V = VecOf<S>::V, Q = L::Q;
+  using VA = typename VT<S, V>::a;
+  const int nx = g.nf[0], ny = g.nf[1], nz = g.nf[2];
+  const int x0 = 1 + V * k;
+  if (y == 0 || y == ny - 1 || z == 0 || z == nz - 1 || k == -1) {
+    // ring row or plane, or the vector ending at ring node x = 0
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int x = x0 + j;
+      const bool in = x >= 0 && x <= nx - 1;
+      const int64_t p = fpos(g, in ? x : 0, y, z);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) T[i][j] = in ? half[pop_at<S, Q>(p, i)] : S(0);
+    }
+    return;
+  }
+  const Pull<S, Q, V, 1, 3> pl(g.pf, g.fxo, x0, y, z, nx, ny, nz);
+  pl.template load_all<L>(src, T);
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    S f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = T[i][j];
+    N::collide(f, MODEL, om, S(0), S(0), nullptr);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) T[i][j] = f[i];
+  }
+  if (k == nv - 1) {
+    // the ring node x = nx - 1 inside the last vector of the row
+    const int jr = nx - 1 - x0;
+    if (jr >= 0 && jr < V) {
+      const int64_t p = fpos(g, nx - 1, y, z);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const S h = half[pop_at<S, Q>(p, i)];
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          if (j == jr) T[i][j] = h;
+      }
+    }
+  }
+  if (band) {
+    const bool rows = y <= 4 || y >= ny - 5 || z <= 4 || z >= nz - 5;
+    const int64_t p0 = fpos(g, x0, y, z);
+    if (rows && x0 + V - 1 <= nx - 2) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) *(VA*)(half + pop_at<S, Q>(p0, i)) = T[i];
+    } else {
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const int x = x0 + j;
+        if (x > nx - 2 || !(rows || x <= 4 || x >= nx - 5)) continue;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) half[pop_at<S, Q>(p0 + j, i)] = T[i][j];
+      }
+    }
+  }
+}
+
+template <int LAT, bool DEV, typename S, int MODEL, bool NT, int TXV, int TY, int MINW>
+__global__ __launch_bounds__(256, MINW) void k_fine3(const S* __restrict__ src, S* __restrict__ dst,
+                                                     S* __restrict__ half, const Geo g, const S om, int ntx, int nty,
+                                                     int nzc, int zlen, int per_xcd) {
+  using L = Lattice<LAT>;
+  using N = Node<LAT, DEV, S>;
+  using C = Fine3Sets<LAT>;
+  constexpr int V = VecOf<S>::V, Q = L::Q;
+  using VA = typename VT<S, V>::a;
+  constexpr int HX = TXV + 2, HY = TY + 2, RW = HX * V;
+  static_assert(L::D == 3, "the marching fused kernel is three-dimensional");
+  static_assert(HX * HY <= 256, "one lane per tile-and-halo vector");
+  static_assert(C::NS == 16 && C::NU == 4 && C::NM == 8, "D3Q19 population classes");
+  __shared__ S lds[C::NS][HY][RW];
+  const int b = blockIdx.x;
+  const int item = (b % kXCD) * per_xcd + b / kXCD;
+  const int ntile = ntx * nty;
+  if (item >= ntile * nzc) return;  // whole work group, before any barrier
+  const int zc = item / ntile, tile = item - zc * ntile;
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int ny = g.nf[1], nz = g.nf[2];
+  const int nv = (g.nf[0] - 1 + V - 1) / V;
+  const int t = threadIdx.x;
+  const int hv = t % HX, hr = t / HX;
+  const int k = tx * TXV - 1 + hv, y = ty * TY + hr;
+  const bool lane = t < HX * HY;
+  const bool live = lane && y <= ny - 1 && k <= nv - 1;
+  const bool inner = live && hv >= 1 && hv <= TXV && hr >= 1 && hr <= TY && y <= ny - 2;
+  const int zs = 1 + zc * zlen, ze = min(zs + zlen - 1, nz - 2);
+  VA U0[C::NU], U1[C::NU], M[C::NM], R, Z0, Z1;
+  const VA zero = VA(S(0));
+#pragma unroll
+  for (int i = 0; i < C::NU; ++i) U0[i] = U1[i] = zero;
+#pragma unroll
+  for (int i = 0; i < C::NM; ++i) M[i] = zero;
+  R = Z0 = Z1 = zero;
+  for (int z = zs - 2; z <= ze; ++z) {
+    const int zl = z + 1;
+    VA T[Q];
+    if (live) {
+      fine3_s1<LAT, DEV, S, MODEL>(src, half, g, om, k, y, zl, nv, T, inner && zl >= zs && zl <= ze);
+    } else {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) T[i] = zero;
+    }
+    if (z >= zs) {
+      if (lane) {
+        static_for<Q>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          if constexpr (C::moving(i)) {
+            const VA w = L::cz(i) == -1 ? T[i] : (L::cz(i) == 0 ? M[C::midx(i)] : U1[C::uidx(i)]);
+            *(VA*)&lds[C::slot(i)][hr][hv * V] = w;
+          }
+        });
+      }
+      __syncthreads();
+      if (inner) {
+        VA v[Q];
+        static_for<Q>([&](auto I) {
+          constexpr int i = decltype(I)::value;
+          if constexpr (C::moving(i)) {
+#pragma unroll
+            for (int j = 0; j < V; ++j) v[i][j] = lds[C::slot(i)][hr - L::cy(i)][hv * V + j - L::cx(i)];
+          } else {
+            v[i] = L::cz(i) == 0 ? R : (L::cz(i) == 1 ? Z1 : T[i]);
+          }
+        });
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+          S f[Q];
+#pragma unroll
+          for (int i = 0; i < Q; ++i) f[i] = v[i][j];
+          N::collide(f, MODEL, om, S(0), S(0), nullptr);
+#pragma unroll
+          for (int i = 0; i < Q; ++i) v[i][j] = f[i];
+        }
+        const int64_t own = fpos(g, 1 + V * k, y, z);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + pop_at<S, Q>(own, i)), v[i]);
+      }
+      __syncthreads();
+    }
+    // the planes move up by one
+    static_for<Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      if constexpr (C::moving(i) && L::cz(i) == 1) {
+        U1[C::uidx(i)] = U0[C::uidx(i)];
+        U0[C::uidx(i)] = T[i];
+      } else if constexpr (C::moving(i) && L::cz(i) == 0) {
+        M[C::midx(i)] = T[i];
+      } else if constexpr (!C::moving(i) && L::cz(i) == 0) {
+        R = T[i];
+      } else if constexpr (!C::moving(i) && L::cz(i) == 1) {
+        Z1 = Z0;
+        Z0 = T[i];
+      }
+    });
   }
 }
 

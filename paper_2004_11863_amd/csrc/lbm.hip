@@ -203,13 +203,16 @@ struct Grid final : GridBase {
   DevBuf cbuf[2], fbuf[3], mac_c, mac_f, hist[3], G, tmp_rho, tmp_u, tmp_f, part, tot;
   DevBuf d_hnode, d_rnode, d_rnp, d_rpt, d_tnf, d_tnc;
   int cpar = 0;  // coarse buffer holding the current state
-  // Fine buffers: fbuf[fpar] holds the state at integer times.  D2Q9 BGK / RR
-  // run both fine substeps in one kernel (k_fine2) from fbuf[fpar] into the
-  // other buffer, which then becomes current; fbuf[2] receives the t+1/2 ring
-  // and the t+1/2 band the fine-to-coarse transfer pulls from.  Otherwise the
-  // substeps go fbuf[0] -> fbuf[1] -> fbuf[0] and fpar stays 0.
+  // Fine buffers: fbuf[fpar] holds the state at integer times.  A fused step
+  // (BGK / RR: always in 2D, k_fine2; in 3D when the fine-role variant picks
+  // k_fine3) runs both fine substeps in one kernel from fbuf[fpar] into the
+  // other buffer, which then becomes current; fbuf[2] receives the t+1/2
+  // ring and the t+1/2 band the fine-to-coarse transfer pulls from.
+  // Otherwise the substeps go fbuf[fpar] -> other -> fbuf[fpar].
   int fpar = 0;
   bool fused = false;
+  int n_cu = 0;
+  int f3_slots[kNVar] = {0, 0, 0, 0};  // resident k_fine3 work groups per device, per variant
   int hs[3] = {0, 1, 2};
   Iface itf{};
   double tau_c = 0, tau_f = 0, sig = 0;
@@ -219,15 +222,14 @@ struct Grid final : GridBase {
 
   // Velocity planes (H-RR): padded planes plus 64 spare elements.
   static size_t plane_bytes(int64_t NP, int nplanes) { return sizeof(S) * ((size_t)NP * nplanes + 64); }
-  // Populations: whole storage blocks up to and including position NP (the
-  // last x-vector of a fine row, which holds the ring column and is
-  // overwritten afterwards, pulls one position past the end of its row).
+  // Populations: whole storage blocks up to and including position NP.
   static size_t pop_bytes(int64_t NP) { return sizeof(S) * (size_t)pop_elems<S>(NP, Q); }
 
   void init() override {
-    fused = D == 2 && desc.collision != LBM_HRR && g.has_fine;
-    timed_factor = fused ? 2 : 1;
+    fused = desc.collision != LBM_HRR && g.has_fine;
+    HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device));
     if (fused) var[1] = 0;
+    timed_factor = fused_now() ? 2 : 1;
     for (int p = 0; p < 2; ++p) cbuf[p].alloc(pop_bytes(g.Ncp));
     if (g.has_fine)
       for (int p = 0; p < (fused ? 3 : 2); ++p) fbuf[p].alloc(pop_bytes(g.Nfp));
@@ -305,9 +307,8 @@ struct Grid final : GridBase {
                        (unsigned)kVarLds[v], s, src, dst, mac, g, f, (S)(1.0 - 1.0 / tau), (S)tau, (S)sig);
   }
 
-  // Both fine substeps (D2Q9 BGK / RR), src -> dst, t+1/2 ring and band in half.
-  // Both fine substeps (D2Q9 BGK / RR), src -> dst, t+1/2 ring and band in
-  // half.  Variants of the fine role (tile vectors x rows, waves per SIMD the
+  // Both fine substeps (BGK / RR), src -> dst, t+1/2 ring and band in half.
+  // D2Q9 variants of the fine role (tile vectors x rows, waves per SIMD the
   // registers must allow): 32 x 6, 32 x 6 at 4, 32 x 4 at 5, 16 x 6 at 6.
   template <int MODEL, int TXV, int TY, int MINW>
   void go_fine2(const S* src, S* dst, S* half, hipStream_t s) {
@@ -319,14 +320,87 @@ struct Grid final : GridBase {
                          s, src, dst, half, g, (S)(1.0 - 1.0 / tau_f), ntx, nty, per);
     }
   }
+  // D3Q19: fine-role variants 0 and 1 run the substeps as two k_stream
+  // launches (at most 2 / 3 resident work groups per CU), 2 and 3 as one
+  // k_fine3 launch with tiles of 14 x 14 and 30 x 6 (vectors x rows) at 2
+  // waves per SIMD; the autotuner keeps the faster.  The planes are cut into
+  // runs so that the work groups fill the device in few rounds: a run of zlen
+  // planes costs zlen + 2 substep-1 planes (its first step needs two), and
+  // runs are at least kMinZRun planes long so that this overhead stays small.
+  template <int MODEL, int TXV, int TY, int MINW>
+  void go_fine3(const S* src, S* dst, S* half, hipStream_t s, int v) {
+    if constexpr (D == 3 && MODEL != M_HRR) {
+      auto kern = k_fine3<LAT, DEV, S, MODEL, NT, TXV, TY, MINW>;
+      if (f3_slots[v] == 0) {
+        int nb = 0;
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0));
+        f3_slots[v] = std::max(1, nb) * std::max(1, n_cu);
+      }
+      const int nv = (g.nf[0] - 1 + V - 1) / V;
+      const int ntx = (nv + TXV - 1) / TXV, nty = (g.nf[1] - 2 + TY - 1) / TY, nzm = g.nf[2] - 2;
+      const int64_t ntile = (int64_t)ntx * nty;
+      int zlen = nzm;
+      double best = -1.0;
+      constexpr int kMinZRun = 8;
+      for (int nzc = 1; nzc <= nzm; ++nzc) {
+        const int zl = (nzm + nzc - 1) / nzc;
+        if (zl < kMinZRun && nzc > 1) break;
+        if ((nzm + zl - 1) / zl != nzc) continue;
+        const int64_t rounds = (ntile * nzc + f3_slots[v] - 1) / f3_slots[v];
+        const double cost = (double)rounds * (zl + 2);
+        if (best < 0.0 || cost < best) {
+          best = cost;
+          zlen = zl;
+        }
+      }
+      const int nzc = (nzm + zlen - 1) / zlen;
+      const int per = (int)((ntile * nzc + kXCD - 1) / kXCD);
+      hipLaunchKernelGGL(kern, dim3((unsigned)(per * kXCD)), dim3(256), 0, s, src, dst, half, g,
+                         (S)(1.0 - 1.0 / tau_f), ntx, nty, nzc, zlen, per);
+    }
+  }
+  template <typename K>
+  void fine3_launch(K kern, int TXV, int TY, const S* src, S* dst, S* half, hipStream_t s, int v) {
+    if (f3_slots[v] == 0) {
+      int nb = 0;
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0));
+      f3_slots[v] = std::max(1, nb) * std::max(1, n_cu);
+    }
+    const int nv = (g.nf[0] - 1 + V - 1) / V;
+    const int ntx = (nv + TXV - 1) / TXV, nty = (g.nf[1] - 2 + TY - 1) / TY, nzm = g.nf[2] - 2;
+    const int64_t ntile = (int64_t)ntx * nty;
+    int zlen = nzm;
+    double best = -1.0;
+    constexpr int kMinZRun = 8;
+    for (int nzc = 1; nzc <= nzm; ++nzc) {
+      const int zl = (nzm + nzc - 1) / nzc;
+      if (zl < kMinZRun && nzc > 1) break;
+      if ((nzm + zl - 1) / zl != nzc) continue;
+      const int64_t rounds = (ntile * nzc + f3_slots[v] - 1) / f3_slots[v];
+      const double cost = (double)rounds * (zl + 2);
+      if (best < 0.0 || cost < best) {
+        best = cost;
+        zlen = zl;
+      }
+    }
+    const int nzc = (nzm + zlen - 1) / zlen;
+    const int per = (int)((ntile * nzc + kXCD - 1) / kXCD);
+    hipLaunchKernelGGL(kern, dim3((unsigned)(per * kXCD)), dim3(256), 0, s, src, dst, half, g,
+                       (S)(1.0 - 1.0 / tau_f), ntx, nty, nzc, zlen, per);
+  }
   template <int MODEL>
-  void launch_fine2(const S* src, S* dst, S* half, hipStream_t s, int v = -1) {
+  void launch_fused(const S* src, S* dst, S* half, hipStream_t s, int v = -1) {
     if (v < 0) v = var[1];
-    switch (v) {
-      case 0: go_fine2<MODEL, 32, 6, 1>(src, dst, half, s); break;
-      case 1: go_fine2<MODEL, 32, 6, 4>(src, dst, half, s); break;
-      case 2: go_fine2<MODEL, 32, 4, 5>(src, dst, half, s); break;
-      default: go_fine2<MODEL, 16, 6, 6>(src, dst, half, s); break;
+    if constexpr (D == 2) {
+      switch (v) {
+        case 0: go_fine2<MODEL, 32, 6, 1>(src, dst, half, s); break;
+        case 1: go_fine2<MODEL, 32, 6, 4>(src, dst, half, s); break;
+        case 2: go_fine2<MODEL, 32, 4, 5>(src, dst, half, s); break;
+        default: go_fine2<MODEL, 16, 6, 6>(src, dst, half, s); break;
+      }
+    } else {
+      if (v == 2) go_fine3<MODEL, 14, 14, 2>(src, dst, half, s, 2);
+      else go_fine3<MODEL, 30, 6, 2>(src, dst, half, s, 3);
     }
   }
 
@@ -345,11 +419,16 @@ struct Grid final : GridBase {
       events.emplace_back(e0, e1);
     }
   }
+  // True when this step runs both fine substeps in one kernel.
+  bool fused_now() const { return fused && (D == 2 || var[1] >= 2); }
+  // LDS variant of the fine k_stream launches for fine-role variant v.
+  int fine_lds_var(int v) const { return (fused && D == 3) ? (v == 0 ? 2 : 1) : v; }
   // Fine-level pull-stream + collide (BGK, RR): the timed kernel.
   void fine_stream_timed(int model, const S* src, S* dst, hipStream_t s) {
+    const int lv = fine_lds_var(var[1]);
     timed(s, [&] {
-      if (model == M_BGK) launch_stream<M_BGK, 1>(src, dst, nullptr, tau_f, s);
-      else launch_stream<M_RR, 1>(src, dst, nullptr, tau_f, s);
+      if (model == M_BGK) launch_stream<M_BGK, 1>(src, dst, nullptr, tau_f, s, lv);
+      else launch_stream<M_RR, 1>(src, dst, nullptr, tau_f, s, lv);
     });
   }
 
@@ -365,11 +444,17 @@ struct Grid final : GridBase {
       if (model == M_BGK) launch_stream<M_BGK, 0>(c_cur, c_oth, nullptr, tau_c, s, v);
       else if (model == M_RR) launch_stream<M_RR, 0>(c_cur, c_oth, nullptr, tau_c, s, v);
       else launch_stream<M_HRR, 0>(c_cur, c_oth, mac_c.as<S>(), tau_c, s, v);
+    } else if (role == 1 && fused && D == 3 && v < 2) {
+      // both substeps as two launches (timed on the same buffers)
+      for (int k = 0; k < 2; ++k) {
+        if (model == M_BGK) launch_stream<M_BGK, 1>(fineA(), fineB(), nullptr, tau_f, s, fine_lds_var(v));
+        else launch_stream<M_RR, 1>(fineA(), fineB(), nullptr, tau_f, s, fine_lds_var(v));
+      }
     } else if (role == 1 && fused) {
       // both substeps: writes the other buffer and the t+1/2 band, which the
       // next step rewrites
-      if (model == M_BGK) launch_fine2<M_BGK>(fineA(), fineB(), fbuf[2].as<S>(), s, v);
-      else launch_fine2<M_RR>(fineA(), fineB(), fbuf[2].as<S>(), s, v);
+      if (model == M_BGK) launch_fused<M_BGK>(fineA(), fineB(), fbuf[2].as<S>(), s, v);
+      else launch_fused<M_RR>(fineA(), fineB(), fbuf[2].as<S>(), s, v);
     } else if (role == 1) {
       if (model == M_BGK) launch_stream<M_BGK, 1>(fineA(), fineB(), nullptr, tau_f, s, v);
       else if (model == M_RR) launch_stream<M_RR, 1>(fineA(), fineB(), nullptr, tau_f, s, v);
@@ -454,13 +539,14 @@ struct Grid final : GridBase {
     const unsigned bh = xblocks(NH, IB), br = xblocks(itf.NR, IB), bt = xblocks(itf.NT, IB), bg = blocks(NH * F::N, 256);
     const unsigned bc = xblocks(itf.NT, PER);
     hipLaunchKernelGGL((k_hist_capture<LAT, DEV, S, MODEL>), dim3(bh), dim3(IB), 0, s, csrc, Hp, g, itf);
-    if (MODEL != M_HRR && fused) {
+    timed_factor = fused_now() ? 2 : 1;
+    if (MODEL != M_HRR && fused_now()) {
       S* fH = fbuf[2].as<S>();
       launch_stream<MODEL, 0>(csrc, cdst, nullptr, tau_c, s);
       hipLaunchKernelGGL(k_hist_time, dim3(bg), dim3(256), 0, s, Hm, H0, Hp, G.as<double>(), NH * F::N, c0, c1, c2);
       hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL, true>), dim3(br), dim3(IB), 0, s, G.as<double>(), fH, g, itf, kf, omf,
                          tau_f, sig);
-      timed(s, [&] { launch_fine2<MODEL>(fA, fB, fH, s); });
+      timed(s, [&] { launch_fused<MODEL>(fA, fB, fH, s); });
       hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL, true>), dim3(br), dim3(IB), 0, s, Hp, fB, g, itf, kf, omf, tau_f, sig);
       hipLaunchKernelGGL((k_coalesce<LAT, DEV, S, MODEL>), dim3(bc), dim3(256), 0, s, fH, cdst, g, itf, kc, omc,
                          tau_c, sig);
@@ -705,6 +791,8 @@ static Geo validate(const lbm_grid_desc& d) {
   g.fxo = d.precision == LBM_FP32_DEV ? 3 : 1;
   g.pf = g.has_fine ? pitch_of(g.nf[0] + g.fxo) : 0;
   g.Nfp = g.has_fine ? (int64_t)g.pf * g.nf[1] * g.nf[2] : 0;
+  // the bulk kernels number node positions and vectors in 32 bits
+  if (g.Ncp >= ((int64_t)1 << 31) || g.Nfp >= ((int64_t)1 << 31)) throw LbmError(LBM_EINVAL, "grid too large");
   return g;
 }
 

@@ -30,8 +30,10 @@ def _wl(geom, k):
                       pulses=[I.Pulse(center=c, A=1e-3, R=3.0)])
 
 
-def _alone(wl, model, prec, steps):
+def _alone(wl, model, prec, steps, variants=None):
     gpu, _, levels = make_pair(wl, model, prec, with_oracle=False)
+    if variants is not None:
+        gpu.set_variants(variants)
     gpu.step(steps)
     out = [gpu.get_populations(lv) for lv in levels]
     live = gpu.class_map(0) != _lbm().LBM_C_COVERED
@@ -56,6 +58,32 @@ def _check_same(batch, sl, alone):
     assert np.array_equal(b0[:, live], out[0][:, live])
     if len(out) > 1:
         assert np.array_equal(batch.get_populations(sl, 1), out[1])
+
+
+def _geoms3d():
+    return [I.Geometry(3, (40, 36, 34), (5, 4, 6), (35, 20, 28)),   # fine 61 x 33 x 45
+            I.Geometry(3, (27, 21, 22), (4, 5, 3), (19, 14, 17)),   # fine 31 x 19 x 29
+            I.Geometry(3, (20, 18, 16), (0, 0, 0), (0, 0, 0))]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("model", ["BGK", "RR"])
+def test_batch_equals_alone_d3q19(prec, model):
+    """A single D3Q19 grid runs both fine substeps either as two launches
+    (fine-role variants 0, 1) or in one marching kernel with the half-step
+    state on chip (variants 2, 3); a batch runs them as two launches.  All
+    are bitwise equal, over several tiles, z-runs and ragged row ends."""
+    lbm = _lbm()
+    mcode = {"BGK": lbm.LBM_BGK, "RR": lbm.LBM_RR}[model]
+    p = lbm.LBM_FP32_DEV if prec == "fp32" else lbm.LBM_FP64
+    batch = lbm.Batch(lbm.LBM_D3Q19, mcode, p, capacity=3)
+    wls = [_wl(g, k) for k, g in enumerate(_geoms3d())]
+    slots = [_add(batch, w) for w in wls]
+    batch.step(7)
+    for w, sl in zip(wls, slots):
+        for v in (0, 2, 3):
+            _check_same(batch, sl, _alone(w, model, p, 7, variants=[0, v, 0, 0]))
+    batch.close()
 
 
 @pytest.mark.parametrize("model", ["BGK", "RR", "HRR"])
