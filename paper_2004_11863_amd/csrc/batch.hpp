@@ -154,7 +154,7 @@ __global__ __launch_bounds__(64) void kb_hist_time(const InstDev* __restrict__ i
     const InstDev& I = inst[w.inst];
     const int64_t k = (int64_t)w.idx * 64 + threadIdx.x;
     if (k < I.itf.NH * NFIELD)
-      I.G[k] = -0.125 * I.hist[I.hs[0]][k] + 0.75 * I.hist[I.hs[1]][k] + 0.375 * I.hist[I.hs[2]][k];
+      I.G[k] = time_half(I.hist[I.hs[0]][k], I.hist[I.hs[1]][k], I.hist[I.hs[2]][k]);
   }
 }
 

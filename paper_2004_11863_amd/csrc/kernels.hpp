@@ -488,11 +488,21 @@ __device__ __forceinline__ S store_pop(double f, int i) {
   return (S)(f - (DEV ? Lattice<LAT>::w(i) : 0.0));
 }
 
+// Temporal interpolation of a history value to t+1/2 (eq TempInt):
+// -1/8 H(t-1) + 3/4 H(t) + 3/8 H(t+1).
+__device__ __forceinline__ double time_half(double hm, double h0, double hp) {
+  return -0.125 * hm + 0.75 * h0 + 0.375 * hp;
+}
+
 // Pre-collision state of coarse history nodes at t+1 (pulled from the
 // post-collision coarse state at t): rho, u and the non-equilibrium part.
+// With G set (BGK, RR: every field is known here) each value is also
+// interpolated to t+1/2 from the two older levels Hm, H0 into G.
 template <int LAT, bool DEV, typename S, int MODEL>
 __device__ __forceinline__ void hist_capture_body(const S* __restrict__ src, double* __restrict__ H, const Geo& g,
-                                         const Iface& itf, int64_t h) {
+                                         const Iface& itf, int64_t h, double* __restrict__ G = nullptr,
+                                         const double* __restrict__ Hm = nullptr,
+                                         const double* __restrict__ H0 = nullptr) {
   using L = Lattice<LAT>;
   using F = HF<LAT, MODEL>;
   using N = Node<LAT, false, double>;
@@ -511,24 +521,30 @@ __device__ __forceinline__ void hist_capture_body(const S* __restrict__ src, dou
   double rho, r0, u[3];
   N::moments(f, rho, r0, u);
   const int64_t NH = itf.NH;
-  H[F::RHO * NH + h] = rho;
+  auto put = [&](int field, double v) {
+    const int64_t k = (int64_t)field * NH + h;
+    H[k] = v;
+    if (G) G[k] = time_half(Hm[k], H0[k], v);
+  };
+  put(F::RHO, rho);
 #pragma unroll
-  for (int d = 0; d < L::D; ++d) H[(F::U + d) * NH + h] = u[d];
+  for (int d = 0; d < L::D; ++d) put(F::U + d, u[d]);
   if (MODEL == M_BGK) {
     double f0[Q];
     N::feq(rho, r0, u, f0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) H[(F::F1 + i) * NH + h] = f[i] - f0[i];
+    for (int i = 0; i < Q; ++i) put(F::F1 + i, f[i] - f0[i]);
   } else {
     double a[NS<L::D>::value];
     sym_put<L::D>(a1_of<LAT>(f, rho, u), a, 1.0);
 #pragma unroll
-    for (int k = 0; k < NS<L::D>::value; ++k) H[(F::F1 + k) * NH + h] = a[k];
+    for (int k = 0; k < NS<L::D>::value; ++k) put(F::F1 + k, a[k]);
   }
 }
 template <int LAT, bool DEV, typename S, int MODEL>
-__global__ void k_hist_capture(const S* __restrict__ src, double* __restrict__ H, const Geo g, const Iface itf) {
-  hist_capture_body<LAT, DEV, S, MODEL>(src, H, g, itf, xcd_block() * blockDim.x + threadIdx.x);
+__global__ void k_hist_capture(const S* __restrict__ src, double* __restrict__ H, const Geo g, const Iface itf,
+                               double* __restrict__ G, const double* __restrict__ Hm, const double* __restrict__ H0) {
+  hist_capture_body<LAT, DEV, S, MODEL>(src, H, g, itf, xcd_block() * blockDim.x + threadIdx.x, G, Hm, H0);
 }
 
 
@@ -567,14 +583,14 @@ __global__ void k_hist_strain(const T* __restrict__ mac_c, double* __restrict__ 
 }
 
 
-// Temporal interpolation of every history field (eq TempInt): G = c0 H(t-1)
-// + c1 H(t) + c2 H(t+1), for all fields of all history nodes.
+// Temporal interpolation of every history field to t+1/2 (time_half), for
+// all fields of all history nodes (H-RR, whose strain-rate fields are filled
+// after the capture).
 __global__ void k_hist_time(const double* __restrict__ Hm, const double* __restrict__ H0,
-                            const double* __restrict__ Hp, double* __restrict__ G, int64_t n, double c0,
-                            double c1, double c2) {
+                            const double* __restrict__ Hp, double* __restrict__ G, int64_t n) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  G[k] = c0 * Hm[k] + c1 * H0[k] + c2 * Hp[k];
+  G[k] = time_half(Hm[k], H0[k], Hp[k]);
 }
 
 __device__ __forceinline__ double cubic_w(int s) { return (s == 1 || s == 2) ? 9.0 / 16.0 : -1.0 / 16.0; }
@@ -827,6 +843,30 @@ template <int LAT, bool DEV, typename S, int MODEL>
 __global__ __launch_bounds__(256) void k_coalesce(const S* __restrict__ src_f, S* __restrict__ dst_c, const Geo g,
                                                   const Iface itf, double kc, double om_c, double tau_c, double sig) {
   coalesce_body<LAT, DEV, S, MODEL>(src_f, dst_c, g, itf, kc, om_c, tau_c, sig, xcd_block());
+}
+
+// Ring reconstruction at t+1 (Hp -> the fine buffer of integer times,
+// populations that stream inward) and the fine-to-coarse transfer (fine
+// state at t+1/2 -> coarse TN) in one launch: they write disjoint buffers and
+// read none of each other's outputs.  Blocks [0, nrb) take 256 ring nodes
+// each, the rest PER TN nodes each; both parts are XCD-contiguous (nrb is a
+// multiple of 8).
+template <int LAT, bool DEV, typename S, int MODEL>
+__global__ __launch_bounds__(256) void k_ring_coalesce(const double* __restrict__ Hp, S* __restrict__ fdst,
+                                                       const S* __restrict__ src_f, S* __restrict__ dst_c,
+                                                       const Geo g, const Iface itf, double kf, double om_f,
+                                                       double tau_f, double kc, double om_c, double tau_c, double sig,
+                                                       int nrb) {
+  const int b = blockIdx.x;
+  if (b < nrb) {
+    const int per = nrb / kXCD;
+    const int64_t blk = (int64_t)(b % kXCD) * per + b / kXCD;
+    ring_body<LAT, DEV, S, MODEL, true>(Hp, fdst, g, itf, kf, om_f, tau_f, sig, blk * 256 + threadIdx.x);
+  } else {
+    const int b2 = b - nrb, per = ((int)gridDim.x - nrb) / kXCD;
+    coalesce_body<LAT, DEV, S, MODEL>(src_f, dst_c, g, itf, kc, om_c, tau_c, sig,
+                                      (int64_t)(b2 % kXCD) * per + b2 / kXCD);
+  }
 }
 
 // ---------------------------------------------------------------------------

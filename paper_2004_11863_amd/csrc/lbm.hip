@@ -533,34 +533,33 @@ struct Grid final : GridBase {
     const int64_t NH = itf.NH;
     const double kf = tau_f / (2.0 * tau_c), kc = 2.0 * tau_c / tau_f;
     const double omf = 1.0 - 1.0 / tau_f, omc = 1.0 - 1.0 / tau_c;
-    const double c0 = -1.0 / 8.0, c1 = 3.0 / 4.0, c2 = 3.0 / 8.0;
+    const double c0 = -1.0 / 8.0, c1 = 3.0 / 4.0, c2 = 3.0 / 8.0;  // eq TempInt at t+1/2
     constexpr int IB = kIfaceBlock;
     constexpr int PER = 256 / (D == 2 ? 9 : 27);
     const unsigned bh = xblocks(NH, IB), br = xblocks(itf.NR, IB), bt = xblocks(itf.NT, IB), bg = blocks(NH * F::N, 256);
-    const unsigned bc = xblocks(itf.NT, PER);
-    hipLaunchKernelGGL((k_hist_capture<LAT, DEV, S, MODEL>), dim3(bh), dim3(IB), 0, s, csrc, Hp, g, itf);
+    const unsigned bc = xblocks(itf.NT, PER), br2 = xblocks(itf.NR, 256);
+    // BGK / RR: the capture also interpolates every history value to t+1/2
+    // (G); H-RR fills its strain-rate fields later and interpolates then
+    hipLaunchKernelGGL((k_hist_capture<LAT, DEV, S, MODEL>), dim3(bh), dim3(IB), 0, s, csrc, Hp, g, itf,
+                       MODEL == M_HRR ? nullptr : G.as<double>(), Hm, H0);
     timed_factor = fused_now() ? 2 : 1;
     if (MODEL != M_HRR && fused_now()) {
       S* fH = fbuf[2].as<S>();
       launch_stream<MODEL, 0>(csrc, cdst, nullptr, tau_c, s);
-      hipLaunchKernelGGL(k_hist_time, dim3(bg), dim3(256), 0, s, Hm, H0, Hp, G.as<double>(), NH * F::N, c0, c1, c2);
       hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL, true>), dim3(br), dim3(IB), 0, s, G.as<double>(), fH, g, itf, kf, omf,
                          tau_f, sig);
       timed(s, [&] { launch_fused<MODEL>(fA, fB, fH, s); });
-      hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL, true>), dim3(br), dim3(IB), 0, s, Hp, fB, g, itf, kf, omf, tau_f, sig);
-      hipLaunchKernelGGL((k_coalesce<LAT, DEV, S, MODEL>), dim3(bc), dim3(256), 0, s, fH, cdst, g, itf, kc, omc,
-                         tau_c, sig);
+      hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, MODEL>), dim3(br2 + bc), dim3(256), 0, s, Hp, fB, fH, cdst, g, itf,
+                         kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2);
       fpar ^= 1;
     } else if (MODEL != M_HRR) {
       launch_stream<MODEL, 0>(csrc, cdst, nullptr, tau_c, s);
       fine_stream_timed(MODEL, fA, fB, s);
-      hipLaunchKernelGGL(k_hist_time, dim3(bg), dim3(256), 0, s, Hm, H0, Hp, G.as<double>(), NH * F::N, c0, c1, c2);
       hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL, true>), dim3(br), dim3(IB), 0, s, G.as<double>(), fB, g, itf, kf, omf,
                          tau_f, sig);
       fine_stream_timed(MODEL, fB, fA, s);
-      hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL, true>), dim3(br), dim3(IB), 0, s, Hp, fA, g, itf, kf, omf, tau_f, sig);
-      hipLaunchKernelGGL((k_coalesce<LAT, DEV, S, MODEL>), dim3(bc), dim3(256), 0, s, fB, cdst, g, itf, kc, omc,
-                         tau_c, sig);
+      hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, MODEL>), dim3(br2 + bc), dim3(256), 0, s, Hp, fA, fB, cdst, g, itf,
+                         kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2);
     } else {
       S* mc = mac_c.as<S>();
       S* mf = mac_f.as<S>();
@@ -572,7 +571,7 @@ struct Grid final : GridBase {
       timed(s, [&] { launch_collide_hrr<1>(fA, fB, mf, tau_f, s); });
       hipLaunchKernelGGL((k_fict<LAT, DEV, S, S>), dim3(bt), dim3(IB), 0, s, fB, mc, g, itf);
       hipLaunchKernelGGL((k_hist_strain<LAT, S>), dim3(bh), dim3(IB), 0, s, mc, Hp, g, itf);
-      hipLaunchKernelGGL(k_hist_time, dim3(bg), dim3(256), 0, s, Hm, H0, Hp, G.as<double>(), NH * F::N, c0, c1, c2);
+      hipLaunchKernelGGL(k_hist_time, dim3(bg), dim3(256), 0, s, Hm, H0, Hp, G.as<double>(), NH * F::N);
       hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR, true>), dim3(br), dim3(IB), 0, s, G.as<double>(), fB, g, itf, kf, omf,
                          tau_f, sig);
       launch_stream<M_HRR, 1>(fB, fA, mf, tau_f, s);
