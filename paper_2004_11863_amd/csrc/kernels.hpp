@@ -845,6 +845,27 @@ __global__ __launch_bounds__(256) void k_coalesce(const S* __restrict__ src_f, S
   coalesce_body<LAT, DEV, S, MODEL>(src_f, dst_c, g, itf, kc, om_c, tau_c, sig, xcd_block());
 }
 
+// Coarse pull-stream + collide (BGK, RR) and the ring reconstruction at
+// t+1/2 (G -> the fine buffer of half times) in one launch: independent work,
+// the ring latency-bound and the stream bandwidth-bound, so the ring hides
+// inside the stream.  Blocks [0, nrb) take 256 ring nodes each (dispatched
+// first), the rest are the stream's chunks; both parts are XCD-contiguous.
+template <int LAT, bool DEV, typename S, int MODEL, bool NT>
+__global__ __launch_bounds__(256) void k_stream_ring(const S* __restrict__ src, S* __restrict__ dst, const Geo g,
+                                                     const Flat fl, const S om, const double* __restrict__ G,
+                                                     S* __restrict__ fdst, const Iface itf, double kf, double om_f,
+                                                     double tau_f, double sig, int nrb) {
+  const int b = blockIdx.x;
+  if (b < nrb) {
+    const int per = nrb / kXCD;
+    const int64_t blk = (int64_t)(b % kXCD) * per + b / kXCD;
+    ring_body<LAT, DEV, S, MODEL, true>(G, fdst, g, itf, kf, om_f, tau_f, sig, blk * 256 + threadIdx.x);
+  } else {
+    const int b2 = b - nrb;
+    stream_body<LAT, DEV, S, MODEL, 0, NT>(src, dst, nullptr, g, fl, om, (b2 % kXCD) * fl.per_xcd + b2 / kXCD);
+  }
+}
+
 // Ring reconstruction at t+1 (Hp -> the fine buffer of integer times,
 // populations that stream inward) and the fine-to-coarse transfer (fine
 // state at t+1/2 -> coarse TN) in one launch: they write disjoint buffers and

@@ -298,6 +298,17 @@ struct Grid final : GridBase {
                        (unsigned)kVarLds[v], s, src, dst, mac, g, f, (S)(1.0 - 1.0 / tau));
   }
 
+  // Coarse stream (BGK, RR) and the t+1/2 ring reconstruction from G into
+  // fdst, one launch (k_stream_ring).
+  template <int MODEL>
+  void launch_stream_ring(const S* src, S* dst, S* fdst, double kf, double omf, hipStream_t s) {
+    const Flat f = flat(0);
+    const unsigned nrb = xblocks(itf.NR, 256);
+    hipLaunchKernelGGL((k_stream_ring<LAT, DEV, S, MODEL, NT>), dim3(nrb + (unsigned)(f.per_xcd * kXCD)), dim3(256),
+                       (unsigned)kVarLds[var[0]], s, src, dst, g, f, (S)(1.0 - 1.0 / tau_c), G.as<double>(), fdst, itf,
+                       kf, omf, tau_f, sig, (int)nrb);
+  }
+
   template <int LEVEL>
   void launch_collide_hrr(const S* src, S* dst, const S* mac, double tau, hipStream_t s, int v = -1) {
     if (v < 0) v = var[2 + LEVEL];
@@ -545,18 +556,16 @@ struct Grid final : GridBase {
     timed_factor = fused_now() ? 2 : 1;
     if (MODEL != M_HRR && fused_now()) {
       S* fH = fbuf[2].as<S>();
-      launch_stream<MODEL, 0>(csrc, cdst, nullptr, tau_c, s);
-      hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL, true>), dim3(br), dim3(IB), 0, s, G.as<double>(), fH, g, itf, kf, omf,
-                         tau_f, sig);
+      launch_stream_ring<MODEL>(csrc, cdst, fH, kf, omf, s);
       timed(s, [&] { launch_fused<MODEL>(fA, fB, fH, s); });
       hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, MODEL>), dim3(br2 + bc), dim3(256), 0, s, Hp, fB, fH, cdst, g, itf,
                          kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2);
       fpar ^= 1;
     } else if (MODEL != M_HRR) {
-      launch_stream<MODEL, 0>(csrc, cdst, nullptr, tau_c, s);
+      // substep 1 writes the ring column x = nx - 1 of B, so the t+1/2 ring
+      // (sharing a launch with the coarse stream) follows it
       fine_stream_timed(MODEL, fA, fB, s);
-      hipLaunchKernelGGL((k_ring<LAT, DEV, S, MODEL, true>), dim3(br), dim3(IB), 0, s, G.as<double>(), fB, g, itf, kf, omf,
-                         tau_f, sig);
+      launch_stream_ring<MODEL>(csrc, cdst, fB, kf, omf, s);
       fine_stream_timed(MODEL, fB, fA, s);
       hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, MODEL>), dim3(br2 + bc), dim3(256), 0, s, Hp, fA, fB, cdst, g, itf,
                          kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2);
