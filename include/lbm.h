@@ -167,9 +167,9 @@ int lbm_kernel_time(lbm_handle h, int64_t* launches, double* mean_ms, int64_t* n
  * launched with 0, 53, 80 or 160 KB of unused LDS per 256-lane work group,
  * which caps the work groups resident on a CU (no cap, 3, 2, 1).  For the
  * fine role of a D2Q9 BGK / RR grid, whose kernel runs both substeps with
- * the half-step state on chip, the variants are tile shapes (vectors x rows)
- * and register budgets (waves per SIMD the compiler must fit): 32 x 6,
- * 32 x 6 at 4, 32 x 4 at 5 and 16 x 6 at 6.  For the fine role of a D3Q19
+ * the half-step state on chip, the variants are work-group tiles of one
+ * lane per vector, halo included (vectors x rows): 64 x 8, 64 x 16, 32 x 16
+ * and 32 x 8.  For the fine role of a D3Q19
  * BGK / RR grid, variants 0 and 1 run the two substeps as two launches
  * (capped at 2 and 3 resident work groups per CU), 2 and 3 as one kernel
  * walking tiles of 14 x 14 and 30 x 6 along z.  Every variant computes

@@ -996,50 +996,49 @@ __device__ __forceinline__ void fine2_s2(S* __restrict__ dst, const Geo& g, cons
   for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + pop_at<S, Q>(own, i)), v[i]);
 }
 
-// Tiles (k_fine2): a work group owns TXV vectors x TY rows of middle nodes
-// and computes substep 1 for the tile plus a one-node halo (one vector on
-// each side, one row above and below) into LDS, then substep 2 for the tile.
-// MINW asks the compiler to fit that many waves per SIMD (registers), so
-// small tiles can be resident several at a time.
-template <int LAT, bool DEV, typename S, int MODEL, bool NT, int TXV, int TY, int MINW>
-__global__ __launch_bounds__(256, MINW) void k_fine2(const S* __restrict__ src, S* __restrict__ dst,
-                                               S* __restrict__ half, const Geo g, const S om, int ntx, int nty,
-                                               int per_xcd) {
+// Tiles (k_fine2): a work group of HXV x HYR lanes owns the middle nodes of
+// HXV - 2 vectors x HYR - 2 rows.  Each lane computes substep 1 of one
+// vector of the tile or of its halo (one vector on each side, one row above
+// and below) into LDS; after the barrier the inner lanes compute substep 2
+// of their own vector.  One lane per vector: waves made only of halo lanes
+// skip substep 2, and the halo costs (HXV HYR) / ((HXV - 2)(HYR - 2)) of the
+// substep-1 work.  MINW asks the compiler to fit that many waves per SIMD.
+template <int LAT, bool DEV, typename S, int MODEL, bool NT, int HXV, int HYR, int MINW>
+__global__ __launch_bounds__(HXV * HYR, MINW) void k_fine2(const S* __restrict__ src, S* __restrict__ dst,
+                                                         S* __restrict__ half, const Geo g, const S om, int ntx,
+                                                         int nty, int per_xcd) {
   using L = Lattice<LAT>;
   constexpr int V = VecOf<S>::V, Q = L::Q;
-  constexpr int RV = TXV + 2, RH = TY + 2, RW = RV * V;
+  constexpr int TXV = HXV - 2, TY = HYR - 2, RW = HXV * V;
   static_assert(L::D == 2, "fused fine substeps are two-dimensional");
-  __shared__ S lds[Q][RH][RW];
+  static_assert((HXV * HYR) % 64 == 0 && HXV * HYR <= 1024, "whole waves");
+  __shared__ S lds[Q][HYR][RW];
   const int b = blockIdx.x;
   const int tile = (b % kXCD) * per_xcd + b / kXCD;
   if (tile >= ntx * nty) return;  // whole work group, before any barrier
   const int tx = tile % ntx, ty = tile / ntx;
   const int ny = g.nf[1];
   const int nv = (g.nf[0] - 1 + V - 1) / V;
-  const int kx0 = tx * TXV, y0 = 1 + ty * TY;
-  for (int e = threadIdx.x; e < RV * RH; e += 256) {
-    const int rv = e % RV, rr = e / RV;
-    const int k = kx0 - 1 + rv, y = y0 - 1 + rr;
-    if (y < 0 || y > ny - 1 || k < -1 || k >= nv) continue;  // never read
+  const int t = threadIdx.x;
+  const int rv = t % HXV, rr = t / HXV;
+  const int k = tx * TXV - 1 + rv, y = ty * TY + rr;  // vector and row of this lane (k >= -1, y >= 0)
+  const bool inner = rr >= 1 && rr <= TY && rv >= 1 && rv <= TXV;
+  if (y <= ny - 1 && k < nv) {
     S* row[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) row[i] = &lds[i][rr][0];
-    const bool interior = rr >= 1 && rr <= TY && rv >= 1 && rv <= TXV;
-    fine2_s1<LAT, DEV, S, MODEL>(src, half, g, om, k, y, nv, row, rv * V, interior);
+    fine2_s1<LAT, DEV, S, MODEL>(src, half, g, om, k, y, nv, row, rv * V, inner);
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < TXV * TY; e += 256) {
-    const int iv = e % TXV, ir = e / TXV;
-    const int k = kx0 + iv, y = y0 + ir;
-    if (k >= nv || y > ny - 2) continue;
+  if (inner && k < nv && y <= ny - 2) {
     S *rm[Q], *r0[Q], *rp[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      rm[i] = &lds[i][ir][0];
-      r0[i] = &lds[i][ir + 1][0];
-      rp[i] = &lds[i][ir + 2][0];
+      rm[i] = &lds[i][rr - 1][0];
+      r0[i] = &lds[i][rr][0];
+      rp[i] = &lds[i][rr + 1][0];
     }
-    fine2_s2<LAT, DEV, S, MODEL, NT>(dst, g, om, k, y, rm, r0, rp, (iv + 1) * V);
+    fine2_s2<LAT, DEV, S, MODEL, NT>(dst, g, om, k, y, rm, r0, rp, rv * V);
   }
 }
 

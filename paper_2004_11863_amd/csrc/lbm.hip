@@ -319,16 +319,19 @@ struct Grid final : GridBase {
   }
 
   // Both fine substeps (BGK / RR), src -> dst, t+1/2 ring and band in half.
-  // D2Q9 variants of the fine role (tile vectors x rows, waves per SIMD the
-  // registers must allow): 32 x 6, 32 x 6 at 4, 32 x 4 at 5, 16 x 6 at 6.
-  template <int MODEL, int TXV, int TY, int MINW>
+  // D2Q9 variants of the fine role (halo-tile lanes, vectors x rows): 64 x 8,
+  // 64 x 16, 32 x 16 and 32 x 8 (measured on the 4097 x 2049 patch, FP32:
+  // 119, 134-147, 135 and 135 us; narrower or non-power-of-two widths and
+  // 1024-lane tiles were slower still).
+  template <int MODEL, int HXV, int HYR>
   void go_fine2(const S* src, S* dst, S* half, hipStream_t s) {
     if constexpr (D == 2 && MODEL != M_HRR) {
+      constexpr int TXV = HXV - 2, TY = HYR - 2;
       const int nv = (g.nf[0] - 1 + V - 1) / V;
       const int ntx = (nv + TXV - 1) / TXV, nty = (g.nf[1] - 2 + TY - 1) / TY;
       const int per = (ntx * nty + kXCD - 1) / kXCD;
-      hipLaunchKernelGGL((k_fine2<LAT, DEV, S, MODEL, NT, TXV, TY, MINW>), dim3((unsigned)(per * kXCD)), dim3(256), 0,
-                         s, src, dst, half, g, (S)(1.0 - 1.0 / tau_f), ntx, nty, per);
+      hipLaunchKernelGGL((k_fine2<LAT, DEV, S, MODEL, NT, HXV, HYR, 4>), dim3((unsigned)(per * kXCD)),
+                         dim3(HXV * HYR), 0, s, src, dst, half, g, (S)(1.0 - 1.0 / tau_f), ntx, nty, per);
     }
   }
   // D3Q19: fine-role variants 0 and 1 run the substeps as two k_stream
@@ -404,10 +407,10 @@ struct Grid final : GridBase {
     if (v < 0) v = var[1];
     if constexpr (D == 2) {
       switch (v) {
-        case 0: go_fine2<MODEL, 32, 6, 1>(src, dst, half, s); break;
-        case 1: go_fine2<MODEL, 32, 6, 4>(src, dst, half, s); break;
-        case 2: go_fine2<MODEL, 32, 4, 5>(src, dst, half, s); break;
-        default: go_fine2<MODEL, 16, 6, 6>(src, dst, half, s); break;
+        case 0: go_fine2<MODEL, 64, 8>(src, dst, half, s); break;
+        case 1: go_fine2<MODEL, 64, 16>(src, dst, half, s); break;
+        case 2: go_fine2<MODEL, 32, 16>(src, dst, half, s); break;
+        default: go_fine2<MODEL, 32, 8>(src, dst, half, s); break;
       }
     } else {
       if (v == 2) go_fine3<MODEL, 14, 14, 2>(src, dst, half, s, 2);
