@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fine_stream.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_dominant_kernel.json")
 
 
 def parse():
