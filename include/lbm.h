@@ -229,9 +229,10 @@ int lbm_batch_info(lbm_batch_handle b, int64_t info[3]);
 int lbm_batch_slot_steps(lbm_batch_handle b, int slot, int64_t* steps);
 /* Device bytes a grid of this descriptor occupies in a batch slot
  * (populations, macro planes, history, interface tables), for admission by
- * memory footprint.  A single grid (lbm_create_grid) with BGK or RR and a
- * fine patch holds one more fine population buffer (the half-step ring and
- * band of its fused fine kernel). */
+ * memory footprint.  Fine levels hold three population buffers for D2Q9
+ * BGK / RR (the third keeps the half-step ring and band of the fused fine
+ * kernel), two otherwise; a single D3Q19 BGK / RR grid (lbm_create_grid)
+ * also holds a third. */
 int lbm_footprint(const lbm_grid_desc* d, int64_t* bytes);
 const char* lbm_batch_last_error(lbm_batch_handle b);
 

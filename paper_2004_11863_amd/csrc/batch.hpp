@@ -5,9 +5,11 @@
 // table of InstDev descriptors holds their geometry, buffer pointers and
 // time-level state (coarse ping-pong parity, history rotation).  For each
 // phase of the coarse step there is one work list of (instance, index)
-// items: a bulk chunk of 256 vectors, a block of 64 interface nodes, or a
-// block of TN nodes.  A phase is one launch with one work group per list
-// entry; the list is split into 8 contiguous parts, one per XCD, so the
+// items: a bulk chunk of 256 vectors, a fused fine tile (D2Q9 BGK / RR: both
+// fine substeps, as k_fine2), a block of 64 interface nodes, or a block of
+// TN nodes.  A phase is one launch with one work group per list entry (two
+// phases that touch disjoint data may share a launch, each part with its
+// own list); the list is split into 8 contiguous parts, one per XCD, so the
 // chunks of one instance stay in one L2.  The last launch of a step flips
 // each instance's parity and rotates its history on the device, so the
 // launch sequence of a step is the same every step and is captured once as a
@@ -24,7 +26,8 @@ struct InstDev {
   Iface itf;
   Flat fc, ff;  // flat numbering of the coarse / fine bulk vectors
   void* cbuf[2];
-  void* fbuf[2];
+  void* fbuf[2];  // fbuf[fpar] holds the fine state at integer times
+  void* fh;       // fused: the t+1/2 ring and band (fine-to-coarse source)
   void* mac_c;
   void* mac_f;
   double* hist[3];
@@ -35,7 +38,9 @@ struct InstDev {
   int cpar;    // coarse buffer holding the current state
   int hs[3];  // history buffers holding t-1, t, t+1
   int active;
-  int pad;
+  int fpar;   // fine buffer holding the state at integer times
+  int fused;  // both fine substeps in one phase (D2Q9 BGK / RR): fpar flips every step
+  int ntx;    // fused: fine tiles per row of tiles
 };
 
 struct Work {
@@ -52,22 +57,28 @@ enum WorkKind : int {
   W_RING = 4,    // 64 ring nodes
   W_TN = 5,      // 64 TN nodes
   W_TNB = 6,     // PER TN nodes (one fine-to-coarse work group)
-  W_KINDS = 7
+  W_TILE = 7,    // fused fine tile (kFineTileX x kFineTileY lanes)
+  W_KINDS = 8
 };
+
+// Lanes of a fused fine tile (k_fine2 / kb_fine2) in the batch.
+constexpr int kFineTileX = 64, kFineTileY = 8;
 
 // Item of this work group, or -1.  A phase launches one work group per entry
 // of its list's capacity (a multiple of 8); the live count is read from
 // device memory, so a captured launch stays valid while grids join and leave.
 // Groups are handed to the XCDs round-robin; the item index is remapped so
 // each XCD serves one contiguous part of the list, in dispatch order.
-__device__ __forceinline__ int item_of(int n) {
-  const int b = blockIdx.x;
+// item_in: the same for block b of one part of a launch that serves two
+// lists (each part's block count a multiple of 8).
+__device__ __forceinline__ int item_in(int b, int n) {
   const int per = (n + kXCD - 1) / kXCD;
   const int w = b / kXCD;
   if (w >= per) return -1;
   const int it = (b % kXCD) * per + w;
   return it < n ? it : -1;
 }
+__device__ __forceinline__ int item_of(int n) { return item_in(blockIdx.x, n); }
 
 __device__ __forceinline__ Work load_item(const Work* __restrict__ items, int it) {
   Work w = items[it];
@@ -77,7 +88,7 @@ __device__ __forceinline__ Work load_item(const Work* __restrict__ items, int it
 }
 
 // Bulk stream of one level; SUB selects the fine buffer direction (0: A->B,
-// 1: B->A).
+// 1: B->A, with A = fbuf[fpar]).
 template <int LAT, bool DEV, typename S, int MODEL, int LEVEL, int SUB, bool NT>
 __global__ __launch_bounds__(256) void kb_stream(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                                  const int* __restrict__ count) {
@@ -91,8 +102,8 @@ __global__ __launch_bounds__(256) void kb_stream(const InstDev* __restrict__ ins
       S* dst = (S*)I.cnext;
       stream_body<LAT, DEV, S, MODEL, 0, NT>(src, dst, (S*)I.mac_c, I.g, I.fc, (S)(1.0 - 1.0 / I.tau_c), w.idx);
     } else {
-      const S* src = (const S*)I.fbuf[SUB];
-      S* dst = (S*)I.fbuf[SUB ^ 1];
+      const S* src = (const S*)I.fbuf[I.fpar ^ SUB];
+      S* dst = (S*)I.fbuf[I.fpar ^ SUB ^ 1];
       stream_body<LAT, DEV, S, MODEL, 1, NT>(src, dst, (S*)I.mac_f, I.g, I.ff, (S)(1.0 - 1.0 / I.tau_f), w.idx);
     }
   }
@@ -112,7 +123,8 @@ __global__ __launch_bounds__(256) void kb_collide(const InstDev* __restrict__ in
       collide_hrr_body<LAT, DEV, S, 0, NT>((const S*)I.ccur, (S*)I.cnext, (const S*)I.mac_c, I.g,
                                            I.fc, (S)(1.0 - 1.0 / I.tau_c), (S)I.tau_c, (S)I.sig, w.idx);
     } else {
-      collide_hrr_body<LAT, DEV, S, 1, NT>((const S*)I.fbuf[SUB], (S*)I.fbuf[SUB ^ 1], (const S*)I.mac_f, I.g, I.ff,
+      collide_hrr_body<LAT, DEV, S, 1, NT>((const S*)I.fbuf[I.fpar ^ SUB], (S*)I.fbuf[I.fpar ^ SUB ^ 1],
+                                           (const S*)I.mac_f, I.g, I.ff,
                                            (S)(1.0 - 1.0 / I.tau_f), (S)I.tau_f, (S)I.sig, w.idx);
     }
   }
@@ -126,8 +138,10 @@ __global__ __launch_bounds__(64) void kb_hist_capture(const InstDev* __restrict_
   {
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
+    // BGK / RR: also the t+1/2 interpolation into G (H-RR: kb_hist_time)
     hist_capture_body<LAT, DEV, S, MODEL>((const S*)I.ccur, I.hist[I.hs[2]], I.g, I.itf,
-                                          (int64_t)w.idx * 64 + threadIdx.x);
+                                          (int64_t)w.idx * 64 + threadIdx.x, MODEL == M_HRR ? nullptr : I.G,
+                                          I.hist[I.hs[0]], I.hist[I.hs[1]]);
   }
 }
 
@@ -158,9 +172,18 @@ __global__ __launch_bounds__(64) void kb_hist_time(const InstDev* __restrict__ i
   }
 }
 
-// Ring reconstruction: SUB 0 (t+1/2, from G, into fine B), SUB 1 (t+1, from
-// the t+1 history, into fine A); only the populations the stepping reads
-// (the full ring of A is completed before it is observed).
+// Ring reconstruction of one 64-node item: SUB 0 (t+1/2, from G, into the
+// half-time buffer: fh when fused, else B), SUB 1 (t+1, from the t+1
+// history, into the buffer that holds t+1 after the step: B when fused, else
+// A); only the populations the stepping reads (the full ring of A is
+// completed before it is observed).
+template <int LAT, bool DEV, typename S, int MODEL, int SUB>
+__device__ __forceinline__ void kb_ring_item(const InstDev& I, int idx, int lane) {
+  const double* G = SUB == 0 ? I.G : I.hist[I.hs[2]];
+  S* dst = (S*)(SUB == 0 ? (I.fused ? I.fh : I.fbuf[I.fpar ^ 1]) : I.fbuf[I.fpar ^ I.fused]);
+  ring_body<LAT, DEV, S, MODEL, true>(G, dst, I.g, I.itf, I.tau_f / (2.0 * I.tau_c), 1.0 - 1.0 / I.tau_f, I.tau_f, I.sig,
+                                      (int64_t)idx * 64 + lane);
+}
 template <int LAT, bool DEV, typename S, int MODEL, int SUB>
 __global__ __launch_bounds__(64) void kb_ring(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                               const int* __restrict__ count) {
@@ -168,12 +191,45 @@ __global__ __launch_bounds__(64) void kb_ring(const InstDev* __restrict__ inst, 
   if (it < 0) return;
   {
     const Work w = load_item(items, it);
-    const InstDev& I = inst[w.inst];
-    const double* G = SUB == 0 ? I.G : I.hist[I.hs[2]];
-    S* dst = (S*)I.fbuf[SUB == 0 ? 1 : 0];
-    ring_body<LAT, DEV, S, MODEL, true>(G, dst, I.g, I.itf, I.tau_f / (2.0 * I.tau_c), 1.0 - 1.0 / I.tau_f, I.tau_f, I.sig,
-                                  (int64_t)w.idx * 64 + threadIdx.x);
+    kb_ring_item<LAT, DEV, S, MODEL, SUB>(inst[w.inst], w.idx, threadIdx.x);
   }
+}
+
+// Coarse stream (BGK, RR) and the t+1/2 ring in one launch: blocks [0, nrb)
+// take ring items (64 lanes each), the rest coarse chunks.
+template <int LAT, bool DEV, typename S, int MODEL, bool NT>
+__global__ __launch_bounds__(256) void kb_stream_ring(const InstDev* __restrict__ inst, const Work* __restrict__ ritems,
+                                                      const int* __restrict__ rcount, const Work* __restrict__ citems,
+                                                      const int* __restrict__ ccount, int nrb) {
+  const int b = blockIdx.x;
+  if (b < nrb) {
+    if (threadIdx.x >= 64) return;
+    const int it = item_in(b, *rcount);
+    if (it < 0) return;
+    const Work w = load_item(ritems, it);
+    kb_ring_item<LAT, DEV, S, MODEL, 0>(inst[w.inst], w.idx, threadIdx.x);
+  } else {
+    const int it = item_in(b - nrb, *ccount);
+    if (it < 0) return;
+    const Work w = load_item(citems, it);
+    const InstDev& I = inst[w.inst];
+    stream_body<LAT, DEV, S, MODEL, 0, NT>((const S*)I.ccur, (S*)I.cnext, nullptr, I.g, I.fc, (S)(1.0 - 1.0 / I.tau_c),
+                                           w.idx);
+  }
+}
+
+// Both fine substeps of one tile (D2Q9 BGK / RR), A -> B with the t+1/2 ring
+// and band in fh.
+template <int LAT, bool DEV, typename S, int MODEL, bool NT>
+__global__ __launch_bounds__(kFineTileX * kFineTileY) void kb_fine2(const InstDev* __restrict__ inst,
+                                                                    const Work* __restrict__ items,
+                                                                    const int* __restrict__ count) {
+  const int it = item_of(*count);
+  if (it < 0) return;
+  const Work w = load_item(items, it);
+  const InstDev& I = inst[w.inst];
+  fine2_tile<LAT, DEV, S, MODEL, NT, kFineTileX, kFineTileY>((const S*)I.fbuf[I.fpar], (S*)I.fbuf[I.fpar ^ 1],
+                                                             (S*)I.fh, I.g, (S)(1.0 - 1.0 / I.tau_f), I.ntx, w.idx);
 }
 
 // H-RR ring rho, u at t+1/2 (SUB 0) or t+1 (SUB 1).
@@ -199,10 +255,16 @@ __global__ __launch_bounds__(64) void kb_fict(const InstDev* __restrict__ inst, 
   {
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
-    fict_body<LAT, DEV, S, S>((const S*)I.fbuf[1], (S*)I.mac_c, I.g, I.itf, (int64_t)w.idx * 64 + threadIdx.x);
+    fict_body<LAT, DEV, S, S>((const S*)I.fbuf[I.fpar ^ 1], (S*)I.mac_c, I.g, I.itf, (int64_t)w.idx * 64 + threadIdx.x);
   }
 }
 
+// Fine-to-coarse transfer from the t+1/2 state (fh when fused, else B).
+template <int LAT, bool DEV, typename S, int MODEL>
+__device__ __forceinline__ void kb_coalesce_item(const InstDev& I, int idx) {
+  coalesce_body<LAT, DEV, S, MODEL>((const S*)(I.fused ? I.fh : I.fbuf[I.fpar ^ 1]), (S*)I.cnext, I.g, I.itf,
+                                    2.0 * I.tau_c / I.tau_f, 1.0 - 1.0 / I.tau_c, I.tau_c, I.sig, idx);
+}
 template <int LAT, bool DEV, typename S, int MODEL>
 __global__ __launch_bounds__(256) void kb_coalesce(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                                    const int* __restrict__ count) {
@@ -210,9 +272,28 @@ __global__ __launch_bounds__(256) void kb_coalesce(const InstDev* __restrict__ i
   if (it < 0) return;
   {
     const Work w = load_item(items, it);
-    const InstDev& I = inst[w.inst];
-    coalesce_body<LAT, DEV, S, MODEL>((const S*)I.fbuf[1], (S*)I.cnext, I.g, I.itf, 2.0 * I.tau_c / I.tau_f,
-                                      1.0 - 1.0 / I.tau_c, I.tau_c, I.sig, w.idx);
+    kb_coalesce_item<LAT, DEV, S, MODEL>(inst[w.inst], w.idx);
+  }
+}
+
+// The t+1 ring and the fine-to-coarse transfer in one launch: blocks
+// [0, nrb) take ring items (64 lanes each), the rest TN blocks.
+template <int LAT, bool DEV, typename S, int MODEL>
+__global__ __launch_bounds__(256) void kb_ring_coalesce(const InstDev* __restrict__ inst, const Work* __restrict__ ritems,
+                                                        const int* __restrict__ rcount, const Work* __restrict__ titems,
+                                                        const int* __restrict__ tcount, int nrb) {
+  const int b = blockIdx.x;
+  if (b < nrb) {
+    if (threadIdx.x >= 64) return;
+    const int it = item_in(b, *rcount);
+    if (it < 0) return;
+    const Work w = load_item(ritems, it);
+    kb_ring_item<LAT, DEV, S, MODEL, 1>(inst[w.inst], w.idx, threadIdx.x);
+  } else {
+    const int it = item_in(b - nrb, *tcount);
+    if (it < 0) return;  // whole work group: the transfer synchronises its lanes
+    const Work w = load_item(titems, it);
+    kb_coalesce_item<LAT, DEV, S, MODEL>(inst[w.inst], w.idx);
   }
 }
 
@@ -224,6 +305,7 @@ __global__ void kb_advance(InstDev* __restrict__ inst, int n) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n || !inst[k].active) return;
   inst[k].cpar ^= 1;
+  inst[k].fpar ^= inst[k].fused;
   void* t = inst[k].ccur;
   inst[k].ccur = inst[k].cnext;
   inst[k].cnext = t;

@@ -1003,19 +1003,17 @@ __device__ __forceinline__ void fine2_s2(S* __restrict__ dst, const Geo& g, cons
 // of their own vector.  One lane per vector: waves made only of halo lanes
 // skip substep 2, and the halo costs (HXV HYR) / ((HXV - 2)(HYR - 2)) of the
 // substep-1 work.  MINW asks the compiler to fit that many waves per SIMD.
-template <int LAT, bool DEV, typename S, int MODEL, bool NT, int HXV, int HYR, int MINW>
-__global__ __launch_bounds__(HXV * HYR, MINW) void k_fine2(const S* __restrict__ src, S* __restrict__ dst,
-                                                         S* __restrict__ half, const Geo g, const S om, int ntx,
-                                                         int nty, int per_xcd) {
+// Tile `tile` (of ntx per row of tiles) of one grid; the whole work group
+// calls it.
+template <int LAT, bool DEV, typename S, int MODEL, bool NT, int HXV, int HYR>
+__device__ __forceinline__ void fine2_tile(const S* __restrict__ src, S* __restrict__ dst, S* __restrict__ half,
+                                           const Geo& g, const S om, int ntx, int tile) {
   using L = Lattice<LAT>;
   constexpr int V = VecOf<S>::V, Q = L::Q;
   constexpr int TXV = HXV - 2, TY = HYR - 2, RW = HXV * V;
   static_assert(L::D == 2, "fused fine substeps are two-dimensional");
   static_assert((HXV * HYR) % 64 == 0 && HXV * HYR <= 1024, "whole waves");
   __shared__ S lds[Q][HYR][RW];
-  const int b = blockIdx.x;
-  const int tile = (b % kXCD) * per_xcd + b / kXCD;
-  if (tile >= ntx * nty) return;  // whole work group, before any barrier
   const int tx = tile % ntx, ty = tile / ntx;
   const int ny = g.nf[1];
   const int nv = (g.nf[0] - 1 + V - 1) / V;
@@ -1040,6 +1038,23 @@ __global__ __launch_bounds__(HXV * HYR, MINW) void k_fine2(const S* __restrict__
     }
     fine2_s2<LAT, DEV, S, MODEL, NT>(dst, g, om, k, y, rm, r0, rp, rv * V);
   }
+}
+
+// Fine tiles per row of tiles and rows of tiles of a grid for HXV x HYR lanes.
+template <typename S>
+__host__ __device__ inline int fine2_ntx(const Geo& g, int HXV) {
+  return ((g.nf[0] - 1 + VecOf<S>::V - 1) / VecOf<S>::V + HXV - 3) / (HXV - 2);
+}
+__host__ __device__ inline int fine2_nty(const Geo& g, int HYR) { return (g.nf[1] - 2 + HYR - 3) / (HYR - 2); }
+
+template <int LAT, bool DEV, typename S, int MODEL, bool NT, int HXV, int HYR, int MINW>
+__global__ __launch_bounds__(HXV * HYR, MINW) void k_fine2(const S* __restrict__ src, S* __restrict__ dst,
+                                                         S* __restrict__ half, const Geo g, const S om, int ntx,
+                                                         int nty, int per_xcd) {
+  const int b = blockIdx.x;
+  const int tile = (b % kXCD) * per_xcd + b / kXCD;
+  if (tile >= ntx * nty) return;  // whole work group, before any barrier
+  fine2_tile<LAT, DEV, S, MODEL, NT, HXV, HYR>(src, dst, half, g, om, ntx, tile);
 }
 
 // ---------------------------------------------------------------------------

@@ -326,9 +326,7 @@ struct Grid final : GridBase {
   template <int MODEL, int HXV, int HYR>
   void go_fine2(const S* src, S* dst, S* half, hipStream_t s) {
     if constexpr (D == 2 && MODEL != M_HRR) {
-      constexpr int TXV = HXV - 2, TY = HYR - 2;
-      const int nv = (g.nf[0] - 1 + V - 1) / V;
-      const int ntx = (nv + TXV - 1) / TXV, nty = (g.nf[1] - 2 + TY - 1) / TY;
+      const int ntx = fine2_ntx<S>(g, HXV), nty = fine2_nty(g, HYR);
       const int per = (ntx * nty + kXCD - 1) / kXCD;
       hipLaunchKernelGGL((k_fine2<LAT, DEV, S, MODEL, NT, HXV, HYR, 4>), dim3((unsigned)(per * kXCD)),
                          dim3(HXV * HYR), 0, s, src, dst, half, g, (S)(1.0 - 1.0 / tau_f), ntx, nty, per);
@@ -831,15 +829,18 @@ struct BatchBase {
   virtual int64_t slot_steps(int slot) = 0;
 };
 
-// Device bytes one grid of this descriptor needs (populations, macro planes,
-// history, interface tables), without any scratch.
+// Device bytes one grid of this descriptor needs in a batch slot
+// (populations, macro planes, history, interface tables), without any
+// scratch.  D2Q9 BGK / RR keep a third fine population buffer (the fused
+// fine phase's t+1/2 ring and band).
 static int64_t grid_footprint(const lbm_grid_desc& d, const Geo& g) {
   const int Q = d.lattice == LBM_D2Q9 ? 9 : 19;
   const int D = g.D;
   const bool f32 = d.precision == LBM_FP32_DEV;
   const int64_t sb = f32 ? 4 : 8;
   auto pops = [&](int64_t NP) { return sb * (f32 ? pop_elems<float>(NP, Q) : pop_elems<double>(NP, Q)); };
-  int64_t bytes = 2 * pops(g.Ncp) + (g.has_fine ? 2 * pops(g.Nfp) : 0);
+  const int nfine = (g.D == 2 && d.collision != LBM_HRR) ? 3 : 2;
+  int64_t bytes = 2 * pops(g.Ncp) + (g.has_fine ? nfine * pops(g.Nfp) : 0);
   if (d.collision == LBM_HRR) bytes += sb * (1 + D) * (g.Ncp + g.Nfp + 128);
   if (g.has_fine) {
     int64_t nh = 0, ring_out = 1, ring_in = 1, tn_out = 1, tn_in = 1;
@@ -875,16 +876,18 @@ struct Batch final : BatchBase {
     lbm_grid_desc desc{};
     Geo g{};
     HostTables tabs;
-    DevBuf cbuf[2], fbuf[2], mac_c, mac_f, hist[3], G, d_hnode, d_rnode, d_rnp, d_rpt, d_tnf, d_tnc;
+    DevBuf cbuf[2], fbuf[3], mac_c, mac_f, hist[3], G, d_hnode, d_rnode, d_rnp, d_rpt, d_tnf, d_tnc;
     Iface itf{};
   };
+  // D2Q9 BGK / RR instances run both fine substeps in one phase (kb_fine2).
+  bool fused() const { return D == 2 && collision != LBM_HRR; }
   std::vector<std::unique_ptr<Inst>> slots;
   std::vector<InstDev> hinst;
   std::vector<int64_t> steps_done;
   std::vector<char> ring_partial;  // per slot: fine A holds a partial ring (see Grid)
   DevBuf d_inst, d_counts, d_items[W_KINDS];
-  size_t item_cap[W_KINDS] = {0, 0, 0, 0, 0, 0, 0};
-  int counts[W_KINDS] = {0, 0, 0, 0, 0, 0, 0};
+  size_t item_cap[W_KINDS] = {};
+  int counts[W_KINDS] = {};
   DevBuf tmp_rho, tmp_u, tmp_f;
   int var_c = Grid<LAT, PREC>::kDefaultVar, var_f = Grid<LAT, PREC>::kDefaultVar;
   bool use_graph = true, graph_ok = false;
@@ -953,6 +956,10 @@ struct Batch final : BatchBase {
       for (int64_t c = 0; c < (nr + 63) / 64; ++c) lists[W_RING].push_back({sl, (int)c});
       for (int64_t c = 0; c < (nt + 63) / 64; ++c) lists[W_TN].push_back({sl, (int)c});
       for (int64_t c = 0; c < (nt + PER - 1) / PER; ++c) lists[W_TNB].push_back({sl, (int)c});
+      if (I.fused) {
+        const int ntile = I.ntx * fine2_nty(I.g, kFineTileY);
+        for (int c = 0; c < ntile; ++c) lists[W_TILE].push_back({sl, c});
+      }
     }
     for (int k = 0; k < W_KINDS; ++k) {
       grow_items(k, lists[k].size());
@@ -990,7 +997,7 @@ struct Batch final : BatchBase {
       HIPCHK(hipMemset(in->mac_c.p, 0, in->mac_c.bytes));
     }
     if (g.has_fine) {
-      for (int p = 0; p < 2; ++p) {
+      for (int p = 0; p < (fused() ? 3 : 2); ++p) {
         in->fbuf[p].alloc(sb * (size_t)pop_elems<S>(g.Nfp, Q));
         HIPCHK(hipMemset(in->fbuf[p].p, 0, in->fbuf[p].bytes));
       }
@@ -1033,6 +1040,10 @@ struct Batch final : BatchBase {
     I.cbuf[1] = in->cbuf[1].p;
     I.fbuf[0] = in->fbuf[0].p;
     I.fbuf[1] = in->fbuf[1].p;
+    I.fh = in->fbuf[2].p;
+    I.fpar = 0;
+    I.fused = (g.has_fine && fused()) ? 1 : 0;
+    I.ntx = g.has_fine ? fine2_ntx<S>(g, kFineTileX) : 0;
     I.mac_c = in->mac_c.p;
     I.mac_f = in->mac_f.p;
     for (int k = 0; k < 3; ++k) I.hist[k] = in->hist[k].template as<double>();
@@ -1080,7 +1091,7 @@ struct Batch final : BatchBase {
     const double kf = I.tau_f / (2.0 * I.tau_c), omf = 1.0 - 1.0 / I.tau_f;
     const dim3 gr((unsigned)((in.itf.NR + 8 * kIfaceBlock - 1) / (8 * kIfaceBlock) * 8)), bl(kIfaceBlock);
     const double* H = I.hist[I.hs[1]];
-    S* A = (S*)I.fbuf[0];
+    S* A = (S*)I.fbuf[I.fpar];
     if (collision == LBM_BGK)
       hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_BGK, false>), gr, bl, 0, stream, H, A, in.g, in.itf, kf, omf, I.tau_f, I.sig);
     else if (collision == LBM_RR)
@@ -1106,7 +1117,7 @@ struct Batch final : BatchBase {
     const hipMemcpyKind k = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
     HIPCHK(hipMemcpy(tmp_rho.p, rho, sizeof(double) * N, k));
     HIPCHK(hipMemcpy(tmp_u.p, u, sizeof(double) * N * D, k));
-    S* dst = (S*)(level == 0 ? I.cbuf[I.cpar] : I.fbuf[0]);
+    S* dst = (S*)(level == 0 ? I.cbuf[I.cpar] : I.fbuf[I.fpar]);
     hipLaunchKernelGGL((k_set_state<LAT, DEV, S>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream,
                        tmp_rho.template as<double>(), tmp_u.template as<double>(), dst, in.g, level);
     if (level == 0 && in.g.has_fine) {
@@ -1139,9 +1150,9 @@ struct Batch final : BatchBase {
     complete_ring(sl);
     const InstDev& I = hinst[(size_t)sl];
     const int64_t N = level == 0 ? in.g.Nc : in.g.Nf;
-    const S* src = (const S*)(level == 0 ? I.cbuf[I.cpar] : I.fbuf[0]);
+    const S* src = (const S*)(level == 0 ? I.cbuf[I.cpar] : I.fbuf[I.fpar]);
     hipLaunchKernelGGL((k_macros<LAT, DEV, S>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream, src,
-                       (const S*)I.fbuf[0], tmp_rho.template as<double>(), tmp_u.template as<double>(), in.g, level);
+                       (const S*)I.fbuf[I.fpar], tmp_rho.template as<double>(), tmp_u.template as<double>(), in.g, level);
     HIPCHK(hipGetLastError());
     const hipMemcpyKind k = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     HIPCHK(hipMemcpyAsync(rho, tmp_rho.p, sizeof(double) * N, k, stream));
@@ -1163,7 +1174,7 @@ struct Batch final : BatchBase {
       tmp_f.p = nullptr;
       tmp_f.alloc(sizeof(double) * Q * (size_t)N);
     }
-    const S* src = (const S*)(level == 0 ? I.cbuf[I.cpar] : I.fbuf[0]);
+    const S* src = (const S*)(level == 0 ? I.cbuf[I.cpar] : I.fbuf[I.fpar]);
     hipLaunchKernelGGL((k_pops_out<LAT, DEV, S>), dim3((unsigned)((Q * N + 255) / 256)), dim3(256), 0, stream, src,
                        tmp_f.template as<double>(), in.g, level);
     HIPCHK(hipGetLastError());
@@ -1199,14 +1210,25 @@ struct Batch final : BatchBase {
     hipLaunchKernelGGL((kb_hist_capture<LAT, DEV, S, MODEL>), grid_of(W_HIST), ib, 0, s, di(), items(W_HIST),
                        cnt(W_HIST));
     if (MODEL != M_HRR) {
-      phase_stream<MODEL, 0, 0>(s, var_c);
-      phase_stream<MODEL, 1, 0>(s, var_f);
-      hipLaunchKernelGGL((kb_hist_time<F::N>), grid_of(W_HTIME), ib, 0, s, di(), items(W_HTIME), cnt(W_HTIME));
-      hipLaunchKernelGGL((kb_ring<LAT, DEV, S, MODEL, 0>), grid_of(W_RING), ib, 0, s, di(), items(W_RING), cnt(W_RING));
-      phase_stream<MODEL, 1, 1>(s, var_f);
-      hipLaunchKernelGGL((kb_ring<LAT, DEV, S, MODEL, 1>), grid_of(W_RING), ib, 0, s, di(), items(W_RING), cnt(W_RING));
-      hipLaunchKernelGGL((kb_coalesce<LAT, DEV, S, MODEL>), grid_of(W_TNB), dim3(256), 0, s, di(), items(W_TNB),
-                         cnt(W_TNB));
+      // as Grid::step_two_level: the capture interpolated G; the t+1/2 ring
+      // shares the coarse launch; the t+1 ring shares the transfer's launch
+      const unsigned nrb = grid_of(W_RING).x;
+      auto stream_ring = [&] {
+        hipLaunchKernelGGL((kb_stream_ring<LAT, DEV, S, MODEL, NT>), dim3(nrb + grid_of(W_COARSE).x), dim3(256),
+                           (unsigned)kVarLds[var_c], s, di(), items(W_RING), cnt(W_RING), items(W_COARSE),
+                           cnt(W_COARSE), (int)nrb);
+      };
+      if constexpr (D == 2) {  // fused() for BGK / RR
+        stream_ring();
+        hipLaunchKernelGGL((kb_fine2<LAT, DEV, S, MODEL, NT>), grid_of(W_TILE), dim3(kFineTileX * kFineTileY), 0, s, di(),
+                           items(W_TILE), cnt(W_TILE));
+      } else {
+        phase_stream<MODEL, 1, 0>(s, var_f);  // writes B's ring column: the t+1/2 ring follows
+        stream_ring();
+        phase_stream<MODEL, 1, 1>(s, var_f);
+      }
+      hipLaunchKernelGGL((kb_ring_coalesce<LAT, DEV, S, MODEL>), dim3(nrb + grid_of(W_TNB).x), dim3(256), 0, s, di(),
+                         items(W_RING), cnt(W_RING), items(W_TNB), cnt(W_TNB), (int)nrb);
     } else {
       phase_stream<M_HRR, 0, 0>(s, var_c);
       phase_stream<M_HRR, 1, 0>(s, var_f);
@@ -1277,6 +1299,7 @@ struct Batch final : BatchBase {
     HIPCHK(hipEventCreate(&e1));
     for (int level = 0; level < 2; ++level) {
       if (counts[level == 0 ? W_COARSE : W_FINE] == 0) continue;
+      if (level == 1 && fused()) continue;  // the fused fine phase has one shape
       float best = -1.f;
       int bv = 0;
       for (int v = 0; v < NVAR; ++v) {
