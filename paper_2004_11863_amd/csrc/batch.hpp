@@ -43,6 +43,26 @@ struct InstDev {
   int ntx;    // fused: fine tiles per row of tiles
 };
 
+// Pointers read from the descriptor table are generic to the compiler, which
+// then issues flat memory instructions; every buffer lives in device global
+// memory, and saying so gives global loads and stores (vector memory
+// counters only, immediate offsets).
+template <typename T>
+__device__ __forceinline__ T* glob(T* p) {
+  using GT = __attribute__((address_space(1))) T;
+  return (T*)(GT*)(uintptr_t)p;  // through an integer, so the cast is not folded away
+}
+__device__ __forceinline__ Iface glob(const Iface& a) {
+  Iface b = a;
+  b.hnode = glob(a.hnode);
+  b.rnode = glob(a.rnode);
+  b.rnp = glob(a.rnp);
+  b.rpt = glob(a.rpt);
+  b.tnf = glob(a.tnf);
+  b.tnc = glob(a.tnc);
+  return b;
+}
+
 struct Work {
   int inst;
   int idx;
@@ -98,13 +118,13 @@ __global__ __launch_bounds__(256) void kb_stream(const InstDev* __restrict__ ins
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
     if (LEVEL == 0) {
-      const S* src = (const S*)I.ccur;
-      S* dst = (S*)I.cnext;
-      stream_body<LAT, DEV, S, MODEL, 0, NT>(src, dst, (S*)I.mac_c, I.g, I.fc, (S)(1.0 - 1.0 / I.tau_c), w.idx);
+      const S* src = glob((const S*)I.ccur);
+      S* dst = glob((S*)I.cnext);
+      stream_body<LAT, DEV, S, MODEL, 0, NT>(src, dst, glob((S*)I.mac_c), I.g, I.fc, (S)(1.0 - 1.0 / I.tau_c), w.idx);
     } else {
-      const S* src = (const S*)I.fbuf[I.fpar ^ SUB];
-      S* dst = (S*)I.fbuf[I.fpar ^ SUB ^ 1];
-      stream_body<LAT, DEV, S, MODEL, 1, NT>(src, dst, (S*)I.mac_f, I.g, I.ff, (S)(1.0 - 1.0 / I.tau_f), w.idx);
+      const S* src = glob((const S*)I.fbuf[I.fpar ^ SUB]);
+      S* dst = glob((S*)I.fbuf[I.fpar ^ SUB ^ 1]);
+      stream_body<LAT, DEV, S, MODEL, 1, NT>(src, dst, glob((S*)I.mac_f), I.g, I.ff, (S)(1.0 - 1.0 / I.tau_f), w.idx);
     }
   }
 }
@@ -120,11 +140,11 @@ __global__ __launch_bounds__(256) void kb_collide(const InstDev* __restrict__ in
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
     if (LEVEL == 0) {
-      collide_hrr_body<LAT, DEV, S, 0, NT>((const S*)I.ccur, (S*)I.cnext, (const S*)I.mac_c, I.g,
+      collide_hrr_body<LAT, DEV, S, 0, NT>(glob((const S*)I.ccur), glob((S*)I.cnext), glob((const S*)I.mac_c), I.g,
                                            I.fc, (S)(1.0 - 1.0 / I.tau_c), (S)I.tau_c, (S)I.sig, w.idx);
     } else {
-      collide_hrr_body<LAT, DEV, S, 1, NT>((const S*)I.fbuf[I.fpar ^ SUB], (S*)I.fbuf[I.fpar ^ SUB ^ 1],
-                                           (const S*)I.mac_f, I.g, I.ff,
+      collide_hrr_body<LAT, DEV, S, 1, NT>(glob((const S*)I.fbuf[I.fpar ^ SUB]), glob((S*)I.fbuf[I.fpar ^ SUB ^ 1]),
+                                           glob((const S*)I.mac_f), I.g, I.ff,
                                            (S)(1.0 - 1.0 / I.tau_f), (S)I.tau_f, (S)I.sig, w.idx);
     }
   }
@@ -139,9 +159,9 @@ __global__ __launch_bounds__(64) void kb_hist_capture(const InstDev* __restrict_
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
     // BGK / RR: also the t+1/2 interpolation into G (H-RR: kb_hist_time)
-    hist_capture_body<LAT, DEV, S, MODEL>((const S*)I.ccur, I.hist[I.hs[2]], I.g, I.itf,
-                                          (int64_t)w.idx * 64 + threadIdx.x, MODEL == M_HRR ? nullptr : I.G,
-                                          I.hist[I.hs[0]], I.hist[I.hs[1]]);
+    hist_capture_body<LAT, DEV, S, MODEL>(glob((const S*)I.ccur), glob(I.hist[I.hs[2]]), I.g, glob(I.itf),
+                                          (int64_t)w.idx * 64 + threadIdx.x, MODEL == M_HRR ? nullptr : glob(I.G),
+                                          glob(I.hist[I.hs[0]]), glob(I.hist[I.hs[1]]));
   }
 }
 
@@ -153,7 +173,7 @@ __global__ __launch_bounds__(64) void kb_hist_strain(const InstDev* __restrict__
   {
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
-    hist_strain_body<LAT, S>((const S*)I.mac_c, I.hist[I.hs[2]], I.g, I.itf, (int64_t)w.idx * 64 + threadIdx.x);
+    hist_strain_body<LAT, S>(glob((const S*)I.mac_c), glob(I.hist[I.hs[2]]), I.g, glob(I.itf), (int64_t)w.idx * 64 + threadIdx.x);
   }
 }
 
@@ -168,7 +188,7 @@ __global__ __launch_bounds__(64) void kb_hist_time(const InstDev* __restrict__ i
     const InstDev& I = inst[w.inst];
     const int64_t k = (int64_t)w.idx * 64 + threadIdx.x;
     if (k < I.itf.NH * NFIELD)
-      I.G[k] = time_half(I.hist[I.hs[0]][k], I.hist[I.hs[1]][k], I.hist[I.hs[2]][k]);
+      glob(I.G)[k] = time_half(glob(I.hist[I.hs[0]])[k], glob(I.hist[I.hs[1]])[k], glob(I.hist[I.hs[2]])[k]);
   }
 }
 
@@ -179,9 +199,9 @@ __global__ __launch_bounds__(64) void kb_hist_time(const InstDev* __restrict__ i
 // completed before it is observed).
 template <int LAT, bool DEV, typename S, int MODEL, int SUB>
 __device__ __forceinline__ void kb_ring_item(const InstDev& I, int idx, int lane) {
-  const double* G = SUB == 0 ? I.G : I.hist[I.hs[2]];
-  S* dst = (S*)(SUB == 0 ? (I.fused ? I.fh : I.fbuf[I.fpar ^ 1]) : I.fbuf[I.fpar ^ I.fused]);
-  ring_body<LAT, DEV, S, MODEL, true>(G, dst, I.g, I.itf, I.tau_f / (2.0 * I.tau_c), 1.0 - 1.0 / I.tau_f, I.tau_f, I.sig,
+  const double* G = glob(SUB == 0 ? I.G : I.hist[I.hs[2]]);
+  S* dst = glob((S*)(SUB == 0 ? (I.fused ? I.fh : I.fbuf[I.fpar ^ 1]) : I.fbuf[I.fpar ^ I.fused]));
+  ring_body<LAT, DEV, S, MODEL, true>(G, dst, I.g, glob(I.itf), I.tau_f / (2.0 * I.tau_c), 1.0 - 1.0 / I.tau_f, I.tau_f, I.sig,
                                       (int64_t)idx * 64 + lane);
 }
 template <int LAT, bool DEV, typename S, int MODEL, int SUB>
@@ -213,7 +233,7 @@ __global__ __launch_bounds__(256) void kb_stream_ring(const InstDev* __restrict_
     if (it < 0) return;
     const Work w = load_item(citems, it);
     const InstDev& I = inst[w.inst];
-    stream_body<LAT, DEV, S, MODEL, 0, NT>((const S*)I.ccur, (S*)I.cnext, nullptr, I.g, I.fc, (S)(1.0 - 1.0 / I.tau_c),
+    stream_body<LAT, DEV, S, MODEL, 0, NT>(glob((const S*)I.ccur), glob((S*)I.cnext), nullptr, I.g, I.fc, (S)(1.0 - 1.0 / I.tau_c),
                                            w.idx);
   }
 }
@@ -228,8 +248,8 @@ __global__ __launch_bounds__(kFineTileX * kFineTileY) void kb_fine2(const InstDe
   if (it < 0) return;
   const Work w = load_item(items, it);
   const InstDev& I = inst[w.inst];
-  fine2_tile<LAT, DEV, S, MODEL, NT, kFineTileX, kFineTileY>((const S*)I.fbuf[I.fpar], (S*)I.fbuf[I.fpar ^ 1],
-                                                             (S*)I.fh, I.g, (S)(1.0 - 1.0 / I.tau_f), I.ntx, w.idx);
+  fine2_tile<LAT, DEV, S, MODEL, NT, kFineTileX, kFineTileY>(glob((const S*)I.fbuf[I.fpar]),
+                                                             glob((S*)I.fbuf[I.fpar ^ 1]), glob((S*)I.fh), I.g, (S)(1.0 - 1.0 / I.tau_f), I.ntx, w.idx);
 }
 
 // H-RR ring rho, u at t+1/2 (SUB 0) or t+1 (SUB 1).
@@ -242,7 +262,8 @@ __global__ __launch_bounds__(64) void kb_ring_macro(const InstDev* __restrict__ 
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
     const double c0 = SUB == 0 ? -0.125 : 0.0, c1 = SUB == 0 ? 0.75 : 0.0, c2 = SUB == 0 ? 0.375 : 1.0;
-    ring_macro_body<LAT, S>(I.hist[I.hs[0]], I.hist[I.hs[1]], I.hist[I.hs[2]], c0, c1, c2, (S*)I.mac_f, I.g, I.itf,
+    ring_macro_body<LAT, S>(glob(I.hist[I.hs[0]]), glob(I.hist[I.hs[1]]), glob(I.hist[I.hs[2]]), c0, c1, c2,
+                            glob((S*)I.mac_f), I.g, glob(I.itf),
                             (int64_t)w.idx * 64 + threadIdx.x);
   }
 }
@@ -255,14 +276,15 @@ __global__ __launch_bounds__(64) void kb_fict(const InstDev* __restrict__ inst, 
   {
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
-    fict_body<LAT, DEV, S, S>((const S*)I.fbuf[I.fpar ^ 1], (S*)I.mac_c, I.g, I.itf, (int64_t)w.idx * 64 + threadIdx.x);
+    fict_body<LAT, DEV, S, S>(glob((const S*)I.fbuf[I.fpar ^ 1]), glob((S*)I.mac_c), I.g, glob(I.itf), (int64_t)w.idx * 64 + threadIdx.x);
   }
 }
 
 // Fine-to-coarse transfer from the t+1/2 state (fh when fused, else B).
 template <int LAT, bool DEV, typename S, int MODEL>
 __device__ __forceinline__ void kb_coalesce_item(const InstDev& I, int idx) {
-  coalesce_body<LAT, DEV, S, MODEL>((const S*)(I.fused ? I.fh : I.fbuf[I.fpar ^ 1]), (S*)I.cnext, I.g, I.itf,
+  coalesce_body<LAT, DEV, S, MODEL>(glob((const S*)(I.fused ? I.fh : I.fbuf[I.fpar ^ 1])), glob((S*)I.cnext), I.g,
+                                    glob(I.itf),
                                     2.0 * I.tau_c / I.tau_f, 1.0 - 1.0 / I.tau_c, I.tau_c, I.sig, idx);
 }
 template <int LAT, bool DEV, typename S, int MODEL>
