@@ -219,7 +219,9 @@ int lbm_batch_step(lbm_batch_handle b, int n, void* hip_stream);
 /* on = 0: launch the phases directly instead of replaying the graph. */
 int lbm_batch_use_graph(lbm_batch_handle b, int on);
 /* Autotuner over the bulk-kernel variants of the whole batch; variants[2]
- * receives the chosen coarse and fine variant.  Synchronous. */
+ * receives the chosen coarse and fine variant (for D2Q9 BGK / RR batches,
+ * whose fine phase runs both substeps in one launch, the fine variant is its
+ * tile shape: 0 = 64 x 8, 1 = 32 x 8 lanes).  Synchronous. */
 int lbm_batch_tune(lbm_batch_handle b, int reps, int32_t variants[2]);
 /* info[3] = {grids held, lattice updates per coarse step over all grids,
  * device bytes of their state}. */

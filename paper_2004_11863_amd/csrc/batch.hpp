@@ -40,7 +40,7 @@ struct InstDev {
   int active;
   int fpar;   // fine buffer holding the state at integer times
   int fused;  // both fine substeps in one phase (D2Q9 BGK / RR): fpar flips every step
-  int ntx;    // fused: fine tiles per row of tiles
+  int ntx;    // fused: fine tiles per row of tiles (of the batch's tile shape)
 };
 
 // Pointers read from the descriptor table are generic to the compiler, which
@@ -77,12 +77,14 @@ enum WorkKind : int {
   W_RING = 4,    // 64 ring nodes
   W_TN = 5,      // 64 TN nodes
   W_TNB = 6,     // PER TN nodes (one fine-to-coarse work group)
-  W_TILE = 7,    // fused fine tile (kFineTileX x kFineTileY lanes)
+  W_TILE = 7,    // fused fine tile (the batch's tile shape)
   W_KINDS = 8
 };
 
-// Lanes of a fused fine tile (k_fine2 / kb_fine2) in the batch.
-constexpr int kFineTileX = 64, kFineTileY = 8;
+// Fused fine tile shapes of the batch (lanes, vectors x rows), chosen by its
+// autotuner: wide tiles suit long fine rows, narrow ones short rows.
+constexpr int kNTile = 2;
+constexpr int kTileX[kNTile] = {64, 32}, kTileY[kNTile] = {8, 8};
 
 // Item of this work group, or -1.  A phase launches one work group per entry
 // of its list's capacity (a multiple of 8); the live count is read from
@@ -240,15 +242,14 @@ __global__ __launch_bounds__(256) void kb_stream_ring(const InstDev* __restrict_
 
 // Both fine substeps of one tile (D2Q9 BGK / RR), A -> B with the t+1/2 ring
 // and band in fh.
-template <int LAT, bool DEV, typename S, int MODEL, bool NT>
-__global__ __launch_bounds__(kFineTileX * kFineTileY) void kb_fine2(const InstDev* __restrict__ inst,
-                                                                    const Work* __restrict__ items,
-                                                                    const int* __restrict__ count) {
+template <int LAT, bool DEV, typename S, int MODEL, bool NT, int HXV, int HYR>
+__global__ __launch_bounds__(HXV * HYR) void kb_fine2(const InstDev* __restrict__ inst, const Work* __restrict__ items,
+                                                      const int* __restrict__ count) {
   const int it = item_of(*count);
   if (it < 0) return;
   const Work w = load_item(items, it);
   const InstDev& I = inst[w.inst];
-  fine2_tile<LAT, DEV, S, MODEL, NT, kFineTileX, kFineTileY>(glob((const S*)I.fbuf[I.fpar]),
+  fine2_tile<LAT, DEV, S, MODEL, NT, HXV, HYR>(glob((const S*)I.fbuf[I.fpar]),
                                                              glob((S*)I.fbuf[I.fpar ^ 1]), glob((S*)I.fh), I.g, (S)(1.0 - 1.0 / I.tau_f), I.ntx, w.idx);
 }
 

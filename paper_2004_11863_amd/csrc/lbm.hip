@@ -879,8 +879,10 @@ struct Batch final : BatchBase {
     DevBuf cbuf[2], fbuf[3], mac_c, mac_f, hist[3], G, d_hnode, d_rnode, d_rnp, d_rpt, d_tnf, d_tnc;
     Iface itf{};
   };
-  // D2Q9 BGK / RR instances run both fine substeps in one phase (kb_fine2).
+  // D2Q9 BGK / RR instances run both fine substeps in one phase (kb_fine2),
+  // in tiles of shape tile_var (kTileX, kTileY).
   bool fused() const { return D == 2 && collision != LBM_HRR; }
+  int tile_var = 0;
   std::vector<std::unique_ptr<Inst>> slots;
   std::vector<InstDev> hinst;
   std::vector<int64_t> steps_done;
@@ -957,7 +959,7 @@ struct Batch final : BatchBase {
       for (int64_t c = 0; c < (nt + 63) / 64; ++c) lists[W_TN].push_back({sl, (int)c});
       for (int64_t c = 0; c < (nt + PER - 1) / PER; ++c) lists[W_TNB].push_back({sl, (int)c});
       if (I.fused) {
-        const int ntile = I.ntx * fine2_nty(I.g, kFineTileY);
+        const int ntile = fine2_ntx<S>(I.g, kTileX[tile_var]) * fine2_nty(I.g, kTileY[tile_var]);
         for (int c = 0; c < ntile; ++c) lists[W_TILE].push_back({sl, c});
       }
     }
@@ -1043,7 +1045,7 @@ struct Batch final : BatchBase {
     I.fh = in->fbuf[2].p;
     I.fpar = 0;
     I.fused = (g.has_fine && fused()) ? 1 : 0;
-    I.ntx = g.has_fine ? fine2_ntx<S>(g, kFineTileX) : 0;
+    I.ntx = g.has_fine ? fine2_ntx<S>(g, kTileX[tile_var]) : 0;
     I.mac_c = in->mac_c.p;
     I.mac_f = in->mac_f.p;
     for (int k = 0; k < 3; ++k) I.hist[k] = in->hist[k].template as<double>();
@@ -1203,6 +1205,33 @@ struct Batch final : BatchBase {
                        di(), items(LEVEL == 0 ? W_COARSE : W_FINE), cnt(LEVEL == 0 ? W_COARSE : W_FINE));
   }
 
+  // Fused fine phase (D2Q9 BGK / RR) in the current tile shape.
+  template <int MODEL>
+  void phase_fine2(hipStream_t s) {
+    if constexpr (D == 2 && MODEL != M_HRR) {
+      if (tile_var == 0)
+        hipLaunchKernelGGL((kb_fine2<LAT, DEV, S, MODEL, NT, kTileX[0], kTileY[0]>), grid_of(W_TILE),
+                           dim3(kTileX[0] * kTileY[0]), 0, s, di(), items(W_TILE), cnt(W_TILE));
+      else
+        hipLaunchKernelGGL((kb_fine2<LAT, DEV, S, MODEL, NT, kTileX[1], kTileY[1]>), grid_of(W_TILE),
+                           dim3(kTileX[1] * kTileY[1]), 0, s, di(), items(W_TILE), cnt(W_TILE));
+    }
+  }
+  // Sets the fused tile shape: every instance's tile count per row on the
+  // device (that field only: the rest of a descriptor advances on the device)
+  // and the tile list.
+  void set_tile_var(int tv) {
+    tile_var = tv;
+    for (int sl = 0; sl < capacity; ++sl) {
+      if (!slots[(size_t)sl] || !hinst[(size_t)sl].fused) continue;
+      const int ntx = fine2_ntx<S>(hinst[(size_t)sl].g, kTileX[tv]);
+      hinst[(size_t)sl].ntx = ntx;
+      HIPCHK(hipMemcpy(&(d_inst.template as<InstDev>() + sl)->ntx, &ntx, sizeof(int), hipMemcpyHostToDevice));
+    }
+    rebuild_lists();
+    drop_graph();
+  }
+
   template <int MODEL>
   void launch_step_model(hipStream_t s) {
     using F = HF<LAT, MODEL>;
@@ -1220,8 +1249,7 @@ struct Batch final : BatchBase {
       };
       if constexpr (D == 2) {  // fused() for BGK / RR
         stream_ring();
-        hipLaunchKernelGGL((kb_fine2<LAT, DEV, S, MODEL, NT>), grid_of(W_TILE), dim3(kFineTileX * kFineTileY), 0, s, di(),
-                           items(W_TILE), cnt(W_TILE));
+        phase_fine2<MODEL>(s);
       } else {
         phase_stream<MODEL, 1, 0>(s, var_f);  // writes B's ring column: the t+1/2 ring follows
         stream_ring();
@@ -1297,9 +1325,35 @@ struct Batch final : BatchBase {
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    if (fused() && counts[W_FINE] > 0) {
+      // fused fine phase: one variant per tile shape (it rewrites B and the
+      // half-step buffer, which the next step rewrites)
+      float best = -1.f;
+      int bt = 0;
+      for (int tv = 0; tv < kNTile; ++tv) {
+        set_tile_var(tv);
+        auto run = [&] {
+          if (collision == LBM_BGK) phase_fine2<M_BGK>(stream);
+          else phase_fine2<M_RR>(stream);
+        };
+        run();
+        HIPCHK(hipEventRecord(e0, stream));
+        for (int k = 0; k < reps; ++k) run();
+        HIPCHK(hipEventRecord(e1, stream));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (best < 0.f || ms < best) {
+          best = ms;
+          bt = tv;
+        }
+      }
+      set_tile_var(bt);
+      var_f = bt;
+    }
     for (int level = 0; level < 2; ++level) {
       if (counts[level == 0 ? W_COARSE : W_FINE] == 0) continue;
-      if (level == 1 && fused()) continue;  // the fused fine phase has one shape
+      if (level == 1 && fused()) continue;  // tuned above
       float best = -1.f;
       int bv = 0;
       for (int v = 0; v < NVAR; ++v) {
