@@ -68,6 +68,8 @@ def kernel_label(D, collision):
     if D == 2 and collision != "HRR":
         return ("k_fine2: both fine substeps of a coarse step (pull + collide twice, the t+1/2 state in LDS); "
                 "algorithmic bytes count 2 Q P_b per lattice update, 2 updates per node per launch")
+    if collision == "HRR" and D == 2:
+        return "k_hrr2: one H-RR fine substep in one pass (pull, velocities of the tile in LDS, strain rate, collide)"
     if collision == "HRR":
         return "k_collide_hrr: fine-level pull + H-RR collide (second pass)"
     return "k_stream: fine-level pull + collide"

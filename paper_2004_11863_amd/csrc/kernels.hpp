@@ -1058,6 +1058,112 @@ __global__ __launch_bounds__(HXV * HYR, MINW) void k_fine2(const S* __restrict__
 }
 
 // ---------------------------------------------------------------------------
+// One H-RR fine substep in one pass (D2Q9): a work group of HXV x HYR lanes,
+// one lane per vector of a tile and its one-vector / one-row halo.  Every
+// lane pulls its vector and takes the velocity of its nodes from the pulled
+// moments (ring nodes: from the velocity planes, where the ring macro step
+// stored them) into LDS; after the barrier the inner lanes take the strain
+// rate by centred differences of the neighbouring velocities and collide
+// their own pulled populations.  Same arithmetic as the velocity pass
+// followed by k_collide_hrr, without the velocity planes' round trip through
+// HBM and without pulling the populations twice.
+template <int LAT, bool DEV, typename S, bool NT, int HXV, int HYR>
+__device__ __forceinline__ void hrr2_tile(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ mac,
+                                          const Geo& g, const S om, const S tau, const S sig, int ntx, int tile) {
+  using L = Lattice<LAT>;
+  using N = Node<LAT, DEV, S>;
+  constexpr int V = VecOf<S>::V, Q = L::Q;
+  using VA = typename VT<S, V>::a;
+  constexpr int TXV = HXV - 2, TY = HYR - 2, RW = HXV * V;
+  static_assert(L::D == 2, "the one-pass H-RR tile is two-dimensional");
+  __shared__ S lu[2][HYR][RW];
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int nx = g.nf[0], ny = g.nf[1];
+  const int nv = (nx - 1 + V - 1) / V;
+  const int64_t NP = g.Nfp;
+  const int t = threadIdx.x;
+  const int rv = t % HXV, rr = t / HXV;
+  const int k = tx * TXV - 1 + rv, y = ty * TY + rr;  // vector and row of this lane (k >= -1, y >= 0)
+  const int x0 = 1 + V * k;
+  const bool inner = rr >= 1 && rr <= TY && rv >= 1 && rv <= TXV && k < nv && y <= ny - 2;
+  const bool mid = y >= 1 && y <= ny - 2 && k >= 0 && k < nv;
+  VA v[Q];
+  if (mid) {
+    const Pull<S, Q, V, 1, 2> pl(g.pf, g.fxo, x0, y, 0, nx, ny, 1);
+    pl.template load_all<L>(src, v);
+    VA ux, uy;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      S f[Q], rho, r0, u[3];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) f[i] = v[i][j];
+      N::moments(f, rho, r0, u);
+      ux[j] = u[0];
+      uy[j] = u[1];
+    }
+    if (k == nv - 1) {
+      // the ring node x = nx - 1 inside the last vector of the row
+      const int jr = nx - 1 - x0;
+      const int64_t p = fpos(g, nx - 1, y, 0);
+      const S rx = mac[NP + p], ry = mac[2 * NP + p];
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        if (j == jr) {
+          ux[j] = rx;
+          uy[j] = ry;
+        }
+    }
+    *(VA*)&lu[0][rr][rv * V] = ux;
+    *(VA*)&lu[1][rr][rv * V] = uy;
+  } else if (y <= ny - 1 && k < nv) {
+    // ring row, or the vector ending at ring node x = 0
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int x = x0 + j;
+      if (x < 0 || x > nx - 1) continue;
+      const int64_t p = fpos(g, x, y, 0);
+      lu[0][rr][rv * V + j] = mac[NP + p];
+      lu[1][rr][rv * V + j] = mac[2 * NP + p];
+    }
+  }
+  __syncthreads();
+  if (!inner) return;
+  const int c = rv * V;
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    // gr[a][b] = (u_b(x + e_a) - u_b(x - e_a)) / 2
+    const S g00 = (lu[0][rr][c + j + 1] - lu[0][rr][c + j - 1]) * S(0.5);
+    const S g01 = (lu[1][rr][c + j + 1] - lu[1][rr][c + j - 1]) * S(0.5);
+    const S g10 = (lu[0][rr + 1][c + j] - lu[0][rr - 1][c + j]) * S(0.5);
+    const S g11 = (lu[1][rr + 1][c + j] - lu[1][rr - 1][c + j]) * S(0.5);
+    Sym<S> Sr;
+    Sr.xx = g00;
+    Sr.yy = g11;
+    Sr.xy = S(0.5) * (g01 + g10);
+    Sr.zz = Sr.xz = Sr.yz = S(0);
+    S f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = v[i][j];
+    N::collide(f, M_HRR, om, tau, sig, &Sr);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i][j] = f[i];
+  }
+  const int64_t own = fpos(g, x0, y, 0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + pop_at<S, Q>(own, i)), v[i]);
+}
+
+template <int LAT, bool DEV, typename S, bool NT, int HXV, int HYR>
+__global__ __launch_bounds__(HXV * HYR) void k_hrr2(const S* __restrict__ src, S* __restrict__ dst,
+                                                    const S* __restrict__ mac, const Geo g, const S om, const S tau,
+                                                    const S sig, int ntx, int nty, int per_xcd) {
+  const int b = blockIdx.x;
+  const int tile = (b % kXCD) * per_xcd + b / kXCD;
+  if (tile >= ntx * nty) return;  // whole work group, before any barrier
+  hrr2_tile<LAT, DEV, S, NT, HXV, HYR>(src, dst, mac, g, om, tau, sig, ntx, tile);
+}
+
+// ---------------------------------------------------------------------------
 // Both fine substeps of a coarse step in one kernel (D3Q19, BGK / RR).
 // A work group owns TXV vectors x TY rows of middle nodes over a run of zlen
 // planes and walks it along z.  The iteration for plane z computes substep 1

@@ -309,6 +309,28 @@ struct Grid final : GridBase {
                        kf, omf, tau_f, sig, (int)nrb);
   }
 
+  // One H-RR fine substep in one pass (D2Q9, k_hrr2): variants of the fine
+  // H-RR role are tile shapes (lanes, vectors x rows) 64 x 8, 32 x 8,
+  // 32 x 16, 128 x 4.
+  template <int HXV, int HYR>
+  void go_hrr2(const S* src, S* dst, const S* mac, hipStream_t s) {
+    if constexpr (D == 2) {
+      const int ntx = fine2_ntx<S>(g, HXV), nty = fine2_nty(g, HYR);
+      const int per = (ntx * nty + kXCD - 1) / kXCD;
+      hipLaunchKernelGGL((k_hrr2<LAT, DEV, S, NT, HXV, HYR>), dim3((unsigned)(per * kXCD)), dim3(HXV * HYR), 0, s, src,
+                         dst, mac, g, (S)(1.0 - 1.0 / tau_f), (S)tau_f, (S)sig, ntx, nty, per);
+    }
+  }
+  void launch_hrr2(const S* src, S* dst, const S* mac, hipStream_t s, int v = -1) {
+    if (v < 0) v = var[3];
+    switch (v) {
+      case 0: go_hrr2<64, 8>(src, dst, mac, s); break;
+      case 1: go_hrr2<32, 8>(src, dst, mac, s); break;
+      case 2: go_hrr2<32, 16>(src, dst, mac, s); break;
+      default: go_hrr2<128, 4>(src, dst, mac, s); break;
+    }
+  }
+
   template <int LEVEL>
   void launch_collide_hrr(const S* src, S* dst, const S* mac, double tau, hipStream_t s, int v = -1) {
     if (v < 0) v = var[2 + LEVEL];
@@ -473,6 +495,8 @@ struct Grid final : GridBase {
       else launch_stream<M_HRR, 1>(fineA(), fineB(), mac_f.as<S>(), tau_f, s, v);
     } else if (role == 2) {
       launch_collide_hrr<0>(c_cur, c_oth, mac_c.as<S>(), tau_c, s, v);
+    } else if (D == 2) {
+      launch_hrr2(fineA(), fineB(), mac_f.as<S>(), s, v);
     } else {
       launch_collide_hrr<1>(fineA(), fineB(), mac_f.as<S>(), tau_f, s, v);
     }
@@ -494,6 +518,7 @@ struct Grid final : GridBase {
       const bool used = (role & 1) ? g.has_fine : true;
       const bool hrr_role = role >= 2;
       if (!used || (hrr_role && desc.collision != LBM_HRR)) continue;
+      if (role == 1 && D == 2 && desc.collision == LBM_HRR) continue;  // no fine velocity pass (k_hrr2)
 
       float best = -1.f;
       for (int v = 0; v < NVAR; ++v) {
@@ -576,17 +601,28 @@ struct Grid final : GridBase {
       // velocity passes (rho, u of the pulled states), ring rho, u, then
       // pull-stream + collide with the strain rate of those velocities
       launch_stream<M_HRR, 0>(csrc, cdst, mc, tau_c, s);
-      launch_stream<M_HRR, 1>(fA, fB, mf, tau_f, s);
-      hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, c0, c1, c2, mf, g, itf);
-      timed(s, [&] { launch_collide_hrr<1>(fA, fB, mf, tau_f, s); });
+      if constexpr (D == 2) {
+        // one pass per fine substep (k_hrr2): ring rho, u first
+        hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, c0, c1, c2, mf, g, itf);
+        timed(s, [&] { launch_hrr2(fA, fB, mf, s); });
+      } else {
+        launch_stream<M_HRR, 1>(fA, fB, mf, tau_f, s);
+        hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, c0, c1, c2, mf, g, itf);
+        timed(s, [&] { launch_collide_hrr<1>(fA, fB, mf, tau_f, s); });
+      }
       hipLaunchKernelGGL((k_fict<LAT, DEV, S, S>), dim3(bt), dim3(IB), 0, s, fB, mc, g, itf);
       hipLaunchKernelGGL((k_hist_strain<LAT, S>), dim3(bh), dim3(IB), 0, s, mc, Hp, g, itf);
       hipLaunchKernelGGL(k_hist_time, dim3(bg), dim3(256), 0, s, Hm, H0, Hp, G.as<double>(), NH * F::N);
       hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR, true>), dim3(br), dim3(IB), 0, s, G.as<double>(), fB, g, itf, kf, omf,
                          tau_f, sig);
-      launch_stream<M_HRR, 1>(fB, fA, mf, tau_f, s);
-      hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, 0.0, 0.0, 1.0, mf, g, itf);
-      timed(s, [&] { launch_collide_hrr<1>(fB, fA, mf, tau_f, s); });
+      if constexpr (D == 2) {
+        hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, 0.0, 0.0, 1.0, mf, g, itf);
+        timed(s, [&] { launch_hrr2(fB, fA, mf, s); });
+      } else {
+        launch_stream<M_HRR, 1>(fB, fA, mf, tau_f, s);
+        hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, 0.0, 0.0, 1.0, mf, g, itf);
+        timed(s, [&] { launch_collide_hrr<1>(fB, fA, mf, tau_f, s); });
+      }
       hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR, true>), dim3(br), dim3(IB), 0, s, Hp, fA, g, itf, kf, omf, tau_f, sig);
       // coarse collision before the TN transfer: the vector kernel also
       // passes over TN nodes, which the transfer then overwrites
