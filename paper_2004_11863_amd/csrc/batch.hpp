@@ -167,7 +167,7 @@ __global__ __launch_bounds__(64) void kb_hist_capture(const InstDev* __restrict_
   }
 }
 
-template <int LAT, typename S>
+template <int LAT, bool DEV, typename S>
 __global__ __launch_bounds__(64) void kb_hist_strain(const InstDev* __restrict__ inst, const Work* __restrict__ items,
                                                      const int* __restrict__ count) {
   const int it = item_of(*count);
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(64) void kb_hist_strain(const InstDev* __restrict__
   {
     const Work w = load_item(items, it);
     const InstDev& I = inst[w.inst];
-    hist_strain_body<LAT, S>(glob((const S*)I.mac_c), glob(I.hist[I.hs[2]]), I.g, glob(I.itf), (int64_t)w.idx * 64 + threadIdx.x);
+    hist_strain_body<LAT, DEV, S, false>(nullptr, glob((const S*)I.mac_c), glob(I.hist[I.hs[2]]), I.g, glob(I.itf), (int64_t)w.idx * 64 + threadIdx.x);
   }
 }
 

@@ -551,9 +551,31 @@ __global__ void k_hist_capture(const S* __restrict__ src, double* __restrict__ H
 // H-RR: coarse strain rate at t+1 on the history nodes, by centred
 // differences of the coarse velocity planes (TN entries come from the
 // fictitious propagation on the fine level).
-template <int LAT, typename T>
-__device__ __forceinline__ void hist_strain_body(const T* __restrict__ mac_c, double* __restrict__ H, const Geo& g,
-                                        const Iface& itf, int64_t h) {
+// With PULL (the one-pass coarse H-RR path, which writes no velocity
+// planes) the velocities of the neighbours are the moments of their pulled
+// coarse state, computed here exactly as the velocity pass would (TN nodes:
+// the planes, where the fictitious propagation stored them).
+template <int LAT, bool DEV, typename T, bool PULL>
+__device__ __forceinline__ T hist_u(const T* __restrict__ src, const T* __restrict__ mac_c, const Geo& g, int x, int y,
+                                    int z, int b) {
+  using L = Lattice<LAT>;
+  using N = Node<LAT, DEV, T>;
+  constexpr int Q = L::Q;
+  const int64_t ip = cpos(g, x, y, z);
+  if (!PULL || coarse_class(g, x, y, z) == CC_TN) return mac_c[(1 + b) * g.Ncp + ip];
+  T f[Q], rho, r0, u[3];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int xs = wrap(x - L::cx(i), g.n[0]), ys = wrap(y - L::cy(i), g.n[1]);
+    const int zs = L::D == 3 ? wrap(z - L::cz(i), g.n[2]) : 0;
+    f[i] = src[pop_at<T, Q>(cpos(g, xs, ys, zs), i)];
+  }
+  N::moments(f, rho, r0, u);
+  return u[b];
+}
+template <int LAT, bool DEV, typename T, bool PULL>
+__device__ __forceinline__ void hist_strain_body(const T* __restrict__ src, const T* __restrict__ mac_c,
+                                                 double* __restrict__ H, const Geo& g, const Iface& itf, int64_t h) {
   using L = Lattice<LAT>;
   using F = HF<LAT, M_HRR>;
   constexpr int D = L::D;
@@ -566,8 +588,9 @@ __device__ __forceinline__ void hist_strain_body(const T* __restrict__ mac_c, do
     int cp[3] = {x, y, z}, cm[3] = {x, y, z};
     cp[a] = wrap(cp[a] + 1, n3[a]);
     cm[a] = wrap(cm[a] - 1, n3[a]);
-    const int64_t ip = cpos(g, cp[0], cp[1], cp[2]), im = cpos(g, cm[0], cm[1], cm[2]);
-    for (int b = 0; b < D; ++b) gr[a][b] = 0.5 * ((double)mac_c[(1 + b) * g.Ncp + ip] - (double)mac_c[(1 + b) * g.Ncp + im]);
+    for (int b = 0; b < D; ++b)
+      gr[a][b] = 0.5 * ((double)hist_u<LAT, DEV, T, PULL>(src, mac_c, g, cp[0], cp[1], cp[2], b) -
+                        (double)hist_u<LAT, DEV, T, PULL>(src, mac_c, g, cm[0], cm[1], cm[2], b));
   }
   const Sym<double> S{gr[0][0], gr[1][1], gr[2][2], 0.5 * (gr[0][1] + gr[1][0]), 0.5 * (gr[0][2] + gr[2][0]),
                       0.5 * (gr[1][2] + gr[2][1])};
@@ -577,9 +600,10 @@ __device__ __forceinline__ void hist_strain_body(const T* __restrict__ mac_c, do
 #pragma unroll
   for (int k = 0; k < NS<D>::value; ++k) H[(F::S + k) * NH + h] = v[k];
 }
-template <int LAT, typename T>
-__global__ void k_hist_strain(const T* __restrict__ mac_c, double* __restrict__ H, const Geo g, const Iface itf) {
-  hist_strain_body<LAT, T>(mac_c, H, g, itf, xcd_block() * blockDim.x + threadIdx.x);
+template <int LAT, bool DEV, typename T, bool PULL>
+__global__ void k_hist_strain(const T* __restrict__ src, const T* __restrict__ mac_c, double* __restrict__ H,
+                              const Geo g, const Iface itf) {
+  hist_strain_body<LAT, DEV, T, PULL>(src, mac_c, H, g, itf, xcd_block() * blockDim.x + threadIdx.x);
 }
 
 
@@ -1151,6 +1175,91 @@ __device__ __forceinline__ void hrr2_tile(const S* __restrict__ src, S* __restri
   const int64_t own = fpos(g, x0, y, 0);
 #pragma unroll
   for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + pop_at<S, Q>(own, i)), v[i]);
+}
+
+// The coarse level in one pass (D2Q9 H-RR; rows a whole number of vectors):
+// as hrr2_tile, periodic -- halo lanes take the wrapped neighbour vector and
+// row -- with the velocity of TN nodes from the velocity planes (the
+// fictitious propagation stored it there) and vectors wholly inside the
+// covered box skipped, as k_collide_hrr does.
+template <int LAT, bool DEV, typename S, bool NT, int HXV, int HYR>
+__device__ __forceinline__ void hrr2c_tile(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ mac,
+                                           const Geo& g, const S om, const S tau, const S sig, int ntx, int tile) {
+  using L = Lattice<LAT>;
+  using N = Node<LAT, DEV, S>;
+  constexpr int V = VecOf<S>::V, Q = L::Q;
+  using VA = typename VT<S, V>::a;
+  constexpr int TXV = HXV - 2, TY = HYR - 2, RW = HXV * V;
+  static_assert(L::D == 2, "the one-pass H-RR tile is two-dimensional");
+  __shared__ S lu[2][HYR][RW];
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int nx = g.n[0], ny = g.n[1];
+  const int nv = nx / V;
+  const int64_t NP = g.Ncp;
+  const int t = threadIdx.x;
+  const int rv = t % HXV, rr = t / HXV;
+  const int kr = tx * TXV - 1 + rv, yr = ty * TY - 1 + rr;  // unwrapped vector and row (>= -1)
+  const int k = (kr + nv) % nv, y = (yr + ny) % ny;          // a tile may be wider than the period
+  const int x0 = V * k;
+  const bool skip = skip_vec<0>(g, x0, V, y, 0, nx);
+  const bool inner = rr >= 1 && rr <= TY && rv >= 1 && rv <= TXV && kr < nv && yr < ny && !skip;
+  VA v[Q];
+  if (!skip) {
+    const Pull<S, Q, V, 0, 2> pl(g.pc, 0, x0, y, 0, nx, ny, 1);
+    pl.template load_all<L>(src, v);
+    VA ux, uy;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      if (coarse_class(g, x0 + j, y, 0) == CC_TN) {
+        const int64_t p = cpos(g, x0 + j, y, 0);
+        ux[j] = mac[NP + p];
+        uy[j] = mac[2 * NP + p];
+      } else {
+        S f[Q], rho, r0, u[3];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = v[i][j];
+        N::moments(f, rho, r0, u);
+        ux[j] = u[0];
+        uy[j] = u[1];
+      }
+    }
+    *(VA*)&lu[0][rr][rv * V] = ux;
+    *(VA*)&lu[1][rr][rv * V] = uy;
+  }
+  __syncthreads();
+  if (!inner) return;
+  const int c = rv * V;
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    const S g00 = (lu[0][rr][c + j + 1] - lu[0][rr][c + j - 1]) * S(0.5);
+    const S g01 = (lu[1][rr][c + j + 1] - lu[1][rr][c + j - 1]) * S(0.5);
+    const S g10 = (lu[0][rr + 1][c + j] - lu[0][rr - 1][c + j]) * S(0.5);
+    const S g11 = (lu[1][rr + 1][c + j] - lu[1][rr - 1][c + j]) * S(0.5);
+    Sym<S> Sr;
+    Sr.xx = g00;
+    Sr.yy = g11;
+    Sr.xy = S(0.5) * (g01 + g10);
+    Sr.zz = Sr.xz = Sr.yz = S(0);
+    S f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = v[i][j];
+    N::collide(f, M_HRR, om, tau, sig, &Sr);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i][j] = f[i];
+  }
+  const int64_t own = cpos(g, x0, y, 0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + pop_at<S, Q>(own, i)), v[i]);
+}
+
+template <int LAT, bool DEV, typename S, bool NT, int HXV, int HYR>
+__global__ __launch_bounds__(HXV * HYR) void k_hrr2c(const S* __restrict__ src, S* __restrict__ dst,
+                                                     const S* __restrict__ mac, const Geo g, const S om, const S tau,
+                                                     const S sig, int ntx, int nty, int per_xcd) {
+  const int b = blockIdx.x;
+  const int tile = (b % kXCD) * per_xcd + b / kXCD;
+  if (tile >= ntx * nty) return;  // whole work group, before any barrier
+  hrr2c_tile<LAT, DEV, S, NT, HXV, HYR>(src, dst, mac, g, om, tau, sig, ntx, tile);
 }
 
 template <int LAT, bool DEV, typename S, bool NT, int HXV, int HYR>

@@ -321,6 +321,27 @@ struct Grid final : GridBase {
                          dst, mac, g, (S)(1.0 - 1.0 / tau_f), (S)tau_f, (S)sig, ntx, nty, per);
     }
   }
+  // The coarse level in one pass (D2Q9 H-RR, rows a whole number of vectors:
+  // coarse_one_pass()); same tile variants, role 2.
+  bool coarse_one_pass() const { return D == 2 && desc.collision == LBM_HRR && g.n[0] % V == 0; }
+  template <int HXV, int HYR>
+  void go_hrr2c(const S* src, S* dst, const S* mac, hipStream_t s) {
+    if constexpr (D == 2) {
+      const int ntx = (g.n[0] / V + HXV - 3) / (HXV - 2), nty = (g.n[1] + HYR - 3) / (HYR - 2);
+      const int per = (ntx * nty + kXCD - 1) / kXCD;
+      hipLaunchKernelGGL((k_hrr2c<LAT, DEV, S, NT, HXV, HYR>), dim3((unsigned)(per * kXCD)), dim3(HXV * HYR), 0, s, src,
+                         dst, mac, g, (S)(1.0 - 1.0 / tau_c), (S)tau_c, (S)sig, ntx, nty, per);
+    }
+  }
+  void launch_hrr2c(const S* src, S* dst, const S* mac, hipStream_t s, int v = -1) {
+    if (v < 0) v = var[2];
+    switch (v) {
+      case 0: go_hrr2c<64, 8>(src, dst, mac, s); break;
+      case 1: go_hrr2c<32, 8>(src, dst, mac, s); break;
+      case 2: go_hrr2c<32, 16>(src, dst, mac, s); break;
+      default: go_hrr2c<128, 4>(src, dst, mac, s); break;
+    }
+  }
   void launch_hrr2(const S* src, S* dst, const S* mac, hipStream_t s, int v = -1) {
     if (v < 0) v = var[3];
     switch (v) {
@@ -493,6 +514,8 @@ struct Grid final : GridBase {
       if (model == M_BGK) launch_stream<M_BGK, 1>(fineA(), fineB(), nullptr, tau_f, s, v);
       else if (model == M_RR) launch_stream<M_RR, 1>(fineA(), fineB(), nullptr, tau_f, s, v);
       else launch_stream<M_HRR, 1>(fineA(), fineB(), mac_f.as<S>(), tau_f, s, v);
+    } else if (role == 2 && coarse_one_pass()) {
+      launch_hrr2c(c_cur, c_oth, mac_c.as<S>(), s, v);
     } else if (role == 2) {
       launch_collide_hrr<0>(c_cur, c_oth, mac_c.as<S>(), tau_c, s, v);
     } else if (D == 2) {
@@ -519,6 +542,7 @@ struct Grid final : GridBase {
       const bool hrr_role = role >= 2;
       if (!used || (hrr_role && desc.collision != LBM_HRR)) continue;
       if (role == 1 && D == 2 && desc.collision == LBM_HRR) continue;  // no fine velocity pass (k_hrr2)
+      if (role == 0 && coarse_one_pass()) continue;                    // no coarse velocity pass (k_hrr2c)
 
       float best = -1.f;
       for (int v = 0; v < NVAR; ++v) {
@@ -600,7 +624,8 @@ struct Grid final : GridBase {
       S* mf = mac_f.as<S>();
       // velocity passes (rho, u of the pulled states), ring rho, u, then
       // pull-stream + collide with the strain rate of those velocities
-      launch_stream<M_HRR, 0>(csrc, cdst, mc, tau_c, s);
+      const bool one_c = coarse_one_pass();
+      if (!one_c) launch_stream<M_HRR, 0>(csrc, cdst, mc, tau_c, s);
       if constexpr (D == 2) {
         // one pass per fine substep (k_hrr2): ring rho, u first
         hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, c0, c1, c2, mf, g, itf);
@@ -611,7 +636,10 @@ struct Grid final : GridBase {
         timed(s, [&] { launch_collide_hrr<1>(fA, fB, mf, tau_f, s); });
       }
       hipLaunchKernelGGL((k_fict<LAT, DEV, S, S>), dim3(bt), dim3(IB), 0, s, fB, mc, g, itf);
-      hipLaunchKernelGGL((k_hist_strain<LAT, S>), dim3(bh), dim3(IB), 0, s, mc, Hp, g, itf);
+      // the coarse velocities at the history nodes' neighbours: from the
+      // velocity pass, or (one-pass coarse level) pulled here
+      if (one_c) hipLaunchKernelGGL((k_hist_strain<LAT, DEV, S, true>), dim3(bh), dim3(IB), 0, s, csrc, mc, Hp, g, itf);
+      else hipLaunchKernelGGL((k_hist_strain<LAT, DEV, S, false>), dim3(bh), dim3(IB), 0, s, csrc, mc, Hp, g, itf);
       hipLaunchKernelGGL(k_hist_time, dim3(bg), dim3(256), 0, s, Hm, H0, Hp, G.as<double>(), NH * F::N);
       hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR, true>), dim3(br), dim3(IB), 0, s, G.as<double>(), fB, g, itf, kf, omf,
                          tau_f, sig);
@@ -626,7 +654,8 @@ struct Grid final : GridBase {
       hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR, true>), dim3(br), dim3(IB), 0, s, Hp, fA, g, itf, kf, omf, tau_f, sig);
       // coarse collision before the TN transfer: the vector kernel also
       // passes over TN nodes, which the transfer then overwrites
-      launch_collide_hrr<0>(csrc, cdst, mc, tau_c, s);
+      if (one_c) launch_hrr2c(csrc, cdst, mc, s);
+      else launch_collide_hrr<0>(csrc, cdst, mc, tau_c, s);
       hipLaunchKernelGGL((k_coalesce<LAT, DEV, S, M_HRR>), dim3(bc), dim3(256), 0, s, fB, cdst, g, itf, kc, omc,
                          tau_c, sig);
     }
@@ -1299,7 +1328,7 @@ struct Batch final : BatchBase {
       hipLaunchKernelGGL((kb_ring_macro<LAT, S, 0>), grid_of(W_RING), ib, 0, s, di(), items(W_RING), cnt(W_RING));
       phase_collide<1, 0>(s, var_f);
       hipLaunchKernelGGL((kb_fict<LAT, DEV, S>), grid_of(W_TN), ib, 0, s, di(), items(W_TN), cnt(W_TN));
-      hipLaunchKernelGGL((kb_hist_strain<LAT, S>), grid_of(W_HIST), ib, 0, s, di(), items(W_HIST), cnt(W_HIST));
+      hipLaunchKernelGGL((kb_hist_strain<LAT, DEV, S>), grid_of(W_HIST), ib, 0, s, di(), items(W_HIST), cnt(W_HIST));
       hipLaunchKernelGGL((kb_hist_time<F::N>), grid_of(W_HTIME), ib, 0, s, di(), items(W_HTIME), cnt(W_HTIME));
       hipLaunchKernelGGL((kb_ring<LAT, DEV, S, M_HRR, 0>), grid_of(W_RING), ib, 0, s, di(), items(W_RING), cnt(W_RING));
       phase_stream<M_HRR, 1, 1>(s, var_f);
