@@ -172,10 +172,13 @@ int lbm_kernel_time(lbm_handle h, int64_t* launches, double* mean_ms, int64_t* n
  * and 32 x 8.  For the fine role of a D3Q19 BGK / RR grid, variants 0 and 1
  * run the two substeps as two launches (capped at 2 and 3 resident work
  * groups per CU), 2 and 3 as one kernel walking tiles of 14 x 14 and 30 x 6
- * along z.  For the fine H-RR role of a D2Q9 grid, whose kernel runs a
- * substep in one pass (velocities of the tile in LDS), the variants are
- * tiles of 64 x 8, 32 x 8, 32 x 16 and 128 x 4 lanes.  Every variant
- * computes bitwise the same result. */
+ * along z.  For the H-RR roles of a D2Q9 grid, whose kernels run a coarse
+ * step or a fine substep in one pass (velocities of the tile in LDS), the
+ * variants are tiles of 64 x 8, 32 x 8, 32 x 16 and 128 x 4 lanes; for the
+ * fine H-RR role of a D3Q19 grid, variants 0 and 1 run the velocity pass and
+ * the collision (capped at 2 and 3 resident work groups per CU), 2 and 3 one
+ * pass walking tiles of 30 x 6 and 62 x 2 along z.  Every variant computes
+ * bitwise the same result. */
 enum { LBM_N_VARIANTS = 4 };
 /* Autotuner: times every bulk-kernel variant of each bulk role of this grid
  * -- coarse stream, fine stream, coarse and fine H-RR collision -- over reps

@@ -1471,6 +1471,146 @@ __global__ __launch_bounds__(256, MINW) void k_fine3(const S* __restrict__ src, 
 }
 
 // ---------------------------------------------------------------------------
+// One H-RR fine substep in one pass (D3Q19, k_hrr3): a work group owns TXV
+// vectors x TY rows of a run of zlen planes and walks it along z, one lane per
+// vector of the tile and its x/y halo.  The iteration for plane z pulls plane
+// z+1 into registers and writes its velocities into one of three LDS plane
+// slots (ring nodes: from the velocity planes, where the ring macro step
+// stored them); after the barrier the inner lanes take the strain rate of
+// plane z from the three slots and collide the populations they pulled one
+// iteration earlier.  Same arithmetic as the velocity pass followed by
+// k_collide_hrr.
+template <int LAT, bool DEV, typename S>
+__device__ __forceinline__ void hrr3_pull(const S* __restrict__ src, const S* __restrict__ mac, const Geo& g, int k,
+                                          int y, int z, int nv, typename VT<S, VecOf<S>::V>::a* P,
+                                          typename VT<S, VecOf<S>::V>::a* u) {
+  using L = Lattice<LAT>;
+  using N = Node<LAT, DEV, S>;
+  constexpr int V = VecOf<S>::V, Q = L::Q;
+  const int nx = g.nf[0], ny = g.nf[1], nz = g.nf[2];
+  const int64_t NP = g.Nfp;
+  const int x0 = 1 + V * k;
+  if (y == 0 || y == ny - 1 || z == 0 || z == nz - 1 || k == -1) {
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      const int x = x0 + j;
+      const bool in = x >= 0 && x <= nx - 1;
+      const int64_t p = fpos(g, in ? x : 0, y, z);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) u[d][j] = in ? mac[(int64_t)(1 + d) * NP + p] : S(0);
+    }
+    return;
+  }
+  const Pull<S, Q, V, 1, 3> pl(g.pf, g.fxo, x0, y, z, nx, ny, nz);
+  pl.template load_all<L>(src, P);
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    S f[Q], rho, r0, uu[3];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = P[i][j];
+    N::moments(f, rho, r0, uu);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) u[d][j] = uu[d];
+  }
+  if (k == nv - 1) {
+    const int jr = nx - 1 - x0;
+    const int64_t p = fpos(g, nx - 1, y, z);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const S r = mac[(int64_t)(1 + d) * NP + p];
+#pragma unroll
+      for (int j = 0; j < V; ++j)
+        if (j == jr) u[d][j] = r;
+    }
+  }
+}
+
+template <int LAT, bool DEV, typename S, bool NT, int TXV, int TY, int MINW>
+__global__ __launch_bounds__(256, MINW) void k_hrr3(const S* __restrict__ src, S* __restrict__ dst,
+                                                    const S* __restrict__ mac, const Geo g, const S om, const S tau,
+                                                    const S sig, int ntx, int nty, int nzc, int zlen, int per_xcd) {
+  using L = Lattice<LAT>;
+  using N = Node<LAT, DEV, S>;
+  constexpr int V = VecOf<S>::V, Q = L::Q;
+  using VA = typename VT<S, V>::a;
+  constexpr int HX = TXV + 2, HY = TY + 2, RW = HX * V;
+  static_assert(L::D == 3, "the marching one-pass H-RR kernel is three-dimensional");
+  static_assert(HX * HY <= 256, "one lane per tile-and-halo vector");
+  __shared__ S lu[3][3][HY][RW];  // [plane slot][component][row][node]
+  const int b = blockIdx.x;
+  const int item = (b % kXCD) * per_xcd + b / kXCD;
+  const int ntile = ntx * nty;
+  if (item >= ntile * nzc) return;  // whole work group, before any barrier
+  const int zc = item / ntile, tile = item - zc * ntile;
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int ny = g.nf[1], nz = g.nf[2];
+  const int nv = (g.nf[0] - 1 + V - 1) / V;
+  const int t = threadIdx.x;
+  const int hv = t % HX, hr = t / HX;
+  const int k = tx * TXV - 1 + hv, y = ty * TY + hr;
+  const bool lane = t < HX * HY;
+  const bool live = lane && y <= ny - 1 && k <= nv - 1;
+  const bool inner = live && hv >= 1 && hv <= TXV && hr >= 1 && hr <= TY && y <= ny - 2;
+  const int zs = 1 + zc * zlen, ze = min(zs + zlen - 1, nz - 2);
+  const VA zero = VA(S(0));
+  VA T[Q], P[Q], u[3];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) T[i] = P[i] = zero;
+  auto put = [&](int zp) {
+    const int sl = zp % 3;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) *(VA*)&lu[sl][d][hr][hv * V] = u[d];
+  };
+  // planes zs - 1 (velocities) and zs (velocities and populations)
+  if (live) {
+    hrr3_pull<LAT, DEV, S>(src, mac, g, k, y, zs - 1, nv, P, u);
+    put(zs - 1);
+    hrr3_pull<LAT, DEV, S>(src, mac, g, k, y, zs, nv, T, u);
+    put(zs);
+  }
+  for (int z = zs; z <= ze; ++z) {
+    if (live) {
+      hrr3_pull<LAT, DEV, S>(src, mac, g, k, y, z + 1, nv, P, u);
+      put(z + 1);
+    }
+    __syncthreads();
+    if (inner) {
+      const int sm = (z + 2) % 3, s0 = z % 3, sp = (z + 1) % 3;
+      const int c = hv * V;
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        S gr[3][3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          gr[0][d] = (lu[s0][d][hr][c + j + 1] - lu[s0][d][hr][c + j - 1]) * S(0.5);
+          gr[1][d] = (lu[s0][d][hr + 1][c + j] - lu[s0][d][hr - 1][c + j]) * S(0.5);
+          gr[2][d] = (lu[sp][d][hr][c + j] - lu[sm][d][hr][c + j]) * S(0.5);
+        }
+        Sym<S> Sr;
+        Sr.xx = gr[0][0];
+        Sr.yy = gr[1][1];
+        Sr.xy = S(0.5) * (gr[0][1] + gr[1][0]);
+        Sr.zz = gr[2][2];
+        Sr.xz = S(0.5) * (gr[0][2] + gr[2][0]);
+        Sr.yz = S(0.5) * (gr[1][2] + gr[2][1]);
+        S f[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = T[i][j];
+        N::collide(f, M_HRR, om, tau, sig, &Sr);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) T[i][j] = f[i];
+      }
+      const int64_t own = fpos(g, 1 + V * k, y, z);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + pop_at<S, Q>(own, i)), T[i]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < Q; ++i) T[i] = P[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
 // State transfer kernels (logical x-fastest arrays <-> device storage).
 
 template <int LAT, bool DEV, typename S>

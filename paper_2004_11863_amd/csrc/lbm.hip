@@ -213,6 +213,7 @@ struct Grid final : GridBase {
   bool fused = false;
   int n_cu = 0;
   int f3_slots[kNVar] = {0, 0, 0, 0};  // resident k_fine3 work groups per device, per variant
+  int h3_slots[kNVar] = {0, 0, 0, 0};  // the same for k_hrr3
   int hs[3] = {0, 1, 2};
   Iface itf{};
   double tau_c = 0, tau_f = 0, sig = 0;
@@ -229,6 +230,7 @@ struct Grid final : GridBase {
     fused = desc.collision != LBM_HRR && g.has_fine;
     HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device));
     if (fused) var[1] = 0;
+    if (D == 3 && desc.collision == LBM_HRR) var[3] = 0;
     timed_factor = fused_now() ? 2 : 1;
     for (int p = 0; p < 2; ++p) cbuf[p].alloc(pop_bytes(g.Ncp));
     if (g.has_fine)
@@ -414,34 +416,69 @@ struct Grid final : GridBase {
                          (S)(1.0 - 1.0 / tau_f), ntx, nty, nzc, zlen, per);
     }
   }
-  template <typename K>
-  void fine3_launch(K kern, int TXV, int TY, const S* src, S* dst, S* half, hipStream_t s, int v) {
-    if (f3_slots[v] == 0) {
-      int nb = 0;
-      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0));
-      f3_slots[v] = std::max(1, nb) * std::max(1, n_cu);
-    }
+  // Work decomposition of a marching fine kernel (k_fine3, k_hrr3) with
+  // TXV x TY tiles, for `slots` resident work groups on the device.
+  struct ZRuns {
+    int ntx, nty, nzc, zlen, per;
+  };
+  ZRuns zruns(int TXV, int TY, int slots) const {
+    ZRuns r;
     const int nv = (g.nf[0] - 1 + V - 1) / V;
-    const int ntx = (nv + TXV - 1) / TXV, nty = (g.nf[1] - 2 + TY - 1) / TY, nzm = g.nf[2] - 2;
-    const int64_t ntile = (int64_t)ntx * nty;
-    int zlen = nzm;
+    r.ntx = (nv + TXV - 1) / TXV;
+    r.nty = (g.nf[1] - 2 + TY - 1) / TY;
+    const int nzm = g.nf[2] - 2;
+    const int64_t ntile = (int64_t)r.ntx * r.nty;
+    r.zlen = nzm;
     double best = -1.0;
     constexpr int kMinZRun = 8;
     for (int nzc = 1; nzc <= nzm; ++nzc) {
       const int zl = (nzm + nzc - 1) / nzc;
       if (zl < kMinZRun && nzc > 1) break;
       if ((nzm + zl - 1) / zl != nzc) continue;
-      const int64_t rounds = (ntile * nzc + f3_slots[v] - 1) / f3_slots[v];
+      const int64_t rounds = (ntile * nzc + slots - 1) / slots;
       const double cost = (double)rounds * (zl + 2);
       if (best < 0.0 || cost < best) {
         best = cost;
-        zlen = zl;
+        r.zlen = zl;
       }
     }
-    const int nzc = (nzm + zlen - 1) / zlen;
-    const int per = (int)((ntile * nzc + kXCD - 1) / kXCD);
-    hipLaunchKernelGGL(kern, dim3((unsigned)(per * kXCD)), dim3(256), 0, s, src, dst, half, g,
-                       (S)(1.0 - 1.0 / tau_f), ntx, nty, nzc, zlen, per);
+    r.nzc = (nzm + r.zlen - 1) / r.zlen;
+    r.per = (int)((ntile * r.nzc + kXCD - 1) / kXCD);
+    return r;
+  }
+  template <typename K>
+  int occupancy_slots(K kern, int& cache) {
+    if (cache == 0) {
+      int nb = 0;
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0));
+      cache = std::max(1, nb) * std::max(1, n_cu);
+    }
+    return cache;
+  }
+  template <typename K>
+  void fine3_launch(K kern, int TXV, int TY, const S* src, S* dst, S* half, hipStream_t s, int v) {
+    const ZRuns r = zruns(TXV, TY, occupancy_slots(kern, f3_slots[v]));
+    hipLaunchKernelGGL(kern, dim3((unsigned)(r.per * kXCD)), dim3(256), 0, s, src, dst, half, g,
+                       (S)(1.0 - 1.0 / tau_f), r.ntx, r.nty, r.nzc, r.zlen, r.per);
+  }
+  // One H-RR fine substep in one pass (D3Q19, k_hrr3), fine H-RR role
+  // variants 2 (30 x 6 tiles) and 3 (62 x 2); variants 0 and 1 run the
+  // velocity pass and k_collide_hrr (capped at 2 / 3 resident work groups).
+  bool hrr_one_pass3() const { return D == 3 && desc.collision == LBM_HRR && var[3] >= 2; }
+  int hrr_lds_var(int v) const { return (D == 3 && desc.collision == LBM_HRR) ? (v == 0 ? 2 : 1) : v; }
+  template <int TXV, int TY>
+  void go_hrr3(const S* src, S* dst, const S* mac, hipStream_t s, int v) {
+    if constexpr (D == 3) {
+      auto kern = k_hrr3<LAT, DEV, S, NT, TXV, TY, 2>;
+      const ZRuns r = zruns(TXV, TY, occupancy_slots(kern, h3_slots[v]));
+      hipLaunchKernelGGL(kern, dim3((unsigned)(r.per * kXCD)), dim3(256), 0, s, src, dst, mac, g,
+                         (S)(1.0 - 1.0 / tau_f), (S)tau_f, (S)sig, r.ntx, r.nty, r.nzc, r.zlen, r.per);
+    }
+  }
+  void launch_hrr3(const S* src, S* dst, const S* mac, hipStream_t s, int v = -1) {
+    if (v < 0) v = var[3];
+    if (v == 2) go_hrr3<30, 6>(src, dst, mac, s, 2);
+    else go_hrr3<62, 2>(src, dst, mac, s, 3);
   }
   template <int MODEL>
   void launch_fused(const S* src, S* dst, S* half, hipStream_t s, int v = -1) {
@@ -520,8 +557,12 @@ struct Grid final : GridBase {
       launch_collide_hrr<0>(c_cur, c_oth, mac_c.as<S>(), tau_c, s, v);
     } else if (D == 2) {
       launch_hrr2(fineA(), fineB(), mac_f.as<S>(), s, v);
+    } else if (v >= 2) {
+      launch_hrr3(fineA(), fineB(), mac_f.as<S>(), s, v);
     } else {
-      launch_collide_hrr<1>(fineA(), fineB(), mac_f.as<S>(), tau_f, s, v);
+      // the two passes the one-pass variants replace
+      launch_stream<M_HRR, 1>(fineA(), fineB(), mac_f.as<S>(), tau_f, s);
+      launch_collide_hrr<1>(fineA(), fineB(), mac_f.as<S>(), tau_f, s, hrr_lds_var(v));
     }
   }
 
@@ -630,10 +671,13 @@ struct Grid final : GridBase {
         // one pass per fine substep (k_hrr2): ring rho, u first
         hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, c0, c1, c2, mf, g, itf);
         timed(s, [&] { launch_hrr2(fA, fB, mf, s); });
+      } else if (hrr_one_pass3()) {
+        hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, c0, c1, c2, mf, g, itf);
+        timed(s, [&] { launch_hrr3(fA, fB, mf, s); });
       } else {
         launch_stream<M_HRR, 1>(fA, fB, mf, tau_f, s);
         hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, c0, c1, c2, mf, g, itf);
-        timed(s, [&] { launch_collide_hrr<1>(fA, fB, mf, tau_f, s); });
+        timed(s, [&] { launch_collide_hrr<1>(fA, fB, mf, tau_f, s, hrr_lds_var(var[3])); });
       }
       hipLaunchKernelGGL((k_fict<LAT, DEV, S, S>), dim3(bt), dim3(IB), 0, s, fB, mc, g, itf);
       // the coarse velocities at the history nodes' neighbours: from the
@@ -646,10 +690,13 @@ struct Grid final : GridBase {
       if constexpr (D == 2) {
         hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, 0.0, 0.0, 1.0, mf, g, itf);
         timed(s, [&] { launch_hrr2(fB, fA, mf, s); });
+      } else if (hrr_one_pass3()) {
+        hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, 0.0, 0.0, 1.0, mf, g, itf);
+        timed(s, [&] { launch_hrr3(fB, fA, mf, s); });
       } else {
         launch_stream<M_HRR, 1>(fB, fA, mf, tau_f, s);
         hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, 0.0, 0.0, 1.0, mf, g, itf);
-        timed(s, [&] { launch_collide_hrr<1>(fB, fA, mf, tau_f, s); });
+        timed(s, [&] { launch_collide_hrr<1>(fB, fA, mf, tau_f, s, hrr_lds_var(var[3])); });
       }
       hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR, true>), dim3(br), dim3(IB), 0, s, Hp, fA, g, itf, kf, omf, tau_f, sig);
       // coarse collision before the TN transfer: the vector kernel also

@@ -307,3 +307,32 @@ def test_variants_on_ragged_3d_and_2d(D):
             ref = out
         else:
             assert np.array_equal(out, ref)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_d3q19_hrr_one_pass_variants(prec):
+    """D3Q19 H-RR fine substeps run as velocity pass + collision (fine H-RR
+    role variants 0, 1) or in one marching pass with the velocities of three
+    planes in LDS (variants 2, 3): bitwise the same, several tiles, z-runs and
+    ragged row ends; the two-pass run against the oracle (FP64)."""
+    lbm = _lbm()
+    p = lbm.LBM_FP32_DEV if prec == "fp32" else lbm.LBM_FP64
+    geom = _geom(3, (40, 36, 34), (5, 4, 6), (35, 20, 28))
+    wl = I.Workload(geom=geom, U=(0.04, 0.01, -0.01), pulses=[I.Pulse(center=(20.0, 12.0, 17.0), A=1e-3, R=3.0)])
+    ref = None
+    for v in range(lbm.LBM_N_VARIANTS):
+        check = v == 0 and prec == "fp64"
+        gpu, orc, levels = make_pair(wl, "HRR", p, with_oracle=check)
+        gpu.set_variants([0, 0, 0, v])
+        gpu.step(5)
+        if check:
+            orc.step(5)
+            w = compare_fp64(gpu, orc, levels)
+            assert max(w.values()) <= TOL64, w
+        live = gpu.class_map(0) != lbm.LBM_C_COVERED
+        out = (gpu.get_populations(0)[:, live], gpu.get_populations(1))
+        gpu.close()
+        if ref is None:
+            ref = out
+        else:
+            assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), v
