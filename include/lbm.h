@@ -92,8 +92,9 @@ typedef struct {
 
 /* Creates a grid: validates the descriptor, builds the node-class maps and
  * interface stencil tables, allocates all device state (two population
- * buffers per level, a third fine one for BGK / RR, the three-time-level
- * coarse history, stencil tables) and a non-blocking stream.  The state is
+ * buffers per level, a third fine one for BGK / RR, for D3Q19 BGK / RR a
+ * compact copy of the fine x-normal bands, the three-time-level coarse
+ * history, stencil tables) and a non-blocking stream.  The state is
  * zero until lbm_set_state.  LBM_EINVAL for a bad descriptor, including a
  * level of 2^31 or more padded node positions (rows padded to a multiple of
  * 4 nodes). */

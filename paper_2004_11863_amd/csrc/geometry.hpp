@@ -103,6 +103,17 @@ __host__ __device__ inline int fine_class(const Geo& g, int x, int y, int z) {
   return (even && in_tn && on_tn) ? FC_TN : FC_MIDDLE;
 }
 
+// Compact copy of the fine state in the two x-normal bands of the patch,
+// x in [0, 4] (side 0) and [nx - 5, nx - 1] (side 1), five nodes per row:
+// [side][population][z][y][x offset].  In the row-major layout every
+// population of those nodes fills its own cache line; here consecutive rows
+// are 5 values apart.  (The bands overlap when nx < 10: a node may sit on
+// both sides.)
+__host__ __device__ inline int64_t xband_at(const Geo& g, int Q, int side, int q, int y, int z, int xo) {
+  return ((((int64_t)side * Q + q) * g.nf[2] + z) * g.nf[1] + y) * 5 + xo;
+}
+__host__ __device__ inline int64_t xband_elems(const Geo& g, int Q) { return (int64_t)2 * Q * g.nf[2] * g.nf[1] * 5; }
+
 // Periodic wrap of a coarse coordinate displaced by at most one period.
 __host__ __device__ inline int wrap(int x, int n) { return x < 0 ? x + n : (x >= n ? x - n : x); }
 

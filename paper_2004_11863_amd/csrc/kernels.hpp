@@ -251,9 +251,12 @@ __device__ __forceinline__ bool skip_vec(const Geo& g, int x0, int V, int y, int
 // Every node of a processed vector is written, including coarse TN/covered
 // nodes and the fine ring column x = nx - 1: the schedule overwrites TN and
 // ring nodes afterwards and never reads covered ones.
+// With xb set (fine level, the first substep of the two-launch D3Q19 path)
+// the results of middle nodes in the x-bands also go to the compact band copy
+// (xband_at), which the fine-to-coarse transfer reads.
 template <int LAT, bool DEV, typename S, int MODEL, int LEVEL, bool NT>
 __device__ __forceinline__ void stream_body(const S* __restrict__ src, S* __restrict__ dst, S* __restrict__ mac, const Geo& g,
-                                   const Flat& fl, const S om, int chunk) {
+                                   const Flat& fl, const S om, int chunk, S* __restrict__ xb = nullptr) {
   using L = Lattice<LAT>;
   using N = Node<LAT, DEV, S>;
   constexpr int V = VecOf<S>::V;
@@ -301,12 +304,35 @@ __device__ __forceinline__ void stream_body(const S* __restrict__ src, S* __rest
   }
 #pragma unroll
   for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + pop_at<S, Q>(own, i)), v[i]);
+  if (LEVEL == 1 && xb && (x0 <= 4 || x0 + V - 1 >= nx - 5)) {
+    // A vector wholly inside a band goes out as one 16-byte store per
+    // population (it may hold the ring column x = nx - 1: the ring
+    // reconstruction, which runs next, rewrites every population of it that
+    // is read); otherwise node by node, middle nodes only.
+    using VU = typename VT<S, V>::u;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int xo0 = side == 0 ? x0 : x0 - (nx - 5);
+      if (xo0 >= 0 && xo0 + V - 1 <= 4 && x0 + V - 1 <= nx - 1) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) *(VU*)(xb + xband_at(g, Q, side, i, y, z, xo0)) = (VU)v[i];
+      } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          const int xo = xo0 + k;
+          if (xo < 0 || xo > 4 || x0 + k > nx - 2) continue;
+#pragma unroll
+          for (int i = 0; i < Q; ++i) xb[xband_at(g, Q, side, i, y, z, xo)] = v[i][k];
+        }
+      }
+    }
+  }
 }
 
 template <int LAT, bool DEV, typename S, int MODEL, int LEVEL, bool NT>
 __global__ __launch_bounds__(256) void k_stream(const S* __restrict__ src, S* __restrict__ dst, S* __restrict__ mac,
-                                                const Geo g, const Flat fl, const S om) {
-  stream_body<LAT, DEV, S, MODEL, LEVEL, NT>(src, dst, mac, g, fl, om, xcd_chunk(fl));
+                                                const Geo g, const Flat fl, const S om, S* __restrict__ xb) {
+  stream_body<LAT, DEV, S, MODEL, LEVEL, NT>(src, dst, mac, g, fl, om, xcd_chunk(fl), xb);
 }
 
 // H-RR pull-stream and collision of a level: dst = collide(pull(src)) with
@@ -675,9 +701,12 @@ __global__ void k_ring_macro(const double* __restrict__ Hm, const double* __rest
 // cache line, so skipping the others saves most of this kernel's traffic.
 // The full state is rebuilt from the same history level before it can be
 // observed (ring completion), with bitwise the same values.
+// With xb set (the t+1/2 ring of the two-launch D3Q19 path) ring nodes in
+// the x-bands also store the same populations into the compact band copy.
 template <int LAT, bool DEV, typename S, int MODEL, bool PARTIAL>
 __device__ __forceinline__ void ring_body(const double* __restrict__ G, S* __restrict__ dst, const Geo& g, const Iface& itf,
-                                 double kf, double om_f, double tau_f, double sig, int64_t r) {
+                                 double kf, double om_f, double tau_f, double sig, int64_t r,
+                                 S* __restrict__ xb = nullptr) {
   using L = Lattice<LAT>;
   using F = HF<LAT, MODEL>;
   using N = Node<LAT, false, double>;
@@ -719,7 +748,12 @@ __device__ __forceinline__ void ring_body(const double* __restrict__ G, S* __res
       if (D == 3) in = in && zs >= 1 && zs <= g.nf[2] - 2;
       if (!in) continue;
     }
-    dst[pop_at<S, Q>(fi, i)] = store_pop<S, DEV, LAT>(f[i], i);
+    const S sv = store_pop<S, DEV, LAT>(f[i], i);
+    dst[pop_at<S, Q>(fi, i)] = sv;
+    if (xb) {
+      if (x <= 4) xb[xband_at(g, Q, 0, i, y, z, x)] = sv;
+      if (x >= g.nf[0] - 5) xb[xband_at(g, Q, 1, i, y, z, x - (g.nf[0] - 5))] = sv;
+    }
   }
 }
 template <int LAT, bool DEV, typename S, int MODEL, bool PARTIAL>
@@ -732,11 +766,19 @@ __global__ void k_ring(const double* __restrict__ G, S* __restrict__ dst, const 
 
 // Pull of Q populations into fine node (x, y, z) from a fine buffer.
 template <int LAT, bool DEV, typename S>
-__device__ __forceinline__ void pull_fine(const S* __restrict__ src, const Geo& g, int x, int y, int z, double* f) {
+__device__ __forceinline__ void pull_fine(const S* __restrict__ src, const Geo& g, int x, int y, int z, double* f,
+                                          const S* __restrict__ xb = nullptr) {
   using L = Lattice<LAT>;
+  constexpr int Q = L::Q;
+  // nodes whose pulls stay inside an x-band read the compact band copy
+  const int side = !xb ? -1 : (x <= 3 ? 0 : (x >= g.nf[0] - 4 ? 1 : -1));
+  const int xb0 = side == 1 ? g.nf[0] - 5 : 0;
 #pragma unroll
-  for (int i = 0; i < L::Q; ++i)
-    f[i] = full_pop<S, DEV, LAT>(src[pop_at<S, L::Q>(fpos(g, x - L::cx(i), y - L::cy(i), z - L::cz(i)), i)], i);
+  for (int i = 0; i < Q; ++i) {
+    const int xs = x - L::cx(i), ys = y - L::cy(i), zs = z - L::cz(i);
+    const S v = side >= 0 ? xb[xband_at(g, Q, side, i, ys, zs, xs - xb0)] : src[pop_at<S, Q>(fpos(g, xs, ys, zs), i)];
+    f[i] = full_pop<S, DEV, LAT>(v, i);
+  }
 }
 
 // H-RR: fictitious propagation onto TN^f (Sec. 4.3, step e): u(TN, t+1) from
@@ -779,7 +821,8 @@ __global__ void k_fict(const S* __restrict__ src_f, T* __restrict__ mac_c, const
 // rebuilds and collides.
 template <int LAT, bool DEV, typename S, int MODEL>
 __device__ __forceinline__ void coalesce_body(const S* __restrict__ src_f, S* __restrict__ dst_c, const Geo& g, const Iface& itf,
-                                     double kc, double om_c, double tau_c, double sig, int64_t blk) {
+                                     double kc, double om_c, double tau_c, double sig, int64_t blk,
+                                     const S* __restrict__ xb = nullptr) {
   using L = Lattice<LAT>;
   using N = Node<LAT, false, double>;
   using F = HF<LAT, MODEL>;
@@ -799,7 +842,7 @@ __device__ __forceinline__ void coalesce_body(const S* __restrict__ src_f, S* __
     fdecode(g, itf.tnf[t], x, y, z);
     const int ox = s % 3 - 1, oy = (s / 3) % 3 - 1, oz = (D == 3) ? s / 9 - 1 : 0;
     double f[Q], rho, r0, u[3];
-    pull_fine<LAT, DEV, S>(src_f, g, x + ox, y + oy, z + oz, f);
+    pull_fine<LAT, DEV, S>(src_f, g, x + ox, y + oy, z + oz, f, xb);
     N::moments(f, rho, r0, u);
     const double w = (ox ? 0.25 : 0.5) * (oy ? 0.25 : 0.5) * (D == 3 ? (oz ? 0.25 : 0.5) : 1.0);
     if (MODEL == M_BGK) {
@@ -878,12 +921,12 @@ template <int LAT, bool DEV, typename S, int MODEL, bool NT>
 __global__ __launch_bounds__(256) void k_stream_ring(const S* __restrict__ src, S* __restrict__ dst, const Geo g,
                                                      const Flat fl, const S om, const double* __restrict__ G,
                                                      S* __restrict__ fdst, const Iface itf, double kf, double om_f,
-                                                     double tau_f, double sig, int nrb) {
+                                                     double tau_f, double sig, int nrb, S* __restrict__ xb) {
   const int b = blockIdx.x;
   if (b < nrb) {
     const int per = nrb / kXCD;
     const int64_t blk = (int64_t)(b % kXCD) * per + b / kXCD;
-    ring_body<LAT, DEV, S, MODEL, true>(G, fdst, g, itf, kf, om_f, tau_f, sig, blk * 256 + threadIdx.x);
+    ring_body<LAT, DEV, S, MODEL, true>(G, fdst, g, itf, kf, om_f, tau_f, sig, blk * 256 + threadIdx.x, xb);
   } else {
     const int b2 = b - nrb;
     stream_body<LAT, DEV, S, MODEL, 0, NT>(src, dst, nullptr, g, fl, om, (b2 % kXCD) * fl.per_xcd + b2 / kXCD);
@@ -901,7 +944,7 @@ __global__ __launch_bounds__(256) void k_ring_coalesce(const double* __restrict_
                                                        const S* __restrict__ src_f, S* __restrict__ dst_c,
                                                        const Geo g, const Iface itf, double kf, double om_f,
                                                        double tau_f, double kc, double om_c, double tau_c, double sig,
-                                                       int nrb) {
+                                                       int nrb, const S* __restrict__ xb) {
   const int b = blockIdx.x;
   if (b < nrb) {
     const int per = nrb / kXCD;
@@ -910,7 +953,7 @@ __global__ __launch_bounds__(256) void k_ring_coalesce(const double* __restrict_
   } else {
     const int b2 = b - nrb, per = ((int)gridDim.x - nrb) / kXCD;
     coalesce_body<LAT, DEV, S, MODEL>(src_f, dst_c, g, itf, kc, om_c, tau_c, sig,
-                                      (int64_t)(b2 % kXCD) * per + b2 / kXCD);
+                                      (int64_t)(b2 % kXCD) * per + b2 / kXCD, xb);
   }
 }
 

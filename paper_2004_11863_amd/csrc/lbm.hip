@@ -201,6 +201,7 @@ struct Grid final : GridBase {
   int var[4] = {kDefaultVar, kDefaultVar, kDefaultVar, kDefaultVar};
 
   DevBuf cbuf[2], fbuf[3], mac_c, mac_f, hist[3], G, tmp_rho, tmp_u, tmp_f, part, tot;
+  DevBuf xbuf;  // D3Q19 BGK / RR: compact copy of the fine x-bands at t+1/2 (xband_at)
   DevBuf d_hnode, d_rnode, d_rnp, d_rpt, d_tnf, d_tnc;
   int cpar = 0;  // coarse buffer holding the current state
   // Fine buffers: fbuf[fpar] holds the state at integer times.  A fused step
@@ -235,6 +236,10 @@ struct Grid final : GridBase {
     for (int p = 0; p < 2; ++p) cbuf[p].alloc(pop_bytes(g.Ncp));
     if (g.has_fine)
       for (int p = 0; p < (fused ? 3 : 2); ++p) fbuf[p].alloc(pop_bytes(g.Nfp));
+    if (g.has_fine && D == 3 && desc.collision != LBM_HRR) {
+      xbuf.alloc(sizeof(S) * (size_t)xband_elems(g, Q));
+      HIPCHK(hipMemset(xbuf.p, 0, xbuf.bytes));
+    }
     if (desc.collision == LBM_HRR) {
       mac_c.alloc(plane_bytes(g.Ncp, 1 + D));
       if (g.has_fine) mac_f.alloc(plane_bytes(g.Nfp, 1 + D));
@@ -292,23 +297,23 @@ struct Grid final : GridBase {
   S* fineB() { return fbuf[fpar ^ 1].as<S>(); }   // the other buffer
 
   template <int MODEL, int LEVEL>
-  void launch_stream(const S* src, S* dst, S* mac, double tau, hipStream_t s, int v = -1) {
+  void launch_stream(const S* src, S* dst, S* mac, double tau, hipStream_t s, int v = -1, S* xb = nullptr) {
     if (v < 0) v = var[LEVEL];
     const Flat f = flat(LEVEL);
     if (f.nchunks == 0) return;
     hipLaunchKernelGGL((k_stream<LAT, DEV, S, MODEL, LEVEL, NT>), dim3((unsigned)(f.per_xcd * kXCD)), dim3(256),
-                       (unsigned)kVarLds[v], s, src, dst, mac, g, f, (S)(1.0 - 1.0 / tau));
+                       (unsigned)kVarLds[v], s, src, dst, mac, g, f, (S)(1.0 - 1.0 / tau), xb);
   }
 
   // Coarse stream (BGK, RR) and the t+1/2 ring reconstruction from G into
   // fdst, one launch (k_stream_ring).
   template <int MODEL>
-  void launch_stream_ring(const S* src, S* dst, S* fdst, double kf, double omf, hipStream_t s) {
+  void launch_stream_ring(const S* src, S* dst, S* fdst, double kf, double omf, hipStream_t s, S* xb = nullptr) {
     const Flat f = flat(0);
     const unsigned nrb = xblocks(itf.NR, 256);
     hipLaunchKernelGGL((k_stream_ring<LAT, DEV, S, MODEL, NT>), dim3(nrb + (unsigned)(f.per_xcd * kXCD)), dim3(256),
                        (unsigned)kVarLds[var[0]], s, src, dst, g, f, (S)(1.0 - 1.0 / tau_c), G.as<double>(), fdst, itf,
-                       kf, omf, tau_f, sig, (int)nrb);
+                       kf, omf, tau_f, sig, (int)nrb, xb);
   }
 
   // One H-RR fine substep in one pass (D2Q9, k_hrr2): variants of the fine
@@ -516,11 +521,11 @@ struct Grid final : GridBase {
   // LDS variant of the fine k_stream launches for fine-role variant v.
   int fine_lds_var(int v) const { return (fused && D == 3) ? (v == 0 ? 2 : 1) : v; }
   // Fine-level pull-stream + collide (BGK, RR): the timed kernel.
-  void fine_stream_timed(int model, const S* src, S* dst, hipStream_t s) {
+  void fine_stream_timed(int model, const S* src, S* dst, hipStream_t s, S* xb = nullptr) {
     const int lv = fine_lds_var(var[1]);
     timed(s, [&] {
-      if (model == M_BGK) launch_stream<M_BGK, 1>(src, dst, nullptr, tau_f, s, lv);
-      else launch_stream<M_RR, 1>(src, dst, nullptr, tau_f, s, lv);
+      if (model == M_BGK) launch_stream<M_BGK, 1>(src, dst, nullptr, tau_f, s, lv, xb);
+      else launch_stream<M_RR, 1>(src, dst, nullptr, tau_f, s, lv, xb);
     });
   }
 
@@ -650,16 +655,18 @@ struct Grid final : GridBase {
       launch_stream_ring<MODEL>(csrc, cdst, fH, kf, omf, s);
       timed(s, [&] { launch_fused<MODEL>(fA, fB, fH, s); });
       hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, MODEL>), dim3(br2 + bc), dim3(256), 0, s, Hp, fB, fH, cdst, g, itf,
-                         kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2);
+                         kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, (const S*)nullptr);
       fpar ^= 1;
     } else if (MODEL != M_HRR) {
       // substep 1 writes the ring column x = nx - 1 of B, so the t+1/2 ring
-      // (sharing a launch with the coarse stream) follows it
-      fine_stream_timed(MODEL, fA, fB, s);
-      launch_stream_ring<MODEL>(csrc, cdst, fB, kf, omf, s);
+      // (sharing a launch with the coarse stream) follows it; both also fill
+      // the compact copy of the x-bands, from which the transfer reads
+      S* xb = xbuf.as<S>();
+      fine_stream_timed(MODEL, fA, fB, s, xb);
+      launch_stream_ring<MODEL>(csrc, cdst, fB, kf, omf, s, xb);
       fine_stream_timed(MODEL, fB, fA, s);
       hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, MODEL>), dim3(br2 + bc), dim3(256), 0, s, Hp, fA, fB, cdst, g, itf,
-                         kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2);
+                         kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, (const S*)xb);
     } else {
       S* mc = mac_c.as<S>();
       S* mf = mac_f.as<S>();
