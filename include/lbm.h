@@ -204,6 +204,15 @@ const char* lbm_last_error(lbm_handle h);
  * which rewrites device work lists (the launch is captured again only when a
  * list outgrows its buffer).  A grid in a batch computes exactly what the
  * same grid computes alone.
+ *
+ * Every call but lbm_batch_step returns when it is done, and first waits for
+ * the batch's own work only: the steps last enqueued (on the stream passed to
+ * lbm_batch_step) and its internal stream.  Work of other batches on other
+ * streams keeps running meanwhile, so a server can admit or read grids of one
+ * batch while another batch steps.  (Freeing device memory, in
+ * lbm_batch_remove or when lbm_batch_add grows the shared scratch, waits for
+ * the whole device, as hipFree does.)  Calls on one batch handle must not
+ * overlap (one host thread at a time per batch).
  * ------------------------------------------------------------------------ */
 typedef struct lbm_batch* lbm_batch_handle;
 
@@ -240,7 +249,8 @@ int lbm_batch_slot_steps(lbm_batch_handle b, int slot, int64_t* steps);
  * memory footprint.  Fine levels hold three population buffers for D2Q9
  * BGK / RR (the third keeps the half-step ring and band of the fused fine
  * kernel), two otherwise; a single D3Q19 BGK / RR grid (lbm_create_grid)
- * also holds a third. */
+ * also holds a third.  D3Q19 BGK / RR fine levels add the compact copy of
+ * the fine x-bands (2 * 19 * 5 values per fine (y, z) row). */
 int lbm_footprint(const lbm_grid_desc* d, int64_t* bytes);
 const char* lbm_batch_last_error(lbm_batch_handle b);
 

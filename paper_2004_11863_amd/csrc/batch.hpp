@@ -28,6 +28,7 @@ struct InstDev {
   void* cbuf[2];
   void* fbuf[2];  // fbuf[fpar] holds the fine state at integer times
   void* fh;       // fused: the t+1/2 ring and band (fine-to-coarse source)
+  void* xb;       // D3Q19 BGK / RR: compact copy of the fine x-bands at t+1/2 (xband_at)
   void* mac_c;
   void* mac_f;
   double* hist[3];
@@ -126,7 +127,10 @@ __global__ __launch_bounds__(256) void kb_stream(const InstDev* __restrict__ ins
     } else {
       const S* src = glob((const S*)I.fbuf[I.fpar ^ SUB]);
       S* dst = glob((S*)I.fbuf[I.fpar ^ SUB ^ 1]);
-      stream_body<LAT, DEV, S, MODEL, 1, NT>(src, dst, glob((S*)I.mac_f), I.g, I.ff, (S)(1.0 - 1.0 / I.tau_f), w.idx);
+      // the first substep also fills the x-band copy (as the single grid)
+      S* xb = (SUB == 0 && I.xb) ? glob((S*)I.xb) : nullptr;
+      stream_body<LAT, DEV, S, MODEL, 1, NT>(src, dst, glob((S*)I.mac_f), I.g, I.ff, (S)(1.0 - 1.0 / I.tau_f), w.idx,
+                                             xb);
     }
   }
 }
@@ -203,8 +207,9 @@ template <int LAT, bool DEV, typename S, int MODEL, int SUB>
 __device__ __forceinline__ void kb_ring_item(const InstDev& I, int idx, int lane) {
   const double* G = glob(SUB == 0 ? I.G : I.hist[I.hs[2]]);
   S* dst = glob((S*)(SUB == 0 ? (I.fused ? I.fh : I.fbuf[I.fpar ^ 1]) : I.fbuf[I.fpar ^ I.fused]));
+  S* xb = (SUB == 0 && I.xb) ? glob((S*)I.xb) : nullptr;  // the t+1/2 ring fills the x-band copy
   ring_body<LAT, DEV, S, MODEL, true>(G, dst, I.g, glob(I.itf), I.tau_f / (2.0 * I.tau_c), 1.0 - 1.0 / I.tau_f, I.tau_f, I.sig,
-                                      (int64_t)idx * 64 + lane);
+                                      (int64_t)idx * 64 + lane, xb);
 }
 template <int LAT, bool DEV, typename S, int MODEL, int SUB>
 __global__ __launch_bounds__(64) void kb_ring(const InstDev* __restrict__ inst, const Work* __restrict__ items,
@@ -284,9 +289,10 @@ __global__ __launch_bounds__(64) void kb_fict(const InstDev* __restrict__ inst, 
 // Fine-to-coarse transfer from the t+1/2 state (fh when fused, else B).
 template <int LAT, bool DEV, typename S, int MODEL>
 __device__ __forceinline__ void kb_coalesce_item(const InstDev& I, int idx) {
+  const S* xb = I.xb ? glob((const S*)I.xb) : nullptr;
   coalesce_body<LAT, DEV, S, MODEL>(glob((const S*)(I.fused ? I.fh : I.fbuf[I.fpar ^ 1])), glob((S*)I.cnext), I.g,
                                     glob(I.itf),
-                                    2.0 * I.tau_c / I.tau_f, 1.0 - 1.0 / I.tau_c, I.tau_c, I.sig, idx);
+                                    2.0 * I.tau_c / I.tau_f, 1.0 - 1.0 / I.tau_c, I.tau_c, I.sig, idx, xb);
 }
 template <int LAT, bool DEV, typename S, int MODEL>
 __global__ __launch_bounds__(256) void kb_coalesce(const InstDev* __restrict__ inst, const Work* __restrict__ items,

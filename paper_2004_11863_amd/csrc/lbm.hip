@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,15 @@
 namespace lbm {
 
 static thread_local std::string g_create_error;
+
+// A blocking HIP call (synchronous copy or memset, allocation, free, device
+// or stream wait) made by one thread while another thread captures a
+// hipGraph invalidates that capture.  Every entry point that makes such calls
+// holds this lock for its whole call, and a batch holds it while it captures
+// its step graph, so calls from several threads never overlap a capture.
+// lbm_batch_step (launches only, apart from a capture) and the host-only
+// queries do not take it.  Recursive: a call may re-enter it.
+static std::recursive_mutex g_api_mu;
 
 #define HIPCHK(expr)                                                                       \
   do {                                                                                     \
@@ -932,9 +942,19 @@ static Geo validate(const lbm_grid_desc& d) {
 struct BatchBase {
   int lattice = 0, collision = 0, precision = 0, device = 0, capacity = 0;
   hipStream_t stream = nullptr;
+  // Recorded on the caller's stream after each step: the batch's own host
+  // calls wait for it and for `stream`, never for the whole device, so work
+  // of other batches (other streams) keeps running meanwhile.
+  hipEvent_t stepped = nullptr;
+  bool stepped_rec = false;
   std::string err;
   virtual ~BatchBase() {
+    if (stepped) (void)hipEventDestroy(stepped);
     if (stream) (void)hipStreamDestroy(stream);
+  }
+  void quiesce() {
+    if (stepped_rec) HIPCHK(hipEventSynchronize(stepped));
+    HIPCHK(hipStreamSynchronize(stream));
   }
   virtual int add(const lbm_grid_desc& d) = 0;
   virtual void remove(int slot) = 0;
@@ -951,7 +971,8 @@ struct BatchBase {
 // Device bytes one grid of this descriptor needs in a batch slot
 // (populations, macro planes, history, interface tables), without any
 // scratch.  D2Q9 BGK / RR keep a third fine population buffer (the fused
-// fine phase's t+1/2 ring and band).
+// fine phase's t+1/2 ring and band), D3Q19 BGK / RR the compact copy of the
+// fine x-bands.
 static int64_t grid_footprint(const lbm_grid_desc& d, const Geo& g) {
   const int Q = d.lattice == LBM_D2Q9 ? 9 : 19;
   const int D = g.D;
@@ -960,6 +981,7 @@ static int64_t grid_footprint(const lbm_grid_desc& d, const Geo& g) {
   auto pops = [&](int64_t NP) { return sb * (f32 ? pop_elems<float>(NP, Q) : pop_elems<double>(NP, Q)); };
   const int nfine = (g.D == 2 && d.collision != LBM_HRR) ? 3 : 2;
   int64_t bytes = 2 * pops(g.Ncp) + (g.has_fine ? nfine * pops(g.Nfp) : 0);
+  if (g.has_fine && g.D == 3 && d.collision != LBM_HRR) bytes += sb * xband_elems(g, Q);
   if (d.collision == LBM_HRR) bytes += sb * (1 + D) * (g.Ncp + g.Nfp + 128);
   if (g.has_fine) {
     int64_t nh = 0, ring_out = 1, ring_in = 1, tn_out = 1, tn_in = 1;
@@ -995,7 +1017,7 @@ struct Batch final : BatchBase {
     lbm_grid_desc desc{};
     Geo g{};
     HostTables tabs;
-    DevBuf cbuf[2], fbuf[3], mac_c, mac_f, hist[3], G, d_hnode, d_rnode, d_rnp, d_rpt, d_tnf, d_tnc;
+    DevBuf cbuf[2], fbuf[3], xb, mac_c, mac_f, hist[3], G, d_hnode, d_rnode, d_rnp, d_rpt, d_tnf, d_tnc;
     Iface itf{};
   };
   // D2Q9 BGK / RR instances run both fine substeps in one phase (kb_fine2),
@@ -1106,7 +1128,7 @@ struct Batch final : BatchBase {
     in->desc = d;
     in->g = g;
     HIPCHK(hipSetDevice(device));
-    HIPCHK(hipDeviceSynchronize());
+    quiesce();
     build_tables(g, in->tabs);
     const size_t sb = sizeof(S);
     for (int p = 0; p < 2; ++p) {
@@ -1125,6 +1147,10 @@ struct Batch final : BatchBase {
       if (collision == LBM_HRR) {
         in->mac_f.alloc(sb * ((size_t)g.Nfp * (1 + D) + 64));
         HIPCHK(hipMemset(in->mac_f.p, 0, in->mac_f.bytes));
+      }
+      if (D == 3 && collision != LBM_HRR) {
+        in->xb.alloc(sb * (size_t)xband_elems(g, Q));
+        HIPCHK(hipMemset(in->xb.p, 0, in->xb.bytes));
       }
       const size_t NH = in->tabs.hnode.size();
       for (int k = 0; k < 3; ++k) in->hist[k].alloc(sizeof(double) * HN * NH);
@@ -1162,6 +1188,7 @@ struct Batch final : BatchBase {
     I.fbuf[0] = in->fbuf[0].p;
     I.fbuf[1] = in->fbuf[1].p;
     I.fh = in->fbuf[2].p;
+    I.xb = in->xb.p;
     I.fpar = 0;
     I.fused = (g.has_fine && fused()) ? 1 : 0;
     I.ntx = g.has_fine ? fine2_ntx<S>(g, kTileX[tile_var]) : 0;
@@ -1196,7 +1223,7 @@ struct Batch final : BatchBase {
   void remove(int sl) override {
     slot_ref(sl);
     HIPCHK(hipSetDevice(device));
-    HIPCHK(hipDeviceSynchronize());
+    quiesce();
     hinst[(size_t)sl] = InstDev{};
     upload_inst(sl);
     slots[(size_t)sl].reset();
@@ -1228,7 +1255,7 @@ struct Batch final : BatchBase {
     Inst& in = slot_ref(sl);
     if (level == 1 && !in.g.has_fine) throw LbmError(LBM_EINVAL, "no fine level");
     HIPCHK(hipSetDevice(device));
-    HIPCHK(hipDeviceSynchronize());
+    quiesce();
     fetch_inst(sl);
     InstDev& I = hinst[(size_t)sl];
     // a coarse reset replaces the history the ring completion reads
@@ -1266,7 +1293,7 @@ struct Batch final : BatchBase {
     Inst& in = slot_ref(sl);
     if (level == 1 && !in.g.has_fine) throw LbmError(LBM_EINVAL, "no fine level");
     HIPCHK(hipSetDevice(device));
-    HIPCHK(hipDeviceSynchronize());
+    quiesce();
     fetch_inst(sl);
     complete_ring(sl);
     const InstDev& I = hinst[(size_t)sl];
@@ -1285,7 +1312,7 @@ struct Batch final : BatchBase {
     Inst& in = slot_ref(sl);
     if (level == 1 && !in.g.has_fine) throw LbmError(LBM_EINVAL, "no fine level");
     HIPCHK(hipSetDevice(device));
-    HIPCHK(hipDeviceSynchronize());
+    quiesce();
     fetch_inst(sl);
     complete_ring(sl);
     const InstDev& I = hinst[(size_t)sl];
@@ -1403,6 +1430,7 @@ struct Batch final : BatchBase {
   }
 
   void capture() {
+    std::lock_guard<std::recursive_mutex> lk(g_api_mu);
     drop_graph();
     HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
     launch_step(stream);
@@ -1424,6 +1452,8 @@ struct Batch final : BatchBase {
       else launch_step(s);
     }
     HIPCHK(hipGetLastError());
+    HIPCHK(hipEventRecord(stepped, s));
+    stepped_rec = true;
     for (int k = 0; k < capacity; ++k)
       if (slots[(size_t)k]) {
         steps_done[(size_t)k] += n;
@@ -1440,7 +1470,7 @@ struct Batch final : BatchBase {
   // fine stream phases (writing only buffers the next step rewrites).
   void tune(int reps, int32_t* out) override {
     HIPCHK(hipSetDevice(device));
-    HIPCHK(hipDeviceSynchronize());
+    quiesce();
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1552,8 +1582,10 @@ struct lbm_grid {
   std::unique_ptr<GridBase> impl;
 };
 
+
 template <typename F>
 static int guard(lbm_handle h, F&& fn) {
+  std::lock_guard<std::recursive_mutex> lk(g_api_mu);
   try {
     fn();
     return LBM_OK;
@@ -1572,6 +1604,7 @@ static int guard(lbm_handle h, F&& fn) {
 extern "C" {
 
 int lbm_create_grid(const lbm_grid_desc* d, lbm_handle* out) {
+  std::lock_guard<std::recursive_mutex> lk(g_api_mu);
   if (!d || !out) {
     g_create_error = "null argument";
     return LBM_EINVAL;
@@ -1607,6 +1640,7 @@ int lbm_create_grid(const lbm_grid_desc* d, lbm_handle* out) {
 
 int lbm_destroy(lbm_handle h) {
   if (!h) return LBM_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g_api_mu);
   (void)hipSetDevice(h->impl->device);
   (void)hipStreamSynchronize(h->impl->stream);
   delete h;
@@ -1802,8 +1836,10 @@ struct lbm_batch {
   std::unique_ptr<BatchBase> impl;
 };
 
-template <typename F>
+template <bool LOCK = true, typename F>
 static int bguard(lbm_batch_handle b, F&& fn) {
+  std::unique_lock<std::recursive_mutex> lk(g_api_mu, std::defer_lock);
+  if (LOCK) lk.lock();
   try {
     fn();
     return LBM_OK;
@@ -1823,6 +1859,7 @@ extern "C" {
 
 int lbm_batch_create(int lattice, int collision, int precision, int device, int capacity, lbm_batch_handle* out) {
   if (!out) return LBM_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g_api_mu);
   *out = nullptr;
   if ((lattice != LBM_D2Q9 && lattice != LBM_D3Q19) || collision < LBM_BGK || collision > LBM_HRR ||
       (precision != LBM_FP64 && precision != LBM_FP32_DEV) || capacity < 1 || capacity > (1 << 20)) {
@@ -1840,6 +1877,7 @@ int lbm_batch_create(int lattice, int collision, int precision, int device, int 
     b->device = device;
     HIPCHK(hipSetDevice(device));
     HIPCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&b->stepped, hipEventDisableTiming));
     if (lattice == LBM_D2Q9 && precision == LBM_FP64) static_cast<Batch<0, LBM_FP64>*>(b.get())->init(capacity);
     if (lattice == LBM_D2Q9 && precision == LBM_FP32_DEV) static_cast<Batch<0, LBM_FP32_DEV>*>(b.get())->init(capacity);
     if (lattice == LBM_D3Q19 && precision == LBM_FP64) static_cast<Batch<1, LBM_FP64>*>(b.get())->init(capacity);
@@ -1860,6 +1898,7 @@ int lbm_batch_create(int lattice, int collision, int precision, int device, int 
 
 int lbm_batch_destroy(lbm_batch_handle b) {
   if (!b) return LBM_EINVAL;
+  std::lock_guard<std::recursive_mutex> lk(g_api_mu);
   (void)hipSetDevice(b->impl->device);
   (void)hipDeviceSynchronize();
   delete b;
@@ -1893,7 +1932,7 @@ int lbm_batch_get_populations(lbm_batch_handle b, int slot, int level, double* f
 
 int lbm_batch_step(lbm_batch_handle b, int n, void* stream) {
   if (!b || n < 0) return LBM_EINVAL;
-  return bguard(b, [&] { b->impl->step(n, stream ? (hipStream_t)stream : b->impl->stream); });
+  return bguard<false>(b, [&] { b->impl->step(n, stream ? (hipStream_t)stream : b->impl->stream); });
 }
 
 int lbm_batch_use_graph(lbm_batch_handle b, int on) {
@@ -1908,12 +1947,12 @@ int lbm_batch_tune(lbm_batch_handle b, int reps, int32_t variants[2]) {
 
 int lbm_batch_info(lbm_batch_handle b, int64_t info[3]) {
   if (!b || !info) return LBM_EINVAL;
-  return bguard(b, [&] { b->impl->info(info); });
+  return bguard<false>(b, [&] { b->impl->info(info); });
 }
 
 int lbm_batch_slot_steps(lbm_batch_handle b, int slot, int64_t* steps) {
   if (!b || !steps) return LBM_EINVAL;
-  return bguard(b, [&] { *steps = b->impl->slot_steps(slot); });
+  return bguard<false>(b, [&] { *steps = b->impl->slot_steps(slot); });
 }
 
 int lbm_footprint(const lbm_grid_desc* d, int64_t* bytes) {

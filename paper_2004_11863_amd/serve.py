@@ -27,7 +27,10 @@ host code and is tested on the CPU with a fake executor.
 from __future__ import annotations
 
 import math
+import threading
 import time
+from concurrent.futures import FIRST_COMPLETED, ThreadPoolExecutor
+from concurrent.futures import wait as futures_wait
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -131,6 +134,11 @@ class Server:
       step({group: n})                      (advances each listed group n steps, then waits)
       read(handle) -> dict                   (macroscopic fields)
       release(handle)
+    overlap_host (attribute, default False): admit, read and release may run
+    on another thread for a group while other groups step; then
+      open(group)                           (optional, on the main thread before
+                                             a group's first admission there)
+      settle(group)                         (optional, after each job on the worker)
     """
 
     def __init__(self, executor, hbm_budget: int, clock=time.perf_counter, max_chunk: int = 32,
@@ -174,65 +182,155 @@ class Server:
     def run(self, requests, realtime: bool = True):
         """Runs the trace; returns the requests with admission and finish
         times (seconds from the start).  With realtime=False arrival times are
-        ignored (every request is waiting from the start)."""
+        ignored (every request is waiting from the start).
+
+        With an executor that allows host work on one group while others step
+        (overlap_host = True), the slow host work runs on a worker thread
+        beside the rounds: admitting requests into groups with no member
+        stepping (allocation, upload of the initial state) and reading back
+        and releasing groups whose members all finished.  A group with such a
+        job in progress is held: not stepped and not touched until it ends.
+        A request that joins a group with members stepping is admitted on the
+        main thread between rounds, once the worker is idle (a blocking call
+        there would wait for the worker's); the read of a finished member
+        whose group steps on is made there too, or, while the worker is busy,
+        queued to it with the group held.  After each job the executor may
+        settle the group (autotune it) on the worker."""
         pending = sorted(requests, key=lambda r: r.arrival)
         waiting = []                # arrived, not admitted (arrival order)
-        active = {}                 # handle -> _Active
+        active = {}                 # handle -> _Active, still stepping
         used = 0
         t0 = self.clock()
         now = lambda: self.clock() - t0
         i = 0
         done = []
-        while i < len(pending) or waiting or active:
-            t = now()
-            while i < len(pending) and (not realtime or pending[i].arrival <= t):
-                waiting.append(pending[i])
-                i += 1
-            for r in list(waiting):
-                fp = self.ex.footprint(r, r.fp64)
-                if fp > self.budget:
-                    raise ValueError(f"request {r.rid} needs {fp} bytes, more than the whole budget")
-                g = r.group()
-                if used + fp > self.budget or self.ex.free_slots(g) <= 0:
-                    continue
-                waiting.remove(r)
-                h = self.ex.admit(r, r.fp64, g)
-                r.admitted = now()
-                active[h] = _Active(r, r.steps, r.fp64, fp, g)
-                used += fp
-            if not active:
-                if i < len(pending) and realtime:
-                    wait = pending[i].arrival - now()
-                    if wait > 0:
-                        time.sleep(min(wait, 0.05))
-                continue
-            groups = {}
-            for a in active.values():
-                groups.setdefault(a.group, []).append(a)
-            plan = self.plan(groups)
-            self.ex.step(plan)
-            finished = []
-            for h, a in active.items():
-                if a.group in plan:
-                    a.left -= plan[a.group]
-                    if a.left <= 0:
-                        finished.append(h)
-            for h in finished:
-                a = active.pop(h)
+        overlap = getattr(self.ex, "overlap_host", False)
+        pool = ThreadPoolExecutor(max_workers=1) if overlap else None
+        jobs = {}                   # future -> (kind, group, payload)
+        held = set()                # groups with a job in progress
+
+        def deliver(items, res):
+            for h, a in items:
                 r = a.req
-                res = self.ex.read(h)
-                self.ex.release(h)
-                used -= a.bytes
-                ok = all(np.isfinite(v).all() for v in res.values())
+                ok = all(np.isfinite(v).all() for v in res[h].values())
                 if not ok and not a.fp64:
                     # FP64 fallback: the request is run again from its start
                     r.fell_back = True
                     r.fp64 = True
                     waiting.insert(0, r)
                     continue
-                r.result = res
+                r.result = res[h]
                 r.finished = now()
                 done.append(r)
+
+        def read_release(items):
+            res = {h: self.ex.read(h) for h, _ in items}
+            for h, _ in items:
+                self.ex.release(h)
+            return res
+
+        settle = getattr(self.ex, "settle", lambda g: None)
+
+        def admit_job(g, items):
+            hs = [self.ex.admit(r, r.fp64, g) for r, _ in items]
+            settle(g)
+            return hs
+
+        def read_job(g, items):
+            res = read_release(items)
+            settle(g)
+            return res
+
+        def collect(timeout):
+            nonlocal used
+            if not jobs:
+                return
+            if timeout != 0:
+                futures_wait(list(jobs), timeout=timeout, return_when=FIRST_COMPLETED)
+            for f in [f for f in jobs if f.done()]:
+                kind, g, payload = jobs.pop(f)
+                held.discard(g)
+                out = f.result()
+                if kind == "admit":
+                    for (r, fp), h in zip(payload, out):
+                        r.admitted = now()
+                        active[h] = _Active(r, r.steps, r.fp64, fp, g)
+                else:
+                    used -= sum(a.bytes for _, a in payload)
+                    deliver(payload, out)
+
+        try:
+            while i < len(pending) or waiting or active or jobs:
+                t = now()
+                while i < len(pending) and (not realtime or pending[i].arrival <= t):
+                    waiting.append(pending[i])
+                    i += 1
+                collect(0)
+                live = {a.group for a in active.values()}
+                new = {}
+                for r in list(waiting):
+                    fp = self.ex.footprint(r, r.fp64)
+                    if fp > self.budget:
+                        raise ValueError(f"request {r.rid} needs {fp} bytes, more than the whole budget")
+                    g = r.group()
+                    if g in held or used + fp > self.budget:
+                        continue
+                    if self.ex.free_slots(g) - len(new.get(g, ())) <= 0:
+                        continue
+                    if overlap and g in live and jobs:
+                        continue                   # joins once the worker is idle
+                    waiting.remove(r)
+                    used += fp
+                    if overlap and g not in live:
+                        new.setdefault(g, []).append((r, fp))
+                        continue
+                    h = self.ex.admit(r, r.fp64, g)
+                    r.admitted = now()
+                    active[h] = _Active(r, r.steps, r.fp64, fp, g)
+                for g, items in new.items():
+                    held.add(g)
+                    if hasattr(self.ex, "open"):
+                        self.ex.open(g)          # device objects of a group are made on this thread
+                    jobs[pool.submit(admit_job, g, items)] = ("admit", g, items)
+                groups = {}
+                for a in active.values():
+                    if a.group not in held:
+                        groups.setdefault(a.group, []).append(a)
+                if not groups:
+                    nxt = pending[i].arrival - now() if i < len(pending) and realtime else None
+                    if jobs:
+                        collect(None if nxt is None else max(nxt, 1e-4))
+                    elif nxt is not None and nxt > 0:
+                        time.sleep(min(nxt, 0.05))
+                    continue
+                plan = self.plan(groups)
+                self.ex.step(plan)
+                for a in active.values():
+                    if a.group in plan:
+                        a.left -= plan[a.group]
+                now_done = [(h, a) for h, a in active.items() if a.left <= 0]
+                for h, _ in now_done:
+                    del active[h]
+                still = {a.group for a in active.values()}
+                # finished members are read before their group steps again:
+                # here if the worker is idle and the group steps on, else on
+                # the worker with the group held (a group that is all done is
+                # read there while other groups step)
+                collect(0)
+                inline = [(h, a) for h, a in now_done if not overlap or (a.group in still and not jobs)]
+                if inline:
+                    used -= sum(a.bytes for _, a in inline)
+                    deliver(inline, read_release(inline))
+                later = {}
+                for h, a in now_done:
+                    if overlap and not (a.group in still and not jobs):
+                        later.setdefault(a.group, []).append((h, a))
+                for g, items in later.items():
+                    held.add(g)
+                    jobs[pool.submit(read_job, g, items)] = ("read", g, items)
+        finally:
+            if pool is not None:
+                pool.shutdown(wait=True)
         return done
 
 
@@ -253,9 +351,12 @@ def latency_stats(done):
 
 class DeviceExecutor:
     """Runs requests on the HIP library: one batch per group, each stepped on
-    its own stream.  A group whose membership changed is autotuned before it
-    is stepped again if its work per step is at least `tune_min` lattice
-    updates (kernel variants give bitwise the same results)."""
+    its own stream.  Library calls on one batch wait for that batch's work
+    only, so a worker thread can admit into or read from one group while the
+    main thread steps others (overlap_host).  A group whose membership
+    changed is autotuned before it is stepped again if its work per step is
+    at least `tune_min` lattice updates (kernel variants give bitwise the
+    same results)."""
 
     def __init__(self, capacity: int = 64, device: int = 0, tune_min: float = 4e6):
         import torch
@@ -270,12 +371,18 @@ class DeviceExecutor:
         self.next = 0
         self.tune_min = tune_min
         self.changed = set()
+        self.lock = threading.Lock()   # handle counter and maps, shared with the worker thread
+
+    overlap_host = True
 
     def _code(self, key):
         lat, col, prec = key[:3]
         lbm = self.lbm
         return (lat, {"BGK": lbm.LBM_BGK, "RR": lbm.LBM_RR, "HRR": lbm.LBM_HRR}[col],
                 lbm.LBM_FP64 if prec == "fp64" else lbm.LBM_FP32_DEV)
+
+    def open(self, group):
+        self.batch(group)
 
     def batch(self, group):
         if group not in self.batches:
@@ -303,19 +410,25 @@ class DeviceExecutor:
         for lv in (0, 1):
             rho, u = req.fields(lv)
             b.set_state(sl, lv, rho, u)
-        h = self.next
-        self.next += 1
-        self.where[h] = (group, sl)
-        self.changed.add(group)
+        with self.lock:
+            h = self.next
+            self.next += 1
+            self.where[h] = (group, sl)
+            self.changed.add(group)
         return h
+
+    def settle(self, group):
+        """Autotunes a group whose membership changed, if it is large enough."""
+        with self.lock:
+            tune = group in self.changed
+            self.changed.discard(group)
+        b = self.batches.get(group)
+        if tune and b is not None and b.info()["updates_per_step"] >= self.tune_min:
+            b.tune(reps=2)
 
     def step(self, plan):
         for g in plan:
-            if g in self.changed:
-                self.changed.discard(g)
-                b = self.batches[g]
-                if b.info()["updates_per_step"] >= self.tune_min:
-                    b.tune(reps=2)
+            self.settle(g)
         for g, n in plan.items():
             self.batches[g].step(n, self.streams[g].cuda_stream)
         for g in plan:
@@ -332,9 +445,11 @@ class DeviceExecutor:
         return out
 
     def release(self, h):
-        group, sl = self.where.pop(h)
+        with self.lock:
+            group, sl = self.where.pop(h)
         self.batches[group].remove(sl)
-        self.changed.add(group)
+        with self.lock:
+            self.changed.add(group)
 
     def close(self):
         for b in self.batches.values():

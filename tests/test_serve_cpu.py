@@ -1,6 +1,8 @@
 """Host logic of the continuous-batching server, on the CPU with a fake
 executor that runs each request on the CPU oracle (tiny grids)."""
 import math
+import threading
+import time
 
 import numpy as np
 import pytest
@@ -278,3 +280,138 @@ def test_prepared_payload_is_used():
     assert set(r.payload) == {0, 1}
     rho, u = r.fields(0)
     assert rho.shape[0] == r.workload.geom.nodes(0)
+
+
+class ThreadedFakeExecutor(FakeExecutor):
+    """Host jobs on a worker thread beside the rounds.  Stepping a group while
+    a host call works on it, or two host calls on one group at once, is an
+    error (on the device it would race with the batch's work)."""
+
+    overlap_host = True
+
+    def __init__(self, **kw):
+        super().__init__(**kw)
+        self.lock = threading.Lock()
+        self.flight = set()           # groups of the round being stepped
+        self.touch = {}               # group -> host calls in progress
+        self.overlapped = {"admit": 0, "read": 0, "release": 0, "settle": 0}
+
+    def _enter(self, key, what):
+        with self.lock:
+            assert key not in self.flight, f"{what} on group {key} while it steps"
+            assert self.touch.get(key, 0) == 0, f"two host calls on group {key}"
+            self.touch[key] = 1
+            if self.flight:
+                self.overlapped[what] += 1
+
+    def _leave(self, key):
+        with self.lock:
+            self.touch[key] = 0
+
+    def admit(self, req, fp64, group):
+        self._enter(group, "admit")
+        try:
+            with self.lock:
+                h = self.next
+                self.next += 1
+                self.steps_seen[h] = 0
+            g = req.workload.geom
+            D = g.D
+            grid = O.Grid(O.D2Q9 if D == 2 else O.D3Q19, O.RR, g.n[:D], g.lo[:D], g.hi[:D], tau_c=req.tau_coarse)
+            for lv in (0, 1):
+                grid.set_state(lv, *req.fields(lv))
+            time.sleep(0.002)                           # an upload takes a while
+            with self.lock:
+                self.grids[h] = (grid, req, fp64, group)
+                self.used_slots[group] = self.used_slots.get(group, 0) + 1
+                self.bytes_used += self.footprint(req, fp64)
+                self.max_bytes = max(self.max_bytes, self.bytes_used)
+                self.admit_order.append(req.rid)
+            return h
+        finally:
+            self._leave(group)
+
+    def read(self, h):
+        key = self.grids[h][3]
+        self._enter(key, "read")
+        try:
+            time.sleep(0.002)
+            return super().read(h)
+        finally:
+            self._leave(key)
+
+    def release(self, h):
+        key = self.grids[h][3]
+        self._enter(key, "release")
+        try:
+            with self.lock:
+                super().release(h)
+        finally:
+            self._leave(key)
+
+    def settle(self, group):
+        self._enter(group, "settle")
+        self.settled = getattr(self, "settled", 0) + 1
+        self._leave(group)
+
+    def step(self, plan):
+        with self.lock:
+            assert not any(self.touch.get(g, 0) for g in plan), "stepping a group a host call works on"
+            self.flight = set(plan)
+            members = [(h, v) for h, v in self.grids.items() if v[3] in plan]
+        self.plans.append(dict(plan))
+        for h, (grid, req, _, key) in members:
+            grid.step(plan[key])
+            self.steps_seen[h] += plan[key]
+        time.sleep(0.003)
+        with self.lock:
+            self.flight = set()
+
+
+def _alone_equal(r):
+    g = r.workload.geom
+    D = g.D
+    alone = O.Grid(O.D2Q9 if D == 2 else O.D3Q19, O.RR, g.n[:D], g.lo[:D], g.hi[:D], tau_c=r.tau_coarse)
+    for lv in (0, 1):
+        alone.set_state(lv, *I.fields(r.workload, lv))
+    alone.step(r.steps)
+    for lv in (0, 1):
+        rho, u = alone.get_macros(lv)
+        assert np.array_equal(rho, r.result[f"rho{lv}"]) and np.array_equal(u, r.result[f"u{lv}"])
+
+
+@pytest.mark.parametrize("policy", ["srpt", "share"])
+def test_host_jobs_beside_rounds_equal_running_alone(policy):
+    reqs = _trace(n=8, seed=5)
+    ex = ThreadedFakeExecutor(capacity=2)
+    budget = 3 * max(ex.footprint(r, True) for r in reqs)
+    done = serve.Server(ex, budget, max_chunk=3, policy=policy).run(reqs, realtime=False)
+    assert sorted(r.rid for r in done) == list(range(len(reqs)))
+    assert ex.max_bytes <= budget and max(ex.used_slots.values()) == 0
+    assert ex.overlapped["admit"] + ex.overlapped["read"] > 0     # some host work ran beside a round
+    assert ex.settled > 0
+    for r in done:
+        assert r.finished >= r.admitted
+        _alone_equal(r)
+
+
+def test_host_jobs_beside_rounds_keep_the_fp64_fallback():
+    reqs = _trace(n=6, seed=7)
+    for r in reqs:
+        r.fp64 = False
+    ex = ThreadedFakeExecutor(capacity=3, nan_fp32=True)
+    done = serve.Server(ex, 10 ** 12, max_chunk=3).run(reqs, realtime=False)
+    assert len(done) == len(reqs)
+    for r in done:
+        assert r.fell_back == (r.rid % 2 == 0)
+        assert np.isfinite(r.result["rho0"]).all()
+        _alone_equal(r)
+
+
+def test_host_jobs_beside_rounds_in_real_time():
+    reqs = _trace(n=6, seed=9)
+    ex = ThreadedFakeExecutor(capacity=2)
+    done = serve.Server(ex, 10 ** 12, max_chunk=3).run(reqs, realtime=True)
+    assert sorted(r.rid for r in done) == list(range(len(reqs)))
+    for r in done:
+        assert r.admitted >= r.arrival - 1e-9 and r.finished >= r.admitted
