@@ -238,6 +238,10 @@ int lbm_batch_use_graph(lbm_batch_handle b, int on);
  * whose fine phase runs both substeps in one launch, the fine variant is its
  * tile shape: 0 = 64 x 8, 1 = 32 x 8 lanes).  Synchronous. */
 int lbm_batch_tune(lbm_batch_handle b, int reps, int32_t variants[2]);
+/* Applies variants as lbm_batch_tune returns them (coarse, fine or tile
+ * shape), e.g. from a stored tuning result; LBM_EINVAL when an index is out
+ * of range.  Results do not depend on the variants.  Synchronous. */
+int lbm_batch_set_variants(lbm_batch_handle b, const int32_t variants[2]);
 /* info[3] = {grids held, lattice updates per coarse step over all grids,
  * device bytes of their state}. */
 int lbm_batch_info(lbm_batch_handle b, int64_t info[3]);

@@ -963,6 +963,7 @@ struct BatchBase {
   virtual void get_pops(int slot, int level, double* f, bool dev) = 0;
   virtual void step(int n, hipStream_t s) = 0;
   virtual void tune(int reps, int32_t* out) = 0;
+  virtual void set_variants(const int32_t* v) = 0;
   virtual void set_graph(bool on) = 0;
   virtual void info(int64_t* out) = 0;
   virtual int64_t slot_steps(int slot) = 0;
@@ -1540,6 +1541,19 @@ struct Batch final : BatchBase {
     out[1] = var_f;
   }
 
+  // Applies variants a previous tune returned (same meaning as its output).
+  void set_variants(const int32_t* v) override {
+    const int nf = fused() ? kNTile : NVAR;
+    if (v[0] < 0 || v[0] >= NVAR || v[1] < 0 || v[1] >= nf)
+      throw LbmError(LBM_EINVAL, "variant index out of range");
+    HIPCHK(hipSetDevice(device));
+    quiesce();
+    var_c = v[0];
+    var_f = v[1];
+    if (fused()) set_tile_var(v[1]);
+    drop_graph();
+  }
+
   void info(int64_t* out) override {
     int64_t active = 0, ups = 0, bytes = 0;
     for (int k = 0; k < capacity; ++k) {
@@ -1943,6 +1957,11 @@ int lbm_batch_use_graph(lbm_batch_handle b, int on) {
 int lbm_batch_tune(lbm_batch_handle b, int reps, int32_t variants[2]) {
   if (!b || reps < 1 || !variants) return LBM_EINVAL;
   return bguard(b, [&] { b->impl->tune(reps, variants); });
+}
+
+int lbm_batch_set_variants(lbm_batch_handle b, const int32_t variants[2]) {
+  if (!b || !variants) return LBM_EINVAL;
+  return bguard(b, [&] { b->impl->set_variants(variants); });
 }
 
 int lbm_batch_info(lbm_batch_handle b, int64_t info[3]) {

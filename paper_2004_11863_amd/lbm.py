@@ -37,7 +37,7 @@ EXPORTS = (
     "lbm_updates_per_step", "lbm_profile_enable", "lbm_kernel_time", "lbm_tune", "lbm_set_variants",
     "lbm_last_error", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove",
     "lbm_batch_set_state", "lbm_batch_get_macros", "lbm_batch_get_populations", "lbm_batch_step",
-    "lbm_batch_use_graph", "lbm_batch_tune", "lbm_batch_info", "lbm_batch_slot_steps", "lbm_footprint",
+    "lbm_batch_use_graph", "lbm_batch_tune", "lbm_batch_set_variants", "lbm_batch_info", "lbm_batch_slot_steps", "lbm_footprint",
     "lbm_batch_last_error",
 )
 
@@ -101,6 +101,7 @@ def load(path: str = LIB_PATH):
     L.lbm_batch_step.argtypes = [vp, ip, vp]
     L.lbm_batch_use_graph.argtypes = [vp, ip]
     L.lbm_batch_tune.argtypes = [vp, ip, i32p]
+    L.lbm_batch_set_variants.argtypes = [vp, i32p]
     L.lbm_batch_info.argtypes = [vp, i64p]
     L.lbm_batch_slot_steps.argtypes = [vp, ip, i64p]
     L.lbm_footprint.argtypes = [ctypes.POINTER(lbm_grid_desc), i64p]
@@ -275,6 +276,10 @@ class Grid:
         self.h = lbm_create_grid(lattice, collision, precision, n, lo, hi, tau_coarse, sigma, device)
         self.D, self.Q, self.xi, self.w = lbm_lattice_info(lattice)
         self.lattice, self.collision, self.precision = lattice, collision, precision
+        D = self.D
+        self.shape = (tuple(int(x) for x in list(n)[:D]), None if lo is None else tuple(int(x) for x in list(lo)[:D]),
+                      None if hi is None else tuple(int(x) for x in list(hi)[:D]))
+        self.device = device
 
     def close(self):
         if self.h:
@@ -356,7 +361,9 @@ class Batch:
             raise LbmError(rc, load().lbm_batch_last_error(None).decode())
         self.D, self.Q, self.xi, self.w = lbm_lattice_info(lattice)
         self.lattice, self.collision, self.precision = lattice, collision, precision
+        self.device = device
         self.dims = {}
+        self.shapes = {}
 
     def close(self):
         if self.b:
@@ -379,11 +386,14 @@ class Batch:
         if lo is not None and any(int(a) != int(b) for a, b in zip(lo, hi)):
             nf = [2 * (int(h) - int(l)) + 1 for l, h in zip(list(lo)[:D], list(hi)[:D])]
         self.dims[slot.value] = (nc, nf)
+        self.shapes[slot.value] = (tuple(nc), None if lo is None else tuple(int(x) for x in list(lo)[:D]),
+                                   None if hi is None else tuple(int(x) for x in list(hi)[:D]))
         return slot.value
 
     def remove(self, slot):
         _bcheck(load().lbm_batch_remove(self.b, slot), self.b)
         self.dims.pop(slot, None)
+        self.shapes.pop(slot, None)
 
     def nodes(self, slot, level):
         nc, nf = self.dims[slot]
@@ -417,6 +427,10 @@ class Batch:
         v = (ctypes.c_int32 * 2)()
         _bcheck(load().lbm_batch_tune(self.b, int(reps), v), self.b)
         return list(v)
+
+    def set_variants(self, variants):
+        v = (ctypes.c_int32 * 2)(*[int(x) for x in variants])
+        _bcheck(load().lbm_batch_set_variants(self.b, v), self.b)
 
     def info(self):
         v = (ctypes.c_int64 * 3)()

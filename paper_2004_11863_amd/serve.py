@@ -372,6 +372,8 @@ class DeviceExecutor:
         self.tune_min = tune_min
         self.changed = set()
         self.lock = threading.Lock()   # handle counter and maps, shared with the worker thread
+        from .tuning import TuneCache
+        self.tunings = TuneCache(None)  # in memory: variants per batch membership
 
     overlap_host = True
 
@@ -418,13 +420,14 @@ class DeviceExecutor:
         return h
 
     def settle(self, group):
-        """Autotunes a group whose membership changed, if it is large enough."""
+        """Autotunes a group whose membership changed, if it is large enough
+        (a membership seen before reuses its stored variants)."""
         with self.lock:
             tune = group in self.changed
             self.changed.discard(group)
         b = self.batches.get(group)
         if tune and b is not None and b.info()["updates_per_step"] >= self.tune_min:
-            b.tune(reps=2)
+            self.tunings.apply(b, reps=2)
 
     def step(self, plan):
         for g in plan:
