@@ -160,3 +160,53 @@ def test_batch_rejects_mismatched_descriptor_and_overflow():
         batch.add((32, 32), (8, 8), (40, 24))  # patch outside the grid
     assert e.value.code == lbm.LBM_EINVAL
     batch.close()
+
+
+def test_batch_calls_from_two_threads_beside_graph_capture():
+    """One thread steps a batch whose step graph is captured again every
+    round while another thread adds, fills, steps, reads and removes grids of
+    a second batch: a blocking call there must not invalidate the capture,
+    and the first batch's grids still compute what they compute alone."""
+    import threading
+
+    import torch
+    lbm = _lbm()
+    geoms = _geoms2d()
+    wls = [_wl(geoms[0], 0), _wl(geoms[3], 1)]
+    rounds, per = 10, 2
+    a = lbm.Batch(lbm.LBM_D2Q9, lbm.LBM_RR, lbm.LBM_FP32_DEV, capacity=4)
+    slots = [_add(a, w) for w in wls]
+    b = lbm.Batch(lbm.LBM_D2Q9, lbm.LBM_RR, lbm.LBM_FP32_DEV, capacity=4)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    stop = threading.Event()
+    errors, cycles = [], [0]
+
+    def other():
+        try:
+            while not stop.is_set():
+                sl = _add(b, _wl(geoms[1], cycles[0]))
+                b.step(1, sb.cuda_stream)
+                rho, u = b.get_macros(sl, 0)
+                assert np.isfinite(rho).all()
+                b.remove(sl)
+                cycles[0] += 1
+        except Exception as e:            # reported by the main thread
+            errors.append(e)
+
+    th = threading.Thread(target=other)
+    th.start()
+    try:
+        for _ in range(rounds):
+            a.use_graph(False)            # drops the graph: the next step captures it again
+            a.use_graph(True)
+            a.step(per, sa.cuda_stream)
+            sa.synchronize()
+    finally:
+        stop.set()
+        th.join()
+    assert not errors, errors
+    assert cycles[0] > 0
+    for sl, w in zip(slots, wls):
+        _check_same(a, sl, _alone(w, "RR", lbm.LBM_FP32_DEV, rounds * per))
+    a.close()
+    b.close()
