@@ -391,6 +391,7 @@ def main():
                 ("d2q9_4096_rr_fp64", "d2q9-4096", "RR", "fp64", 200),
                 ("d2q9_4096_hrr_fp32", "d2q9-4096", "HRR", "fp32", 200),
                 ("d3q19_384_rr_fp32", "d3q19-384", "RR", "fp32", 60),
+                ("d3q19_384_rr_fp64", "d3q19-384", "RR", "fp64", 30),
                 ("d3q19_384_hrr_fp32", "d3q19-384", "HRR", "fp32", 40)):
             if (wname, col, prec) == (args.workload, args.collision, args.precision):
                 continue
