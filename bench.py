@@ -63,15 +63,22 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def kernel_label(D, collision):
-    """The fine-level kernel lbm_profile_enable times for this grid."""
+def kernel_label(D, collision, variants=None):
+    """The fine-level kernel lbm_profile_enable times for this grid with the
+    autotuner's variants (D3Q19: the fine role's variants 2 and 3 select the
+    one-pass kernels)."""
+    v = list(variants) if variants is not None else [0, 0, 0, 0]
     if D == 2 and collision != "HRR":
         return ("k_fine2: both fine substeps of a coarse step (pull + collide twice, the t+1/2 state in LDS); "
                 "algorithmic bytes count 2 Q P_b per lattice update, 2 updates per node per launch")
     if collision == "HRR" and D == 2:
         return "k_hrr2: one H-RR fine substep in one pass (pull, velocities of the tile in LDS, strain rate, collide)"
     if collision == "HRR":
+        if v[3] >= 2:
+            return "k_hrr3: one H-RR fine substep in one marching pass (velocity planes in LDS, strain rate, collide)"
         return "k_collide_hrr: fine-level pull + H-RR collide (second pass)"
+    if v[1] >= 2:
+        return "k_fine3: both fine substeps of a coarse step in one marching pass (2 updates per node per launch)"
     return "k_stream: fine-level pull + collide"
 
 
@@ -364,7 +371,7 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": kernel_label(D, args.collision),
+            "kernel": kernel_label(D, args.collision, variants),
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -403,7 +410,9 @@ def main():
             a2 = 2 * q2 * pb2 * k2[2] / (k2[1] * 1e-3) / 1e9
             extra[name] = {"mlups": round(u2 * steps / d2 / 1e6, 1), "steps": steps,
                            "ms_per_step": d2 / steps * 1e3,
-                           "fine_kernel": kernel_label(2 if wname.startswith("d2q9") else 3, col).split(":")[0],
+                           "fine_kernel": kernel_label(2 if wname.startswith("d2q9") else 3, col,
+                                                       getattr(gr, "variants", None)).split(":")[0],
+                           "variants": getattr(gr, "variants", None),
                            "fine_kernel_alg_GBs": round(a2, 1), "fine_kernel_alg_frac": round(a2 / HBM_PEAK_GBS, 4)}
             gr.close()
             del gr, w2
