@@ -48,7 +48,7 @@ enum {
   LBM_OK = 0,
   LBM_EINVAL = -1,        /* bad argument or descriptor                         */
   LBM_ENOMEM = -2,        /* device or host allocation failed                   */
-  LBM_EUNSUPPORTED = -3,  /* valid request this build does not serve            */
+  LBM_EUNSUPPORTED = -3,  /* valid request the library does not serve          */
   LBM_EUNSTABLE = -4,     /* non-finite totals detected                         */
   LBM_EDEVICE = -5        /* a HIP call failed                                  */
 };
