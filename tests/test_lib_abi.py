@@ -57,6 +57,28 @@ def test_invalid_descriptor_rejected(kw):
     assert e.value.code == lbm.LBM_EINVAL
 
 
+LIMITS = [
+    # positions of a level are numbered in 32 bits: 1400^3 coarse nodes are past 2^31
+    (lbm.LBM_D3Q19, (1400, 1400, 1400), (400, 400, 400), (410, 410, 410)),
+    # ... and so is a fine cube of 1301^3 nodes inside a small coarse grid
+    (lbm.LBM_D3Q19, (660, 660, 660), (5, 5, 5), (655, 655, 655)),
+    # population storage past 2^40 elements
+    (lbm.LBM_D3Q19, (4000, 4000, 4000), (0, 0, 0), (0, 0, 0)),
+    # fewer than 3 coarse nodes on an axis
+    (lbm.LBM_D2Q9, (2, 64), (0, 0), (0, 0)),
+]
+
+
+@pytest.mark.parametrize("lat,n,lo,hi", LIMITS)
+def test_size_limits_rejected_before_any_device_call(lat, n, lo, hi):
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_create_grid(lat, lbm.LBM_RR, lbm.LBM_FP32_DEV, n, lo, hi)
+    assert e.value.code == lbm.LBM_EINVAL
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_footprint(lbm.make_desc(lat, lbm.LBM_RR, lbm.LBM_FP32_DEV, n, lo, hi, 0.51, 0.995))
+    assert e.value.code == lbm.LBM_EINVAL
+
+
 @pytest.mark.parametrize("lat,n,lo,hi", [(lbm.LBM_D2Q9, (64, 64), (16, 16), (48, 48)),
                                          (lbm.LBM_D2Q9, (8, 9), (0, 0), (0, 0)),
                                          (lbm.LBM_D3Q19, (24, 24, 24), (6, 6, 6), (17, 17, 17))])
