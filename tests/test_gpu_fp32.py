@@ -103,3 +103,43 @@ def test_full_size_config3_fp32_one_step():
     gpu.close()
     print(out)
     _check(out)
+
+
+def test_full_size_config2_hrr_fp32_tuned():
+    """The 4096^2 grid with H-RR (one-pass tiled kernels on both levels) in
+    the autotuner's variants, two coarse steps, against the oracle."""
+    lbm = _lbm()
+    wl = I.config2(seed=0, n=4096)
+    gpu, ref, levels = make_pair(wl, "HRR", lbm.LBM_FP32_DEV)
+    v = gpu.tune(reps=1)
+    gpu.step(2)
+    ref.step(2)
+    out = compare_fp32(gpu, ref, levels)
+    gpu.close()
+    print(v, out)
+    _check(out)
+
+
+def test_full_size_config3_hrr_fp32_one_step_tuned():
+    """The 384^3 grid with H-RR, one coarse step, against the oracle: the
+    autotuner's bulk variants with the fine H-RR substep forced to the
+    one-pass marching kernel (the two-pass default is covered elsewhere)."""
+    import os
+    try:
+        mem = os.sysconf("SC_PAGE_SIZE") * os.sysconf("SC_PHYS_PAGES")
+    except (ValueError, OSError):
+        mem = 0
+    if mem < 96 * 2 ** 30:
+        pytest.skip("needs about 60 GiB of host memory for the oracle")
+    lbm = _lbm()
+    wl = I.config3(seed=0, n=384)
+    gpu, ref, levels = make_pair(wl, "HRR", lbm.LBM_FP32_DEV)
+    v = gpu.tune(reps=1)
+    v[3] = 2
+    gpu.set_variants(v)
+    gpu.step(1)
+    ref.step(1)
+    out = compare_fp32(gpu, ref, levels)
+    gpu.close()
+    print(v, out)
+    _check(out)
