@@ -233,12 +233,12 @@ def batched(n_inst, steps):
             "speedup": round((ups * steps / dt) / (ups * loop_steps / dl), 2)}
 
 
-def serve_trace(n_req, rate, realtime=True):
+def serve_trace(n_req, rate, realtime=True, seed=5, **shape):
     """Served (continuous batching) and FIFO one-at-a-time runs of one trace;
     latency statistics and aggregate throughput of each."""
     import torch
     from paper_2004_11863_amd import serve
-    reqs = [r.prepare() for r in serve.poisson_trace(n_req, rate=rate, seed=5)]
+    reqs = [r.prepare() for r in serve.poisson_trace(n_req, rate=rate, seed=seed, **shape)]
     work = sum(r.updates() for r in reqs)
     free, total = torch.cuda.mem_get_info()
     ex = serve.DeviceExecutor(capacity=64)
@@ -249,7 +249,7 @@ def serve_trace(n_req, rate, realtime=True):
     ex.close()
     torch.cuda.empty_cache()
     st = serve.latency_stats(done)
-    reqs2 = [r.prepare() for r in serve.poisson_trace(n_req, rate=rate, seed=5)]
+    reqs2 = [r.prepare() for r in serve.poisson_trace(n_req, rate=rate, seed=seed, **shape)]
     t0 = time.perf_counter()
     done2 = serve.fifo_loop(reqs2, realtime=realtime)
     span2 = time.perf_counter() - t0
@@ -271,7 +271,8 @@ def serving(n_req, rate=200.0, utilization=0.7):
     batching (size-class groups, shortest remaining time first with backfill)
     against the plain FIFO per-instance loop on the same trace; then the same
     requests arriving at the rate that offers `utilization` of the measured
-    served throughput (the request mix is the same: the seed fixes it)."""
+    served throughput (the request mix is the same: the seed fixes it); and
+    64 arrivals of the same generator with small grids."""
     import inspect
     from paper_2004_11863_amd import serve
     SERVER_DEFAULTS = {k: v.default for k, v in inspect.signature(serve.Server).parameters.items()}
@@ -288,6 +289,12 @@ def serving(n_req, rate=200.0, utilization=0.7):
     sub = serve_trace(n_req, rate_u)
     out["sub_saturation"] = {"utilization_target": utilization, "rate_per_s": round(rate_u, 4),
                              "served": sub["served"], "fifo_per_instance": sub["fifo_per_instance"]}
+    # the same generator with small grids (64 requests: D2Q9 sides 64-512,
+    # D3Q19 sides 32-96), where per-request launches dominate and batching pays
+    small = serve_trace(64, rate, seed=11, d2_side=(64, 512), d3_side=(32, 96))
+    out["small_requests"] = {"requests": 64, "rate_per_s": rate, "d2_side": [64, 512], "d3_side": [32, 96],
+                             "seed": 11, "total_updates": small["total_updates"],
+                             "served": small["served"], "fifo_per_instance": small["fifo_per_instance"]}
     return out
 
 
