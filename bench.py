@@ -44,7 +44,8 @@ def parse():
     p.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     p.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    p.add_argument("--cpu-steps", type=int, default=3)
+    p.add_argument("--cpu-steps", type=int, default=24,
+                   help="coarse steps of the CPU oracle sample (about 10 s on 16 host cores at D2Q9 4096^2)")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-instances measurement")
     p.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     p.add_argument("--batch-n", type=int, default=256)
@@ -298,6 +299,25 @@ def serving(n_req, rate=200.0, utilization=0.7):
     return out
 
 
+def d2d_copy_GBs(mib=2048, reps=10):
+    """Device-to-device copy bandwidth (bytes read + written per second) of a
+    plain `copy_` of mib MiB, timed with HIP events on the current stream."""
+    import torch
+    a = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    gbs = 2 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def copy_probe(mib):
     import torch
     n = mib * (1 << 20) // 4
@@ -325,6 +345,7 @@ def main():
     from paper_2004_11863_amd import lbm
     lbm.load()
 
+    copy_gbs = (d2d_copy_GBs(), lbm.lbm_copy_probe(2 << 30, 10))
     wl = workload(args.workload)
     grid = make_gpu(wl, args.collision, args.precision)
     ups = grid.updates_per_step()
@@ -393,6 +414,11 @@ def main():
             # performs several lattice updates per node
             "hbm_achieved": None if traffic is None else round(traffic / (mean_ms * 1e-3) / 1e9, 1),
             "hbm_frac": None if traffic is None else round(traffic / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            # the same against the faster of two device-to-device copies
+            # measured in this run (hipMemcpy through torch, and the
+            # library's streaming copy kernel), bytes read + written
+            "copy_GBs": {"memcpy": round(copy_gbs[0], 1), "streaming_kernel": round(copy_gbs[1], 1)},
+            "hbm_frac_of_copy": None if traffic is None else round(traffic / (mean_ms * 1e-3) / 1e9 / max(copy_gbs), 4),
         },
         "kernel_variants": variants,
         "totals_finite": bool(all(map(lambda v: v == v, list(m) + list(p.ravel())))),

@@ -256,6 +256,15 @@ int lbm_batch_slot_steps(lbm_batch_handle b, int slot, int64_t* steps);
  * also holds a third.  D3Q19 BGK / RR fine levels add the compact copy of
  * the fine x-bands (2 * 19 * 5 values per fine (y, z) row). */
 int lbm_footprint(const lbm_grid_desc* d, int64_t* bytes);
+
+/* Bandwidth reference (diagnostic): copies `bytes` (rounded down to 16) from
+ * one device buffer to another `reps` times with a streaming kernel
+ * (16-byte non-temporal loads and stores, 1024 per work group) after one untimed
+ * pass, and stores the bytes read plus written per second, in GB/s, timed
+ * with HIP events.  Allocates and frees its two buffers (LBM_ENOMEM if they
+ * do not fit); LBM_EINVAL for bytes < 16, reps < 1 or an unknown device.
+ * Synchronous. */
+int lbm_copy_probe(int device, int64_t bytes, int reps, double* gbs);
 const char* lbm_batch_last_error(lbm_batch_handle b);
 
 #ifdef __cplusplus

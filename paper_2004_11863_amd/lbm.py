@@ -37,7 +37,7 @@ EXPORTS = (
     "lbm_updates_per_step", "lbm_profile_enable", "lbm_kernel_time", "lbm_tune", "lbm_set_variants",
     "lbm_last_error", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove",
     "lbm_batch_set_state", "lbm_batch_get_macros", "lbm_batch_get_populations", "lbm_batch_step",
-    "lbm_batch_use_graph", "lbm_batch_tune", "lbm_batch_set_variants", "lbm_batch_info", "lbm_batch_slot_steps", "lbm_footprint",
+    "lbm_batch_use_graph", "lbm_batch_tune", "lbm_batch_set_variants", "lbm_batch_info", "lbm_batch_slot_steps", "lbm_footprint", "lbm_copy_probe",
     "lbm_batch_last_error",
 )
 
@@ -105,6 +105,7 @@ def load(path: str = LIB_PATH):
     L.lbm_batch_info.argtypes = [vp, i64p]
     L.lbm_batch_slot_steps.argtypes = [vp, ip, i64p]
     L.lbm_footprint.argtypes = [ctypes.POINTER(lbm_grid_desc), i64p]
+    L.lbm_copy_probe.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     L.lbm_batch_last_error.argtypes = [vp]
     L.lbm_batch_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -147,6 +148,15 @@ def make_desc(lattice, collision, precision, n, lo=None, hi=None, tau_coarse=0.5
         d.n[k], d.lo[k], d.hi[k] = int(nn[k]), int(lo[k]), int(hi[k])
     d.tau_coarse, d.sigma, d.device, d.reserved = float(tau_coarse), float(sigma), int(device), 0
     return d
+
+
+def lbm_copy_probe(bytes_, reps=10, device=0):
+    """GB/s (read + written) of the library's streaming device copy."""
+    v = ctypes.c_double()
+    rc = load().lbm_copy_probe(int(device), int(bytes_), int(reps), ctypes.byref(v))
+    if rc != LBM_OK:
+        raise LbmError(rc, load().lbm_last_error(None).decode())
+    return v.value
 
 
 def lbm_footprint(desc):

@@ -91,3 +91,17 @@ def test_valid_descriptor_passes_validation(lat, n, lo, hi):
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_create_grid(lat, lbm.LBM_RR, lbm.LBM_FP64, n, lo, hi)
     assert e.value.code == lbm.LBM_EDEVICE
+
+
+@pytest.mark.parametrize("nbytes,reps", [(8, 1), (1 << 20, 0)])
+def test_copy_probe_rejects_bad_arguments(nbytes, reps):
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_copy_probe(nbytes, reps)
+    assert e.value.code == lbm.LBM_EINVAL
+
+
+@pytest.mark.gpu
+def test_copy_probe_reports_a_plausible_bandwidth():
+    gbs = lbm.lbm_copy_probe(256 << 20, 5)
+    assert 500.0 < gbs < 8000.0 * 1.05      # below the HBM peak (the buffers exceed no cache: 2 x 256 MiB)
+    assert lbm.lbm_copy_probe(4096 + 8, 1) > 0.0   # a size that is not a multiple of the work per pass
