@@ -34,6 +34,8 @@
  *     copies in and out and keeps no pointer to it.
  *   - A handle is used by one host thread at a time.  All device work is
  *     ordered on the stream given to lbm_step (or the handle's own stream).
+ *     Different handles may be used from different threads at once: the
+ *     library serialises its blocking HIP calls with its hipGraph captures.
  */
 #ifndef LBM_H_
 #define LBM_H_
@@ -154,9 +156,12 @@ int lbm_interface_tables(lbm_handle h, int64_t* hist_nodes, int64_t* ring_nodes,
 int lbm_updates_per_step(lbm_handle h, int64_t* updates);
 
 /* Per-launch timing of the fine-level pull-stream + collide kernel (the
- * dominant kernel; D2Q9 BGK / RR: the kernel that runs both fine substeps of
- * a coarse step; H-RR: its second pass, which pulls again and collides with
- * the strain rate of the velocities the first pass wrote): when enabled,
+ * dominant kernel): D2Q9 BGK / RR the kernel that runs both fine substeps of
+ * a coarse step; D3Q19 BGK / RR the fine stream of each substep, or in fine
+ * variants 2 and 3 the marching kernel of both substeps; D2Q9 H-RR the
+ * one-pass substep kernel; D3Q19 H-RR the collision pass (which pulls again
+ * and collides with the strain rate of the velocities the first pass wrote),
+ * or in variants 2 and 3 the one-pass marching kernel.  When enabled,
  * lbm_step records HIP events around each of its launches on the launch
  * stream; lbm_kernel_time returns the number of timed launches, their mean
  * duration in ms and the lattice updates one launch performs (fine middle
@@ -201,8 +206,9 @@ const char* lbm_last_error(lbm_handle h);
  * Each coarse step is one sequence of launches over the work of all grids
  * (bulk chunks, interface node blocks), captured once as a hipGraph and
  * replayed; grids may join and leave between steps (continuous batching),
- * which rewrites device work lists (the launch is captured again only when a
- * list outgrows its buffer).  A grid in a batch computes exactly what the
+ * which rewrites device work lists (the launch is captured again when a list
+ * outgrows its buffer, after lbm_batch_tune or lbm_batch_set_variants, and
+ * when graphs are switched off and on).  A grid in a batch computes exactly what the
  * same grid computes alone.
  *
  * Every call but lbm_batch_step returns when it is done, and first waits for
