@@ -38,3 +38,24 @@ def test_served_fp32_within_tolerance_of_fp64():
             assert np.abs(r.result[f"rho{lv}"] - ref[f"rho{lv}"]).max() < 1e-5
             du = r.result[f"u{lv}"] - ref[f"u{lv}"]
             assert np.linalg.norm(du) / np.linalg.norm(ref[f"u{lv}"]) < 1e-4
+
+
+@pytest.mark.parametrize("seed,collision", [(21, "RR"), (22, "HRR")])
+def test_served_in_real_time_with_autotuning_equals_running_alone(seed, collision):
+    """Arrivals in real time, admission and read-back on the worker thread
+    beside the rounds, groups autotuned after every membership change: each
+    result is still bitwise the request run alone."""
+    reqs = serve.poisson_trace(12, rate=400.0, seed=seed, d2_side=(64, 256), d3_side=(24, 48), steps=(10, 40),
+                               fp64_frac=0.25, collision=collision)
+    ex = serve.DeviceExecutor(capacity=4, tune_min=1e4)
+    assert ex.overlap_host
+    fps = [ex.footprint(r, r.fp64) for r in reqs]
+    budget = sum(sorted(fps)[-5:])
+    done = serve.Server(ex, budget, max_chunk=6, slice_s=0.005).run(reqs, realtime=True)
+    ex.close()
+    assert sorted(r.rid for r in done) == list(range(len(reqs)))
+    for r in done:
+        assert r.finished >= r.admitted >= r.arrival - 1e-9
+        alone = serve.run_alone(r)
+        for k, v in alone.items():
+            assert np.array_equal(v, r.result[k]), (r.rid, k)
