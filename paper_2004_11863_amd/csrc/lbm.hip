@@ -1057,7 +1057,7 @@ struct Batch final : BatchBase {
     HIPCHK(hipMemset(d_inst.p, 0, d_inst.bytes));
     d_counts.alloc(sizeof(int) * W_KINDS);
     HIPCHK(hipMemset(d_counts.p, 0, d_counts.bytes));
-    for (int k = 0; k < W_KINDS; ++k) grow_items(k, 1024);
+    for (int k = 0; k < W_KINDS; ++k) grow_items(k, 64);
   }
 
   void grow_items(int k, size_t n) {
