@@ -715,13 +715,13 @@ struct Grid final : GridBase {
         hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, 0.0, 0.0, 1.0, mf, g, itf);
         timed(s, [&] { launch_collide_hrr<1>(fB, fA, mf, tau_f, s, hrr_lds_var(var[3])); });
       }
-      hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR, true>), dim3(br), dim3(IB), 0, s, Hp, fA, g, itf, kf, omf, tau_f, sig);
       // coarse collision before the TN transfer: the vector kernel also
-      // passes over TN nodes, which the transfer then overwrites
+      // passes over TN nodes, which the transfer then overwrites; the t+1
+      // ring (into fine A, independent of both) shares the transfer's launch
       if (one_c) launch_hrr2c(csrc, cdst, mc, s);
       else launch_collide_hrr<0>(csrc, cdst, mc, tau_c, s);
-      hipLaunchKernelGGL((k_coalesce<LAT, DEV, S, M_HRR>), dim3(bc), dim3(256), 0, s, fB, cdst, g, itf, kc, omc,
-                         tau_c, sig);
+      hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, M_HRR>), dim3(br2 + bc), dim3(256), 0, s, Hp, fA, fB, cdst, g,
+                         itf, kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, (const S*)nullptr);
     }
     HIPCHK(hipGetLastError());
     cpar ^= 1;
@@ -1416,10 +1416,11 @@ struct Batch final : BatchBase {
       phase_stream<M_HRR, 1, 1>(s, var_f);
       hipLaunchKernelGGL((kb_ring_macro<LAT, S, 1>), grid_of(W_RING), ib, 0, s, di(), items(W_RING), cnt(W_RING));
       phase_collide<1, 1>(s, var_f);
-      hipLaunchKernelGGL((kb_ring<LAT, DEV, S, M_HRR, 1>), grid_of(W_RING), ib, 0, s, di(), items(W_RING), cnt(W_RING));
       phase_collide<0, 0>(s, var_c);
-      hipLaunchKernelGGL((kb_coalesce<LAT, DEV, S, M_HRR>), grid_of(W_TNB), dim3(256), 0, s, di(), items(W_TNB),
-                         cnt(W_TNB));
+      // the t+1 ring shares the transfer's launch (as for BGK / RR)
+      const unsigned nrb = grid_of(W_RING).x;
+      hipLaunchKernelGGL((kb_ring_coalesce<LAT, DEV, S, M_HRR>), dim3(nrb + grid_of(W_TNB).x), dim3(256), 0, s, di(),
+                         items(W_RING), cnt(W_RING), items(W_TNB), cnt(W_TNB), (int)nrb);
     }
     hipLaunchKernelGGL(kb_advance, dim3((unsigned)((capacity + 255) / 256)), dim3(256), 0, s, d_inst.template as<InstDev>(),
                        capacity);
