@@ -633,6 +633,24 @@ __global__ void k_hist_strain(const T* __restrict__ src, const T* __restrict__ m
 }
 
 
+// H-RR: the coarse strain rate of history node h (as k_hist_strain), then
+// the temporal interpolation of all of that node's fields to t+1/2 (as
+// k_hist_time) -- one thread per history node, one launch for both.
+template <int LAT, bool DEV, typename T, bool PULL>
+__global__ void k_hist_strain_time(const T* __restrict__ src, const T* __restrict__ mac_c, const double* __restrict__ Hm,
+                                   const double* __restrict__ H0, double* __restrict__ Hp, double* __restrict__ G,
+                                   const Geo g, const Iface itf) {
+  using F = HF<LAT, M_HRR>;
+  const int64_t h = xcd_block() * blockDim.x + threadIdx.x;
+  if (h >= itf.NH) return;
+  hist_strain_body<LAT, DEV, T, PULL>(src, mac_c, Hp, g, itf, h);
+#pragma unroll
+  for (int f = 0; f < F::N; ++f) {
+    const int64_t k = (int64_t)f * itf.NH + h;
+    G[k] = time_half(Hm[k], H0[k], Hp[k]);
+  }
+}
+
 // Temporal interpolation of every history field to t+1/2 (time_half), for
 // all fields of all history nodes (H-RR, whose strain-rate fields are filled
 // after the capture).
@@ -761,6 +779,22 @@ __global__ void k_ring(const double* __restrict__ G, S* __restrict__ dst, const 
                        double kf, double om_f, double tau_f, double sig) {
   ring_body<LAT, DEV, S, MODEL, PARTIAL>(G, dst, g, itf, kf, om_f, tau_f, sig,
                                          xcd_block() * blockDim.x + threadIdx.x);
+}
+
+// H-RR: the t+1/2 ring populations (as k_ring, from G into dst) and the
+// t+1 ring velocities (as k_ring_macro with weights (0, 0, 1), into mac_f)
+// in one launch of two XCD-contiguous halves of `half` blocks each: they
+// read the history and write disjoint buffers.
+template <int LAT, bool DEV, typename S, int MODEL>
+__global__ void k_ring_half_macro(const double* __restrict__ G, S* __restrict__ dst, const double* __restrict__ Hm,
+                                  const double* __restrict__ H0, const double* __restrict__ Hp, S* __restrict__ mac_f,
+                                  const Geo g, const Iface itf, double kf, double om_f, double tau_f, double sig,
+                                  int half) {
+  const int part = (int)blockIdx.x >= half;
+  const int b = (int)blockIdx.x - part * half, per = half / kXCD;
+  const int64_t r = ((int64_t)(b % kXCD) * per + b / kXCD) * blockDim.x + threadIdx.x;
+  if (part == 0) ring_body<LAT, DEV, S, MODEL, true>(G, dst, g, itf, kf, om_f, tau_f, sig, r);
+  else ring_macro_body<LAT, S>(Hm, H0, Hp, 0.0, 0.0, 1.0, mac_f, g, itf, r);
 }
 
 

@@ -699,16 +699,25 @@ struct Grid final : GridBase {
       hipLaunchKernelGGL((k_fict<LAT, DEV, S, S>), dim3(bt), dim3(IB), 0, s, fB, mc, g, itf);
       // the coarse velocities at the history nodes' neighbours: from the
       // velocity pass, or (one-pass coarse level) pulled here
-      if (one_c) hipLaunchKernelGGL((k_hist_strain<LAT, DEV, S, true>), dim3(bh), dim3(IB), 0, s, csrc, mc, Hp, g, itf);
-      else hipLaunchKernelGGL((k_hist_strain<LAT, DEV, S, false>), dim3(bh), dim3(IB), 0, s, csrc, mc, Hp, g, itf);
-      hipLaunchKernelGGL(k_hist_time, dim3(bg), dim3(256), 0, s, Hm, H0, Hp, G.as<double>(), NH * F::N);
-      hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR, true>), dim3(br), dim3(IB), 0, s, G.as<double>(), fB, g, itf, kf, omf,
-                         tau_f, sig);
+      // strain rate at the history nodes, then the temporal interpolation
+      // of their fields (one thread per history node, one launch)
+      if (one_c)
+        hipLaunchKernelGGL((k_hist_strain_time<LAT, DEV, S, true>), dim3(bh), dim3(IB), 0, s, csrc, mc, Hm, H0, Hp,
+                           G.as<double>(), g, itf);
+      else
+        hipLaunchKernelGGL((k_hist_strain_time<LAT, DEV, S, false>), dim3(bh), dim3(IB), 0, s, csrc, mc, Hm, H0, Hp,
+                           G.as<double>(), g, itf);
+      if (D == 2 || hrr_one_pass3()) {
+        // the t+1/2 ring and the t+1 ring velocities in one launch
+        hipLaunchKernelGGL((k_ring_half_macro<LAT, DEV, S, M_HRR>), dim3(2 * br), dim3(IB), 0, s, G.as<double>(), fB, Hm,
+                           H0, Hp, mf, g, itf, kf, omf, tau_f, sig, (int)br);
+      } else {
+        hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR, true>), dim3(br), dim3(IB), 0, s, G.as<double>(), fB, g, itf, kf,
+                           omf, tau_f, sig);
+      }
       if constexpr (D == 2) {
-        hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, 0.0, 0.0, 1.0, mf, g, itf);
         timed(s, [&] { launch_hrr2(fB, fA, mf, s); });
       } else if (hrr_one_pass3()) {
-        hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, 0.0, 0.0, 1.0, mf, g, itf);
         timed(s, [&] { launch_hrr3(fB, fA, mf, s); });
       } else {
         launch_stream<M_HRR, 1>(fB, fA, mf, tau_f, s);
