@@ -1281,10 +1281,13 @@ __device__ __forceinline__ void hrr2c_tile(const S* __restrict__ src, S* __restr
   const bool skip = skip_vec<0>(g, x0, V, y, 0, nx);
   const bool inner = rr >= 1 && rr <= TY && rv >= 1 && rv <= TXV && kr < nv && yr < ny && !skip;
   VA v[Q];
+  // a skipped (wholly covered) vector stores zero velocities: only its TN
+  // and covered neighbours read them (TN is rewritten by the transfer,
+  // covered nodes are not evolved), but every slot a lane reads is defined
+  VA ux = VA(S(0)), uy = VA(S(0));
   if (!skip) {
     const Pull<S, Q, V, 0, 2> pl(g.pc, 0, x0, y, 0, nx, ny, 1);
     pl.template load_all<L>(src, v);
-    VA ux, uy;
 #pragma unroll
     for (int j = 0; j < V; ++j) {
       if (coarse_class(g, x0 + j, y, 0) == CC_TN) {
@@ -1300,9 +1303,9 @@ __device__ __forceinline__ void hrr2c_tile(const S* __restrict__ src, S* __restr
         uy[j] = u[1];
       }
     }
-    *(VA*)&lu[0][rr][rv * V] = ux;
-    *(VA*)&lu[1][rr][rv * V] = uy;
   }
+  *(VA*)&lu[0][rr][rv * V] = ux;
+  *(VA*)&lu[1][rr][rv * V] = uy;
   __syncthreads();
   if (!inner) return;
   const int c = rv * V;

@@ -243,24 +243,29 @@ struct Grid final : GridBase {
     if (fused) var[1] = 0;
     if (D == 3 && desc.collision == LBM_HRR) var[3] = 0;
     timed_factor = fused_now() ? 2 : 1;
-    for (int p = 0; p < 2; ++p) cbuf[p].alloc(pop_bytes(g.Ncp));
+    // every state buffer starts at zero: the state is zero until
+    // lbm_set_state, and values no step writes (the populations of covered
+    // coarse nodes in the buffer they are not set in) stay the same from
+    // run to run
+    auto zalloc = [](DevBuf& b, size_t bytes) {
+      b.alloc(bytes);
+      if (bytes) HIPCHK(hipMemset(b.p, 0, bytes));
+    };
+    for (int p = 0; p < 2; ++p) zalloc(cbuf[p], pop_bytes(g.Ncp));
     if (g.has_fine)
-      for (int p = 0; p < (fused ? 3 : 2); ++p) fbuf[p].alloc(pop_bytes(g.Nfp));
-    if (g.has_fine && D == 3 && desc.collision != LBM_HRR) {
-      xbuf.alloc(sizeof(S) * (size_t)xband_elems(g, Q));
-      HIPCHK(hipMemset(xbuf.p, 0, xbuf.bytes));
-    }
+      for (int p = 0; p < (fused ? 3 : 2); ++p) zalloc(fbuf[p], pop_bytes(g.Nfp));
+    if (g.has_fine && D == 3 && desc.collision != LBM_HRR) zalloc(xbuf, sizeof(S) * (size_t)xband_elems(g, Q));
     if (desc.collision == LBM_HRR) {
-      mac_c.alloc(plane_bytes(g.Ncp, 1 + D));
-      if (g.has_fine) mac_f.alloc(plane_bytes(g.Nfp, 1 + D));
+      zalloc(mac_c, plane_bytes(g.Ncp, 1 + D));
+      if (g.has_fine) zalloc(mac_f, plane_bytes(g.Nfp, 1 + D));
     }
     tau_c = desc.tau_coarse;
     tau_f = 2.0 * tau_c - 0.5;
     sig = desc.sigma;
     if (g.has_fine) {
       const size_t NH = tabs.hnode.size();
-      for (int s = 0; s < 3; ++s) hist[s].alloc(sizeof(double) * HN * NH);
-      G.alloc(sizeof(double) * HN * NH);
+      for (int s = 0; s < 3; ++s) zalloc(hist[s], sizeof(double) * HN * NH);
+      zalloc(G, sizeof(double) * HN * NH);
       auto up = [&](DevBuf& b, const void* src, size_t bytes) {
         b.alloc(bytes);
         if (bytes) HIPCHK(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
