@@ -179,7 +179,7 @@ def test_groups_split_by_key_and_size_class():
     for r in reqs:
         lat, col, prec, sc = r.group()
         assert (lat, col, prec) == r.key()
-        assert 4 ** sc <= r.ups() < 4 ** (sc + 1)
+        assert serve.SIZE_BIN ** sc <= r.ups() < serve.SIZE_BIN ** (sc + 1)
     r = reqs[0]
     assert r.group(fp64=True)[2] == "fp64" and r.group(fp64=False)[2] == "fp32"
 
