@@ -294,16 +294,6 @@ __device__ __forceinline__ void kb_coalesce_item(const InstDev& I, int idx) {
                                     glob(I.itf),
                                     2.0 * I.tau_c / I.tau_f, 1.0 - 1.0 / I.tau_c, I.tau_c, I.sig, idx, xb);
 }
-template <int LAT, bool DEV, typename S, int MODEL>
-__global__ __launch_bounds__(256) void kb_coalesce(const InstDev* __restrict__ inst, const Work* __restrict__ items,
-                                                   const int* __restrict__ count) {
-  const int it = item_of(*count);
-  if (it < 0) return;
-  {
-    const Work w = load_item(items, it);
-    kb_coalesce_item<LAT, DEV, S, MODEL>(inst[w.inst], w.idx);
-  }
-}
 
 // The t+1 ring and the fine-to-coarse transfer in one launch: blocks
 // [0, nrb) take ring items (64 lanes each), the rest TN blocks.

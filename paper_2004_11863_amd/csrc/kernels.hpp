@@ -626,16 +626,11 @@ __device__ __forceinline__ void hist_strain_body(const T* __restrict__ src, cons
 #pragma unroll
   for (int k = 0; k < NS<D>::value; ++k) H[(F::S + k) * NH + h] = v[k];
 }
-template <int LAT, bool DEV, typename T, bool PULL>
-__global__ void k_hist_strain(const T* __restrict__ src, const T* __restrict__ mac_c, double* __restrict__ H,
-                              const Geo g, const Iface itf) {
-  hist_strain_body<LAT, DEV, T, PULL>(src, mac_c, H, g, itf, xcd_block() * blockDim.x + threadIdx.x);
-}
 
 
-// H-RR: the coarse strain rate of history node h (as k_hist_strain), then
-// the temporal interpolation of all of that node's fields to t+1/2 (as
-// k_hist_time) -- one thread per history node, one launch for both.
+// H-RR: the coarse strain rate of history node h (hist_strain_body), then
+// the temporal interpolation of all of that node's fields to t+1/2
+// (time_half) -- one thread per history node, one launch for both.
 template <int LAT, bool DEV, typename T, bool PULL>
 __global__ void k_hist_strain_time(const T* __restrict__ src, const T* __restrict__ mac_c, const double* __restrict__ Hm,
                                    const double* __restrict__ H0, double* __restrict__ Hp, double* __restrict__ G,
@@ -651,15 +646,6 @@ __global__ void k_hist_strain_time(const T* __restrict__ src, const T* __restric
   }
 }
 
-// Temporal interpolation of every history field to t+1/2 (time_half), for
-// all fields of all history nodes (H-RR, whose strain-rate fields are filled
-// after the capture).
-__global__ void k_hist_time(const double* __restrict__ Hm, const double* __restrict__ H0,
-                            const double* __restrict__ Hp, double* __restrict__ G, int64_t n) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  G[k] = time_half(Hm[k], H0[k], Hp[k]);
-}
 
 __device__ __forceinline__ double cubic_w(int s) { return (s == 1 || s == 2) ? 9.0 / 16.0 : -1.0 / 16.0; }
 
@@ -940,11 +926,6 @@ __device__ __forceinline__ void coalesce_body(const S* __restrict__ src_f, S* __
   for (int i = 0; i < Q; ++i) dst_c[pop_at<S, Q>(ci, i)] = store_pop<S, DEV, LAT>(f[i], i);
 }
 
-template <int LAT, bool DEV, typename S, int MODEL>
-__global__ __launch_bounds__(256) void k_coalesce(const S* __restrict__ src_f, S* __restrict__ dst_c, const Geo g,
-                                                  const Iface itf, double kc, double om_c, double tau_c, double sig) {
-  coalesce_body<LAT, DEV, S, MODEL>(src_f, dst_c, g, itf, kc, om_c, tau_c, sig, xcd_block());
-}
 
 // Coarse pull-stream + collide (BGK, RR) and the ring reconstruction at
 // t+1/2 (G -> the fine buffer of half times) in one launch: independent work,
