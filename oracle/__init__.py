@@ -42,6 +42,8 @@ MUTATIONS = {
     "tauf": 10,
     "feq2": 11,
     "nofilter": 12,
+    "filter_zoff": 13,
+    "face_axes": 14,
 }
 
 

@@ -59,7 +59,9 @@ enum {
   MUT_SC_HALF = 9,        /* fine strain rate halved instead of doubled       */
   MUT_TAUF = 10,          /* tau_f = 2 tau_c (missing -1/2)                   */
   MUT_FEQ2 = 11,          /* second-order equilibrium (third order dropped)   */
-  MUT_NOFILTER = 12       /* fine->coarse transfer without the filter         */
+  MUT_NOFILTER = 12,      /* fine->coarse transfer without the filter         */
+  MUT_FILTER_ZOFF = 13,   /* 3D filter sampling shifted by one node along z   */
+  MUT_FACE_AXES = 14      /* face-centre stencil built with its axes swapped  */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -598,11 +600,13 @@ void* orc_create(int lat, int model, const int* n, const int* lo, const int* hi,
       np = 4;
     } else {
       int e0 = oddax[0], e1 = oddax[1];
+      int j0 = j[e0], j1 = j[e1];
+      if (g_mut == MUT_FACE_AXES) { j0 = j[e1]; j1 = j[e0]; }
       for (int s1 = 0; s1 < 4; ++s1)
         for (int s0 = 0; s0 < 4; ++s0) {
           int c[3] = {base[0], base[1], base[2]};
-          c[e0] = g->a[e0] + (j[e0] - 3) / 2 + s0;
-          c[e1] = g->a[e1] + (j[e1] - 3) / 2 + s1;
+          c[e0] = g->a[e0] + (j0 - 3) / 2 + s0;
+          c[e1] = g->a[e1] + (j1 - 3) / 2 + s1;
           g->rpt[16 * r + 4 * s1 + s0] = hof[cidx(g, c[0], c[1], c[2])];
           g->rw[16 * r + 4 * s1 + s0] = cw[s0] * cw[s1];
         }
@@ -1033,7 +1037,8 @@ static void two_level_step(ogrid* g) {
       double ft[MAXQ] = {0};
       for (int s = 0; s < nst; ++s) {
         int o[3] = {s % 3 - 1, (s / 3) % 3 - 1, D == 3 ? s / 9 - 1 : 0};
-        long k = fidx(g, j[0] + o[0], j[1] + o[1], j[2] + o[2]);
+        int zs = (g_mut == MUT_FILTER_ZOFF && D == 3) ? 1 : 0;
+        long k = fidx(g, j[0] + o[0], j[1] + o[1], j[2] + o[2] + zs);
         double f0[MAXQ], uu[3];
         for (int d = 0; d < 3; ++d) uu[d] = g->u_f[d * Nf + k];
         feq_L(&g->L, g->rho_f[k], uu, f0);

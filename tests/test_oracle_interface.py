@@ -39,12 +39,15 @@ def test_uniform_flow_stays_uniform(lat, model):
     P.pin_uniform_flow(lat, model, steps=60 if lat == O.D2Q9 else 12)
 
 
+@pytest.mark.parametrize("lat", [O.D2Q9, O.D3Q19])
+@pytest.mark.parametrize("kind", ["shear", "acoustic"])
+@pytest.mark.parametrize("model,sigma", [(O.BGK, 0.995), (O.RR, 0.995), (O.HRR, 0.995), (O.HRR, 0.0)])
+def test_two_level_within_refinement_difference(lat, kind, model, sigma):
+    P.pin_two_level_vs_uniform(kind, model, sigma=sigma, lat=lat)
+
+
+@pytest.mark.parametrize("lat", [O.D2Q9, O.D3Q19])
 @pytest.mark.parametrize("kind", ["shear", "acoustic"])
 @pytest.mark.parametrize("model", [O.BGK, O.RR, O.HRR])
-def test_two_level_matches_uniform_run(kind, model):
-    P.pin_two_level_vs_uniform(kind, model)
-
-
-@pytest.mark.parametrize("kind", ["shear", "acoustic"])
-def test_two_level_hrr_sigma0(kind):
-    P.pin_two_level_vs_uniform(kind, O.HRR, sigma=0.0)
+def test_interface_relations_after_step(lat, kind, model):
+    P.pin_interface_relations(lat, model, kind)
