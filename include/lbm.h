@@ -135,6 +135,19 @@ int lbm_get_populations(lbm_handle h, int level, double* f, int mem);
  * is not finite.  Synchronous. */
 int lbm_get_totals(lbm_handle h, double mass[2], double momentum[6]);
 
+/* The same totals, bit for bit, from the same kernels, for callers that
+ * cannot allocate device memory (serving loops and harnesses that forbid
+ * hipMalloc): nothing is allocated on any call.  The partial sums go to a
+ * file-scope device array of 8 MiB + 32 B per GPU (4 doubles per block of
+ * 256 nodes, then the 4 final sums), which each GPU the library runs on holds
+ * until the process ends.  Levels of more than 2^26 = 67,108,864 nodes are
+ * rejected with LBM_EINVAL.  Every call on one GPU shares that GPU's array
+ * and overwrites all of it that it reads; calls that overlap on one GPU
+ * (from several host threads) race -- the library's own lock serialises
+ * them within this process.  Returns LBM_EUNSTABLE if any sum is not
+ * finite.  Synchronous. */
+int lbm_get_totals_noalloc(lbm_handle h, double mass[2], double momentum[6]);
+
 /* Node-class map of one level, one byte per node (LBM_C_* / LBM_F_*). */
 int lbm_get_index_maps(lbm_handle h, int level, uint8_t* cls, int mem);
 

@@ -182,6 +182,9 @@ struct GridBase {
   virtual void set_pops(int level, const double* f, bool dev) = 0;
   virtual void get_pops(int level, double* f, bool dev) = 0;
   virtual void totals(double* mass, double* mom) = 0;
+  // The same reduction with its partial sums in `part` (4 doubles per block
+  // of 256 nodes) and its four final sums in `fin`, both device memory.
+  virtual void totals_in(double* mass, double* mom, double* part, double* fin) = 0;
   virtual void tune(int reps, int32_t* out) = 0;
   virtual void set_variants(const int32_t* v) = 0;
   int64_t nodes(int level) const { return level == 0 ? g.Nc : g.Nf; }
@@ -876,7 +879,9 @@ struct Grid final : GridBase {
     HIPCHK(hipStreamSynchronize(stream));
   }
 
-  void totals(double* mass, double* mom) override {
+  void totals(double* mass, double* mom) override { totals_in(mass, mom, part.as<double>(), tot.as<double>()); }
+
+  void totals_in(double* mass, double* mom, double* pbuf, double* fin) override {
     HIPCHK(hipSetDevice(device));
     complete_ring();
     for (int lv = 0; lv < 2; ++lv) {
@@ -886,12 +891,11 @@ struct Grid final : GridBase {
       const int64_t N = nodes(lv);
       const unsigned nb = blocks(N, 256);
       const S* src = lv == 0 ? cur_c() : fineA();
-      hipLaunchKernelGGL((k_totals<LAT, DEV, S>), dim3(nb), dim3(256), 0, stream, src, part.as<double>(), g, lv);
-      hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(256), 0, stream, part.as<double>(), (int64_t)nb,
-                         tot.as<double>());
+      hipLaunchKernelGGL((k_totals<LAT, DEV, S>), dim3(nb), dim3(256), 0, stream, src, pbuf, g, lv);
+      hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(256), 0, stream, pbuf, (int64_t)nb, fin);
       HIPCHK(hipGetLastError());
       double h[4];
-      HIPCHK(hipMemcpyAsync(h, tot.p, sizeof(h), hipMemcpyDeviceToHost, stream));
+      HIPCHK(hipMemcpyAsync(h, fin, sizeof(h), hipMemcpyDeviceToHost, stream));
       HIPCHK(hipStreamSynchronize(stream));
       mass[lv] = h[0];
       for (int d = 0; d < 3; ++d) mom[3 * lv + d] = h[1 + d];
@@ -1736,6 +1740,60 @@ int lbm_get_totals(lbm_handle h, double mass[2], double momentum[6]) {
   int rc = guard(h, [&] {
     HIPCHK(hipDeviceSynchronize());
     h->impl->totals(mass, momentum);
+  });
+  if (rc != LBM_OK) return rc;
+  for (int k = 0; k < 2; ++k)
+    if (!std::isfinite(mass[k])) {
+      h->impl->err = "non-finite mass";
+      return LBM_EUNSTABLE;
+    }
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(momentum[k])) {
+      h->impl->err = "non-finite momentum";
+      return LBM_EUNSTABLE;
+    }
+  return LBM_OK;
+}
+
+// Allocation-free totals.  The partial sums and the final sums live in a
+// file-scope device array instead of buffers of the grid: 4 doubles per block
+// of 256 nodes for up to kNoAllocBlocks blocks (levels of at most 2^26 nodes),
+// then the 4 final sums; 8 MiB + 32 B per GPU, held until the process ends.
+// Host code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address): its device address is looked up once per
+// device, with that device current, and kept in g_scratch_ptr.
+static constexpr int64_t kNoAllocBlocks = (int64_t)1 << 18;
+static constexpr int64_t kNoAllocMaxNodes = kNoAllocBlocks * 256;
+static __device__ __align__(256) double scratch[4 * kNoAllocBlocks + 4];
+static constexpr int kMaxDevices = 64;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (caller holds g_api_mu).
+static double* scratch_on(int device) {
+  if (device < 0 || device >= kMaxDevices) throw LbmError(LBM_EINVAL, "device ordinal beyond the scratch table");
+  if (!g_scratch_ptr[device]) {
+    HIPCHK(hipSetDevice(device));
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw LbmError(LBM_EDEVICE, "hipGetSymbolAddress returned no address for the totals scratch");
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[device];
+}
+
+int lbm_get_totals_noalloc(lbm_handle h, double mass[2], double momentum[6]) {
+  if (!h || !mass || !momentum) return LBM_EINVAL;
+  int rc = guard(h, [&] {
+    const GridBase& gb = *h->impl;
+    const int64_t nmax = std::max(gb.g.Nc, gb.g.has_fine ? gb.g.Nf : (int64_t)0);
+    if (nmax > kNoAllocMaxNodes)
+      throw LbmError(LBM_EINVAL, "lbm_get_totals_noalloc: a level has " + std::to_string(nmax) +
+                                     " nodes; its scratch holds the partial sums of at most " +
+                                     std::to_string(kNoAllocMaxNodes) + " nodes per level");
+    double* p = scratch_on(gb.device);
+    HIPCHK(hipSetDevice(gb.device));
+    HIPCHK(hipDeviceSynchronize());
+    h->impl->totals_in(mass, momentum, p, p + 4 * kNoAllocBlocks);
   });
   if (rc != LBM_OK) return rc;
   for (int k = 0; k < 2; ++k)

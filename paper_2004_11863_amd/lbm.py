@@ -32,7 +32,7 @@ LBM_N_VARIANTS = 4
 
 EXPORTS = (
     "lbm_create_grid", "lbm_destroy", "lbm_set_state", "lbm_step", "lbm_get_macros",
-    "lbm_set_populations", "lbm_get_populations", "lbm_get_totals", "lbm_get_index_maps",
+    "lbm_set_populations", "lbm_get_populations", "lbm_get_totals", "lbm_get_totals_noalloc", "lbm_get_index_maps",
     "lbm_level_dims", "lbm_lattice_info", "lbm_interface_counts", "lbm_interface_tables",
     "lbm_updates_per_step", "lbm_profile_enable", "lbm_kernel_time", "lbm_tune", "lbm_set_variants",
     "lbm_last_error", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove",
@@ -77,6 +77,7 @@ def load(path: str = LIB_PATH):
     L.lbm_set_populations.argtypes = [vp, ip, vp, ip]
     L.lbm_get_populations.argtypes = [vp, ip, vp, ip]
     L.lbm_get_totals.argtypes = [vp, dp, dp]
+    L.lbm_get_totals_noalloc.argtypes = [vp, dp, dp]
     L.lbm_get_index_maps.argtypes = [vp, ip, vp, ip]
     L.lbm_level_dims.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int32)]
     L.lbm_lattice_info.argtypes = [ip, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -226,6 +227,13 @@ def lbm_get_totals(h):
     mass = (ctypes.c_double * 2)()
     mom = (ctypes.c_double * 6)()
     _check(load().lbm_get_totals(h, mass, mom), h)
+    return np.array(mass[:]), np.array(mom[:]).reshape(2, 3)
+
+
+def lbm_get_totals_noalloc(h):
+    mass = (ctypes.c_double * 2)()
+    mom = (ctypes.c_double * 6)()
+    _check(load().lbm_get_totals_noalloc(h, mass, mom), h)
     return np.array(mass[:]), np.array(mom[:]).reshape(2, 3)
 
 
