@@ -102,6 +102,7 @@ def lib():
         L.orc_strain_f2c.restype = ctypes.c_double
         L.orc_set_mutation.argtypes = [ctypes.c_int]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_sensors.argtypes = [vp, ctypes.c_int, ctypes.c_double, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -286,6 +287,20 @@ class Grid:
         w = np.zeros((n, 16))
         lib().orc_ring_stencils(self._h, node.ctypes.data, np_.ctypes.data, pts.ctypes.data, w.ctypes.data)
         return node, np_, pts, w
+
+    def sensors(self, level: int, thr: float):
+        """NH-sensor flags of a level's last iteration (bit 0 SpuriousAc, bit 1
+        SpuriousS, bit 2 SpuriousG; Sec. 7) and the quantities they test: the
+        divergence product, the curl product and the norm of the ghost part
+        of the non-equilibrium populations."""
+        N = self.nodes(level)
+        flags = np.zeros(N, np.uint8)
+        dp, cp, gn = np.zeros(N), np.zeros(N), np.zeros(N)
+        rc = lib().orc_sensors(self._h, level, float(thr), flags.ctypes.data, dp.ctypes.data, cp.ctypes.data,
+                               gn.ctypes.data)
+        if rc != 0:
+            raise ValueError("sensors need a level that exists and a step taken")
+        return flags, dp, cp, gn
 
     def totals(self):
         mass = np.zeros(2)

@@ -393,6 +393,9 @@ typedef struct {
   long NT;
   long *tn_f, *tn_c;
   long steps;
+  /* NH sensors (Sec. 7): velocities of the iteration before the last one
+   * of each level (coarse: t, fine: t+1/2, for a step t -> t+1) */
+  double *u_c_prev, *u_f_prev;
 } ogrid;
 
 static long cidx(const ogrid* g, int x, int y, int z) {
@@ -460,6 +463,7 @@ void orc_destroy(void* hp) {
   free(g->rnode); free(g->rnp); free(g->rpt); free(g->rw);
   free(g->r_rho); free(g->r_u); free(g->r_f); free(g->r_S);
   free(g->tn_f); free(g->tn_c);
+  free(g->u_c_prev); free(g->u_f_prev);
   free(g);
 }
 
@@ -502,6 +506,7 @@ void* orc_create(int lat, int model, const int* n, const int* lo, const int* hi,
   g->fc_pre = calloc((size_t)Q * g->Nc, sizeof(double));
   g->rho_c = calloc((size_t)g->Nc, sizeof(double));
   g->u_c = calloc((size_t)3 * g->Nc, sizeof(double));
+  g->u_c_prev = calloc((size_t)3 * g->Nc, sizeof(double));
   g->cls_c = calloc((size_t)g->Nc, 1);
   for (long i = 0; i < g->Nc; ++i) {
     int c[3];
@@ -515,6 +520,7 @@ void* orc_create(int lat, int model, const int* n, const int* lo, const int* hi,
   g->ff_half = calloc((size_t)Q * g->Nf, sizeof(double));
   g->rho_f = calloc((size_t)g->Nf, sizeof(double));
   g->u_f = calloc((size_t)3 * g->Nf, sizeof(double));
+  g->u_f_prev = calloc((size_t)3 * g->Nf, sizeof(double));
   g->cls_f = calloc((size_t)g->Nf, 1);
   for (long i = 0; i < g->Nf; ++i) {
     int j[3];
@@ -938,6 +944,7 @@ static void ring_reconstruct_collide(ogrid* g, int half, double* dst) {
 
 static void uniform_step(ogrid* g) {
   long N = g->Nc;
+  memcpy(g->u_c_prev, g->u_c, sizeof(double) * 3 * (size_t)N);
 #pragma omp parallel for schedule(static)
   for (long i = 0; i < N; ++i) stream_coarse_node(g, i);
 #pragma omp parallel for schedule(static)
@@ -953,6 +960,8 @@ static void two_level_step(ogrid* g) {
   const long Nc = g->Nc, Nf = g->Nf, NH = g->NH;
   const int hrr = (g->model == MOD_HRR);
 
+  /* velocities of the coarse iteration t, kept for the NH sensors */
+  memcpy(g->u_c_prev, g->u_c, sizeof(double) * 3 * (size_t)Nc);
   /* Asynchronous iteration: fine t -> t+1/2, coarse t -> t+1. */
   /* (a) propagation of the coarse nodes other than TN^c (and covered) */
 #pragma omp parallel for schedule(static)
@@ -1014,6 +1023,9 @@ static void two_level_step(ogrid* g) {
   /* (g, h, i) ring populations and strain rate at t+1/2, ring collision */
   ring_reconstruct_collide(g, 1, g->ff_half);
 
+  /* velocities of the fine iteration t+1/2 (ring included), kept for the
+   * NH sensors */
+  memcpy(g->u_f_prev, g->u_f, sizeof(double) * 3 * (size_t)Nf);
   /* Synchronous iteration: fine t+1/2 -> t+1. */
   /* (a) propagation of the fine middle nodes */
 #pragma omp parallel for schedule(static)
@@ -1091,6 +1103,121 @@ int orc_step(void* hp, int nsteps) {
     if (g->has_fine) two_level_step(g);
     else uniform_step(g);
     g->steps++;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Non-hydrodynamic-mode sensors of Sec. 7, evaluated on the last iteration
+ * of a level after a step (coarse: t+1 against t; fine: t+1 against t+1/2;
+ * uniform grid: t+1 against t).
+ *   bit 0, SpuriousAc (eq sensorSpuriousAc): div u(previous) * div u(last) < 0
+ *   bit 1, SpuriousS  (eq sensorSpuriousS):  curl u(previous) . curl u(last) < 0
+ *          Reading: in 3D the product of the two curl vectors is their dot
+ *          product; in 2D the curl is the scalar d_x u_y - d_y u_x.
+ *   bit 2, SpuriousG  (eqs fneqSplit, reguProceduref1S, sensorSpuriousG):
+ *          ||f1 - f1,S|| > thr and neither bit above, with f1 = f - f0(rho, u)
+ *          of the pre-collision populations of the last iteration and f1,S
+ *          their projection on the second-order Hermite polynomials.
+ *          Reading: the paper's "> 0" is taken as "> thr", a threshold the
+ *          caller states above the rounding of the populations.
+ * A product exactly zero gives 0 (the paper's ">= 0 -> 0").  Derivatives
+ * are centred differences in the level's lattice units.  Nodes whose
+ * stencil or pre-collision state is not part of the level's evolution get
+ * 0: coarse TN^c and covered nodes (their neighbours include covered
+ * nodes) and the fine ring (rebuilt by interpolation, not streamed).
+ * The previous iteration's velocities exist once a step has been taken. */
+static void div_curl(int D, const double* u, long N, const long* nb, double* div, double* curl) {
+  /* nb[2a], nb[2a+1]: node indices at x + e_a, x - e_a */
+  double gr[3][3] = {{0}};
+  for (int a = 0; a < D; ++a)
+    for (int b = 0; b < D; ++b) gr[a][b] = (u[b * N + nb[2 * a]] - u[b * N + nb[2 * a + 1]]) / 2.0;
+  *div = 0.0;
+  for (int a = 0; a < D; ++a) *div += gr[a][a];
+  if (D == 2) {
+    curl[0] = gr[0][1] - gr[1][0];
+    curl[1] = curl[2] = 0.0;
+  } else {
+    curl[0] = gr[1][2] - gr[2][1];
+    curl[1] = gr[2][0] - gr[0][2];
+    curl[2] = gr[0][1] - gr[1][0];
+  }
+}
+
+int orc_sensors(void* hp, int level, double thr, uint8_t* flags, double* div_prod, double* curl_prod,
+                double* g_norm) {
+  ogrid* g = (ogrid*)hp;
+  if (level == 1 && !g->has_fine) return -1;
+  if (g->steps == 0) return -2;
+  const int D = g->D, Q = g->Q;
+  const long N = level == 0 ? g->Nc : g->Nf;
+  const double* up = level == 0 ? g->u_c_prev : g->u_f_prev;
+  const double* uc = level == 0 ? g->u_c : g->u_f;
+  const double* fp = level == 0 ? g->fc_pre : g->ff_pre;
+  const double* fpost = level == 0 ? g->fc : g->ff;
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < N; ++i) {
+    flags[i] = 0;
+    if (div_prod) div_prod[i] = 0.0;
+    if (curl_prod) curl_prod[i] = 0.0;
+    if (g_norm) g_norm[i] = 0.0;
+    int c[3];
+    long nb[6] = {i, i, i, i, i, i};
+    if (level == 0) {
+      if (g->has_fine && g->cls_c[i] != C_MIDDLE && g->cls_c[i] != C_TFC) continue;
+      cco(g, i, c);
+      for (int a = 0; a < D; ++a) {
+        int p[3] = {c[0], c[1], c[2]}, q[3] = {c[0], c[1], c[2]};
+        p[a]++;
+        q[a]--;
+        nb[2 * a] = cidx(g, p[0], p[1], p[2]);
+        nb[2 * a + 1] = cidx(g, q[0], q[1], q[2]);
+      }
+    } else {
+      if (g->cls_f[i] != F_MIDDLE && g->cls_f[i] != F_TNF) continue;
+      fco(g, i, c);
+      for (int a = 0; a < D; ++a) {
+        int p[3] = {c[0], c[1], c[2]}, q[3] = {c[0], c[1], c[2]};
+        p[a]++;
+        q[a]--;
+        nb[2 * a] = fidx(g, p[0], p[1], p[2]);
+        nb[2 * a + 1] = fidx(g, q[0], q[1], q[2]);
+      }
+    }
+    double dp, dc, cp[3], cc[3];
+    div_curl(D, up, N, nb, &dp, cp);
+    div_curl(D, uc, N, nb, &dc, cc);
+    const double pd = dp * dc;
+    const double pc = cp[0] * cc[0] + cp[1] * cc[1] + cp[2] * cc[2];
+    const int ac = pd < 0.0, sp = pc < 0.0;
+    /* pre-collision populations of the last iteration: the streamed state
+     * (uniform grid: the post-collision state of the step before is not
+     * kept, so the pre-collision one is fc_pre as well) */
+    (void)fpost;
+    double f[MAXQ], f0[MAXQ], r, uu[3];
+    for (int q = 0; q < Q; ++q) f[q] = fp[q * N + i];
+    moments_L(&g->L, f, 1, &r, uu);
+    feq_L(&g->L, r, uu, f0);
+    double f1[MAXQ], a2[3][3] = {{0}};
+    for (int q = 0; q < Q; ++q) f1[q] = f[q] - f0[q];
+    for (int a = 0; a < D; ++a)
+      for (int b = 0; b < D; ++b)
+        for (int q = 0; q < Q; ++q) a2[a][b] += g->L.H2[q][a][b] * f1[q];
+    double nrm = 0.0;
+    for (int q = 0; q < Q; ++q) {
+      double hs = 0.0;
+      for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b) hs += g->L.H2[q][a][b] * a2[a][b];
+      const double f1s = g->L.w[q] * hs / (2.0 * CS2 * CS2);
+      const double gq = f1[q] - f1s;
+      nrm += gq * gq;
+    }
+    nrm = sqrt(nrm);
+    const int gs = (nrm > thr) && !ac && !sp;
+    flags[i] = (uint8_t)(ac | (sp << 1) | (gs << 2));
+    if (div_prod) div_prod[i] = pd;
+    if (curl_prod) curl_prod[i] = pc;
+    if (g_norm) g_norm[i] = nrm;
   }
   return 0;
 }
