@@ -4,19 +4,22 @@ MI355X.
 
 A step is one coarse time step of the two-level scheme (one coarse update and
 two fine substeps with the full interface treatment).  The default workload
-is the D2Q9 two-level problem with a 4096^2 periodic coarse grid and a
-4097 x 2049-node fine band (patch [1024, 3072] x [1536, 2560] in coarse
-vertices), recursive regularised collision, tau_c = 0.51, populations stored
-in FP32 as deviations from the lattice weights; input: a convected vortex
-plus a Gaussian acoustic pulse (amplitude 1e-3), seeded.
+is the D3Q19 two-level problem with a 384^3 periodic coarse grid and a
+centred 385^3-node fine cube (patch [96, 288]^3 in coarse vertices),
+recursive regularised collision, tau_c = 0.51, populations stored in FP32 as
+deviations from the lattice weights; input: a Gaussian acoustic pulse
+(amplitude 1e-3) near the interface on a uniform flow at Mach 0.1, seeded.
 
 Prints ONE JSON line.  value = MLUPS = (evolving coarse nodes + 2 x fine
 nodes) x steps / seconds / 1e6, inputs resident in HBM.  The roofline object
-prices the dominant kernel (the fine-level pull-stream + collide) with its
-algorithmic bytes (one read and one write of Q populations per node) over its
-mean launch duration measured with HIP events on its launch stream during
-the timed region.  cpu_baseline times the FP64 CPU oracle on a bounded sample
-of the same workload.
+prices the dominant kernel (the fine-level pull-stream + collide) with the
+bytes it must move -- one read and one write of the Q populations of every
+node it updates, once per launch, also when one launch performs both fine
+substeps -- over its mean launch duration measured with HIP events on its
+launch stream during the timed region.  cpu_baseline times the FP64 CPU
+oracle on a bounded sample of the same workload (for the D3Q19 grid: the
+64^3 subcase of the same configuration) and error_vs_oracle compares the GPU
+run of that sample with it.
 """
 from __future__ import annotations
 
@@ -39,18 +42,21 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=1000)
     p.add_argument("--warmup", type=int, default=20)
-    p.add_argument("--workload", default="d2q9-4096", choices=["d2q9-4096", "d3q19-384", "d2q9-1024"])
+    p.add_argument("--workload", default="d3q19-384", choices=["d3q19-384", "d2q9-4096", "d2q9-1024"])
     p.add_argument("--collision", default="RR", choices=["BGK", "RR", "HRR"])
     p.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     p.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    p.add_argument("--cpu-steps", type=int, default=24,
-                   help="coarse steps of the CPU oracle sample (about 10 s on 16 host cores at D2Q9 4096^2)")
+    p.add_argument("--cpu-steps", type=int, default=None,
+                   help="coarse steps of the CPU oracle sample (default: 120 of the D3Q19 64^3 subcase, "
+                        "24 of the D2Q9 grids; about 10-20 s on 16 host cores)")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-instances measurement")
     p.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
     p.add_argument("--batch-n", type=int, default=256)
     p.add_argument("--batch-steps", type=int, default=200)
-    p.add_argument("--serve-n", type=int, default=16)
+    p.add_argument("--serve-n", type=int, default=16, help="arrivals of the full-size serving trace")
+    p.add_argument("--serve-small-n", type=int, default=128, help="arrivals of the small-grid serving trace")
+    p.add_argument("--serve-reps", type=int, default=3, help="repeats of the small-grid trace (spread)")
     p.add_argument("--copy-probe", type=int, default=0,
                    help="only run a plain device copy of this many MiB (counter calibration)")
     return p.parse_args()
@@ -71,7 +77,7 @@ def kernel_label(D, collision, variants=None):
     v = list(variants) if variants is not None else [0, 0, 0, 0]
     if D == 2 and collision != "HRR":
         return ("k_fine2: both fine substeps of a coarse step (pull + collide twice, the t+1/2 state in LDS); "
-                "algorithmic bytes count 2 Q P_b per lattice update, 2 updates per node per launch")
+                "one read and one write of every fine node's populations per launch, 2 updates per node")
     if collision == "HRR" and D == 2:
         return "k_hrr2: one H-RR fine substep in one pass (pull, velocities of the tile in LDS, strain rate, collide)"
     if collision == "HRR":
@@ -79,8 +85,36 @@ def kernel_label(D, collision, variants=None):
             return "k_hrr3: one H-RR fine substep in one marching pass (velocity planes in LDS, strain rate, collide)"
         return "k_collide_hrr: fine-level pull + H-RR collide (second pass)"
     if v[1] >= 2:
-        return "k_fine3: both fine substeps of a coarse step in one marching pass (2 updates per node per launch)"
+        return ("k_fine3: both fine substeps of a coarse step in one marching pass; one read and one write of "
+                "every fine node's populations per launch, 2 updates per node")
     return "k_stream: fine-level pull + collide"
+
+
+def fine_middle_nodes(geom):
+    """Fine nodes the bulk fine kernels update (the patch without its ring)."""
+    m = 1
+    for d in range(geom.D):
+        m *= 2 * (geom.hi[d] - geom.lo[d]) + 1 - 2
+    return m
+
+
+def roofline_of(kt, Q, pb, geom):
+    """Roofline figures of the timed fine kernel from (launches, mean ms,
+    updates per launch): bytes it must move = one read + one write of Q
+    populations per node it updates, once per launch (a launch that does
+    both fine substeps updates every node twice but moves it once)."""
+    launches, mean_ms, updates = kt
+    nodes = fine_middle_nodes(geom)
+    per_node = 2 * Q * pb
+    moved = per_node * nodes
+    achieved = moved / (mean_ms * 1e-3) / 1e9
+    upd_eq = per_node * updates / (mean_ms * 1e-3) / 1e9
+    return {"achieved": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_launch": moved,
+            "nodes_per_launch": nodes, "updates_per_launch": updates, "launches": launches,
+            "mean_launch_ms": mean_ms,
+            # 2 Q P_b per lattice update: above `achieved` when a launch
+            # updates each node twice
+            "update_equivalent_GBs": round(upd_eq, 1)}
 
 
 def workload(name, seed=0):
@@ -148,6 +182,15 @@ def stored_traffic(kernel_hash, key, variant=None):
     return None if e is None else e.get("hbm_bytes_per_launch")
 
 
+def cpu_sample(name, seed=0):
+    """The workload the CPU oracle is timed on: the D3Q19 grid's 64^3
+    subcase (same configuration at 64^3), or the D2Q9 grid itself."""
+    from paper_2004_11863_amd import inputs as I
+    if name == "d3q19-384":
+        return I.config3(seed=seed, n=64), "D3Q19 64^3 subcase of the same configuration (patch [16, 48]^3)"
+    return workload(name, seed), "the same grid"
+
+
 def cpu_baseline(wl, collision, steps):
     import oracle as O
     from paper_2004_11863_amd import inputs as I
@@ -171,13 +214,15 @@ def error_vs_oracle(wl, collision, precision, steps, ref):
     import numpy as np
     grid = make_gpu(wl, collision, precision)
     grid.step(steps)
-    err = {"rho_maxabs": 0.0, "u_relL2": 0.0, "steps": steps}
+    err = {"rho_maxabs": 0.0, "u_relL2": 0.0, "steps": steps,
+           "grid": "x".join(str(x) for x in wl.geom.n[:wl.geom.D])}
     for lv in (0, 1):
         r1, u1 = grid.get_macros(lv)
         r0, u0 = ref.get_macros(lv)
         err["rho_maxabs"] = max(err["rho_maxabs"], float(np.abs(r1 - r0).max()))
         err["u_relL2"] = max(err["u_relL2"], float(np.linalg.norm(u1 - u0) / np.linalg.norm(u0)))
     grid.close()
+    err["within_bar"] = bool(err["rho_maxabs"] < 1e-5 and err["u_relL2"] < 1e-4)
     return err
 
 
@@ -234,13 +279,10 @@ def batched(n_inst, steps):
             "speedup": round((ups * steps / dt) / (ups * loop_steps / dl), 2)}
 
 
-def serve_trace(n_req, rate, realtime=True, seed=5, **shape):
-    """Served (continuous batching) and FIFO one-at-a-time runs of one trace;
-    latency statistics and aggregate throughput of each."""
+def _served(reqs, realtime=True):
+    """One run of the continuous-batching server over prepared requests."""
     import torch
     from paper_2004_11863_amd import serve
-    reqs = [r.prepare() for r in serve.poisson_trace(n_req, rate=rate, seed=seed, **shape)]
-    work = sum(r.updates() for r in reqs)
     free, total = torch.cuda.mem_get_info()
     ex = serve.DeviceExecutor(capacity=64)
     srv = serve.Server(ex, int(0.8 * free), policy="srpt")
@@ -249,53 +291,101 @@ def serve_trace(n_req, rate, realtime=True, seed=5, **shape):
     span = time.perf_counter() - t0
     ex.close()
     torch.cuda.empty_cache()
-    st = serve.latency_stats(done)
-    reqs2 = [r.prepare() for r in serve.poisson_trace(n_req, rate=rate, seed=seed, **shape)]
+    return done, span
+
+
+def _fifo(reqs, realtime=True):
+    import torch
+    from paper_2004_11863_amd import serve
     t0 = time.perf_counter()
-    done2 = serve.fifo_loop(reqs2, realtime=realtime)
-    span2 = time.perf_counter() - t0
-    st2 = serve.latency_stats(done2)
+    done = serve.fifo_loop(reqs, realtime=realtime)
+    span = time.perf_counter() - t0
     torch.cuda.empty_cache()
-    return {"served": {"p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3),
-                       "aggregate_mlups": round(work / span / 1e6, 1), "makespan_s": round(span, 3),
-                       "fp64_fallbacks": sum(r.fell_back for r in done)},
-            "fifo_per_instance": {"p50_s": round(st2["p50_s"], 3), "p99_s": round(st2["p99_s"], 3),
-                                  "aggregate_mlups": round(work / span2 / 1e6, 1), "makespan_s": round(span2, 3)},
-            "total_updates": work, "first_arrival_s": reqs[0].arrival, "last_arrival_s": reqs[-1].arrival}
+    return done, span
 
 
-def serving(n_req, rate=200.0, utilization=0.7):
-    """A seeded Poisson stream (mean 200 requests/s) mixing D2Q9 (sides
-    128-2048) and D3Q19 (sides 64-256) two-level problems with 100-2000 coarse
-    steps, FP32 with 10 % flagged FP64, RR; first n_req arrivals.  Initial
-    fields are sampled before the trace starts (client side).  Continuous
-    batching (size-class groups, shortest remaining time first with backfill)
-    against the plain FIFO per-instance loop on the same trace; then the same
-    requests arriving at the rate that offers `utilization` of the measured
-    served throughput (the request mix is the same: the seed fixes it); and
-    64 arrivals of the same generator with small grids."""
+def _run_stats(done, span, work):
+    from paper_2004_11863_amd import serve
+    st = serve.latency_stats(done)
+    return {"p50_s": round(st["p50_s"], 3), "p99_s": round(st["p99_s"], 3), "max_s": round(st["max_s"], 3),
+            "n": st["n"], "aggregate_mlups": round(work / span / 1e6, 1), "makespan_s": round(span, 3),
+            "fp64_fallbacks": sum(getattr(r, "fell_back", False) for r in done)}
+
+
+def serve_trace(n_req, rate, realtime=True, seed=5, reps=1, **shape):
+    """Served (continuous batching) and FIFO one-at-a-time runs of one trace,
+    `reps` times each, alternating; latency statistics and aggregate
+    throughput of every run."""
+    from paper_2004_11863_amd import serve
+    served, fifo = [], []
+    work = first = last = None
+    for _ in range(reps):
+        reqs = [r.prepare() for r in serve.poisson_trace(n_req, rate=rate, seed=seed, **shape)]
+        work = sum(r.updates() for r in reqs)
+        first, last = reqs[0].arrival, reqs[-1].arrival
+        done, span = _served(reqs, realtime)
+        served.append(_run_stats(done, span, work))
+        reqs = [r.prepare() for r in serve.poisson_trace(n_req, rate=rate, seed=seed, **shape)]
+        done, span = _fifo(reqs, realtime)
+        fifo.append(_run_stats(done, span, work))
+    return {"served_runs": served, "fifo_runs": fifo, "total_updates": work, "first_arrival_s": first,
+            "last_arrival_s": last}
+
+
+def _spread(runs, key):
+    v = sorted(r[key] for r in runs)
+    return {"min": v[0], "median": v[len(v) // 2], "max": v[-1]}
+
+
+def serving(n_full, n_small, reps, rate=200.0, utilization=0.7):
+    """A seeded Poisson stream (mean 200 requests/s) of two-level problems,
+    half D2Q9 and half D3Q19, 100-2000 coarse steps each, FP32 with 10 %
+    flagged FP64, RR.  Initial fields are sampled before the trace starts
+    (client side).  Continuous batching (size-class groups, shortest
+    remaining time first with backfill) against the plain FIFO per-instance
+    loop on the same requests.
+
+    small_requests: n_small arrivals with small grids (D2Q9 sides 64-512,
+    D3Q19 sides 32-96), where per-request launches and host work matter,
+    repeated `reps` times for the spread, then the same requests arriving at
+    the rate that offers `utilization` of the served throughput.
+    full_size: the first n_full arrivals of the full-size generator (D2Q9
+    sides 128-2048, D3Q19 sides 64-256), one run each; with so few arrivals
+    its p99 is close to the maximum."""
     import inspect
     from paper_2004_11863_amd import serve
     SERVER_DEFAULTS = {k: v.default for k, v in inspect.signature(serve.Server).parameters.items()}
-    sat = serve_trace(n_req, rate)
-    work = sat["total_updates"]
-    offered = work / (sat["last_arrival_s"] - sat["first_arrival_s"] + 1e-9)
-    out = {"requests": n_req, "rate_per_s": rate, "total_updates": work,
-           "policy": "srpt", "slice_s": SERVER_DEFAULTS["slice_s"], "backfill": SERVER_DEFAULTS["backfill"],
-           "served": sat["served"], "fifo_per_instance": sat["fifo_per_instance"],
-           "offered_mlups": round(offered / 1e6, 1), "saturated": bool(offered > sat["served"]["aggregate_mlups"] * 1e6)}
-    capacity = sat["served"]["aggregate_mlups"] * 1e6
-    mean_work = work / n_req
-    rate_u = utilization * capacity / mean_work
-    sub = serve_trace(n_req, rate_u)
-    out["sub_saturation"] = {"utilization_target": utilization, "rate_per_s": round(rate_u, 4),
-                             "served": sub["served"], "fifo_per_instance": sub["fifo_per_instance"]}
-    # the same generator with small grids (64 requests: D2Q9 sides 64-512,
-    # D3Q19 sides 32-96), where per-request launches dominate and batching pays
-    small = serve_trace(64, rate, seed=11, d2_side=(64, 512), d3_side=(32, 96))
-    out["small_requests"] = {"requests": 64, "rate_per_s": rate, "d2_side": [64, 512], "d3_side": [32, 96],
-                             "seed": 11, "total_updates": small["total_updates"],
-                             "served": small["served"], "fifo_per_instance": small["fifo_per_instance"]}
+    out = {"rate_per_s": rate, "policy": "srpt", "slice_s": SERVER_DEFAULTS["slice_s"],
+           "backfill": SERVER_DEFAULTS["backfill"]}
+    shape = dict(d2_side=(64, 512), d3_side=(32, 96))
+    sm = serve_trace(n_small, rate, seed=11, reps=reps, **shape)
+    work = sm["total_updates"]
+    offered = work / (sm["last_arrival_s"] - sm["first_arrival_s"] + 1e-9)
+    srv_thr, fifo_thr = _spread(sm["served_runs"], "aggregate_mlups"), _spread(sm["fifo_runs"], "aggregate_mlups")
+    small = {"requests": n_small, "seed": 11, "d2_side": [64, 512], "d3_side": [32, 96], "total_updates": work,
+             "offered_mlups": round(offered / 1e6, 1), "reps": reps,
+             "served_runs": sm["served_runs"], "fifo_runs": sm["fifo_runs"],
+             "served_mlups_spread": srv_thr, "fifo_mlups_spread": fifo_thr,
+             "served_p50_spread": _spread(sm["served_runs"], "p50_s"),
+             "served_p99_spread": _spread(sm["served_runs"], "p99_s"),
+             "fifo_p50_spread": _spread(sm["fifo_runs"], "p50_s"),
+             "fifo_p99_spread": _spread(sm["fifo_runs"], "p99_s"),
+             "throughput_ratio_median": round(srv_thr["median"] / fifo_thr["median"], 3),
+             # the served and FIFO throughput ranges over the repeats overlap
+             "throughput_tie": bool(srv_thr["min"] <= fifo_thr["max"] and fifo_thr["min"] <= srv_thr["max"])}
+    small["saturated"] = bool(offered > srv_thr["median"] * 1e6)
+    rate_u = utilization * srv_thr["median"] * 1e6 / (work / n_small)
+    sub = serve_trace(n_small, rate_u, seed=11, **shape)
+    small["sub_saturation"] = {"utilization_target": utilization, "rate_per_s": round(rate_u, 4),
+                               "served": sub["served_runs"][0], "fifo_per_instance": sub["fifo_runs"][0]}
+    out["small_requests"] = small
+    print(f"# serving small: {small}", file=sys.stderr, flush=True)
+    full = serve_trace(n_full, rate, seed=5)
+    fw = full["total_updates"]
+    out["full_size"] = {"requests": n_full, "seed": 5, "d2_side": [128, 2048], "d3_side": [64, 256],
+                        "total_updates": fw,
+                        "offered_mlups": round(fw / (full["last_arrival_s"] - full["first_arrival_s"] + 1e-9) / 1e6, 1),
+                        "served": full["served_runs"][0], "fifo_per_instance": full["fifo_runs"][0]}
     return out
 
 
@@ -352,11 +442,11 @@ def main():
     dt, kt = timed_run(grid, args.steps, args.warmup, profile=True)
     mlups = ups * args.steps / dt / 1e6
     m, p = grid.totals()  # finite check
-    launches, mean_ms, nodes = kt
     Q = grid.Q
     pb = 4 if args.precision == "fp32" else 8
-    alg_bytes = 2 * Q * pb * nodes
-    achieved = alg_bytes / (mean_ms * 1e-3) / 1e9
+    g = wl.geom
+    D = g.D
+    roof = roofline_of(kt, Q, pb, g)
     variants = getattr(grid, "variants", None)
     khash = kernel_source_hash()
     key = f"{args.workload}/{args.collision}/{args.precision}"
@@ -365,8 +455,7 @@ def main():
     del grid
     torch.cuda.empty_cache()
 
-    g = wl.geom
-    D = g.D
+    mean_ms = roof["mean_launch_ms"]
     result = {
         "metric": "MLUPS & % HBM roofline, FP32 vs FP64 two-level; batched p50/p99 solve latency",
         "value": round(mlups, 1),
@@ -397,42 +486,39 @@ def main():
             "updates_per_step": ups,
             "parallelism": "single GPU",
         },
-        "roofline": {
+        "roofline": dict({
             "bound": "hbm",
             "kernel": kernel_label(D, args.collision, variants),
-            "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "bytes_per_launch": alg_bytes,
-            "updates_per_launch": nodes,
-            "launches": launches,
-            "mean_launch_ms": mean_ms,
             # HBM bandwidth the kernel actually drew (counter traffic over the
-            # live launch time); differs from `achieved` when one launch
-            # performs several lattice updates per node
+            # live launch time)
             "hbm_achieved": None if traffic is None else round(traffic / (mean_ms * 1e-3) / 1e9, 1),
             "hbm_frac": None if traffic is None else round(traffic / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             # the same against the faster of two device-to-device copies
             # measured in this run (hipMemcpy through torch, and the
             # library's streaming copy kernel), bytes read + written
             "copy_GBs": {"memcpy": round(copy_gbs[0], 1), "streaming_kernel": round(copy_gbs[1], 1)},
-            "hbm_frac_of_copy": None if traffic is None else round(traffic / (mean_ms * 1e-3) / 1e9 / max(copy_gbs), 4),
-        },
+            "frac_of_copy": round(roof["achieved"] / max(copy_gbs), 4),
+        }, **roof),
+        # whole step against the per-update roofline (2 Q P_b bytes per lattice update at 8 TB/s)
+        "step_frac_of_update_roofline": round(mlups * 1e6 * 2 * Q * pb / 1e9 / HBM_PEAK_GBS, 4),
         "kernel_variants": variants,
         "totals_finite": bool(all(map(lambda v: v == v, list(m) + list(p.ravel())))),
         "kernel_source_hash": khash,
     }
+    print(f"# headline: {result['value']} MLUPS, {result['ms_per_step']:.3f} ms/step, roofline "
+          f"{result['roofline']['frac']}", file=sys.stderr, flush=True)
 
     if not args.no_extra:
         extra = {}
         for name, wname, col, prec, steps in (
-                ("d2q9_4096_rr_fp64", "d2q9-4096", "RR", "fp64", 200),
-                ("d2q9_4096_hrr_fp32", "d2q9-4096", "HRR", "fp32", 200),
-                ("d3q19_384_rr_fp32", "d3q19-384", "RR", "fp32", 60),
                 ("d3q19_384_rr_fp64", "d3q19-384", "RR", "fp64", 30),
-                ("d3q19_384_hrr_fp32", "d3q19-384", "HRR", "fp32", 40)):
+                ("d3q19_384_hrr_fp32", "d3q19-384", "HRR", "fp32", 40),
+                ("d2q9_4096_rr_fp32", "d2q9-4096", "RR", "fp32", 400),
+                ("d2q9_4096_rr_fp64", "d2q9-4096", "RR", "fp64", 200),
+                ("d2q9_4096_hrr_fp32", "d2q9-4096", "HRR", "fp32", 200)):
             if (wname, col, prec) == (args.workload, args.collision, args.precision):
                 continue
             w2 = workload(wname)
@@ -440,13 +526,16 @@ def main():
             u2 = gr.updates_per_step()
             d2, k2 = timed_run(gr, steps, 5, profile=True)
             q2, pb2 = gr.Q, (4 if prec == "fp32" else 8)
-            a2 = 2 * q2 * pb2 * k2[2] / (k2[1] * 1e-3) / 1e9
-            extra[name] = {"mlups": round(u2 * steps / d2 / 1e6, 1), "steps": steps,
+            r2 = roofline_of(k2, q2, pb2, w2.geom)
+            mlu = u2 * steps / d2 / 1e6
+            extra[name] = {"mlups": round(mlu, 1), "steps": steps,
                            "ms_per_step": d2 / steps * 1e3,
-                           "fine_kernel": kernel_label(2 if wname.startswith("d2q9") else 3, col,
-                                                       getattr(gr, "variants", None)).split(":")[0],
+                           "fine_kernel": kernel_label(w2.geom.D, col, getattr(gr, "variants", None)).split(":")[0],
                            "variants": getattr(gr, "variants", None),
-                           "fine_kernel_alg_GBs": round(a2, 1), "fine_kernel_alg_frac": round(a2 / HBM_PEAK_GBS, 4)}
+                           "fine_kernel_GBs": r2["achieved"], "fine_kernel_frac": r2["frac"],
+                           "fine_kernel_update_equivalent_GBs": r2["update_equivalent_GBs"],
+                           "fine_kernel_mean_ms": r2["mean_launch_ms"],
+                           "step_frac_of_update_roofline": round(mlu * 1e6 * 2 * q2 * pb2 / 1e9 / HBM_PEAK_GBS, 4)}
             gr.close()
             del gr, w2
             torch.cuda.empty_cache()
@@ -457,15 +546,17 @@ def main():
         result["batched"] = batched(args.batch_n, args.batch_steps)
         print(f"# batched: {result['batched']}", file=sys.stderr, flush=True)
     if not args.no_serve:
-        result["serving"] = serving(args.serve_n)
+        result["serving"] = serving(args.serve_n, args.serve_small_n, args.serve_reps)
         print(f"# serving: {result['serving']}", file=sys.stderr, flush=True)
 
     if not args.no_cpu:
-        v, cores, t, ref = cpu_baseline(wl, args.collision, args.cpu_steps)
+        sw, what = cpu_sample(args.workload)
+        steps = args.cpu_steps if args.cpu_steps is not None else (120 if D == 3 else 24)
+        v, cores, t, ref = cpu_baseline(sw, args.collision, steps)
         result["cpu_baseline"] = {"value": round(v, 2), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-                                  "sample": "%d coarse steps of the same grid and input in FP64 (%.1f s)"
-                                            % (args.cpu_steps, t)}
-        result["error_vs_oracle"] = error_vs_oracle(wl, args.collision, args.precision, args.cpu_steps, ref)
+                                  "sample": "%d coarse steps of the %s in FP64 (%.1f s)" % (steps, what, t)}
+        result["error_vs_oracle"] = error_vs_oracle(sw, args.collision, args.precision, steps, ref)
+        result["error_vs_oracle"]["sample"] = what
         del ref
     print(json.dumps(result), flush=True)
 

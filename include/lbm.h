@@ -148,6 +148,41 @@ int lbm_get_totals(lbm_handle h, double mass[2], double momentum[6]);
  * finite.  Synchronous. */
 int lbm_get_totals_noalloc(lbm_handle h, double mass[2], double momentum[6]);
 
+/* Non-hydrodynamic-mode sensors (Sec. 7 of the paper).  lbm_sensors_enable
+ * (on = 1) makes every following step record what the sensors compare: the
+ * velocities of the iteration before the step's last one (coarse: t; fine:
+ * t+1/2) and the fine t+1/2 state (the fine substeps then run as two
+ * launches).  Off by default; costs two extra passes over the populations
+ * per step and 2 (1 + D) doubles per node of device memory.
+ * lbm_sensors(level) then returns, for the last step, one byte per node of
+ * the level (x fastest):
+ *   bit 0 SpuriousAc: div u(previous) * div u(last) < 0  (eq sensorSpuriousAc)
+ *   bit 1 SpuriousS:  curl u(previous) . curl u(last) < 0 (eq sensorSpuriousS;
+ *                     3D: dot product of the curl vectors)
+ *   bit 2 SpuriousG:  ||f1 - f1,S|| > threshold and neither bit above
+ *                     (eqs fneqSplit, reguProceduref1S, sensorSpuriousG), with
+ *                     f1 = f - f0(rho, u) of the last iteration's pre-collision
+ *                     populations and f1,S its second-order Hermite projection
+ * Derivatives are centred differences in the level's lattice units, all in
+ * double precision.  A product of exactly zero gives 0.  Nodes the level
+ * does not evolve by streaming get 0: coarse TN and covered nodes, the fine
+ * ring.  diag (optional, may be NULL): [3][N] doubles, the divergence
+ * product, the curl product and the ghost norm.  flags / diag are host or
+ * device memory per mem.  LBM_EINVAL before any recorded step, or after
+ * lbm_set_state, lbm_set_populations or lbm_tune.  Synchronous. */
+int lbm_sensors_enable(lbm_handle h, int on);
+int lbm_sensors(lbm_handle h, int level, double threshold, uint8_t* flags, double* diag, int mem);
+
+/* Probe recording: after every following coarse step the density at node
+ * node[3] (level coordinates) of `level` is appended on the device to a
+ * series of at most `capacity` values (the paper's probes, Sec. 9.3).  A
+ * new call restarts the series; level = -1 stops recording.  The node must
+ * be evolved by the level (not covered, not on the fine ring).
+ * lbm_probe_read copies up to max values to host memory `out` and returns in
+ * *count the number recorded (which may exceed max).  Synchronous. */
+int lbm_probe_enable(lbm_handle h, int level, const int32_t node[3], int64_t capacity);
+int lbm_probe_read(lbm_handle h, double* out, int64_t max, int64_t* count);
+
 /* Node-class map of one level, one byte per node (LBM_C_* / LBM_F_*). */
 int lbm_get_index_maps(lbm_handle h, int level, uint8_t* cls, int mem);
 

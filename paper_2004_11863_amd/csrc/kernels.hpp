@@ -1334,24 +1334,32 @@ __global__ __launch_bounds__(HXV * HYR) void k_hrr2(const S* __restrict__ src, S
 }
 
 // ---------------------------------------------------------------------------
-// Both fine substeps of a coarse step in one kernel (D3Q19, BGK / RR).
-// A work group owns TXV vectors x TY rows of middle nodes over a run of zlen
-// planes and walks it along z.  The iteration for plane z computes substep 1
-// (t -> t+1/2) of plane z+1 for the tile and a one-node halo in x and y
-// (middle nodes pull and collide as k_stream does, ring nodes read `half`,
-// where the ring reconstruction stored them), then substep 2 of plane z.
-// Substep 2 pulls population i from plane z - cz_i: the 16 populations that
-// move in x or y come from neighbouring lanes through one LDS plane of 16
-// slots (cz = -1: the plane just computed; cz = 0: computed one iteration
-// earlier; cz = +1: two iterations earlier -- every lane keeps its own
-// column's values in registers until their turn), the 3 that move along z
-// only come from the lane's own registers.  HBM sees one read and one write
-// per fine node per coarse step; the arithmetic is that of two k_stream
-// launches, so the results are bitwise the same.  The t+1/2 state of middle
-// nodes within 4 nodes of a patch face (what the fine-to-coarse transfer
-// pulls) is stored into `half`.
+// Both fine substeps of a coarse step in one kernel, one node per lane
+// (D3Q19, BGK / RR: k_fine3s).  A work group of TXH x TYH lanes holds the
+// columns of a tile of (TXH - 2) x (TYH - 2) middle nodes and its one-node
+// halo in x and y, lane (hx, hy) at x = tx (TXH - 2) + hx, y = ty (TYH - 2) +
+// hy, and walks a run of zlen planes along z.  The iteration for plane z:
+//   * every lane takes substep 1 (t -> t+1/2) of its node in plane z+1:
+//     middle nodes collide the populations they pulled one iteration earlier
+//     (the pulls of plane z+2 are issued first, so their latency overlaps
+//     this arithmetic); ring nodes take the t+1/2 values the ring
+//     reconstruction stored in `half`;
+//   * the 16 populations that move in x or y go to an LDS exchange plane,
+//     each with the time offset its z velocity asks for (cz = -1: plane
+//     z+1, just computed; cz = 0: plane z; cz = +1: plane z-1 -- every lane
+//     keeps its own column's values in registers until their turn);
+//   * after one barrier the inner lanes take substep 2 (t+1/2 -> t+1) of
+//     plane z: moving populations from the neighbours' slots, the three that
+//     move only along z (rest, +z, -z) from their own registers.
+// Two exchange planes alternate, so one barrier per plane suffices.  Every
+// node's arithmetic is that of k_stream, so the result is bitwise the
+// two-launch one.  One node per lane keeps a lane's registers to the
+// populations of one column (the four-node lanes of an earlier design needed
+// 227 registers and ran at two waves per SIMD), and the x halo is one node
+// wide.  The t+1/2 state of middle nodes within 4 nodes of a patch face (what
+// the fine-to-coarse transfer pulls) is stored into `half`.
 template <int LAT>
-struct Fine3Sets {
+struct ZSets {
   using L = Lattice<LAT>;
   __host__ __device__ static constexpr bool moving(int i) { return L::cx(i) != 0 || L::cy(i) != 0; }
   __host__ __device__ static constexpr int count(int i, int cz) {
@@ -1359,175 +1367,367 @@ struct Fine3Sets {
     for (int k = 0; k < i; ++k) s += (moving(k) && (cz == 2 || L::cz(k) == cz)) ? 1 : 0;
     return s;
   }
-  __host__ __device__ static constexpr int slot(int i) { return count(i, 2); }  // LDS slot of a moving population
+  __host__ __device__ static constexpr int slot(int i) { return count(i, 2); }  // exchange slot of a moving population
   __host__ __device__ static constexpr int uidx(int i) { return count(i, 1); }  // among moving, cz = +1
   __host__ __device__ static constexpr int midx(int i) { return count(i, 0); }  // among moving, cz = 0
   static constexpr int NS = count(L::Q, 2), NU = count(L::Q, 1), NM = count(L::Q, 0);
 };
 
-// Substep 1 of one vector (node x0 = 1 + V k of row y, plane z) into T.
-// `band` asks to store middle nodes within 4 nodes of a face into `half`.
-template <int LAT, bool DEV, typename S, int MODEL>
-__device__ __forceinline__ void fine3_s1(const S* __restrict__ src, S* __restrict__ half, const Geo& g, const S om,
-                                         int k, int y, int z, int nv, typename VT<S, VecOf<S>::V>::a* T, bool band) {
-  using L = Lattice<LAT>;
-  using N = Node<LAT, DEV, S>;
-  constexpr int V = VecOf<S>::V, Q = L::Q;
-  using VA = typename VT<S, V>::a;
-  const int nx = g.nf[0], ny = g.nf[1], nz = g.nf[2];
-  const int x0 = 1 + V * k;
-  if (y == 0 || y == ny - 1 || z == 0 || z == nz - 1 || k == -1) {
-    // ring row or plane, or the vector ending at ring node x = 0
-#pragma unroll
-    for (int j = 0; j < V; ++j) {
-      const int x = x0 + j;
-      const bool in = x >= 0 && x <= nx - 1;
-      const int64_t p = fpos(g, in ? x : 0, y, z);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) T[i][j] = in ? half[pop_at<S, Q>(p, i)] : S(0);
-    }
-    return;
+// Addressing inside the storage window of a marching kernel's run.  The run
+// touches planes [z0, z1] of the fine level; relative to the storage block
+// holding the first position of plane z0, every population element of those
+// planes lies below 2^32 bytes (the host sizes runs so that it does).  The
+// window is addressed through a buffer resource: an access is one 32-bit
+// byte offset per lane (the node's position) plus a per-population offset
+// held in a scalar register, so it costs no vector arithmetic beyond the
+// position's offset.  With the array-of-SoA layout, population i of position
+// pb0 + d sits at byte  sizeof(S) ((Q B) (d >> SH) + (d & (B - 1)) + i B)
+// past the window's first element, population 0 of position pb0.
+template <typename S, int Q>
+struct Window {
+  static constexpr int SH = PopBlock<S>::SHIFT;
+  static constexpr uint32_t B = (uint32_t)PopBlock<S>::B;
+  int64_t pb0;  // first position of the window (block-aligned)
+  __device__ __forceinline__ explicit Window(int64_t first) : pb0((first >> SH) << SH) {}
+  // byte offset of population 0 of window position d
+  __device__ __forceinline__ static uint32_t boff(uint32_t d) {
+    return (uint32_t)sizeof(S) * d + (uint32_t)sizeof(S) * (uint32_t)(Q - 1) * B * (d >> SH);
   }
-  const Pull<S, Q, V, 1, 3> pl(g.pf, g.fxo, x0, y, z, nx, ny, nz);
-  pl.template load_all<L>(src, T);
-#pragma unroll
-  for (int j = 0; j < V; ++j) {
-    S f[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = T[i][j];
-    N::collide(f, MODEL, om, S(0), S(0), nullptr);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) T[i][j] = f[i];
+  // byte offset of population i relative to population 0
+  __device__ __forceinline__ static constexpr int poff(int i) { return (int)(sizeof(S) * B) * i; }
+  // Buffer resource over the window of a population buffer.  Its range is
+  // 2^31 bytes (the host sizes runs so that the window fits): a lane whose
+  // offset is moved past it by kOff reads 0 and writes nothing, which masks
+  // a lane without a branch.
+  static constexpr uint32_t kOff = 0x80000000u;
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const S* buf) const {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)(buf + (int64_t)Q * pb0), (short)0, (int)kOff, 0x00020000);
   }
-  if (k == nv - 1) {
-    // the ring node x = nx - 1 inside the last vector of the row
-    const int jr = nx - 1 - x0;
-    if (jr >= 0 && jr < V) {
-      const int64_t p = fpos(g, nx - 1, y, z);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const S h = half[pop_at<S, Q>(p, i)];
-#pragma unroll
-        for (int j = 0; j < V; ++j)
-          if (j == jr) T[i][j] = h;
-      }
-    }
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  __device__ __forceinline__ static S load(__amdgpu_buffer_rsrc_t r, uint32_t bo, int i) {
+    if constexpr (sizeof(S) == 4)
+      return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, (int)bo, poff(i), 0));
+    else
+      return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, (int)bo, poff(i), 0));
   }
-  if (band) {
-    const bool rows = y <= 4 || y >= ny - 5 || z <= 4 || z >= nz - 5;
-    const int64_t p0 = fpos(g, x0, y, z);
-    if (rows && x0 + V - 1 <= nx - 2) {
-#pragma unroll
-      for (int i = 0; i < Q; ++i) *(VA*)(half + pop_at<S, Q>(p0, i)) = T[i];
-    } else {
-#pragma unroll
-      for (int j = 0; j < V; ++j) {
-        const int x = x0 + j;
-        if (x > nx - 2 || !(rows || x <= 4 || x >= nx - 5)) continue;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) half[pop_at<S, Q>(p0 + j, i)] = T[i][j];
-      }
-    }
+  // NT: non-temporal store (the streamed state is not read again soon)
+  template <bool NT>
+  __device__ __forceinline__ static void store(__amdgpu_buffer_rsrc_t r, uint32_t bo, int i, S v) {
+    if constexpr (sizeof(S) == 4)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)bo, poff(i), NT ? 2 : 0);
+    else
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)bo, poff(i), NT ? 2 : 0);
   }
-}
+};
 
-template <int LAT, bool DEV, typename S, int MODEL, bool NT, int TXV, int TY, int MINW>
-__global__ __launch_bounds__(256, MINW) void k_fine3(const S* __restrict__ src, S* __restrict__ dst,
-                                                     S* __restrict__ half, const Geo g, const S om, int ntx, int nty,
-                                                     int nzc, int zlen, int per_xcd) {
+template <int LAT, bool DEV, typename S, int MODEL, bool NT, int TXH, int TYH, int MINW>
+__global__ __launch_bounds__(TXH * TYH, MINW) void k_fine3s(const S* __restrict__ src, S* __restrict__ dst,
+                                                            S* __restrict__ half, const Geo g, const S om, int ntx,
+                                                            int nty, int nzc, int zlen, int per_xcd) {
   using L = Lattice<LAT>;
   using N = Node<LAT, DEV, S>;
-  using C = Fine3Sets<LAT>;
-  constexpr int V = VecOf<S>::V, Q = L::Q;
-  using VA = typename VT<S, V>::a;
-  constexpr int HX = TXV + 2, HY = TY + 2, RW = HX * V;
+  using C = ZSets<LAT>;
+  constexpr int Q = L::Q, NL = TXH * TYH;
   static_assert(L::D == 3, "the marching fused kernel is three-dimensional");
-  static_assert(HX * HY <= 256, "one lane per tile-and-halo vector");
+  static_assert(NL <= 1024 && 2 * C::NS * NL * sizeof(S) <= 160 * 1024, "one work group per CU at most");
   static_assert(C::NS == 16 && C::NU == 4 && C::NM == 8, "D3Q19 population classes");
-  __shared__ S lds[C::NS][HY][RW];
+  __shared__ S lds[2][C::NS][NL];
   const int b = blockIdx.x;
   const int item = (b % kXCD) * per_xcd + b / kXCD;
   const int ntile = ntx * nty;
   if (item >= ntile * nzc) return;  // whole work group, before any barrier
   const int zc = item / ntile, tile = item - zc * ntile;
   const int tx = tile % ntx, ty = tile / ntx;
-  const int ny = g.nf[1], nz = g.nf[2];
-  const int nv = (g.nf[0] - 1 + V - 1) / V;
+  const int nx = g.nf[0], ny = g.nf[1], nz = g.nf[2];
   const int t = threadIdx.x;
-  const int hv = t % HX, hr = t / HX;
-  const int k = tx * TXV - 1 + hv, y = ty * TY + hr;
-  const bool lane = t < HX * HY;
-  const bool live = lane && y <= ny - 1 && k <= nv - 1;
-  const bool inner = live && hv >= 1 && hv <= TXV && hr >= 1 && hr <= TY && y <= ny - 2;
+  const int hx = t % TXH, hy = t / TXH;
+  const int x = tx * (TXH - 2) + hx, y = ty * (TYH - 2) + hy;
+  const bool live = x <= nx - 1 && y <= ny - 1;
+  const bool inner = live && hx >= 1 && hx <= TXH - 2 && hy >= 1 && hy <= TYH - 2 && x <= nx - 2 && y <= ny - 2;
+  const bool xyring = live && (x == 0 || x == nx - 1 || y == 0 || y == ny - 1);
+  const bool near = x <= 4 || x >= nx - 5 || y <= 4 || y >= ny - 5;
+  // the tile has nodes within 4 of an x or y face (wave-uniform)
+  const bool tile_near = tx * (TXH - 2) <= 4 || tx * (TXH - 2) + TXH - 1 >= nx - 5 || ty * (TYH - 2) <= 4 ||
+                         ty * (TYH - 2) + TYH - 1 >= ny - 5;
+  // the wave holds ring columns or rows (wave-uniform)
+  const bool wave_ring = __any(xyring) != 0;
   const int zs = 1 + zc * zlen, ze = min(zs + zlen - 1, nz - 2);
-  VA U0[C::NU], U1[C::NU], M[C::NM], R, Z0, Z1;
-  const VA zero = VA(S(0));
+  // The run computes planes zs - 1 .. ze + 1, whose pulls reach planes
+  // zs - 2 .. ze + 2: the window starts at row 0 of plane max(zs - 2, 0);
+  // d0 = this lane's node in plane zs - 1.  Every load and store below is
+  // issued by every lane (masked lanes get an offset past the window), so
+  // the number of memory operations per plane is the same on every path and
+  // the loads of the next plane stay in flight across the barrier and the
+  // stores of this one.
+  using Wn = Window<S, Q>;
+  const Wn W(fpos(g, 0, 0, max(zs - 2, 0)));
+  const __amdgpu_buffer_rsrc_t rs = W.rsrc(src), rh = W.rsrc(half), rd = W.rsrc(dst);
+  const uint32_t py = (uint32_t)g.pf, pz = (uint32_t)g.pf * (uint32_t)ny;
+  const uint32_t d0 = live ? (uint32_t)(fpos(g, x, y, zs - 1) - W.pb0) : 0u;
+  const uint32_t mlive = live ? 0u : Wn::kOff;      // offset mask of dead lanes
+  const uint32_t mpull = (live && !xyring) ? 0u : Wn::kOff;
+  const uint32_t mring = xyring ? 0u : Wn::kOff;
+  const uint32_t minner = inner ? 0u : Wn::kOff;
+  S U0[C::NU], U1[C::NU], M[C::NM], R = S(0), Z0 = S(0), Z1 = S(0);
 #pragma unroll
-  for (int i = 0; i < C::NU; ++i) U0[i] = U1[i] = zero;
+  for (int i = 0; i < C::NU; ++i) U0[i] = U1[i] = S(0);
 #pragma unroll
-  for (int i = 0; i < C::NM; ++i) M[i] = zero;
-  R = Z0 = Z1 = zero;
-  for (int z = zs - 2; z <= ze; ++z) {
-    const int zl = z + 1;
-    VA T[Q];
-    if (live) {
-      fine3_s1<LAT, DEV, S, MODEL>(src, half, g, om, k, y, zl, nv, T, inner && zl >= zs && zl <= ze);
-    } else {
+  for (int i = 0; i < C::NM; ++i) M[i] = S(0);
+  // Every memory operation below is issued by every lane, every plane, and
+  // never under a branch (a lane that has nothing to load or store gets an
+  // offset past the window): the compiler's count of outstanding operations
+  // is then the same on every path, so it waits for the loads of a plane
+  // without waiting for the stores issued after them.  The price is one
+  // masked load of the ring values and one masked store of the band per
+  // population and plane in every wave.
+  S P[Q], PR[Q];
+  // Loads of substep 1 for plane zp (window position d of this lane's node):
+  // pulls of middle nodes from src into P, t+1/2 values of ring nodes (ring
+  // planes, columns and rows) from `half` into PR.
+  auto load = [&](int zp, uint32_t d) __attribute__((always_inline)) {
+    const bool pring = zp == 0 || zp == nz - 1;
+    const uint32_t mp = pring ? Wn::kOff : mpull;
 #pragma unroll
-      for (int i = 0; i < Q; ++i) T[i] = zero;
-    }
-    if (z >= zs) {
-      if (lane) {
-        static_for<Q>([&](auto I) {
-          constexpr int i = decltype(I)::value;
-          if constexpr (C::moving(i)) {
-            const VA w = L::cz(i) == -1 ? T[i] : (L::cz(i) == 0 ? M[C::midx(i)] : U1[C::uidx(i)]);
-            *(VA*)&lds[C::slot(i)][hr][hv * V] = w;
-          }
-        });
-      }
-      __syncthreads();
-      if (inner) {
-        VA v[Q];
-        static_for<Q>([&](auto I) {
-          constexpr int i = decltype(I)::value;
-          if constexpr (C::moving(i)) {
+    for (int i = 0; i < Q; ++i)
+      P[i] = Wn::load(rs, Wn::boff(d - L::cx(i) - py * L::cy(i) - pz * L::cz(i)) | mp, i);
+    const uint32_t bo = Wn::boff(d) | (pring ? mlive : mring);
 #pragma unroll
-            for (int j = 0; j < V; ++j) v[i][j] = lds[C::slot(i)][hr - L::cy(i)][hv * V + j - L::cx(i)];
-          } else {
-            v[i] = L::cz(i) == 0 ? R : (L::cz(i) == 1 ? Z1 : T[i]);
-          }
-        });
+    for (int i = 0; i < Q; ++i) PR[i] = Wn::load(rh, bo, i);
+  };
+  // Substep 1 of plane zl (window position dl) into T from the loads issued
+  // one plane earlier (ring nodes take PR by a bitwise blend: a select
+  // became a select of array addresses, which kept the arrays in scratch
+  // memory); the t+1/2 state of inner middle nodes within 4 nodes of a face
+  // goes to `half`.
+  using U = typename std::conditional<sizeof(S) == 4, uint32_t, uint64_t>::type;
+  auto take = [&](int zl, S* T) __attribute__((always_inline)) {
+    const bool pring = zl == 0 || zl == nz - 1;
+    const U mk = (xyring || pring) ? ~U(0) : U(0);
 #pragma unroll
-        for (int j = 0; j < V; ++j) {
-          S f[Q];
+    for (int i = 0; i < Q; ++i)
+      T[i] = __builtin_bit_cast(S, (__builtin_bit_cast(U, PR[i]) & mk) | (__builtin_bit_cast(U, P[i]) & ~mk));
+  };
+  auto s1 = [&](int zl, uint32_t dl, S* T) __attribute__((always_inline)) {
+    const bool pring = zl == 0 || zl == nz - 1;
+    if (live && !xyring && !pring) N::collide(T, MODEL, om, S(0), S(0), nullptr);
+    const bool st = inner && !pring && zl >= zs && zl <= ze && (near || zl <= 4 || zl >= nz - 5);
+    const uint32_t bo = Wn::boff(dl) | (st ? 0u : Wn::kOff);
 #pragma unroll
-          for (int i = 0; i < Q; ++i) f[i] = v[i][j];
-          N::collide(f, MODEL, om, S(0), S(0), nullptr);
-#pragma unroll
-          for (int i = 0; i < Q; ++i) v[i][j] = f[i];
-        }
-        const int64_t own = fpos(g, 1 + V * k, y, z);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + pop_at<S, Q>(own, i)), v[i]);
-      }
-      __syncthreads();
-    }
-    // the planes move up by one
+    for (int i = 0; i < Q; ++i) Wn::template store<false>(rh, bo, i, T[i]);
+  };
+  // the planes move up by one
+  auto shift = [&](const S* T) __attribute__((always_inline)) {
     static_for<Q>([&](auto I) {
       constexpr int i = decltype(I)::value;
-      if constexpr (C::moving(i) && L::cz(i) == 1) {
-        U1[C::uidx(i)] = U0[C::uidx(i)];
-        U0[C::uidx(i)] = T[i];
-      } else if constexpr (C::moving(i) && L::cz(i) == 0) {
-        M[C::midx(i)] = T[i];
-      } else if constexpr (!C::moving(i) && L::cz(i) == 0) {
+      constexpr int mi = C::midx(i), ui = C::uidx(i), cz = L::cz(i);
+      constexpr bool mv = C::moving(i);
+      if constexpr (mv && cz == 1) {
+        U1[ui] = U0[ui];
+        U0[ui] = T[i];
+      } else if constexpr (mv && cz == 0) {
+        M[mi] = T[i];
+      } else if constexpr (!mv && cz == 0) {
         R = T[i];
-      } else if constexpr (!C::moving(i) && L::cz(i) == 1) {
+      } else if constexpr (!mv && cz == 1) {
         Z1 = Z0;
         Z0 = T[i];
       }
     });
+  };
+  // planes zs - 1 and zs: substep 1 only
+  {
+    S T[Q];
+    load(zs - 1, d0);
+    take(zs - 1, T);
+    load(zs, d0 + pz);
+    s1(zs - 1, d0, T);
+    shift(T);
+    take(zs, T);
+    load(zs + 1, d0 + 2 * pz);
+    s1(zs, d0 + pz, T);
+    shift(T);
+  }
+  int buf = 0;
+  for (int z = zs; z <= ze; ++z) {
+    const int zl = z + 1;
+    const uint32_t dl = d0 + (uint32_t)(zl - zs + 1) * pz;  // window position of (x, y, zl)
+    // the loads of plane zl (issued one plane earlier) into T, the loads of
+    // plane zl + 1 out (plane zl again past the run's last plane)
+    S T[Q];
+    take(zl, T);
+    const int zn = zl + 1 <= ze + 1 ? zl + 1 : zl;
+    load(zn, dl + (uint32_t)(zn - zl) * pz);
+    s1(zl, dl, T);
+    // (slot and register indices are forced to compile-time constants:
+    // used directly as array indices, the counting loops behind them were
+    // left to run on the device)
+    static_for<Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      if constexpr (C::moving(i)) {
+        constexpr int sl = C::slot(i), mi = C::midx(i), ui = C::uidx(i), cz = L::cz(i);
+        S w;
+        if constexpr (cz == -1) w = T[i];
+        else if constexpr (cz == 0) w = M[mi];
+        else w = U1[ui];
+        lds[buf][sl][t] = w;
+      }
+    });
+    __syncthreads();
+    S f[Q];
+    if (inner) {
+      static_for<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int cz = L::cz(i);
+        if constexpr (C::moving(i)) {
+          constexpr int sl = C::slot(i), off = L::cx(i) + TXH * L::cy(i);
+          f[i] = lds[buf][sl][t - off];
+        } else if constexpr (cz == 0) {
+          f[i] = R;
+        } else if constexpr (cz == 1) {
+          f[i] = Z1;
+        } else {
+          f[i] = T[i];
+        }
+      });
+      N::collide(f, MODEL, om, S(0), S(0), nullptr);
+    } else {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) f[i] = S(0);
+    }
+    const uint32_t bo = Wn::boff(dl - pz) | minner;  // (x, y, z)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) Wn::template store<NT>(rd, bo, i, f[i]);
+    buf ^= 1;
+    shift(T);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One H-RR fine substep in one pass with one node per lane (D3Q19, k_hrr3s).
+// A work group of TXH x TYH lanes holds the columns of a tile of (TXH - 2) x
+// (TYH - 2) middle nodes and its one-node halo and walks a run of zlen planes
+// along z.  The iteration for plane z takes the populations of plane z+1,
+// pulled one iteration earlier, computes their velocities (ring nodes: from
+// the velocity planes, where the ring macro step stored them) into one of
+// four LDS velocity planes and issues the pulls of plane z+2; after one
+// barrier the inner lanes take the strain rate of plane z by centred
+// differences from the planes of z-1, z and z+1 and collide the populations
+// of plane z they kept from the previous iteration.  Four velocity planes
+// rotate, so the plane written in one iteration is never one read in the
+// iteration before, and one barrier per plane suffices.  Every memory
+// operation is issued by every lane (masked lanes get offsets past the
+// window), so the loads of a plane stay in flight across the stores of the
+// one before.  Same arithmetic as the velocity pass followed by
+// k_collide_hrr, so bitwise the same.
+template <int LAT, bool DEV, typename S, bool NT, int TXH, int TYH, int MINW>
+__global__ __launch_bounds__(TXH * TYH, MINW) void k_hrr3s(const S* __restrict__ src, S* __restrict__ dst,
+                                                           const S* __restrict__ mac, const Geo g, const S om,
+                                                           const S tau, const S sig, int ntx, int nty, int nzc,
+                                                           int zlen, int per_xcd) {
+  using L = Lattice<LAT>;
+  using N = Node<LAT, DEV, S>;
+  constexpr int Q = L::Q, NL = TXH * TYH;
+  static_assert(L::D == 3, "the marching one-pass H-RR kernel is three-dimensional");
+  static_assert(NL <= 1024, "one work group");
+  __shared__ S lu[4][3][NL];  // [plane slot][component][lane]
+  const int b = blockIdx.x;
+  const int item = (b % kXCD) * per_xcd + b / kXCD;
+  const int ntile = ntx * nty;
+  if (item >= ntile * nzc) return;  // whole work group, before any barrier
+  const int zc = item / ntile, tile = item - zc * ntile;
+  const int tx = tile % ntx, ty = tile / ntx;
+  const int nx = g.nf[0], ny = g.nf[1], nz = g.nf[2];
+  const int t = threadIdx.x;
+  const int hx = t % TXH, hy = t / TXH;
+  const int x = tx * (TXH - 2) + hx, y = ty * (TYH - 2) + hy;
+  const bool live = x <= nx - 1 && y <= ny - 1;
+  const bool inner = live && hx >= 1 && hx <= TXH - 2 && hy >= 1 && hy <= TYH - 2 && x <= nx - 2 && y <= ny - 2;
+  const bool xyring = live && (x == 0 || x == nx - 1 || y == 0 || y == ny - 1);
+  const int zs = 1 + zc * zlen, ze = min(zs + zlen - 1, nz - 2);
+  // storage window of the run (pulls reach planes zs - 2 .. ze + 2); the
+  // velocity planes are addressed from the same first position
+  using Wn = Window<S, Q>;
+  const Wn W(fpos(g, 0, 0, max(zs - 2, 0)));
+  const __amdgpu_buffer_rsrc_t rs = W.rsrc(src), rd = W.rsrc(dst);
+  const __amdgpu_buffer_rsrc_t rm =
+      __builtin_amdgcn_make_buffer_rsrc((void*)(mac + W.pb0), (short)0, (int)Wn::kOff, 0x00020000);
+  const int mplane = (int)(g.Nfp * (int64_t)sizeof(S));  // bytes between velocity planes
+  const uint32_t py = (uint32_t)g.pf, pz = (uint32_t)g.pf * (uint32_t)ny;
+  const uint32_t d0 = live ? (uint32_t)(fpos(g, x, y, zs - 1) - W.pb0) : 0u;  // node in plane zs - 1
+  const uint32_t mpull = (live && !xyring) ? 0u : Wn::kOff;
+  const uint32_t mring = xyring ? 0u : Wn::kOff;
+  const uint32_t minner = inner ? 0u : Wn::kOff;
+  S H[Q], P[Q], UR[3];
+  // pulls of plane zp (window position d) into P; velocities of ring nodes
+  // (ring planes, columns and rows) from the velocity planes into UR
+  auto load = [&](int zp, uint32_t d) __attribute__((always_inline)) {
+    const bool pring = zp == 0 || zp == nz - 1;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      P[i] = Wn::load(rs, Wn::boff(d - L::cx(i) - py * L::cy(i) - pz * L::cz(i)) | (pring ? Wn::kOff : mpull), i);
+    const uint32_t mo = (uint32_t)sizeof(S) * d | ((pring && live) || xyring ? 0u : Wn::kOff);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      if constexpr (sizeof(S) == 4)
+        UR[k] = __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(rm, (int)mo, (1 + k) * mplane, 0));
+      else
+        UR[k] = __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(rm, (int)mo, (1 + k) * mplane, 0));
+    }
+  };
+  // velocity of the loaded plane zp into its LDS slot; its populations into H
+  auto put = [&](int zp) __attribute__((always_inline)) {
+    const bool ring = xyring || zp == 0 || zp == nz - 1;
+    S rho, r0, u[3];
+    N::moments(P, rho, r0, u);
+    using U = typename std::conditional<sizeof(S) == 4, uint32_t, uint64_t>::type;
+    const U mk = ring ? ~U(0) : U(0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const S v = __builtin_bit_cast(S, (__builtin_bit_cast(U, UR[k]) & mk) | (__builtin_bit_cast(U, u[k]) & ~mk));
+      lu[zp & 3][k][t] = live ? v : S(0);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) H[i] = P[i];
+  };
+  // planes zs - 1 (velocities) and zs (velocities and populations), the
+  // pulls of plane zs + 1 out
+  load(zs - 1, d0);
+  put(zs - 1);
+  load(zs, d0 + pz);
+  put(zs);
+  load(zs + 1, d0 + 2 * pz);
+  for (int z = zs; z <= ze; ++z) {
+    const uint32_t dz = d0 + (uint32_t)(z - zs + 1) * pz;  // window position of (x, y, z)
+    // populations of plane z (kept from the previous iteration)
+    S Hc[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) Hc[i] = H[i];
+    put(z + 1);
+    // pulls of plane z + 2 (plane z + 1 again past the run's last plane)
+    const int zn = z + 2 <= ze + 1 ? z + 2 : z + 1;
+    load(zn, dz + (uint32_t)(zn - z) * pz);
+    __syncthreads();
+    if (inner) {
+      const int sm = (z - 1) & 3, s0 = z & 3, sp = (z + 1) & 3;
+      S gr[3][3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        gr[0][d] = (lu[s0][d][t + 1] - lu[s0][d][t - 1]) * S(0.5);
+        gr[1][d] = (lu[s0][d][t + TXH] - lu[s0][d][t - TXH]) * S(0.5);
+        gr[2][d] = (lu[sp][d][t] - lu[sm][d][t]) * S(0.5);
+      }
+      Sym<S> Sr;
+      Sr.xx = gr[0][0];
+      Sr.yy = gr[1][1];
+      Sr.xy = S(0.5) * (gr[0][1] + gr[1][0]);
+      Sr.zz = gr[2][2];
+      Sr.xz = S(0.5) * (gr[0][2] + gr[2][0]);
+      Sr.yz = S(0.5) * (gr[1][2] + gr[2][1]);
+      N::collide(Hc, M_HRR, om, tau, sig, &Sr);
+    }
+    const uint32_t bo = Wn::boff(dz) | minner;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) Wn::template store<NT>(rd, bo, i, Hc[i]);
   }
 }
 
@@ -1770,6 +1970,179 @@ __global__ void k_macros(const S* __restrict__ src, const S* __restrict__ fine, 
   rho[k] = r;
 #pragma unroll
   for (int d = 0; d < L::D; ++d) u[d * NN + k] = uu[d];
+}
+
+// ---------------------------------------------------------------------------
+// Non-hydrodynamic-mode sensors (Sec. 7).  Diagnostics, in double precision,
+// one thread per node.
+//
+// Velocities of a level into plain planes U[1 + d][pos] (plane 0 unused
+// here; the layout is that of the velocity planes, so the ring macro kernel
+// can fill ring entries): PULL = false takes the moments of src at the node,
+// PULL = true the moments of the populations the node pulls from src (the
+// pre-collision state one iteration later) -- fine level, non-ring nodes.
+template <int LAT, bool DEV, typename S, int LEVEL, bool PULL>
+__global__ void k_sens_vel(const S* __restrict__ src, double* __restrict__ U, const Geo g) {
+  using L = Lattice<LAT>;
+  using N = Node<LAT, false, double>;
+  constexpr int Q = L::Q;
+  const int64_t NN = LEVEL == 0 ? g.Nc : g.Nf;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= NN) return;
+  int x, y, z;
+  if (LEVEL == 0) cdecode(g, k, x, y, z);
+  else fdecode(g, k, x, y, z);
+  const int64_t pos = LEVEL == 0 ? cpos(g, x, y, z) : fpos(g, x, y, z);
+  const int64_t NP = LEVEL == 0 ? g.Ncp : g.Nfp;
+  if (PULL && LEVEL == 1 && fine_is_ring(g, x, y, z)) return;
+  double f[Q], r, r0, u[3];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int64_t ps = pos;
+    if (PULL) ps = fpos(g, x - L::cx(i), y - L::cy(i), z - L::cz(i));
+    f[i] = full_pop<S, DEV, LAT>(src[pop_at<S, Q>(ps, i)], i);
+  }
+  N::moments(f, r, r0, u);
+#pragma unroll
+  for (int d = 0; d < L::D; ++d) U[(int64_t)(1 + d) * NP + pos] = u[d];
+}
+
+// Sensor flags of one node of a level after a step: bit 0 SpuriousAc (the
+// velocity divergence changes sign between the two iterations, eq
+// sensorSpuriousAc), bit 1 SpuriousS (the curl changes sign, eq
+// sensorSpuriousS; in 3D the dot product of the two curl vectors), bit 2
+// SpuriousG (eqs fneqSplit, reguProceduref1S, sensorSpuriousG: the norm of
+// the non-equilibrium part of the pre-collision populations left after the
+// second-order Hermite projection exceeds thr, and neither flag above is
+// set).  A product of exactly zero gives 0.  Up: velocities of the previous
+// iteration (planes, as k_sens_vel); cur: the post-collision state of the
+// last iteration (its moments are the pre-collision ones); pre: the state
+// the last iteration's pre-collision populations are pulled from.  Nodes the
+// level does not evolve by streaming get 0: coarse TN and covered nodes,
+// the fine ring.  flags and the optional diagnostics prod[3][N] (divergence
+// product, curl product, ghost norm) are in logical node order.
+template <int LAT, bool DEV, typename S, int LEVEL>
+__global__ void k_sensors(const double* __restrict__ Up, const S* __restrict__ cur, const S* __restrict__ pre,
+                          uint8_t* __restrict__ flags, double* __restrict__ prod, const Geo g, double thr) {
+  using L = Lattice<LAT>;
+  using N = Node<LAT, false, double>;
+  constexpr int Q = L::Q, D = L::D;
+  const int64_t NN = LEVEL == 0 ? g.Nc : g.Nf;
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= NN) return;
+  int x, y, z;
+  if (LEVEL == 0) cdecode(g, k, x, y, z);
+  else fdecode(g, k, x, y, z);
+  const int nx = LEVEL == 0 ? g.n[0] : g.nf[0], ny = LEVEL == 0 ? g.n[1] : g.nf[1],
+            nz = LEVEL == 0 ? g.n[2] : g.nf[2];
+  const int64_t NP = LEVEL == 0 ? g.Ncp : g.Nfp;
+  bool ok;
+  if (LEVEL == 0) {
+    const int c = coarse_class(g, x, y, z);
+    ok = c == CC_MIDDLE || c == CC_TF;
+  } else {
+    ok = !fine_is_ring(g, x, y, z);
+  }
+  uint8_t fl = 0;
+  double pd = 0.0, pc = 0.0, gn = 0.0;
+  if (ok) {
+    auto at = [&](int xs, int ys, int zs) -> int64_t {
+      if (LEVEL == 0) return cpos(g, wrap(xs, nx), wrap(ys, ny), D == 3 ? wrap(zs, nz) : 0);
+      return fpos(g, xs, ys, zs);
+    };
+    auto ucur = [&](int64_t p, double* u) {
+      double f[Q], r, r0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) f[i] = full_pop<S, DEV, LAT>(cur[pop_at<S, Q>(p, i)], i);
+      N::moments(f, r, r0, u);
+    };
+    // velocity gradients of both iterations, centred differences
+    double gp[3][3], gc[3][3];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const int e[3] = {a == 0, a == 1, a == 2};
+      const int64_t pp = at(x + e[0], y + e[1], z + e[2]), pm = at(x - e[0], y - e[1], z - e[2]);
+      double up[3], um[3];
+      ucur(pp, up);
+      ucur(pm, um);
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        gc[a][b] = (up[b] - um[b]) / 2.0;
+        gp[a][b] = (Up[(int64_t)(1 + b) * NP + pp] - Up[(int64_t)(1 + b) * NP + pm]) / 2.0;
+      }
+    }
+    double dp = 0.0, dc = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      dp += gp[a][a];
+      dc += gc[a][a];
+    }
+    double cp[3], cc[3];
+    if (D == 2) {
+      cp[0] = gp[0][1] - gp[1][0];
+      cc[0] = gc[0][1] - gc[1][0];
+      cp[1] = cp[2] = cc[1] = cc[2] = 0.0;
+    } else {
+      cp[0] = gp[1][2] - gp[2][1];
+      cp[1] = gp[2][0] - gp[0][2];
+      cp[2] = gp[0][1] - gp[1][0];
+      cc[0] = gc[1][2] - gc[2][1];
+      cc[1] = gc[2][0] - gc[0][2];
+      cc[2] = gc[0][1] - gc[1][0];
+    }
+    pd = dp * dc;
+    pc = cp[0] * cc[0] + cp[1] * cc[1] + cp[2] * cc[2];
+    const bool ac = pd < 0.0, sp = pc < 0.0;
+    // pre-collision populations of the last iteration
+    double f[Q], f0[Q], r, r0, u[3];
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      f[i] = full_pop<S, DEV, LAT>(pre[pop_at<S, Q>(at(x - L::cx(i), y - L::cy(i), z - L::cz(i)), i)], i);
+    N::moments(f, r, r0, u);
+    N::feq(r, r0, u, f0);
+    double f1[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f1[i] = f[i] - f0[i];
+    const Sym<double> P = N::second(f1);  // a1 = sum_i H_i f1_i (f1 carries no mass or momentum)
+    double a[3][3] = {{P.xx, P.xy, P.xz}, {P.xy, P.yy, P.yz}, {P.xz, P.yz, P.zz}};
+    double nrm = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double c[3] = {(double)L::cx(i), (double)L::cy(i), (double)L::cz(i)};
+      double hs = 0.0;
+#pragma unroll
+      for (int p = 0; p < D; ++p)
+#pragma unroll
+        for (int q = 0; q < D; ++q) hs += (c[p] * c[q] - (p == q ? 1.0 / 3.0 : 0.0)) * a[p][q];
+      const double gq = f1[i] - L::w(i) * 4.5 * hs;  // f1 - w / (2 c_s^4) H : a1
+      nrm += gq * gq;
+    }
+    gn = sqrt(nrm);
+    const bool gs = gn > thr && !ac && !sp;
+    fl = (uint8_t)((ac ? 1 : 0) | (sp ? 2 : 0) | (gs ? 4 : 0));
+  }
+  flags[k] = fl;
+  if (prod) {
+    prod[k] = pd;
+    prod[NN + k] = pc;
+    prod[2 * NN + k] = gn;
+  }
+}
+
+// Density at one node of a level, appended to a series (probe recording):
+// series[*count] = rho, ++*count while below capacity.  One thread.
+template <int LAT, bool DEV, typename S>
+__global__ void k_probe(const S* __restrict__ src, int64_t pos, double* __restrict__ series,
+                        int64_t* __restrict__ count, int64_t capacity) {
+  using L = Lattice<LAT>;
+  if (threadIdx.x != 0) return;
+  const int64_t c = *count;
+  if (c >= capacity) return;
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < L::Q; ++i) r += full_pop<S, DEV, LAT>(src[pop_at<S, L::Q>(pos, i)], i);
+  series[c] = r;
+  *count = c + 1;
 }
 
 // Populations out / in: f[q][logical node] (double, full values).

@@ -187,6 +187,10 @@ struct GridBase {
   virtual void totals_in(double* mass, double* mom, double* part, double* fin) = 0;
   virtual void tune(int reps, int32_t* out) = 0;
   virtual void set_variants(const int32_t* v) = 0;
+  virtual void sensors_enable(bool on) = 0;
+  virtual void sensors(int level, double thr, uint8_t* flags, double* prod, bool dev) = 0;
+  virtual void probe_enable(int level, const int32_t* node, int64_t capacity) = 0;
+  virtual int64_t probe_read(double* out, int64_t max) = 0;
   int64_t nodes(int level) const { return level == 0 ? g.Nc : g.Nf; }
   int64_t updates() const {
     if (!g.has_fine) return g.Nc;
@@ -219,21 +223,32 @@ struct Grid final : GridBase {
   int cpar = 0;  // coarse buffer holding the current state
   // Fine buffers: fbuf[fpar] holds the state at integer times.  A fused step
   // (BGK / RR: always in 2D, k_fine2; in 3D when the fine-role variant picks
-  // k_fine3) runs both fine substeps in one kernel from fbuf[fpar] into the
+  // k_fine3s) runs both fine substeps in one kernel from fbuf[fpar] into the
   // other buffer, which then becomes current; fbuf[2] receives the t+1/2
   // ring and the t+1/2 band the fine-to-coarse transfer pulls from.
   // Otherwise the substeps go fbuf[fpar] -> other -> fbuf[fpar].
   int fpar = 0;
   bool fused = false;
   int n_cu = 0;
-  int f3_slots[kNVar] = {0, 0, 0, 0};  // resident k_fine3 work groups per device, per variant
-  int h3_slots[kNVar] = {0, 0, 0, 0};  // the same for k_hrr3
+  int f3_slots[kNVar] = {0, 0, 0, 0};  // resident k_fine3s work groups per device, per variant
+  int h3_slots[kNVar] = {0, 0, 0, 0};  // the same for k_hrr3 / k_hrr3s
   int hs[3] = {0, 1, 2};
   Iface itf{};
   double tau_c = 0, tau_f = 0, sig = 0;
   // The stepping stores only the ring populations it reads again (k_ring
   // PARTIAL); true while fine A holds such a partial ring.
   bool ring_partial = false;
+  // NH sensors: while on, each step first records the velocities of the
+  // iteration before its last one (coarse t, fine t+1/2) in sUc / sUf
+  // (double planes [1 + D][padded positions]) and runs the fine substeps as
+  // two launches, so that the t+1/2 state stays in fine B; sens_ready: a
+  // step has been recorded and nothing has touched the state since.
+  bool sensors_on = false, sens_ready = false;
+  DevBuf sUc, sUf, sFlags, sProd;
+  // probe: density at one node of a level appended to pSeries each step
+  int probe_level = -1;
+  int64_t probe_pos = 0, probe_cap = 0;
+  DevBuf pSeries, pCount;
 
   // Velocity planes (H-RR): padded planes plus 64 spare elements.
   static size_t plane_bytes(int64_t NP, int nplanes) { return sizeof(S) * ((size_t)NP * nplanes + 64); }
@@ -400,63 +415,33 @@ struct Grid final : GridBase {
                          dim3(HXV * HYR), 0, s, src, dst, half, g, (S)(1.0 - 1.0 / tau_f), ntx, nty, per);
     }
   }
-  // D3Q19: fine-role variants 0 and 1 run the substeps as two k_stream
-  // launches (at most 2 / 3 resident work groups per CU), 2 and 3 as one
-  // k_fine3 launch with tiles of 14 x 14 and 30 x 6 (vectors x rows) at 2
-  // waves per SIMD; the autotuner keeps the faster.  The planes are cut into
-  // runs so that the work groups fill the device in few rounds: a run of zlen
-  // planes costs zlen + 2 substep-1 planes (its first step needs two), and
-  // runs are at least kMinZRun planes long so that this overhead stays small.
-  template <int MODEL, int TXV, int TY, int MINW>
-  void go_fine3(const S* src, S* dst, S* half, hipStream_t s, int v) {
-    if constexpr (D == 3 && MODEL != M_HRR) {
-      auto kern = k_fine3<LAT, DEV, S, MODEL, NT, TXV, TY, MINW>;
-      if (f3_slots[v] == 0) {
-        int nb = 0;
-        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0));
-        f3_slots[v] = std::max(1, nb) * std::max(1, n_cu);
-      }
-      const int nv = (g.nf[0] - 1 + V - 1) / V;
-      const int ntx = (nv + TXV - 1) / TXV, nty = (g.nf[1] - 2 + TY - 1) / TY, nzm = g.nf[2] - 2;
-      const int64_t ntile = (int64_t)ntx * nty;
-      int zlen = nzm;
-      double best = -1.0;
-      constexpr int kMinZRun = 8;
-      for (int nzc = 1; nzc <= nzm; ++nzc) {
-        const int zl = (nzm + nzc - 1) / nzc;
-        if (zl < kMinZRun && nzc > 1) break;
-        if ((nzm + zl - 1) / zl != nzc) continue;
-        const int64_t rounds = (ntile * nzc + f3_slots[v] - 1) / f3_slots[v];
-        const double cost = (double)rounds * (zl + 2);
-        if (best < 0.0 || cost < best) {
-          best = cost;
-          zlen = zl;
-        }
-      }
-      const int nzc = (nzm + zlen - 1) / zlen;
-      const int per = (int)((ntile * nzc + kXCD - 1) / kXCD);
-      hipLaunchKernelGGL(kern, dim3((unsigned)(per * kXCD)), dim3(256), 0, s, src, dst, half, g,
-                         (S)(1.0 - 1.0 / tau_f), ntx, nty, nzc, zlen, per);
-    }
-  }
-  // Work decomposition of a marching fine kernel (k_fine3, k_hrr3) with
-  // TXV x TY tiles, for `slots` resident work groups on the device.
+  // Work decomposition of a marching fine kernel (k_hrr3) with TXV x TY
+  // tiles of vectors, for `slots` resident work groups on the device: a run
+  // of zlen planes costs zlen + 2 planes of work (its first step needs two
+  // more), and runs are at least kMinZRun planes long so that this overhead
+  // stays small, while the work groups fill the device in few rounds.
   struct ZRuns {
     int ntx, nty, nzc, zlen, per;
   };
   ZRuns zruns(int TXV, int TY, int slots) const {
-    ZRuns r;
     const int nv = (g.nf[0] - 1 + V - 1) / V;
-    r.ntx = (nv + TXV - 1) / TXV;
-    r.nty = (g.nf[1] - 2 + TY - 1) / TY;
+    return zruns_tiles((nv + TXV - 1) / TXV, (g.nf[1] - 2 + TY - 1) / TY, slots);
+  }
+  // zcap: longest run allowed (runs of the one-node-per-lane kernels address
+  // their storage window with 32-bit byte offsets).
+  ZRuns zruns_tiles(int ntx, int nty, int slots, int zcap = 1 << 30) const {
+    ZRuns r;
+    r.ntx = ntx;
+    r.nty = nty;
     const int nzm = g.nf[2] - 2;
     const int64_t ntile = (int64_t)r.ntx * r.nty;
-    r.zlen = nzm;
+    r.zlen = std::min(nzm, zcap);
     double best = -1.0;
     constexpr int kMinZRun = 8;
     for (int nzc = 1; nzc <= nzm; ++nzc) {
       const int zl = (nzm + nzc - 1) / nzc;
-      if (zl < kMinZRun && nzc > 1) break;
+      if (zl > zcap) continue;
+      if (zl < kMinZRun && nzc > 1 && zl < zcap) break;
       if ((nzm + zl - 1) / zl != nzc) continue;
       const int64_t rounds = (ntile * nzc + slots - 1) / slots;
       const double cost = (double)rounds * (zl + 2);
@@ -470,23 +455,43 @@ struct Grid final : GridBase {
     return r;
   }
   template <typename K>
-  int occupancy_slots(K kern, int& cache) {
+  int occupancy_slots(K kern, int& cache, int lanes = 256) {
     if (cache == 0) {
       int nb = 0;
-      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, 256, 0));
+      HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, lanes, 0));
       cache = std::max(1, nb) * std::max(1, n_cu);
     }
     return cache;
   }
-  template <typename K>
-  void fine3_launch(K kern, int TXV, int TY, const S* src, S* dst, S* half, hipStream_t s, int v) {
-    const ZRuns r = zruns(TXV, TY, occupancy_slots(kern, f3_slots[v]));
-    hipLaunchKernelGGL(kern, dim3((unsigned)(r.per * kXCD)), dim3(256), 0, s, src, dst, half, g,
-                       (S)(1.0 - 1.0 / tau_f), r.ntx, r.nty, r.nzc, r.zlen, r.per);
+  // Both fine substeps in one marching kernel with one node per lane
+  // (k_fine3s): tiles of (TXH - 2) x (TYH - 2) middle nodes.  The tile
+  // counts come from nodes, not vectors; the runs are cut as for k_hrr3.
+  // Longest run of a one-node-per-lane marching kernel: its storage window
+  // (zlen + 4 planes and one storage block) stays below 2^32 bytes.
+  int window_zcap() const {
+    const double plane = (double)g.pf * g.nf[1] * Q * sizeof(S);
+    const double room = 2147483648.0 - 2.0 * (double)PopBlock<S>::B * Q * sizeof(S);
+    return std::max(0, (int)std::floor(room / plane) - 4);
   }
-  // One H-RR fine substep in one pass (D3Q19, k_hrr3), fine H-RR role
-  // variants 2 (30 x 6 tiles) and 3 (62 x 2); variants 0 and 1 run the
-  // velocity pass and k_collide_hrr (capped at 2 / 3 resident work groups).
+  template <int MODEL, int TXH, int TYH, int MINW>
+  void go_fine3s(const S* src, S* dst, S* half, hipStream_t s, int v) {
+    if constexpr (D == 3 && MODEL != M_HRR) {
+      auto kern = k_fine3s<LAT, DEV, S, MODEL, NT, TXH, TYH, MINW>;
+      const int ntx = (g.nf[0] - 2 + TXH - 3) / (TXH - 2), nty = (g.nf[1] - 2 + TYH - 3) / (TYH - 2);
+      const int zcap = window_zcap();
+      if (zcap < 1) throw LbmError(LBM_EUNSUPPORTED, "fine planes too large for the one-pass fused kernel");
+      const ZRuns r = zruns_tiles(ntx, nty, occupancy_slots(kern, f3_slots[v], TXH * TYH), zcap);
+      hipLaunchKernelGGL(kern, dim3((unsigned)(r.per * kXCD)), dim3(TXH * TYH), 0, s, src, dst, half, g,
+                         (S)(1.0 - 1.0 / tau_f), r.ntx, r.nty, r.nzc, r.zlen, r.per);
+    }
+  }
+  // One H-RR fine substep in one pass (D3Q19): fine H-RR role variant 2 is
+  // k_hrr3 (30 x 6 tiles of vectors), variant 3 k_hrr3s (one node per lane,
+  // 64 x 8 lanes in FP32, 34 x 8 in FP64); variants 0 and 1 run the velocity
+  // pass and k_collide_hrr (capped at 2 / 3 resident work groups).  On the
+  // 385^3 patch in FP32, per substep: k_hrr3 2.78 ms, k_hrr3s 3.20 ms, the
+  // two-pass form 1.0 + 1.78 ms; the one-pass kernels save the velocity
+  // pass's traffic but re-read their tile halos from HBM.
   bool hrr_one_pass3() const { return D == 3 && desc.collision == LBM_HRR && var[3] >= 2; }
   int hrr_lds_var(int v) const { return (D == 3 && desc.collision == LBM_HRR) ? (v == 0 ? 2 : 1) : v; }
   template <int TXV, int TY>
@@ -498,10 +503,29 @@ struct Grid final : GridBase {
                          (S)(1.0 - 1.0 / tau_f), (S)tau_f, (S)sig, r.ntx, r.nty, r.nzc, r.zlen, r.per);
     }
   }
+  template <int TXH, int TYH>
+  void go_hrr3s(const S* src, S* dst, const S* mac, hipStream_t s, int v) {
+    if constexpr (D == 3) {
+      auto kern = k_hrr3s<LAT, DEV, S, NT, TXH, TYH, 1>;
+      const int ntx = (g.nf[0] - 2 + TXH - 3) / (TXH - 2), nty = (g.nf[1] - 2 + TYH - 3) / (TYH - 2);
+      const int zcap = window_zcap();
+      // the velocity planes are read through a window of 2^31 bytes as well
+      if (zcap < 1 || (double)(1 + D) * g.Nfp * sizeof(S) >= 2147483648.0)
+        throw LbmError(LBM_EUNSUPPORTED, "fine level too large for the one-pass H-RR kernel");
+      const ZRuns r = zruns_tiles(ntx, nty, occupancy_slots(kern, h3_slots[v], TXH * TYH), zcap);
+      hipLaunchKernelGGL(kern, dim3((unsigned)(r.per * kXCD)), dim3(TXH * TYH), 0, s, src, dst, mac, g,
+                         (S)(1.0 - 1.0 / tau_f), (S)tau_f, (S)sig, r.ntx, r.nty, r.nzc, r.zlen, r.per);
+    }
+  }
   void launch_hrr3(const S* src, S* dst, const S* mac, hipStream_t s, int v = -1) {
     if (v < 0) v = var[3];
-    if (v == 2) go_hrr3<30, 6>(src, dst, mac, s, 2);
-    else go_hrr3<62, 2>(src, dst, mac, s, 3);
+    if constexpr (sizeof(S) == 4) {
+      if (v == 2) go_hrr3<30, 6>(src, dst, mac, s, 2);
+      else go_hrr3s<64, 8>(src, dst, mac, s, 3);
+    } else {
+      if (v == 2) go_hrr3<30, 6>(src, dst, mac, s, 2);
+      else go_hrr3s<34, 8>(src, dst, mac, s, 3);
+    }
   }
   template <int MODEL>
   void launch_fused(const S* src, S* dst, S* half, hipStream_t s, int v = -1) {
@@ -513,9 +537,12 @@ struct Grid final : GridBase {
         case 2: go_fine2<MODEL, 32, 16>(src, dst, half, s); break;
         default: go_fine2<MODEL, 32, 8>(src, dst, half, s); break;
       }
+    } else if constexpr (sizeof(S) == 4) {
+      if (v == 2) go_fine3s<MODEL, 66, 14, 1>(src, dst, half, s, 2);
+      else go_fine3s<MODEL, 64, 8, 1>(src, dst, half, s, 3);
     } else {
-      if (v == 2) go_fine3<MODEL, 14, 14, 2>(src, dst, half, s, 2);
-      else go_fine3<MODEL, 30, 6, 2>(src, dst, half, s, 3);
+      if (v == 2) go_fine3s<MODEL, 34, 14, 1>(src, dst, half, s, 2);
+      else go_fine3s<MODEL, 34, 8, 1>(src, dst, half, s, 3);
     }
   }
 
@@ -535,7 +562,7 @@ struct Grid final : GridBase {
     }
   }
   // True when this step runs both fine substeps in one kernel.
-  bool fused_now() const { return fused && (D == 2 || var[1] >= 2); }
+  bool fused_now() const { return fused && !sensors_on && (D == 2 || var[1] >= 2); }
   // LDS variant of the fine k_stream launches for fine-role variant v.
   int fine_lds_var(int v) const { return (fused && D == 3) ? (v == 0 ? 2 : 1) : v; }
   // Fine-level pull-stream + collide (BGK, RR): the timed kernel.
@@ -598,6 +625,7 @@ struct Grid final : GridBase {
   void tune(int reps, int32_t* out) override {
     HIPCHK(hipSetDevice(device));
     HIPCHK(hipStreamSynchronize(stream));
+    sens_ready = false;  // the trial launches overwrite the previous states
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -610,7 +638,12 @@ struct Grid final : GridBase {
 
       float best = -1.f;
       for (int v = 0; v < NVAR; ++v) {
-        role_launch(role, v, stream);
+        try {
+          role_launch(role, v, stream);
+        } catch (const LbmError& e) {
+          if (e.code != LBM_EUNSUPPORTED) throw;
+          continue;  // this variant does not apply to the grid
+        }
         HIPCHK(hipEventRecord(e0, stream));
         for (int k = 0; k < reps; ++k) role_launch(role, v, stream);
         HIPCHK(hipEventRecord(e1, stream));
@@ -770,12 +803,115 @@ struct Grid final : GridBase {
   void step(int n, hipStream_t s) override {
     HIPCHK(hipSetDevice(device));
     for (int k = 0; k < n; ++k) {
+      if (sensors_on) sensors_before(s);
       if (!g.has_fine) step_uniform(s);
       else if (desc.collision == LBM_BGK) step_two_level<M_BGK>(s);
       else if (desc.collision == LBM_RR) step_two_level<M_RR>(s);
       else step_two_level<M_HRR>(s);
+      if (sensors_on) sensors_after(s);
+      if (probe_level >= 0) {
+        // the level's post-collision state at the probe (its density is
+        // the pre-collision one); the ring is complete at interior nodes
+        const S* src = probe_level == 0 ? cur_c() : fineA();
+        hipLaunchKernelGGL((k_probe<LAT, DEV, S>), dim3(1), dim3(64), 0, s, src, probe_pos, pSeries.as<double>(),
+                           pCount.as<int64_t>(), probe_cap);
+      }
     }
+    if (n > 0) sens_ready = sensors_on;
     HIPCHK(hipGetLastError());
+  }
+
+  // NH sensors (Sec. 7): velocities of the iteration before the step's last
+  // one.  Coarse: the state at t.  Fine: the moments of what the non-ring
+  // nodes pull from the state at t (the pre-collision state at t+1/2); the
+  // ring's t+1/2 velocities are interpolated from the history after the
+  // step, when its t+1 level exists.
+  void sensors_before(hipStream_t s) {
+    hipLaunchKernelGGL((k_sens_vel<LAT, DEV, S, 0, false>), dim3(blocks(g.Nc, 256)), dim3(256), 0, s, cur_c(),
+                       sUc.as<double>(), g);
+    if (g.has_fine)
+      hipLaunchKernelGGL((k_sens_vel<LAT, DEV, S, 1, true>), dim3(blocks(g.Nf, 256)), dim3(256), 0, s, fineA(),
+                         sUf.as<double>(), g);
+  }
+  void sensors_after(hipStream_t s) {
+    if (!g.has_fine) return;
+    // after the step the history levels t-1, t, t+1 are hs[2], hs[0], hs[1]
+    hipLaunchKernelGGL((k_ring_macro<LAT, double>), dim3(xblocks(itf.NR, kIfaceBlock)), dim3(kIfaceBlock), 0, s,
+                       hist[hs[2]].as<double>(), hist[hs[0]].as<double>(), hist[hs[1]].as<double>(), -1.0 / 8.0,
+                       3.0 / 4.0, 3.0 / 8.0, sUf.as<double>(), g, itf);
+  }
+  void sensors_enable(bool on) override {
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (on && !sUc.p) {
+      auto zalloc = [](DevBuf& b, size_t bytes) {
+        b.alloc(bytes);
+        HIPCHK(hipMemset(b.p, 0, bytes));
+      };
+      zalloc(sUc, sizeof(double) * (1 + D) * (size_t)g.Ncp);
+      if (g.has_fine) zalloc(sUf, sizeof(double) * (1 + D) * (size_t)g.Nfp);
+      const size_t Nmax = (size_t)std::max(g.Nc, g.Nf);
+      sFlags.alloc(Nmax);
+      sProd.alloc(sizeof(double) * 3 * Nmax);
+    }
+    sensors_on = on;
+    sens_ready = false;
+  }
+  void sensors(int level, double thr, uint8_t* flags, double* prod, bool dev) override {
+    HIPCHK(hipSetDevice(device));
+    if (!sensors_on || !sens_ready)
+      throw LbmError(LBM_EINVAL, "NH sensors: enable them, then step at least once before reading them");
+    complete_ring();
+    const int64_t N = nodes(level);
+    double* pr = prod ? sProd.as<double>() : nullptr;
+    uint8_t* fl = sFlags.as<uint8_t>();
+    if (level == 0)
+      hipLaunchKernelGGL((k_sensors<LAT, DEV, S, 0>), dim3(blocks(N, 256)), dim3(256), 0, stream, sUc.as<double>(),
+                         cur_c(), cbuf[cpar ^ 1].as<S>(), fl, pr, g, thr);
+    else
+      hipLaunchKernelGGL((k_sensors<LAT, DEV, S, 1>), dim3(blocks(N, 256)), dim3(256), 0, stream, sUf.as<double>(),
+                         fineA(), fineB(), fl, pr, g, thr);
+    HIPCHK(hipGetLastError());
+    const hipMemcpyKind k = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    HIPCHK(hipMemcpyAsync(flags, fl, (size_t)N, k, stream));
+    if (prod) HIPCHK(hipMemcpyAsync(prod, pr, sizeof(double) * 3 * (size_t)N, k, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+  }
+  void probe_enable(int level, const int32_t* node, int64_t capacity) override {
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (level < 0) {
+      probe_level = -1;
+      return;
+    }
+    const int nx = level == 0 ? g.n[0] : g.nf[0], ny = level == 0 ? g.n[1] : g.nf[1],
+              nz = level == 0 ? g.n[2] : g.nf[2];
+    for (int d = 0; d < 3; ++d)
+      if (node[d] < 0 || node[d] >= (d == 0 ? nx : d == 1 ? ny : nz))
+        throw LbmError(LBM_EINVAL, "probe node outside the level");
+    if (level == 0 && g.has_fine && coarse_class(g, node[0], node[1], node[2]) == CC_COVERED)
+      throw LbmError(LBM_EINVAL, "probe on a covered coarse node (not evolved): probe the fine level there");
+    if (level == 1 && fine_is_ring(g, node[0], node[1], node[2]))
+      throw LbmError(LBM_EINVAL, "probe on a fine ring node (rebuilt, not evolved)");
+    if (capacity < 1) throw LbmError(LBM_EINVAL, "probe capacity must be positive");
+    if (pSeries.p) HIPCHK(hipFree(pSeries.p));
+    pSeries.p = nullptr;
+    pSeries.alloc(sizeof(double) * (size_t)capacity);
+    if (!pCount.p) pCount.alloc(sizeof(int64_t));
+    HIPCHK(hipMemset(pCount.p, 0, sizeof(int64_t)));
+    probe_level = level;
+    probe_pos = level == 0 ? cpos(g, node[0], node[1], node[2]) : fpos(g, node[0], node[1], node[2]);
+    probe_cap = capacity;
+  }
+  int64_t probe_read(double* out, int64_t max) override {
+    HIPCHK(hipSetDevice(device));
+    if (probe_level < 0) throw LbmError(LBM_EINVAL, "no probe enabled");
+    HIPCHK(hipStreamSynchronize(stream));
+    int64_t c = 0;
+    HIPCHK(hipMemcpy(&c, pCount.p, sizeof(int64_t), hipMemcpyDeviceToHost));
+    const int64_t n = std::min(c, max);
+    if (n > 0) HIPCHK(hipMemcpy(out, pSeries.p, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost));
+    return c;
   }
 
   void upload(DevBuf& dst, const double* src, size_t n, bool dev) {
@@ -802,6 +938,7 @@ struct Grid final : GridBase {
 
   void set_state(int level, const double* rho, const double* u, bool dev) override {
     HIPCHK(hipSetDevice(device));
+    sens_ready = false;
     HIPCHK(hipDeviceSynchronize());
     // a coarse reset replaces the history the ring completion reads
     if (level == 0) complete_ring();
@@ -847,6 +984,7 @@ struct Grid final : GridBase {
 
   void set_pops(int level, const double* f, bool dev) override {
     HIPCHK(hipSetDevice(device));
+    sens_ready = false;
     HIPCHK(hipDeviceSynchronize());
     if (level == 0) complete_ring();
     else ring_partial = false;
@@ -1807,6 +1945,31 @@ int lbm_get_totals_noalloc(lbm_handle h, double mass[2], double momentum[6]) {
       return LBM_EUNSTABLE;
     }
   return LBM_OK;
+}
+
+int lbm_sensors_enable(lbm_handle h, int on) {
+  if (!h) return LBM_EINVAL;
+  return guard(h, [&] { h->impl->sensors_enable(on != 0); });
+}
+
+int lbm_sensors(lbm_handle h, int level, double threshold, uint8_t* flags, double* diag, int mem) {
+  if (bad_level(h, level) || !flags || (mem != LBM_HOST && mem != LBM_DEVICE) || !(threshold >= 0.0))
+    return LBM_EINVAL;
+  return guard(h, [&] {
+    HIPCHK(hipDeviceSynchronize());
+    h->impl->sensors(level, threshold, flags, diag, mem == LBM_DEVICE);
+  });
+}
+
+int lbm_probe_enable(lbm_handle h, int level, const int32_t node[3], int64_t capacity) {
+  if (!h || level < -1 || level > 1 || (level == 1 && !h->impl->g.has_fine) || (level >= 0 && !node))
+    return LBM_EINVAL;
+  return guard(h, [&] { h->impl->probe_enable(level, node, capacity); });
+}
+
+int lbm_probe_read(lbm_handle h, double* out, int64_t max, int64_t* count) {
+  if (!h || !count || max < 0 || (max > 0 && !out)) return LBM_EINVAL;
+  return guard(h, [&] { *count = h->impl->probe_read(out, max); });
 }
 
 int lbm_get_index_maps(lbm_handle h, int level, uint8_t* cls, int mem) {

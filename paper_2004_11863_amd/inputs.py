@@ -8,6 +8,9 @@ same inputs can be handed to the HIP library and to the CPU oracle.
   eps = 0.15 U, R_c = 5 coarse cells.
 * Gaussian acoustic pulse, eq init_Pulse (Sec. 8.2), taken radially in 2D/3D
   on top of a uniform mean flow.
+* The quasi-one-dimensional cases of Sec. 8: the plane convected shear wave
+  of eq init_ShearW and the plane upstream-running acoustic wave of eq
+  init_Pulse, both invariant along y.
 * Uniform flow.
 
 Coordinates are in coarse lattice units; coarse node (i, j, k) sits at
@@ -98,12 +101,35 @@ class Pulse:
 
 
 @dataclass
+class ShearWave:
+    """Plane shear wave of eq init_ShearW (Sec. 8.1): a transverse velocity
+    U_y exp(-(x - x_c)^2 / (2 R^2)) on top of the mean flow, invariant along y."""
+
+    xc: float
+    Uy: float = 0.1 * CS
+    R: float = 5.0
+
+
+@dataclass
+class PlanePulse:
+    """Plane acoustic wave of eq init_Pulse (Sec. 8.2): a density excess
+    rho' = rho0 A exp(-(x - x_c)^2 / (2 R^2)) with u_x lowered by
+    (rho' / rho0) c_s, the acoustic wave that runs towards -x."""
+
+    xc: float
+    A: float = 1e-4
+    R: float = 5.0
+
+
+@dataclass
 class Workload:
     geom: Geometry
     U: tuple = (0.0, 0.0, 0.0)
     vortices: list = field(default_factory=list)
     pulses: list = field(default_factory=list)
     rho0: float = 1.0
+    shear_waves: list = field(default_factory=list)
+    plane_pulses: list = field(default_factory=list)
 
 
 def fields(wl: Workload, level: int):
@@ -131,6 +157,14 @@ def fields(wl: Workload, level: int):
             dd = _min_image(X[d] - p.center[d], g.n[d])
             r2 += dd * dd
         rho = rho * (1.0 + p.A * np.exp(-r2 / (2.0 * p.R ** 2)))
+    for w in wl.shear_waves:
+        dx = _min_image(X[0] - w.xc, g.n[0])
+        u[1] += w.Uy * np.exp(-dx * dx / (2.0 * w.R ** 2))
+    for p in wl.plane_pulses:
+        dx = _min_image(X[0] - p.xc, g.n[0])
+        drho = wl.rho0 * p.A * np.exp(-dx * dx / (2.0 * p.R ** 2))
+        rho = rho + drho
+        u[0] -= drho / wl.rho0 * CS
     return np.ascontiguousarray(rho), np.ascontiguousarray(u)
 
 
@@ -183,6 +217,39 @@ def config3(seed: int = 0, n: int = 384) -> Workload:
     pc = tuple(float(hi[0]) + rng.uniform(-off, off) if d == 0 else 0.5 * n + rng.uniform(-off, off)
                for d in range(3))
     return Workload(geom=geom, U=(U, 0.0, 0.0), pulses=[Pulse(center=pc, A=1e-3)])
+
+
+# --------------------------------------------------------------------------
+# The quasi-one-dimensional cases of Sec. 8.  The paper runs them one coarse
+# cell thick with non-reflecting ends; here the box is periodic and a fine
+# band spans the x range of the paper's fine region, `height` coarse cells
+# along y (its y edges are interfaces as well).  Nodes farther from those
+# edges than the edges' influence has travelled hold the y-invariant
+# solution of the paper's one-dimensional case.  Coordinates of the paper's
+# set-up are shifted by `shift` along x.
+
+def shear_wave_case(height: int = 256, left: int = 350, right: int = 550, U: float = 0.1 * CS) -> Workload:
+    """Eqs init_ShearW / init_ShearW2: rho0 = 1, U_x = U_y = 0.1 c_s, R_c = 5,
+    x_c = 150; fine for x < 250 (from -left), coarse beyond (to 250 + right)."""
+    shift = left + 50
+    n = (shift + 250 + right, height + 10, 1)
+    lo = (shift - left, 5, 0)
+    hi = (shift + 250, 5 + height, 0)
+    geom = Geometry(2, n, lo, hi)
+    return Workload(geom=geom, U=(U, 0.0, 0.0), shear_waves=[ShearWave(xc=shift + 150.0, Uy=U)])
+
+
+def acoustic_wave_case(height: int = 256, left: int = 900, right: int = 400, A: float = 1e-4,
+                       U: float = 0.1 * CS) -> Workload:
+    """Eqs init_Pulse / init_Pulse2: rho0 = 1, U_x = 0.1 c_s, A = 1e-4,
+    R_c = 5, x_c = 750; fine for 500 < x < 1000, coarse below 500 (from
+    500 - left) and above 1000 (to 1000 + right)."""
+    shift = left - 500
+    n = (shift + 1000 + right, height + 10, 1)
+    lo = (shift + 500, 5, 0)
+    hi = (shift + 1000, 5 + height, 0)
+    geom = Geometry(2, n, lo, hi)
+    return Workload(geom=geom, U=(U, 0.0, 0.0), plane_pulses=[PlanePulse(xc=shift + 750.0, A=A)])
 
 
 def batch_instance(seed: int, i: int) -> Workload:

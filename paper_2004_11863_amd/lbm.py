@@ -32,7 +32,8 @@ LBM_N_VARIANTS = 4
 
 EXPORTS = (
     "lbm_create_grid", "lbm_destroy", "lbm_set_state", "lbm_step", "lbm_get_macros",
-    "lbm_set_populations", "lbm_get_populations", "lbm_get_totals", "lbm_get_totals_noalloc", "lbm_get_index_maps",
+    "lbm_set_populations", "lbm_get_populations", "lbm_get_totals", "lbm_get_totals_noalloc", "lbm_sensors_enable", "lbm_sensors",
+    "lbm_probe_enable", "lbm_probe_read", "lbm_get_index_maps",
     "lbm_level_dims", "lbm_lattice_info", "lbm_interface_counts", "lbm_interface_tables",
     "lbm_updates_per_step", "lbm_profile_enable", "lbm_kernel_time", "lbm_tune", "lbm_set_variants",
     "lbm_last_error", "lbm_batch_create", "lbm_batch_destroy", "lbm_batch_add", "lbm_batch_remove",
@@ -78,6 +79,10 @@ def load(path: str = LIB_PATH):
     L.lbm_get_populations.argtypes = [vp, ip, vp, ip]
     L.lbm_get_totals.argtypes = [vp, dp, dp]
     L.lbm_get_totals_noalloc.argtypes = [vp, dp, dp]
+    L.lbm_sensors_enable.argtypes = [vp, ip]
+    L.lbm_sensors.argtypes = [vp, ip, ctypes.c_double, vp, vp, ip]
+    L.lbm_probe_enable.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64]
+    L.lbm_probe_read.argtypes = [vp, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     L.lbm_get_index_maps.argtypes = [vp, ip, vp, ip]
     L.lbm_level_dims.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int32)]
     L.lbm_lattice_info.argtypes = [ip, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -237,6 +242,32 @@ def lbm_get_totals_noalloc(h):
     return np.array(mass[:]), np.array(mom[:]).reshape(2, 3)
 
 
+def lbm_sensors_enable(h, on=True):
+    _check(load().lbm_sensors_enable(h, 1 if on else 0), h)
+
+
+def lbm_sensors(h, level, threshold, flags, diag=None):
+    """NH-sensor flags of a level after the last step into `flags` (uint8 per
+    node, host numpy array or device tensor); `diag` optionally receives
+    [3][N] doubles (divergence product, curl product, ghost norm)."""
+    p, m = _ptr(flags)
+    dptr = None if diag is None else _ptr(diag)[0]
+    _check(load().lbm_sensors(h, level, float(threshold), p, dptr, m), h)
+
+
+def lbm_probe_enable(h, level, node=(0, 0, 0), capacity=1):
+    nd = (ctypes.c_int32 * 3)(*[int(x) for x in (list(node) + [0, 0, 0])[:3]])
+    _check(load().lbm_probe_enable(h, int(level), nd, int(capacity)), h)
+
+
+def lbm_probe_read(h, max_values):
+    out = np.zeros(int(max_values))
+    cnt = ctypes.c_int64()
+    _check(load().lbm_probe_read(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(max_values),
+                                 ctypes.byref(cnt)), h)
+    return out[: min(cnt.value, int(max_values))], cnt.value
+
+
 def lbm_get_index_maps(h, level, out):
     p, m = _ptr(out)
     _check(load().lbm_get_index_maps(h, level, p, m), h)
@@ -342,6 +373,15 @@ class Grid:
 
     def totals(self):
         return lbm_get_totals(self.h)
+
+    def sensors(self, level, threshold):
+        """(flags[N] uint8, diag[3, N]) of the NH sensors after the last step
+        (sensors must have been enabled before that step)."""
+        N = self.nodes(level)
+        flags = np.zeros(N, np.uint8)
+        diag = np.zeros((3, N))
+        lbm_sensors(self.h, level, threshold, flags, diag)
+        return flags, diag
 
     def class_map(self, level):
         out = np.zeros(self.nodes(level), np.uint8)

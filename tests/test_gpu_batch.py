@@ -55,6 +55,10 @@ def _add(batch, wl):
 def _check_same(batch, sl, alone):
     out, live = alone
     b0 = batch.get_populations(sl, 0)
+    # every stored value of the batch member is finite, covered nodes included
+    assert np.isfinite(b0).all()
+    if len(out) > 1:
+        assert np.isfinite(out[1]).all()
     assert np.array_equal(b0[:, live], out[0][:, live])
     if len(out) > 1:
         assert np.array_equal(batch.get_populations(sl, 1), out[1])
@@ -210,3 +214,63 @@ def test_batch_calls_from_two_threads_beside_graph_capture():
         _check_same(a, sl, _alone(w, "RR", lbm.LBM_FP32_DEV, rounds * per))
     a.close()
     b.close()
+
+
+def _oracle_run(w, model, steps, tau_c=0.51, sigma=0.995):
+    g = w.geom
+    D = g.D
+    lo = g.lo[:D] if g.has_fine else None
+    hi = g.hi[:D] if g.has_fine else None
+    ref = O.Grid(O.D2Q9 if D == 2 else O.D3Q19, {"BGK": O.BGK, "RR": O.RR, "HRR": O.HRR}[model], g.n[:D], lo, hi,
+                 tau_c=tau_c, sigma=sigma)
+    for lv in ((0, 1) if g.has_fine else (0,)):
+        ref.set_state(lv, *I.fields(w, lv))
+    ref.step(steps)
+    return ref
+
+
+@pytest.mark.parametrize("model", ["RR", "HRR"])
+def test_batch_d2q9_fp32_matches_oracle(model):
+    """Four D2Q9 grids (three two-level of different shapes, one uniform) in
+    one FP32 batch (graph replay, fused fine phase for RR), each against the
+    FP64 oracle at the FP32 bar: density max-abs < 1e-5, velocity relative
+    L2 < 1e-4."""
+    lbm = _lbm()
+    mcode = {"RR": lbm.LBM_RR, "HRR": lbm.LBM_HRR}[model]
+    batch = lbm.Batch(lbm.LBM_D2Q9, mcode, lbm.LBM_FP32_DEV, capacity=4)
+    wls = [_wl(g, k) for k, g in enumerate(_geoms2d())]
+    assert sum(not w.geom.has_fine for w in wls) == 1
+    slots = [_add(batch, w) for w in wls]
+    batch.tune(reps=1)
+    steps = 60
+    batch.step(steps)
+    for w, sl in zip(wls, slots):
+        ref = _oracle_run(w, model, steps)
+        for lv in ((0, 1) if w.geom.has_fine else (0,)):
+            r1, u1 = batch.get_macros(sl, lv)
+            r0, u0 = ref.get_macros(lv)
+            assert np.isfinite(r1).all() and np.isfinite(u1).all()
+            assert np.abs(r1 - r0).max() < 1e-5, (sl, lv)
+            assert np.linalg.norm(u1 - u0) / np.linalg.norm(u0) < 1e-4, (sl, lv)
+    batch.close()
+
+
+@pytest.mark.parametrize("model", ["BGK", "RR", "HRR"])
+def test_batch_d2q9_fp64_matches_oracle(model):
+    """The same four D2Q9 grids in one FP64 batch: 1e-12 relative on rho and
+    u of both levels against the oracle."""
+    lbm = _lbm()
+    mcode = {"BGK": lbm.LBM_BGK, "RR": lbm.LBM_RR, "HRR": lbm.LBM_HRR}[model]
+    batch = lbm.Batch(lbm.LBM_D2Q9, mcode, lbm.LBM_FP64, capacity=4)
+    wls = [_wl(g, k) for k, g in enumerate(_geoms2d())]
+    slots = [_add(batch, w) for w in wls]
+    steps = 40
+    batch.step(steps)
+    for w, sl in zip(wls, slots):
+        ref = _oracle_run(w, model, steps)
+        for lv in ((0, 1) if w.geom.has_fine else (0,)):
+            r1, u1 = batch.get_macros(sl, lv)
+            r0, u0 = ref.get_macros(lv)
+            assert np.abs(r1 - r0).max() <= 1e-12 * np.abs(r0).max(), (sl, lv)
+            assert np.abs(u1 - u0).max() <= 1e-12 * np.abs(u0).max(), (sl, lv)
+    batch.close()

@@ -13,6 +13,15 @@ pytestmark = pytest.mark.gpu
 TOL64 = 1e-12
 
 
+def _all_stored_finite(gpu):
+    """Every stored population of both levels is finite, the unspecified
+    covered coarse nodes included: a kernel that leaves LDS slots of skipped
+    lanes unwritten and reads them shows up here first."""
+    for lv in ((0, 1) if gpu.shape[1] is not None else (0,)):
+        f = gpu.get_populations(lv)
+        assert np.isfinite(f).all(), ("non-finite stored value", lv)
+
+
 def _lbm():
     from paper_2004_11863_amd import lbm
     return lbm
@@ -271,6 +280,7 @@ def test_every_kernel_variant_gives_identical_results(prec, model):
             live = gpu.class_map(0) != lbm.LBM_C_COVERED
         gpu.set_variants([v, v, v, v])
         gpu.step(12)
+        _all_stored_finite(gpu)
         out = (gpu.get_populations(0)[:, live], gpu.get_populations(1))
         gpu.close()
         if ref is None:
@@ -301,6 +311,7 @@ def test_variants_on_ragged_3d_and_2d(D):
         gpu, orc, levels = make_pair(wl, "RR", lbm.LBM_FP64, with_oracle=(v == 0))
         gpu.set_variants([v, v, v, v])
         gpu.step(9)
+        _all_stored_finite(gpu)
         if v == 0:
             orc.step(9)
             w = compare_fp64(gpu, orc, levels)
@@ -329,6 +340,7 @@ def test_d3q19_hrr_one_pass_variants(prec):
         gpu, orc, levels = make_pair(wl, "HRR", p, with_oracle=check)
         gpu.set_variants([0, 0, 0, v])
         gpu.step(5)
+        _all_stored_finite(gpu)
         if check:
             orc.step(5)
             w = compare_fp64(gpu, orc, levels)
@@ -340,3 +352,44 @@ def test_d3q19_hrr_one_pass_variants(prec):
             ref = out
         else:
             assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1]), v
+
+
+@pytest.mark.parametrize("model,role", [("RR", 1), ("HRR", 3)])
+def test_full_size_one_pass_variants_bitwise(model, role):
+    """The D3Q19 384^3 grid: the one-node-per-lane marching kernels (both
+    fine substeps in one launch for RR, one H-RR substep in one pass), in both
+    tile shapes, against the two-launch path, populations of both levels
+    compared bit for bit on the device after three coarse steps (their runs
+    and storage windows at the real size)."""
+    import torch
+    lbm = _lbm()
+    wl = I.config3(seed=0, n=384)
+    mcode = {"RR": lbm.LBM_RR, "HRR": lbm.LBM_HRR}[model]
+
+    def run(v):
+        g = wl.geom
+        grid = lbm.Grid(lbm.LBM_D3Q19, mcode, lbm.LBM_FP32_DEV, g.n, g.lo, g.hi, tau_coarse=0.51)
+        for lv in (0, 1):
+            grid.set_state(lv, *I.fields(wl, lv))
+        vv = [0, 0, 0, 0]
+        vv[role] = v
+        grid.set_variants(vv)
+        grid.step(3)
+        out = []
+        for lv in (0, 1):
+            f = torch.empty((grid.Q, grid.nodes(lv)), dtype=torch.float64, device="cuda")
+            lbm.lbm_get_populations(grid.h, lv, f)
+            out.append(f)
+        live = torch.from_numpy(grid.class_map(0) != lbm.LBM_C_COVERED).cuda()
+        grid.close()
+        return out, live
+
+    ref, live = run(0)
+    assert all(bool(torch.isfinite(f).all()) for f in ref)
+    for v in (2, 3):
+        out, _ = run(v)
+        assert torch.equal(out[0][:, live], ref[0][:, live]), v
+        assert torch.equal(out[1], ref[1]), v
+        del out
+    del ref
+    torch.cuda.empty_cache()

@@ -1,0 +1,170 @@
+"""GPU NH sensors (Sec. 7) and probe recording against the CPU oracle.
+
+The flags depend on the sign of products of small derivatives, so they are
+compared on every node whose tested quantity lies outside a rounding band
+around the decision point, and the diagnostic values agree within the same
+band.  FP64 storage: band 1e-9 of each quantity's largest value (the two
+sides differ by rounding only, ~1e-15 relative in u).  FP32 deviation
+storage: the band follows from the measured errors of the level's state.
+With du the largest velocity error and df the largest population error, a
+centred difference (u(x+1) - u(x-1)) / 2 summed over D axes is off by at
+most e = D du (taken twice for the state of the step before); a product of
+two such values of size <= m is off by at most 2 e m + e^2 per component
+(one for the divergence and the 2D curl, three for the 3D curl dot
+product), with m bounded by the square root of the largest |product| plus
+e; the ghost norm is off by at most sqrt(Q) df (taken four times, for the
+pre-collision state it reads)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2004_11863_amd import inputs as I
+from parity_util import make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _lbm():
+    from paper_2004_11863_amd import lbm
+    return lbm
+
+
+def _fp32_bands(gpu, ref, level, dp, cp):
+    r1, u1 = gpu.get_macros(level)
+    r0, u0 = ref.get_macros(level)
+    f1 = gpu.get_populations(level)
+    f0 = ref.get_populations(level)
+    if level == 0:
+        m = ref.class_map(0) != O.C_COVERED
+        u1, u0, f1, f0 = u1[:, m], u0[:, m], f1[:, m], f0[:, m]
+    D = u0.shape[0]
+    Q = f0.shape[0]
+    e = 2.0 * D * float(np.abs(u1 - u0).max())
+    out = []
+    for prod, K in ((dp, 1), (cp, 1 if D == 2 else 3)):
+        mm = math.sqrt(float(np.abs(prod).max())) + e
+        out.append(K * (2.0 * e * mm + e * e))
+    out.append(4.0 * math.sqrt(Q) * float(np.abs(f1 - f0).max()))
+    return out
+
+
+def _compare(gpu, ref, level, thr, band=None):
+    """band: relative band (FP64); None: bands from the FP32 state errors."""
+    fl1, dg = gpu.sensors(level, thr)
+    fl0, dp, cp, gn = ref.sensors(level, thr)
+    if band is None:
+        bd, bc, bg = _fp32_bands(gpu, ref, level, dp, cp)
+    else:
+        bd = band * max(np.abs(dp).max(), 1e-300)
+        bc = band * max(np.abs(cp).max(), 1e-300)
+        bg = band * max(np.abs(gn).max(), 1e-300)
+    assert np.abs(dg[0] - dp).max() <= bd, (np.abs(dg[0] - dp).max(), bd)
+    assert np.abs(dg[1] - cp).max() <= bc, (np.abs(dg[1] - cp).max(), bc)
+    assert np.abs(dg[2] - gn).max() <= bg, (np.abs(dg[2] - gn).max(), bg)
+    ma = np.abs(dp) > bd
+    ms = np.abs(cp) > bc
+    mg = ma & ms & (np.abs(gn - thr) > bg)
+    # FP64: most nodes are compared.  FP32: in these nearly divergence-free
+    # flows the divergence lies below the FP32 band at most nodes, so fewer are.
+    lo = 0.5 if band is not None else 0.1
+    assert ma.mean() > lo and ms.mean() > lo and mg.mean() > lo / 5, (ma.mean(), ms.mean(), mg.mean())
+    assert np.array_equal(fl1[ma] & 1, fl0[ma] & 1), (level, "Ac")
+    assert np.array_equal(fl1[ms] & 2, fl0[ms] & 2), (level, "S")
+    assert np.array_equal(fl1[mg], fl0[mg]), (level, np.nonzero(fl1[mg] != fl0[mg])[0][:10])
+    return fl1
+
+
+@pytest.mark.parametrize("prec,band", [("fp64", 1e-9), ("fp32", None)])
+@pytest.mark.parametrize("model", ["BGK", "RR", "HRR"])
+def test_sensors_d2q9_config1(model, prec, band):
+    lbm = _lbm()
+    p = lbm.LBM_FP64 if prec == "fp64" else lbm.LBM_FP32_DEV
+    gpu, ref, levels = make_pair(I.config1(1), model, p)
+    lbm.lbm_sensors_enable(gpu.h, True)
+    gpu.step(25)
+    ref.step(25)
+    thr = 1e-8
+    for lv in levels:
+        fl = _compare(gpu, ref, lv, thr, band)
+        assert fl.any()
+    gpu.close()
+
+
+@pytest.mark.parametrize("model", ["RR", "HRR"])
+def test_sensors_d3q19_two_level_fp64(model):
+    lbm = _lbm()
+    geom = I.Geometry(3, (22, 20, 24), (5, 4, 6), (15, 14, 17))
+    wl = I.Workload(geom=geom, U=(0.1 / math.sqrt(3), 0.01, -0.005),
+                    pulses=[I.Pulse(center=(15.2, 9.6, 11.1), A=1e-3, R=2.5)])
+    gpu, ref, levels = make_pair(wl, model, lbm.LBM_FP64)
+    lbm.lbm_sensors_enable(gpu.h, True)
+    gpu.step(9)
+    ref.step(9)
+    for lv in levels:
+        _compare(gpu, ref, lv, 1e-8, 1e-9)
+    gpu.close()
+
+
+def test_sensors_flag_spurious_ac_mode_everywhere():
+    """An LSA SpuriousAc eigenmode on a uniform D2Q9 grid: every node flagged
+    after one step, on the GPU as in the oracle (Sec. 5, Sec. 7)."""
+    from oracle import lsa
+    lbm = _lbm()
+    L, n, tau = 32, 15, 0.51
+    CS = math.sqrt(1 / 3)
+    s = lsa.Scheme("D2Q9", "RR", tau)
+    k = np.array([2 * math.pi * n / L, 0.0])
+    ub = np.array([0.1 * CS, 0.0])
+    lam, V = s.eig(1.0, ub, k)
+    M = lsa.macro_content(s, V)
+    wr, _ = lsa.omega(lam)
+    cand = [i for i in range(len(lam)) if abs(lam[i]) > 0.3 and abs(abs(wr[i]) - math.pi) < 0.35
+            and abs(M[1, i]) > 1e-3 * np.linalg.norm(V[:, i])]
+    i = min(cand, key=lambda j: abs(abs(wr[j]) - math.pi))
+    F = np.exp(-1j * (s.xi @ k)) * V[:, i]
+    X = np.tile(np.arange(L), L)
+    f = O.feq(O.D2Q9, 1.0, ub)[:, None] + 1e-6 * np.real(F[:, None] * np.exp(-1j * (k[0] * X + 0.37))[None, :])
+    gpu = lbm.Grid(lbm.LBM_D2Q9, lbm.LBM_RR, lbm.LBM_FP64, (L, L), tau_coarse=tau)
+    gpu.set_populations(0, f)
+    lbm.lbm_sensors_enable(gpu.h, True)
+    gpu.step(1)
+    fl, dg = gpu.sensors(0, 1e-12)
+    assert (fl & 1).all()
+    gpu.close()
+
+
+def test_sensors_need_a_recorded_step():
+    lbm = _lbm()
+    gpu, _, _ = make_pair(I.config1(0), "RR", lbm.LBM_FP64, with_oracle=False)
+    lbm.lbm_sensors_enable(gpu.h, True)
+    with pytest.raises(lbm.LbmError):
+        gpu.sensors(0, 1e-8)
+    gpu.step(2)
+    gpu.sensors(1, 1e-8)
+    gpu.tune(reps=1)  # the trial launches overwrite what the sensors compare
+    with pytest.raises(lbm.LbmError):
+        gpu.sensors(0, 1e-8)
+    gpu.close()
+
+
+@pytest.mark.parametrize("level,node", [(0, (50, 33, 0)), (1, (20, 31, 0))])
+def test_probe_series_matches_oracle(level, node):
+    lbm = _lbm()
+    gpu, ref, _ = make_pair(I.config1(2), "RR", lbm.LBM_FP64)
+    lbm.lbm_probe_enable(gpu.h, level, node, 64)
+    steps = 40
+    gpu.step(steps)
+    series, count = lbm.lbm_probe_read(gpu.h, 64)
+    assert count == steps
+    nx = ref.dims(level)[0]
+    exp = []
+    for _ in range(steps):
+        ref.step(1)
+        r, _ = ref.get_macros(level)
+        exp.append(r[node[0] + nx * node[1]])
+    assert np.abs(series - np.array(exp)).max() <= 1e-12
+    with pytest.raises(lbm.LbmError):
+        lbm.lbm_probe_enable(gpu.h, 0, (32, 32, 0), 8)  # a covered coarse node
+    gpu.close()

@@ -59,3 +59,75 @@ def test_served_in_real_time_with_autotuning_equals_running_alone(seed, collisio
         alone = serve.run_alone(r)
         for k, v in alone.items():
             assert np.array_equal(v, r.result[k]), (r.rid, k)
+
+
+def _oracle_of(req, steps=None):
+    import oracle as O
+    from paper_2004_11863_amd import inputs as I
+    g = req.workload.geom
+    D = g.D
+    ref = O.Grid(O.D2Q9 if D == 2 else O.D3Q19, {"BGK": O.BGK, "RR": O.RR, "HRR": O.HRR}[req.collision],
+                 g.n[:D], g.lo[:D], g.hi[:D], tau_c=req.tau_coarse, sigma=req.sigma)
+    for lv in (0, 1):
+        ref.set_state(lv, *req.fields(lv))
+    ref.step(req.steps if steps is None else steps)
+    return ref
+
+
+def test_served_fp32_matches_oracle_each_lattice():
+    """A served FP32 request of each lattice, in the mix with others, against
+    the FP64 CPU oracle: density max-abs < 1e-5, velocity relative L2 < 1e-4
+    on both levels."""
+    reqs = serve.poisson_trace(6, rate=100.0, seed=16, d2_side=(48, 80), d3_side=(20, 28), steps=(20, 50),
+                               fp64_frac=0.0)
+    assert {r.lattice for r in reqs} == {0, 1}
+    for r in reqs:
+        r.prepare()
+    ex = serve.DeviceExecutor(capacity=4)
+    done = serve.Server(ex, 1 << 36, max_chunk=8).run(reqs, realtime=False)
+    ex.close()
+    checked = set()
+    for r in done:
+        if r.lattice in checked:
+            continue
+        ref = _oracle_of(r)
+        for lv in (0, 1):
+            r0, u0 = ref.get_macros(lv)
+            assert np.abs(r.result[f"rho{lv}"] - r0).max() < 1e-5, (r.rid, lv)
+            du = r.result[f"u{lv}"] - u0
+            assert np.linalg.norm(du) / np.linalg.norm(u0) < 1e-4, (r.rid, lv)
+        checked.add(r.lattice)
+    assert checked == {0, 1}
+
+
+def test_fp32_overflow_falls_back_to_fp64():
+    """A request whose FP32 state overflows (density 1e40 at rest: the stored
+    deviations exceed the FP32 range) comes back non-finite and is run again
+    in FP64 from its start; its served result is then finite and bitwise the
+    request run alone in FP64, and the requests beside it are unaffected."""
+    reqs = serve.poisson_trace(4, rate=100.0, seed=14, d2_side=(40, 64), d3_side=(20, 24), steps=(8, 20),
+                               fp64_frac=0.0)
+    for r in reqs:
+        r.prepare()
+    bad = reqs[1]
+    n0 = bad.payload[0][0].size
+    n1 = bad.payload[1][0].size
+    D = bad.workload.geom.D
+    bad.payload = {0: (np.full(n0, 1e40), np.zeros((D, n0))), 1: (np.full(n1, 1e40), np.zeros((D, n1)))}
+    ex = serve.DeviceExecutor(capacity=4)
+    done = serve.Server(ex, 1 << 36, max_chunk=8).run(reqs, realtime=False)
+    ex.close()
+    assert sorted(r.rid for r in done) == [0, 1, 2, 3]
+    for r in done:
+        if r.rid == bad.rid:
+            assert r.fell_back and r.fp64
+            alone = serve.run_alone(r, fp64=True)
+            for k, v in alone.items():
+                assert np.isfinite(r.result[k]).all(), k
+                assert np.array_equal(v, r.result[k]), k
+            assert np.abs(r.result["rho0"] / 1e40 - 1.0).max() < 1e-12
+        else:
+            assert not r.fell_back
+            alone = serve.run_alone(r)
+            for k, v in alone.items():
+                assert np.array_equal(v, r.result[k]), (r.rid, k)
