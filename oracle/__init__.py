@@ -103,6 +103,8 @@ def lib():
         L.orc_set_mutation.argtypes = [ctypes.c_int]
         L.orc_threads.restype = ctypes.c_int
         L.orc_sensors.argtypes = [vp, ctypes.c_int, ctypes.c_double, vp, vp, vp, vp]
+        L.orc_set_dynamic_sigma.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        L.orc_dynamic_mask.argtypes = [vp, ctypes.c_int, vp]
         _lib = L
     return _lib
 
@@ -301,6 +303,21 @@ class Grid:
         if rc != 0:
             raise ValueError("sensors need a level that exists and a step taken")
         return flags, dp, cp, gn
+
+    def set_dynamic_sigma(self, on: bool, sigma_dyn: float = 0.0, threshold: float = 0.0):
+        """H-RR with sigma chosen per node from the SpuriousAc / SpuriousS tests
+        between consecutive bulk collisions (sigma_dyn where a product falls
+        below -threshold, the grid's sigma elsewhere); a variant Sec. 9.3 and
+        Sec. 11 suggest."""
+        if lib().orc_set_dynamic_sigma(self._h, 1 if on else 0, float(sigma_dyn), float(threshold)) != 0:
+            raise ValueError("dynamic sigma needs H-RR, sigma_dyn in [0, 1] and a threshold >= 0")
+
+    def dynamic_mask(self, level: int):
+        """1 on the nodes of a level whose last bulk collision took sigma_dyn."""
+        out = np.zeros(self.nodes(level), np.uint8)
+        if lib().orc_dynamic_mask(self._h, level, out.ctypes.data) != 0:
+            raise ValueError("no such level")
+        return out
 
     def totals(self):
         mass = np.zeros(2)

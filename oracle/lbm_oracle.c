@@ -396,6 +396,13 @@ typedef struct {
   /* NH sensors (Sec. 7): velocities of the iteration before the last one
    * of each level (coarse: t, fine: t+1/2, for a step t -> t+1) */
   double *u_c_prev, *u_f_prev;
+  /* Dynamic sigma (H-RR, suggested in Sec. 9.3 and Sec. 11): on/off, the
+   * sigma taken where a node's sensors fire, and per node the divergence and
+   * curl of the velocity gradient of its previous bulk collision [4][N]. */
+  int dyn;
+  double sigma_dyn, dyn_thr;
+  double *dyn_c, *dyn_f;
+  uint8_t *dyn_mask_c, *dyn_mask_f; /* 1 where the last collision took sigma_dyn */
 } ogrid;
 
 static long cidx(const ogrid* g, int x, int y, int z) {
@@ -464,6 +471,7 @@ void orc_destroy(void* hp) {
   free(g->r_rho); free(g->r_u); free(g->r_f); free(g->r_S);
   free(g->tn_f); free(g->tn_c);
   free(g->u_c_prev); free(g->u_f_prev);
+  free(g->dyn_c); free(g->dyn_f); free(g->dyn_mask_c); free(g->dyn_mask_f);
   free(g);
 }
 
@@ -507,6 +515,8 @@ void* orc_create(int lat, int model, const int* n, const int* lo, const int* hi,
   g->rho_c = calloc((size_t)g->Nc, sizeof(double));
   g->u_c = calloc((size_t)3 * g->Nc, sizeof(double));
   g->u_c_prev = calloc((size_t)3 * g->Nc, sizeof(double));
+  g->dyn_c = calloc((size_t)4 * g->Nc, sizeof(double));
+  g->dyn_mask_c = calloc((size_t)g->Nc, 1);
   g->cls_c = calloc((size_t)g->Nc, 1);
   for (long i = 0; i < g->Nc; ++i) {
     int c[3];
@@ -521,6 +531,8 @@ void* orc_create(int lat, int model, const int* n, const int* lo, const int* hi,
   g->rho_f = calloc((size_t)g->Nf, sizeof(double));
   g->u_f = calloc((size_t)3 * g->Nf, sizeof(double));
   g->u_f_prev = calloc((size_t)3 * g->Nf, sizeof(double));
+  g->dyn_f = calloc((size_t)4 * g->Nf, sizeof(double));
+  g->dyn_mask_f = calloc((size_t)g->Nf, 1);
   g->cls_f = calloc((size_t)g->Nf, 1);
   for (long i = 0; i < g->Nf; ++i) {
     int j[3];
@@ -689,7 +701,7 @@ int orc_ring_stencils(void* hp, int64_t* node, int32_t* np, int64_t* pts, double
 /* Finite differences: second-order centred, in the level's lattice units
  * (Sec. 3.3).  S_ab = (d_a u_b + d_b u_a) / 2.  Reading: the full symmetric
  * strain rate (trace included) is used, as in Appendix A.                 */
-static void strain_from(int D, const double up[3][3], const double um[3][3], double* S) {
+static void strain_from(int D, const double up[3][3], const double um[3][3], double* S, double gout[3][3]) {
   /* up[a][b]: u_b at x + e_a;  um[a][b]: u_b at x - e_a */
   double gr[3][3] = {{0}};
   for (int a = 0; a < D; ++a)
@@ -699,8 +711,11 @@ static void strain_from(int D, const double up[3][3], const double um[3][3], dou
     }
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) S[3 * a + b] = (a < D && b < D) ? 0.5 * (gr[a][b] + gr[b][a]) : 0.0;
+  if (gout)
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) gout[a][b] = gr[a][b];
 }
-static void strain_coarse(const ogrid* g, long i, double* S) {
+static void strain_coarse_g(const ogrid* g, long i, double* S, double gout[3][3]) {
   int c[3];
   double up[3][3], um[3][3];
   cco(g, i, c);
@@ -714,9 +729,10 @@ static void strain_coarse(const ogrid* g, long i, double* S) {
       um[a][b] = g->u_c[b * g->Nc + iq];
     }
   }
-  strain_from(g->D, up, um, S);
+  strain_from(g->D, up, um, S, gout);
 }
-static void strain_fine(const ogrid* g, long i, double* S) {
+static void strain_coarse(const ogrid* g, long i, double* S) { strain_coarse_g(g, i, S, NULL); }
+static void strain_fine_g(const ogrid* g, long i, double* S, double gout[3][3]) {
   int j[3];
   double up[3][3], um[3][3];
   fco(g, i, j);
@@ -730,7 +746,67 @@ static void strain_fine(const ogrid* g, long i, double* S) {
       um[a][b] = g->u_f[b * g->Nf + iq];
     }
   }
-  strain_from(g->D, up, um, S);
+  strain_from(g->D, up, um, S, gout);
+}
+static void strain_fine(const ogrid* g, long i, double* S) { strain_fine_g(g, i, S, NULL); }
+
+/* Dynamic sigma (an H-RR variant the paper suggests in Sec. 9.3 and Sec. 11
+ * without defining it).  Reading: at each bulk H-RR collision of a node, the
+ * SpuriousAc and SpuriousS tests of Sec. 7 (eqs sensorSpuriousAc,
+ * sensorSpuriousS) compare the divergence and the curl of the velocity
+ * gradient this collision uses (gr[a][b] = d_a u_b) with those of the node's
+ * previous bulk collision on its level (zero before the first); a product
+ * below -thr (3D curl: dot product; thr = 0 is the paper's tie-break, a
+ * small thr keeps products of rounding noise from switching) takes
+ * sigma_dyn, otherwise the grid's sigma.  The new divergence and curl
+ * replace the stored ones.  Interface collisions (ring nodes, TN^c) keep the
+ * grid's sigma. */
+static double dyn_sigma(const ogrid* g, double* prev, uint8_t* mask, long N, long i, const double gr[3][3]) {
+  double dv = 0.0, c[3] = {0.0, 0.0, 0.0};
+  int nc = 1;
+  for (int a = 0; a < g->D; ++a) dv += gr[a][a];
+  if (g->D == 2) {
+    c[0] = gr[0][1] - gr[1][0];
+  } else {
+    c[0] = gr[1][2] - gr[2][1];
+    c[1] = gr[2][0] - gr[0][2];
+    c[2] = gr[0][1] - gr[1][0];
+    nc = 3;
+  }
+  const double pd = prev[i] * dv;
+  double pc = 0.0;
+  for (int k = 0; k < nc; ++k) pc += prev[(1 + k) * N + i] * c[k];
+  prev[i] = dv;
+  for (int k = 0; k < nc; ++k) prev[(1 + k) * N + i] = c[k];
+  mask[i] = (uint8_t)(pd < -g->dyn_thr || pc < -g->dyn_thr);
+  return mask[i] ? g->sigma_dyn : g->sigma;
+}
+
+/* Switches dynamic sigma on (with the sigma taken where the sensors fire and
+ * the threshold of the products) or off; switching on forgets the stored
+ * divergences and curls.  Returns -1 for a model other than H-RR, sigma_dyn
+ * outside [0, 1] or a negative threshold. */
+int orc_set_dynamic_sigma(void* hp, int on, double sigma_dyn, double thr) {
+  ogrid* g = (ogrid*)hp;
+  if (on && (g->model != MOD_HRR || !(sigma_dyn >= 0.0 && sigma_dyn <= 1.0) || !(thr >= 0.0))) return -1;
+  g->dyn = on ? 1 : 0;
+  g->sigma_dyn = sigma_dyn;
+  g->dyn_thr = thr;
+  memset(g->dyn_c, 0, sizeof(double) * 4 * (size_t)g->Nc);
+  memset(g->dyn_mask_c, 0, (size_t)g->Nc);
+  if (g->has_fine) {
+    memset(g->dyn_f, 0, sizeof(double) * 4 * (size_t)g->Nf);
+    memset(g->dyn_mask_f, 0, (size_t)g->Nf);
+  }
+  return 0;
+}
+
+/* Which nodes of a level took sigma_dyn in their last bulk collision. */
+int orc_dynamic_mask(void* hp, int level, uint8_t* out) {
+  ogrid* g = (ogrid*)hp;
+  if (level == 1 && !g->has_fine) return -1;
+  memcpy(out, level == 0 ? g->dyn_mask_c : g->dyn_mask_f, (size_t)(level == 0 ? g->Nc : g->Nf));
+  return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -949,9 +1025,10 @@ static void uniform_step(ogrid* g) {
   for (long i = 0; i < N; ++i) stream_coarse_node(g, i);
 #pragma omp parallel for schedule(static)
   for (long i = 0; i < N; ++i) {
-    double S[9] = {0};
-    if (g->model == MOD_HRR) strain_coarse(g, i, S);
-    collide_L(&g->L, g->model, g->tau_c, g->sigma, g->fc_pre + i, N, S, g->fc + i, N);
+    double S[9] = {0}, gr[3][3] = {{0}}, sg = g->sigma;
+    if (g->model == MOD_HRR) strain_coarse_g(g, i, S, gr);
+    if (g->dyn) sg = dyn_sigma(g, g->dyn_c, g->dyn_mask_c, N, i, gr);
+    collide_L(&g->L, g->model, g->tau_c, sg, g->fc_pre + i, N, S, g->fc + i, N);
   }
 }
 
@@ -992,9 +1069,10 @@ static void two_level_step(ogrid* g) {
 #pragma omp parallel for schedule(static)
   for (long i = 0; i < Nf; ++i) {
     if (g->cls_f[i] != F_MIDDLE && g->cls_f[i] != F_TNF) continue;
-    double S[9] = {0};
-    if (hrr) strain_fine(g, i, S);
-    collide_L(&g->L, g->model, g->tau_f, g->sigma, g->ff_pre + i, Nf, S, g->ff_half + i, Nf);
+    double S[9] = {0}, gr[3][3] = {{0}}, sg = g->sigma;
+    if (hrr) strain_fine_g(g, i, S, gr);
+    if (g->dyn) sg = dyn_sigma(g, g->dyn_f, g->dyn_mask_f, Nf, i, gr);
+    collide_L(&g->L, g->model, g->tau_f, sg, g->ff_pre + i, Nf, S, g->ff_half + i, Nf);
   }
   if (hrr) {
     /* (e) fictitious propagation onto TN^f: u(TN, t+1) */
@@ -1073,17 +1151,19 @@ static void two_level_step(ogrid* g) {
 #pragma omp parallel for schedule(static)
   for (long i = 0; i < Nf; ++i) {
     if (g->cls_f[i] != F_MIDDLE && g->cls_f[i] != F_TNF) continue;
-    double S[9] = {0};
-    if (hrr) strain_fine(g, i, S);
-    collide_L(&g->L, g->model, g->tau_f, g->sigma, g->ff_pre + i, Nf, S, g->ff + i, Nf);
+    double S[9] = {0}, gr[3][3] = {{0}}, sg = g->sigma;
+    if (hrr) strain_fine_g(g, i, S, gr);
+    if (g->dyn) sg = dyn_sigma(g, g->dyn_f, g->dyn_mask_f, Nf, i, gr);
+    collide_L(&g->L, g->model, g->tau_f, sg, g->ff_pre + i, Nf, S, g->ff + i, Nf);
   }
   ring_reconstruct_collide(g, 0, g->ff);
 #pragma omp parallel for schedule(static)
   for (long i = 0; i < Nc; ++i) {
     if (g->cls_c[i] != C_MIDDLE && g->cls_c[i] != C_TFC) continue;
-    double S[9] = {0};
-    if (hrr) strain_coarse(g, i, S);
-    collide_L(&g->L, g->model, g->tau_c, g->sigma, g->fc_pre + i, Nc, S, g->fc + i, Nc);
+    double S[9] = {0}, gr[3][3] = {{0}}, sg = g->sigma;
+    if (hrr) strain_coarse_g(g, i, S, gr);
+    if (g->dyn) sg = dyn_sigma(g, g->dyn_c, g->dyn_mask_c, Nc, i, gr);
+    collide_L(&g->L, g->model, g->tau_c, sg, g->fc_pre + i, Nc, S, g->fc + i, Nc);
   }
 #pragma omp parallel for schedule(static)
   for (long t = 0; t < g->NT; ++t) {
