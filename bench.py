@@ -52,11 +52,15 @@ def parse():
                         "24 of the D2Q9 grids; about 10-20 s on 16 host cores)")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-instances measurement")
     p.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
+    p.add_argument("--no-paper", action="store_true",
+                   help="skip the paper's cases (acoustic wave, sensors, dynamic sigma)")
     p.add_argument("--batch-n", type=int, default=256)
     p.add_argument("--batch-steps", type=int, default=200)
     p.add_argument("--serve-n", type=int, default=16, help="arrivals of the full-size serving trace")
     p.add_argument("--serve-small-n", type=int, default=128, help="arrivals of the small-grid serving trace")
     p.add_argument("--serve-reps", type=int, default=3, help="repeats of the small-grid trace (spread)")
+    p.add_argument("--variants", default=None,
+                   help="launch variants of the headline grid as r0,r1,r2,r3 instead of autotuning")
     p.add_argument("--copy-probe", type=int, default=0,
                    help="only run a plain device copy of this many MiB (counter calibration)")
     return p.parse_args()
@@ -81,12 +85,15 @@ def kernel_label(D, collision, variants=None):
     if collision == "HRR" and D == 2:
         return "k_hrr2: one H-RR fine substep in one pass (pull, velocities of the tile in LDS, strain rate, collide)"
     if collision == "HRR":
-        if v[3] >= 2:
+        if v[3] == 2:
             return "k_hrr3: one H-RR fine substep in one marching pass (velocity planes in LDS, strain rate, collide)"
+        if v[3] == 3:
+            return ("k_hrr3s: one H-RR fine substep in one marching pass, one node per lane (velocity planes in "
+                    "LDS, strain rate, collide)")
         return "k_collide_hrr: fine-level pull + H-RR collide (second pass)"
     if v[1] >= 2:
-        return ("k_fine3: both fine substeps of a coarse step in one marching pass; one read and one write of "
-                "every fine node's populations per launch, 2 updates per node")
+        return ("k_fine3s: both fine substeps of a coarse step in one marching pass, one node per lane; one read "
+                "and one write of every fine node's populations per launch, 2 updates per node")
     return "k_stream: fine-level pull + collide"
 
 
@@ -126,7 +133,7 @@ def workload(name, seed=0):
     return I.config3(seed=seed, n=384)
 
 
-def make_gpu(wl, collision, precision):
+def make_gpu(wl, collision, precision, tau_coarse=0.51):
     from paper_2004_11863_amd import inputs as I
     from paper_2004_11863_amd import lbm
     g = wl.geom
@@ -134,7 +141,7 @@ def make_gpu(wl, collision, precision):
     lat = lbm.LBM_D2Q9 if D == 2 else lbm.LBM_D3Q19
     col = {"BGK": lbm.LBM_BGK, "RR": lbm.LBM_RR, "HRR": lbm.LBM_HRR}[collision]
     prec = lbm.LBM_FP32_DEV if precision == "fp32" else lbm.LBM_FP64
-    grid = lbm.Grid(lat, col, prec, g.n[:D], g.lo[:D], g.hi[:D], tau_coarse=0.51, sigma=0.995)
+    grid = lbm.Grid(lat, col, prec, g.n[:D], g.lo[:D], g.hi[:D], tau_coarse=tau_coarse, sigma=0.995)
     for lv in (0, 1):
         rho, u = I.fields(wl, lv)
         grid.set_state(lv, rho, u)
@@ -224,6 +231,88 @@ def error_vs_oracle(wl, collision, precision, steps, ref):
     grid.close()
     err["within_bar"] = bool(err["rho_maxabs"] < 1e-5 and err["u_relL2"] < 1e-4)
     return err
+
+
+def paper_cases():
+    """The paper's own diagnostics and cases on one GPU:
+    * the acoustic wave of Sec. 8.2 (eq init_Pulse, A = 1e-4, nu = 1e-6) on its
+      full set-up (fine band 500 < x < 1000, 2620 coarse steps, FP64), RR and
+      H-RR: throughput, the waves RR emits at t = 2620 as fractions of A (the
+      paper reports about A/25 upstream and A/100 downstream), H-RR's, and the
+      fine-level SpuriousAc detections (divergence product below -1e-18);
+    * the NH sensors and the probe switched on over a D2Q9 4096^2 RR FP32
+      run, and dynamic sigma over a D2Q9 4096^2 H-RR FP32 run: throughput
+      against the same runs without them."""
+    import numpy as np
+    import torch
+    from paper_2004_11863_amd import inputs as I
+    from paper_2004_11863_amd import lbm
+    out = {}
+    T = 2620
+    A = 1e-4
+    for col in ("RR", "HRR"):
+        wl = I.acoustic_wave_case(height=2 * T + 64, left=1500, A=A)
+        g = wl.geom
+        gr = make_gpu(wl, col, "fp64", tau_coarse=0.5 + 1e-6 / I.CS2)
+        ups = gr.updates_per_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gr.step(T - 1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        lbm.lbm_sensors_enable(gr.h, True)
+        gr.step(1)
+        nxc, nyc = g.n[0], g.n[1]
+        nxf, nyf = g.fine_shape()
+        jm = (nyf - 1) // 2
+        ym = g.lo[1] + jm // 2
+        shift = wl.plane_pulses[0].xc - 750.0
+        rc = gr.get_macros(0)[0].reshape(nyc, nxc)[ym] - 1.0
+        rf = gr.get_macros(1)[0].reshape(nyf, nxf)[jm] - 1.0
+        _, dg = gr.sensors(1, 0.0)
+        dprod = dg[0].reshape(nyf, nxf)[jm]
+        gr.close()
+        del gr
+        torch.cuda.empty_cache()
+        xc = np.arange(nxc) - shift
+        up = np.abs(rc[(xc > 0) & (xc < 500)]).max()
+        dn = np.abs(rf).max()
+        out[f"acoustic_wave_{col.lower()}_fp64"] = {
+            "mlups": round(ups * (T - 1) / dt / 1e6, 1), "steps": T, "updates_per_step": ups,
+            "emitted_upstream_over_A": float(up / A), "emitted_downstream_over_A": float(dn / A),
+            "fine_spurious_ac_detections": int((dprod < -1e-18).sum())}
+        print(f"# paper case acoustic {col}: {out[f'acoustic_wave_{col.lower()}_fp64']}", file=sys.stderr, flush=True)
+    for name, col, switch in (("sensors_probe", "RR", "sensors"), ("dynamic_sigma", "HRR", "dyn")):
+        wl = workload("d2q9-4096")
+        res = {}
+        for on in (False, True):
+            gr = make_gpu(wl, col, "fp32")
+            gr.variants = gr.tune(reps=2)
+            if on and switch == "sensors":
+                lbm.lbm_sensors_enable(gr.h, True)
+                lbm.lbm_probe_enable(gr.h, 1, (100, 100, 0), 1000)
+            elif on:
+                gr.set_dynamic_sigma(True, 0.0, 1e-12)
+            gr.step(5)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gr.step(200)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res["on" if on else "off"] = round(gr.updates_per_step() * 200 / dt / 1e6, 1)
+            if on and switch == "sensors":
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                gr.sensors(1, 1e-8)
+                res["readout_fine_s"] = round(time.perf_counter() - t0, 4)
+            gr.close()
+            del gr
+            torch.cuda.empty_cache()
+        out[f"d2q9_4096_{col.lower()}_fp32_{name}"] = {"mlups_off": res["off"], "mlups_on": res["on"],
+                                                       **({"readout_fine_s": res["readout_fine_s"]}
+                                                          if "readout_fine_s" in res else {})}
+        print(f"# paper case {name}: {out[f'd2q9_4096_{col.lower()}_fp32_{name}']}", file=sys.stderr, flush=True)
+    return out
 
 
 def batched(n_inst, steps):
@@ -439,15 +528,18 @@ def main():
     wl = workload(args.workload)
     grid = make_gpu(wl, args.collision, args.precision)
     ups = grid.updates_per_step()
-    dt, kt = timed_run(grid, args.steps, args.warmup, profile=True)
+    if args.variants:
+        grid.variants = [int(x) for x in args.variants.split(",")]
+        grid.set_variants(grid.variants)
+    dt, kt = timed_run(grid, args.steps, args.warmup, profile=True, tune=not args.variants)
     mlups = ups * args.steps / dt / 1e6
     m, p = grid.totals()  # finite check
     Q = grid.Q
     pb = 4 if args.precision == "fp32" else 8
     g = wl.geom
     D = g.D
-    roof = roofline_of(kt, Q, pb, g)
     variants = getattr(grid, "variants", None)
+    roof = roofline_of(kt, Q, pb, g)
     khash = kernel_source_hash()
     key = f"{args.workload}/{args.collision}/{args.precision}"
     traffic = stored_traffic(khash, key, None if variants is None else variants[1])
@@ -542,6 +634,8 @@ def main():
             print(f"# extra {name}: {extra[name]}", file=sys.stderr, flush=True)
         result["extra"] = extra
 
+    if not args.no_paper:
+        result["paper_cases"] = paper_cases()
     if not args.no_batch:
         result["batched"] = batched(args.batch_n, args.batch_steps)
         print(f"# batched: {result['batched']}", file=sys.stderr, flush=True)

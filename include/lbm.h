@@ -173,6 +173,23 @@ int lbm_get_totals_noalloc(lbm_handle h, double mass[2], double momentum[6]);
 int lbm_sensors_enable(lbm_handle h, int on);
 int lbm_sensors(lbm_handle h, int level, double threshold, uint8_t* flags, double* diag, int mem);
 
+/* Dynamic sigma (H-RR only): a variant that Sec. 9.3 and Sec. 11 of the
+ * paper suggest without defining it -- lower sigma (more finite-difference
+ * stress) only where non-hydrodynamic modes are detected.  While on, every
+ * bulk H-RR collision (coarse and fine middle nodes, TF^c, TN^f; not the
+ * ring or TN^c, which keep sigma) compares the divergence and curl of the
+ * velocity gradient it uses with those of the node's previous collision on
+ * its level, as the SpuriousAc and SpuriousS sensors do, and takes
+ * sigma_dyn where either product is below -threshold (3D curl: dot
+ * product; threshold 0 is the sensors' own test, a small positive one keeps
+ * products of rounding noise from switching).  Switching on clears the
+ * stored divergences and curls (no switch at a node's first collision).
+ * Costs 4 values of the storage type per node and level of device memory
+ * and runs the H-RR substeps in two passes (velocity pass, then pull +
+ * collide).  LBM_EINVAL: not an H-RR grid, sigma_dyn outside [0, 1], or a
+ * negative or non-finite threshold.  Not available for batches. */
+int lbm_set_dynamic_sigma(lbm_handle h, int on, double sigma_dyn, double threshold);
+
 /* Probe recording: after every following coarse step the density at node
  * node[3] (level coordinates) of `level` is appended on the device to a
  * series of at most `capacity` values (the paper's probes, Sec. 9.3).  A

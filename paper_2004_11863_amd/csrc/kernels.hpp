@@ -41,6 +41,10 @@ constexpr int kVarLds[kNVar] = {0, 53 * 1024, 80 * 1024, 160 * 1024};
 // from the neighbouring velocities and collides.
 enum Model : int { M_BGK = 0, M_RR = 1, M_HRR = 2 };
 
+// A product rounded on its own (never fused into a following add).
+__device__ __forceinline__ float mul_rn(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+
 // 16-byte vectors: "a" is the aligned type, "u" the same vector with element
 // alignment only (used for the x-shifted loads).
 template <typename S, int V>
@@ -340,10 +344,19 @@ __global__ __launch_bounds__(256) void k_stream(const S* __restrict__ src, S* __
 // units) of the velocity planes of mac (Sec. 3.3), which the first pass and
 // the interface kernels filled.  Processes whole vectors like k_stream; the
 // coarse pass runs before the fine-to-coarse transfer overwrites TN nodes.
-template <int LAT, bool DEV, typename S, int LEVEL, bool NT>
+//
+// DYN: sigma per node from the non-hydrodynamic sensors (a variant Sec. 9.3
+// and Sec. 11 suggest): the divergence and curl of this collision's velocity
+// gradient are compared with those of the node's previous collision on the
+// level, kept in dyn ([4][NP]: divergence, then the curl's 1 or 3
+// components); a product below -dthr (the SpuriousAc / SpuriousS tests of
+// Sec. 7, the 3D curl as a dot product) takes sig_dyn, otherwise sig.  The
+// products are formed without contraction, as the tests define them.
+template <int LAT, bool DEV, typename S, int LEVEL, bool NT, bool DYN = false>
 __device__ __forceinline__ void collide_hrr_body(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ mac,
                                         const Geo& g, const Flat& fl, const S om, const S tau, const S sig,
-                                        int chunk) {
+                                        int chunk, S* __restrict__ dyn = nullptr, const S sig_dyn = S(0),
+                                        const S dthr = S(0)) {
   using L = Lattice<LAT>;
   using N = Node<LAT, DEV, S>;
   constexpr int V = VecOf<S>::V;
@@ -389,6 +402,24 @@ __device__ __forceinline__ void collide_hrr_body(const S* __restrict__ src, S* _
   }
   VA v[Q];
   pl.template load_all<L>(src, v);
+  // DYN: the node's previous divergence and curl, then this collision's
+  constexpr int NC = D == 2 ? 1 : 3;
+  VA pv[1 + NC], cv[1 + NC];
+  if constexpr (DYN) {
+#pragma unroll
+    for (int c = 0; c <= NC; ++c) pv[c] = *(const VA*)(dyn + (int64_t)c * NP + own);
+    cv[0] = gr[0][0] + gr[1][1];
+    if constexpr (D == 3) {
+      cv[0] = cv[0] + gr[2][2];
+      cv[1] = gr[1][2] - gr[2][1];
+      cv[2] = gr[2][0] - gr[0][2];
+      cv[3] = gr[0][1] - gr[1][0];
+    } else {
+      cv[1] = gr[0][1] - gr[1][0];
+    }
+#pragma unroll
+    for (int c = 0; c <= NC; ++c) *(VA*)(dyn + (int64_t)c * NP + own) = cv[c];
+  }
 #pragma unroll
   for (int k = 0; k < V; ++k) {
     Sym<S> Sr;
@@ -402,10 +433,18 @@ __device__ __forceinline__ void collide_hrr_body(const S* __restrict__ src, S* _
     } else {
       Sr.zz = Sr.xz = Sr.yz = S(0);
     }
+    S sg = sig;
+    if constexpr (DYN) {
+      const S pd = mul_rn(pv[0][k], cv[0][k]);
+      S pc = mul_rn(pv[1][k], cv[1][k]);
+#pragma unroll
+      for (int c = 2; c <= NC; ++c) pc = pc + mul_rn(pv[c][k], cv[c][k]);
+      if (pd < -dthr || pc < -dthr) sg = sig_dyn;
+    }
     S s[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) s[i] = v[i][k];
-    N::collide(s, M_HRR, om, tau, sig, &Sr);
+    N::collide(s, M_HRR, om, tau, sg, &Sr);
 #pragma unroll
     for (int i = 0; i < Q; ++i) v[i][k] = s[i];
   }
@@ -413,11 +452,12 @@ __device__ __forceinline__ void collide_hrr_body(const S* __restrict__ src, S* _
   for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + pop_at<S, Q>(own, i)), v[i]);
 }
 
-template <int LAT, bool DEV, typename S, int LEVEL, bool NT>
+template <int LAT, bool DEV, typename S, int LEVEL, bool NT, bool DYN = false>
 __global__ __launch_bounds__(256) void k_collide_hrr(const S* __restrict__ src, S* __restrict__ dst,
                                                      const S* __restrict__ mac, const Geo g, const Flat fl, const S om,
-                                                     const S tau, const S sig) {
-  collide_hrr_body<LAT, DEV, S, LEVEL, NT>(src, dst, mac, g, fl, om, tau, sig, xcd_chunk(fl));
+                                                     const S tau, const S sig, S* __restrict__ dyn, const S sig_dyn,
+                                                     const S dthr) {
+  collide_hrr_body<LAT, DEV, S, LEVEL, NT, DYN>(src, dst, mac, g, fl, om, tau, sig, xcd_chunk(fl), dyn, sig_dyn, dthr);
 }
 
 // ---------------------------------------------------------------------------

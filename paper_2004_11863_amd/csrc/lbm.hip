@@ -188,6 +188,7 @@ struct GridBase {
   virtual void tune(int reps, int32_t* out) = 0;
   virtual void set_variants(const int32_t* v) = 0;
   virtual void sensors_enable(bool on) = 0;
+  virtual void set_dynamic_sigma(bool on, double sigma_dyn, double thr) = 0;
   virtual void sensors(int level, double thr, uint8_t* flags, double* prod, bool dev) = 0;
   virtual void probe_enable(int level, const int32_t* node, int64_t capacity) = 0;
   virtual int64_t probe_read(double* out, int64_t max) = 0;
@@ -245,6 +246,14 @@ struct Grid final : GridBase {
   // step has been recorded and nothing has touched the state since.
   bool sensors_on = false, sens_ready = false;
   DevBuf sUc, sUf, sFlags, sProd;
+  // Dynamic sigma (H-RR): while on, the bulk H-RR collisions take sig_dyn
+  // where the sensors' divergence or curl product falls below -dyn_thr
+  // (k_collide_hrr DYN); dynC / dynF hold each node's previous divergence
+  // and curl ([4][padded positions] in the storage type).  Forces the
+  // two-pass H-RR substeps (the one-pass kernels carry no such state).
+  bool dyn_on = false;
+  double sig_dyn = 0.0, dyn_thr = 0.0;
+  DevBuf dynC, dynF;
   // probe: density at one node of a level appended to pSeries each step
   int probe_level = -1;
   int64_t probe_pos = 0, probe_cap = 0;
@@ -337,7 +346,6 @@ struct Grid final : GridBase {
     hipLaunchKernelGGL((k_stream<LAT, DEV, S, MODEL, LEVEL, NT>), dim3((unsigned)(f.per_xcd * kXCD)), dim3(256),
                        (unsigned)kVarLds[v], s, src, dst, mac, g, f, (S)(1.0 - 1.0 / tau), xb);
   }
-
   // Coarse stream (BGK, RR) and the t+1/2 ring reconstruction from G into
   // fdst, one launch (k_stream_ring).
   template <int MODEL>
@@ -363,7 +371,9 @@ struct Grid final : GridBase {
   }
   // The coarse level in one pass (D2Q9 H-RR, rows a whole number of vectors:
   // coarse_one_pass()); same tile variants, role 2.
-  bool coarse_one_pass() const { return D == 2 && desc.collision == LBM_HRR && g.n[0] % V == 0; }
+  bool coarse_one_pass() const { return D == 2 && desc.collision == LBM_HRR && g.n[0] % V == 0 && !dyn_on; }
+  // D2Q9 H-RR fine substeps in one pass (k_hrr2)
+  bool fine_one_pass2() const { return D == 2 && !dyn_on; }
   template <int HXV, int HYR>
   void go_hrr2c(const S* src, S* dst, const S* mac, hipStream_t s) {
     if constexpr (D == 2) {
@@ -392,13 +402,22 @@ struct Grid final : GridBase {
     }
   }
 
+  // dyn: use the dynamic-sigma state (stepping only; the tuner's trial
+  // launches leave it alone)
   template <int LEVEL>
-  void launch_collide_hrr(const S* src, S* dst, const S* mac, double tau, hipStream_t s, int v = -1) {
+  void launch_collide_hrr(const S* src, S* dst, const S* mac, double tau, hipStream_t s, int v = -1,
+                          bool dyn = false) {
     if (v < 0) v = var[2 + LEVEL];
     const Flat f = flat(LEVEL);
     if (f.nchunks == 0) return;
-    hipLaunchKernelGGL((k_collide_hrr<LAT, DEV, S, LEVEL, NT>), dim3((unsigned)(f.per_xcd * kXCD)), dim3(256),
-                       (unsigned)kVarLds[v], s, src, dst, mac, g, f, (S)(1.0 - 1.0 / tau), (S)tau, (S)sig);
+    const dim3 gr((unsigned)(f.per_xcd * kXCD)), bl(256);
+    if (dyn && dyn_on)
+      hipLaunchKernelGGL((k_collide_hrr<LAT, DEV, S, LEVEL, NT, true>), gr, bl, (unsigned)kVarLds[v], s, src, dst, mac,
+                         g, f, (S)(1.0 - 1.0 / tau), (S)tau, (S)sig, (LEVEL == 0 ? dynC : dynF).as<S>(), (S)sig_dyn,
+                         (S)dyn_thr);
+    else
+      hipLaunchKernelGGL((k_collide_hrr<LAT, DEV, S, LEVEL, NT, false>), gr, bl, (unsigned)kVarLds[v], s, src, dst,
+                         mac, g, f, (S)(1.0 - 1.0 / tau), (S)tau, (S)sig, (S*)nullptr, (S)0, (S)0);
   }
 
   // Both fine substeps (BGK / RR), src -> dst, t+1/2 ring and band in half.
@@ -492,7 +511,7 @@ struct Grid final : GridBase {
   // 385^3 patch in FP32, per substep: k_hrr3 2.78 ms, k_hrr3s 3.20 ms, the
   // two-pass form 1.0 + 1.78 ms; the one-pass kernels save the velocity
   // pass's traffic but re-read their tile halos from HBM.
-  bool hrr_one_pass3() const { return D == 3 && desc.collision == LBM_HRR && var[3] >= 2; }
+  bool hrr_one_pass3() const { return D == 3 && desc.collision == LBM_HRR && var[3] >= 2 && !dyn_on; }
   int hrr_lds_var(int v) const { return (D == 3 && desc.collision == LBM_HRR) ? (v == 0 ? 2 : 1) : v; }
   template <int TXV, int TY>
   void go_hrr3(const S* src, S* dst, const S* mac, hipStream_t s, int v) {
@@ -670,7 +689,7 @@ struct Grid final : GridBase {
     else if (model == M_RR) launch_stream<M_RR, 0>(src, dst, nullptr, tau_c, s);
     else {
       launch_stream<M_HRR, 0>(src, dst, mac_c.as<S>(), tau_c, s);
-      launch_collide_hrr<0>(src, dst, mac_c.as<S>(), tau_c, s);
+      launch_collide_hrr<0>(src, dst, mac_c.as<S>(), tau_c, s, -1, true);
     }
     cpar ^= 1;
   }
@@ -725,7 +744,7 @@ struct Grid final : GridBase {
       // pull-stream + collide with the strain rate of those velocities
       const bool one_c = coarse_one_pass();
       if (!one_c) launch_stream<M_HRR, 0>(csrc, cdst, mc, tau_c, s);
-      if constexpr (D == 2) {
+      if (fine_one_pass2()) {
         // one pass per fine substep (k_hrr2): ring rho, u first
         hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, c0, c1, c2, mf, g, itf);
         timed(s, [&] { launch_hrr2(fA, fB, mf, s); });
@@ -735,7 +754,7 @@ struct Grid final : GridBase {
       } else {
         launch_stream<M_HRR, 1>(fA, fB, mf, tau_f, s);
         hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, c0, c1, c2, mf, g, itf);
-        timed(s, [&] { launch_collide_hrr<1>(fA, fB, mf, tau_f, s, hrr_lds_var(var[3])); });
+        timed(s, [&] { launch_collide_hrr<1>(fA, fB, mf, tau_f, s, hrr_lds_var(var[3]), true); });
       }
       hipLaunchKernelGGL((k_fict<LAT, DEV, S, S>), dim3(bt), dim3(IB), 0, s, fB, mc, g, itf);
       // the coarse velocities at the history nodes' neighbours: from the
@@ -748,7 +767,7 @@ struct Grid final : GridBase {
       else
         hipLaunchKernelGGL((k_hist_strain_time<LAT, DEV, S, false>), dim3(bh), dim3(IB), 0, s, csrc, mc, Hm, H0, Hp,
                            G.as<double>(), g, itf);
-      if (D == 2 || hrr_one_pass3()) {
+      if (fine_one_pass2() || hrr_one_pass3()) {
         // the t+1/2 ring and the t+1 ring velocities in one launch
         hipLaunchKernelGGL((k_ring_half_macro<LAT, DEV, S, M_HRR>), dim3(2 * br), dim3(IB), 0, s, G.as<double>(), fB, Hm,
                            H0, Hp, mf, g, itf, kf, omf, tau_f, sig, (int)br);
@@ -756,20 +775,20 @@ struct Grid final : GridBase {
         hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR, true>), dim3(br), dim3(IB), 0, s, G.as<double>(), fB, g, itf, kf,
                            omf, tau_f, sig);
       }
-      if constexpr (D == 2) {
+      if (fine_one_pass2()) {
         timed(s, [&] { launch_hrr2(fB, fA, mf, s); });
       } else if (hrr_one_pass3()) {
         timed(s, [&] { launch_hrr3(fB, fA, mf, s); });
       } else {
         launch_stream<M_HRR, 1>(fB, fA, mf, tau_f, s);
         hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, 0.0, 0.0, 1.0, mf, g, itf);
-        timed(s, [&] { launch_collide_hrr<1>(fB, fA, mf, tau_f, s, hrr_lds_var(var[3])); });
+        timed(s, [&] { launch_collide_hrr<1>(fB, fA, mf, tau_f, s, hrr_lds_var(var[3]), true); });
       }
       // coarse collision before the TN transfer: the vector kernel also
       // passes over TN nodes, which the transfer then overwrites; the t+1
       // ring (into fine A, independent of both) shares the transfer's launch
       if (one_c) launch_hrr2c(csrc, cdst, mc, s);
-      else launch_collide_hrr<0>(csrc, cdst, mc, tau_c, s);
+      else launch_collide_hrr<0>(csrc, cdst, mc, tau_c, s, -1, true);
       hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, M_HRR>), dim3(br2 + bc), dim3(256), 0, s, Hp, fA, fB, cdst, g,
                          itf, kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, (const S*)nullptr);
     }
@@ -839,6 +858,22 @@ struct Grid final : GridBase {
     hipLaunchKernelGGL((k_ring_macro<LAT, double>), dim3(xblocks(itf.NR, kIfaceBlock)), dim3(kIfaceBlock), 0, s,
                        hist[hs[2]].as<double>(), hist[hs[0]].as<double>(), hist[hs[1]].as<double>(), -1.0 / 8.0,
                        3.0 / 4.0, 3.0 / 8.0, sUf.as<double>(), g, itf);
+  }
+  void set_dynamic_sigma(bool on, double sigma_dyn, double thr) override {
+    HIPCHK(hipSetDevice(device));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (on) {
+      // a fresh start: no previous divergences and curls
+      auto zalloc = [](DevBuf& b, size_t bytes) {
+        if (!b.p) b.alloc(bytes);
+        HIPCHK(hipMemset(b.p, 0, bytes));
+      };
+      zalloc(dynC, sizeof(S) * 4 * (size_t)g.Ncp);
+      if (g.has_fine) zalloc(dynF, sizeof(S) * 4 * (size_t)g.Nfp);
+    }
+    dyn_on = on;
+    sig_dyn = sigma_dyn;
+    dyn_thr = thr;
   }
   void sensors_enable(bool on) override {
     HIPCHK(hipSetDevice(device));
@@ -1950,6 +1985,14 @@ int lbm_get_totals_noalloc(lbm_handle h, double mass[2], double momentum[6]) {
 int lbm_sensors_enable(lbm_handle h, int on) {
   if (!h) return LBM_EINVAL;
   return guard(h, [&] { h->impl->sensors_enable(on != 0); });
+}
+
+int lbm_set_dynamic_sigma(lbm_handle h, int on, double sigma_dyn, double threshold) {
+  if (!h) return LBM_EINVAL;
+  if (on && (h->impl->desc.collision != LBM_HRR || !(sigma_dyn >= 0.0 && sigma_dyn <= 1.0) ||
+             !(threshold >= 0.0) || !std::isfinite(threshold)))
+    return LBM_EINVAL;
+  return guard(h, [&] { h->impl->set_dynamic_sigma(on != 0, sigma_dyn, threshold); });
 }
 
 int lbm_sensors(lbm_handle h, int level, double threshold, uint8_t* flags, double* diag, int mem) {

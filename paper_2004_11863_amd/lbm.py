@@ -33,6 +33,7 @@ LBM_N_VARIANTS = 4
 EXPORTS = (
     "lbm_create_grid", "lbm_destroy", "lbm_set_state", "lbm_step", "lbm_get_macros",
     "lbm_set_populations", "lbm_get_populations", "lbm_get_totals", "lbm_get_totals_noalloc", "lbm_sensors_enable", "lbm_sensors",
+    "lbm_set_dynamic_sigma",
     "lbm_probe_enable", "lbm_probe_read", "lbm_get_index_maps",
     "lbm_level_dims", "lbm_lattice_info", "lbm_interface_counts", "lbm_interface_tables",
     "lbm_updates_per_step", "lbm_profile_enable", "lbm_kernel_time", "lbm_tune", "lbm_set_variants",
@@ -81,6 +82,7 @@ def load(path: str = LIB_PATH):
     L.lbm_get_totals_noalloc.argtypes = [vp, dp, dp]
     L.lbm_sensors_enable.argtypes = [vp, ip]
     L.lbm_sensors.argtypes = [vp, ip, ctypes.c_double, vp, vp, ip]
+    L.lbm_set_dynamic_sigma.argtypes = [vp, ip, ctypes.c_double, ctypes.c_double]
     L.lbm_probe_enable.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int32), ctypes.c_int64]
     L.lbm_probe_read.argtypes = [vp, dp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     L.lbm_get_index_maps.argtypes = [vp, ip, vp, ip]
@@ -255,6 +257,12 @@ def lbm_sensors(h, level, threshold, flags, diag=None):
     _check(load().lbm_sensors(h, level, float(threshold), p, dptr, m), h)
 
 
+def lbm_set_dynamic_sigma(h, on=True, sigma_dyn=0.0, threshold=0.0):
+    """H-RR with sigma_dyn at nodes whose divergence or curl product (sensor
+    tests between consecutive collisions) falls below -threshold."""
+    _check(load().lbm_set_dynamic_sigma(h, 1 if on else 0, float(sigma_dyn), float(threshold)), h)
+
+
 def lbm_probe_enable(h, level, node=(0, 0, 0), capacity=1):
     nd = (ctypes.c_int32 * 3)(*[int(x) for x in (list(node) + [0, 0, 0])[:3]])
     _check(load().lbm_probe_enable(h, int(level), nd, int(capacity)), h)
@@ -382,6 +390,9 @@ class Grid:
         diag = np.zeros((3, N))
         lbm_sensors(self.h, level, threshold, flags, diag)
         return flags, diag
+
+    def set_dynamic_sigma(self, on=True, sigma_dyn=0.0, threshold=0.0):
+        lbm_set_dynamic_sigma(self.h, on, sigma_dyn, threshold)
 
     def class_map(self, level):
         out = np.zeros(self.nodes(level), np.uint8)

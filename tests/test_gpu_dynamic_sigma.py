@@ -1,0 +1,158 @@
+"""Dynamic sigma (the H-RR variant Sec. 9.3 and Sec. 11 suggest) on the GPU
+against the oracle's, through the C ABI.
+
+FP64: within 1e-12 relative of the oracle on rho, u and the populations of
+both levels, 2D and 3D, with thresholds 1e-24 and 1e-12.  The switch is a
+decision on the sign of a product.  With threshold 0 (the sensors' own
+tie-break) a product of rounding noise decides -- the divergence inside the
+divergence-free vortex is ~1e-17 with either sign -- and the two sides,
+whose velocities differ in the last bits, may switch different nodes of the
+vortex core, where the two stresses differ: a legitimate 1e-9 difference,
+so parity is stated with thresholds above the noise (products of rounding
+noise are ~1e-34).  Threshold 0 is exercised by the eigenmode test, whose
+products have no noise-level nodes.
+FP32 deviation storage: the stated FP32 bars.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import lsa
+from paper_2004_11863_amd import inputs as I
+from parity_util import compare_fp32, compare_fp64, make_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _lbm():
+    from paper_2004_11863_amd import lbm
+    return lbm
+
+
+def _vortex_and_pulse():
+    wl = I.config1(1)
+    wl.pulses = [I.Pulse(center=(40.0, 30.0), A=1e-2)]
+    return wl
+
+
+def _pulse_3d():
+    geom = I.Geometry(3, (22, 20, 24), (5, 4, 6), (15, 14, 17))
+    return I.Workload(geom=geom, U=(0.1 / math.sqrt(3), 0.01, -0.005),
+                      pulses=[I.Pulse(center=(15.2, 9.6, 11.1), A=1e-3, R=2.5)])
+
+
+def _uniform():
+    geom = I.Geometry(2, (48, 40, 1), (0, 0, 0), (0, 0, 0))
+    return I.Workload(geom=geom, U=(0.1 * I.CS, 0.0, 0.0), vortices=[I.Vortex(center=(20.0, 21.0), eps=0.01)],
+                      pulses=[I.Pulse(center=(30.0, 12.0), A=1e-2)])
+
+
+CASES = {"2d": (_vortex_and_pulse, 30), "3d": (_pulse_3d, 12), "uniform": (_uniform, 30)}
+
+
+@pytest.mark.parametrize("thr", [1e-24, 1e-12])
+@pytest.mark.parametrize("case", ["2d", "3d", "uniform"])
+def test_dynamic_sigma_fp64_matches_oracle(case, thr):
+    lbm = _lbm()
+    mk, steps = CASES[case]
+    gpu, ref, levels = make_pair(mk(), "HRR", lbm.LBM_FP64)
+    gpu.set_dynamic_sigma(True, 0.0, thr)
+    ref.set_dynamic_sigma(True, 0.0, thr)
+    gpu.step(steps)
+    ref.step(steps)
+    out = compare_fp64(gpu, ref, levels)
+    # the switch changed the result: against the static scheme
+    st, _, _ = make_pair(mk(), "HRR", lbm.LBM_FP64, with_oracle=False)
+    st.step(steps)
+    moved = max(float(np.abs(gpu.get_macros(lv)[1] - st.get_macros(lv)[1]).max()) for lv in levels)
+    gpu.close()
+    st.close()
+    print(case, thr, out, moved)
+    assert max(out.values()) <= 1e-12, out
+    assert moved > 1e-9
+
+
+def test_dynamic_sigma_fp32_matches_oracle():
+    lbm = _lbm()
+    gpu, ref, levels = make_pair(_vortex_and_pulse(), "HRR", lbm.LBM_FP32_DEV)
+    gpu.set_dynamic_sigma(True, 0.0, 1e-12)
+    ref.set_dynamic_sigma(True, 0.0, 1e-12)
+    gpu.step(60)
+    ref.step(60)
+    out = compare_fp32(gpu, ref, levels)
+    gpu.close()
+    print(out)
+    for k, v in out.items():
+        assert v < (1e-5 if k.startswith("rho") else 1e-4), (k, v)
+
+
+def test_sigma_dyn_equal_to_sigma_is_the_static_scheme():
+    """The two-pass substeps dynamic sigma runs, with sigma_dyn = sigma, give
+    bitwise the static scheme (which runs the one-pass D2Q9 kernels)."""
+    lbm = _lbm()
+    a, _, levels = make_pair(_vortex_and_pulse(), "HRR", lbm.LBM_FP64, with_oracle=False)
+    b, _, _ = make_pair(_vortex_and_pulse(), "HRR", lbm.LBM_FP64, with_oracle=False)
+    a.set_dynamic_sigma(True, 0.995, 0.0)
+    a.step(12)
+    b.step(12)
+    for lv in levels:
+        assert np.array_equal(a.get_populations(lv), b.get_populations(lv)), lv
+    a.close()
+    b.close()
+
+
+def test_spurious_ac_mode_switches_everywhere():
+    """A SpuriousAc eigenmode (Sec. 5) on a uniform grid: every node takes
+    sigma_dyn from the second step, so two dynamic steps equal one static
+    step at sigma and one at sigma_dyn, bit for bit (on the GPU alone)."""
+    lbm = _lbm()
+    L, n, tau = 32, 15, 0.51
+    CS = math.sqrt(1 / 3)
+    s = lsa.Scheme("D2Q9", "HRR", tau, 0.995)
+    k = np.array([2 * math.pi * n / L, 0.0])
+    ub = np.array([0.1 * CS, 0.0])
+    lam, V = s.eig(1.0, ub, k)
+    M = lsa.macro_content(s, V)
+    wr, _ = lsa.omega(lam)
+    cand = [i for i in range(len(lam)) if abs(lam[i]) > 0.3 and abs(abs(wr[i]) - math.pi) < 0.35
+            and abs(M[1, i]) > 1e-3 * np.linalg.norm(V[:, i]) and abs(M[2, i]) < 1e-2 * abs(M[1, i])]
+    i = min(cand, key=lambda j: abs(abs(wr[j]) - math.pi))
+    F = np.exp(-1j * (s.xi @ k)) * V[:, i]
+    X = np.tile(np.arange(L), L)
+    f = O.feq(O.D2Q9, 1.0, ub)[:, None] + 1e-6 * np.real(F[:, None] * np.exp(-1j * (k[0] * X + 0.37))[None, :])
+
+    def grid(sigma):
+        g = lbm.Grid(lbm.LBM_D2Q9, lbm.LBM_HRR, lbm.LBM_FP64, (L, L), tau_coarse=tau, sigma=sigma)
+        g.set_populations(0, f)
+        return g
+
+    a = grid(0.995)
+    a.set_dynamic_sigma(True, 0.0, 0.0)
+    a.step(2)
+    b = grid(0.995)
+    b.step(1)
+    c = lbm.Grid(lbm.LBM_D2Q9, lbm.LBM_HRR, lbm.LBM_FP64, (L, L), tau_coarse=tau, sigma=0.0)
+    c.set_populations(0, b.get_populations(0))
+    c.step(1)
+    assert np.array_equal(a.get_populations(0), c.get_populations(0))
+    d = grid(0.995)
+    d.step(2)
+    assert not np.array_equal(a.get_populations(0), d.get_populations(0))
+    for g in (a, b, c, d):
+        g.close()
+
+
+def test_dynamic_sigma_rejects_bad_arguments():
+    lbm = _lbm()
+    rr, _, _ = make_pair(I.config1(0), "RR", lbm.LBM_FP64, with_oracle=False)
+    with pytest.raises(lbm.LbmError):
+        rr.set_dynamic_sigma(True, 0.0, 0.0)
+    rr.set_dynamic_sigma(False)  # switching off is always allowed
+    rr.close()
+    h, _, _ = make_pair(I.config1(0), "HRR", lbm.LBM_FP64, with_oracle=False)
+    for sd, thr in ((1.5, 0.0), (-0.1, 0.0), (0.0, -1.0), (0.0, float("inf")), (0.0, float("nan"))):
+        with pytest.raises(lbm.LbmError):
+            h.set_dynamic_sigma(True, sd, thr)
+    h.close()

@@ -66,10 +66,9 @@ def _compare(gpu, ref, level, thr, band=None):
     ma = np.abs(dp) > bd
     ms = np.abs(cp) > bc
     mg = ma & ms & (np.abs(gn - thr) > bg)
-    # FP64: most nodes are compared.  FP32: in these nearly divergence-free
-    # flows the divergence lies below the FP32 band at most nodes, so fewer are.
-    lo = 0.5 if band is not None else 0.1
-    assert ma.mean() > lo and ms.mean() > lo and mg.mean() > lo / 5, (ma.mean(), ms.mean(), mg.mean())
+    # nodes are compared where the quantity stands above the band (FP32: near
+    # the pulse's fronts and the vortex); enough of them to make it a test
+    assert ma.sum() >= 200 and ms.sum() >= 200 and mg.sum() >= 50, (ma.sum(), ms.sum(), mg.sum())
     assert np.array_equal(fl1[ma] & 1, fl0[ma] & 1), (level, "Ac")
     assert np.array_equal(fl1[ms] & 2, fl0[ms] & 2), (level, "S")
     assert np.array_equal(fl1[mg], fl0[mg]), (level, np.nonzero(fl1[mg] != fl0[mg])[0][:10])
@@ -81,7 +80,9 @@ def _compare(gpu, ref, level, thr, band=None):
 def test_sensors_d2q9_config1(model, prec, band):
     lbm = _lbm()
     p = lbm.LBM_FP64 if prec == "fp64" else lbm.LBM_FP32_DEV
-    gpu, ref, levels = make_pair(I.config1(1), model, p)
+    wl = I.config1(1)
+    wl.pulses = [I.Pulse(center=(40.0, 30.0), A=1e-2)]  # acoustic content: a divergence to sense
+    gpu, ref, levels = make_pair(wl, model, p)
     lbm.lbm_sensors_enable(gpu.h, True)
     gpu.step(25)
     ref.step(25)
