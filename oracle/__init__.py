@@ -44,6 +44,8 @@ MUTATIONS = {
     "nofilter": 12,
     "filter_zoff": 13,
     "face_axes": 14,
+    "nest_sync": 15,
+    "nest_ring": 16,
 }
 
 
@@ -71,6 +73,11 @@ def lib():
         vp = ctypes.c_void_p
         L.orc_create.restype = vp
         L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ip, ip, ip, ctypes.c_double, ctypes.c_double]
+        L.orc_create_nested.restype = vp
+        L.orc_create_nested.argtypes = [ctypes.c_int, ctypes.c_int, ip, ip, ip, ip, ip, ctypes.c_double,
+                                        ctypes.c_double]
+        L.orc_child.restype = vp
+        L.orc_child.argtypes = [vp]
         L.orc_destroy.argtypes = [vp]
         for name in ("orc_set_state", "orc_get_macros"):
             getattr(L, name).argtypes = [vp, ctypes.c_int, dp, dp]
@@ -324,3 +331,106 @@ class Grid:
         mom = np.zeros(6)
         lib().orc_totals(self._h, _dp(mass), _dp(mom))
         return mass, mom.reshape(2, 3)
+
+
+class _View(Grid):
+    """The child pair of a nested grid (owned by its root: never destroyed
+    here)."""
+
+    def __init__(self, handle, lattice_id, model, n, lo, hi, tau_c, sigma):
+        D, Q, xi, w = lattice(lattice_id)
+        self.D, self.Q, self.xi, self.w = D, Q, xi, w
+        self.lattice_id, self.model = lattice_id, model
+        nn = np.ones(3, np.int32)
+        nn[:D] = n
+        self.n = nn
+        self.lo, self.hi = np.zeros(3, np.int32), np.zeros(3, np.int32)
+        self.lo[:D], self.hi[:D] = lo, hi
+        self.has_fine = True
+        self.tau_c, self.sigma = tau_c, sigma
+        self._h = handle
+
+    def __del__(self):
+        self._h = None
+
+
+class Nested:
+    """Three nested levels: level 0 the periodic coarse grid, level 1 the
+    patch [lo, hi] of coarse vertices, level 2 the patch [lo2, hi2] of level-1
+    vertices (ratio 2 at each interface).  The two-level step of Sec. 4.3
+    applied to each pair: every substep of level 1 is a whole step of the
+    pair (1, 2).  BGK and RR."""
+
+    def __init__(self, lattice_id, model, n, lo, hi, lo2, hi2, tau_c=0.51, sigma=0.995):
+        D, Q, xi, w = lattice(lattice_id)
+        self.D, self.Q = D, Q
+        self.lattice_id, self.model = lattice_id, model
+        a = [np.zeros(3, np.int32) for _ in range(5)]
+        a[0][:] = 1
+        for arr, v in zip(a, (n, lo, hi, lo2, hi2)):
+            arr[:D] = v
+        self._h = lib().orc_create_nested(lattice_id, model, _ip(a[0]), _ip(a[1]), _ip(a[2]), _ip(a[3]), _ip(a[4]),
+                                          float(tau_c), float(sigma))
+        if not self._h:
+            raise ValueError("oracle rejected the nested grid description")
+        self.root = _View(self._h, lattice_id, model, n, lo, hi, tau_c, sigma)
+        nf = [2 * (int(h) - int(l)) + 1 for l, h in zip(lo, hi)]
+        self.child = _View(lib().orc_child(self._h), lattice_id, model, nf, lo2, hi2, 2 * tau_c - 0.5, sigma)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_destroy(h)
+            self._h = None
+
+    def _at(self, level):
+        return {0: (self.root, 0), 1: (self.root, 1), 2: (self.child, 1)}[level]
+
+    def nodes(self, level):
+        g, lv = self._at(level)
+        return g.nodes(lv)
+
+    def dims(self, level):
+        g, lv = self._at(level)
+        return g.dims(lv)
+
+    def set_state(self, level, rho, u):
+        g, lv = self._at(level)
+        g.set_state(lv, rho, u)
+        if level == 1:
+            self.child.set_state(0, rho, u)
+
+    def step(self, n=1):
+        lib().orc_step(self._h, int(n))
+
+    def get_populations(self, level):
+        g, lv = self._at(level)
+        return g.get_populations(lv)
+
+    def class_map(self, level):
+        g, lv = self._at(level)
+        return g.class_map(lv)
+
+    def get_macros(self, level):
+        """Moments of the current state; nodes a finer level covers take the
+        values of its co-located node (output only)."""
+        if level == 2:
+            return self.child.get_macros(1)
+        if level == 1:
+            r, u = self.child.get_macros(0)
+            ring = np.isin(self.root.class_map(1), [F_TFF, F_IE, F_IEFACE])
+            rr, ur = self.root.get_macros(1)
+            r[ring], u[:, ring] = rr[ring], ur[:, ring]
+            return r, u
+        r, u = self.root.get_macros(0)
+        cov = self.root.class_map(0) == C_COVERED
+        if cov.any():
+            r1, u1 = self.get_macros(1)
+            nf = self.root.dims(1)
+            idx = np.nonzero(cov)[0]
+            n = self.root.n
+            c = [(idx // int(np.prod(n[:d]))) % n[d] for d in range(self.D)]
+            j = [2 * (c[d] - self.root.lo[d]) for d in range(self.D)]
+            fi = sum(j[d] * int(np.prod(nf[:d])) for d in range(self.D))
+            r[idx], u[:, idx] = r1[fi], u1[:, fi]
+        return r, u

@@ -61,7 +61,9 @@ enum {
   MUT_FEQ2 = 11,          /* second-order equilibrium (third order dropped)   */
   MUT_NOFILTER = 12,      /* fine->coarse transfer without the filter         */
   MUT_FILTER_ZOFF = 13,   /* 3D filter sampling shifted by one node along z   */
-  MUT_FACE_AXES = 14      /* face-centre stencil built with its axes swapped  */
+  MUT_FACE_AXES = 14,     /* face-centre stencil built with its axes swapped  */
+  MUT_NEST_SYNC = 15,     /* nested: second child step from the state at t    */
+  MUT_NEST_RING = 16      /* nested: no ring rebuilt at t+1/2 for the child   */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -367,7 +369,7 @@ double orc_filter_weight(int D, const int* o) {
 
 /* ------------------------------------------------------------------------ */
 /* Grid state.                                                              */
-typedef struct {
+typedef struct ogrid_s {
   lattice_t L;
   int lat, model, D, Q;
   int n[3], a[3], m[3], nf[3];
@@ -403,6 +405,12 @@ typedef struct {
   double sigma_dyn, dyn_thr;
   double *dyn_c, *dyn_f;
   uint8_t *dyn_mask_c, *dyn_mask_f; /* 1 where the last collision took sigma_dyn */
+  /* Nested refinement: the fine level carries a patch of its own.  child is
+   * a two-level grid whose coarse level is this grid's fine level (same
+   * nodes, same order; its periodic wrap only reaches the fine ring, which
+   * this grid rebuilds), evolved by child steps in place of the fine
+   * substeps. */
+  struct ogrid_s* child;
 } ogrid;
 
 static long cidx(const ogrid* g, int x, int y, int z) {
@@ -472,6 +480,7 @@ void orc_destroy(void* hp) {
   free(g->tn_f); free(g->tn_c);
   free(g->u_c_prev); free(g->u_f_prev);
   free(g->dyn_c); free(g->dyn_f); free(g->dyn_mask_c); free(g->dyn_mask_f);
+  if (g->child) orc_destroy(g->child);
   free(g);
 }
 
@@ -655,6 +664,27 @@ void* orc_create(int lat, int model, const int* n, const int* lo, const int* hi,
   }
   return g;
 }
+
+/* A grid of three nested levels: the coarse grid and patch of orc_create,
+ * and a patch of the fine level given by lo2/hi2 in fine-level vertices
+ * (the same rules: at least 4 cells, 2 nodes from the fine ring).  The
+ * fine level's pair has tau = 2 tau_f - 1/2 (eq rescTau, applied to each
+ * pair).  BGK and RR only.  NULL on invalid input. */
+void* orc_create_nested(int lat, int model, const int* n, const int* lo, const int* hi, const int* lo2,
+                        const int* hi2, double tau_c, double sigma) {
+  if (model == MOD_HRR) return NULL;
+  ogrid* g = (ogrid*)orc_create(lat, model, n, lo, hi, tau_c, sigma);
+  if (!g) return NULL;
+  if (!g->has_fine) { orc_destroy(g); return NULL; }
+  int any = 0;
+  for (int d = 0; d < g->D; ++d) any |= (hi2[d] != lo2[d]);
+  ogrid* c = any ? (ogrid*)orc_create(lat, model, g->nf, lo2, hi2, g->tau_f, sigma) : NULL;
+  if (!c) { orc_destroy(g); return NULL; }
+  g->child = c;
+  return g;
+}
+/* The child pair of a nested grid (its coarse level is the fine level). */
+void* orc_child(void* hp) { return ((ogrid*)hp)->child; }
 
 int orc_level_dims(void* hp, int level, int* dims) {
   ogrid* g = (ogrid*)hp;
@@ -1032,6 +1062,97 @@ static void uniform_step(ogrid* g) {
   }
 }
 
+/* The phases of one coarse step (Sec. 4.3), shared by the two-level step and
+ * the nested step below. */
+
+/* Coarse propagation (every node but TN^c and the covered ones) and the
+ * history at t+1: pre-collision rho, u and f1 = f - f0. */
+static void coarse_stream_history(ogrid* g) {
+  const int Q = g->Q;
+  const long Nc = g->Nc, NH = g->NH;
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < Nc; ++i)
+    if (g->cls_c[i] == C_MIDDLE || g->cls_c[i] == C_TFC) stream_coarse_node(g, i);
+  double* Hp = g->hist[g->hs[2]];
+#pragma omp parallel for schedule(static)
+  for (long h = 0; h < NH; ++h) {
+    long i = g->hnode[h];
+    double f0[MAXQ], uu[3];
+    for (int d = 0; d < 3; ++d) uu[d] = g->u_c[d * Nc + i];
+    feq_L(&g->L, g->rho_c[i], uu, f0);
+    Hp[F_RHO * NH + h] = g->rho_c[i];
+    for (int d = 0; d < 3; ++d) Hp[(F_U + d) * NH + h] = uu[d];
+    for (int q = 0; q < MAXQ; ++q)
+      Hp[(F_F1 + q) * NH + h] = q < Q ? g->fc_pre[q * Nc + i] - f0[q] : 0.0;
+  }
+}
+
+/* Filtered fine -> coarse reconstruction at TN (eqs filterFneq, rescfc,
+ * PijResc) from the fine pre-collision state at t+1.  Reading: rho and u at
+ * TN^c are those of the co-located fine node (unfiltered); the filter acts
+ * on the non-equilibrium part only. */
+static void coalesce_tn(ogrid* g) {
+  const int Q = g->Q;
+  const long Nc = g->Nc, Nf = g->Nf;
+  const int hrr = (g->model == MOD_HRR);
+  const double kc = orc_rescale_f2c(g->tau_c, g->tau_f);
+  const double ks = orc_strain_f2c();
+  const int D = g->D;
+  const int nst = (D == 2) ? 9 : 27;
+#pragma omp parallel for schedule(static)
+  for (long t = 0; t < g->NT; ++t) {
+    int j[3];
+    long i = g->tn_f[t];
+    fco(g, i, j);
+    double ft[MAXQ] = {0};
+    for (int s = 0; s < nst; ++s) {
+      int o[3] = {s % 3 - 1, (s / 3) % 3 - 1, D == 3 ? s / 9 - 1 : 0};
+      int zs = (g_mut == MUT_FILTER_ZOFF && D == 3) ? 1 : 0;
+      long k = fidx(g, j[0] + o[0], j[1] + o[1], j[2] + o[2] + zs);
+      double f0[MAXQ], uu[3];
+      for (int d = 0; d < 3; ++d) uu[d] = g->u_f[d * Nf + k];
+      feq_L(&g->L, g->rho_f[k], uu, f0);
+      double wgt = orc_filter_weight(D, o);
+      for (int q = 0; q < Q; ++q) ft[q] += wgt * (g->ff_pre[q * Nf + k] - f0[q]);
+    }
+    double f0[MAXQ], uu[3];
+    for (int d = 0; d < 3; ++d) uu[d] = g->u_f[d * Nf + i];
+    feq_L(&g->L, g->rho_f[i], uu, f0);
+    long ic = g->tn_c[t];
+    for (int q = 0; q < Q; ++q) g->fc_pre[q * Nc + ic] = f0[q] + kc * ft[q];
+    g->rho_c[ic] = g->rho_f[i];
+    for (int d = 0; d < 3; ++d) g->u_c[d * Nc + ic] = uu[d];
+    double S[9] = {0};
+    if (hrr) strain_fine(g, i, S);
+    for (int k = 0; k < 9; ++k) g->S_tn[9 * t + k] = ks * S[k];
+  }
+}
+
+/* Collision of the coarse nodes (middle and TF^c, then TN^c with the strain
+ * rate handed over by the fine level), then the time levels move on: t+1
+ * becomes t, t becomes t-1. */
+static void coarse_collide_advance(ogrid* g) {
+  const long Nc = g->Nc;
+  const int hrr = (g->model == MOD_HRR);
+#pragma omp parallel for schedule(static)
+  for (long i = 0; i < Nc; ++i) {
+    if (g->cls_c[i] != C_MIDDLE && g->cls_c[i] != C_TFC) continue;
+    double S[9] = {0}, gr[3][3] = {{0}}, sg = g->sigma;
+    if (hrr) strain_coarse_g(g, i, S, gr);
+    if (g->dyn) sg = dyn_sigma(g, g->dyn_c, g->dyn_mask_c, Nc, i, gr);
+    collide_L(&g->L, g->model, g->tau_c, sg, g->fc_pre + i, Nc, S, g->fc + i, Nc);
+  }
+#pragma omp parallel for schedule(static)
+  for (long t = 0; t < g->NT; ++t) {
+    long ic = g->tn_c[t];
+    collide_L(&g->L, g->model, g->tau_c, g->sigma, g->fc_pre + ic, Nc, g->S_tn + 9 * t, g->fc + ic, Nc);
+  }
+  int old = g->hs[0];
+  g->hs[0] = g->hs[1];
+  g->hs[1] = g->hs[2];
+  g->hs[2] = old;
+}
+
 static void two_level_step(ogrid* g) {
   const int Q = g->Q;
   const long Nc = g->Nc, Nf = g->Nf, NH = g->NH;
@@ -1040,25 +1161,9 @@ static void two_level_step(ogrid* g) {
   /* velocities of the coarse iteration t, kept for the NH sensors */
   memcpy(g->u_c_prev, g->u_c, sizeof(double) * 3 * (size_t)Nc);
   /* Asynchronous iteration: fine t -> t+1/2, coarse t -> t+1. */
-  /* (a) propagation of the coarse nodes other than TN^c (and covered) */
-#pragma omp parallel for schedule(static)
-  for (long i = 0; i < Nc; ++i)
-    if (g->cls_c[i] == C_MIDDLE || g->cls_c[i] == C_TFC) stream_coarse_node(g, i);
-  /* history at t+1: pre-collision rho, u and f1 = f - f0 */
-  {
-    double* Hp = g->hist[g->hs[2]];
-#pragma omp parallel for schedule(static)
-    for (long h = 0; h < NH; ++h) {
-      long i = g->hnode[h];
-      double f0[MAXQ], uu[3];
-      for (int d = 0; d < 3; ++d) uu[d] = g->u_c[d * Nc + i];
-      feq_L(&g->L, g->rho_c[i], uu, f0);
-      Hp[F_RHO * NH + h] = g->rho_c[i];
-      for (int d = 0; d < 3; ++d) Hp[(F_U + d) * NH + h] = uu[d];
-      for (int q = 0; q < MAXQ; ++q)
-        Hp[(F_F1 + q) * NH + h] = q < Q ? g->fc_pre[q * Nc + i] - f0[q] : 0.0;
-    }
-  }
+  /* (a) propagation of the coarse nodes other than TN^c (and covered),
+   * history at t+1 */
+  coarse_stream_history(g);
   /* (a) propagation of the fine middle nodes */
 #pragma omp parallel for schedule(static)
   for (long i = 0; i < Nf; ++i)
@@ -1111,42 +1216,8 @@ static void two_level_step(ogrid* g) {
     if (g->cls_f[i] == F_MIDDLE || g->cls_f[i] == F_TNF) stream_fine_node(g, g->ff_half, i);
   /* (b, c) ring at t+1 by direct transfer / spatial interpolation */
   ring_macros(g, 0);
-  /* (d) filtered fine -> coarse reconstruction at TN (eqs filterFneq, rescfc,
-   * PijResc).  Reading: rho and u at TN^c are those of the co-located fine
-   * node (unfiltered); the filter acts on the non-equilibrium part only. */
-  {
-    const double kc = orc_rescale_f2c(g->tau_c, g->tau_f);
-    const double ks = orc_strain_f2c();
-    const int D = g->D;
-    const int nst = (D == 2) ? 9 : 27;
-#pragma omp parallel for schedule(static)
-    for (long t = 0; t < g->NT; ++t) {
-      int j[3];
-      long i = g->tn_f[t];
-      fco(g, i, j);
-      double ft[MAXQ] = {0};
-      for (int s = 0; s < nst; ++s) {
-        int o[3] = {s % 3 - 1, (s / 3) % 3 - 1, D == 3 ? s / 9 - 1 : 0};
-        int zs = (g_mut == MUT_FILTER_ZOFF && D == 3) ? 1 : 0;
-        long k = fidx(g, j[0] + o[0], j[1] + o[1], j[2] + o[2] + zs);
-        double f0[MAXQ], uu[3];
-        for (int d = 0; d < 3; ++d) uu[d] = g->u_f[d * Nf + k];
-        feq_L(&g->L, g->rho_f[k], uu, f0);
-        double wgt = orc_filter_weight(D, o);
-        for (int q = 0; q < Q; ++q) ft[q] += wgt * (g->ff_pre[q * Nf + k] - f0[q]);
-      }
-      double f0[MAXQ], uu[3];
-      for (int d = 0; d < 3; ++d) uu[d] = g->u_f[d * Nf + i];
-      feq_L(&g->L, g->rho_f[i], uu, f0);
-      long ic = g->tn_c[t];
-      for (int q = 0; q < Q; ++q) g->fc_pre[q * Nc + ic] = f0[q] + kc * ft[q];
-      g->rho_c[ic] = g->rho_f[i];
-      for (int d = 0; d < 3; ++d) g->u_c[d * Nc + ic] = uu[d];
-      double S[9] = {0};
-      if (hrr) strain_fine(g, i, S);
-      for (int k = 0; k < 9; ++k) g->S_tn[9 * t + k] = ks * S[k];
-    }
-  }
+  /* (d) filtered fine -> coarse reconstruction at TN */
+  coalesce_tn(g);
   /* (e) collision of all nodes */
 #pragma omp parallel for schedule(static)
   for (long i = 0; i < Nf; ++i) {
@@ -1157,32 +1228,66 @@ static void two_level_step(ogrid* g) {
     collide_L(&g->L, g->model, g->tau_f, sg, g->ff_pre + i, Nf, S, g->ff + i, Nf);
   }
   ring_reconstruct_collide(g, 0, g->ff);
-#pragma omp parallel for schedule(static)
-  for (long i = 0; i < Nc; ++i) {
-    if (g->cls_c[i] != C_MIDDLE && g->cls_c[i] != C_TFC) continue;
-    double S[9] = {0}, gr[3][3] = {{0}}, sg = g->sigma;
-    if (hrr) strain_coarse_g(g, i, S, gr);
-    if (g->dyn) sg = dyn_sigma(g, g->dyn_c, g->dyn_mask_c, Nc, i, gr);
-    collide_L(&g->L, g->model, g->tau_c, sg, g->fc_pre + i, Nc, S, g->fc + i, Nc);
+  coarse_collide_advance(g);
+}
+
+/* Nested refinement (more than two levels; the cylinder case of Sec. 10 nests
+ * several refinement domains).  Reading: the two-level step of Sec. 4.3 is
+ * applied recursively -- each substep of the fine level is one whole step of
+ * the pair (fine level, its own patch), so a level of depth l advances 2^l
+ * times per coarse step and every interface keeps the rules of Sec. 4.2 with
+ * its own pair's relaxation times.  Here the fine level's substeps are the
+ * child's steps: the fine state (ring included) is handed to the child's
+ * coarse level, the child steps, and its coarse level comes back; the ring
+ * and the transfer to TN^c are this grid's, as in the two-level step.  BGK
+ * and RR only (the H-RR middle level would need the ring velocities inside
+ * the child's step). */
+static void level_to_child(ogrid* g, const double* f) {
+  ogrid* c = g->child;
+  memcpy(c->fc, f, sizeof(double) * (size_t)g->Q * g->Nf);
+}
+static void child_to_level(ogrid* g, double* f, int pre) {
+  ogrid* c = g->child;
+  memcpy(f, c->fc, sizeof(double) * (size_t)g->Q * g->Nf);
+  if (pre) {
+    memcpy(g->ff_pre, c->fc_pre, sizeof(double) * (size_t)g->Q * g->Nf);
+    memcpy(g->rho_f, c->rho_c, sizeof(double) * (size_t)g->Nf);
+    memcpy(g->u_f, c->u_c, sizeof(double) * 3 * (size_t)g->Nf);
   }
-#pragma omp parallel for schedule(static)
-  for (long t = 0; t < g->NT; ++t) {
-    long ic = g->tn_c[t];
-    collide_L(&g->L, g->model, g->tau_c, g->sigma, g->fc_pre + ic, Nc, g->S_tn + 9 * t, g->fc + ic, Nc);
-  }
-  /* the time levels move on: t+1 becomes t, t becomes t-1 */
-  int old = g->hs[0];
-  g->hs[0] = g->hs[1];
-  g->hs[1] = g->hs[2];
-  g->hs[2] = old;
+}
+static void level_step(ogrid* g);
+static void nested_step(ogrid* g) {
+  memcpy(g->u_c_prev, g->u_c, sizeof(double) * 3 * (size_t)g->Nc);
+  /* Asynchronous iteration: coarse t -> t+1 (propagation, history), fine
+   * t -> t+1/2 as one step of the child from the fine state at t */
+  coarse_stream_history(g);
+  level_to_child(g, g->ff);
+  level_step(g->child);
+  child_to_level(g, g->ff_half, 0);
+  /* ring at t+1/2 */
+  ring_macros(g, 1);
+  if (g_mut != MUT_NEST_RING) ring_reconstruct_collide(g, 1, g->ff_half);
+  /* Synchronous iteration: fine t+1/2 -> t+1, one more child step */
+  level_to_child(g, g_mut == MUT_NEST_SYNC ? g->ff : g->ff_half);
+  level_step(g->child);
+  child_to_level(g, g->ff, 1);
+  /* ring at t+1, transfer to TN^c from the fine pre-collision state at t+1 */
+  ring_macros(g, 0);
+  coalesce_tn(g);
+  ring_reconstruct_collide(g, 0, g->ff);
+  coarse_collide_advance(g);
+}
+static void level_step(ogrid* g) {
+  if (g->child) nested_step(g);
+  else if (g->has_fine) two_level_step(g);
+  else uniform_step(g);
+  g->steps++;
 }
 
 int orc_step(void* hp, int nsteps) {
   ogrid* g = (ogrid*)hp;
   for (int s = 0; s < nsteps; ++s) {
-    if (g->has_fine) two_level_step(g);
-    else uniform_step(g);
-    g->steps++;
+    level_step(g);
   }
   return 0;
 }

@@ -443,9 +443,12 @@ def _smooth_fields(kind, geom, lv):
     velocity component varies along another axis (divergence-free) and the
     acoustic phase runs along (1, 1, 1), so every axis of the interface is
     exercised."""
-    X = I._mesh(geom, lv)
-    D = geom.D
-    n = geom.n[0]
+    return fields_at(kind, I._mesh(geom, lv), geom.n[0], geom.D)
+
+
+def fields_at(kind, X, n, D):
+    """The fields of _smooth_fields at node coordinates X (coarse units) of a
+    periodic box of n coarse cells."""
     k = 2 * math.pi / n
     N = X[0].size
     rho = np.ones(N)
@@ -588,7 +591,6 @@ def pin_interface_relations(lat, model, kind="shear", n=None, lo=None, hi=None, 
     Post-collision non-equilibrium parts are turned back into pre-collision
     ones by 1/(1 - 1/tau_L): BGK scales every population by 1 - 1/tau (eq
     BGKmodel), RR the a2 moment (eqs f1RR, LBMscheme_reg)."""
-    import itertools
     D = 2 if lat == O.D2Q9 else 3
     if n is None:
         n, lo, hi = (32, 8, 24) if D == 2 else (16, 4, 12)
@@ -597,6 +599,17 @@ def pin_interface_relations(lat, model, kind="shear", n=None, lo=None, hi=None, 
     for lv in (0, 1):
         g.set_state(lv, *_smooth_fields(kind, geom, lv))
     g.step(steps)
+    check_interface_relations(g.get_populations(0), g.get_populations(1), g.class_map(1),
+                              g.class_map(0) if model == O.HRR else None, lat, model, n, lo, hi, tau, tol,
+                              label=(kind, sigma))
+
+
+def check_interface_relations(Fc, Ff, fcls, ccls, lat, model, n, lo, hi, tau, tol, label=None):
+    """The relations of pin_interface_relations between the post-collision
+    states Fc (a coarse level of n^D nodes, periodic) and Ff (its patch
+    [lo, hi]^D), fine classes fcls (coarse classes ccls for H-RR)."""
+    import itertools
+    D = 2 if lat == O.D2Q9 else 3
     _, Q, xi, _ = O.lattice(lat)
     G = golden()
     tf = G["tau_fine"]["a"] * tau + G["tau_fine"]["b_num"] / G["tau_fine"]["b_den"]
@@ -604,7 +617,6 @@ def pin_interface_relations(lat, model, kind="shear", n=None, lo=None, hi=None, 
     kcf, kfc = tf / (2 * tau), 2 * tau / tf
     cw = [float(x) for x in _frac(G["spatial_weights"]["num"], G["spatial_weights"]["den"])]
     nf = 2 * (hi - lo) + 1
-    Fc, Ff = g.get_populations(0), g.get_populations(1)
     rc, uc, ac = _level_moments(Fc, xi, D)
     rf, uf, af = _level_moments(Ff, xi, D)
     Sc, Sf = _strain(uc, (n,) * D, D), _strain(uf, (nf,) * D, D)
@@ -614,7 +626,6 @@ def pin_interface_relations(lat, model, kind="shear", n=None, lo=None, hi=None, 
     def neq(F, r, u, i, lat_):
         return F[:, i] - O.feq(lat_, r[i], u[:, i])
 
-    fcls = g.class_map(1)
     pairs = {"macros": ([], []), "ring": ([], []), "tn": ([], [])}
     for idx in np.nonzero(fcls != O.F_MIDDLE)[0]:
         cl = fcls[idx]
@@ -658,7 +669,6 @@ def pin_interface_relations(lat, model, kind="shear", n=None, lo=None, hi=None, 
             pairs["tn"][0].append(lhs)
             pairs["tn"][1].append(rhs)
     if model == O.HRR:
-        ccls = g.class_map(0)
         mc = (ccls == O.C_MIDDLE) | (ccls == O.C_TFC)
         mf = (fcls == O.F_MIDDLE) | (fcls == O.F_TNF)
         pairs["hrr_coarse"] = ((ac / oc)[:, :, mc], (-2 * tau * rc / 3.0 * Sc)[:, :, mc])
@@ -667,4 +677,4 @@ def pin_interface_relations(lat, model, kind="shear", n=None, lo=None, hi=None, 
         lhs, rhs = np.asarray(lhs), np.asarray(rhs)
         assert lhs.size > 0 and np.abs(rhs).max() > 1e-6, (name, "relation not exercised")
         err = float(np.abs(lhs - rhs).max())
-        assert err <= tol, (name, lat, model, kind, err, float(np.abs(rhs).max()))
+        assert err <= tol, (name, lat, model, label, err, float(np.abs(rhs).max()))
