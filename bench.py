@@ -48,7 +48,7 @@ def parse():
     p.add_argument("--no-extra", action="store_true", help="skip the secondary measurements")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-steps", type=int, default=None,
-                   help="coarse steps of the CPU oracle sample (default: 120 of the D3Q19 64^3 subcase, "
+                   help="coarse steps of the CPU oracle sample (default: 300 of the D3Q19 64^3 subcase, "
                         "24 of the D2Q9 grids; about 10-20 s on 16 host cores)")
     p.add_argument("--no-batch", action="store_true", help="skip the batched-instances measurement")
     p.add_argument("--no-serve", action="store_true", help="skip the serving measurement")
@@ -645,7 +645,7 @@ def main():
 
     if not args.no_cpu:
         sw, what = cpu_sample(args.workload)
-        steps = args.cpu_steps if args.cpu_steps is not None else (120 if D == 3 else 24)
+        steps = args.cpu_steps if args.cpu_steps is not None else (300 if D == 3 else 24)
         v, cores, t, ref = cpu_baseline(sw, args.collision, steps)
         result["cpu_baseline"] = {"value": round(v, 2), "unit": "MLUPS", "cores": cores, "kind": "oracle",
                                   "sample": "%d coarse steps of the %s in FP64 (%.1f s)" % (steps, what, t)}

@@ -173,6 +173,23 @@ int lbm_get_totals_noalloc(lbm_handle h, double mass[2], double momentum[6]);
 int lbm_sensors_enable(lbm_handle h, int on);
 int lbm_sensors(lbm_handle h, int level, double threshold, uint8_t* flags, double* diag, int mem);
 
+/* Three nested levels: the grid of *d whose patch (level 1) carries a patch
+ * of its own (level 2), the box [lo2, hi2] of level-1 vertices, with the same
+ * rules as the level-1 patch (at least 4 cells per axis, lo2 >= 2, hi2 <=
+ * nodes - 3).  Each pair of levels is coupled as the two-level grid is (Sec.
+ * 4), with tau = 2 tau - 1/2 from one level to the next (eq rescTau), and
+ * every substep of level 1 is one whole step of the pair (1, 2): level 2
+ * takes four steps per coarse step (the paper's cylinder case nests several
+ * refinement domains, Sec. 10).  Levels 0, 1, 2 in lbm_set_state,
+ * lbm_get_macros, lbm_set/get_populations, lbm_level_dims and
+ * lbm_get_index_maps (level 1 has the classes of its own ring and TN nodes).
+ * In lbm_get_macros covered nodes take the co-located node of the next
+ * level; a level-1 node under level 2 holds no evolved value itself, so the
+ * level-0 nodes above it are unspecified.  BGK and RR only (LBM_EUNSUPPORTED for H-RR); totals,
+ * tuning, variants, sensors, probes and dynamic sigma return
+ * LBM_EUNSUPPORTED on a nested grid.  Errors as lbm_create_grid. */
+int lbm_create_nested(const lbm_grid_desc* d, const int32_t lo2[3], const int32_t hi2[3], lbm_handle* out);
+
 /* Dynamic sigma (H-RR only): a variant that Sec. 9.3 and Sec. 11 of the
  * paper suggest without defining it -- lower sigma (more finite-difference
  * stress) only where non-hydrodynamic modes are detected.  While on, every

@@ -46,16 +46,23 @@ struct LbmError {
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  bool own = true;  // false: a view of another grid's buffer
   void alloc(size_t b) {
     bytes = b;
+    own = true;
     if (b == 0) return;
     if (hipMalloc(&p, b) != hipSuccess) {
       p = nullptr;
       throw LbmError(LBM_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
     }
   }
+  void view(void* q, size_t b) {
+    p = q;
+    bytes = b;
+    own = false;
+  }
   ~DevBuf() {
-    if (p) (void)hipFree(p);
+    if (p && own) (void)hipFree(p);
   }
   template <typename T>
   T* as() const {
@@ -168,6 +175,13 @@ struct GridBase {
   int64_t prof_launches = 0;
   double prof_ms = 0.0;
   int timed_factor = 1;  // fine substeps one timed launch performs
+  // Nested refinement: the fine level carries a patch of its own.  child is
+  // the pair (fine level, its patch), a grid whose periodic coarse level is
+  // this grid's fine level -- the same buffers and layout; its wrap reaches
+  // only the fine ring, which this grid rebuilds -- and whose steps replace
+  // this grid's fine substeps.  Levels 1 and 2 of the nested grid are the
+  // child's levels 0 and 1.
+  std::unique_ptr<GridBase> child;
   virtual ~GridBase() {
     for (auto& e : events) {
       (void)hipEventDestroy(e.first);
@@ -192,12 +206,19 @@ struct GridBase {
   virtual void sensors(int level, double thr, uint8_t* flags, double* prod, bool dev) = 0;
   virtual void probe_enable(int level, const int32_t* node, int64_t capacity) = 0;
   virtual int64_t probe_read(double* out, int64_t max) = 0;
-  int64_t nodes(int level) const { return level == 0 ? g.Nc : g.Nf; }
+  virtual void* coarse_buffer(int i) const = 0;
+  virtual size_t coarse_bytes() const = 0;
+  int64_t nodes(int level) const {
+    if (child && level >= 1) return child->nodes(level - 1);
+    return level == 0 ? g.Nc : g.Nf;
+  }
+  int levels() const { return child ? 3 : (g.has_fine ? 2 : 1); }
   int64_t updates() const {
     if (!g.has_fine) return g.Nc;
     int64_t cov = 1;
     for (int d = 0; d < g.D; ++d) cov *= (g.m[d] - 3);
-    return g.Nc - cov + 2 * g.Nf;
+    // a nested fine level: its own evolving nodes plus twice its patch, twice
+    return g.Nc - cov + 2 * (child ? child->updates() : g.Nf);
   }
 };
 
@@ -265,7 +286,7 @@ struct Grid final : GridBase {
   static size_t pop_bytes(int64_t NP) { return sizeof(S) * (size_t)pop_elems<S>(NP, Q); }
 
   void init() override {
-    fused = desc.collision != LBM_HRR && g.has_fine;
+    fused = desc.collision != LBM_HRR && g.has_fine && !child;
     HIPCHK(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device));
     if (fused) var[1] = 0;
     if (D == 3 && desc.collision == LBM_HRR) var[3] = 0;
@@ -279,9 +300,14 @@ struct Grid final : GridBase {
       if (bytes) HIPCHK(hipMemset(b.p, 0, bytes));
     };
     for (int p = 0; p < 2; ++p) zalloc(cbuf[p], pop_bytes(g.Ncp));
-    if (g.has_fine)
+    if (child) {
+      // the fine level is the child's coarse level: its two state buffers
+      for (int p = 0; p < 2; ++p) fbuf[p].view(child->coarse_buffer(p), child->coarse_bytes());
+    } else if (g.has_fine) {
       for (int p = 0; p < (fused ? 3 : 2); ++p) zalloc(fbuf[p], pop_bytes(g.Nfp));
-    if (g.has_fine && D == 3 && desc.collision != LBM_HRR) zalloc(xbuf, sizeof(S) * (size_t)xband_elems(g, Q));
+    }
+    if (g.has_fine && !child && D == 3 && desc.collision != LBM_HRR)
+      zalloc(xbuf, sizeof(S) * (size_t)xband_elems(g, Q));
     if (desc.collision == LBM_HRR) {
       zalloc(mac_c, plane_bytes(g.Ncp, 1 + D));
       if (g.has_fine) zalloc(mac_f, plane_bytes(g.Nfp, 1 + D));
@@ -319,7 +345,7 @@ struct Grid final : GridBase {
     part.alloc(sizeof(double) * 4 * ((Nmax + 255) / 256));
     tot.alloc(sizeof(double) * 4);
     for (int p = 0; p < 2; ++p) HIPCHK(hipMemset(cbuf[p].p, 0, cbuf[p].bytes));
-    if (g.has_fine)
+    if (g.has_fine && !child)
       for (int p = 0; p < (fused ? 3 : 2); ++p) HIPCHK(hipMemset(fbuf[p].p, 0, fbuf[p].bytes));
     if (mac_c.p) HIPCHK(hipMemset(mac_c.p, 0, mac_c.bytes));
     if (mac_f.p) HIPCHK(hipMemset(mac_f.p, 0, mac_f.bytes));
@@ -334,6 +360,11 @@ struct Grid final : GridBase {
     return make_flat(g.nf[0], g.nf[1], g.nf[2], V, true, D);
   }
 
+  void* coarse_buffer(int i) const override { return cbuf[i].p; }
+  size_t coarse_bytes() const override { return cbuf[0].bytes; }
+  void no_nesting(const char* what) const {
+    if (child) throw LbmError(LBM_EUNSUPPORTED, std::string(what) + " is not available for a nested grid");
+  }
   S* cur_c() { return cbuf[cpar].as<S>(); }
   S* fineA() { return fbuf[fpar].as<S>(); }       // state at integer times
   S* fineB() { return fbuf[fpar ^ 1].as<S>(); }   // the other buffer
@@ -636,6 +667,7 @@ struct Grid final : GridBase {
   }
 
   void set_variants(const int32_t* v) override {
+    no_nesting("launch variants");
     for (int r = 0; r < 4; ++r)
       if (v[r] < 0 || v[r] >= NVAR) throw LbmError(LBM_EINVAL, "variant index out of range");
     for (int r = 0; r < 4; ++r) var[r] = v[r];
@@ -643,6 +675,7 @@ struct Grid final : GridBase {
 
   void tune(int reps, int32_t* out) override {
     HIPCHK(hipSetDevice(device));
+    no_nesting("tuning");
     HIPCHK(hipStreamSynchronize(stream));
     sens_ready = false;  // the trial launches overwrite the previous states
     hipEvent_t e0, e1;
@@ -801,6 +834,43 @@ struct Grid final : GridBase {
     ring_partial = true;
   }
 
+  // One coarse step of a nested grid (BGK / RR): the two-level step of Sec.
+  // 4.3 with each fine substep replaced by one step of the child pair (the
+  // fine level and its patch), applied recursively.  Fine A / B are the
+  // child's coarse buffers: the child steps A -> B (t -> t+1/2), the t+1/2
+  // ring (with the coarse stream) goes into B, the child steps B -> A
+  // (t+1/2 -> t+1), then the t+1 ring into A and the transfer to TN^c.
+  template <int MODEL>
+  void step_nested(hipStream_t s) {
+    S* csrc = cbuf[cpar].as<S>();
+    S* cdst = cbuf[cpar ^ 1].as<S>();
+    S* fA = fineA();
+    S* fB = fineB();
+    double* Hm = hist[hs[0]].as<double>();
+    double* H0 = hist[hs[1]].as<double>();
+    double* Hp = hist[hs[2]].as<double>();
+    const int64_t NH = itf.NH;
+    const double kf = tau_f / (2.0 * tau_c), kc = 2.0 * tau_c / tau_f;
+    const double omf = 1.0 - 1.0 / tau_f, omc = 1.0 - 1.0 / tau_c;
+    constexpr int IB = kIfaceBlock;
+    constexpr int PER = 256 / (D == 2 ? 9 : 27);
+    const unsigned bh = xblocks(NH, IB), bc = xblocks(itf.NT, PER), br2 = xblocks(itf.NR, 256);
+    hipLaunchKernelGGL((k_hist_capture<LAT, DEV, S, MODEL>), dim3(bh), dim3(IB), 0, s, csrc, Hp, g, itf,
+                       G.as<double>(), Hm, H0);
+    child->step(1, s);
+    launch_stream_ring<MODEL>(csrc, cdst, fB, kf, omf, s, nullptr);
+    child->step(1, s);
+    hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, MODEL>), dim3(br2 + bc), dim3(256), 0, s, Hp, fA, fB, cdst, g, itf,
+                       kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, (const S*)nullptr);
+    HIPCHK(hipGetLastError());
+    cpar ^= 1;
+    const int old = hs[0];
+    hs[0] = hs[1];
+    hs[1] = hs[2];
+    hs[2] = old;
+    ring_partial = true;
+  }
+
   // Completes the ring of fine A: rebuilds every population of the ring
   // nodes from the history level the last step's synchronous ring used (now
   // the middle level), which reproduces bitwise the populations stored then.
@@ -821,6 +891,14 @@ struct Grid final : GridBase {
 
   void step(int n, hipStream_t s) override {
     HIPCHK(hipSetDevice(device));
+    if (child) {
+      for (int k = 0; k < n; ++k) {
+        if (desc.collision == LBM_BGK) step_nested<M_BGK>(s);
+        else step_nested<M_RR>(s);
+      }
+      HIPCHK(hipGetLastError());
+      return;
+    }
     for (int k = 0; k < n; ++k) {
       if (sensors_on) sensors_before(s);
       if (!g.has_fine) step_uniform(s);
@@ -861,6 +939,7 @@ struct Grid final : GridBase {
   }
   void set_dynamic_sigma(bool on, double sigma_dyn, double thr) override {
     HIPCHK(hipSetDevice(device));
+    no_nesting("dynamic sigma");
     HIPCHK(hipStreamSynchronize(stream));
     if (on) {
       // a fresh start: no previous divergences and curls
@@ -877,6 +956,7 @@ struct Grid final : GridBase {
   }
   void sensors_enable(bool on) override {
     HIPCHK(hipSetDevice(device));
+    no_nesting("the NH sensors");
     HIPCHK(hipStreamSynchronize(stream));
     if (on && !sUc.p) {
       auto zalloc = [](DevBuf& b, size_t bytes) {
@@ -914,6 +994,7 @@ struct Grid final : GridBase {
   }
   void probe_enable(int level, const int32_t* node, int64_t capacity) override {
     HIPCHK(hipSetDevice(device));
+    no_nesting("probe recording");
     HIPCHK(hipStreamSynchronize(stream));
     if (level < 0) {
       probe_level = -1;
@@ -973,6 +1054,12 @@ struct Grid final : GridBase {
 
   void set_state(int level, const double* rho, const double* u, bool dev) override {
     HIPCHK(hipSetDevice(device));
+    if (child && level >= 1) {
+      HIPCHK(hipDeviceSynchronize());
+      ring_partial = false;
+      child->set_state(level - 1, rho, u, dev);
+      return;
+    }
     sens_ready = false;
     HIPCHK(hipDeviceSynchronize());
     // a coarse reset replaces the history the ring completion reads
@@ -1001,6 +1088,11 @@ struct Grid final : GridBase {
     HIPCHK(hipSetDevice(device));
     const int64_t N = nodes(level);
     complete_ring();
+    if (child && level >= 1) {
+      HIPCHK(hipStreamSynchronize(stream));
+      child->get_macros(level - 1, rho, u, dev);
+      return;
+    }
     compute_macros(level);
     const hipMemcpyKind k = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     HIPCHK(hipMemcpyAsync(rho, tmp_rho.p, sizeof(double) * N, k, stream));
@@ -1019,6 +1111,12 @@ struct Grid final : GridBase {
 
   void set_pops(int level, const double* f, bool dev) override {
     HIPCHK(hipSetDevice(device));
+    if (child && level >= 1) {
+      HIPCHK(hipDeviceSynchronize());
+      ring_partial = false;
+      child->set_pops(level - 1, f, dev);
+      return;
+    }
     sens_ready = false;
     HIPCHK(hipDeviceSynchronize());
     if (level == 0) complete_ring();
@@ -1042,6 +1140,11 @@ struct Grid final : GridBase {
     HIPCHK(hipSetDevice(device));
     const int64_t N = nodes(level);
     complete_ring();
+    if (child && level >= 1) {
+      HIPCHK(hipStreamSynchronize(stream));
+      child->get_pops(level - 1, f, dev);
+      return;
+    }
     ensure_tmp_f(N);
     const S* src = level == 0 ? cur_c() : fineA();
     hipLaunchKernelGGL((k_pops_out<LAT, DEV, S>), dim3(blocks(Q * N, 256)), dim3(256), 0, stream, src,
@@ -1056,6 +1159,7 @@ struct Grid final : GridBase {
 
   void totals_in(double* mass, double* mom, double* pbuf, double* fin) override {
     HIPCHK(hipSetDevice(device));
+    no_nesting("totals");
     complete_ring();
     for (int lv = 0; lv < 2; ++lv) {
       mass[lv] = 0.0;
@@ -1864,6 +1968,65 @@ int lbm_create_grid(const lbm_grid_desc* d, lbm_handle* out) {
   return LBM_OK;
 }
 
+int lbm_create_nested(const lbm_grid_desc* d, const int32_t lo2[3], const int32_t hi2[3], lbm_handle* out) {
+  std::lock_guard<std::recursive_mutex> lk(g_api_mu);
+  if (!d || !lo2 || !hi2 || !out) {
+    g_create_error = "null argument";
+    return LBM_EINVAL;
+  }
+  *out = nullptr;
+  std::unique_ptr<GridBase> gb;
+  try {
+    Geo geo = validate(*d);
+    if (!geo.has_fine) throw LbmError(LBM_EINVAL, "a nested grid needs the level-1 patch");
+    if (d->collision == LBM_HRR) throw LbmError(LBM_EUNSUPPORTED, "nested grids take BGK or RR");
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (d->device < 0 || d->device >= ndev) throw LbmError(LBM_EINVAL, "no such HIP device");
+    // the pair (level 1, level 2): level 1 as a periodic coarse grid
+    lbm_grid_desc dc = *d;
+    for (int k = 0; k < 3; ++k) {
+      dc.n[k] = geo.nf[k];
+      dc.lo[k] = lo2[k];
+      dc.hi[k] = hi2[k];
+    }
+    dc.tau_coarse = 2.0 * d->tau_coarse - 0.5;
+    Geo gc = validate(dc);
+    if (!gc.has_fine) throw LbmError(LBM_EINVAL, "a nested grid needs the level-2 patch");
+    std::unique_ptr<GridBase> child(make_grid(dc));
+    child->desc = dc;
+    child->g = gc;
+    child->device = d->device;
+    HIPCHK(hipSetDevice(d->device));
+    HIPCHK(hipStreamCreateWithFlags(&child->stream, hipStreamNonBlocking));
+    build_tables(gc, child->tabs);
+    child->init();
+    // level 1 is stored in the child's coarse layout
+    geo.pf = gc.pc;
+    geo.fxo = 0;
+    geo.Nfp = gc.Ncp;
+    gb.reset(make_grid(*d));
+    gb->desc = *d;
+    gb->g = geo;
+    gb->device = d->device;
+    gb->child = std::move(child);
+    HIPCHK(hipStreamCreateWithFlags(&gb->stream, hipStreamNonBlocking));
+    build_tables(geo, gb->tabs);
+    gb->init();
+    HIPCHK(hipDeviceSynchronize());
+  } catch (const LbmError& e) {
+    g_create_error = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    g_create_error = "host allocation failed";
+    return LBM_ENOMEM;
+  }
+  auto* h = new lbm_grid;
+  h->impl = std::move(gb);
+  *out = h;
+  return LBM_OK;
+}
+
 int lbm_destroy(lbm_handle h) {
   if (!h) return LBM_EINVAL;
   std::lock_guard<std::recursive_mutex> lk(g_api_mu);
@@ -1874,7 +2037,7 @@ int lbm_destroy(lbm_handle h) {
 }
 
 static bool bad_level(lbm_handle h, int level) {
-  return !h || level < 0 || level > 1 || (level == 1 && !h->impl->g.has_fine);
+  return !h || level < 0 || level >= h->impl->levels();
 }
 
 int lbm_set_state(lbm_handle h, int level, const double* rho, const double* u, int mem) {
@@ -2018,7 +2181,10 @@ int lbm_probe_read(lbm_handle h, double* out, int64_t max, int64_t* count) {
 int lbm_get_index_maps(lbm_handle h, int level, uint8_t* cls, int mem) {
   if (bad_level(h, level) || !cls || (mem != LBM_HOST && mem != LBM_DEVICE)) return LBM_EINVAL;
   return guard(h, [&] {
-    const auto& v = level == 0 ? h->impl->tabs.cls_c : h->impl->tabs.cls_f;
+    // nested: level 1 has the classes of the parent pair (its ring, TN^f),
+    // level 2 those of the child pair
+    const GridBase& G = level == 2 ? *h->impl->child : *h->impl;
+    const auto& v = level == 0 ? G.tabs.cls_c : G.tabs.cls_f;
     if (mem == LBM_HOST) std::memcpy(cls, v.data(), v.size());
     else HIPCHK(hipMemcpy(cls, v.data(), v.size(), hipMemcpyHostToDevice));
   });
@@ -2026,7 +2192,8 @@ int lbm_get_index_maps(lbm_handle h, int level, uint8_t* cls, int mem) {
 
 int lbm_level_dims(lbm_handle h, int level, int32_t dims[3]) {
   if (bad_level(h, level) || !dims) return LBM_EINVAL;
-  for (int k = 0; k < 3; ++k) dims[k] = level == 0 ? h->impl->g.n[k] : h->impl->g.nf[k];
+  const Geo& G = level == 2 ? h->impl->child->g : h->impl->g;
+  for (int k = 0; k < 3; ++k) dims[k] = level == 0 ? G.n[k] : G.nf[k];
   return LBM_OK;
 }
 

@@ -33,7 +33,7 @@ LBM_N_VARIANTS = 4
 EXPORTS = (
     "lbm_create_grid", "lbm_destroy", "lbm_set_state", "lbm_step", "lbm_get_macros",
     "lbm_set_populations", "lbm_get_populations", "lbm_get_totals", "lbm_get_totals_noalloc", "lbm_sensors_enable", "lbm_sensors",
-    "lbm_set_dynamic_sigma",
+    "lbm_set_dynamic_sigma", "lbm_create_nested",
     "lbm_probe_enable", "lbm_probe_read", "lbm_get_index_maps",
     "lbm_level_dims", "lbm_lattice_info", "lbm_interface_counts", "lbm_interface_tables",
     "lbm_updates_per_step", "lbm_profile_enable", "lbm_kernel_time", "lbm_tune", "lbm_set_variants",
@@ -72,6 +72,8 @@ def load(path: str = LIB_PATH):
     L = ctypes.CDLL(path)
     vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
     L.lbm_create_grid.argtypes = [ctypes.POINTER(lbm_grid_desc), ctypes.POINTER(vp)]
+    L.lbm_create_nested.argtypes = [ctypes.POINTER(lbm_grid_desc), ctypes.POINTER(ctypes.c_int32),
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(vp)]
     L.lbm_destroy.argtypes = [vp]
     L.lbm_set_state.argtypes = [vp, ip, vp, vp, ip]
     L.lbm_step.argtypes = [vp, ip, vp]
@@ -173,6 +175,33 @@ def lbm_footprint(desc):
     if rc != LBM_OK:
         raise LbmError(rc, load().lbm_last_error(None).decode())
     return v.value
+
+
+def make_desc_(lattice, collision, precision, n, lo, hi, tau_coarse, sigma, device):
+    d = lbm_grid_desc()
+    d.lattice, d.collision, d.precision = lattice, collision, precision
+    D = 2 if lattice == LBM_D2Q9 else 3
+    nn = list(n) + [1] * (3 - len(n))
+    lo = list(lo if lo is not None else [0] * D) + [0] * (3 - D)
+    hi = list(hi if hi is not None else [0] * D) + [0] * (3 - D)
+    for k in range(3):
+        d.n[k], d.lo[k], d.hi[k] = int(nn[k]), int(lo[k]), int(hi[k])
+    d.tau_coarse, d.sigma, d.device, d.reserved = float(tau_coarse), float(sigma), int(device), 0
+    return d
+
+
+def lbm_create_nested(lattice, collision, precision, n, lo, hi, lo2, hi2, tau_coarse=0.51, sigma=0.995, device=0):
+    """Three nested levels: the patch [lo, hi] of coarse vertices carries the
+    patch [lo2, hi2] of its own vertices (BGK, RR)."""
+    d = make_desc_(lattice, collision, precision, n, lo, hi, tau_coarse, sigma, device)
+    D = 2 if lattice == LBM_D2Q9 else 3
+    l2 = (ctypes.c_int32 * 3)(*[int(x) for x in (list(lo2)[:D] + [0] * (3 - D))])
+    h2 = (ctypes.c_int32 * 3)(*[int(x) for x in (list(hi2)[:D] + [0] * (3 - D))])
+    h = ctypes.c_void_p()
+    rc = load().lbm_create_nested(ctypes.byref(d), l2, h2, ctypes.byref(h))
+    if rc != LBM_OK:
+        raise LbmError(rc, load().lbm_last_error(None).decode())
+    return h
 
 
 def lbm_create_grid(lattice, collision, precision, n, lo=None, hi=None, tau_coarse=0.51, sigma=0.995, device=0):
@@ -510,3 +539,18 @@ class Batch:
         v = ctypes.c_int64()
         _bcheck(load().lbm_batch_slot_steps(self.b, slot, ctypes.byref(v)), self.b)
         return v.value
+
+
+class Nested(Grid):
+    """Three nested levels (levels 0, 1, 2) over one handle: the coarse
+    periodic grid, its patch [lo, hi], and the patch [lo2, hi2] of level-1
+    vertices.  BGK and RR."""
+
+    def __init__(self, lattice, collision, precision, n, lo, hi, lo2, hi2, tau_coarse=0.51, sigma=0.995, device=0):
+        self.h = lbm_create_nested(lattice, collision, precision, n, lo, hi, lo2, hi2, tau_coarse, sigma, device)
+        self.D, self.Q, self.xi, self.w = lbm_lattice_info(lattice)
+        self.lattice, self.collision, self.precision = lattice, collision, precision
+        D = self.D
+        self.shape = (tuple(int(x) for x in list(n)[:D]), tuple(int(x) for x in list(lo)[:D]),
+                      tuple(int(x) for x in list(hi)[:D]))
+        self.device = device
