@@ -312,7 +312,68 @@ def paper_cases():
                                                        **({"readout_fine_s": res["readout_fine_s"]}
                                                           if "readout_fine_s" in res else {})}
         print(f"# paper case {name}: {out[f'd2q9_4096_{col.lower()}_fp32_{name}']}", file=sys.stderr, flush=True)
+    out["d3q19_256_three_levels_rr_fp32"] = three_levels()
+    print(f"# paper case three levels: {out['d3q19_256_three_levels_rr_fp32']}", file=sys.stderr, flush=True)
     return out
+
+
+def three_levels(steps=40):
+    """Nested refinement (Sec. 10): D3Q19 RR FP32, coarse 256^3 with the
+    level-1 patch [64, 192]^3 (257^3 nodes) and the level-2 patch [64, 192]^3
+    of level-1 vertices (257^3 nodes, coarse [96, 160]^3); a plane-wave
+    pulse crossing both interfaces on a uniform flow.  Throughput in lattice
+    updates (level l counts 2^l per coarse step) against the two-level grid
+    of the same coarse grid and level-1 patch, and its fraction of the
+    per-update roofline (one read and one write of the populations)."""
+    import numpy as np
+    import torch
+    from paper_2004_11863_amd import lbm
+    n, lo, hi, lo2, hi2 = 256, 64, 192, 64, 192
+    U, A, R = 0.05, 1e-3, 6.0
+
+    def level_x(lv):
+        if lv == 0:
+            return np.arange(n, dtype=np.float64)
+        x1 = lo + 0.5 * np.arange(2 * (hi - lo) + 1)
+        return x1 if lv == 1 else lo + 0.5 * (lo2 + 0.5 * np.arange(2 * (hi2 - lo2) + 1))
+
+    def state(g, lv):
+        x = level_x(lv)
+        m = x.size
+        rho1 = 1.0 + A * np.exp(-((x - 80.0) ** 2) / (2 * R * R))  # varies along x only
+        rho = np.broadcast_to(rho1[None, None, :], (m, m, m)).reshape(-1).copy()
+        u = np.zeros((3, m ** 3))
+        u[0] = U
+        g.set_state(lv, rho, u)
+
+    res = {}
+    for levels in (3, 2):
+        if levels == 3:
+            g = lbm.Nested(lbm.LBM_D3Q19, lbm.LBM_RR, lbm.LBM_FP32_DEV, (n,) * 3, (lo,) * 3, (hi,) * 3, (lo2,) * 3,
+                           (hi2,) * 3, tau_coarse=0.51)
+        else:
+            g = lbm.Grid(lbm.LBM_D3Q19, lbm.LBM_RR, lbm.LBM_FP32_DEV, (n,) * 3, (lo,) * 3, (hi,) * 3, tau_coarse=0.51)
+            g.variants = g.tune(reps=2)
+        for lv in range(levels):
+            state(g, lv)
+        g.step(3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ups = g.updates_per_step()
+        mlups = ups * steps / dt / 1e6
+        r, _ = g.get_macros(levels - 1)
+        finite = bool(np.isfinite(r).all())
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+        res[f"levels{levels}"] = {"mlups": round(mlups, 1), "updates_per_step": ups,
+                                  "ms_per_step": round(dt / steps * 1e3, 3),
+                                  "frac_of_update_roofline": round(mlups * 1e6 * 2 * 19 * 4 / 1e9 / HBM_PEAK_GBS, 4),
+                                  "finite": finite}
+    return {"steps": steps, **res}
 
 
 def batched(n_inst, steps):

@@ -127,21 +127,25 @@ struct Node {
   };
 
   // eqs moment_rho, moment_rhoU.  r0: sum of stored values (rho for DEV = 0,
-  // rho - 1 for DEV = 1).
+  // rho - 1 for DEV = 1).  Opposite velocities enter as the pair sum (even
+  // moments) and the pair difference (odd moments); sums start from -0, which
+  // the compiler folds away (x + -0 = x exactly).
   __device__ __host__ static __forceinline__ void moments(const T* s, T& rho, T& r0, T* u) {
-    T m = T(0), jx = T(0), jy = T(0), jz = T(0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      m += s[i];
-      if (L::cx(i) > 0) jx += s[i];
-      if (L::cx(i) < 0) jx -= s[i];
-      if (L::cy(i) > 0) jy += s[i];
-      if (L::cy(i) < 0) jy -= s[i];
-      if (D == 3) {
-        if (L::cz(i) > 0) jz += s[i];
-        if (L::cz(i) < 0) jz -= s[i];
+    T m = s[0], jx = T(-0.0), jy = T(-0.0), jz = T(-0.0);
+    static_for<Q>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      constexpr int j = opp(i);
+      if constexpr (i != 0 && i < j) {
+        const T p = s[i] + s[j], d = s[i] - s[j];
+        m += p;
+        if constexpr (L::cx(i) > 0) jx += d;
+        if constexpr (L::cx(i) < 0) jx -= d;
+        if constexpr (L::cy(i) > 0) jy += d;
+        if constexpr (L::cy(i) < 0) jy -= d;
+        if constexpr (D == 3 && L::cz(i) > 0) jz += d;
+        if constexpr (D == 3 && L::cz(i) < 0) jz -= d;
       }
-    }
+    });
     r0 = m;
     rho = DEV ? T(1) + m : m;
     const T ir = T(1) / rho;
@@ -150,24 +154,28 @@ struct Node {
     u[2] = (D == 3) ? jz * ir : T(0);
   }
 
-  // Second moments Pi_ab = sum_i xi_a xi_b s_i.
+  // Second moments Pi_ab = sum_i xi_a xi_b s_i, from the pair sums (xi_a xi_b
+  // is the same for opposite velocities).
   __device__ __host__ static __forceinline__ Sym<T> second(const T* s) {
-    T pxx = T(0), pyy = T(0), pzz = T(0), pxy = T(0), pxz = T(0), pyz = T(0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const int x = L::cx(i), y = L::cy(i), z = L::cz(i);
-      if (x) pxx += s[i];
-      if (y) pyy += s[i];
-      if (D == 3 && z) pzz += s[i];
-      if (x * y > 0) pxy += s[i];
-      if (x * y < 0) pxy -= s[i];
-      if (D == 3) {
-        if (x * z > 0) pxz += s[i];
-        if (x * z < 0) pxz -= s[i];
-        if (y * z > 0) pyz += s[i];
-        if (y * z < 0) pyz -= s[i];
+    T pxx = T(-0.0), pyy = T(-0.0), pzz = T(-0.0), pxy = T(-0.0), pxz = T(-0.0), pyz = T(-0.0);
+    static_for<Q>([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      constexpr int j = opp(i);
+      if constexpr (i != 0 && i < j) {
+        constexpr int x = L::cx(i), y = L::cy(i), z = L::cz(i);
+        const T p = s[i] + s[j];
+        if constexpr (x != 0) pxx += p;
+        if constexpr (y != 0) pyy += p;
+        if constexpr (D == 3 && z != 0) pzz += p;
+        if constexpr (x * y > 0) pxy += p;
+        if constexpr (x * y < 0) pxy -= p;
+        if constexpr (D == 3 && x * z > 0) pxz += p;
+        if constexpr (D == 3 && x * z < 0) pxz -= p;
+        if constexpr (D == 3 && y * z > 0) pyz += p;
+        if constexpr (D == 3 && y * z < 0) pyz -= p;
       }
-    }
+    });
+    if constexpr (D == 2) pzz = pxz = pyz = T(0);
     return Sym<T>{pxx, pyy, pzz, pxy, pxz, pyz};
   }
 
@@ -236,7 +244,7 @@ struct Node {
   template <int i>
   __device__ __host__ static __forceinline__ T odd(const Coef& c) {
     constexpr int x = L::cx(i), y = L::cy(i), z = L::cz(i);
-    T o = T(0);
+    T o = T(-0.0);  // folded away by the first term
     if (x > 0) o += c.J[0];
     if (x < 0) o -= c.J[0];
     if (y > 0) o += c.J[1];

@@ -325,6 +325,40 @@ def test_variants_on_ragged_3d_and_2d(D):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_d3q19_fused_fine_wide_patch(prec):
+    """The fused D3Q19 fine kernel (fine-role variants 2, 3) on a patch that
+    spans several tiles in x (fine 141 nodes) and y and a run of planes in z,
+    so that tiles with neither ring nor band nodes exist beside the edge
+    tiles; BGK and RR: bitwise the two-launch substeps, every stored value
+    finite, and the two-launch run against the oracle (FP64)."""
+    lbm = _lbm()
+    p = lbm.LBM_FP32_DEV if prec == "fp32" else lbm.LBM_FP64
+    geom = _geom(3, (80, 20, 22), (4, 4, 3), (74, 15, 19))
+    wl = I.Workload(geom=geom, U=(0.05, -0.01, 0.02), pulses=[I.Pulse(center=(40.0, 9.6, 11.3), A=1e-3, R=3.0)],
+                    vortices=[I.Vortex(center=(38.0, 10.0, 0.0), eps=0.01)])
+    for model in ("BGK", "RR"):
+        ref = None
+        for v in range(lbm.LBM_N_VARIANTS):
+            check = v == 0 and prec == "fp64"
+            gpu, orc, levels = make_pair(wl, model, p, with_oracle=check)
+            gpu.set_variants([0, v, 0, 0])
+            gpu.step(4)
+            _all_stored_finite(gpu)
+            if check:
+                orc.step(4)
+                w = compare_fp64(gpu, orc, levels)
+                assert max(w.values()) <= TOL64, (model, w)
+            out = (gpu.get_populations(0), gpu.get_populations(1))
+            live = gpu.class_map(0) != lbm.LBM_C_COVERED
+            gpu.close()
+            if ref is None:
+                ref = out
+            else:
+                assert np.array_equal(out[0][:, live], ref[0][:, live]), (model, v)
+                assert np.array_equal(out[1], ref[1]), (model, v)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_d3q19_hrr_one_pass_variants(prec):
     """D3Q19 H-RR fine substeps run as velocity pass + collision (fine H-RR
     role variants 0, 1) or in one marching pass with the velocities of three
