@@ -46,6 +46,7 @@ MUTATIONS = {
     "face_axes": 14,
     "nest_sync": 15,
     "nest_ring": 16,
+    "nest_inj": 17,
 }
 
 
@@ -359,7 +360,8 @@ class Nested:
     patch [lo, hi] of coarse vertices, level 2 the patch [lo2, hi2] of level-1
     vertices (ratio 2 at each interface).  The two-level step of Sec. 4.3
     applied to each pair: every substep of level 1 is a whole step of the
-    pair (1, 2).  BGK and RR."""
+    pair (1, 2), which receives the level-1 ring's rho and u at its time.
+    BGK, RR and H-RR."""
 
     def __init__(self, lattice_id, model, n, lo, hi, lo2, hi2, tau_c=0.51, sigma=0.995):
         D, Q, xi, w = lattice(lattice_id)

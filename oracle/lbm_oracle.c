@@ -63,7 +63,8 @@ enum {
   MUT_FILTER_ZOFF = 13,   /* 3D filter sampling shifted by one node along z   */
   MUT_FACE_AXES = 14,     /* face-centre stencil built with its axes swapped  */
   MUT_NEST_SYNC = 15,     /* nested: second child step from the state at t    */
-  MUT_NEST_RING = 16      /* nested: no ring rebuilt at t+1/2 for the child   */
+  MUT_NEST_RING = 16,     /* nested: no ring rebuilt at t+1/2 for the child   */
+  MUT_NEST_INJ = 17       /* nested H-RR: child without the ring's rho, u     */
 };
 
 /* ------------------------------------------------------------------------ */
@@ -411,6 +412,12 @@ typedef struct ogrid_s {
    * this grid rebuilds), evolved by child steps in place of the fine
    * substeps. */
   struct ogrid_s* child;
+  /* Set on a child: rho and u of the parent's fine ring at the time of the
+   * child's step (n_inj nodes of this grid's coarse level), written over the
+   * values its periodic propagation leaves there. */
+  const long* inj_node;
+  const double *inj_rho, *inj_u;
+  long n_inj;
 } ogrid;
 
 static long cidx(const ogrid* g, int x, int y, int z) {
@@ -669,10 +676,9 @@ void* orc_create(int lat, int model, const int* n, const int* lo, const int* hi,
  * and a patch of the fine level given by lo2/hi2 in fine-level vertices
  * (the same rules: at least 4 cells, 2 nodes from the fine ring).  The
  * fine level's pair has tau = 2 tau_f - 1/2 (eq rescTau, applied to each
- * pair).  BGK and RR only.  NULL on invalid input. */
+ * pair).  NULL on invalid input. */
 void* orc_create_nested(int lat, int model, const int* n, const int* lo, const int* hi, const int* lo2,
                         const int* hi2, double tau_c, double sigma) {
-  if (model == MOD_HRR) return NULL;
   ogrid* g = (ogrid*)orc_create(lat, model, n, lo, hi, tau_c, sigma);
   if (!g) return NULL;
   if (!g->has_fine) { orc_destroy(g); return NULL; }
@@ -1073,6 +1079,12 @@ static void coarse_stream_history(ogrid* g) {
 #pragma omp parallel for schedule(static)
   for (long i = 0; i < Nc; ++i)
     if (g->cls_c[i] == C_MIDDLE || g->cls_c[i] == C_TFC) stream_coarse_node(g, i);
+  if (g_mut != MUT_NEST_INJ)
+    for (long r = 0; r < g->n_inj; ++r) {
+      long i = g->inj_node[r];
+      g->rho_c[i] = g->inj_rho[r];
+      for (int d = 0; d < 3; ++d) g->u_c[d * Nc + i] = g->inj_u[3 * r + d];
+    }
   double* Hp = g->hist[g->hs[2]];
 #pragma omp parallel for schedule(static)
   for (long h = 0; h < NH; ++h) {
@@ -1153,9 +1165,37 @@ static void coarse_collide_advance(ogrid* g) {
   g->hs[2] = old;
 }
 
-static void two_level_step(ogrid* g) {
+/* H-RR, after the fine collision at t+1/2 (Sec. 4.3 with the strain rate of
+ * eq stressT): (e) fictitious propagation of the fine post-collision state
+ * onto TN^f gives u(TN^c, t+1); (f) the coarse strain rate at t+1 on the
+ * history nodes, which the ring interpolates. */
+static void hrr_tn_strain(ogrid* g) {
   const int Q = g->Q;
   const long Nc = g->Nc, Nf = g->Nf, NH = g->NH;
+#pragma omp parallel for schedule(static)
+  for (long t = 0; t < g->NT; ++t) {
+    int j[3];
+    long i = g->tn_f[t];
+    fco(g, i, j);
+    double f[MAXQ], r, uu[3];
+    for (int q = 0; q < Q; ++q)
+      f[q] = g->ff_half[q * Nf + fidx(g, j[0] - g->L.xi[q][0], j[1] - g->L.xi[q][1], j[2] - g->L.xi[q][2])];
+    moments_L(&g->L, f, 1, &r, uu);
+    long ic = g->tn_c[t];
+    g->rho_c[ic] = r;
+    for (int d = 0; d < 3; ++d) g->u_c[d * Nc + ic] = uu[d];
+  }
+  double* Hp = g->hist[g->hs[2]];
+#pragma omp parallel for schedule(static)
+  for (long h = 0; h < NH; ++h) {
+    double S[9];
+    strain_coarse(g, g->hnode[h], S);
+    for (int k = 0; k < 9; ++k) Hp[(F_S + k) * NH + h] = S[k];
+  }
+}
+
+static void two_level_step(ogrid* g) {
+  const long Nc = g->Nc, Nf = g->Nf;
   const int hrr = (g->model == MOD_HRR);
 
   /* velocities of the coarse iteration t, kept for the NH sensors */
@@ -1179,30 +1219,7 @@ static void two_level_step(ogrid* g) {
     if (g->dyn) sg = dyn_sigma(g, g->dyn_f, g->dyn_mask_f, Nf, i, gr);
     collide_L(&g->L, g->model, g->tau_f, sg, g->ff_pre + i, Nf, S, g->ff_half + i, Nf);
   }
-  if (hrr) {
-    /* (e) fictitious propagation onto TN^f: u(TN, t+1) */
-#pragma omp parallel for schedule(static)
-    for (long t = 0; t < g->NT; ++t) {
-      int j[3];
-      long i = g->tn_f[t];
-      fco(g, i, j);
-      double f[MAXQ], r, uu[3];
-      for (int q = 0; q < Q; ++q)
-        f[q] = g->ff_half[q * Nf + fidx(g, j[0] - g->L.xi[q][0], j[1] - g->L.xi[q][1], j[2] - g->L.xi[q][2])];
-      moments_L(&g->L, f, 1, &r, uu);
-      long ic = g->tn_c[t];
-      g->rho_c[ic] = r;
-      for (int d = 0; d < 3; ++d) g->u_c[d * Nc + ic] = uu[d];
-    }
-    /* (f) coarse strain rate at t+1 on the history nodes */
-    double* Hp = g->hist[g->hs[2]];
-#pragma omp parallel for schedule(static)
-    for (long h = 0; h < NH; ++h) {
-      double S[9];
-      strain_coarse(g, g->hnode[h], S);
-      for (int k = 0; k < 9; ++k) Hp[(F_S + k) * NH + h] = S[k];
-    }
-  }
+  if (hrr) hrr_tn_strain(g);
   /* (g, h, i) ring populations and strain rate at t+1/2, ring collision */
   ring_reconstruct_collide(g, 1, g->ff_half);
 
@@ -1239,12 +1256,17 @@ static void two_level_step(ogrid* g) {
  * its own pair's relaxation times.  Here the fine level's substeps are the
  * child's steps: the fine state (ring included) is handed to the child's
  * coarse level, the child steps, and its coarse level comes back; the ring
- * and the transfer to TN^c are this grid's, as in the two-level step.  BGK
- * and RR only (the H-RR middle level would need the ring velocities inside
- * the child's step). */
+ * and the transfer to TN^c are this grid's, as in the two-level step.  The
+ * ring's rho and u at the child's time (t+1/2, then t+1) are computed before
+ * the child steps and given to it: with H-RR its collision of the nodes next
+ * to the ring takes the centred differences of eq stressT across them. */
 static void level_to_child(ogrid* g, const double* f) {
   ogrid* c = g->child;
   memcpy(c->fc, f, sizeof(double) * (size_t)g->Q * g->Nf);
+  c->inj_node = g->rnode;
+  c->inj_rho = g->r_rho;
+  c->inj_u = g->r_u;
+  c->n_inj = g->NR;
 }
 static void child_to_level(ogrid* g, double* f, int pre) {
   ogrid* c = g->child;
@@ -1261,18 +1283,20 @@ static void nested_step(ogrid* g) {
   /* Asynchronous iteration: coarse t -> t+1 (propagation, history), fine
    * t -> t+1/2 as one step of the child from the fine state at t */
   coarse_stream_history(g);
+  ring_macros(g, 1);
   level_to_child(g, g->ff);
   level_step(g->child);
   child_to_level(g, g->ff_half, 0);
+  /* H-RR: u(TN^c, t+1) and the strain rate on the history nodes */
+  if (g->model == MOD_HRR) hrr_tn_strain(g);
   /* ring at t+1/2 */
-  ring_macros(g, 1);
   if (g_mut != MUT_NEST_RING) ring_reconstruct_collide(g, 1, g->ff_half);
   /* Synchronous iteration: fine t+1/2 -> t+1, one more child step */
+  ring_macros(g, 0);
   level_to_child(g, g_mut == MUT_NEST_SYNC ? g->ff : g->ff_half);
   level_step(g->child);
   child_to_level(g, g->ff, 1);
-  /* ring at t+1, transfer to TN^c from the fine pre-collision state at t+1 */
-  ring_macros(g, 0);
+  /* transfer to TN^c from the fine pre-collision state at t+1, ring at t+1 */
   coalesce_tn(g);
   ring_reconstruct_collide(g, 0, g->ff);
   coarse_collide_advance(g);

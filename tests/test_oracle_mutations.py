@@ -54,6 +54,7 @@ def test_all_pins_pass_without_mutation():
     assert bad == []
 
 
+# (the nest_* mistakes act only in nested grids; the nested pins catch them)
 @pytest.mark.parametrize("mutation", sorted(m for m in O.MUTATIONS if not m.startswith("nest_")))
 def test_mutation_is_detected(mutation):
     O.set_mutation(mutation)

@@ -2,12 +2,19 @@
 case of Sec. 10 nests refinement domains).  Reading: the two-level step of
 Sec. 4.3 applied to each pair -- every substep of level 1 is a whole step of
 the pair (level 1, level 2) -- with tau = 2 tau - 1/2 from one level to the
-next (eq rescTau).  BGK and RR.
+next (eq rescTau); the child pair receives the level-1 ring's rho and u at
+its time, across which its H-RR collision takes centred differences.  BGK,
+RR and H-RR.
 
 * A uniform flow stays uniform on all three levels.
 * After a few steps both interfaces obey the closed-form transfer relations
   of Sec. 4.2 exactly (the two-level pin's relations, rebuilt from their
-  definitions, applied to the pair (0, 1) and to the pair (1, 2)).
+  definitions, applied to the pair (0, 1) and to the pair (1, 2)); with
+  H-RR at sigma = 0 also the collision relation a2 = (1 - 1/tau)(-2 tau rho
+  c_s^2 S) at every node a level collides with its own centred differences
+  -- on level 1 up to its ring, so the ring velocities the child used are
+  checked against those of the ring's final state.  The child run without
+  them (planted) breaks that relation.
 * Derived bound, one level up: the three-level grid is the two-level grid
   with part of its patch refined once more; with a consistent interface its
   solution departs from the two-level one by no more than a uniformly
@@ -42,9 +49,9 @@ def _coords(D, n, lo, hi, lo2, hi2, lv):
     return [lo + 0.5 * (lo2 + 0.5 * np.arange(2 * (hi2 - lo2) + 1))] * D
 
 
-def _nested(lat, model, kind, n, lo, hi, lo2, hi2):
+def _nested(lat, model, kind, n, lo, hi, lo2, hi2, sigma=0.995):
     D = 2 if lat == O.D2Q9 else 3
-    g = O.Nested(lat, model, (n,) * D, (lo,) * D, (hi,) * D, (lo2,) * D, (hi2,) * D, tau_c=TAU)
+    g = O.Nested(lat, model, (n,) * D, (lo,) * D, (hi,) * D, (lo2,) * D, (hi2,) * D, tau_c=TAU, sigma=sigma)
     for lv in (0, 1, 2):
         g.set_state(lv, *fields_at(kind, _mesh(_coords(D, n, lo, hi, lo2, hi2, lv), D), n, D))
     return g
@@ -53,7 +60,7 @@ def _nested(lat, model, kind, n, lo, hi, lo2, hi2):
 SIZES = {O.D2Q9: (32, 8, 24, 8, 24), O.D3Q19: (16, 4, 12, 4, 12)}
 
 
-@pytest.mark.parametrize("model", [O.BGK, O.RR])
+@pytest.mark.parametrize("model", [O.BGK, O.RR, O.HRR])
 @pytest.mark.parametrize("lat", [O.D2Q9, O.D3Q19])
 def test_uniform_flow_stays_uniform(lat, model):
     D = 2 if lat == O.D2Q9 else 3
@@ -82,6 +89,42 @@ def test_interface_relations_at_both_interfaces(lat, model, kind):
                               2 * (hi - lo) + 1, lo2, hi2, 2 * TAU - 0.5, 1e-13, label=("levels 1-2", kind))
 
 
+def _hrr_relations(lat, kind, steps=3):
+    """H-RR, sigma = 0: the relations of both interfaces and of the collision
+    (see the module docstring).  Level-1 nodes the child covers or transfers
+    to are left out of the pair (0, 1)'s collision relation (level 2 decides
+    them), and the level-1 ring out of the pair (1, 2)'s (the pair (0, 1)
+    rebuilds it)."""
+    n, lo, hi, lo2, hi2 = SIZES[lat]
+    g = _nested(lat, O.HRR, kind, n, lo, hi, lo2, hi2, sigma=0.0)
+    g.step(steps)
+    c1, cc = g.class_map(1), g.child.class_map(0)
+    f01 = c1.copy()
+    f01[(cc == O.C_COVERED) | (cc == O.C_TNC)] = 99
+    check_interface_relations(g.get_populations(0), g.get_populations(1), f01, g.class_map(0), lat, O.HRR, n, lo,
+                              hi, TAU, 1e-13, label=("levels 0-1", kind))
+    c12 = cc.copy()
+    c12[np.isin(c1, [O.F_TFF, O.F_IE, O.F_IEFACE])] = 99
+    check_interface_relations(g.get_populations(1), g.get_populations(2), g.class_map(2), c12, lat, O.HRR,
+                              2 * (hi - lo) + 1, lo2, hi2, 2 * TAU - 0.5, 1e-13, label=("levels 1-2", kind))
+
+
+@pytest.mark.parametrize("kind", ["shear", "acoustic"])
+@pytest.mark.parametrize("lat", [O.D2Q9, O.D3Q19])
+def test_hrr_relations_at_both_interfaces(lat, kind):
+    _hrr_relations(lat, kind)
+
+
+@pytest.mark.parametrize("lat", [O.D2Q9, O.D3Q19])
+def test_hrr_child_without_ring_velocities_is_caught(lat):
+    O.set_mutation("nest_inj")
+    try:
+        with pytest.raises(AssertionError):
+            _hrr_relations(lat, "shear")
+    finally:
+        O.set_mutation(None)
+
+
 def _bound(model, kind, steps=40):
     lat, D = O.D2Q9, 2
     n, lo, hi, lo2, hi2 = SIZES[lat]
@@ -108,7 +151,7 @@ def _bound(model, kind, steps=40):
 
 
 @pytest.mark.parametrize("kind", ["shear", "acoustic"])
-@pytest.mark.parametrize("model", [O.BGK, O.RR])
+@pytest.mark.parametrize("model", [O.BGK, O.RR, O.HRR])
 def test_three_levels_within_the_refinement_difference(model, kind):
     e, eref = _bound(model, kind)
     assert e <= eref, (e, eref)
