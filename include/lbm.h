@@ -185,8 +185,10 @@ int lbm_sensors(lbm_handle h, int level, double threshold, uint8_t* flags, doubl
  * lbm_get_index_maps (level 1 has the classes of its own ring and TN nodes).
  * In lbm_get_macros covered nodes take the co-located node of the next
  * level; a level-1 node under level 2 holds no evolved value itself, so the
- * level-0 nodes above it are unspecified.  BGK and RR only (LBM_EUNSUPPORTED for H-RR); totals,
- * tuning, variants, sensors, probes and dynamic sigma return
+ * level-0 nodes above it are unspecified.  BGK, RR and H-RR (with H-RR the
+ * pair (1, 2) takes the level-1 ring's rho and u at its own time, t+1/2 and
+ * t+1, for the centred differences of eq stressT next to that ring).
+ * Totals, tuning, variants, sensors, probes and dynamic sigma return
  * LBM_EUNSUPPORTED on a nested grid.  Errors as lbm_create_grid. */
 int lbm_create_nested(const lbm_grid_desc* d, const int32_t lo2[3], const int32_t hi2[3], lbm_handle* out);
 

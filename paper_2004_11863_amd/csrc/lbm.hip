@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -182,6 +183,15 @@ struct GridBase {
   // this grid's fine substeps.  Levels 1 and 2 of the nested grid are the
   // child's levels 0 and 1.
   std::unique_ptr<GridBase> child;
+  // Set on the child of a nested grid.  Its coarse level is the parent's
+  // fine level, whose ring the parent rebuilds: with H-RR the parent writes
+  // the ring's rho and u at the child's time into the child's coarse
+  // velocity planes (coarse_vel_hook, run right after the child's coarse
+  // velocity pass), so that the child's centred differences next to the
+  // ring take them; the child's coarse level never takes the one-pass form,
+  // which computes every velocity itself.
+  bool nested_child = false;
+  std::function<void(hipStream_t)> coarse_vel_hook;
   virtual ~GridBase() {
     for (auto& e : events) {
       (void)hipEventDestroy(e.first);
@@ -208,6 +218,8 @@ struct GridBase {
   virtual int64_t probe_read(double* out, int64_t max) = 0;
   virtual void* coarse_buffer(int i) const = 0;
   virtual size_t coarse_bytes() const = 0;
+  virtual void* coarse_mac() const = 0;
+  virtual size_t coarse_mac_bytes() const = 0;
   int64_t nodes(int level) const {
     if (child && level >= 1) return child->nodes(level - 1);
     return level == 0 ? g.Nc : g.Nf;
@@ -310,7 +322,9 @@ struct Grid final : GridBase {
       zalloc(xbuf, sizeof(S) * (size_t)xband_elems(g, Q));
     if (desc.collision == LBM_HRR) {
       zalloc(mac_c, plane_bytes(g.Ncp, 1 + D));
-      if (g.has_fine) zalloc(mac_f, plane_bytes(g.Nfp, 1 + D));
+      // a nested grid's fine velocity planes are the child's coarse ones
+      if (child) mac_f.view(child->coarse_mac(), child->coarse_mac_bytes());
+      else if (g.has_fine) zalloc(mac_f, plane_bytes(g.Nfp, 1 + D));
     }
     tau_c = desc.tau_coarse;
     tau_f = 2.0 * tau_c - 0.5;
@@ -362,6 +376,8 @@ struct Grid final : GridBase {
 
   void* coarse_buffer(int i) const override { return cbuf[i].p; }
   size_t coarse_bytes() const override { return cbuf[0].bytes; }
+  void* coarse_mac() const override { return mac_c.p; }
+  size_t coarse_mac_bytes() const override { return mac_c.bytes; }
   void no_nesting(const char* what) const {
     if (child) throw LbmError(LBM_EUNSUPPORTED, std::string(what) + " is not available for a nested grid");
   }
@@ -402,7 +418,9 @@ struct Grid final : GridBase {
   }
   // The coarse level in one pass (D2Q9 H-RR, rows a whole number of vectors:
   // coarse_one_pass()); same tile variants, role 2.
-  bool coarse_one_pass() const { return D == 2 && desc.collision == LBM_HRR && g.n[0] % V == 0 && !dyn_on; }
+  bool coarse_one_pass() const {
+    return D == 2 && desc.collision == LBM_HRR && g.n[0] % V == 0 && !dyn_on && !nested_child;
+  }
   // D2Q9 H-RR fine substeps in one pass (k_hrr2)
   bool fine_one_pass2() const { return D == 2 && !dyn_on; }
   template <int HXV, int HYR>
@@ -777,6 +795,7 @@ struct Grid final : GridBase {
       // pull-stream + collide with the strain rate of those velocities
       const bool one_c = coarse_one_pass();
       if (!one_c) launch_stream<M_HRR, 0>(csrc, cdst, mc, tau_c, s);
+      if (coarse_vel_hook) coarse_vel_hook(s);  // nested child: the parent's ring rho, u
       if (fine_one_pass2()) {
         // one pass per fine substep (k_hrr2): ring rho, u first
         hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, c0, c1, c2, mf, g, itf);
@@ -871,6 +890,68 @@ struct Grid final : GridBase {
     ring_partial = true;
   }
 
+  // One coarse step of a nested grid with H-RR: as step_nested, with the
+  // H-RR phases of the two-level step around the child's steps -- the
+  // coarse velocity pass first; before each child step the ring's rho, u at
+  // the child's time (t+1/2, then t+1) for the child's coarse collision
+  // (coarse_vel_hook); after the first, the fictitious propagation onto
+  // TN^f (u(TN^c, t+1)), the strain rate at the history nodes and the t+1/2
+  // ring; at the end the coarse collision, the t+1 ring and the transfer.
+  void step_nested_hrr(hipStream_t s) {
+    S* csrc = cbuf[cpar].as<S>();
+    S* cdst = cbuf[cpar ^ 1].as<S>();
+    S* fA = fineA();
+    S* fB = fineB();
+    S* mc = mac_c.as<S>();
+    S* mf = mac_f.as<S>();  // the child's coarse velocity planes
+    double* Hm = hist[hs[0]].as<double>();
+    double* H0 = hist[hs[1]].as<double>();
+    double* Hp = hist[hs[2]].as<double>();
+    const int64_t NH = itf.NH;
+    const double kf = tau_f / (2.0 * tau_c), kc = 2.0 * tau_c / tau_f;
+    const double omf = 1.0 - 1.0 / tau_f, omc = 1.0 - 1.0 / tau_c;
+    const double c0 = -1.0 / 8.0, c1 = 3.0 / 4.0, c2 = 3.0 / 8.0;  // eq TempInt at t+1/2
+    constexpr int IB = kIfaceBlock;
+    constexpr int PER = 256 / (D == 2 ? 9 : 27);
+    const unsigned bh = xblocks(NH, IB), br = xblocks(itf.NR, IB), bt = xblocks(itf.NT, IB);
+    const unsigned bc = xblocks(itf.NT, PER), br2 = xblocks(itf.NR, 256);
+    const Geo gg = g;
+    const Iface it = itf;
+    hipLaunchKernelGGL((k_hist_capture<LAT, DEV, S, M_HRR>), dim3(bh), dim3(IB), 0, s, csrc, Hp, g, itf, nullptr, Hm,
+                       H0);
+    const bool one_c = coarse_one_pass();
+    if (!one_c) launch_stream<M_HRR, 0>(csrc, cdst, mc, tau_c, s);
+    child->coarse_vel_hook = [=](hipStream_t st) {
+      hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, st, Hm, H0, Hp, c0, c1, c2, mf, gg, it);
+    };
+    child->step(1, s);
+    hipLaunchKernelGGL((k_fict<LAT, DEV, S, S>), dim3(bt), dim3(IB), 0, s, fB, mc, g, itf);
+    if (one_c)
+      hipLaunchKernelGGL((k_hist_strain_time<LAT, DEV, S, true>), dim3(bh), dim3(IB), 0, s, csrc, mc, Hm, H0, Hp,
+                         G.as<double>(), g, itf);
+    else
+      hipLaunchKernelGGL((k_hist_strain_time<LAT, DEV, S, false>), dim3(bh), dim3(IB), 0, s, csrc, mc, Hm, H0, Hp,
+                         G.as<double>(), g, itf);
+    hipLaunchKernelGGL((k_ring<LAT, DEV, S, M_HRR, true>), dim3(br), dim3(IB), 0, s, G.as<double>(), fB, g, itf, kf,
+                       omf, tau_f, sig);
+    child->coarse_vel_hook = [=](hipStream_t st) {
+      hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, st, Hm, H0, Hp, 0.0, 0.0, 1.0, mf, gg, it);
+    };
+    child->step(1, s);
+    child->coarse_vel_hook = nullptr;
+    if (one_c) launch_hrr2c(csrc, cdst, mc, s);
+    else launch_collide_hrr<0>(csrc, cdst, mc, tau_c, s, -1, true);
+    hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, M_HRR>), dim3(br2 + bc), dim3(256), 0, s, Hp, fA, fB, cdst, g,
+                       itf, kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, (const S*)nullptr);
+    HIPCHK(hipGetLastError());
+    cpar ^= 1;
+    const int old = hs[0];
+    hs[0] = hs[1];
+    hs[1] = hs[2];
+    hs[2] = old;
+    ring_partial = true;
+  }
+
   // Completes the ring of fine A: rebuilds every population of the ring
   // nodes from the history level the last step's synchronous ring used (now
   // the middle level), which reproduces bitwise the populations stored then.
@@ -894,7 +975,8 @@ struct Grid final : GridBase {
     if (child) {
       for (int k = 0; k < n; ++k) {
         if (desc.collision == LBM_BGK) step_nested<M_BGK>(s);
-        else step_nested<M_RR>(s);
+        else if (desc.collision == LBM_RR) step_nested<M_RR>(s);
+        else step_nested_hrr(s);
       }
       HIPCHK(hipGetLastError());
       return;
@@ -1979,7 +2061,6 @@ int lbm_create_nested(const lbm_grid_desc* d, const int32_t lo2[3], const int32_
   try {
     Geo geo = validate(*d);
     if (!geo.has_fine) throw LbmError(LBM_EINVAL, "a nested grid needs the level-1 patch");
-    if (d->collision == LBM_HRR) throw LbmError(LBM_EUNSUPPORTED, "nested grids take BGK or RR");
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
     if (d->device < 0 || d->device >= ndev) throw LbmError(LBM_EINVAL, "no such HIP device");
@@ -1999,6 +2080,7 @@ int lbm_create_nested(const lbm_grid_desc* d, const int32_t lo2[3], const int32_
     child->device = d->device;
     HIPCHK(hipSetDevice(d->device));
     HIPCHK(hipStreamCreateWithFlags(&child->stream, hipStreamNonBlocking));
+    child->nested_child = true;
     build_tables(gc, child->tabs);
     child->init();
     // level 1 is stored in the child's coarse layout

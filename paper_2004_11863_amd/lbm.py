@@ -192,7 +192,7 @@ def make_desc_(lattice, collision, precision, n, lo, hi, tau_coarse, sigma, devi
 
 def lbm_create_nested(lattice, collision, precision, n, lo, hi, lo2, hi2, tau_coarse=0.51, sigma=0.995, device=0):
     """Three nested levels: the patch [lo, hi] of coarse vertices carries the
-    patch [lo2, hi2] of its own vertices (BGK, RR)."""
+    patch [lo2, hi2] of its own vertices (BGK, RR, H-RR)."""
     d = make_desc_(lattice, collision, precision, n, lo, hi, tau_coarse, sigma, device)
     D = 2 if lattice == LBM_D2Q9 else 3
     l2 = (ctypes.c_int32 * 3)(*[int(x) for x in (list(lo2)[:D] + [0] * (3 - D))])
@@ -544,7 +544,7 @@ class Batch:
 class Nested(Grid):
     """Three nested levels (levels 0, 1, 2) over one handle: the coarse
     periodic grid, its patch [lo, hi], and the patch [lo2, hi2] of level-1
-    vertices.  BGK and RR."""
+    vertices.  BGK, RR and H-RR."""
 
     def __init__(self, lattice, collision, precision, n, lo, hi, lo2, hi2, tau_coarse=0.51, sigma=0.995, device=0):
         self.h = lbm_create_nested(lattice, collision, precision, n, lo, hi, lo2, hi2, tau_coarse, sigma, device)

@@ -1,8 +1,11 @@
 """Three nested levels on the GPU (lbm_create_nested) against the oracle's
 nested grid: the two-level step applied to each pair, every substep of level
-1 a whole step of the pair (1, 2).  FP64 within 1e-12 relative on rho, u and
-the populations of every evolved node of the three levels; FP32 deviation
-storage within the stated FP32 bars."""
+1 a whole step of the pair (1, 2), which with H-RR takes the level-1 ring's
+rho and u at its own time.  BGK, RR and H-RR (sigma 0.995 and 0), D2Q9 (the
+coarse level in the one-pass H-RR form, level 1 in the two-pass form) and
+D3Q19.  FP64 within 1e-12 relative on rho, u and the populations of every
+evolved node of the three levels; FP32 deviation storage within the stated
+FP32 bars."""
 import math
 
 import numpy as np
@@ -37,13 +40,14 @@ def _coords(D, n, lo, hi, lo2, hi2, lv):
 SIZES = {2: (40, 10, 30, 9, 31), 3: (18, 4, 14, 5, 15)}
 
 
-def _pair(D, model, prec, kind):
+def _pair(D, model, prec, kind, sigma=0.995):
     lbm = _lbm()
     lat, olat = (lbm.LBM_D2Q9, O.D2Q9) if D == 2 else (lbm.LBM_D3Q19, O.D3Q19)
-    mg, mo = {"BGK": (lbm.LBM_BGK, O.BGK), "RR": (lbm.LBM_RR, O.RR)}[model]
+    mg, mo = {"BGK": (lbm.LBM_BGK, O.BGK), "RR": (lbm.LBM_RR, O.RR), "HRR": (lbm.LBM_HRR, O.HRR)}[model]
     n, lo, hi, lo2, hi2 = SIZES[D]
-    gpu = lbm.Nested(lat, mg, prec, (n,) * D, (lo,) * D, (hi,) * D, (lo2,) * D, (hi2,) * D, tau_coarse=TAU)
-    ref = O.Nested(olat, mo, (n,) * D, (lo,) * D, (hi,) * D, (lo2,) * D, (hi2,) * D, tau_c=TAU)
+    gpu = lbm.Nested(lat, mg, prec, (n,) * D, (lo,) * D, (hi,) * D, (lo2,) * D, (hi2,) * D, tau_coarse=TAU,
+                     sigma=sigma)
+    ref = O.Nested(olat, mo, (n,) * D, (lo,) * D, (hi,) * D, (lo2,) * D, (hi2,) * D, tau_c=TAU, sigma=sigma)
     for lv in (0, 1, 2):
         rho, u = fields_at(kind, _mesh(_coords(D, n, lo, hi, lo2, hi2, lv), D), n, D)
         gpu.set_state(lv, rho, u)
@@ -63,11 +67,12 @@ def _rel(a, b):
 
 
 @pytest.mark.parametrize("kind", ["shear", "acoustic"])
-@pytest.mark.parametrize("model", ["BGK", "RR"])
+@pytest.mark.parametrize("model", ["BGK", "RR", "HRR", "HRR0"])
 @pytest.mark.parametrize("D", [2, 3])
 def test_nested_fp64_matches_oracle(D, model, kind):
     lbm = _lbm()
-    gpu, ref = _pair(D, model, lbm.LBM_FP64, kind)
+    sigma = 0.0 if model == "HRR0" else 0.995
+    gpu, ref = _pair(D, model[:3] if model.startswith("HRR") else model, lbm.LBM_FP64, kind, sigma)
     steps = 6 if D == 3 else 10
     gpu.step(steps)
     ref.step(steps)
@@ -85,11 +90,13 @@ def test_nested_fp64_matches_oracle(D, model, kind):
     assert max(worst.values()) <= 1e-12, worst
 
 
-def test_nested_fp32_within_bars():
+@pytest.mark.parametrize("D,model", [(2, "RR"), (2, "HRR"), (3, "HRR")])
+def test_nested_fp32_within_bars(D, model):
     lbm = _lbm()
-    gpu, ref = _pair(2, "RR", lbm.LBM_FP32_DEV, "acoustic")
-    gpu.step(40)
-    ref.step(40)
+    gpu, ref = _pair(D, model, lbm.LBM_FP32_DEV, "acoustic")
+    steps = 40 if D == 2 else 12
+    gpu.step(steps)
+    ref.step(steps)
     ev = _evolved(ref)
     for lv in (0, 1, 2):
         m = ev[lv]
@@ -113,7 +120,5 @@ def test_nested_levels_and_refusals():
         with pytest.raises(lbm.LbmError):
             call()
     g.close()
-    with pytest.raises(lbm.LbmError):  # H-RR is not nested
-        lbm.Nested(lbm.LBM_D2Q9, lbm.LBM_HRR, lbm.LBM_FP64, (n, n), (lo, lo), (hi, hi), (lo2, lo2), (hi2, hi2))
     with pytest.raises(lbm.LbmError):  # level-2 patch too close to the level-1 ring
         lbm.Nested(lbm.LBM_D2Q9, lbm.LBM_RR, lbm.LBM_FP64, (n, n), (lo, lo), (hi, hi), (1, 1), (hi2, hi2))
