@@ -127,10 +127,10 @@ def roofline_of(kt, Q, pb, geom):
 def workload(name, seed=0):
     from paper_2004_11863_amd import inputs as I
     if name == "d2q9-4096":
-        return I.config2(seed=seed, n=4096)
+        return I.vortex_pulse_4096(seed=seed, n=4096)
     if name == "d2q9-1024":
-        return I.config2(seed=seed, n=1024)
-    return I.config3(seed=seed, n=384)
+        return I.vortex_pulse_4096(seed=seed, n=1024)
+    return I.pulse_cube_384(seed=seed, n=384)
 
 
 def make_gpu(wl, collision, precision, tau_coarse=0.51):
@@ -194,7 +194,7 @@ def cpu_sample(name, seed=0):
     subcase (same configuration at 64^3), or the D2Q9 grid itself."""
     from paper_2004_11863_amd import inputs as I
     if name == "d3q19-384":
-        return I.config3(seed=seed, n=64), "D3Q19 64^3 subcase of the same configuration (patch [16, 48]^3)"
+        return I.pulse_cube_384(seed=seed, n=64), "D3Q19 64^3 subcase of the same configuration (patch [16, 48]^3)"
     return workload(name, seed), "the same grid"
 
 

@@ -173,9 +173,9 @@ def uniform_flow(geom: Geometry, U=(0.1 * CS, 0.0, 0.0), rho0: float = 1.0) -> W
 
 
 # --------------------------------------------------------------------------
-# The five benchmark configurations (sizes as stated for this hot path).
+# The benchmark workloads (sizes as stated for this hot path).
 
-def config1(seed: int = 0) -> Workload:
+def vortex_crossing_64(seed: int = 0) -> Workload:
     """D2Q9 periodic 64^2, patch [16,48]^2 (64^2 fine cells), vortex crossing
     the x = 48 edge from fine to coarse."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -187,7 +187,7 @@ def config1(seed: int = 0) -> Workload:
     return Workload(geom=geom, U=(U, 0.0, 0.0), vortices=[v])
 
 
-def config2(seed: int = 0, n: int = 4096) -> Workload:
+def vortex_pulse_4096(seed: int = 0, n: int = 4096) -> Workload:
     """D2Q9 periodic 4096^2, fine band 4096 x 2048 fine cells (patch
     [n/4, 3n/4] x [3n/8, 5n/8]), vortex near the right patch edge plus a
     Gaussian pulse (A = 1e-3) within 200 coarse cells of the interface."""
@@ -204,7 +204,7 @@ def config2(seed: int = 0, n: int = 4096) -> Workload:
     return Workload(geom=geom, U=(U, 0.0, 0.0), vortices=[v], pulses=[Pulse(center=pc, A=1e-3)])
 
 
-def config3(seed: int = 0, n: int = 384) -> Workload:
+def pulse_cube_384(seed: int = 0, n: int = 384) -> Workload:
     """D3Q19 periodic n^3, centred fine cube of n^3 fine cells (patch
     [n/4, 3n/4]^3), Gaussian pulse (A = 1e-3) near the interface plus a
     uniform flow at Mach 0.1 along x."""

@@ -127,7 +127,7 @@ def sweep(path: str = FILE, reps: int = 5, log=print):
     from . import inputs as I
     from . import lbm
     cache = TuneCache(path)
-    for wl in (I.config2(n=4096), I.config3(n=384)):
+    for wl in (I.vortex_pulse_4096(n=4096), I.pulse_cube_384(n=384)):
         g = wl.geom
         D = g.D
         lat = lbm.LBM_D2Q9 if D == 2 else lbm.LBM_D3Q19

@@ -32,7 +32,7 @@ def _lbm():
 
 
 def _vortex_and_pulse():
-    wl = I.config1(1)
+    wl = I.vortex_crossing_64(1)
     wl.pulses = [I.Pulse(center=(40.0, 30.0), A=1e-2)]
     return wl
 
@@ -146,12 +146,12 @@ def test_spurious_ac_mode_switches_everywhere():
 
 def test_dynamic_sigma_rejects_bad_arguments():
     lbm = _lbm()
-    rr, _, _ = make_pair(I.config1(0), "RR", lbm.LBM_FP64, with_oracle=False)
+    rr, _, _ = make_pair(I.vortex_crossing_64(0), "RR", lbm.LBM_FP64, with_oracle=False)
     with pytest.raises(lbm.LbmError):
         rr.set_dynamic_sigma(True, 0.0, 0.0)
     rr.set_dynamic_sigma(False)  # switching off is always allowed
     rr.close()
-    h, _, _ = make_pair(I.config1(0), "HRR", lbm.LBM_FP64, with_oracle=False)
+    h, _, _ = make_pair(I.vortex_crossing_64(0), "HRR", lbm.LBM_FP64, with_oracle=False)
     for sd, thr in ((1.5, 0.0), (-0.1, 0.0), (0.0, -1.0), (0.0, float("inf")), (0.0, float("nan"))):
         with pytest.raises(lbm.LbmError):
             h.set_dynamic_sigma(True, sd, thr)

@@ -27,9 +27,9 @@ def _check(out):
 
 
 @pytest.mark.parametrize("model", ["BGK", "RR", "HRR"])
-def test_fp32_config1(model):
+def test_fp32_vortex_crossing_64(model):
     lbm = _lbm()
-    gpu, ref, levels = make_pair(I.config1(0), model, lbm.LBM_FP32_DEV)
+    gpu, ref, levels = make_pair(I.vortex_crossing_64(0), model, lbm.LBM_FP32_DEV)
     gpu.step(200)
     ref.step(200)
     out = compare_fp32(gpu, ref, levels)
@@ -39,11 +39,11 @@ def test_fp32_config1(model):
 
 
 @pytest.mark.parametrize("model", ["RR", "HRR"])
-def test_fp32_config2_at_512(model):
+def test_fp32_vortex_pulse_at_512(model):
     """Config 2's workload at 512^2 over its full 1000 coarse steps: the FP32
     error does not grow past the bar over a whole run."""
     lbm = _lbm()
-    gpu, ref, levels = make_pair(I.config2(seed=1, n=512), model, lbm.LBM_FP32_DEV)
+    gpu, ref, levels = make_pair(I.vortex_pulse_4096(seed=1, n=512), model, lbm.LBM_FP32_DEV)
     gpu.step(1000)
     ref.step(1000)
     out = compare_fp32(gpu, ref, levels)
@@ -53,10 +53,10 @@ def test_fp32_config2_at_512(model):
 
 
 @pytest.mark.parametrize("model", ["RR", "HRR"])
-def test_fp32_config3_64cube_subcase(model):
+def test_fp32_pulse_cube_64_subcase(model):
     """Config 3's 64^3 error subcase over its full 500 coarse steps."""
     lbm = _lbm()
-    gpu, ref, levels = make_pair(I.config3(seed=2, n=64), model, lbm.LBM_FP32_DEV)
+    gpu, ref, levels = make_pair(I.pulse_cube_384(seed=2, n=64), model, lbm.LBM_FP32_DEV)
     gpu.step(500)
     ref.step(500)
     out = compare_fp32(gpu, ref, levels)
@@ -65,10 +65,10 @@ def test_fp32_config3_64cube_subcase(model):
     _check(out)
 
 
-def test_full_size_config2_fp32_and_fp64():
+def test_full_size_vortex_pulse_4096_fp32_and_fp64():
     """The 4096^2 benchmark grid itself, two coarse steps, against the oracle."""
     lbm = _lbm()
-    wl = I.config2(seed=0, n=4096)
+    wl = I.vortex_pulse_4096(seed=0, n=4096)
     gpu, ref, levels = make_pair(wl, "RR", lbm.LBM_FP32_DEV)
     g64, _, _ = make_pair(wl, "RR", lbm.LBM_FP64, with_oracle=False)
     gpu.step(2)
@@ -88,7 +88,7 @@ def test_full_size_config2_fp32_and_fp64():
     assert worst <= 1e-12
 
 
-def test_full_size_config3_fp32_one_step():
+def test_full_size_pulse_cube_384_fp32_one_step():
     """The 384^3 benchmark grid itself, one coarse step, against the oracle."""
     import os
     try:
@@ -98,7 +98,7 @@ def test_full_size_config3_fp32_one_step():
     if mem < 96 * 2 ** 30:
         pytest.skip("needs about 60 GiB of host memory for the oracle")
     lbm = _lbm()
-    wl = I.config3(seed=0, n=384)
+    wl = I.pulse_cube_384(seed=0, n=384)
     gpu, ref, levels = make_pair(wl, "RR", lbm.LBM_FP32_DEV)
     gpu.step(1)
     ref.step(1)
@@ -108,11 +108,11 @@ def test_full_size_config3_fp32_one_step():
     _check(out)
 
 
-def test_full_size_config2_hrr_fp32_tuned():
+def test_full_size_vortex_pulse_4096_hrr_fp32_tuned():
     """The 4096^2 grid with H-RR (one-pass tiled kernels on both levels) in
     the autotuner's variants, two coarse steps, against the oracle."""
     lbm = _lbm()
-    wl = I.config2(seed=0, n=4096)
+    wl = I.vortex_pulse_4096(seed=0, n=4096)
     gpu, ref, levels = make_pair(wl, "HRR", lbm.LBM_FP32_DEV)
     v = gpu.tune(reps=1)
     gpu.step(2)
@@ -123,7 +123,7 @@ def test_full_size_config2_hrr_fp32_tuned():
     _check(out)
 
 
-def test_full_size_config3_hrr_fp32_one_step_tuned():
+def test_full_size_pulse_cube_384_hrr_fp32_one_step_tuned():
     """The 384^3 grid with H-RR, one coarse step, against the oracle: the
     autotuner's bulk variants with the fine H-RR substep forced to the
     one-pass marching kernel (the two-pass default is covered elsewhere)."""
@@ -135,7 +135,7 @@ def test_full_size_config3_hrr_fp32_one_step_tuned():
     if mem < 96 * 2 ** 30:
         pytest.skip("needs about 60 GiB of host memory for the oracle")
     lbm = _lbm()
-    wl = I.config3(seed=0, n=384)
+    wl = I.pulse_cube_384(seed=0, n=384)
     gpu, ref, levels = make_pair(wl, "HRR", lbm.LBM_FP32_DEV)
     v = gpu.tune(reps=1)
     v[3] = 2

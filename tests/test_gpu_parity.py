@@ -55,9 +55,9 @@ def test_index_maps_and_tables_bit_exact(D, n, lo, hi):
 
 @pytest.mark.parametrize("model", ["BGK", "RR", "HRR"])
 @pytest.mark.parametrize("seed", [0, 1])
-def test_fp64_d2q9_config1(model, seed):
+def test_fp64_d2q9_vortex_crossing_64(model, seed):
     lbm = _lbm()
-    wl = I.config1(seed)
+    wl = I.vortex_crossing_64(seed)
     gpu, ref, levels = make_pair(wl, model, lbm.LBM_FP64)
     steps = 200 if seed == 0 else 60
     gpu.step(steps)
@@ -114,7 +114,7 @@ def test_fp64_d3q19_two_level_small(model):
 @pytest.mark.parametrize("model", ["RR", "HRR"])
 def test_fp64_d3q19_64cube_subcase(model):
     lbm = _lbm()
-    wl = I.config3(seed=0, n=64)
+    wl = I.pulse_cube_384(seed=0, n=64)
     gpu, ref, levels = make_pair(wl, model, lbm.LBM_FP64, tau_c=0.51)
     gpu.step(6)
     ref.step(6)
@@ -148,7 +148,7 @@ def test_fp64_hrr_sigma_range(sigma):
     """H-RR across the weight of eq a1ij_HRR: sigma = 0 (stress from finite
     differences only) and an intermediate value."""
     lbm = _lbm()
-    wl = I.config1(5)
+    wl = I.vortex_crossing_64(5)
     gpu, ref, levels = make_pair(wl, "HRR", lbm.LBM_FP64, sigma=sigma)
     gpu.step(40)
     ref.step(40)
@@ -165,7 +165,7 @@ def test_hrr_with_sigma_one_is_rr(prec):
     RR path."""
     lbm = _lbm()
     p = lbm.LBM_FP32_DEV if prec == "fp32" else lbm.LBM_FP64
-    wl = I.config1(6)
+    wl = I.vortex_crossing_64(6)
     a, _, _ = make_pair(wl, "HRR", p, sigma=1.0, with_oracle=False)
     b, _, _ = make_pair(wl, "RR", p, sigma=1.0, with_oracle=False)
     a.step(30)
@@ -184,7 +184,7 @@ def test_hrr_with_sigma_one_is_rr(prec):
 def test_fp64_tau_near_one_half():
     """Very low viscosity (tau_c = 0.5005, tau_f = 0.501) over a few steps."""
     lbm = _lbm()
-    wl = I.config1(7)
+    wl = I.vortex_crossing_64(7)
     for model in ("RR", "HRR"):
         gpu, ref, levels = make_pair(wl, model, lbm.LBM_FP64, tau_c=0.5005)
         gpu.step(25)
@@ -196,7 +196,7 @@ def test_fp64_tau_near_one_half():
 
 def test_totals_match_oracle():
     lbm = _lbm()
-    wl = I.config1(2)
+    wl = I.vortex_crossing_64(2)
     gpu, ref, levels = make_pair(wl, "RR", lbm.LBM_FP64)
     gpu.step(30)
     ref.step(30)
@@ -209,7 +209,7 @@ def test_totals_match_oracle():
 
 def test_zero_steps_and_determinism():
     lbm = _lbm()
-    wl = I.config1(3)
+    wl = I.vortex_crossing_64(3)
     outs = []
     for _ in range(2):
         gpu, _, levels = make_pair(wl, "HRR", lbm.LBM_FP32_DEV, with_oracle=False)
@@ -271,7 +271,7 @@ def test_every_kernel_variant_gives_identical_results(prec, model):
     lbm = _lbm()
     p = lbm.LBM_FP32_DEV if prec == "fp32" else lbm.LBM_FP64
     nvar = lbm.LBM_N_VARIANTS
-    wl = I.config1(4)
+    wl = I.vortex_crossing_64(4)
     ref = None
     live = None
     for v in range(nvar):
@@ -397,7 +397,7 @@ def test_full_size_one_pass_variants_bitwise(model, role):
     and storage windows at the real size)."""
     import torch
     lbm = _lbm()
-    wl = I.config3(seed=0, n=384)
+    wl = I.pulse_cube_384(seed=0, n=384)
     mcode = {"RR": lbm.LBM_RR, "HRR": lbm.LBM_HRR}[model]
 
     def run(v):

@@ -77,10 +77,10 @@ def _compare(gpu, ref, level, thr, band=None):
 
 @pytest.mark.parametrize("prec,band", [("fp64", 1e-9), ("fp32", None)])
 @pytest.mark.parametrize("model", ["BGK", "RR", "HRR"])
-def test_sensors_d2q9_config1(model, prec, band):
+def test_sensors_d2q9_vortex_crossing_64(model, prec, band):
     lbm = _lbm()
     p = lbm.LBM_FP64 if prec == "fp64" else lbm.LBM_FP32_DEV
-    wl = I.config1(1)
+    wl = I.vortex_crossing_64(1)
     wl.pulses = [I.Pulse(center=(40.0, 30.0), A=1e-2)]  # acoustic content: a divergence to sense
     gpu, ref, levels = make_pair(wl, model, p)
     lbm.lbm_sensors_enable(gpu.h, True)
@@ -138,7 +138,7 @@ def test_sensors_flag_spurious_ac_mode_everywhere():
 
 def test_sensors_need_a_recorded_step():
     lbm = _lbm()
-    gpu, _, _ = make_pair(I.config1(0), "RR", lbm.LBM_FP64, with_oracle=False)
+    gpu, _, _ = make_pair(I.vortex_crossing_64(0), "RR", lbm.LBM_FP64, with_oracle=False)
     lbm.lbm_sensors_enable(gpu.h, True)
     with pytest.raises(lbm.LbmError):
         gpu.sensors(0, 1e-8)
@@ -153,7 +153,7 @@ def test_sensors_need_a_recorded_step():
 @pytest.mark.parametrize("level,node", [(0, (50, 33, 0)), (1, (20, 31, 0))])
 def test_probe_series_matches_oracle(level, node):
     lbm = _lbm()
-    gpu, ref, _ = make_pair(I.config1(2), "RR", lbm.LBM_FP64)
+    gpu, ref, _ = make_pair(I.vortex_crossing_64(2), "RR", lbm.LBM_FP64)
     lbm.lbm_probe_enable(gpu.h, level, node, 64)
     steps = 40
     gpu.step(steps)

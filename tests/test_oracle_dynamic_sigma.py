@@ -45,7 +45,7 @@ def _grid(wl, lat=O.D2Q9, sigma=0.995, tau=0.51):
 
 
 def _vortex_and_pulse():
-    wl = I.config1(1)
+    wl = I.vortex_crossing_64(1)
     wl.pulses = [I.Pulse(center=(40.0, 30.0), A=1e-2)]
     return wl
 
@@ -68,7 +68,7 @@ def test_sigma_dyn_equal_to_sigma_is_the_static_scheme():
 
 
 def test_dynamic_sigma_needs_hrr_and_a_valid_sigma():
-    wl = I.config1(0)
+    wl = I.vortex_crossing_64(0)
     g = wl.geom
     r = O.Grid(O.D2Q9, O.RR, g.n[:2], g.lo[:2], g.hi[:2], tau_c=0.51, sigma=0.995)
     with pytest.raises(ValueError):

@@ -150,7 +150,7 @@ def test_ghost_sensor():
 
 def test_two_level_sensors_leave_interface_nodes_unflagged():
     from paper_2004_11863_amd import inputs as I
-    wl = I.config1(0)
+    wl = I.vortex_crossing_64(0)
     g0 = wl.geom
     g = O.Grid(O.D2Q9, O.HRR, g0.n[:2], g0.lo[:2], g0.hi[:2], tau_c=0.51)
     for lv in (0, 1):

@@ -71,7 +71,7 @@ def test_committed_file_is_well_formed():
 
 def _grid(fp32):
     from paper_2004_11863_amd import inputs as I
-    wl = I.scaled(I.config3, 48, seed=2)
+    wl = I.scaled(I.pulse_cube_384, 48, seed=2)
     g = wl.geom
     gr = lbm.Grid(lbm.LBM_D3Q19, lbm.LBM_RR, lbm.LBM_FP32_DEV if fp32 else lbm.LBM_FP64, g.n[:3], g.lo[:3], g.hi[:3])
     for lv in (0, 1):

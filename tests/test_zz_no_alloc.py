@@ -35,7 +35,7 @@ def _check(gpu, ref, steps):
 def test_noalloc_totals_two_calls_then_smaller():
     from paper_2004_11863_amd import lbm
     # first call: D3Q19 two-level, FP32 deviation storage (both levels near 2^18 nodes)
-    wl = I.config3(seed=0, n=64)
+    wl = I.pulse_cube_384(seed=0, n=64)
     print("noalloc: D3Q19 64^3 RR FP32", flush=True)
     gpu, ref, _ = make_pair(wl, "RR", lbm.LBM_FP32_DEV)
     gpu.step(0)
@@ -50,7 +50,7 @@ def test_noalloc_totals_two_calls_then_smaller():
     # second call: a smaller D2Q9 FP64 grid; the scratch still holds the
     # larger grid's partial sums, which must not leak into this one
     print("noalloc: D2Q9 64^2 H-RR FP64", flush=True)
-    gpu, ref, _ = make_pair(I.config1(seed=1), "HRR", lbm.LBM_FP64)
+    gpu, ref, _ = make_pair(I.vortex_crossing_64(seed=1), "HRR", lbm.LBM_FP64)
     _check(gpu, ref, 7)
     gpu.close()
 
