@@ -61,6 +61,8 @@ def parse():
     p.add_argument("--serve-reps", type=int, default=3, help="repeats of the small-grid trace (spread)")
     p.add_argument("--variants", default=None,
                    help="launch variants of the headline grid as r0,r1,r2,r3 instead of autotuning")
+    p.add_argument("--three-levels", action="store_true",
+                   help="only run the three-nested-levels case (D3Q19 256^3, RR and H-RR) and print its JSON")
     p.add_argument("--copy-probe", type=int, default=0,
                    help="only run a plain device copy of this many MiB (counter calibration)")
     return p.parse_args()
@@ -585,6 +587,9 @@ def main():
         return
     from paper_2004_11863_amd import lbm
     lbm.load()
+    if args.three_levels:
+        print(json.dumps({"three_levels_d3q19_256_fp32": three_levels()}), flush=True)
+        return
 
     copy_gbs = (d2d_copy_GBs(), lbm.lbm_copy_probe(2 << 30, 10))
     wl = workload(args.workload)
