@@ -264,7 +264,6 @@ static void collide_L(const lattice_t* L, int model, double tau, double sigma, c
     for (int b = 0; b < 3; ++b)
       for (int c = 0; c < 3; ++c) a3[a][b][c] = u[a] * a2[b][c] + u[b] * a2[a][c] + u[c] * a2[a][b];
   for (int i = 0; i < Q; ++i) {
-    const int* xi = L->xi[i];
     double t2 = 0.0, t3 = 0.0;
     for (int a = 0; a < D; ++a)
       for (int b = 0; b < D; ++b) t2 += L->H2[i][a][b] * a2[a][b];
