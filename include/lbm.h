@@ -204,8 +204,9 @@ int lbm_create_nested(const lbm_grid_desc* d, const int32_t lo2[3], const int32_
  * products of rounding noise from switching).  Switching on clears the
  * stored divergences and curls (no switch at a node's first collision).
  * Costs 4 values of the storage type per node and level of device memory
- * and runs the H-RR substeps in two passes (velocity pass, then pull +
- * collide).  LBM_EINVAL: not an H-RR grid, sigma_dyn outside [0, 1], or a
+ * (read and written by every bulk H-RR collision); D3Q19 runs its H-RR
+ * substeps in two passes (velocity pass, then pull + collide), D2Q9 keeps
+ * its one-pass kernels.  LBM_EINVAL: not an H-RR grid, sigma_dyn outside [0, 1], or a
  * negative or non-finite threshold.  Not available for batches. */
 int lbm_set_dynamic_sigma(lbm_handle h, int on, double sigma_dyn, double threshold);
 

@@ -1179,6 +1179,60 @@ __global__ __launch_bounds__(HXV * HYR, MINW) void k_fine2(const S* __restrict__
   fine2_tile<LAT, DEV, S, MODEL, NT, HXV, HYR>(src, dst, half, g, om, ntx, tile);
 }
 
+// The H-RR collision of one lane's vector in the D2Q9 one-pass kernels: the
+// strain rate by centred differences of the LDS velocity rows (ux, uy rows
+// rr - 1 .. rr + 1, the vector's columns c ..  c + V - 1), then the collision,
+// in place on v.  DYN: sigma per node as collide_hrr_body takes it -- the
+// node's previous divergence and curl from dyn ([4][np] in the storage
+// type, at position own), this collision's stored back -- with the same
+// arithmetic, so the one-pass and two-pass substeps agree bitwise.
+template <int LAT, bool DEV, typename S, bool DYN, int RW>
+__device__ __forceinline__ void dyn2_collide(typename VT<S, VecOf<S>::V>::a* v, const S (*ux)[RW], const S (*uy)[RW],
+                                             int rr, int c, const S om, const S tau, const S sig,
+                                             S* __restrict__ dyn, int64_t np, int64_t own, const S sig_dyn,
+                                             const S dthr) {
+  using L = Lattice<LAT>;
+  using N = Node<LAT, DEV, S>;
+  constexpr int V = VecOf<S>::V, Q = L::Q;
+  using VA = typename VT<S, V>::a;
+  VA pv[2], cv[2];
+  if constexpr (DYN) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) pv[k] = *(const VA*)(dyn + (int64_t)k * np + own);
+  }
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    // gr[a][b] = (u_b(x + e_a) - u_b(x - e_a)) / 2
+    const S g00 = (ux[rr][c + j + 1] - ux[rr][c + j - 1]) * S(0.5);
+    const S g01 = (uy[rr][c + j + 1] - uy[rr][c + j - 1]) * S(0.5);
+    const S g10 = (ux[rr + 1][c + j] - ux[rr - 1][c + j]) * S(0.5);
+    const S g11 = (uy[rr + 1][c + j] - uy[rr - 1][c + j]) * S(0.5);
+    Sym<S> Sr;
+    Sr.xx = g00;
+    Sr.yy = g11;
+    Sr.xy = S(0.5) * (g01 + g10);
+    Sr.zz = Sr.xz = Sr.yz = S(0);
+    S sg = sig;
+    if constexpr (DYN) {
+      cv[0][j] = g00 + g11;
+      cv[1][j] = g01 - g10;
+      const S pd = mul_rn(pv[0][j], cv[0][j]);
+      const S pc = mul_rn(pv[1][j], cv[1][j]);
+      if (pd < -dthr || pc < -dthr) sg = sig_dyn;
+    }
+    S f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = v[i][j];
+    N::collide(f, M_HRR, om, tau, sg, &Sr);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i][j] = f[i];
+  }
+  if constexpr (DYN) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) *(VA*)(dyn + (int64_t)k * np + own) = cv[k];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // One H-RR fine substep in one pass (D2Q9): a work group of HXV x HYR lanes,
 // one lane per vector of a tile and its one-vector / one-row halo.  Every
@@ -1189,9 +1243,11 @@ __global__ __launch_bounds__(HXV * HYR, MINW) void k_fine2(const S* __restrict__
 // their own pulled populations.  Same arithmetic as the velocity pass
 // followed by k_collide_hrr, without the velocity planes' round trip through
 // HBM and without pulling the populations twice.
-template <int LAT, bool DEV, typename S, bool NT, int HXV, int HYR>
+template <int LAT, bool DEV, typename S, bool NT, int HXV, int HYR, bool DYN = false>
 __device__ __forceinline__ void hrr2_tile(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ mac,
-                                          const Geo& g, const S om, const S tau, const S sig, int ntx, int tile) {
+                                          const Geo& g, const S om, const S tau, const S sig, int ntx, int tile,
+                                          S* __restrict__ dyn = nullptr, const S sig_dyn = S(0),
+                                          const S dthr = S(0)) {
   using L = Lattice<LAT>;
   using N = Node<LAT, DEV, S>;
   constexpr int V = VecOf<S>::V, Q = L::Q;
@@ -1251,26 +1307,8 @@ __device__ __forceinline__ void hrr2_tile(const S* __restrict__ src, S* __restri
   __syncthreads();
   if (!inner) return;
   const int c = rv * V;
-#pragma unroll
-  for (int j = 0; j < V; ++j) {
-    // gr[a][b] = (u_b(x + e_a) - u_b(x - e_a)) / 2
-    const S g00 = (lu[0][rr][c + j + 1] - lu[0][rr][c + j - 1]) * S(0.5);
-    const S g01 = (lu[1][rr][c + j + 1] - lu[1][rr][c + j - 1]) * S(0.5);
-    const S g10 = (lu[0][rr + 1][c + j] - lu[0][rr - 1][c + j]) * S(0.5);
-    const S g11 = (lu[1][rr + 1][c + j] - lu[1][rr - 1][c + j]) * S(0.5);
-    Sym<S> Sr;
-    Sr.xx = g00;
-    Sr.yy = g11;
-    Sr.xy = S(0.5) * (g01 + g10);
-    Sr.zz = Sr.xz = Sr.yz = S(0);
-    S f[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = v[i][j];
-    N::collide(f, M_HRR, om, tau, sig, &Sr);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) v[i][j] = f[i];
-  }
   const int64_t own = fpos(g, x0, y, 0);
+  dyn2_collide<LAT, DEV, S, DYN>(v, lu[0], lu[1], rr, c, om, tau, sig, dyn, g.Nfp, own, sig_dyn, dthr);
 #pragma unroll
   for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + pop_at<S, Q>(own, i)), v[i]);
 }
@@ -1280,9 +1318,11 @@ __device__ __forceinline__ void hrr2_tile(const S* __restrict__ src, S* __restri
 // row -- with the velocity of TN nodes from the velocity planes (the
 // fictitious propagation stored it there) and vectors wholly inside the
 // covered box skipped, as k_collide_hrr does.
-template <int LAT, bool DEV, typename S, bool NT, int HXV, int HYR>
+template <int LAT, bool DEV, typename S, bool NT, int HXV, int HYR, bool DYN = false>
 __device__ __forceinline__ void hrr2c_tile(const S* __restrict__ src, S* __restrict__ dst, const S* __restrict__ mac,
-                                           const Geo& g, const S om, const S tau, const S sig, int ntx, int tile) {
+                                           const Geo& g, const S om, const S tau, const S sig, int ntx, int tile,
+                                           S* __restrict__ dyn = nullptr, const S sig_dyn = S(0),
+                                           const S dthr = S(0)) {
   using L = Lattice<LAT>;
   using N = Node<LAT, DEV, S>;
   constexpr int V = VecOf<S>::V, Q = L::Q;
@@ -1330,47 +1370,33 @@ __device__ __forceinline__ void hrr2c_tile(const S* __restrict__ src, S* __restr
   __syncthreads();
   if (!inner) return;
   const int c = rv * V;
-#pragma unroll
-  for (int j = 0; j < V; ++j) {
-    const S g00 = (lu[0][rr][c + j + 1] - lu[0][rr][c + j - 1]) * S(0.5);
-    const S g01 = (lu[1][rr][c + j + 1] - lu[1][rr][c + j - 1]) * S(0.5);
-    const S g10 = (lu[0][rr + 1][c + j] - lu[0][rr - 1][c + j]) * S(0.5);
-    const S g11 = (lu[1][rr + 1][c + j] - lu[1][rr - 1][c + j]) * S(0.5);
-    Sym<S> Sr;
-    Sr.xx = g00;
-    Sr.yy = g11;
-    Sr.xy = S(0.5) * (g01 + g10);
-    Sr.zz = Sr.xz = Sr.yz = S(0);
-    S f[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = v[i][j];
-    N::collide(f, M_HRR, om, tau, sig, &Sr);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) v[i][j] = f[i];
-  }
   const int64_t own = cpos(g, x0, y, 0);
+  dyn2_collide<LAT, DEV, S, DYN>(v, lu[0], lu[1], rr, c, om, tau, sig, dyn, g.Ncp, own, sig_dyn, dthr);
 #pragma unroll
   for (int i = 0; i < Q; ++i) vstore<NT>((VA*)(dst + pop_at<S, Q>(own, i)), v[i]);
 }
 
-template <int LAT, bool DEV, typename S, bool NT, int HXV, int HYR>
+// DYN: dynamic sigma (dyn, sig_dyn, dthr as for k_collide_hrr).
+template <int LAT, bool DEV, typename S, bool NT, int HXV, int HYR, bool DYN = false>
 __global__ __launch_bounds__(HXV * HYR) void k_hrr2c(const S* __restrict__ src, S* __restrict__ dst,
                                                      const S* __restrict__ mac, const Geo g, const S om, const S tau,
-                                                     const S sig, int ntx, int nty, int per_xcd) {
+                                                     const S sig, int ntx, int nty, int per_xcd, S* __restrict__ dyn,
+                                                     const S sig_dyn, const S dthr) {
   const int b = blockIdx.x;
   const int tile = (b % kXCD) * per_xcd + b / kXCD;
   if (tile >= ntx * nty) return;  // whole work group, before any barrier
-  hrr2c_tile<LAT, DEV, S, NT, HXV, HYR>(src, dst, mac, g, om, tau, sig, ntx, tile);
+  hrr2c_tile<LAT, DEV, S, NT, HXV, HYR, DYN>(src, dst, mac, g, om, tau, sig, ntx, tile, dyn, sig_dyn, dthr);
 }
 
-template <int LAT, bool DEV, typename S, bool NT, int HXV, int HYR>
+template <int LAT, bool DEV, typename S, bool NT, int HXV, int HYR, bool DYN = false>
 __global__ __launch_bounds__(HXV * HYR) void k_hrr2(const S* __restrict__ src, S* __restrict__ dst,
                                                     const S* __restrict__ mac, const Geo g, const S om, const S tau,
-                                                    const S sig, int ntx, int nty, int per_xcd) {
+                                                    const S sig, int ntx, int nty, int per_xcd, S* __restrict__ dyn,
+                                                    const S sig_dyn, const S dthr) {
   const int b = blockIdx.x;
   const int tile = (b % kXCD) * per_xcd + b / kXCD;
   if (tile >= ntx * nty) return;  // whole work group, before any barrier
-  hrr2_tile<LAT, DEV, S, NT, HXV, HYR>(src, dst, mac, g, om, tau, sig, ntx, tile);
+  hrr2_tile<LAT, DEV, S, NT, HXV, HYR, DYN>(src, dst, mac, g, om, tau, sig, ntx, tile, dyn, sig_dyn, dthr);
 }
 
 // ---------------------------------------------------------------------------

@@ -282,8 +282,9 @@ struct Grid final : GridBase {
   // Dynamic sigma (H-RR): while on, the bulk H-RR collisions take sig_dyn
   // where the sensors' divergence or curl product falls below -dyn_thr
   // (k_collide_hrr DYN); dynC / dynF hold each node's previous divergence
-  // and curl ([4][padded positions] in the storage type).  Forces the
-  // two-pass H-RR substeps (the one-pass kernels carry no such state).
+  // and curl ([4][padded positions] in the storage type).  D2Q9 keeps its
+  // one-pass kernels (k_hrr2, k_hrr2c DYN); D3Q19 takes the two-pass H-RR
+  // substeps (its one-pass kernels carry no such state).
   bool dyn_on = false;
   double sig_dyn = 0.0, dyn_thr = 0.0;
   DevBuf dynC, dynF;
@@ -407,47 +408,61 @@ struct Grid final : GridBase {
   // One H-RR fine substep in one pass (D2Q9, k_hrr2): variants of the fine
   // H-RR role are tile shapes (lanes, vectors x rows) 64 x 8, 32 x 8,
   // 32 x 16, 128 x 4.
+  // dyn: with dynamic sigma on, the DYN kernels and the fine level's state
+  // (stepping only; the tuner's trial launches leave the state alone)
   template <int HXV, int HYR>
-  void go_hrr2(const S* src, S* dst, const S* mac, hipStream_t s) {
+  void go_hrr2(const S* src, S* dst, const S* mac, hipStream_t s, bool dyn) {
     if constexpr (D == 2) {
       const int ntx = fine2_ntx<S>(g, HXV), nty = fine2_nty(g, HYR);
       const int per = (ntx * nty + kXCD - 1) / kXCD;
-      hipLaunchKernelGGL((k_hrr2<LAT, DEV, S, NT, HXV, HYR>), dim3((unsigned)(per * kXCD)), dim3(HXV * HYR), 0, s, src,
-                         dst, mac, g, (S)(1.0 - 1.0 / tau_f), (S)tau_f, (S)sig, ntx, nty, per);
+      const dim3 gr((unsigned)(per * kXCD)), bl(HXV * HYR);
+      if (dyn && dyn_on)
+        hipLaunchKernelGGL((k_hrr2<LAT, DEV, S, NT, HXV, HYR, true>), gr, bl, 0, s, src, dst, mac, g,
+                           (S)(1.0 - 1.0 / tau_f), (S)tau_f, (S)sig, ntx, nty, per, dynF.as<S>(), (S)sig_dyn,
+                           (S)dyn_thr);
+      else
+        hipLaunchKernelGGL((k_hrr2<LAT, DEV, S, NT, HXV, HYR, false>), gr, bl, 0, s, src, dst, mac, g,
+                           (S)(1.0 - 1.0 / tau_f), (S)tau_f, (S)sig, ntx, nty, per, (S*)nullptr, (S)0, (S)0);
     }
   }
   // The coarse level in one pass (D2Q9 H-RR, rows a whole number of vectors:
   // coarse_one_pass()); same tile variants, role 2.
   bool coarse_one_pass() const {
-    return D == 2 && desc.collision == LBM_HRR && g.n[0] % V == 0 && !dyn_on && !nested_child;
+    return D == 2 && desc.collision == LBM_HRR && g.n[0] % V == 0 && !nested_child;
   }
   // D2Q9 H-RR fine substeps in one pass (k_hrr2)
-  bool fine_one_pass2() const { return D == 2 && !dyn_on; }
+  bool fine_one_pass2() const { return D == 2; }
   template <int HXV, int HYR>
-  void go_hrr2c(const S* src, S* dst, const S* mac, hipStream_t s) {
+  void go_hrr2c(const S* src, S* dst, const S* mac, hipStream_t s, bool dyn) {
     if constexpr (D == 2) {
       const int ntx = (g.n[0] / V + HXV - 3) / (HXV - 2), nty = (g.n[1] + HYR - 3) / (HYR - 2);
       const int per = (ntx * nty + kXCD - 1) / kXCD;
-      hipLaunchKernelGGL((k_hrr2c<LAT, DEV, S, NT, HXV, HYR>), dim3((unsigned)(per * kXCD)), dim3(HXV * HYR), 0, s, src,
-                         dst, mac, g, (S)(1.0 - 1.0 / tau_c), (S)tau_c, (S)sig, ntx, nty, per);
+      const dim3 gr((unsigned)(per * kXCD)), bl(HXV * HYR);
+      if (dyn && dyn_on)
+        hipLaunchKernelGGL((k_hrr2c<LAT, DEV, S, NT, HXV, HYR, true>), gr, bl, 0, s, src, dst, mac, g,
+                           (S)(1.0 - 1.0 / tau_c), (S)tau_c, (S)sig, ntx, nty, per, dynC.as<S>(), (S)sig_dyn,
+                           (S)dyn_thr);
+      else
+        hipLaunchKernelGGL((k_hrr2c<LAT, DEV, S, NT, HXV, HYR, false>), gr, bl, 0, s, src, dst, mac, g,
+                           (S)(1.0 - 1.0 / tau_c), (S)tau_c, (S)sig, ntx, nty, per, (S*)nullptr, (S)0, (S)0);
     }
   }
-  void launch_hrr2c(const S* src, S* dst, const S* mac, hipStream_t s, int v = -1) {
+  void launch_hrr2c(const S* src, S* dst, const S* mac, hipStream_t s, int v = -1, bool dyn = false) {
     if (v < 0) v = var[2];
     switch (v) {
-      case 0: go_hrr2c<64, 8>(src, dst, mac, s); break;
-      case 1: go_hrr2c<32, 8>(src, dst, mac, s); break;
-      case 2: go_hrr2c<32, 16>(src, dst, mac, s); break;
-      default: go_hrr2c<128, 4>(src, dst, mac, s); break;
+      case 0: go_hrr2c<64, 8>(src, dst, mac, s, dyn); break;
+      case 1: go_hrr2c<32, 8>(src, dst, mac, s, dyn); break;
+      case 2: go_hrr2c<32, 16>(src, dst, mac, s, dyn); break;
+      default: go_hrr2c<128, 4>(src, dst, mac, s, dyn); break;
     }
   }
-  void launch_hrr2(const S* src, S* dst, const S* mac, hipStream_t s, int v = -1) {
+  void launch_hrr2(const S* src, S* dst, const S* mac, hipStream_t s, int v = -1, bool dyn = false) {
     if (v < 0) v = var[3];
     switch (v) {
-      case 0: go_hrr2<64, 8>(src, dst, mac, s); break;
-      case 1: go_hrr2<32, 8>(src, dst, mac, s); break;
-      case 2: go_hrr2<32, 16>(src, dst, mac, s); break;
-      default: go_hrr2<128, 4>(src, dst, mac, s); break;
+      case 0: go_hrr2<64, 8>(src, dst, mac, s, dyn); break;
+      case 1: go_hrr2<32, 8>(src, dst, mac, s, dyn); break;
+      case 2: go_hrr2<32, 16>(src, dst, mac, s, dyn); break;
+      default: go_hrr2<128, 4>(src, dst, mac, s, dyn); break;
     }
   }
 
@@ -799,7 +814,7 @@ struct Grid final : GridBase {
       if (fine_one_pass2()) {
         // one pass per fine substep (k_hrr2): ring rho, u first
         hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, c0, c1, c2, mf, g, itf);
-        timed(s, [&] { launch_hrr2(fA, fB, mf, s); });
+        timed(s, [&] { launch_hrr2(fA, fB, mf, s, -1, true); });
       } else if (hrr_one_pass3()) {
         hipLaunchKernelGGL((k_ring_macro<LAT, S>), dim3(br), dim3(IB), 0, s, Hm, H0, Hp, c0, c1, c2, mf, g, itf);
         timed(s, [&] { launch_hrr3(fA, fB, mf, s); });
@@ -828,7 +843,7 @@ struct Grid final : GridBase {
                            omf, tau_f, sig);
       }
       if (fine_one_pass2()) {
-        timed(s, [&] { launch_hrr2(fB, fA, mf, s); });
+        timed(s, [&] { launch_hrr2(fB, fA, mf, s, -1, true); });
       } else if (hrr_one_pass3()) {
         timed(s, [&] { launch_hrr3(fB, fA, mf, s); });
       } else {
@@ -839,7 +854,7 @@ struct Grid final : GridBase {
       // coarse collision before the TN transfer: the vector kernel also
       // passes over TN nodes, which the transfer then overwrites; the t+1
       // ring (into fine A, independent of both) shares the transfer's launch
-      if (one_c) launch_hrr2c(csrc, cdst, mc, s);
+      if (one_c) launch_hrr2c(csrc, cdst, mc, s, -1, true);
       else launch_collide_hrr<0>(csrc, cdst, mc, tau_c, s, -1, true);
       hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, M_HRR>), dim3(br2 + bc), dim3(256), 0, s, Hp, fA, fB, cdst, g,
                          itf, kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, (const S*)nullptr);

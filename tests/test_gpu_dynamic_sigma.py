@@ -2,7 +2,8 @@
 against the oracle's, through the C ABI.
 
 FP64: within 1e-12 relative of the oracle on rho, u and the populations of
-both levels, 2D and 3D, with thresholds 1e-24 and 1e-12.  The switch is a
+both levels, 2D (one-pass kernels; a ragged grid with the coarse level in two
+passes) and 3D (two passes), with thresholds 1e-24 and 1e-12.  The switch is a
 decision on the sign of a product.  With threshold 0 (the sensors' own
 tie-break) a product of rounding noise decides -- the divergence inside the
 divergence-free vortex is ~1e-17 with either sign -- and the two sides,
@@ -49,11 +50,19 @@ def _uniform():
                       pulses=[I.Pulse(center=(30.0, 12.0), A=1e-2)])
 
 
-CASES = {"2d": (_vortex_and_pulse, 30), "3d": (_pulse_3d, 12), "uniform": (_uniform, 30)}
+def _ragged_2d():
+    # coarse rows not a whole number of vectors: the coarse level takes the
+    # two-pass H-RR form, the fine level the one-pass kernels
+    geom = I.Geometry(2, (67, 53, 1), (5, 7, 0), (30, 40, 0))
+    return I.Workload(geom=geom, U=(0.1 * I.CS, 0.0, 0.0), vortices=[I.Vortex(center=(25.0, 24.0), eps=0.01)],
+                      pulses=[I.Pulse(center=(33.0, 20.0), A=1e-2)])
+
+
+CASES = {"2d": (_vortex_and_pulse, 30), "3d": (_pulse_3d, 12), "uniform": (_uniform, 30), "ragged": (_ragged_2d, 30)}
 
 
 @pytest.mark.parametrize("thr", [1e-24, 1e-12])
-@pytest.mark.parametrize("case", ["2d", "3d", "uniform"])
+@pytest.mark.parametrize("case", ["2d", "3d", "uniform", "ragged"])
 def test_dynamic_sigma_fp64_matches_oracle(case, thr):
     lbm = _lbm()
     mk, steps = CASES[case]
@@ -89,8 +98,9 @@ def test_dynamic_sigma_fp32_matches_oracle():
 
 
 def test_sigma_dyn_equal_to_sigma_is_the_static_scheme():
-    """The two-pass substeps dynamic sigma runs, with sigma_dyn = sigma, give
-    bitwise the static scheme (which runs the one-pass D2Q9 kernels)."""
+    """Dynamic sigma with sigma_dyn = sigma gives bitwise the static scheme
+    (in D2Q9 both run the one-pass kernels, with and without the sigma
+    state)."""
     lbm = _lbm()
     a, _, levels = make_pair(_vortex_and_pulse(), "HRR", lbm.LBM_FP64, with_oracle=False)
     b, _, _ = make_pair(_vortex_and_pulse(), "HRR", lbm.LBM_FP64, with_oracle=False)
