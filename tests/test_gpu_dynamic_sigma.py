@@ -83,13 +83,15 @@ def test_dynamic_sigma_fp64_matches_oracle(case, thr):
     assert moved > 1e-9
 
 
-def test_dynamic_sigma_fp32_matches_oracle():
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_dynamic_sigma_fp32_matches_oracle(case):
     lbm = _lbm()
-    gpu, ref, levels = make_pair(_vortex_and_pulse(), "HRR", lbm.LBM_FP32_DEV)
+    mk, steps = {"2d": (_vortex_and_pulse, 60), "3d": (_pulse_3d, 24)}[case]
+    gpu, ref, levels = make_pair(mk(), "HRR", lbm.LBM_FP32_DEV)
     gpu.set_dynamic_sigma(True, 0.0, 1e-12)
     ref.set_dynamic_sigma(True, 0.0, 1e-12)
-    gpu.step(60)
-    ref.step(60)
+    gpu.step(steps)
+    ref.step(steps)
     out = compare_fp32(gpu, ref, levels)
     gpu.close()
     print(out)

@@ -90,7 +90,7 @@ def test_nested_fp64_matches_oracle(D, model, kind):
     assert max(worst.values()) <= 1e-12, worst
 
 
-@pytest.mark.parametrize("D,model", [(2, "RR"), (2, "HRR"), (3, "HRR")])
+@pytest.mark.parametrize("D,model", [(2, "RR"), (2, "HRR"), (3, "RR"), (3, "HRR")])
 def test_nested_fp32_within_bars(D, model):
     lbm = _lbm()
     gpu, ref = _pair(D, model, lbm.LBM_FP32_DEV, "acoustic")
