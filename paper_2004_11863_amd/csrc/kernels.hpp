@@ -1029,10 +1029,15 @@ __global__ __launch_bounds__(256) void k_ring_coalesce(const double* __restrict_
 // (`row[i]` points at population i of that row, c0 the vector's first
 // column).  Middle nodes pull from src and collide; ring nodes take their
 // t+1/2 values from `half`; `band` asks to store the result of middle nodes
-// within 2 nodes of the TN line into `half` as well.
-template <int LAT, bool DEV, typename S, int MODEL>
+// within 2 nodes of the TN line into `half` as well.  SENS (the NH sensors'
+// record of this iteration, for the lane that owns the vector, `band`):
+// every middle node's result goes to `half` and the velocity of its pulled
+// (pre-collision) populations to the double planes su ([1 + D][padded
+// positions]), in the arithmetic of k_sens_vel.
+template <int LAT, bool DEV, typename S, int MODEL, bool SENS = false>
 __device__ __forceinline__ void fine2_s1(const S* __restrict__ src, S* __restrict__ half, const Geo& g, const S om,
-                                         int k, int y, int nv, S* const* row, int c0, bool band) {
+                                         int k, int y, int nv, S* const* row, int c0, bool band,
+                                         double* __restrict__ su = nullptr) {
   using L = Lattice<LAT>;
   using N = Node<LAT, DEV, S>;
   constexpr int V = VecOf<S>::V, Q = L::Q;
@@ -1054,6 +1059,22 @@ __device__ __forceinline__ void fine2_s1(const S* __restrict__ src, S* __restric
   const Pull<S, Q, V, 1, 2> pl(g.pf, g.fxo, x0, y, 0, nx, ny, 1);
   VA v[Q];
   pl.template load_all<L>(src, v);
+  if constexpr (SENS) {
+    if (band) {
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const int x = x0 + j;
+        if (x > nx - 2) continue;
+        double f[Q], r, r0, u[3];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = full_pop<S, DEV, LAT>(v[i][j], i);
+        Node<LAT, false, double>::moments(f, r, r0, u);
+        const int64_t p = fpos(g, x, y, 0);
+#pragma unroll
+        for (int d = 0; d < L::D; ++d) su[(int64_t)(1 + d) * g.Nfp + p] = u[d];
+      }
+    }
+  }
 #pragma unroll
   for (int j = 0; j < V; ++j) {
     S f[Q];
@@ -1079,7 +1100,7 @@ __device__ __forceinline__ void fine2_s1(const S* __restrict__ src, S* __restric
 #pragma unroll
     for (int j = 0; j < V; ++j) {
       const int x = x0 + j;
-      if (x > nx - 2 || !(x <= 4 || x >= nx - 5 || y <= 4 || y >= ny - 5)) continue;
+      if (x > nx - 2 || (!SENS && !(x <= 4 || x >= nx - 5 || y <= 4 || y >= ny - 5))) continue;
       const int64_t p = fpos(g, x, y, 0);
 #pragma unroll
       for (int i = 0; i < Q; ++i) half[pop_at<S, Q>(p, i)] = v[i][j];
@@ -1127,9 +1148,10 @@ __device__ __forceinline__ void fine2_s2(S* __restrict__ dst, const Geo& g, cons
 // substep-1 work.  MINW asks the compiler to fit that many waves per SIMD.
 // Tile `tile` (of ntx per row of tiles) of one grid; the whole work group
 // calls it.
-template <int LAT, bool DEV, typename S, int MODEL, bool NT, int HXV, int HYR>
+template <int LAT, bool DEV, typename S, int MODEL, bool NT, int HXV, int HYR, bool SENS = false>
 __device__ __forceinline__ void fine2_tile(const S* __restrict__ src, S* __restrict__ dst, S* __restrict__ half,
-                                           const Geo& g, const S om, int ntx, int tile) {
+                                           const Geo& g, const S om, int ntx, int tile,
+                                           double* __restrict__ su = nullptr) {
   using L = Lattice<LAT>;
   constexpr int V = VecOf<S>::V, Q = L::Q;
   constexpr int TXV = HXV - 2, TY = HYR - 2, RW = HXV * V;
@@ -1147,7 +1169,7 @@ __device__ __forceinline__ void fine2_tile(const S* __restrict__ src, S* __restr
     S* row[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) row[i] = &lds[i][rr][0];
-    fine2_s1<LAT, DEV, S, MODEL>(src, half, g, om, k, y, nv, row, rv * V, inner);
+    fine2_s1<LAT, DEV, S, MODEL, SENS>(src, half, g, om, k, y, nv, row, rv * V, inner, su);
   }
   __syncthreads();
   if (inner && k < nv && y <= ny - 2) {
@@ -1169,14 +1191,15 @@ __host__ __device__ inline int fine2_ntx(const Geo& g, int HXV) {
 }
 __host__ __device__ inline int fine2_nty(const Geo& g, int HYR) { return (g.nf[1] - 2 + HYR - 3) / (HYR - 2); }
 
-template <int LAT, bool DEV, typename S, int MODEL, bool NT, int HXV, int HYR, int MINW>
+// SENS: also the NH sensors' record of the t+1/2 iteration (fine2_s1) in su.
+template <int LAT, bool DEV, typename S, int MODEL, bool NT, int HXV, int HYR, int MINW, bool SENS = false>
 __global__ __launch_bounds__(HXV * HYR, MINW) void k_fine2(const S* __restrict__ src, S* __restrict__ dst,
                                                          S* __restrict__ half, const Geo g, const S om, int ntx,
-                                                         int nty, int per_xcd) {
+                                                         int nty, int per_xcd, double* __restrict__ su) {
   const int b = blockIdx.x;
   const int tile = (b % kXCD) * per_xcd + b / kXCD;
   if (tile >= ntx * nty) return;  // whole work group, before any barrier
-  fine2_tile<LAT, DEV, S, MODEL, NT, HXV, HYR>(src, dst, half, g, om, ntx, tile);
+  fine2_tile<LAT, DEV, S, MODEL, NT, HXV, HYR, SENS>(src, dst, half, g, om, ntx, tile, su);
 }
 
 // The H-RR collision of one lane's vector in the D2Q9 one-pass kernels: the

@@ -272,12 +272,15 @@ struct Grid final : GridBase {
   // The stepping stores only the ring populations it reads again (k_ring
   // PARTIAL); true while fine A holds such a partial ring.
   bool ring_partial = false;
-  // NH sensors: while on, each step first records the velocities of the
-  // iteration before its last one (coarse t, fine t+1/2) in sUc / sUf
-  // (double planes [1 + D][padded positions]) and runs the fine substeps as
-  // two launches, so that the t+1/2 state stays in fine B; sens_ready: a
-  // step has been recorded and nothing has touched the state since.
+  // NH sensors: while on, each step records the velocities of the iteration
+  // before its last one (coarse t, fine t+1/2) in sUc / sUf (double planes
+  // [1 + D][padded positions]) and keeps the t+1/2 state: D2Q9 BGK / RR in
+  // the fused kernel (k_fine2 SENS writes both, the state into fbuf[2]);
+  // otherwise a recording pass before the step and the fine substeps as two
+  // launches (the t+1/2 state in fine B); sens_ready: a step has been
+  // recorded and nothing has touched the state since.
   bool sensors_on = false, sens_ready = false;
+  bool sens_pre_half = false;  // the last step was fused: its t+1/2 state is in fbuf[2]
   DevBuf sUc, sUf, sFlags, sProd;
   // Dynamic sigma (H-RR): while on, the bulk H-RR collisions take sig_dyn
   // where the sensors' divergence or curl product falls below -dyn_thr
@@ -489,13 +492,20 @@ struct Grid final : GridBase {
   // 64 x 16, 32 x 16 and 32 x 8 (measured on the 4097 x 2049 patch, FP32:
   // 119, 134-147, 135 and 135 us; narrower or non-power-of-two widths and
   // 1024-lane tiles were slower still).
+  // su: the NH sensors' velocity planes of the t+1/2 iteration (k_fine2
+  // SENS records them, and the whole t+1/2 state into half), or null.
   template <int MODEL, int HXV, int HYR>
-  void go_fine2(const S* src, S* dst, S* half, hipStream_t s) {
+  void go_fine2(const S* src, S* dst, S* half, hipStream_t s, double* su = nullptr) {
     if constexpr (D == 2 && MODEL != M_HRR) {
       const int ntx = fine2_ntx<S>(g, HXV), nty = fine2_nty(g, HYR);
       const int per = (ntx * nty + kXCD - 1) / kXCD;
-      hipLaunchKernelGGL((k_fine2<LAT, DEV, S, MODEL, NT, HXV, HYR, 4>), dim3((unsigned)(per * kXCD)),
-                         dim3(HXV * HYR), 0, s, src, dst, half, g, (S)(1.0 - 1.0 / tau_f), ntx, nty, per);
+      const dim3 gr((unsigned)(per * kXCD)), bl(HXV * HYR);
+      if (su)
+        hipLaunchKernelGGL((k_fine2<LAT, DEV, S, MODEL, NT, HXV, HYR, 4, true>), gr, bl, 0, s, src, dst, half, g,
+                           (S)(1.0 - 1.0 / tau_f), ntx, nty, per, su);
+      else
+        hipLaunchKernelGGL((k_fine2<LAT, DEV, S, MODEL, NT, HXV, HYR, 4, false>), gr, bl, 0, s, src, dst, half, g,
+                           (S)(1.0 - 1.0 / tau_f), ntx, nty, per, (double*)nullptr);
     }
   }
   // Work decomposition of a marching fine kernel (k_hrr3) with TXV x TY
@@ -611,14 +621,14 @@ struct Grid final : GridBase {
     }
   }
   template <int MODEL>
-  void launch_fused(const S* src, S* dst, S* half, hipStream_t s, int v = -1) {
+  void launch_fused(const S* src, S* dst, S* half, hipStream_t s, int v = -1, double* su = nullptr) {
     if (v < 0) v = var[1];
     if constexpr (D == 2) {
       switch (v) {
-        case 0: go_fine2<MODEL, 64, 8>(src, dst, half, s); break;
-        case 1: go_fine2<MODEL, 64, 16>(src, dst, half, s); break;
-        case 2: go_fine2<MODEL, 32, 16>(src, dst, half, s); break;
-        default: go_fine2<MODEL, 32, 8>(src, dst, half, s); break;
+        case 0: go_fine2<MODEL, 64, 8>(src, dst, half, s, su); break;
+        case 1: go_fine2<MODEL, 64, 16>(src, dst, half, s, su); break;
+        case 2: go_fine2<MODEL, 32, 16>(src, dst, half, s, su); break;
+        default: go_fine2<MODEL, 32, 8>(src, dst, half, s, su); break;
       }
     } else if constexpr (sizeof(S) == 4) {
       if (v == 2) go_fine3s<MODEL, 66, 14, 1>(src, dst, half, s, 2);
@@ -645,7 +655,8 @@ struct Grid final : GridBase {
     }
   }
   // True when this step runs both fine substeps in one kernel.
-  bool fused_now() const { return fused && !sensors_on && (D == 2 || var[1] >= 2); }
+  // (D2Q9 stays fused with the NH sensors on: k_fine2 SENS records them)
+  bool fused_now() const { return fused && (D == 2 || (!sensors_on && var[1] >= 2)); }
   // LDS variant of the fine k_stream launches for fine-role variant v.
   int fine_lds_var(int v) const { return (fused && D == 3) ? (v == 0 ? 2 : 1) : v; }
   // Fine-level pull-stream + collide (BGK, RR): the timed kernel.
@@ -786,10 +797,11 @@ struct Grid final : GridBase {
     hipLaunchKernelGGL((k_hist_capture<LAT, DEV, S, MODEL>), dim3(bh), dim3(IB), 0, s, csrc, Hp, g, itf,
                        MODEL == M_HRR ? nullptr : G.as<double>(), Hm, H0);
     timed_factor = fused_now() ? 2 : 1;
+    sens_pre_half = MODEL != M_HRR && fused_now();
     if (MODEL != M_HRR && fused_now()) {
       S* fH = fbuf[2].as<S>();
       launch_stream_ring<MODEL>(csrc, cdst, fH, kf, omf, s);
-      timed(s, [&] { launch_fused<MODEL>(fA, fB, fH, s); });
+      timed(s, [&] { launch_fused<MODEL>(fA, fB, fH, s, -1, sensors_on ? sUf.as<double>() : nullptr); });
       hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, MODEL>), dim3(br2 + bc), dim3(256), 0, s, Hp, fB, fH, cdst, g, itf,
                          kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, (const S*)nullptr);
       fpar ^= 1;
@@ -1020,10 +1032,11 @@ struct Grid final : GridBase {
   // nodes pull from the state at t (the pre-collision state at t+1/2); the
   // ring's t+1/2 velocities are interpolated from the history after the
   // step, when its t+1 level exists.
+  // (a fused D2Q9 step records the fine level's in k_fine2)
   void sensors_before(hipStream_t s) {
     hipLaunchKernelGGL((k_sens_vel<LAT, DEV, S, 0, false>), dim3(blocks(g.Nc, 256)), dim3(256), 0, s, cur_c(),
                        sUc.as<double>(), g);
-    if (g.has_fine)
+    if (g.has_fine && !(desc.collision != LBM_HRR && fused_now()))
       hipLaunchKernelGGL((k_sens_vel<LAT, DEV, S, 1, true>), dim3(blocks(g.Nf, 256)), dim3(256), 0, s, fineA(),
                          sUf.as<double>(), g);
   }
@@ -1082,7 +1095,7 @@ struct Grid final : GridBase {
                          cur_c(), cbuf[cpar ^ 1].as<S>(), fl, pr, g, thr);
     else
       hipLaunchKernelGGL((k_sensors<LAT, DEV, S, 1>), dim3(blocks(N, 256)), dim3(256), 0, stream, sUf.as<double>(),
-                         fineA(), fineB(), fl, pr, g, thr);
+                         fineA(), sens_pre_half ? fbuf[2].as<S>() : fineB(), fl, pr, g, thr);
     HIPCHK(hipGetLastError());
     const hipMemcpyKind k = dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     HIPCHK(hipMemcpyAsync(flags, fl, (size_t)N, k, stream));
