@@ -303,6 +303,14 @@ def paper_cases():
             dt = time.perf_counter() - t0
             res["on" if on else "off"] = round(gr.updates_per_step() * 200 / dt / 1e6, 1)
             if on and switch == "sensors":
+                # one step per call: every step records (a read-out after
+                # each step); a call of many steps records its last ones only
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(200):
+                    gr.step(1)
+                torch.cuda.synchronize()
+                res["on_every_step"] = round(gr.updates_per_step() * 200 / (time.perf_counter() - t0) / 1e6, 1)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 gr.sensors(1, 1e-8)
@@ -310,9 +318,10 @@ def paper_cases():
             gr.close()
             del gr
             torch.cuda.empty_cache()
-        out[f"d2q9_4096_{col.lower()}_fp32_{name}"] = {"mlups_off": res["off"], "mlups_on": res["on"],
-                                                       **({"readout_fine_s": res["readout_fine_s"]}
-                                                          if "readout_fine_s" in res else {})}
+        out[f"d2q9_4096_{col.lower()}_fp32_{name}"] = {
+            "mlups_off": res["off"], "mlups_on": res["on"],
+            **({"mlups_on_recording_every_step": res["on_every_step"], "readout_fine_s": res["readout_fine_s"]}
+               if "readout_fine_s" in res else {})}
         print(f"# paper case {name}: {out[f'd2q9_4096_{col.lower()}_fp32_{name}']}", file=sys.stderr, flush=True)
     out["d3q19_256_three_levels_fp32"] = three_levels()
     print(f"# paper case three levels: {out['d3q19_256_three_levels_fp32']}", file=sys.stderr, flush=True)

@@ -149,11 +149,16 @@ int lbm_get_totals(lbm_handle h, double mass[2], double momentum[6]);
 int lbm_get_totals_noalloc(lbm_handle h, double mass[2], double momentum[6]);
 
 /* Non-hydrodynamic-mode sensors (Sec. 7 of the paper).  lbm_sensors_enable
- * (on = 1) makes every following step record what the sensors compare: the
- * velocities of the iteration before the step's last one (coarse: t; fine:
- * t+1/2) and the fine t+1/2 state (the fine substeps then run as two
- * launches).  Off by default; costs two extra passes over the populations
- * per step and 2 (1 + D) doubles per node of device memory.
+ * (on = 1) makes the following lbm_step calls record what the sensors
+ * compare: the velocities of the iteration before the last step's last one
+ * (coarse: t; fine: t+1/2) and the fine t+1/2 state.  Only the last step of
+ * each call records (a read-out sees no other); with BGK or RR on two levels
+ * the step before it records the coarse velocities as it streams, else a
+ * recording pass does.  Off by default; a recording step costs about one
+ * extra pass over the populations (D3Q19 runs its fine substeps as two
+ * launches then).  Device memory: 2 (1 + D) doubles per coarse node,
+ * (1 + D) per fine node, and 3 doubles and a byte per node of the larger
+ * level for the read-out.
  * lbm_sensors(level) then returns, for the last step, one byte per node of
  * the level (x fastest):
  *   bit 0 SpuriousAc: div u(previous) * div u(last) < 0  (eq sensorSpuriousAc)

@@ -239,6 +239,17 @@ struct Pull {
   }
 };
 
+// A stored population in double (adds back the weight when the storage holds
+// deviations) and the reverse.
+template <typename S, bool DEV, int LAT>
+__device__ __forceinline__ double full_pop(S v, int i) {
+  return (double)v + (DEV ? Lattice<LAT>::w(i) : 0.0);
+}
+template <typename S, bool DEV, int LAT>
+__device__ __forceinline__ S store_pop(double f, int i) {
+  return (S)(f - (DEV ? Lattice<LAT>::w(i) : 0.0));
+}
+
 // Coarse vectors lying wholly inside the covered box are not evolved.
 template <int LEVEL>
 __device__ __forceinline__ bool skip_vec(const Geo& g, int x0, int V, int y, int z, int nx) {
@@ -258,9 +269,13 @@ __device__ __forceinline__ bool skip_vec(const Geo& g, int x0, int V, int y, int
 // With xb set (fine level, the first substep of the two-launch D3Q19 path)
 // the results of middle nodes in the x-bands also go to the compact band copy
 // (xband_at), which the fine-to-coarse transfer reads.
-template <int LAT, bool DEV, typename S, int MODEL, int LEVEL, bool NT>
+// SENS (BGK, RR): the NH sensors' velocity record of the state this call
+// leaves, the moments of the stored post-collision values in double (as
+// k_sens_vel takes them), into the planes su ([1 + D][padded positions]).
+template <int LAT, bool DEV, typename S, int MODEL, int LEVEL, bool NT, bool SENS = false>
 __device__ __forceinline__ void stream_body(const S* __restrict__ src, S* __restrict__ dst, S* __restrict__ mac, const Geo& g,
-                                   const Flat& fl, const S om, int chunk, S* __restrict__ xb = nullptr) {
+                                   const Flat& fl, const S om, int chunk, S* __restrict__ xb = nullptr,
+                                   double* __restrict__ su = nullptr) {
   using L = Lattice<LAT>;
   using N = Node<LAT, DEV, S>;
   constexpr int V = VecOf<S>::V;
@@ -304,6 +319,16 @@ __device__ __forceinline__ void stream_body(const S* __restrict__ src, S* __rest
       N::collide(s, MODEL, om, S(0), S(0), nullptr);
 #pragma unroll
       for (int i = 0; i < Q; ++i) v[i][k] = s[i];
+      if constexpr (SENS) {
+        if (x0 + k <= nx - 1) {
+          double f[Q], r, r0, u[3];
+#pragma unroll
+          for (int i = 0; i < Q; ++i) f[i] = full_pop<S, DEV, LAT>(s[i], i);
+          Node<LAT, false, double>::moments(f, r, r0, u);
+#pragma unroll
+          for (int d = 0; d < L::D; ++d) su[(int64_t)(1 + d) * NP + own + k] = u[d];
+        }
+      }
     }
   }
 #pragma unroll
@@ -544,15 +569,6 @@ struct Iface {
   const int64_t* tnf;    // [NT] fine TN nodes (logical)
   const int64_t* tnc;    // [NT] coarse TN nodes (logical)
 };
-
-template <typename S, bool DEV, int LAT>
-__device__ __forceinline__ double full_pop(S v, int i) {
-  return (double)v + (DEV ? Lattice<LAT>::w(i) : 0.0);
-}
-template <typename S, bool DEV, int LAT>
-__device__ __forceinline__ S store_pop(double f, int i) {
-  return (S)(f - (DEV ? Lattice<LAT>::w(i) : 0.0));
-}
 
 // Temporal interpolation of a history value to t+1/2 (eq TempInt):
 // -1/8 H(t-1) + 3/4 H(t) + 3/8 H(t+1).
@@ -878,11 +894,12 @@ __global__ void k_fict(const S* __restrict__ src_f, T* __restrict__ mac_c, const
 // t fastest so neighbouring lanes read neighbouring nodes, computes the
 // weighted non-equilibrium part of one stencil node into LDS; lanes per
 // (TN node, component) sum the stencil in a fixed order; one lane per TN node
-// rebuilds and collides.
-template <int LAT, bool DEV, typename S, int MODEL>
+// rebuilds and collides.  SENS: the node's record for the NH sensors, as in
+// stream_body.
+template <int LAT, bool DEV, typename S, int MODEL, bool SENS = false>
 __device__ __forceinline__ void coalesce_body(const S* __restrict__ src_f, S* __restrict__ dst_c, const Geo& g, const Iface& itf,
                                      double kc, double om_c, double tau_c, double sig, int64_t blk,
-                                     const S* __restrict__ xb = nullptr) {
+                                     const S* __restrict__ xb = nullptr, double* __restrict__ su = nullptr) {
   using L = Lattice<LAT>;
   using N = Node<LAT, false, double>;
   using F = HF<LAT, MODEL>;
@@ -963,7 +980,17 @@ __device__ __forceinline__ void coalesce_body(const S* __restrict__ src_f, S* __
   cdecode(g, itf.tnc[t3], cx, cy, cz);
   const int64_t ci = cpos(g, cx, cy, cz);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) dst_c[pop_at<S, Q>(ci, i)] = store_pop<S, DEV, LAT>(f[i], i);
+  for (int i = 0; i < Q; ++i) {
+    const S st = store_pop<S, DEV, LAT>(f[i], i);
+    dst_c[pop_at<S, Q>(ci, i)] = st;
+    if constexpr (SENS) f[i] = full_pop<S, DEV, LAT>(st, i);
+  }
+  if constexpr (SENS) {
+    double r, r0, u[3];
+    N::moments(f, r, r0, u);
+#pragma unroll
+    for (int d = 0; d < D; ++d) su[(int64_t)(1 + d) * g.Ncp + ci] = u[d];
+  }
 }
 
 
@@ -972,11 +999,13 @@ __device__ __forceinline__ void coalesce_body(const S* __restrict__ src_f, S* __
 // the ring latency-bound and the stream bandwidth-bound, so the ring hides
 // inside the stream.  Blocks [0, nrb) take 256 ring nodes each (dispatched
 // first), the rest are the stream's chunks; both parts are XCD-contiguous.
-template <int LAT, bool DEV, typename S, int MODEL, bool NT>
+// SENS: the stream also records the NH sensors' coarse velocities into su.
+template <int LAT, bool DEV, typename S, int MODEL, bool NT, bool SENS = false>
 __global__ __launch_bounds__(256) void k_stream_ring(const S* __restrict__ src, S* __restrict__ dst, const Geo g,
                                                      const Flat fl, const S om, const double* __restrict__ G,
                                                      S* __restrict__ fdst, const Iface itf, double kf, double om_f,
-                                                     double tau_f, double sig, int nrb, S* __restrict__ xb) {
+                                                     double tau_f, double sig, int nrb, S* __restrict__ xb,
+                                                     double* __restrict__ su) {
   const int b = blockIdx.x;
   if (b < nrb) {
     const int per = nrb / kXCD;
@@ -984,7 +1013,8 @@ __global__ __launch_bounds__(256) void k_stream_ring(const S* __restrict__ src, 
     ring_body<LAT, DEV, S, MODEL, true>(G, fdst, g, itf, kf, om_f, tau_f, sig, blk * 256 + threadIdx.x, xb);
   } else {
     const int b2 = b - nrb;
-    stream_body<LAT, DEV, S, MODEL, 0, NT>(src, dst, nullptr, g, fl, om, (b2 % kXCD) * fl.per_xcd + b2 / kXCD);
+    stream_body<LAT, DEV, S, MODEL, 0, NT, SENS>(src, dst, nullptr, g, fl, om, (b2 % kXCD) * fl.per_xcd + b2 / kXCD,
+                                                 nullptr, su);
   }
 }
 
@@ -993,13 +1023,14 @@ __global__ __launch_bounds__(256) void k_stream_ring(const S* __restrict__ src, 
 // state at t+1/2 -> coarse TN) in one launch: they write disjoint buffers and
 // read none of each other's outputs.  Blocks [0, nrb) take 256 ring nodes
 // each, the rest PER TN nodes each; both parts are XCD-contiguous (nrb is a
-// multiple of 8).
-template <int LAT, bool DEV, typename S, int MODEL>
+// multiple of 8).  SENS: the transfer records the NH sensors' velocities of
+// the TN nodes into su.
+template <int LAT, bool DEV, typename S, int MODEL, bool SENS = false>
 __global__ __launch_bounds__(256) void k_ring_coalesce(const double* __restrict__ Hp, S* __restrict__ fdst,
                                                        const S* __restrict__ src_f, S* __restrict__ dst_c,
                                                        const Geo g, const Iface itf, double kf, double om_f,
                                                        double tau_f, double kc, double om_c, double tau_c, double sig,
-                                                       int nrb, const S* __restrict__ xb) {
+                                                       int nrb, const S* __restrict__ xb, double* __restrict__ su) {
   const int b = blockIdx.x;
   if (b < nrb) {
     const int per = nrb / kXCD;
@@ -1007,8 +1038,8 @@ __global__ __launch_bounds__(256) void k_ring_coalesce(const double* __restrict_
     ring_body<LAT, DEV, S, MODEL, true>(Hp, fdst, g, itf, kf, om_f, tau_f, sig, blk * 256 + threadIdx.x);
   } else {
     const int b2 = b - nrb, per = ((int)gridDim.x - nrb) / kXCD;
-    coalesce_body<LAT, DEV, S, MODEL>(src_f, dst_c, g, itf, kc, om_c, tau_c, sig,
-                                      (int64_t)(b2 % kXCD) * per + b2 / kXCD, xb);
+    coalesce_body<LAT, DEV, S, MODEL, SENS>(src_f, dst_c, g, itf, kc, om_c, tau_c, sig,
+                                            (int64_t)(b2 % kXCD) * per + b2 / kXCD, xb, su);
   }
 }
 

@@ -272,16 +272,23 @@ struct Grid final : GridBase {
   // The stepping stores only the ring populations it reads again (k_ring
   // PARTIAL); true while fine A holds such a partial ring.
   bool ring_partial = false;
-  // NH sensors: while on, each step records the velocities of the iteration
-  // before its last one (coarse t, fine t+1/2) in sUc / sUf (double planes
-  // [1 + D][padded positions]) and keeps the t+1/2 state: D2Q9 BGK / RR in
-  // the fused kernel (k_fine2 SENS writes both, the state into fbuf[2]);
-  // otherwise a recording pass before the step and the fine substeps as two
-  // launches (the t+1/2 state in fine B); sens_ready: a step has been
-  // recorded and nothing has touched the state since.
+  // NH sensors: while on, the last step of each lbm_step call (rec_fine:
+  // the read-out sees no other) records the velocities of the iteration
+  // before its last one (coarse t, fine t+1/2) in sUc[sc_cur] / sUf (double
+  // planes [1 + D][padded positions]) and keeps the t+1/2 state: D2Q9 BGK /
+  // RR in the fused kernel (k_fine2 SENS writes both, the state into
+  // fbuf[2]); otherwise a recording pass before the step and the fine
+  // substeps as two launches (the t+1/2 state in fine B).  Coarse, BGK / RR
+  // two-level: the last two steps' stream and transfer (SENS, rec_coarse)
+  // record the state they leave into sUc[sc_cur ^ 1], which the next step
+  // takes over instead of a recording pass (sens_coarse_next).  sens_ready:
+  // a step has been recorded and nothing has touched the state since.
   bool sensors_on = false, sens_ready = false;
+  bool rec_fine = false, rec_coarse = false;
   bool sens_pre_half = false;  // the last step was fused: its t+1/2 state is in fbuf[2]
-  DevBuf sUc, sUf, sFlags, sProd;
+  bool sens_coarse_next = false;
+  int sc_cur = 0;
+  DevBuf sUc[2], sUf, sFlags, sProd;
   // Dynamic sigma (H-RR): while on, the bulk H-RR collisions take sig_dyn
   // where the sensors' divergence or curl product falls below -dyn_thr
   // (k_collide_hrr DYN); dynC / dynF hold each node's previous divergence
@@ -400,12 +407,36 @@ struct Grid final : GridBase {
   // Coarse stream (BGK, RR) and the t+1/2 ring reconstruction from G into
   // fdst, one launch (k_stream_ring).
   template <int MODEL>
-  void launch_stream_ring(const S* src, S* dst, S* fdst, double kf, double omf, hipStream_t s, S* xb = nullptr) {
+  // su: the NH sensors' record of the coarse state it leaves (SENS), or null
+  void launch_stream_ring(const S* src, S* dst, S* fdst, double kf, double omf, hipStream_t s, S* xb = nullptr,
+                          double* su = nullptr) {
     const Flat f = flat(0);
     const unsigned nrb = xblocks(itf.NR, 256);
-    hipLaunchKernelGGL((k_stream_ring<LAT, DEV, S, MODEL, NT>), dim3(nrb + (unsigned)(f.per_xcd * kXCD)), dim3(256),
-                       (unsigned)kVarLds[var[0]], s, src, dst, g, f, (S)(1.0 - 1.0 / tau_c), G.as<double>(), fdst, itf,
-                       kf, omf, tau_f, sig, (int)nrb, xb);
+    const dim3 gr(nrb + (unsigned)(f.per_xcd * kXCD)), bl(256);
+    const unsigned lds = (unsigned)kVarLds[var[0]];
+    const S om = (S)(1.0 - 1.0 / tau_c);
+    if (su)
+      hipLaunchKernelGGL((k_stream_ring<LAT, DEV, S, MODEL, NT, true>), gr, bl, lds, s, src, dst, g, f, om,
+                         G.as<double>(), fdst, itf, kf, omf, tau_f, sig, (int)nrb, xb, su);
+    else
+      hipLaunchKernelGGL((k_stream_ring<LAT, DEV, S, MODEL, NT, false>), gr, bl, lds, s, src, dst, g, f, om,
+                         G.as<double>(), fdst, itf, kf, omf, tau_f, sig, (int)nrb, xb, (double*)nullptr);
+  }
+  // The t+1 ring (Hp -> fdst) and the fine-to-coarse transfer (src_f ->
+  // the TN nodes of cdst), one launch (k_ring_coalesce); su as above.
+  template <int MODEL>
+  void launch_ring_coalesce(const double* Hp, S* fdst, const S* src_f, S* cdst, const S* xb, double* su,
+                            hipStream_t s) {
+    constexpr int PER = 256 / (D == 2 ? 9 : 27);
+    const unsigned br2 = xblocks(itf.NR, 256), bc = xblocks(itf.NT, PER);
+    const double kf = tau_f / (2.0 * tau_c), kc = 2.0 * tau_c / tau_f;
+    const double omf = 1.0 - 1.0 / tau_f, omc = 1.0 - 1.0 / tau_c;
+    if (su)
+      hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, MODEL, true>), dim3(br2 + bc), dim3(256), 0, s, Hp, fdst, src_f,
+                         cdst, g, itf, kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, xb, su);
+    else
+      hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, MODEL, false>), dim3(br2 + bc), dim3(256), 0, s, Hp, fdst,
+                         src_f, cdst, g, itf, kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, xb, (double*)nullptr);
   }
 
   // One H-RR fine substep in one pass (D2Q9, k_hrr2): variants of the fine
@@ -655,8 +686,8 @@ struct Grid final : GridBase {
     }
   }
   // True when this step runs both fine substeps in one kernel.
-  // (D2Q9 stays fused with the NH sensors on: k_fine2 SENS records them)
-  bool fused_now() const { return fused && (D == 2 || (!sensors_on && var[1] >= 2)); }
+  // (D2Q9 stays fused when it records the NH sensors: k_fine2 SENS does)
+  bool fused_now() const { return fused && (D == 2 || (!rec_fine && var[1] >= 2)); }
   // LDS variant of the fine k_stream launches for fine-role variant v.
   int fine_lds_var(int v) const { return (fused && D == 3) ? (v == 0 ? 2 : 1) : v; }
   // Fine-level pull-stream + collide (BGK, RR): the timed kernel.
@@ -721,7 +752,7 @@ struct Grid final : GridBase {
     HIPCHK(hipSetDevice(device));
     no_nesting("tuning");
     HIPCHK(hipStreamSynchronize(stream));
-    sens_ready = false;  // the trial launches overwrite the previous states
+    sens_ready = sens_coarse_next = false;  // the trial launches overwrite the previous states
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -798,12 +829,14 @@ struct Grid final : GridBase {
                        MODEL == M_HRR ? nullptr : G.as<double>(), Hm, H0);
     timed_factor = fused_now() ? 2 : 1;
     sens_pre_half = MODEL != M_HRR && fused_now();
+    // BGK / RR: the coarse record of the state this step leaves
+    double* scn = MODEL != M_HRR && rec_coarse ? sUc[sc_cur ^ 1].as<double>() : nullptr;
+    sens_coarse_next = scn != nullptr;
     if (MODEL != M_HRR && fused_now()) {
       S* fH = fbuf[2].as<S>();
-      launch_stream_ring<MODEL>(csrc, cdst, fH, kf, omf, s);
-      timed(s, [&] { launch_fused<MODEL>(fA, fB, fH, s, -1, sensors_on ? sUf.as<double>() : nullptr); });
-      hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, MODEL>), dim3(br2 + bc), dim3(256), 0, s, Hp, fB, fH, cdst, g, itf,
-                         kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, (const S*)nullptr);
+      launch_stream_ring<MODEL>(csrc, cdst, fH, kf, omf, s, nullptr, scn);
+      timed(s, [&] { launch_fused<MODEL>(fA, fB, fH, s, -1, rec_fine ? sUf.as<double>() : nullptr); });
+      launch_ring_coalesce<MODEL>(Hp, fB, fH, cdst, nullptr, scn, s);
       fpar ^= 1;
     } else if (MODEL != M_HRR) {
       // substep 1 writes the ring column x = nx - 1 of B, so the t+1/2 ring
@@ -811,10 +844,9 @@ struct Grid final : GridBase {
       // the compact copy of the x-bands, from which the transfer reads
       S* xb = xbuf.as<S>();
       fine_stream_timed(MODEL, fA, fB, s, xb);
-      launch_stream_ring<MODEL>(csrc, cdst, fB, kf, omf, s, xb);
+      launch_stream_ring<MODEL>(csrc, cdst, fB, kf, omf, s, xb, scn);
       fine_stream_timed(MODEL, fB, fA, s);
-      hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, MODEL>), dim3(br2 + bc), dim3(256), 0, s, Hp, fA, fB, cdst, g, itf,
-                         kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, (const S*)xb);
+      launch_ring_coalesce<MODEL>(Hp, fA, fB, cdst, xb, scn, s);
     } else {
       S* mc = mac_c.as<S>();
       S* mf = mac_f.as<S>();
@@ -869,7 +901,7 @@ struct Grid final : GridBase {
       if (one_c) launch_hrr2c(csrc, cdst, mc, s, -1, true);
       else launch_collide_hrr<0>(csrc, cdst, mc, tau_c, s, -1, true);
       hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, M_HRR>), dim3(br2 + bc), dim3(256), 0, s, Hp, fA, fB, cdst, g,
-                         itf, kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, (const S*)nullptr);
+                         itf, kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, (const S*)nullptr, (double*)nullptr);
     }
     HIPCHK(hipGetLastError());
     cpar ^= 1;
@@ -907,7 +939,7 @@ struct Grid final : GridBase {
     launch_stream_ring<MODEL>(csrc, cdst, fB, kf, omf, s, nullptr);
     child->step(1, s);
     hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, MODEL>), dim3(br2 + bc), dim3(256), 0, s, Hp, fA, fB, cdst, g, itf,
-                       kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, (const S*)nullptr);
+                       kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, (const S*)nullptr, (double*)nullptr);
     HIPCHK(hipGetLastError());
     cpar ^= 1;
     const int old = hs[0];
@@ -969,7 +1001,7 @@ struct Grid final : GridBase {
     if (one_c) launch_hrr2c(csrc, cdst, mc, s);
     else launch_collide_hrr<0>(csrc, cdst, mc, tau_c, s, -1, true);
     hipLaunchKernelGGL((k_ring_coalesce<LAT, DEV, S, M_HRR>), dim3(br2 + bc), dim3(256), 0, s, Hp, fA, fB, cdst, g,
-                       itf, kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, (const S*)nullptr);
+                       itf, kf, omf, tau_f, kc, omc, tau_c, sig, (int)br2, (const S*)nullptr, (double*)nullptr);
     HIPCHK(hipGetLastError());
     cpar ^= 1;
     const int old = hs[0];
@@ -1009,12 +1041,15 @@ struct Grid final : GridBase {
       return;
     }
     for (int k = 0; k < n; ++k) {
-      if (sensors_on) sensors_before(s);
+      rec_fine = sensors_on && k == n - 1;
+      rec_coarse = sensors_on && k >= n - 2;
+      if (rec_fine) sensors_before(s);
+      sens_coarse_next = false;  // set again by a step that records
       if (!g.has_fine) step_uniform(s);
       else if (desc.collision == LBM_BGK) step_two_level<M_BGK>(s);
       else if (desc.collision == LBM_RR) step_two_level<M_RR>(s);
       else step_two_level<M_HRR>(s);
-      if (sensors_on) sensors_after(s);
+      if (rec_fine) sensors_after(s);
       if (probe_level >= 0) {
         // the level's post-collision state at the probe (its density is
         // the pre-collision one); the ring is complete at interior nodes
@@ -1023,6 +1058,7 @@ struct Grid final : GridBase {
                            pCount.as<int64_t>(), probe_cap);
       }
     }
+    rec_fine = rec_coarse = false;
     if (n > 0) sens_ready = sensors_on;
     HIPCHK(hipGetLastError());
   }
@@ -1032,10 +1068,13 @@ struct Grid final : GridBase {
   // nodes pull from the state at t (the pre-collision state at t+1/2); the
   // ring's t+1/2 velocities are interpolated from the history after the
   // step, when its t+1 level exists.
-  // (a fused D2Q9 step records the fine level's in k_fine2)
+  // (a fused D2Q9 step records the fine level's in k_fine2; a BGK / RR
+  // two-level step the coarse level's of the next step)
   void sensors_before(hipStream_t s) {
-    hipLaunchKernelGGL((k_sens_vel<LAT, DEV, S, 0, false>), dim3(blocks(g.Nc, 256)), dim3(256), 0, s, cur_c(),
-                       sUc.as<double>(), g);
+    if (sens_coarse_next) sc_cur ^= 1;
+    else
+      hipLaunchKernelGGL((k_sens_vel<LAT, DEV, S, 0, false>), dim3(blocks(g.Nc, 256)), dim3(256), 0, s, cur_c(),
+                         sUc[sc_cur].as<double>(), g);
     if (g.has_fine && !(desc.collision != LBM_HRR && fused_now()))
       hipLaunchKernelGGL((k_sens_vel<LAT, DEV, S, 1, true>), dim3(blocks(g.Nf, 256)), dim3(256), 0, s, fineA(),
                          sUf.as<double>(), g);
@@ -1068,19 +1107,20 @@ struct Grid final : GridBase {
     HIPCHK(hipSetDevice(device));
     no_nesting("the NH sensors");
     HIPCHK(hipStreamSynchronize(stream));
-    if (on && !sUc.p) {
+    if (on && !sUc[0].p) {
       auto zalloc = [](DevBuf& b, size_t bytes) {
         b.alloc(bytes);
         HIPCHK(hipMemset(b.p, 0, bytes));
       };
-      zalloc(sUc, sizeof(double) * (1 + D) * (size_t)g.Ncp);
+      zalloc(sUc[0], sizeof(double) * (1 + D) * (size_t)g.Ncp);
+      zalloc(sUc[1], sizeof(double) * (1 + D) * (size_t)g.Ncp);
       if (g.has_fine) zalloc(sUf, sizeof(double) * (1 + D) * (size_t)g.Nfp);
       const size_t Nmax = (size_t)std::max(g.Nc, g.Nf);
       sFlags.alloc(Nmax);
       sProd.alloc(sizeof(double) * 3 * Nmax);
     }
     sensors_on = on;
-    sens_ready = false;
+    sens_ready = sens_coarse_next = false;
   }
   void sensors(int level, double thr, uint8_t* flags, double* prod, bool dev) override {
     HIPCHK(hipSetDevice(device));
@@ -1091,7 +1131,7 @@ struct Grid final : GridBase {
     double* pr = prod ? sProd.as<double>() : nullptr;
     uint8_t* fl = sFlags.as<uint8_t>();
     if (level == 0)
-      hipLaunchKernelGGL((k_sensors<LAT, DEV, S, 0>), dim3(blocks(N, 256)), dim3(256), 0, stream, sUc.as<double>(),
+      hipLaunchKernelGGL((k_sensors<LAT, DEV, S, 0>), dim3(blocks(N, 256)), dim3(256), 0, stream, sUc[sc_cur].as<double>(),
                          cur_c(), cbuf[cpar ^ 1].as<S>(), fl, pr, g, thr);
     else
       hipLaunchKernelGGL((k_sensors<LAT, DEV, S, 1>), dim3(blocks(N, 256)), dim3(256), 0, stream, sUf.as<double>(),
@@ -1170,7 +1210,7 @@ struct Grid final : GridBase {
       child->set_state(level - 1, rho, u, dev);
       return;
     }
-    sens_ready = false;
+    sens_ready = sens_coarse_next = false;
     HIPCHK(hipDeviceSynchronize());
     // a coarse reset replaces the history the ring completion reads
     if (level == 0) complete_ring();
@@ -1227,7 +1267,7 @@ struct Grid final : GridBase {
       child->set_pops(level - 1, f, dev);
       return;
     }
-    sens_ready = false;
+    sens_ready = sens_coarse_next = false;
     HIPCHK(hipDeviceSynchronize());
     if (level == 0) complete_ring();
     else ring_partial = false;
