@@ -1727,10 +1727,12 @@ __global__ __launch_bounds__(TXH * TYH, MINW) void k_fine3s(const S* __restrict_
 // A work group of TXH x TYH lanes holds the columns of a tile of (TXH - 2) x
 // (TYH - 2) middle nodes and its one-node halo and walks a run of zlen planes
 // along z.  The iteration for plane z takes the populations of plane z+1,
-// pulled one iteration earlier, computes their velocities (ring nodes: from
+// pulled two iterations earlier, computes their velocities (ring nodes: from
 // the velocity planes, where the ring macro step stored them) into one of
-// four LDS velocity planes and issues the pulls of plane z+2; after one
-// barrier the inner lanes take the strain rate of plane z by centred
+// four LDS velocity planes and issues the pulls of plane z+3 into the
+// registers they leave (two planes of pulls in flight: two register sets,
+// the loop unrolled by two); after one barrier the inner lanes take the
+// strain rate of plane z by centred
 // differences from the planes of z-1, z and z+1 and collide the populations
 // of plane z they kept from the previous iteration.  Four velocity planes
 // rotate, so the plane written in one iteration is never one read in the
@@ -1777,10 +1779,10 @@ __global__ __launch_bounds__(TXH * TYH, MINW) void k_hrr3s(const S* __restrict__
   const uint32_t mpull = (live && !xyring) ? 0u : Wn::kOff;
   const uint32_t mring = xyring ? 0u : Wn::kOff;
   const uint32_t minner = inner ? 0u : Wn::kOff;
-  S H[Q], P[Q], UR[3];
+  S H[Q], P0[Q], P1[Q], U0[3], U1[3];
   // pulls of plane zp (window position d) into P; velocities of ring nodes
   // (ring planes, columns and rows) from the velocity planes into UR
-  auto load = [&](int zp, uint32_t d) __attribute__((always_inline)) {
+  auto load = [&](int zp, uint32_t d, S (&P)[Q], S (&UR)[3]) __attribute__((always_inline)) {
     const bool pring = zp == 0 || zp == nz - 1;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
@@ -1795,7 +1797,7 @@ __global__ __launch_bounds__(TXH * TYH, MINW) void k_hrr3s(const S* __restrict__
     }
   };
   // velocity of the loaded plane zp into its LDS slot; its populations into H
-  auto put = [&](int zp) __attribute__((always_inline)) {
+  auto put = [&](int zp, const S (&P)[Q], const S (&UR)[3]) __attribute__((always_inline)) {
     const bool ring = xyring || zp == 0 || zp == nz - 1;
     S rho, r0, u[3];
     N::moments(P, rho, r0, u);
@@ -1810,22 +1812,25 @@ __global__ __launch_bounds__(TXH * TYH, MINW) void k_hrr3s(const S* __restrict__
     for (int i = 0; i < Q; ++i) H[i] = P[i];
   };
   // planes zs - 1 (velocities) and zs (velocities and populations), the
-  // pulls of plane zs + 1 out
-  load(zs - 1, d0);
-  put(zs - 1);
-  load(zs, d0 + pz);
-  put(zs);
-  load(zs + 1, d0 + 2 * pz);
-  for (int z = zs; z <= ze; ++z) {
+  // pulls of planes zs + 1 and zs + 2 out (two planes in flight)
+  load(zs - 1, d0, P0, U0);
+  put(zs - 1, P0, U0);
+  load(zs, d0 + pz, P0, U0);
+  put(zs, P0, U0);
+  load(zs + 1, d0 + 2 * pz, P0, U0);
+  {
+    const int zn = zs + 2 <= ze + 1 ? zs + 2 : ze + 1;
+    load(zn, d0 + (uint32_t)(zn - zs + 1) * pz, P1, U1);
+  }
+  auto iter = [&](int z, S (&Pu)[Q], S (&Uu)[3]) __attribute__((always_inline)) {
     const uint32_t dz = d0 + (uint32_t)(z - zs + 1) * pz;  // window position of (x, y, z)
-    // populations of plane z (kept from the previous iteration)
     S Hc[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) Hc[i] = H[i];
-    put(z + 1);
-    // pulls of plane z + 2 (plane z + 1 again past the run's last plane)
-    const int zn = z + 2 <= ze + 1 ? z + 2 : z + 1;
-    load(zn, dz + (uint32_t)(zn - z) * pz);
+    put(z + 1, Pu, Uu);
+    // pulls of plane z + 3 (plane ze + 1 again past the run's last plane)
+    const int zn = z + 3 <= ze + 1 ? z + 3 : ze + 1;
+    load(zn, d0 + (uint32_t)(zn - zs + 1) * pz, Pu, Uu);
     __syncthreads();
     if (inner) {
       const int sm = (z - 1) & 3, s0 = z & 3, sp = (z + 1) & 3;
@@ -1848,6 +1853,10 @@ __global__ __launch_bounds__(TXH * TYH, MINW) void k_hrr3s(const S* __restrict__
     const uint32_t bo = Wn::boff(dz) | minner;
 #pragma unroll
     for (int i = 0; i < Q; ++i) Wn::template store<NT>(rd, bo, i, Hc[i]);
+  };
+  for (int z = zs; z <= ze; z += 2) {
+    iter(z, P0, U0);
+    if (z + 1 <= ze) iter(z + 1, P1, U1);
   }
 }
 

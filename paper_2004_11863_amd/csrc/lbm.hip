@@ -613,7 +613,7 @@ struct Grid final : GridBase {
   // k_hrr3 (30 x 6 tiles of vectors), variant 3 k_hrr3s (one node per lane,
   // 64 x 8 lanes in FP32, 34 x 8 in FP64); variants 0 and 1 run the velocity
   // pass and k_collide_hrr (capped at 2 / 3 resident work groups).  On the
-  // 385^3 patch in FP32, per substep: k_hrr3 2.78 ms, k_hrr3s 3.20 ms, the
+  // 385^3 patch in FP32, per substep: k_hrr3 2.78 ms, k_hrr3s 2.91 ms, the
   // two-pass form 1.0 + 1.78 ms; the one-pass kernels save the velocity
   // pass's traffic but re-read their tile halos from HBM.
   bool hrr_one_pass3() const { return D == 3 && desc.collision == LBM_HRR && var[3] >= 2 && !dyn_on; }
