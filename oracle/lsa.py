@@ -18,7 +18,6 @@ rounding for this polynomial-and-division map.
 """
 from __future__ import annotations
 
-import itertools
 import math
 
 import numpy as np

@@ -1566,11 +1566,6 @@ __global__ __launch_bounds__(TXH * TYH, MINW) void k_fine3s(const S* __restrict_
   const bool inner = live && hx >= 1 && hx <= TXH - 2 && hy >= 1 && hy <= TYH - 2 && x <= nx - 2 && y <= ny - 2;
   const bool xyring = live && (x == 0 || x == nx - 1 || y == 0 || y == ny - 1);
   const bool near = x <= 4 || x >= nx - 5 || y <= 4 || y >= ny - 5;
-  // the tile has nodes within 4 of an x or y face (wave-uniform)
-  const bool tile_near = tx * (TXH - 2) <= 4 || tx * (TXH - 2) + TXH - 1 >= nx - 5 || ty * (TYH - 2) <= 4 ||
-                         ty * (TYH - 2) + TYH - 1 >= ny - 5;
-  // the wave holds ring columns or rows (wave-uniform)
-  const bool wave_ring = __any(xyring) != 0;
   const int zs = 1 + zc * zlen, ze = min(zs + zlen - 1, nz - 2);
   // The run computes planes zs - 1 .. ze + 1, whose pulls reach planes
   // zs - 2 .. ze + 2: the window starts at row 0 of plane max(zs - 2, 0);
@@ -1777,7 +1772,6 @@ __global__ __launch_bounds__(TXH * TYH, MINW) void k_hrr3s(const S* __restrict__
   const uint32_t py = (uint32_t)g.pf, pz = (uint32_t)g.pf * (uint32_t)ny;
   const uint32_t d0 = live ? (uint32_t)(fpos(g, x, y, zs - 1) - W.pb0) : 0u;  // node in plane zs - 1
   const uint32_t mpull = (live && !xyring) ? 0u : Wn::kOff;
-  const uint32_t mring = xyring ? 0u : Wn::kOff;
   const uint32_t minner = inner ? 0u : Wn::kOff;
   S H[Q], P0[Q], P1[Q], U0[3], U1[3];
   // pulls of plane zp (window position d) into P; velocities of ring nodes

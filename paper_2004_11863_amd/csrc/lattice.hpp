@@ -220,7 +220,7 @@ struct Node {
     const T b_xzz = T(2) * u[2] * a.xz + u[0] * a.zz;
     const T b_yyz = T(2) * u[1] * a.yz + u[2] * a.yy;
     const T b_xxz = T(2) * u[0] * a.xz + u[2] * a.xx;
-    const T ru0 = rho * u[0], ru1 = rho * u[1], ru2 = rho * u[2];
+    const T ru0 = rho * u[0], ru1 = rho * u[1];
     T k[6];
     third_combo(ru0 * u[0] * u[1] + om * b_xxy, ru0 * u[1] * u[1] + om * b_xyy, ru1 * u[2] * u[2] + om * b_yzz,
                 ru0 * u[2] * u[2] + om * b_xzz, ru1 * u[1] * u[2] + om * b_yyz, ru0 * u[0] * u[2] + om * b_xxz, k);

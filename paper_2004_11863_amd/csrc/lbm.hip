@@ -807,7 +807,6 @@ struct Grid final : GridBase {
   // A holds the state at integer times, B at half times.
   template <int MODEL>
   void step_two_level(hipStream_t s) {
-    using F = HF<LAT, MODEL>;
     S* csrc = cbuf[cpar].as<S>();
     S* cdst = cbuf[cpar ^ 1].as<S>();
     S* fA = fineA();
@@ -821,7 +820,7 @@ struct Grid final : GridBase {
     const double c0 = -1.0 / 8.0, c1 = 3.0 / 4.0, c2 = 3.0 / 8.0;  // eq TempInt at t+1/2
     constexpr int IB = kIfaceBlock;
     constexpr int PER = 256 / (D == 2 ? 9 : 27);
-    const unsigned bh = xblocks(NH, IB), br = xblocks(itf.NR, IB), bt = xblocks(itf.NT, IB), bg = blocks(NH * F::N, 256);
+    const unsigned bh = xblocks(NH, IB), br = xblocks(itf.NR, IB), bt = xblocks(itf.NT, IB);
     const unsigned bc = xblocks(itf.NT, PER), br2 = xblocks(itf.NR, 256);
     // BGK / RR: the capture also interpolates every history value to t+1/2
     // (G); H-RR fills its strain-rate fields later and interpolates then

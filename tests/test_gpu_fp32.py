@@ -7,7 +7,7 @@ import pytest
 
 import oracle as O
 from paper_2004_11863_amd import inputs as I
-from parity_util import compare_fp32, compare_fp64, make_pair
+from parity_util import compare_fp32, make_pair
 
 pytestmark = pytest.mark.gpu
 

@@ -6,7 +6,6 @@ coarse level in the one-pass H-RR form, level 1 in the two-pass form) and
 D3Q19.  FP64 within 1e-12 relative on rho, u and the populations of every
 evolved node of the three levels; FP32 deviation storage within the stated
 FP32 bars."""
-import math
 
 import numpy as np
 import pytest

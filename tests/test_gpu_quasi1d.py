@@ -27,7 +27,6 @@ acoustic pulse or 1e-7 of the shear wave gives ~1e-18.  The amplitudes are
 not a parity claim: they depend on the paper's domain ends, which it does
 not define.
 """
-import math
 
 import numpy as np
 import pytest

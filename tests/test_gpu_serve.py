@@ -63,7 +63,6 @@ def test_served_in_real_time_with_autotuning_equals_running_alone(seed, collisio
 
 def _oracle_of(req, steps=None):
     import oracle as O
-    from paper_2004_11863_amd import inputs as I
     g = req.workload.geom
     D = g.D
     ref = O.Grid(O.D2Q9 if D == 2 else O.D3Q19, {"BGK": O.BGK, "RR": O.RR, "HRR": O.HRR}[req.collision],

@@ -6,7 +6,6 @@ rejected before any device work."""
 import numpy as np
 import pytest
 
-import oracle as O
 from paper_2004_11863_amd import inputs as I
 from parity_util import make_pair
 
