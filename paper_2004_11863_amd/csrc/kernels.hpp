@@ -1090,19 +1090,33 @@ __device__ __forceinline__ void fine2_s1(const S* __restrict__ src, S* __restric
   const Pull<S, Q, V, 1, 2> pl(g.pf, g.fxo, x0, y, 0, nx, ny, 1);
   VA v[Q];
   pl.template load_all<L>(src, v);
+  // a vector of middle nodes only (x0 .. x0 + V - 1 <= nx - 2): the SENS
+  // records go out as whole vectors (positions of vector starts are
+  // multiples of V)
+  const bool whole = x0 + V - 1 <= nx - 2;
   if constexpr (SENS) {
     if (band) {
+      typedef double DV __attribute__((ext_vector_type(V)));
+      DV uv[2];
 #pragma unroll
       for (int j = 0; j < V; ++j) {
-        const int x = x0 + j;
-        if (x > nx - 2) continue;
         double f[Q], r, r0, u[3];
 #pragma unroll
         for (int i = 0; i < Q; ++i) f[i] = full_pop<S, DEV, LAT>(v[i][j], i);
         Node<LAT, false, double>::moments(f, r, r0, u);
-        const int64_t p = fpos(g, x, y, 0);
+        uv[0][j] = u[0];
+        uv[1][j] = u[1];
+      }
+      const int64_t p0 = fpos(g, x0, y, 0);
+      if (whole) {
 #pragma unroll
-        for (int d = 0; d < L::D; ++d) su[(int64_t)(1 + d) * g.Nfp + p] = u[d];
+        for (int d = 0; d < 2; ++d) *(DV*)(su + (int64_t)(1 + d) * g.Nfp + p0) = uv[d];
+      } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+          if (x0 + j <= nx - 2)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) su[(int64_t)(1 + d) * g.Nfp + p0 + j] = uv[d][j];
       }
     }
   }
@@ -1128,13 +1142,19 @@ __device__ __forceinline__ void fine2_s1(const S* __restrict__ src, S* __restric
       for (int i = 0; i < Q; ++i) row[i][c0 + jr] = half[pop_at<S, Q>(p, i)];
   }
   if (band) {
+    if (SENS && whole) {
+      const int64_t p0 = fpos(g, x0, y, 0);
 #pragma unroll
-    for (int j = 0; j < V; ++j) {
-      const int x = x0 + j;
-      if (x > nx - 2 || (!SENS && !(x <= 4 || x >= nx - 5 || y <= 4 || y >= ny - 5))) continue;
-      const int64_t p = fpos(g, x, y, 0);
+      for (int i = 0; i < Q; ++i) vstore<false>((VA*)(half + pop_at<S, Q>(p0, i)), v[i]);
+    } else {
 #pragma unroll
-      for (int i = 0; i < Q; ++i) half[pop_at<S, Q>(p, i)] = v[i][j];
+      for (int j = 0; j < V; ++j) {
+        const int x = x0 + j;
+        if (x > nx - 2 || (!SENS && !(x <= 4 || x >= nx - 5 || y <= 4 || y >= ny - 5))) continue;
+        const int64_t p = fpos(g, x, y, 0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) half[pop_at<S, Q>(p, i)] = v[i][j];
+      }
     }
   }
 }
