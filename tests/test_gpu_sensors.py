@@ -244,3 +244,39 @@ def test_sensors_record_dropped_by_set_state(model):
         assert np.array_equal(fa, fb), lv
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("case", ["uniform_rr", "two_level_hrr", "d3_two_level_hrr"])
+def test_sensors_one_call_equals_single_steps(case):
+    """A call of several steps records only its last steps; the read-out
+    equals that of the same steps taken one call at a time (every step
+    recording), for the paths that record with the recording pass only: a
+    uniform grid, and H-RR on two levels (D2Q9 and D3Q19)."""
+    lbm = _lbm()
+    if case == "uniform_rr":
+        wl = I.vortex_crossing_64(1)
+        wl.geom = I.Geometry(2, wl.geom.n, (0, 0, 0), (0, 0, 0))
+        model = "RR"
+    elif case == "two_level_hrr":
+        wl = I.vortex_crossing_64(1)
+        model = "HRR"
+    else:
+        geom = I.Geometry(3, (22, 20, 24), (5, 4, 6), (15, 14, 17))
+        wl = I.Workload(geom=geom, U=(0.1 / math.sqrt(3), 0.01, -0.005),
+                        pulses=[I.Pulse(center=(15.2, 9.6, 11.1), A=1e-3, R=2.5)])
+        model = "HRR"
+    wl.pulses = list(wl.pulses) + [I.Pulse(center=(12.0, 9.0, 11.0)[:wl.geom.D], A=1e-3, R=2.5)]
+    a, _, levels = make_pair(wl, model, lbm.LBM_FP32_DEV, with_oracle=False)
+    b, _, _ = make_pair(wl, model, lbm.LBM_FP32_DEV, with_oracle=False)
+    lbm.lbm_sensors_enable(a.h, True)
+    lbm.lbm_sensors_enable(b.h, True)
+    a.step(5)
+    for _ in range(5):
+        b.step(1)
+    for lv in levels:
+        fa, da = a.sensors(lv, 1e-8)
+        fb, db = b.sensors(lv, 1e-8)
+        assert np.array_equal(da, db), (lv, float(np.abs(da - db).max()))
+        assert np.array_equal(fa, fb), lv
+    a.close()
+    b.close()
