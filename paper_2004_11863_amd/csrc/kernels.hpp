@@ -1497,7 +1497,12 @@ __global__ __launch_bounds__(HXV * HYR) void k_hrr2(const S* __restrict__ src, S
 // populations of one column (the four-node lanes of an earlier design needed
 // 227 registers and ran at two waves per SIMD), and the x halo is one node
 // wide.  The t+1/2 state of middle nodes within 4 nodes of a patch face (what
-// the fine-to-coarse transfer pulls) is stored into `half`.
+// the fine-to-coarse transfer pulls) is stored: in the x-bands into the
+// compact band copy `xb` (xband_at, rows 5 values apart, so a tile's band
+// fills whole cache lines instead of a partial line per row and
+// population), in the y- and z-bands into `half`; the t+1/2 ring
+// reconstruction fills both, and a ring column x = 0 / nx - 1 away from the
+// z faces reads the populations it sends inward from `xb`.
 template <int LAT>
 struct ZSets {
   using L = Lattice<LAT>;
@@ -1562,8 +1567,9 @@ struct Window {
 
 template <int LAT, bool DEV, typename S, int MODEL, bool NT, int TXH, int TYH, int MINW>
 __global__ __launch_bounds__(TXH * TYH, MINW) void k_fine3s(const S* __restrict__ src, S* __restrict__ dst,
-                                                            S* __restrict__ half, const Geo g, const S om, int ntx,
-                                                            int nty, int nzc, int zlen, int per_xcd) {
+                                                            S* __restrict__ half, S* __restrict__ xb, const Geo g,
+                                                            const S om, int ntx, int nty, int nzc, int zlen,
+                                                            int per_xcd) {
   using L = Lattice<LAT>;
   using N = Node<LAT, DEV, S>;
   using C = ZSets<LAT>;
@@ -1586,6 +1592,18 @@ __global__ __launch_bounds__(TXH * TYH, MINW) void k_fine3s(const S* __restrict_
   const bool inner = live && hx >= 1 && hx <= TXH - 2 && hy >= 1 && hy <= TYH - 2 && x <= nx - 2 && y <= ny - 2;
   const bool xyring = live && (x == 0 || x == nx - 1 || y == 0 || y == ny - 1);
   const bool near = x <= 4 || x >= nx - 5 || y <= 4 || y >= ny - 5;
+  // Wave modes (wave-uniform bits): 1 full -- the ring values of every
+  // population from `half` and the band there (ring rows, or both ring
+  // columns, in the wave; planes within 5 of a z face); else 2 / 4 the ring
+  // column x = 0 / nx - 1 reads the populations it sends inward from the
+  // compact x-band copy, 32 the y-band goes to `half`; always 8 / 16 the
+  // x-band goes to the compact copy (from which the transfer reads it).
+  const bool xs0 = inner && x <= 4, xs1 = inner && x >= nx - 5;
+  const bool w_r0 = __any(live && x == 0) != 0, w_r1 = __any(live && x == nx - 1) != 0;
+  const bool w_full = __any(live && (y == 0 || y == ny - 1)) != 0 || (w_r0 && w_r1);
+  const int wbits = __builtin_amdgcn_readfirstlane((w_full ? 1 : 0) | (w_r0 ? 2 : 0) | (w_r1 ? 4 : 0) |
+                                                   (__any(xs0) != 0 ? 8 : 0) | (__any(xs1) != 0 ? 16 : 0) |
+                                                   (__any(inner && (y <= 4 || y >= ny - 5)) != 0 ? 32 : 0));
   const int zs = 1 + zc * zlen, ze = min(zs + zlen - 1, nz - 2);
   // The run computes planes zs - 1 .. ze + 1, whose pulls reach planes
   // zs - 2 .. ze + 2: the window starts at row 0 of plane max(zs - 2, 0);
@@ -1603,6 +1621,27 @@ __global__ __launch_bounds__(TXH * TYH, MINW) void k_fine3s(const S* __restrict_
   const uint32_t mpull = (live && !xyring) ? 0u : Wn::kOff;
   const uint32_t mring = xyring ? 0u : Wn::kOff;
   const uint32_t minner = inner ? 0u : Wn::kOff;
+  // the compact x-band copy (xband_at: [side][population][z][y][x offset])
+  // through a buffer resource with the same masking
+  const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void*)xb, (short)0, (int)Wn::kOff, 0x00020000);
+  const int xpop = (int)sizeof(S) * 5 * ny * nz;  // bytes between populations of one side
+  const uint32_t xzb = (uint32_t)sizeof(S) * 5u * (uint32_t)ny;  // bytes per plane
+  const uint32_t xside = (uint32_t)xpop * (uint32_t)Q;            // bytes between the sides
+  const uint32_t xo0 = (uint32_t)sizeof(S) * (uint32_t)(5 * y + x);
+  const uint32_t xo1 = xside + (uint32_t)sizeof(S) * (uint32_t)(5 * y + x - (nx - 5));
+  const uint32_t mr0 = (live && x == 0) ? 0u : Wn::kOff, mr1 = (live && x == nx - 1) ? 0u : Wn::kOff;
+  auto xload = [&](uint32_t bo, int i) __attribute__((always_inline)) -> S {
+    if constexpr (sizeof(S) == 4)
+      return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(rx, (int)bo, i * xpop, 0));
+    else
+      return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(rx, (int)bo, i * xpop, 0));
+  };
+  auto xstore = [&](uint32_t bo, int i, S v) __attribute__((always_inline)) {
+    if constexpr (sizeof(S) == 4)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rx, (int)bo, i * xpop, 0);
+    else
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(typename Wn::u2, v), rx, (int)bo, i * xpop, 0);
+  };
   S U0[C::NU], U1[C::NU], M[C::NM], R = S(0), Z0 = S(0), Z1 = S(0);
 #pragma unroll
   for (int i = 0; i < C::NU; ++i) U0[i] = U1[i] = S(0);
@@ -1619,15 +1658,29 @@ __global__ __launch_bounds__(TXH * TYH, MINW) void k_fine3s(const S* __restrict_
   // Loads of substep 1 for plane zp (window position d of this lane's node):
   // pulls of middle nodes from src into P, t+1/2 values of ring nodes (ring
   // planes, columns and rows) from `half` into PR.
-  auto load = [&](int zp, uint32_t d) __attribute__((always_inline)) {
+  auto load = [&](int zp, uint32_t d, int mode) __attribute__((always_inline)) {
     const bool pring = zp == 0 || zp == nz - 1;
     const uint32_t mp = pring ? Wn::kOff : mpull;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
       P[i] = Wn::load(rs, Wn::boff(d - L::cx(i) - py * L::cy(i) - pz * L::cz(i)) | mp, i);
-    const uint32_t bo = Wn::boff(d) | (pring ? mlive : mring);
+    if (mode & 1) {
+      const uint32_t bo = Wn::boff(d) | (pring ? mlive : mring);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) PR[i] = Wn::load(rh, bo, i);
+      for (int i = 0; i < Q; ++i) PR[i] = Wn::load(rh, bo, i);
+    } else {
+      const uint32_t zb = (uint32_t)zp * xzb;
+      if (mode & 2) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          if (L::cx(i) == 1) PR[i] = xload((zb + (uint32_t)sizeof(S) * (uint32_t)(5 * y)) | mr0, i);
+      }
+      if (mode & 4) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          if (L::cx(i) == -1) PR[i] = xload((xside + zb + (uint32_t)sizeof(S) * (uint32_t)(5 * y + 4)) | mr1, i);
+      }
+    }
   };
   // Substep 1 of plane zl (window position dl) into T from the loads issued
   // one plane earlier (ring nodes take PR by a bitwise blend: a select
@@ -1635,20 +1688,39 @@ __global__ __launch_bounds__(TXH * TYH, MINW) void k_fine3s(const S* __restrict_
   // memory); the t+1/2 state of inner middle nodes within 4 nodes of a face
   // goes to `half`.
   using U = typename std::conditional<sizeof(S) == 4, uint32_t, uint64_t>::type;
-  auto take = [&](int zl, S* T) __attribute__((always_inline)) {
+  // (outside a full plane a ring lane takes only the populations it sends
+  // inward; no inner lane reads its others)
+  auto take = [&](int zl, S* T, int mode) __attribute__((always_inline)) {
     const bool pring = zl == 0 || zl == nz - 1;
     const U mk = (xyring || pring) ? ~U(0) : U(0);
+    const U m0 = (mode & 1) ? mk : U(0), mp1 = (mode & 3) ? mk : U(0), mm1 = (mode & 5) ? mk : U(0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-      T[i] = __builtin_bit_cast(S, (__builtin_bit_cast(U, PR[i]) & mk) | (__builtin_bit_cast(U, P[i]) & ~mk));
+    for (int i = 0; i < Q; ++i) {
+      const U mi = L::cx(i) == 1 ? mp1 : (L::cx(i) == -1 ? mm1 : m0);
+      T[i] = __builtin_bit_cast(S, (__builtin_bit_cast(U, PR[i]) & mi) | (__builtin_bit_cast(U, P[i]) & ~mi));
+    }
   };
-  auto s1 = [&](int zl, uint32_t dl, S* T) __attribute__((always_inline)) {
+  auto s1 = [&](int zl, uint32_t dl, S* T, int mode) __attribute__((always_inline)) {
     const bool pring = zl == 0 || zl == nz - 1;
     if (live && !xyring && !pring) N::collide(T, MODEL, om, S(0), S(0), nullptr);
-    const bool st = inner && !pring && zl >= zs && zl <= ze && (near || zl <= 4 || zl >= nz - 5);
-    const uint32_t bo = Wn::boff(dl) | (st ? 0u : Wn::kOff);
+    const bool own = inner && !pring && zl >= zs && zl <= ze;
+    if (mode & 33) {
+      const bool st = own && (near || zl <= 4 || zl >= nz - 5);
+      const uint32_t bo = Wn::boff(dl) | (st ? 0u : Wn::kOff);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) Wn::template store<false>(rh, bo, i, T[i]);
+      for (int i = 0; i < Q; ++i) Wn::template store<false>(rh, bo, i, T[i]);
+    }
+    const uint32_t zb = (uint32_t)zl * xzb;
+    if (mode & 8) {
+      const uint32_t bo = (zb + xo0) | (own && xs0 ? 0u : Wn::kOff);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) xstore(bo, i, T[i]);
+    }
+    if (mode & 16) {
+      const uint32_t bo = (zb + xo1) | (own && xs1 ? 0u : Wn::kOff);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) xstore(bo, i, T[i]);
+    }
   };
   // the planes move up by one
   auto shift = [&](const S* T) __attribute__((always_inline)) {
@@ -1672,27 +1744,33 @@ __global__ __launch_bounds__(TXH * TYH, MINW) void k_fine3s(const S* __restrict_
   // planes zs - 1 and zs: substep 1 only
   {
     S T[Q];
-    load(zs - 1, d0);
-    take(zs - 1, T);
-    load(zs, d0 + pz);
-    s1(zs - 1, d0, T);
+    load(zs - 1, d0, wbits | 1);
+    take(zs - 1, T, wbits | 1);
+    load(zs, d0 + pz, wbits | 1);
+    s1(zs - 1, d0, T, wbits | 1);
     shift(T);
-    take(zs, T);
-    load(zs + 1, d0 + 2 * pz);
-    s1(zs, d0 + pz, T);
+    take(zs, T, wbits | 1);
+    load(zs + 1, d0 + 2 * pz, wbits | 1);
+    s1(zs, d0 + pz, T, wbits | 1);
     shift(T);
   }
   int buf = 0;
   for (int z = zs; z <= ze; ++z) {
     const int zl = z + 1;
+    // planes zl in [5, nz - 6] are not full (nor those their loads are for,
+    // in [6, nz - 5]; the ring values of a plane are loaded by the mode of the
+    // iteration before, which is full for zl <= 5 and zl >= nz - 4)
+    const int mode = (z <= 3 || z >= nz - 6) ? (wbits | 1) : wbits;
     const uint32_t dl = d0 + (uint32_t)(zl - zs + 1) * pz;  // window position of (x, y, zl)
-    // the loads of plane zl (issued one plane earlier) into T, the loads of
-    // plane zl + 1 out (plane zl again past the run's last plane)
+    // the loads of plane zl (issued one plane earlier) into T; the band
+    // stores of plane zl, then the loads of plane zl + 1 out (plane zl again
+    // past the run's last plane), so that only the stores of this plane's
+    // substep 2 follow the loads a wave waits for
     S T[Q];
-    take(zl, T);
+    take(zl, T, mode);
+    s1(zl, dl, T, mode);
     const int zn = zl + 1 <= ze + 1 ? zl + 1 : zl;
-    load(zn, dl + (uint32_t)(zn - zl) * pz);
-    s1(zl, dl, T);
+    load(zn, dl + (uint32_t)(zn - zl) * pz, mode);
     // (slot and register indices are forced to compile-time constants:
     // used directly as array indices, the counting loops behind them were
     // left to run on the device)

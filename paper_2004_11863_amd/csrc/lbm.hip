@@ -604,9 +604,12 @@ struct Grid final : GridBase {
       const int ntx = (g.nf[0] - 2 + TXH - 3) / (TXH - 2), nty = (g.nf[1] - 2 + TYH - 3) / (TYH - 2);
       const int zcap = window_zcap();
       if (zcap < 1) throw LbmError(LBM_EUNSUPPORTED, "fine planes too large for the one-pass fused kernel");
+      // the compact x-band copy is addressed with 32-bit byte offsets too
+      if ((double)xband_elems(g, Q) * sizeof(S) >= 2147483648.0)
+        throw LbmError(LBM_EUNSUPPORTED, "fine x-bands too large for the one-pass fused kernel");
       const ZRuns r = zruns_tiles(ntx, nty, occupancy_slots(kern, f3_slots[v], TXH * TYH), zcap);
-      hipLaunchKernelGGL(kern, dim3((unsigned)(r.per * kXCD)), dim3(TXH * TYH), 0, s, src, dst, half, g,
-                         (S)(1.0 - 1.0 / tau_f), r.ntx, r.nty, r.nzc, r.zlen, r.per);
+      hipLaunchKernelGGL(kern, dim3((unsigned)(r.per * kXCD)), dim3(TXH * TYH), 0, s, src, dst, half, xbuf.as<S>(),
+                         g, (S)(1.0 - 1.0 / tau_f), r.ntx, r.nty, r.nzc, r.zlen, r.per);
     }
   }
   // One H-RR fine substep in one pass (D3Q19): fine H-RR role variant 2 is
@@ -662,7 +665,7 @@ struct Grid final : GridBase {
         default: go_fine2<MODEL, 32, 8>(src, dst, half, s, su); break;
       }
     } else if constexpr (sizeof(S) == 4) {
-      if (v == 2) go_fine3s<MODEL, 66, 14, 1>(src, dst, half, s, 2);
+      if (v == 2) go_fine3s<MODEL, 64, 16, 1>(src, dst, half, s, 2);
       else go_fine3s<MODEL, 64, 8, 1>(src, dst, half, s, 3);
     } else {
       if (v == 2) go_fine3s<MODEL, 34, 14, 1>(src, dst, half, s, 2);
@@ -833,9 +836,12 @@ struct Grid final : GridBase {
     sens_coarse_next = scn != nullptr;
     if (MODEL != M_HRR && fused_now()) {
       S* fH = fbuf[2].as<S>();
-      launch_stream_ring<MODEL>(csrc, cdst, fH, kf, omf, s, nullptr, scn);
+      // D3Q19: the t+1/2 ring and the fused kernel also fill the compact
+      // x-band copy, from which the transfer reads the x-bands
+      S* xb = D == 3 ? xbuf.as<S>() : nullptr;
+      launch_stream_ring<MODEL>(csrc, cdst, fH, kf, omf, s, xb, scn);
       timed(s, [&] { launch_fused<MODEL>(fA, fB, fH, s, -1, rec_fine ? sUf.as<double>() : nullptr); });
-      launch_ring_coalesce<MODEL>(Hp, fB, fH, cdst, nullptr, scn, s);
+      launch_ring_coalesce<MODEL>(Hp, fB, fH, cdst, xb, scn, s);
       fpar ^= 1;
     } else if (MODEL != M_HRR) {
       // substep 1 writes the ring column x = nx - 1 of B, so the t+1/2 ring
