@@ -123,7 +123,7 @@ def roofline_of(kt, Q, pb, geom):
             "mean_launch_ms": mean_ms,
             # 2 Q P_b per lattice update: above `achieved` when a launch
             # updates each node twice
-            "update_equivalent_GBs": round(upd_eq, 1)}
+            "update_equivalent_GBs": round(upd_eq, 1), "update_equivalent_frac": round(upd_eq / HBM_PEAK_GBS, 4)}
 
 
 def workload(name, seed=0):
