@@ -130,3 +130,36 @@ def test_fp32_overflow_falls_back_to_fp64():
             alone = serve.run_alone(r)
             for k, v in alone.items():
                 assert np.array_equal(v, r.result[k]), (r.rid, k)
+
+
+def test_non_finite_fp32_request_is_rerun_in_fp64_on_the_device():
+    """A served FP32 request whose result is not finite goes back to the
+    queue and runs again in FP64 from its start; the others are unaffected.
+    The request's initial density is NaN (a pulse of NaN amplitude), so its
+    FP64 rerun is not finite either and is delivered as it is: equal, NaN
+    for NaN, to the request run alone in FP64."""
+    import dataclasses
+    reqs = serve.poisson_trace(6, rate=100.0, seed=13, d2_side=(40, 72), d3_side=(20, 24), steps=(8, 20),
+                               fp64_frac=0.0)
+    bad = reqs[2]
+    wl = bad.workload
+    bad.workload = dataclasses.replace(wl, pulses=[dataclasses.replace(p, A=float("nan")) for p in wl.pulses]
+                                       or [serve.I.Pulse(center=tuple(0.5 * n for n in wl.geom.n[:wl.geom.D]),
+                                                         A=float("nan"))])
+    ex = serve.DeviceExecutor(capacity=3)
+    done = serve.Server(ex, 1 << 36, max_chunk=6).run(reqs, realtime=False)
+    ex.close()
+    assert sorted(r.rid for r in done) == list(range(len(reqs)))
+    for r in done:
+        if r.rid == bad.rid:
+            assert getattr(r, "fell_back", False) and r.fp64
+            assert not all(np.isfinite(v).all() for v in r.result.values())
+            alone = serve.run_alone(r, fp64=True)
+            for k, v in alone.items():
+                assert np.array_equal(v, r.result[k], equal_nan=True), k
+        else:
+            assert not getattr(r, "fell_back", False) and not r.fp64
+            alone = serve.run_alone(r)
+            for k, v in alone.items():
+                assert np.array_equal(v, r.result[k]), (r.rid, k)
+    assert sum(bool(getattr(r, "fell_back", False)) for r in done) == 1
